@@ -1,0 +1,370 @@
+"""Seeded synthetic inputs for the embedded-boundary elliptic solve.
+
+This module is shared by the CPU oracle and the GPU library. It holds only
+problem *descriptions*: the box, analytic signed-distance functions sampled at
+grid nodes, the per-cell source density, the per-cell surface charge draw and
+the boundary data. It contains none of the discretisation arithmetic (no
+moments, no stencils, no solves).
+
+Conventions (shared by both sides):
+  * cells are indexed (i_x, i_y[, i_z]); arrays are stored C-order with x
+    fastest, i.e. numpy shape (ny, nx) or (nz, ny, nx);
+  * node-sampled level sets have shape (ny+1, nx+1) or (nz+1, ny+1, nx+1);
+  * an object's signed distance is > 0 outside the object;
+  * nondimensional units with eps0 = 1, so rho means rho/eps0;
+  * all random numbers come from numpy's PCG64 (``numpy.random.default_rng``).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+OBJ_ELECTRODE = 0   # covered for every phase; Dirichlet value on its surface
+OBJ_DIELECTRIC = 1  # region of phase 1 (permittivity = value)
+OBJ_WALL = 2        # covered for every phase; Neumann flux (value) on its surface
+
+BC_DIRICHLET = 0
+BC_NEUMANN = 1
+BC_ROBIN = 2
+
+FACE_NAMES = ("x-", "x+", "y-", "y+", "z-", "z+")
+
+
+@dataclasses.dataclass
+class Obj:
+    kind: int
+    value: float
+    sdf: np.ndarray  # node-sampled, float64, > 0 outside
+
+
+@dataclasses.dataclass
+class Problem:
+    """One elliptic problem: alpha*a*phi + beta*div(b grad phi) = rho."""
+    dim: int
+    n: tuple            # (nx, ny) or (nx, ny, nz)
+    h: float
+    lo: tuple
+    objects: List[Obj]
+    bc_kind: list       # 6 entries (x-, x+, y-, y+, z-, z+)
+    bc_value: list      # Dirichlet value / Neumann outward flux / Robin a3
+    robin_a1: list
+    robin_a2: list
+    alpha: float = 0.0
+    beta: float = -1.0
+    a_gas: float = 0.0
+    a_diel: float = 0.0
+    b_gas: float = 1.0
+    rho: Optional[np.ndarray] = None     # per cell (primary DOF), float64
+    sigma: Optional[np.ndarray] = None   # per cell (used on gas/dielectric facets)
+    name: str = ""
+    seed: Optional[int] = None
+
+    @property
+    def shape(self):
+        """numpy shape of a cell array."""
+        return tuple(reversed(self.n))
+
+    @property
+    def ncells(self):
+        return int(np.prod(self.n))
+
+    def cell_centres(self):
+        """Tuple of coordinate arrays (x, y[, z]) broadcastable to ``shape``."""
+        return _axes(self.dim, self.n, self.h, self.lo, 0.5)
+
+    def nodes(self):
+        return _axes(self.dim, tuple(m + 1 for m in self.n), self.h, self.lo, 0.0)
+
+
+def _axes(dim, n, h, lo, off):
+    out = []
+    for d in range(dim):
+        v = lo[d] + (np.arange(n[d], dtype=np.float64) + off) * h
+        shp = [1] * dim
+        shp[dim - 1 - d] = n[d]
+        out.append(v.reshape(shp))
+    return tuple(out)
+
+
+def _bc(kind, value=0.0, a1=0.0, a2=1.0):
+    return [kind] * 6, [value] * 6, [a1] * 6, [a2] * 6
+
+
+# --------------------------------------------------------------------------
+# analytic signed distances (exact for the shapes named)
+# --------------------------------------------------------------------------
+
+def sdf_sphere(X, centre, r):
+    return np.sqrt(sum((X[d] - centre[d]) ** 2 for d in range(len(X)))) - r
+
+
+def sdf_halfspace_below(coord, level):
+    """Region coord < level (signed distance > 0 above)."""
+    return coord - level
+
+
+def sdf_plane(X, point, normal):
+    """Half-space {(x - point).normal < 0}; distance > 0 on the +normal side."""
+    return sum((X[d] - point[d]) * normal[d] for d in range(len(X)))
+
+
+def sdf_pin3(X, axis_xy, z_tip, r):
+    """Vertical cylinder of radius r on axis (ax, ay) running upward from a
+    hemispherical tip whose apex is at z_tip."""
+    x, y, z = X
+    zc = z_tip + r
+    rxy = np.sqrt((x - axis_xy[0]) ** 2 + (y - axis_xy[1]) ** 2)
+    cap = np.sqrt(rxy ** 2 + (z - zc) ** 2)
+    return np.where(z >= zc, rxy, cap) - r
+
+
+def sdf_blade2(X, axis_x, y_tip, r):
+    """2D blade: strip |x - axis_x| < r above a semicircular tip with apex y_tip."""
+    x, y = X
+    yc = y_tip + r
+    dx = np.abs(x - axis_x)
+    cap = np.sqrt(dx ** 2 + (y - yc) ** 2)
+    return np.where(y >= yc, dx - r, cap - r)
+
+
+def _nodes(dim, n, h, lo):
+    X = _axes(dim, tuple(m + 1 for m in n), h, lo, 0.0)
+    shp = tuple(m + 1 for m in reversed(n))
+    return tuple(np.broadcast_to(a, shp) for a in X)
+
+
+def _centres(dim, n, h, lo):
+    X = _axes(dim, n, h, lo, 0.5)
+    shp = tuple(reversed(n))
+    return tuple(np.broadcast_to(a, shp) for a in X)
+
+
+# --------------------------------------------------------------------------
+# configurations
+# --------------------------------------------------------------------------
+
+def manufactured_sine(n=64):
+    """2D unit square, no embedded boundary, eps = 1, Dirichlet 0 on all sides,
+    rho = 2 pi^2 sin(pi x) sin(pi y) at cell centres (manufactured from
+    phi = sin(pi x) sin(pi y))."""
+    h = 1.0 / n
+    x, y = _centres(2, (n, n), h, (0.0, 0.0))
+    rho = 2.0 * math.pi ** 2 * np.sin(math.pi * x) * np.sin(math.pi * y)
+    k, v, a1, a2 = _bc(BC_DIRICHLET, 0.0)
+    return Problem(2, (n, n), h, (0.0, 0.0), [], k, v, a1, a2,
+                   rho=np.ascontiguousarray(rho), name=f"sine2d-{n}")
+
+
+def two_disks(n=1024, seed=0, sigma_std=0.1):
+    """2D unit square: conducting disk r=0.1 at (0.5,0.7) held at 1, dielectric
+    disk r=0.2 at (0.5,0.3) with eps=4 in gas eps=1, Dirichlet 0 on the box,
+    a Gaussian space-charge blob (amplitude 1, standard deviation 0.02) placed
+    by the seed at least 0.06 away from both disks, and i.i.d. N(0, sigma_std^2)
+    surface charge per cell (used on dielectric facets)."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    ce, re = (0.5, 0.7), 0.1
+    cd, rd = (0.5, 0.3), 0.2
+    while True:
+        c = rng.uniform(0.1, 0.9, size=2)
+        de = math.hypot(c[0] - ce[0], c[1] - ce[1]) - re
+        dd = math.hypot(c[0] - cd[0], c[1] - cd[1]) - rd
+        if de >= 0.06 and dd >= 0.06:
+            break
+    sig = rng.normal(0.0, sigma_std, size=(n, n)) if sigma_std > 0 else None
+    Xn = _nodes(2, (n, n), h, (0.0, 0.0))
+    objs = [Obj(OBJ_ELECTRODE, 1.0, np.ascontiguousarray(sdf_sphere(Xn, ce, re))),
+            Obj(OBJ_DIELECTRIC, 4.0, np.ascontiguousarray(sdf_sphere(Xn, cd, rd)))]
+    x, y = _centres(2, (n, n), h, (0.0, 0.0))
+    rho = np.exp(-((x - c[0]) ** 2 + (y - c[1]) ** 2) / (2 * 0.02 ** 2))
+    k, v, a1, a2 = _bc(BC_DIRICHLET, 0.0)
+    return Problem(2, (n, n), h, (0.0, 0.0), objs, k, v, a1, a2,
+                   rho=np.ascontiguousarray(rho), sigma=sig,
+                   name=f"two-disks-{n}", seed=seed)
+
+
+def _blobs3(rng, nblob, dists):
+    cs, ss = [], []
+    for _ in range(nblob):
+        s = rng.uniform(0.01, 0.05)
+        while True:
+            c = np.array([rng.uniform(0.1, 0.9), rng.uniform(0.1, 0.9), rng.uniform(0.25, 0.95)])
+            if all(f(c) >= 3 * s for f in dists):
+                break
+        cs.append(c)
+        ss.append(s)
+    return cs, ss
+
+
+def _pin_distance_point(c, z_tip=0.6, r=0.02):
+    zc = z_tip + r
+    rxy = math.hypot(c[0] - 0.5, c[1] - 0.5)
+    if c[2] >= zc:
+        return rxy - r
+    return math.sqrt(rxy ** 2 + (c[2] - zc) ** 2) - r
+
+
+def pin_plane(n=256, seed=0, nblob=8):
+    """3D unit cube: pin of radius 0.02 on the axis (0.5,0.5) with a
+    hemispherical tip whose apex is at z=0.6, held at 1 and reaching the top
+    face; dielectric slab eps=4 for z<0.2; z- Dirichlet 0, z+ Dirichlet 1,
+    x/y faces homogeneous Neumann; rho = sum of 8 Gaussian blobs (amplitude 1,
+    standard deviations U[0.01,0.05]) kept 3 sigma away from pin and slab."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    dists = [_pin_distance_point, lambda c: c[2] - 0.2]
+    cs, ss = _blobs3(rng, nblob, dists)
+    Xn = _nodes(3, (n, n, n), h, (0.0, 0.0, 0.0))
+    objs = [Obj(OBJ_ELECTRODE, 1.0, np.ascontiguousarray(sdf_pin3(Xn, (0.5, 0.5), 0.6, 0.02))),
+            Obj(OBJ_DIELECTRIC, 4.0, np.ascontiguousarray(sdf_halfspace_below(Xn[2], 0.2)))]
+    X = _centres(3, (n, n, n), h, (0.0, 0.0, 0.0))
+    rho = np.zeros(X[0].shape)
+    for c, s in zip(cs, ss):
+        rho += np.exp(-((X[0] - c[0]) ** 2 + (X[1] - c[1]) ** 2 + (X[2] - c[2]) ** 2) / (2 * s * s))
+    kind = [BC_NEUMANN, BC_NEUMANN, BC_NEUMANN, BC_NEUMANN, BC_DIRICHLET, BC_DIRICHLET]
+    val = [0.0, 0.0, 0.0, 0.0, 0.0, 1.0]
+    return Problem(3, (n, n, n), h, (0.0, 0.0, 0.0), objs, kind, val, [0.0] * 6, [1.0] * 6,
+                   rho=np.ascontiguousarray(rho), name=f"pin-plane-{n}", seed=seed)
+
+
+def blade_plane(n=512, seed=0, nblob=8):
+    """2D analogue of the pin-plane class: a blade of half-width 0.02 with a
+    semicircular tip at y=0.6 reaching the top, dielectric slab y<0.2,
+    y- Dirichlet 0, y+ Dirichlet 1, x faces Neumann 0."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+
+    def dblade(c):
+        yc = 0.62
+        dx = abs(c[0] - 0.5)
+        return dx - 0.02 if c[1] >= yc else math.hypot(dx, c[1] - yc) - 0.02
+
+    cs, ss = [], []
+    for _ in range(nblob):
+        s = rng.uniform(0.01, 0.05)
+        while True:
+            c = np.array([rng.uniform(0.1, 0.9), rng.uniform(0.25, 0.95)])
+            if dblade(c) >= 3 * s and c[1] - 0.2 >= 3 * s:
+                break
+        cs.append(c)
+        ss.append(s)
+    Xn = _nodes(2, (n, n), h, (0.0, 0.0))
+    objs = [Obj(OBJ_ELECTRODE, 1.0, np.ascontiguousarray(sdf_blade2(Xn, 0.5, 0.6, 0.02))),
+            Obj(OBJ_DIELECTRIC, 4.0, np.ascontiguousarray(sdf_halfspace_below(Xn[1], 0.2)))]
+    X = _centres(2, (n, n), h, (0.0, 0.0))
+    rho = np.zeros(X[0].shape)
+    for c, s in zip(cs, ss):
+        rho += np.exp(-((X[0] - c[0]) ** 2 + (X[1] - c[1]) ** 2) / (2 * s * s))
+    kind = [BC_NEUMANN, BC_NEUMANN, BC_DIRICHLET, BC_DIRICHLET, BC_DIRICHLET, BC_DIRICHLET]
+    val = [0.0, 0.0, 0.0, 1.0, 0.0, 0.0]
+    return Problem(2, (n, n), h, (0.0, 0.0), objs, kind, val, [0.0] * 6, [1.0] * 6,
+                   rho=np.ascontiguousarray(rho), name=f"blade-plane-{n}", seed=seed)
+
+
+def eddington(dim, n, kappa_abs, seed=0, nblob=8):
+    """Eddington (SP1) stationary form kappa*phi - div((1/(3 kappa)) grad phi) = S
+    on the unit box, no embedded boundary, Robin outflow
+    d(phi)/dn + (3 kappa/2) phi = 0 on every face; S = Gaussian blob sum."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    nn = (n,) * dim
+    X = _centres(dim, nn, h, (0.0,) * dim)
+    S = np.zeros(X[0].shape)
+    for _ in range(nblob):
+        s = rng.uniform(0.01, 0.05)
+        c = rng.uniform(0.1, 0.9, size=dim)
+        S += np.exp(-sum((X[d] - c[d]) ** 2 for d in range(dim)) / (2 * s * s))
+    kind = [BC_ROBIN] * 6
+    return Problem(dim, nn, h, (0.0,) * dim, [], kind, [0.0] * 6, [1.5 * kappa_abs] * 6, [1.0] * 6,
+                   alpha=1.0, beta=-1.0, a_gas=kappa_abs, a_diel=kappa_abs,
+                   b_gas=1.0 / (3.0 * kappa_abs), rho=np.ascontiguousarray(S),
+                   name=f"eddington{dim}d-{n}-k{kappa_abs:.3g}", seed=seed)
+
+
+def coaxial(n=256, R0=0.3, R1=0.6, R2=0.9, eps=4.0, phi0=1.0, sigma=0.0):
+    """Coaxial cable cross-section on (-1,1)^2: inner electrode r<R0 at phi0,
+    dielectric shell R0<r<R1 with permittivity eps, gas R1<r<R2, outer
+    electrode r>R2 grounded. Optional uniform surface charge on r=R1."""
+    h = 2.0 / n
+    lo = (-1.0, -1.0)
+    Xn = _nodes(2, (n, n), h, lo)
+    r = np.sqrt(Xn[0] ** 2 + Xn[1] ** 2)
+    objs = [Obj(OBJ_ELECTRODE, phi0, np.ascontiguousarray(r - R0)),
+            Obj(OBJ_ELECTRODE, 0.0, np.ascontiguousarray(R2 - r)),
+            Obj(OBJ_DIELECTRIC, eps, np.ascontiguousarray(r - R1))]
+    k, v, a1, a2 = _bc(BC_DIRICHLET, 0.0)
+    sig = np.full((n, n), float(sigma)) if sigma != 0.0 else None
+    return Problem(2, (n, n), h, lo, objs, k, v, a1, a2,
+                   rho=np.zeros((n, n)), sigma=sig, name=f"coaxial-{n}")
+
+
+def random_box(rng):
+    """One box of the batched workload: edges 8*round(exp(U[ln16, ln64])/8),
+    h = 1/max edge, a random plane splitting eps in {1,2,4,8} (gas side and
+    dielectric side), a sphere electrode (phi=1, radius U[0.1,0.3]*shortest
+    edge, at least 2h inside the box), the plane redrawn while it passes within
+    r+2h of the sphere centre, Dirichlet 0 on the box, and a smooth source of
+    4 Fourier modes with wave vectors in {1,2,3}^3."""
+    n = tuple(int(8 * round(math.exp(rng.uniform(math.log(16), math.log(64))) / 8)) for _ in range(3))
+    h = 1.0 / max(n)
+    L = np.array([m * h for m in n])
+    lmin = L.min()
+    r = rng.uniform(0.1, 0.3) * lmin
+    c = np.array([rng.uniform(r + 2 * h, L[d] - r - 2 * h) for d in range(3)])
+    while True:
+        nv = rng.normal(size=3)
+        nv /= np.linalg.norm(nv)
+        p = rng.uniform(0.0, 1.0, size=3) * L
+        if abs(float(np.dot(c - p, nv))) > r + 2 * h:
+            break
+    eps_gas, eps_diel = rng.choice([1.0, 2.0, 4.0, 8.0], size=2)
+    modes = []
+    for _ in range(4):
+        k = rng.integers(1, 4, size=3)
+        A = rng.normal()
+        th = rng.uniform(0, 2 * math.pi)
+        modes.append((k, A, th))
+    Xn = _nodes(3, n, h, (0.0, 0.0, 0.0))
+    objs = [Obj(OBJ_ELECTRODE, 1.0, np.ascontiguousarray(sdf_sphere(Xn, c, r))),
+            Obj(OBJ_DIELECTRIC, float(eps_diel), np.ascontiguousarray(sdf_plane(Xn, p, nv)))]
+    X = _centres(3, n, h, (0.0, 0.0, 0.0))
+    rho = np.zeros(X[0].shape)
+    for k, A, th in modes:
+        rho += A * np.sin(2 * math.pi * sum(k[d] * X[d] / L[d] for d in range(3)) + th)
+    kk, v, a1, a2 = _bc(BC_DIRICHLET, 0.0)
+    return Problem(3, n, h, (0.0, 0.0, 0.0), objs, kk, v, a1, a2, b_gas=float(eps_gas),
+                   rho=np.ascontiguousarray(rho), name=f"box-{n[0]}x{n[1]}x{n[2]}")
+
+
+def batched_boxes(nbox=512, seed=0):
+    rng = np.random.default_rng(seed)
+    return [random_box(rng) for _ in range(nbox)]
+
+
+def serving_requests(nreq, rate, seed=0):
+    """Request stream: Poisson arrivals at ``rate`` per second; each request is
+    2D (n in {512,1024,2048}) or 3D (n in {32,64,128,256}) with equal odds, and
+    either a pin/blade Poisson solve or an Eddington Helmholtz solve with
+    kappa log-uniform in [1,100]. Returns (arrival times, list of specs); a
+    spec is materialised with ``make_request``."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=nreq))
+    specs = []
+    for i in range(nreq):
+        dim = 2 if rng.uniform() < 0.5 else 3
+        n = int(rng.choice([512, 1024, 2048])) if dim == 2 else int(rng.choice([32, 64, 128, 256]))
+        op = "poisson" if rng.uniform() < 0.5 else "helmholtz"
+        kappa = math.exp(rng.uniform(0.0, math.log(100.0)))
+        specs.append(dict(dim=dim, n=n, op=op, kappa=kappa, seed=int(rng.integers(1 << 31))))
+    return t, specs
+
+
+def make_request(spec):
+    if spec["op"] == "poisson":
+        if spec["dim"] == 3:
+            return pin_plane(spec["n"], seed=spec["seed"])
+        return blade_plane(spec["n"], seed=spec["seed"])
+    return eddington(spec["dim"], spec["n"], spec["kappa"], seed=spec["seed"])

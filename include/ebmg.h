@@ -1,0 +1,197 @@
+/*
+ * ebmg.h — C ABI of an embedded-boundary geometric-multigrid elliptic solver
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Helmholtz-equations section of Marskar, arXiv:1809.03745):
+ *     alpha a(x) phi + beta div( b(x) grad phi ) = rho        on a Cartesian box,
+ * Poisson being alpha = 0, beta = -1, b = relative permittivity (eps0 = 1, so
+ * rho means rho/eps0, electrodynamic-equations section). The box is cut by
+ * embedded boundaries given as signed-distance functions sampled at grid
+ * nodes (spatial-discretisation section): electrodes (Dirichlet), at most one
+ * dielectric object (a second material whose b is the object's value,
+ * coupled to the gas through the multifluid matching condition with surface
+ * charge sigma), and insulating walls (Neumann). Each cut cell carries volume
+ * fraction, face apertures and centroids, and a linearised boundary facet.
+ * The discrete system is the volume-weighted finite-volume form with
+ * centroid-interpolated face fluxes and ray-cast / least-squares boundary
+ * stencils (boundary-conditions subsection); it is solved by geometric
+ * multigrid V-cycles (multigrid-solver subsection) until
+ * ||r|| < rtol * ||r0||, r0 being the residual at phi = 0.
+ *
+ * Conventions (every entry point):
+ *  - Cell arrays are float64, contiguous, x fastest: index i + nx*(j + ny*k).
+ *  - Pointers documented as DEVICE are on the context's device (e.g. a torch
+ *    tensor's data_ptr()); HOST pointers are ordinary CPU memory.
+ *  - The caller owns every array it passes; the library keeps no caller
+ *    pointer after a call returns. The library owns each problem until
+ *    ebmg_release().
+ *  - All device work of a context is ordered on the context's stream. A
+ *    context is not thread-safe.
+ *  - Errors are reported only through ebmg_status; the library never aborts.
+ *    On EBMG_ERR_ARG / EBMG_ERR_GEOMETRY outputs are untouched. On
+ *    EBMG_ERR_NOCONV phi holds the last iterate and info is filled.
+ *    ebmg_last_error() gives a message owned by the context, valid until the
+ *    next call on that context.
+ */
+#ifndef EBMG_H
+#define EBMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EBMG_ABI_VERSION 1
+
+typedef enum {
+  EBMG_OK = 0,
+  EBMG_ERR_ARG = 1,       /* invalid argument or unsupported configuration   */
+  EBMG_ERR_GEOMETRY = 2,  /* saddle / multi-valued / doubly-cut cell, no stencil */
+  EBMG_ERR_OOM = 3,       /* device or host allocation failed, or over budget */
+  EBMG_ERR_DEVICE = 4,    /* HIP runtime error, or a solve on a host-only context */
+  EBMG_ERR_NOCONV = 5,    /* max_cycles reached before the tolerance          */
+  EBMG_ERR_NUMERIC = 6,   /* NaN/Inf in inputs or residual growth             */
+  EBMG_ERR_BUSY = 7
+} ebmg_status;
+
+typedef struct ebmg_ctx_s* ebmg_ctx;
+typedef struct ebmg_problem_s* ebmg_problem;
+typedef struct ebmg_batch_s* ebmg_batch;
+
+/* Box: dim in {2,3}; n[d] cells per axis (n[2] ignored in 2D); isotropic
+ * cell size h; lower corner lo. */
+typedef struct {
+  int32_t dim;
+  int32_t n[3];
+  double h;
+  double lo[3];
+} ebmg_box;
+
+enum { EBMG_OBJ_ELECTRODE = 0, EBMG_OBJ_DIELECTRIC = 1, EBMG_OBJ_WALL = 2 };
+
+/* Embedded object. sdf: HOST, prod(n[d]+1) doubles sampled at nodes
+ * lo + (i,j,k) h, x fastest, > 0 outside the object (copied at setup).
+ * value: electrode potential / dielectric permittivity / wall outward normal
+ * derivative dphi/dn. */
+typedef struct {
+  int32_t kind;
+  double value;
+  const double* sdf;
+} ebmg_object;
+
+enum { EBMG_BC_DIRICHLET = 0, EBMG_BC_NEUMANN = 1, EBMG_BC_ROBIN = 2 };
+
+/* Domain faces in the order x-, x+, y-, y+, z-, z+. value = Dirichlet value,
+ * Neumann outward normal derivative dphi/dn, or Robin a3 in
+ * a1 phi + a2 dphi/dn = a3 (n the outward normal). */
+typedef struct {
+  int32_t kind[6];
+  double value[6];
+  double robin_a1[6];
+  double robin_a2[6];
+} ebmg_domain_bc;
+
+enum { EBMG_FP64 = 0, EBMG_MIXED = 1 };
+
+typedef struct {
+  double alpha, beta;       /* equation coefficients (Poisson: 0, -1)            */
+  double a_gas, a_diel;     /* Helmholtz diagonal a per phase                    */
+  double b_gas;             /* gas-phase b; dielectric b is the object's value   */
+  int32_t dirichlet_closure;/* 0 linear two-point (default), 1 quadratic          */
+  int32_t robin_closure;    /* 0 linear extrapolation (default), 1 Taylor         */
+  int32_t eb_order;         /* Dirichlet EB stencil order: 2 (default) or 1       */
+  int32_t precision;        /* EBMG_FP64 or EBMG_MIXED (FP32 cycle, FP64 refinement) */
+  int32_t nu1, nu2;         /* pre/post smoothing sweeps (0 -> 2)                */
+  int32_t bottom_max_dof;   /* coarsen until at most this many unknowns (0 -> 600) */
+  int32_t krylov;           /* 0 auto (BiCGStab if any embedded object, else plain
+                               V-cycles), 1 plain V-cycles, 2 V-cycle-preconditioned
+                               BiCGStab                                          */
+  int32_t reserved[7];
+} ebmg_options;
+
+typedef struct {
+  int32_t cycles;           /* V-cycles performed                                 */
+  int32_t outer_iters;      /* FP64 outer iterations (refinement or BiCGStab)     */
+  int32_t levels;
+  int32_t n_hist;
+  double r0_norm;           /* ||b||_2 (residual at phi = 0)                      */
+  double rel_residual;      /* final ||b - A phi||_2 / ||b||_2 (FP64)             */
+  double seconds;           /* wall time of the solve call                        */
+  double hist[64];          /* relative residual after each cycle                 */
+} ebmg_solve_info;
+
+/* Fill defaults (Poisson, linear closures, order-2 EB stencils, FP64, V(2,2)). */
+void ebmg_default_options(ebmg_options* opt);
+
+int ebmg_abi_version(void);
+
+/* Create a context on a HIP device with a caller stream (NULL = a stream the
+ * library creates at default priority). device < 0 gives a host-only context
+ * that can set up and export problems but cannot solve (EBMG_ERR_DEVICE). */
+ebmg_status ebmg_create(int32_t device, void* hip_stream, ebmg_ctx* out);
+ebmg_status ebmg_destroy(ebmg_ctx ctx);
+const char* ebmg_last_error(ebmg_ctx ctx);
+
+/* Build geometry moments, the finest-level operator (cut-cell rows), the
+ * multigrid hierarchy and the bottom-level inverse on the host, and upload
+ * them (device contexts). Boundary-condition TYPES and object kinds are fixed
+ * here; values may change per solve. */
+ebmg_status ebmg_setup(ebmg_ctx ctx, const ebmg_box* box, int32_t nobj, const ebmg_object* objs,
+                       const ebmg_domain_bc* bc, const ebmg_options* opt, ebmg_problem* out);
+
+/* Sizes: cells, second-phase unknowns, levels, device bytes held. */
+ebmg_status ebmg_query(ebmg_problem pb, int64_t* n_cells, int64_t* n_phase2, int32_t* n_levels,
+                       int64_t* device_bytes);
+
+/* Sizes of multigrid level `level` (0 = finest): cells and second-phase unknowns. */
+ebmg_status ebmg_query_level(ebmg_problem pb, int32_t level, int64_t* n_cells, int64_t* n_phase2);
+
+/* HOST copies of a level's cell tags (0/1 regular gas/dielectric, 2 explicit
+ * row, 3 covered; +4 when the cell's children do not all map to its primary
+ * unknown), primary phase per cell and cell of each second-phase unknown. */
+ebmg_status ebmg_export_level(ebmg_problem pb, int32_t level, uint8_t* tag, int8_t* primary, int64_t* sec_cell);
+
+/* HOST copies of geometry for cross-checks. kappa: N per phase (phase 0/1);
+ * primary: N int8 (0 gas, 1 dielectric, -1 covered); sec_cell: n_phase2
+ * int64 cell of each second-phase unknown. Any pointer may be NULL. */
+ebmg_status ebmg_export_geometry(ebmg_problem pb, double* kappa_gas, double* kappa_diel,
+                                 int8_t* primary, int64_t* sec_cell);
+
+/* HOST CSR of the level-`level` operator over N+N2 unknowns (covered cells
+ * as identity rows). Call with row_ptr == NULL to get *nnz only. */
+ebmg_status ebmg_export_operator(ebmg_problem pb, int32_t level, int64_t* nnz, int64_t* row_ptr,
+                                 int64_t* cols, double* vals);
+
+/* HOST right-hand side b (N+N2) for the given data, from the stored boundary
+ * coefficients: b = kappa*rho - L(0). rho: N (primary unknowns); sigma: N or
+ * NULL; bc_values: 6 or NULL (setup values); obj_values: nobj or NULL. */
+ebmg_status ebmg_export_rhs(ebmg_problem pb, const double* rho, const double* sigma,
+                            const double* bc_values, const double* obj_values, double* b);
+
+/* Solve. rho, sigma (nullable), phi (in: initial guess, out: primary unknown
+ * per cell; covered cells 0), phi2 (nullable; second-phase unknowns, in/out),
+ * E (nullable; dim*N cell-centred field, component-major) are DEVICE arrays.
+ * bc_values (6) and obj_values (nobj) are HOST arrays or NULL (setup values).
+ * rtol: stop when ||b - A phi||_2 <= rtol ||b||_2. */
+ebmg_status ebmg_solve(ebmg_problem pb, const double* rho, const double* sigma,
+                       const double* bc_values, const double* obj_values, double rtol,
+                       int32_t max_cycles, double* phi, double* phi2, double* E,
+                       ebmg_solve_info* info);
+
+/* out = A [phi; phi2] (FP64, DEVICE arrays; phi2/out2 nullable when N2 = 0). */
+ebmg_status ebmg_apply(ebmg_problem pb, const double* phi, const double* phi2, double* out,
+                       double* out2);
+
+/* Cell-centred E = -grad(phi) from centroid-interpolated face fluxes for a
+ * given solution (DEVICE arrays; data as in ebmg_solve). */
+ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, const double* sigma,
+                        const double* bc_values, const double* obj_values, double* E);
+
+ebmg_status ebmg_release(ebmg_problem pb);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EBMG_H */

@@ -39,9 +39,16 @@ Readings where the text is silent, garbled or ambiguous:
     the cut cell itself is never used; first-order option: one plane,
     linear interpolation, (phi1 - phiB)/t1;
   * least-squares fallback when a ray stencil leaves the box or meets a
-    cell without an unknown of the phase: unknowns within 2 cells in the
-    quadrant of m, weights 1/|x_j - x_EB|^2, fit phi_j - phiB = g.(x_j - x_EB);
-    widen to all directions if the fit lacks rank D, else reject;
+    cell without an unknown of the phase: unknowns within 2 cells that lie
+    in front of the facet ((x_j - x_EB).m > 0, the side the phase occupies),
+    plus the centres of Dirichlet domain faces of those cells and of the cut
+    cell itself (known values; the cut cell's unknown is never used),
+    weights 1/|x_j - x_EB|^2, fit phi_j - phiB = g.(x_j - x_EB); the fit is
+    accepted when it has rank D and a negative weight on phiB (a one-sided
+    derivative); otherwise the radius grows to 3 cells; as a last resort
+    (slivers against box walls with no unknown in front of the facet), the
+    derivative toward the Dirichlet domain face that m faces most,
+    (m.n_w)(phi_wall - phiB)/d_w (d_w >= h/20); else the cell is rejected;
   * multifluid facet: eps_g dphi/dm_g + eps_s dphi/dm_s = -sigma (the sign that
     makes a thin layer of charge sigma/delta converge to it), phi_B eliminated;
   * EB wall (insulator without a phase): F_EB = b g.
@@ -302,22 +309,33 @@ class Builder:
     def _lsq(self, ic, p, xb, m):
         g = self.geo
         dim = g.dim
-        for quadrant in (True, False):
-            rows = []
-            for off in np.ndindex(*(5,) * dim):
-                o = [q - 2 for q in off]
-                r = max(abs(q) for q in o)
-                if r < 1:
-                    continue
-                if quadrant and any(o[d] * (1 if m[d] > 0 else (-1 if m[d] < 0 else 0)) < 0 for d in range(dim)):
-                    continue
+        h = g.h
+        mv = np.asarray(m, dtype=float)
+        for R in (2, 3):
+            rows = []   # (key, dx, weight); key = unknown index or ("face", f)
+            for off in np.ndindex(*(2 * R + 1,) * dim):
+                o = [q - R for q in off]
+                own = max(abs(q) for q in o) < 1
                 cell = [ic[d] + o[d] for d in range(dim)]
                 j = self.dof(cell, p)
                 if j < 0:
                     continue
-                xj = np.array([g.lo[d] + (cell[d] + 0.5) * g.h for d in range(dim)])
+                xj = np.array([g.lo[d] + (cell[d] + 0.5) * h for d in range(dim)])
                 dx = xj - xb
-                rows.append((j, dx, 1.0 / float(dx @ dx)))
+                if not own and float(dx @ mv) > 1e-9 * h:
+                    rows.append((j, dx, 1.0 / float(dx @ dx)))
+                # Dirichlet domain faces of this cell: known values
+                for d in range(dim):
+                    for side in (0, 1):
+                        if cell[d] != (g.n[d] - 1 if side else 0):
+                            continue
+                        f = 2 * d + side
+                        if self.prob.bc_kind[f] != W.BC_DIRICHLET:
+                            continue
+                        dw = dx.copy()
+                        dw[d] += 0.5 * h if side else -0.5 * h
+                        if float(dw @ mv) > 1e-9 * h:
+                            rows.append((("face", f), dw, 1.0 / float(dw @ dw)))
             if len(rows) < dim:
                 continue
             M = np.zeros((dim, dim))
@@ -327,22 +345,53 @@ class Builder:
             if np.linalg.det(M) <= 1e-10 * (tr / dim) ** dim:
                 continue
             Mi = np.linalg.inv(M)
-            mv = np.asarray(m, dtype=float)
             form = Form()
             wsum = 0.0
-            for j, dx, w in rows:
+            for key, dx, w in rows:
                 cj = w * float((Mi @ dx) @ mv)
-                form.c[j] = form.c.get(j, 0.0) + cj
+                if isinstance(key, tuple):
+                    form.d[key] = form.d.get(key, 0.0) + cj
+                else:
+                    form.c[key] = form.c.get(key, 0.0) + cj
                 wsum += cj
+            if wsum <= 0.0:
+                continue
             return -wsum, form
         raise GeometryError("no least-squares stencil at cell %s phase %d" % (ic, p))
+
+    def _wall(self, ic, p, xb, m):
+        """Last resort: derivative toward the Dirichlet domain face of the cut
+        cell that the direction m faces most, (m.n_w)(phi_wall - phiB)/d_w,
+        with d_w the distance from xb to that face (at least h/20)."""
+        g = self.geo
+        h = g.h
+        best = None
+        for d in range(g.dim):
+            for side in (0, 1):
+                if ic[d] != (g.n[d] - 1 if side else 0):
+                    continue
+                f = 2 * d + side
+                if self.prob.bc_kind[f] != W.BC_DIRICHLET:
+                    continue
+                mn = m[d] if side else -m[d]
+                if mn > 1e-12 and (best is None or mn > best[0] + 1e-12):
+                    best = (mn, d, side, f)
+        if best is None:
+            raise GeometryError("no boundary stencil at cell %s phase %d" % (ic, p))
+        mn, d, side, f = best
+        wall = g.lo[d] + (g.n[d] if side else 0) * h
+        dw = max(abs(wall - xb[d]), 0.05 * h)
+        return -mn / dw, Form(d={("face", f): mn / dw})
 
     def dphi_dm(self, ic, p, xb, m, order):
         """Derivative along unit m (into phase p) at xb: (w_B, Form over unknowns)."""
         r = self._ray(ic, p, xb, m, order)
         if r is not None:
             return r
-        return self._lsq(ic, p, xb, m)
+        try:
+            return self._lsq(ic, p, xb, m)
+        except GeometryError:
+            return self._wall(ic, p, xb, m)
 
     def eb_flux(self, ic, p):
         """Outward EB flux form of a cut unknown, with the EB area fraction."""

@@ -1,0 +1,447 @@
+// HIP kernels of the multigrid cycle (gfx950, wave64).
+//
+// Regular cells (tag 0/1) evaluate the (2D+1)-point template on the fly:
+//   (A x)_i = diag_i x_i + coff[p] * sum_{in-box nb} x_nb,
+//   diag_i  = d0[p] + sum_{domain faces touched} cb[f][p];
+// irregular unknowns (tag 2 cells and all second-phase unknowns) use explicit
+// sparse rows. Gauss-Seidel sweeps update red cells, then black cells (each
+// colour reads only the other colour), then the irregular rows class by class
+// (no row of a class reads another row of the same class), so every sweep is
+// race-free and bitwise deterministic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ebmg {
+
+template <typename T>
+struct Tmpl {
+  T coff[2];
+  T d0[2];
+  T cb[6][2];
+  int n[3];
+};
+
+constexpr int kBlock = 256;
+constexpr int kNormBlocks = 1024;
+
+__device__ __forceinline__ uint8_t tclass(uint8_t t) { return t & 3; }
+
+template <typename T, int DIM>
+__device__ __forceinline__ T template_apply(const T* __restrict__ x, const Tmpl<T>& tp, int i, int j, int k,
+                                            int64_t c, int p, T& diag) {
+  const int nx = tp.n[0], ny = tp.n[1];
+  T s = 0;
+  T dg = tp.d0[p];
+  if (i > 0) s += x[c - 1]; else dg += tp.cb[0][p];
+  if (i < nx - 1) s += x[c + 1]; else dg += tp.cb[1][p];
+  if (j > 0) s += x[c - nx]; else dg += tp.cb[2][p];
+  if (j < ny - 1) s += x[c + nx]; else dg += tp.cb[3][p];
+  if (DIM == 3) {
+    const int64_t sxy = (int64_t)nx * ny;
+    if (k > 0) s += x[c - sxy]; else dg += tp.cb[4][p];
+    if (k < tp.n[2] - 1) s += x[c + sxy]; else dg += tp.cb[5][p];
+  }
+  diag = dg;
+  return tp.coff[p] * s;
+}
+
+// Red/black Gauss-Seidel half-sweep over regular cells. One thread per cell
+// of the given colour: i = 2*ih + ((j + k + colour) & 1).
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_rb(const uint8_t* __restrict__ tag, T* __restrict__ x,
+                                               const T* __restrict__ b, Tmpl<T> tp, int colour) {
+  const int nxh = (tp.n[0] + 1) >> 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rows = (int64_t)tp.n[1] * (DIM == 3 ? tp.n[2] : 1);
+  if (t >= (int64_t)nxh * rows) return;
+  const int ih = (int)(t % nxh);
+  const int64_t jk = t / nxh;
+  const int j = (int)(jk % tp.n[1]);
+  const int k = DIM == 3 ? (int)(jk / tp.n[1]) : 0;
+  const int i = 2 * ih + ((j + k + colour) & 1);
+  if (i >= tp.n[0]) return;
+  const int64_t c = i + (int64_t)tp.n[0] * jk;
+  const uint8_t p = tclass(tag[c]);
+  if (p > 1) return;
+  T dg;
+  const T off = template_apply<T, DIM>(x, tp, i, j, k, c, p, dg);
+  x[c] = (b[c] - off) / dg;
+}
+
+// Gauss-Seidel update of one class of irregular rows.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_irr_gs(const int32_t* __restrict__ rows, int nrows,
+                                                   const int64_t* __restrict__ dof, const int64_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                   const T* __restrict__ diag, T* __restrict__ x,
+                                                   const T* __restrict__ b) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows) return;
+  const int r = rows[t];
+  T s = b[dof[r]];
+  for (int64_t e = rp[r]; e < rp[r + 1]; ++e) s -= val[e] * x[col[e]];
+  x[dof[r]] = s / diag[r];
+}
+
+// MODE 0: r = b - A x ; MODE 1: r = A x. Regular cells and covered cells.
+template <typename T, int DIM, int MODE>
+__global__ void __launch_bounds__(kBlock) k_resid_reg(const uint8_t* __restrict__ tag, const T* __restrict__ x,
+                                                      const T* __restrict__ b, T* __restrict__ r, Tmpl<T> tp) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = (int64_t)tp.n[0] * tp.n[1] * (DIM == 3 ? tp.n[2] : 1);
+  if (c >= N) return;
+  const uint8_t p = tclass(tag[c]);
+  if (p == 3) {
+    r[c] = MODE == 0 ? T(0) : x[c];
+    return;
+  }
+  if (p == 2) return;
+  const int i = (int)(c % tp.n[0]);
+  const int64_t jk = c / tp.n[0];
+  const int j = (int)(jk % tp.n[1]);
+  const int k = DIM == 3 ? (int)(jk / tp.n[1]) : 0;
+  T dg;
+  const T off = template_apply<T, DIM>(x, tp, i, j, k, c, p, dg);
+  const T ax = dg * x[c] + off;
+  r[c] = MODE == 0 ? b[c] - ax : ax;
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_resid_irr(int nrows, const int64_t* __restrict__ dof,
+                                                      const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                      const T* __restrict__ val, const T* __restrict__ diag,
+                                                      const T* __restrict__ x, const T* __restrict__ b,
+                                                      T* __restrict__ r) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows) return;
+  const int64_t q = dof[t];
+  T ax = diag[t] * x[q];
+  for (int64_t e = rp[t]; e < rp[t + 1]; ++e) ax += val[e] * x[col[e]];
+  r[q] = MODE == 0 ? b[q] - ax : ax;
+}
+
+// Restriction to simple coarse cells: mean of the 2^D children.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_restrict(const uint8_t* __restrict__ ctag, const T* __restrict__ rf,
+                                                     T* __restrict__ bc, int cnx, int cny, int cnz) {
+  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t NC = (int64_t)cnx * cny * (DIM == 3 ? cnz : 1);
+  if (P >= NC) return;
+  const uint8_t t = ctag[P];
+  if (tclass(t) == 3) {
+    bc[P] = 0;
+    return;
+  }
+  if (t & 4) return;
+  const int I = (int)(P % cnx);
+  const int64_t JK = P / cnx;
+  const int J = (int)(JK % cny);
+  const int K = DIM == 3 ? (int)(JK / cny) : 0;
+  const int fnx = 2 * cnx;
+  const int64_t fsxy = (int64_t)fnx * 2 * cny;
+  const int64_t c0 = 2 * I + (int64_t)fnx * (2 * J) + (DIM == 3 ? fsxy * (2 * K) : 0);
+  T s = rf[c0] + rf[c0 + 1] + rf[c0 + fnx] + rf[c0 + fnx + 1];
+  if (DIM == 3) s += rf[c0 + fsxy] + rf[c0 + fsxy + 1] + rf[c0 + fsxy + fnx] + rf[c0 + fsxy + fnx + 1];
+  bc[P] = s * (DIM == 3 ? T(0.125) : T(0.25));
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_restrict_ns(int n, const int64_t* __restrict__ cdof,
+                                                        const int32_t* __restrict__ ptr,
+                                                        const int64_t* __restrict__ child, const T* __restrict__ rf,
+                                                        T* __restrict__ bc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  T s = 0;
+  for (int e = ptr[t]; e < ptr[t + 1]; ++e) s += rf[child[e]];
+  bc[cdof[t]] = s * (DIM == 3 ? T(0.125) : T(0.25));
+}
+
+// Prolongation: x_f += e_c[parent] for fine cells of simple parents.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_prolong(const uint8_t* __restrict__ ftag, const uint8_t* __restrict__ ctag,
+                                                    const T* __restrict__ ec, T* __restrict__ xf, int fnx, int fny,
+                                                    int fnz) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = (int64_t)fnx * fny * (DIM == 3 ? fnz : 1);
+  if (c >= N) return;
+  if (tclass(ftag[c]) == 3) return;
+  const int i = (int)(c % fnx);
+  const int64_t jk = c / fnx;
+  const int j = (int)(jk % fny);
+  const int k = DIM == 3 ? (int)(jk / fny) : 0;
+  const int cnx = fnx >> 1, cny = fny >> 1;
+  const int64_t P = (i >> 1) + (int64_t)cnx * ((j >> 1) + (int64_t)cny * (k >> 1));
+  if (ctag[P] & 4) return;
+  xf[c] += ec[P];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_ns(int n, const int64_t* __restrict__ fdof,
+                                                       const int64_t* __restrict__ cdof, const T* __restrict__ ec,
+                                                       T* __restrict__ xf) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  xf[fdof[t]] += ec[cdof[t]];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ x, int64_t n, T v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] = v;
+}
+
+// Bottom solve x = Ainv b, one wavefront per row, FP64 accumulation.
+template <typename T>
+__global__ void __launch_bounds__(64) k_bottom(const double* __restrict__ Ainv, const T* __restrict__ b,
+                                               T* __restrict__ x, int n) {
+  const int row = blockIdx.x;
+  const int lane = threadIdx.x;
+  double s = 0;
+  for (int c = lane; c < n; c += 64) s += Ainv[(int64_t)row * n + c] * (double)b[c];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) x[row] = (T)s;
+}
+
+// Deterministic dot products: a fixed grid of per-block partials (wave64
+// shuffles, then a fixed-order sum of the block's waves), then one block sums
+// the partials in a fixed order. No atomics, so results are bitwise
+// reproducible for a given size.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dot_partial(const T* __restrict__ a, const T* __restrict__ b, int64_t n,
+                                                        double* __restrict__ part) {
+  __shared__ double sh[kBlock / 64];
+  double s = 0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    s += (double)a[t] * (double)b[t];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0;
+    for (int w = 0; w < kBlock / 64; ++w) tot += sh[w];
+    part[blockIdx.x] = tot;
+  }
+}
+
+// two dot products sharing one operand: (a, b) and (a, a)
+__global__ void __launch_bounds__(kBlock) k_dot2_partial(const double* __restrict__ a, const double* __restrict__ b,
+                                                         int64_t n, double* __restrict__ part) {
+  __shared__ double sh[2][kBlock / 64];
+  double s0 = 0, s1 = 0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const double av = a[t];
+    s0 += av * b[t];
+    s1 += av * av;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_down(s0, off, 64);
+    s1 += __shfl_down(s1, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = s0;
+    sh[1][threadIdx.x >> 6] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t0 = 0, t1 = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      t0 += sh[0][w];
+      t1 += sh[1][w];
+    }
+    part[blockIdx.x] = t0;
+    part[gridDim.x + blockIdx.x] = t1;
+  }
+}
+
+// sums `nvec` consecutive partial arrays of length n into out[0..nvec)
+__global__ void __launch_bounds__(kBlock) k_dot_final(const double* __restrict__ part, int n, int nvec,
+                                                      double* __restrict__ out) {
+  __shared__ double sh[kBlock / 64];
+  for (int v = 0; v < nvec; ++v) {
+    double s = 0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) s += part[v * n + t];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot = 0;
+      for (int w = 0; w < kBlock / 64; ++w) tot += sh[w];
+      out[v] = tot;
+    }
+    __syncthreads();
+  }
+}
+
+// BiCGStab scalars live on the device: slots of `sc`
+enum { SC_RHO = 0, SC_RHO_OLD, SC_ALPHA, SC_OMEGA, SC_RV, SC_TS, SC_TT, SC_RR, SC_NUM };
+
+__global__ void k_sc_reset(double* sc) {
+  sc[SC_RHO] = 1.0;
+  sc[SC_RHO_OLD] = 1.0;
+  sc[SC_ALPHA] = 1.0;
+  sc[SC_OMEGA] = 1.0;
+}
+
+__global__ void k_sc_alpha(double* sc) { sc[SC_ALPHA] = sc[SC_RHO] / sc[SC_RV]; }
+
+__global__ void k_sc_omega(double* sc) {
+  sc[SC_OMEGA] = sc[SC_TT] > 0.0 ? sc[SC_TS] / sc[SC_TT] : 0.0;
+  sc[SC_RHO_OLD] = sc[SC_RHO];
+}
+
+// p = r + beta (p - omega v), beta = (rho/rho_old)(alpha/omega)
+__global__ void __launch_bounds__(kBlock) k_bicg_p(double* __restrict__ p, const double* __restrict__ r,
+                                                   const double* __restrict__ v, const double* __restrict__ sc,
+                                                   int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double beta = (sc[SC_RHO] / sc[SC_RHO_OLD]) * (sc[SC_ALPHA] / sc[SC_OMEGA]);
+  p[t] = r[t] + beta * (p[t] - sc[SC_OMEGA] * v[t]);
+}
+
+// s = r - alpha v
+__global__ void __launch_bounds__(kBlock) k_bicg_s(double* __restrict__ s, const double* __restrict__ r,
+                                                   const double* __restrict__ v, const double* __restrict__ sc,
+                                                   int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  s[t] = r[t] - sc[SC_ALPHA] * v[t];
+}
+
+// x += alpha ph + omega sh ; r = s - omega t
+__global__ void __launch_bounds__(kBlock) k_bicg_xr(double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ ph, const double* __restrict__ sh,
+                                                    const double* __restrict__ s, const double* __restrict__ tv,
+                                                    const double* __restrict__ sc, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double a = sc[SC_ALPHA], w = sc[SC_OMEGA];
+  x[t] += a * ph[t] + w * sh[t];
+  r[t] = s[t] - w * tv[t];
+}
+
+template <typename S, typename D>
+__global__ void __launch_bounds__(kBlock) k_convert(const S* __restrict__ s, D* __restrict__ d, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) d[t] = (D)s[t];
+}
+
+__global__ void __launch_bounds__(kBlock) k_add_f32(double* __restrict__ x, const float* __restrict__ e, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] += (double)e[t];
+}
+
+// Right-hand side of regular and covered cells.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_rhs_reg(const uint8_t* __restrict__ tag, const double* __restrict__ rho,
+                                                    double* __restrict__ b, Tmpl<double> dat, int unused) {
+  (void)unused;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t N = (int64_t)dat.n[0] * dat.n[1] * (DIM == 3 ? dat.n[2] : 1);
+  if (c >= N) return;
+  const uint8_t p = tclass(tag[c]);
+  if (p == 3) {
+    b[c] = 0;
+    return;
+  }
+  if (p == 2) return;
+  const int i = (int)(c % dat.n[0]);
+  const int64_t jk = c / dat.n[0];
+  const int j = (int)(jk % dat.n[1]);
+  const int k = DIM == 3 ? (int)(jk / dat.n[1]) : 0;
+  double v = rho[c];
+  // dat.cb[f][p] holds dat[f][p] * value_f
+  if (i == 0) v -= dat.cb[0][p];
+  if (i == dat.n[0] - 1) v -= dat.cb[1][p];
+  if (j == 0) v -= dat.cb[2][p];
+  if (j == dat.n[1] - 1) v -= dat.cb[3][p];
+  if (DIM == 3) {
+    if (k == 0) v -= dat.cb[4][p];
+    if (k == dat.n[2] - 1) v -= dat.cb[5][p];
+  }
+  b[c] = v;
+}
+
+struct FaceVals {
+  double v[6];
+};
+
+__global__ void __launch_bounds__(kBlock) k_rhs_irr(int nrows, const int64_t* __restrict__ dof,
+                                                    const int64_t* __restrict__ cell, const double* __restrict__ src,
+                                                    const double* __restrict__ cface, const int32_t* __restrict__ obj,
+                                                    const double* __restrict__ cobj, const double* __restrict__ csig,
+                                                    const double* __restrict__ rho, const double* __restrict__ sigma,
+                                                    const double* __restrict__ objv, FaceVals fv,
+                                                    double* __restrict__ b) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows) return;
+  const int64_t c = cell[t];
+  double v = src[t] * rho[c];
+  for (int f = 0; f < 6; ++f) v -= cface[6 * t + f] * fv.v[f];
+  if (obj[t] >= 0) v -= cobj[t] * objv[obj[t]];
+  if (sigma) v -= csig[t] * sigma[c];
+  b[dof[t]] = v;
+}
+
+// Cell-centred E of regular cells (covered cells 0).
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_efield_reg(const uint8_t* __restrict__ tag, const double* __restrict__ x,
+                                                       double* __restrict__ E, Tmpl<double> ga, Tmpl<double> gbv,
+                                                       double inv_h) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nx = ga.n[0], ny = ga.n[1];
+  const int64_t N = (int64_t)nx * ny * (DIM == 3 ? ga.n[2] : 1);
+  if (c >= N) return;
+  const uint8_t p = tclass(tag[c]);
+  if (p == 3) {
+    for (int d = 0; d < DIM; ++d) E[d * N + c] = 0;
+    return;
+  }
+  if (p == 2) return;
+  const int i = (int)(c % nx);
+  const int64_t jk = c / nx;
+  const int j = (int)(jk % ny);
+  const int k = DIM == 3 ? (int)(jk / ny) : 0;
+  const int idx[3] = {i, j, k};
+  const int64_t stride[3] = {1, nx, (int64_t)nx * ny};
+  const double xc = x[c];
+  for (int d = 0; d < DIM; ++d) {
+    double glo, ghi;
+    // ga.cb[f][p] = closure coefficient on phi, gbv.cb[f][p] = coefficient * value
+    if (idx[d] > 0)
+      glo = (xc - x[c - stride[d]]) * inv_h;
+    else
+      glo = -(ga.cb[2 * d][p] * xc + gbv.cb[2 * d][p]);
+    if (idx[d] < ga.n[d] - 1)
+      ghi = (x[c + stride[d]] - xc) * inv_h;
+    else
+      ghi = ga.cb[2 * d + 1][p] * xc + gbv.cb[2 * d + 1][p];
+    E[d * N + c] = -0.5 * (glo + ghi);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_efield_irr(int ncell, int dim, int64_t N, const int64_t* __restrict__ ecell,
+                                                       const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val, const double* __restrict__ cface,
+                                                       const int32_t* __restrict__ obj, const double* __restrict__ cobj,
+                                                       const double* __restrict__ csig, const double* __restrict__ x,
+                                                       const double* __restrict__ sigma,
+                                                       const double* __restrict__ objv, FaceVals fv,
+                                                       double* __restrict__ E) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncell * dim) return;
+  const int q = t / dim, d = t % dim;
+  const int e = 3 * q + d;
+  const int64_t c = ecell[q];
+  double v = 0;
+  for (int64_t z = rp[e]; z < rp[e + 1]; ++z) v += val[z] * x[col[z]];
+  for (int f = 0; f < 6; ++f) v += cface[6 * e + f] * fv.v[f];
+  if (obj[e] >= 0) v += cobj[e] * objv[obj[e]];
+  if (sigma) v += csig[e] * sigma[c];
+  E[d * N + c] = v;
+}
+
+}  // namespace ebmg

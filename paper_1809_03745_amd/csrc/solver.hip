@@ -1,0 +1,923 @@
+// Solver driver and C ABI (see include/ebmg.h).
+//
+// Multigrid-solver subsection of arXiv:1809.03745: residual-correction
+// geometric multigrid, Gauss-Seidel relaxation (red-black here, plus the
+// irregular rows class by class), a direct bottom solve, and the stopping rule
+// ||r|| < rtol ||r0|| with r0 the residual at phi = 0 (= ||b||).
+// Mixed precision: the V-cycle (smoothing, restriction, prolongation) runs in
+// FP32 on the correction equation A e = r, with r = b - A phi formed in FP64,
+// the bottom level solved in FP64, and phi += e applied in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace ebmg {
+
+struct DeviceError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define HIPCHECK(expr)                                                                    \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw DeviceError(std::string(#expr) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  int64_t n = 0;
+  void alloc(int64_t count, int64_t& bytes) {
+    n = count;
+    if (count > 0) {
+      HIPCHECK(hipMalloc((void**)&p, sizeof(T) * count));
+      bytes += sizeof(T) * count;
+    }
+  }
+  void upload(const T* host, int64_t count, hipStream_t s, int64_t& bytes) {
+    alloc(count, bytes);
+    if (count > 0) HIPCHECK(hipMemcpyAsync(p, host, sizeof(T) * count, hipMemcpyHostToDevice, s));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+struct DevLevel {
+  int dim = 2;
+  int n[3] = {1, 1, 1};
+  int64_t N = 0, N2 = 0, R = 0;
+  DevBuf<uint8_t> tag;
+  DevBuf<int64_t> irow_dof, rp, ns_cdof, ns_child, np_fdof, np_cdof;
+  DevBuf<int32_t> col, cls_rows, ns_ptr;
+  DevBuf<double> val64, diag64;
+  DevBuf<float> val32, diag32;
+  std::vector<int32_t> cls_ptr;
+  int64_t n_ns = 0, n_np = 0;
+  Tmpl<double> t64;
+  Tmpl<float> t32;
+  // vectors
+  DevBuf<double> x64, b64, r64;
+  DevBuf<float> x32, b32, r32;
+  void release() {
+    tag.release(); irow_dof.release(); rp.release(); ns_cdof.release(); ns_child.release();
+    np_fdof.release(); np_cdof.release(); col.release(); cls_rows.release(); ns_ptr.release();
+    val64.release(); diag64.release(); val32.release(); diag32.release();
+    x64.release(); b64.release(); r64.release(); x32.release(); b32.release(); r32.release();
+  }
+};
+
+struct DevProblem {
+  std::vector<DevLevel> lv;
+  DevBuf<double> bottom;
+  int64_t bottom_n = 0;
+  // rhs data of irregular rows
+  DevBuf<int64_t> icell;
+  DevBuf<double> isrc, iface, icobj, icsig;
+  DevBuf<int32_t> iobj;
+  // E rows
+  DevBuf<int64_t> ecell, erp;
+  DevBuf<int32_t> ecol, eobj;
+  DevBuf<double> eval, eface, ecobj, ecsig;
+  DevBuf<double> objv;
+  DevBuf<double> part, scal;
+  double* host_scal = nullptr;
+  // BiCGStab work vectors: r, rh, p, v, ph, s, sh, t
+  DevBuf<double> kv[8];
+  bool krylov = false;
+  int64_t bytes = 0;
+  void release() {
+    for (auto& l : lv) l.release();
+    lv.clear();
+    bottom.release(); icell.release(); isrc.release(); iface.release(); icobj.release(); icsig.release();
+    iobj.release(); ecell.release(); erp.release(); ecol.release(); eobj.release(); eval.release();
+    eface.release(); ecobj.release(); ecsig.release(); objv.release(); part.release(); scal.release();
+    for (auto& k : kv) k.release();
+    if (host_scal) (void)hipHostFree(host_scal);
+    host_scal = nullptr;
+  }
+};
+
+}  // namespace ebmg
+
+struct ebmg_ctx_s {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+};
+
+struct ebmg_problem_s {
+  ebmg_ctx ctx = nullptr;
+  std::unique_ptr<ebmg::Problem> host;
+  ebmg::DevProblem dev;
+  bool on_device = false;
+};
+
+namespace ebmg {
+
+// ---------------------------------------------------------------------------
+// upload
+// ---------------------------------------------------------------------------
+template <typename T>
+static Tmpl<T> make_tmpl(const Level& L) {
+  Tmpl<T> t;
+  for (int p = 0; p < 2; ++p) {
+    t.coff[p] = (T)L.coff[p];
+    t.d0[p] = (T)L.d0[p];
+    for (int f = 0; f < 6; ++f) t.cb[f][p] = (T)L.cb[f][p];
+  }
+  for (int d = 0; d < 3; ++d) t.n[d] = L.g.n[d];
+  return t;
+}
+
+static void upload(ebmg_problem_s* P) {
+  Problem& H = *P->host;
+  DevProblem& D = P->dev;
+  hipStream_t s = P->ctx->stream;
+  int64_t& by = D.bytes;
+  const bool mixed = H.opt.precision == EBMG_MIXED;
+  D.lv.resize(H.levels.size());
+  for (size_t l = 0; l < H.levels.size(); ++l) {
+    const Level& L = H.levels[l];
+    DevLevel& d = D.lv[l];
+    d.dim = L.g.dim;
+    for (int e = 0; e < 3; ++e) d.n[e] = L.g.n[e];
+    d.N = L.N;
+    d.N2 = L.N2;
+    d.R = (int64_t)L.irow_dof.size();
+    d.tag.upload(L.tag.data(), L.N, s, by);
+    d.irow_dof.upload(L.irow_dof.data(), d.R, s, by);
+    d.rp.upload(L.rp.data(), d.R + 1, s, by);
+    d.col.upload(L.col.data(), (int64_t)L.col.size(), s, by);
+    d.cls_rows.upload(L.cls_rows.data(), (int64_t)L.cls_rows.size(), s, by);
+    d.cls_ptr = L.cls_ptr;
+    d.val64.upload(L.val.data(), (int64_t)L.val.size(), s, by);
+    d.diag64.upload(L.idiag.data(), d.R, s, by);
+    if (mixed) {
+      std::vector<float> v(L.val.begin(), L.val.end()), g(L.idiag.begin(), L.idiag.end());
+      d.val32.upload(v.data(), (int64_t)v.size(), s, by);
+      d.diag32.upload(g.data(), (int64_t)g.size(), s, by);
+      HIPCHECK(hipStreamSynchronize(s));
+    }
+    d.n_ns = (int64_t)L.ns_cdof.size();
+    d.ns_cdof.upload(L.ns_cdof.data(), d.n_ns, s, by);
+    d.ns_ptr.upload(L.ns_ptr.data(), (int64_t)L.ns_ptr.size(), s, by);
+    d.ns_child.upload(L.ns_child.data(), (int64_t)L.ns_child.size(), s, by);
+    d.n_np = (int64_t)L.np_fdof.size();
+    d.np_fdof.upload(L.np_fdof.data(), d.n_np, s, by);
+    d.np_cdof.upload(L.np_cdof.data(), d.n_np, s, by);
+    d.t64 = make_tmpl<double>(L);
+    d.t32 = make_tmpl<float>(L);
+    const int64_t nd = L.N + L.N2;
+    if (!mixed || l == 0) {
+      d.x64.alloc(nd, by);
+      d.b64.alloc(nd, by);
+      d.r64.alloc(nd, by);
+    }
+    if (mixed) {
+      d.x32.alloc(nd, by);
+      d.b32.alloc(nd, by);
+      d.r32.alloc(nd, by);
+    }
+  }
+  D.bottom_n = H.bottom_n;
+  D.bottom.upload(H.bottom_inv.data(), (int64_t)H.bottom_inv.size(), s, by);
+  // rhs data
+  const FineData& F = H.fine;
+  const Level& L0 = H.levels[0];
+  const int64_t R = (int64_t)L0.irow_dof.size();
+  std::vector<int64_t> icell(R);
+  std::vector<double> iface(6 * R), icobj(R), icsig(R);
+  std::vector<int32_t> iobj(R);
+  for (int64_t r = 0; r < R; ++r) {
+    const int64_t q = L0.irow_dof[r];
+    icell[r] = q < L0.N ? q : L0.sec_cell[q - L0.N];
+    for (int f = 0; f < 6; ++f) iface[6 * r + f] = F.idata[r].face[f];
+    iobj[r] = F.idata[r].obj;
+    icobj[r] = F.idata[r].cobj;
+    icsig[r] = F.idata[r].csig;
+  }
+  D.icell.upload(icell.data(), R, s, by);
+  D.isrc.upload(F.isrc.data(), R, s, by);
+  D.iface.upload(iface.data(), 6 * R, s, by);
+  D.iobj.upload(iobj.data(), R, s, by);
+  D.icobj.upload(icobj.data(), R, s, by);
+  D.icsig.upload(icsig.data(), R, s, by);
+  const int64_t NE = (int64_t)F.edata.size();
+  std::vector<double> eface(6 * NE), ecobj(NE), ecsig(NE);
+  std::vector<int32_t> eobj(NE);
+  for (int64_t e = 0; e < NE; ++e) {
+    for (int f = 0; f < 6; ++f) eface[6 * e + f] = F.edata[e].face[f];
+    eobj[e] = F.edata[e].obj;
+    ecobj[e] = F.edata[e].cobj;
+    ecsig[e] = F.edata[e].csig;
+  }
+  D.ecell.upload(F.ecell.data(), (int64_t)F.ecell.size(), s, by);
+  D.erp.upload(F.erp.data(), (int64_t)F.erp.size(), s, by);
+  D.ecol.upload(F.ecol.data(), (int64_t)F.ecol.size(), s, by);
+  D.eval.upload(F.eval.data(), (int64_t)F.eval.size(), s, by);
+  D.eface.upload(eface.data(), 6 * NE, s, by);
+  D.eobj.upload(eobj.data(), NE, s, by);
+  D.ecobj.upload(ecobj.data(), NE, s, by);
+  D.ecsig.upload(ecsig.data(), NE, s, by);
+  D.objv.alloc(std::max<int64_t>(1, (int64_t)H.geo.obj_value.size()), by);
+  D.part.alloc(2 * kNormBlocks, by);
+  D.scal.alloc(SC_NUM, by);
+  HIPCHECK(hipHostMalloc((void**)&D.host_scal, SC_NUM * sizeof(double), hipHostMallocDefault));
+  D.krylov = H.opt.krylov == 2;
+  if (D.krylov)
+    for (auto& k : D.kv) k.alloc(L0.N + L0.N2, by);
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// cycle pieces
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+  static double* x(DevLevel& l) { return l.x64.p; }
+  static double* b(DevLevel& l) { return l.b64.p; }
+  static double* r(DevLevel& l) { return l.r64.p; }
+  static const double* val(DevLevel& l) { return l.val64.p; }
+  static const double* diag(DevLevel& l) { return l.diag64.p; }
+  static const Tmpl<double>& t(DevLevel& l) { return l.t64; }
+};
+template <>
+struct Vec<float> {
+  static float* x(DevLevel& l) { return l.x32.p; }
+  static float* b(DevLevel& l) { return l.b32.p; }
+  static float* r(DevLevel& l) { return l.r32.p; }
+  static const float* val(DevLevel& l) { return l.val32.p; }
+  static const float* diag(DevLevel& l) { return l.diag32.p; }
+  static const Tmpl<float>& t(DevLevel& l) { return l.t32; }
+};
+
+template <typename T>
+static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
+  const Tmpl<T>& tp = Vec<T>::t(l);
+  const int64_t nxh = (l.n[0] + 1) / 2;
+  const int64_t nthr = nxh * l.n[1] * (l.dim == 3 ? l.n[2] : 1);
+  for (int it = 0; it < sweeps; ++it) {
+    for (int colour = 0; colour < 2; ++colour) {
+      if (l.dim == 3)
+        hipLaunchKernelGGL((k_rb<T, 3>), dim3(nblk(nthr)), dim3(kBlock), 0, s, l.tag.p, x, b, tp, colour);
+      else
+        hipLaunchKernelGGL((k_rb<T, 2>), dim3(nblk(nthr)), dim3(kBlock), 0, s, l.tag.p, x, b, tp, colour);
+    }
+    for (size_t c = 0; c + 1 < l.cls_ptr.size(); ++c) {
+      const int nr = l.cls_ptr[c + 1] - l.cls_ptr[c];
+      if (nr <= 0) continue;
+      hipLaunchKernelGGL((k_irr_gs<T>), dim3(nblk(nr)), dim3(kBlock), 0, s, l.cls_rows.p + l.cls_ptr[c], nr,
+                         l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b);
+    }
+  }
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename T, int MODE>
+static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
+  const Tmpl<T>& tp = Vec<T>::t(l);
+  if (l.dim == 3)
+    hipLaunchKernelGGL((k_resid_reg<T, 3, MODE>), dim3(nblk(l.N)), dim3(kBlock), 0, s, l.tag.p, x, b, r, tp);
+  else
+    hipLaunchKernelGGL((k_resid_reg<T, 2, MODE>), dim3(nblk(l.N)), dim3(kBlock), 0, s, l.tag.p, x, b, r, tp);
+  if (l.R > 0)
+    hipLaunchKernelGGL((k_resid_irr<T, MODE>), dim3(nblk(l.R)), dim3(kBlock), 0, s, (int)l.R, l.irow_dof.p, l.rp.p,
+                       l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, r);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename T>
+static void restrict_to(DevLevel& f, DevLevel& c, const T* rf, T* bc, hipStream_t s) {
+  if (f.dim == 3)
+    hipLaunchKernelGGL((k_restrict<T, 3>), dim3(nblk(c.N)), dim3(kBlock), 0, s, c.tag.p, rf, bc, c.n[0], c.n[1], c.n[2]);
+  else
+    hipLaunchKernelGGL((k_restrict<T, 2>), dim3(nblk(c.N)), dim3(kBlock), 0, s, c.tag.p, rf, bc, c.n[0], c.n[1], 1);
+  if (f.n_ns > 0) {
+    if (f.dim == 3)
+      hipLaunchKernelGGL((k_restrict_ns<T, 3>), dim3(nblk(f.n_ns)), dim3(kBlock), 0, s, (int)f.n_ns, f.ns_cdof.p,
+                         f.ns_ptr.p, f.ns_child.p, rf, bc);
+    else
+      hipLaunchKernelGGL((k_restrict_ns<T, 2>), dim3(nblk(f.n_ns)), dim3(kBlock), 0, s, (int)f.n_ns, f.ns_cdof.p,
+                         f.ns_ptr.p, f.ns_child.p, rf, bc);
+  }
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename T>
+static void prolong_from(DevLevel& f, DevLevel& c, const T* ec, T* xf, hipStream_t s) {
+  if (f.dim == 3)
+    hipLaunchKernelGGL((k_prolong<T, 3>), dim3(nblk(f.N)), dim3(kBlock), 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1],
+                       f.n[2]);
+  else
+    hipLaunchKernelGGL((k_prolong<T, 2>), dim3(nblk(f.N)), dim3(kBlock), 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1],
+                       1);
+  if (f.n_np > 0)
+    hipLaunchKernelGGL((k_prolong_ns<T>), dim3(nblk(f.n_np)), dim3(kBlock), 0, s, (int)f.n_np, f.np_fdof.p,
+                       f.np_cdof.p, ec, xf);
+  HIPCHECK(hipGetLastError());
+}
+
+template <typename T>
+static void fill(T* x, int64_t n, T v, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL((k_fill<T>), dim3(nblk(n)), dim3(kBlock), 0, s, x, n, v);
+}
+
+template <typename T>
+static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* x, const T* b) {
+  DevLevel& L = D.lv[l];
+  if (l + 1 == D.lv.size()) {
+    if (D.bottom.n > 0) {
+      hipLaunchKernelGGL((k_bottom<T>), dim3((unsigned)D.bottom_n), dim3(64), 0, s, D.bottom.p, b, x,
+                         (int)D.bottom_n);
+      HIPCHECK(hipGetLastError());
+    } else {
+      smooth<T>(L, x, b, 40, s);
+    }
+    return;
+  }
+  DevLevel& C = D.lv[l + 1];
+  smooth<T>(L, x, b, o.nu1, s);
+  T* r = Vec<T>::r(L);
+  residual<T, 0>(L, x, b, r, s);
+  restrict_to<T>(L, C, r, Vec<T>::b(C), s);
+  fill<T>(Vec<T>::x(C), C.N + C.N2, T(0), s);
+  vcycle<T>(D, o, l + 1, s, Vec<T>::x(C), Vec<T>::b(C));
+  prolong_from<T>(L, C, Vec<T>::x(C), x, s);
+  smooth<T>(L, x, b, o.nu2, s);
+}
+
+// preconditioner z = M r: one V-cycle from zero (FP64, or FP32 with the
+// input rounded to FP32 and the output widened to FP64)
+static void precond(DevProblem& D, const Options& o, const double* r, double* z, hipStream_t s) {
+  DevLevel& L = D.lv[0];
+  const int64_t nd = L.N + L.N2;
+  if (o.precision == EBMG_MIXED) {
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(nd)), dim3(kBlock), 0, s, r, L.b32.p, nd);
+    fill<float>(L.x32.p, nd, 0.0f, s);
+    vcycle<float>(D, o, 0, s, L.x32.p, L.b32.p);
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(nd)), dim3(kBlock), 0, s, L.x32.p, z, nd);
+  } else {
+    fill<double>(z, nd, 0.0, s);
+    vcycle<double>(D, o, 0, s, z, r);
+  }
+  HIPCHECK(hipGetLastError());
+}
+
+// deterministic dot product into device scalar slot `slot`
+template <typename T>
+static void dot_dev(DevProblem& D, const T* a, const T* b, int64_t n, int slot, hipStream_t s) {
+  hipLaunchKernelGGL((k_dot_partial<T>), dim3(kNormBlocks), dim3(kBlock), 0, s, a, b, n, D.part.p);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, s, D.part.p, kNormBlocks, 1, D.scal.p + slot);
+  HIPCHECK(hipGetLastError());
+}
+
+static void fetch_scalars(DevProblem& D, hipStream_t s) {
+  HIPCHECK(hipMemcpyAsync(D.host_scal, D.scal.p, SC_NUM * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+template <typename T>
+static double norm2(DevProblem& D, const T* r, int64_t n, hipStream_t s) {
+  dot_dev<T>(D, r, r, n, SC_RR, s);
+  fetch_scalars(D, s);
+  return std::sqrt(D.host_scal[SC_RR]);
+}
+
+static void rhs(ebmg_problem_s* P, const double* rho, const double* sigma, const double* bcv, const double* objv) {
+  Problem& H = *P->host;
+  DevProblem& D = P->dev;
+  DevLevel& L = D.lv[0];
+  hipStream_t s = P->ctx->stream;
+  FaceVals fv;
+  for (int f = 0; f < 6; ++f) fv.v[f] = bcv ? bcv[f] : H.bc.value[f];
+  const size_t no = H.geo.obj_value.size();
+  std::vector<double> ov(std::max<size_t>(1, no), 0.0);
+  for (size_t k = 0; k < no; ++k) ov[k] = objv ? objv[k] : H.geo.obj_value[k];
+  HIPCHECK(hipMemcpyAsync(D.objv.p, ov.data(), sizeof(double) * ov.size(), hipMemcpyHostToDevice, s));
+  Tmpl<double> dat;
+  for (int d = 0; d < 3; ++d) dat.n[d] = L.n[d];
+  for (int f = 0; f < 6; ++f)
+    for (int p = 0; p < 2; ++p) dat.cb[f][p] = H.fine.dat[f][p] * fv.v[f];
+  if (L.dim == 3)
+    hipLaunchKernelGGL((k_rhs_reg<3>), dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, rho, L.b64.p, dat, 0);
+  else
+    hipLaunchKernelGGL((k_rhs_reg<2>), dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, rho, L.b64.p, dat, 0);
+  if (L.R > 0)
+    hipLaunchKernelGGL(k_rhs_irr, dim3(nblk(L.R)), dim3(kBlock), 0, s, (int)L.R, L.irow_dof.p, D.icell.p, D.isrc.p,
+                       D.iface.p, D.iobj.p, D.icobj.p, D.icsig.p, rho, sigma, D.objv.p, fv, L.b64.p);
+  HIPCHECK(hipGetLastError());
+  // the host copy of ov must outlive the async copy
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+static void efield(ebmg_problem_s* P, const double* x, const double* sigma, const double* bcv, double* E) {
+  Problem& H = *P->host;
+  DevProblem& D = P->dev;
+  DevLevel& L = D.lv[0];
+  hipStream_t s = P->ctx->stream;
+  FaceVals fv;
+  for (int f = 0; f < 6; ++f) fv.v[f] = bcv ? bcv[f] : H.bc.value[f];
+  Tmpl<double> ga, gb;
+  for (int d = 0; d < 3; ++d) ga.n[d] = gb.n[d] = L.n[d];
+  for (int f = 0; f < 6; ++f)
+    for (int p = 0; p < 2; ++p) {
+      ga.cb[f][p] = H.fine.ega[f][p];
+      gb.cb[f][p] = H.fine.egb[f][p] * fv.v[f];
+    }
+  const double ih = 1.0 / H.levels[0].g.h;
+  if (L.dim == 3)
+    hipLaunchKernelGGL((k_efield_reg<3>), dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, x, E, ga, gb, ih);
+  else
+    hipLaunchKernelGGL((k_efield_reg<2>), dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, x, E, ga, gb, ih);
+  const int nc = (int)H.fine.ecell.size();
+  if (nc > 0)
+    hipLaunchKernelGGL(k_efield_irr, dim3(nblk((int64_t)nc * L.dim)), dim3(kBlock), 0, s, nc, L.dim, L.N, D.ecell.p,
+                       D.erp.p, D.ecol.p, D.eval.p, D.eface.p, D.eobj.p, D.ecobj.p, D.ecsig.p, x, sigma, D.objv.p,
+                       fv, E);
+  HIPCHECK(hipGetLastError());
+}
+
+// Right-preconditioned BiCGStab with the V-cycle as preconditioner; all
+// scalars stay on the device, one host synchronisation per iteration for the
+// convergence test. On entry L.x64 holds phi, L.r64 the residual b - A phi.
+static ebmg_status bicgstab(DevProblem& D, const Options& o, double bn, double rtol, int max_cycles, double& rel,
+                            int& cyc, ebmg_solve_info& info, hipStream_t s) {
+  DevLevel& L = D.lv[0];
+  const int64_t nd = L.N + L.N2;
+  double *r = D.kv[0].p, *rh = D.kv[1].p, *p = D.kv[2].p, *v = D.kv[3].p;
+  double *ph = D.kv[4].p, *sv = D.kv[5].p, *sh = D.kv[6].p, *t = D.kv[7].p;
+  double* x = L.x64.p;
+  const unsigned nb = nblk(nd);
+  auto restart = [&]() {
+    HIPCHECK(hipMemcpyAsync(r, L.r64.p, sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipMemcpyAsync(rh, L.r64.p, sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
+    fill<double>(p, nd, 0.0, s);
+    fill<double>(v, nd, 0.0, s);
+    hipLaunchKernelGGL(k_sc_reset, dim3(1), dim3(1), 0, s, D.scal.p);
+  };
+  restart();
+  int restarts = 0;
+  while (rel > rtol) {
+    if (cyc + 2 > max_cycles) return EBMG_ERR_NOCONV;
+    dot_dev<double>(D, rh, r, nd, SC_RHO, s);
+    hipLaunchKernelGGL(k_bicg_p, dim3(nb), dim3(kBlock), 0, s, p, r, v, D.scal.p, nd);
+    precond(D, o, p, ph, s);
+    residual<double, 1>(L, ph, nullptr, v, s);
+    dot_dev<double>(D, rh, v, nd, SC_RV, s);
+    hipLaunchKernelGGL(k_sc_alpha, dim3(1), dim3(1), 0, s, D.scal.p);
+    hipLaunchKernelGGL(k_bicg_s, dim3(nb), dim3(kBlock), 0, s, sv, r, v, D.scal.p, nd);
+    precond(D, o, sv, sh, s);
+    residual<double, 1>(L, sh, nullptr, t, s);
+    hipLaunchKernelGGL(k_dot2_partial, dim3(kNormBlocks), dim3(kBlock), 0, s, t, sv, nd, D.part.p);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, s, D.part.p, kNormBlocks, 2, D.scal.p + SC_TS);
+    hipLaunchKernelGGL(k_sc_omega, dim3(1), dim3(1), 0, s, D.scal.p);
+    hipLaunchKernelGGL(k_bicg_xr, dim3(nb), dim3(kBlock), 0, s, x, r, ph, sh, sv, t, D.scal.p, nd);
+    dot_dev<double>(D, r, r, nd, SC_RR, s);
+    HIPCHECK(hipGetLastError());
+    fetch_scalars(D, s);
+    cyc += 2;
+    ++info.outer_iters;
+    const double* h = D.host_scal;
+    double nrel = std::sqrt(h[SC_RR]) / bn;
+    const bool broke = !std::isfinite(nrel) || !std::isfinite(h[SC_ALPHA]) || h[SC_OMEGA] == 0.0 ||
+                       !std::isfinite(h[SC_OMEGA]);
+    if (info.n_hist < 64) info.hist[info.n_hist++] = nrel;
+    if (broke || nrel <= rtol) {
+      // confirm with the true residual (and restart from it if needed)
+      residual<double, 0>(L, x, L.b64.p, L.r64.p, s);
+      nrel = norm2<double>(D, L.r64.p, nd, s) / bn;
+      if (!std::isfinite(nrel) || nrel > 1e6) {
+        rel = nrel;
+        return EBMG_ERR_NUMERIC;
+      }
+      if (nrel > rtol) {
+        if (++restarts > 8) {
+          rel = nrel;
+          return EBMG_ERR_NOCONV;
+        }
+        restart();
+      }
+    } else if (nrel > 1e6) {
+      rel = nrel;
+      return EBMG_ERR_NUMERIC;
+    }
+    rel = nrel;
+  }
+  return EBMG_OK;
+}
+
+static ebmg_status solve(ebmg_problem_s* P, const double* rho, const double* sigma, const double* bcv,
+                         const double* objv, double rtol, int max_cycles, double* phi, double* phi2, double* E,
+                         ebmg_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  Problem& H = *P->host;
+  DevProblem& D = P->dev;
+  hipStream_t s = P->ctx->stream;
+  DevLevel& L = D.lv[0];
+  const int64_t nd = L.N + L.N2;
+  const bool mixed = H.opt.precision == EBMG_MIXED;
+  ebmg_solve_info loc;
+  std::memset(&loc, 0, sizeof(loc));
+  loc.levels = (int)D.lv.size();
+  rhs(P, rho, sigma, bcv, objv);
+  HIPCHECK(hipMemcpyAsync(L.x64.p, phi, sizeof(double) * L.N, hipMemcpyDeviceToDevice, s));
+  if (L.N2 > 0) {
+    if (phi2)
+      HIPCHECK(hipMemcpyAsync(L.x64.p + L.N, phi2, sizeof(double) * L.N2, hipMemcpyDeviceToDevice, s));
+    else
+      fill<double>(L.x64.p + L.N, L.N2, 0.0, s);
+  }
+  const double bn = norm2<double>(D, L.b64.p, nd, s);
+  loc.r0_norm = bn;
+  ebmg_status st = EBMG_OK;
+  if (!std::isfinite(bn)) {
+    st = EBMG_ERR_NUMERIC;
+  } else if (bn == 0.0) {
+    fill<double>(L.x64.p, nd, 0.0, s);
+    loc.rel_residual = 0.0;
+  } else {
+    residual<double, 0>(L, L.x64.p, L.b64.p, L.r64.p, s);
+    double rel = norm2<double>(D, L.r64.p, nd, s) / bn;
+    int cyc = 0;
+    if (D.krylov) {
+      st = bicgstab(D, H.opt, bn, rtol, max_cycles, rel, cyc, loc, s);
+    } else {
+      while (rel > rtol) {
+        if (cyc >= max_cycles) {
+          st = EBMG_ERR_NOCONV;
+          break;
+        }
+        if (mixed) {
+          hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(nd)), dim3(kBlock), 0, s, L.r64.p, L.b32.p, nd);
+          fill<float>(L.x32.p, nd, 0.0f, s);
+          vcycle<float>(D, H.opt, 0, s, L.x32.p, L.b32.p);
+          hipLaunchKernelGGL(k_add_f32, dim3(nblk(nd)), dim3(kBlock), 0, s, L.x64.p, L.x32.p, nd);
+          ++loc.outer_iters;
+        } else {
+          vcycle<double>(D, H.opt, 0, s, L.x64.p, L.b64.p);
+        }
+        ++cyc;
+        residual<double, 0>(L, L.x64.p, L.b64.p, L.r64.p, s);
+        double nrel = norm2<double>(D, L.r64.p, nd, s) / bn;
+        if (loc.n_hist < 64) loc.hist[loc.n_hist++] = nrel;
+        if (!std::isfinite(nrel) || nrel > 1e6) {
+          rel = nrel;
+          st = EBMG_ERR_NUMERIC;
+          break;
+        }
+        rel = nrel;
+      }
+    }
+    loc.cycles = cyc;
+    loc.rel_residual = rel;
+  }
+  HIPCHECK(hipMemcpyAsync(phi, L.x64.p, sizeof(double) * L.N, hipMemcpyDeviceToDevice, s));
+  if (phi2 && L.N2 > 0)
+    HIPCHECK(hipMemcpyAsync(phi2, L.x64.p + L.N, sizeof(double) * L.N2, hipMemcpyDeviceToDevice, s));
+  if (E) efield(P, L.x64.p, sigma, bcv, E);
+  HIPCHECK(hipStreamSynchronize(s));
+  loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = loc;
+  return st;
+}
+
+}  // namespace ebmg
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+using namespace ebmg;
+
+template <typename F>
+static ebmg_status guard(ebmg_ctx ctx, F&& f) {
+  try {
+    return f();
+  } catch (const ArgError& e) {
+    if (ctx) ctx->err = e.what();
+    return EBMG_ERR_ARG;
+  } catch (const GeomError& e) {
+    if (ctx) ctx->err = e.what();
+    return EBMG_ERR_GEOMETRY;
+  } catch (const DeviceError& e) {
+    if (ctx) ctx->err = e.what();
+    return std::string(e.what()).find("out of memory") != std::string::npos ? EBMG_ERR_OOM : EBMG_ERR_DEVICE;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->err = "host allocation failed";
+    return EBMG_ERR_OOM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->err = e.what();
+    return EBMG_ERR_ARG;
+  }
+}
+
+extern "C" {
+
+void ebmg_default_options(ebmg_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->alpha = 0.0;
+  o->beta = -1.0;
+  o->b_gas = 1.0;
+  o->eb_order = 2;
+  o->precision = EBMG_FP64;
+  o->nu1 = 2;
+  o->nu2 = 2;
+  o->bottom_max_dof = 600;
+}
+
+int ebmg_abi_version(void) { return EBMG_ABI_VERSION; }
+
+ebmg_status ebmg_create(int32_t device, void* stream, ebmg_ctx* out) {
+  if (!out) return EBMG_ERR_ARG;
+  *out = nullptr;
+  auto* c = new (std::nothrow) ebmg_ctx_s;
+  if (!c) return EBMG_ERR_OOM;
+  c->device = device;
+  if (device >= 0) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
+      delete c;
+      return EBMG_ERR_DEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+      delete c;
+      return EBMG_ERR_DEVICE;
+    }
+    if (stream) {
+      c->stream = (hipStream_t)stream;
+    } else {
+      if (hipStreamCreate(&c->stream) != hipSuccess) {
+        delete c;
+        return EBMG_ERR_DEVICE;
+      }
+      c->own_stream = true;
+    }
+  }
+  *out = c;
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_destroy(ebmg_ctx ctx) {
+  if (!ctx) return EBMG_ERR_ARG;
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return EBMG_OK;
+}
+
+const char* ebmg_last_error(ebmg_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+ebmg_status ebmg_setup(ebmg_ctx ctx, const ebmg_box* box, int32_t nobj, const ebmg_object* objs,
+                       const ebmg_domain_bc* bc, const ebmg_options* opt, ebmg_problem* out) {
+  if (!ctx || !box || !bc || !out || (nobj > 0 && !objs) || nobj < 0 || nobj > 64) {
+    if (ctx) ctx->err = "invalid argument to ebmg_setup";
+    return EBMG_ERR_ARG;
+  }
+  *out = nullptr;
+  return guard(ctx, [&]() -> ebmg_status {
+    ebmg_options o;
+    if (opt)
+      o = *opt;
+    else
+      ebmg_default_options(&o);
+    auto P = std::make_unique<ebmg_problem_s>();
+    P->ctx = ctx;
+    P->host = std::make_unique<Problem>();
+    Problem& H = *P->host;
+    H.opt.alpha = o.alpha;
+    H.opt.beta = o.beta;
+    H.opt.a_gas = o.a_gas;
+    H.opt.a_diel = o.a_diel;
+    H.opt.b_gas = o.b_gas;
+    H.opt.dirichlet_closure = o.dirichlet_closure;
+    H.opt.robin_closure = o.robin_closure;
+    H.opt.eb_order = o.eb_order == 1 ? 1 : 2;
+    H.opt.precision = o.precision;
+    H.opt.nu1 = o.nu1 > 0 ? o.nu1 : 2;
+    H.opt.nu2 = o.nu2 > 0 ? o.nu2 : 2;
+    H.opt.bottom_max = o.bottom_max_dof > 0 ? o.bottom_max_dof : 600;
+    if (o.krylov < 0 || o.krylov > 2) throw ArgError("bad krylov option");
+    H.opt.krylov = o.krylov == 0 ? (nobj > 0 ? 2 : 1) : o.krylov;
+    if (o.precision != EBMG_FP64 && o.precision != EBMG_MIXED) throw ArgError("bad precision");
+    if (!(o.beta != 0.0) || !std::isfinite(o.beta)) throw ArgError("beta must be nonzero");
+    H.bc = *bc;
+    for (int f = 0; f < 2 * box->dim && f < 6; ++f) {
+      if (bc->kind[f] < 0 || bc->kind[f] > 2) throw ArgError("bad boundary kind");
+      if (bc->kind[f] == EBMG_BC_ROBIN && !(bc->robin_a2[f] != 0.0)) throw ArgError("Robin a2 must be nonzero");
+    }
+    build_geometry(H.geo, *box, nobj, objs);
+    H.bph[0] = o.b_gas;
+    H.aph[0] = o.a_gas;
+    if (H.geo.nphase == 2) {
+      H.bph[1] = H.geo.obj_value[H.geo.diel_obj];
+      H.aph[1] = o.a_diel;
+    } else {
+      H.bph[1] = o.b_gas;
+      H.aph[1] = o.a_diel;
+    }
+    if (!(H.bph[0] > 0) || !(H.bph[1] > 0)) throw ArgError("b must be positive");
+    // a problem with no Dirichlet/Robin data and no mass term is singular
+    bool anchored = o.alpha != 0.0;
+    for (int f = 0; f < 2 * box->dim; ++f) anchored |= bc->kind[f] != EBMG_BC_NEUMANN;
+    for (int k = 0; k < nobj; ++k) anchored |= objs[k].kind == EBMG_OBJ_ELECTRODE;
+    if (!anchored) throw ArgError("pure Neumann problem is singular");
+    build_fine_level(H);
+    build_hierarchy(H);
+    if (ctx->device >= 0) {
+      HIPCHECK(hipSetDevice(ctx->device));
+      try {
+        upload(P.get());
+      } catch (...) {
+        P->dev.release();
+        throw;
+      }
+      P->on_device = true;
+    }
+    *out = P.release();
+    return EBMG_OK;
+  });
+}
+
+ebmg_status ebmg_query(ebmg_problem pb, int64_t* n_cells, int64_t* n_phase2, int32_t* n_levels,
+                       int64_t* device_bytes) {
+  if (!pb) return EBMG_ERR_ARG;
+  if (n_cells) *n_cells = pb->host->geo.N;
+  if (n_phase2) *n_phase2 = pb->host->geo.N2;
+  if (n_levels) *n_levels = (int32_t)pb->host->levels.size();
+  if (device_bytes) *device_bytes = pb->dev.bytes;
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_query_level(ebmg_problem pb, int32_t level, int64_t* n_cells, int64_t* n_phase2) {
+  if (!pb || level < 0 || level >= (int32_t)pb->host->levels.size()) return EBMG_ERR_ARG;
+  if (n_cells) *n_cells = pb->host->levels[level].N;
+  if (n_phase2) *n_phase2 = pb->host->levels[level].N2;
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_export_level(ebmg_problem pb, int32_t level, uint8_t* tag, int8_t* primary, int64_t* sec_cell) {
+  if (!pb || level < 0 || level >= (int32_t)pb->host->levels.size()) return EBMG_ERR_ARG;
+  const Level& L = pb->host->levels[level];
+  for (int64_t c = 0; c < L.N; ++c) {
+    if (tag) tag[c] = L.tag[c];
+    if (primary) primary[c] = L.primary[c];
+  }
+  if (sec_cell)
+    for (int64_t s = 0; s < L.N2; ++s) sec_cell[s] = L.sec_cell[s];
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_export_geometry(ebmg_problem pb, double* kg, double* kd, int8_t* primary, int64_t* sec_cell) {
+  if (!pb) return EBMG_ERR_ARG;
+  const Geometry& G = pb->host->geo;
+  for (int64_t c = 0; c < G.N; ++c) {
+    if (kg) kg[c] = G.kappa(0, c);
+    if (kd) kd[c] = G.kappa(1, c);
+    if (primary) primary[c] = G.primary[c];
+  }
+  if (sec_cell)
+    for (int64_t s = 0; s < G.N2; ++s) sec_cell[s] = G.sec_cell[s];
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_export_operator(ebmg_problem pb, int32_t level, int64_t* nnz, int64_t* row_ptr, int64_t* cols,
+                                 double* vals) {
+  if (!pb || !nnz || level < 0 || level >= (int32_t)pb->host->levels.size()) return EBMG_ERR_ARG;
+  return guard(pb->ctx, [&]() -> ebmg_status {
+    const Level& L = pb->host->levels[level];
+    const int64_t n = L.N + L.N2;
+    std::vector<std::pair<int64_t, double>> buf;
+    int64_t cnt = 0;
+    if (row_ptr) row_ptr[0] = 0;
+    for (int64_t q = 0; q < n; ++q) {
+      const int64_t cell = q < L.N ? q : L.sec_cell[q - L.N];
+      if (q < L.N && L.primary[cell] < 0) {
+        buf.assign(1, {q, 1.0});
+      } else {
+        double m;
+        L.row(q, m, buf);
+        bool found = false;
+        for (auto& e : buf)
+          if (e.first == q) {
+            e.second += m;
+            found = true;
+          }
+        if (!found) buf.emplace_back(q, m);
+      }
+      if (row_ptr) {
+        for (auto& e : buf) {
+          cols[cnt] = e.first;
+          vals[cnt] = e.second;
+          ++cnt;
+        }
+        row_ptr[q + 1] = cnt;
+      } else {
+        cnt += (int64_t)buf.size();
+      }
+    }
+    *nnz = cnt;
+    return EBMG_OK;
+  });
+}
+
+ebmg_status ebmg_export_rhs(ebmg_problem pb, const double* rho, const double* sigma, const double* bcv,
+                            const double* objv, double* b) {
+  if (!pb || !rho || !b) return EBMG_ERR_ARG;
+  return guard(pb->ctx, [&]() -> ebmg_status {
+    host_rhs(*pb->host, rho, sigma, bcv, objv, b);
+    return EBMG_OK;
+  });
+}
+
+ebmg_status ebmg_solve(ebmg_problem pb, const double* rho, const double* sigma, const double* bcv, const double* objv,
+                       double rtol, int32_t max_cycles, double* phi, double* phi2, double* E, ebmg_solve_info* info) {
+  if (!pb) return EBMG_ERR_ARG;
+  ebmg_ctx ctx = pb->ctx;
+  if (!rho || !phi || !(rtol > 0) || max_cycles < 0) {
+    ctx->err = "invalid argument to ebmg_solve";
+    return EBMG_ERR_ARG;
+  }
+  if (!pb->on_device) {
+    ctx->err = "problem is not on a device (host-only context)";
+    return EBMG_ERR_DEVICE;
+  }
+  return guard(ctx, [&]() -> ebmg_status {
+    HIPCHECK(hipSetDevice(ctx->device));
+    return solve(pb, rho, sigma, bcv, objv, rtol, max_cycles, phi, phi2, E, info);
+  });
+}
+
+ebmg_status ebmg_apply(ebmg_problem pb, const double* phi, const double* phi2, double* out, double* out2) {
+  if (!pb || !phi || !out) return EBMG_ERR_ARG;
+  if (!pb->on_device) return EBMG_ERR_DEVICE;
+  return guard(pb->ctx, [&]() -> ebmg_status {
+    HIPCHECK(hipSetDevice(pb->ctx->device));
+    DevLevel& L = pb->dev.lv[0];
+    hipStream_t s = pb->ctx->stream;
+    HIPCHECK(hipMemcpyAsync(L.x64.p, phi, sizeof(double) * L.N, hipMemcpyDeviceToDevice, s));
+    if (L.N2 > 0) {
+      if (!phi2 || !out2) throw ArgError("second-phase arrays required");
+      HIPCHECK(hipMemcpyAsync(L.x64.p + L.N, phi2, sizeof(double) * L.N2, hipMemcpyDeviceToDevice, s));
+    }
+    residual<double, 1>(L, L.x64.p, nullptr, L.r64.p, s);
+    HIPCHECK(hipMemcpyAsync(out, L.r64.p, sizeof(double) * L.N, hipMemcpyDeviceToDevice, s));
+    if (L.N2 > 0) HIPCHECK(hipMemcpyAsync(out2, L.r64.p + L.N, sizeof(double) * L.N2, hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    return EBMG_OK;
+  });
+}
+
+ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, const double* sigma,
+                        const double* bcv, const double* objv, double* E) {
+  if (!pb || !phi || !E) return EBMG_ERR_ARG;
+  if (!pb->on_device) return EBMG_ERR_DEVICE;
+  return guard(pb->ctx, [&]() -> ebmg_status {
+    HIPCHECK(hipSetDevice(pb->ctx->device));
+    DevProblem& D = pb->dev;
+    DevLevel& L = D.lv[0];
+    hipStream_t s = pb->ctx->stream;
+    const Problem& H = *pb->host;
+    const size_t no = H.geo.obj_value.size();
+    std::vector<double> ov(std::max<size_t>(1, no), 0.0);
+    for (size_t k = 0; k < no; ++k) ov[k] = objv ? objv[k] : H.geo.obj_value[k];
+    HIPCHECK(hipMemcpyAsync(D.objv.p, ov.data(), sizeof(double) * ov.size(), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(L.x64.p, phi, sizeof(double) * L.N, hipMemcpyDeviceToDevice, s));
+    if (L.N2 > 0) {
+      if (!phi2) throw ArgError("second-phase array required");
+      HIPCHECK(hipMemcpyAsync(L.x64.p + L.N, phi2, sizeof(double) * L.N2, hipMemcpyDeviceToDevice, s));
+    }
+    efield(pb, L.x64.p, sigma, bcv, E);
+    HIPCHECK(hipStreamSynchronize(s));
+    return EBMG_OK;
+  });
+}
+
+ebmg_status ebmg_release(ebmg_problem pb) {
+  if (!pb) return EBMG_ERR_ARG;
+  if (pb->on_device) {
+    (void)hipSetDevice(pb->ctx->device);
+    (void)hipStreamSynchronize(pb->ctx->stream);
+    pb->dev.release();
+  }
+  delete pb;
+  return EBMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,288 @@
+"""ctypes binding of libebmg.so (include/ebmg.h). Argument marshalling only:
+every step of setup and solve runs in the library (host C++ setup, HIP
+kernels for the solve). The library must have been built
+(``paper_1809_03745_amd.build``); importing this module fails loudly if it
+is missing.
+
+Device arrays are passed as torch tensors (their data_ptr on the context's
+device); host arrays as numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libebmg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libebmg.so is not built: run `python -m paper_1809_03745_amd.build` "
+                      "(or __graft_entry__.build()) first")
+
+_lib = C.CDLL(LIB_PATH)
+
+OK, ERR_ARG, ERR_GEOMETRY, ERR_OOM, ERR_DEVICE, ERR_NOCONV, ERR_NUMERIC, ERR_BUSY = range(8)
+STATUS_NAMES = ["OK", "ERR_ARG", "ERR_GEOMETRY", "ERR_OOM", "ERR_DEVICE", "ERR_NOCONV", "ERR_NUMERIC",
+                "ERR_BUSY"]
+FP64, MIXED = 0, 1
+
+
+class EbmgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 8 else status}: {msg}")
+        self.status = status
+
+
+class Box(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("h", C.c_double), ("lo", C.c_double * 3)]
+
+
+class Object(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("value", C.c_double), ("sdf", C.POINTER(C.c_double))]
+
+
+class DomainBC(C.Structure):
+    _fields_ = [("kind", C.c_int32 * 6), ("value", C.c_double * 6), ("robin_a1", C.c_double * 6),
+                ("robin_a2", C.c_double * 6)]
+
+
+class Options(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("beta", C.c_double), ("a_gas", C.c_double), ("a_diel", C.c_double),
+                ("b_gas", C.c_double), ("dirichlet_closure", C.c_int32), ("robin_closure", C.c_int32),
+                ("eb_order", C.c_int32), ("precision", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
+                ("bottom_max_dof", C.c_int32), ("krylov", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("outer_iters", C.c_int32), ("levels", C.c_int32), ("n_hist", C.c_int32),
+                ("r0_norm", C.c_double), ("rel_residual", C.c_double), ("seconds", C.c_double),
+                ("hist", C.c_double * 64)]
+
+    def as_dict(self):
+        return dict(cycles=self.cycles, outer_iters=self.outer_iters, levels=self.levels,
+                    r0_norm=self.r0_norm, rel_residual=self.rel_residual, seconds=self.seconds,
+                    hist=[self.hist[i] for i in range(self.n_hist)])
+
+
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+_i64p = C.POINTER(C.c_int64)
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("ebmg_default_options", None, [C.POINTER(Options)])
+_sig("ebmg_abi_version", C.c_int, [])
+_sig("ebmg_create", C.c_int, [C.c_int32, _vp, C.POINTER(_vp)])
+_sig("ebmg_destroy", C.c_int, [_vp])
+_sig("ebmg_last_error", C.c_char_p, [_vp])
+_sig("ebmg_setup", C.c_int, [_vp, C.POINTER(Box), C.c_int32, C.POINTER(Object), C.POINTER(DomainBC),
+                             C.POINTER(Options), C.POINTER(_vp)])
+_sig("ebmg_query", C.c_int, [_vp, _i64p, _i64p, C.POINTER(C.c_int32), _i64p])
+_sig("ebmg_query_level", C.c_int, [_vp, C.c_int32, _i64p, _i64p])
+_sig("ebmg_export_level", C.c_int, [_vp, C.c_int32, _vp, _vp, _vp])
+_sig("ebmg_export_geometry", C.c_int, [_vp, _vp, _vp, _vp, _vp])
+_sig("ebmg_export_operator", C.c_int, [_vp, C.c_int32, _i64p, _vp, _vp, _vp])
+_sig("ebmg_export_rhs", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp])
+_sig("ebmg_solve", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int32, _vp, _vp, _vp,
+                             C.POINTER(SolveInfo)])
+_sig("ebmg_apply", C.c_int, [_vp, _vp, _vp, _vp, _vp])
+_sig("ebmg_efield", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp])
+_sig("ebmg_release", C.c_int, [_vp])
+
+EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_destroy", "ebmg_last_error",
+            "ebmg_setup", "ebmg_query", "ebmg_query_level", "ebmg_export_level",
+            "ebmg_export_geometry", "ebmg_export_operator", "ebmg_export_rhs",
+            "ebmg_solve", "ebmg_apply", "ebmg_efield", "ebmg_release"]
+
+
+def abi_version():
+    return _lib.ebmg_abi_version()
+
+
+def _ptr(a):
+    """Address of a numpy array (host) or torch tensor (device); None -> NULL."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _host_f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Context:
+    """A device (>= 0) with a HIP stream, or a host-only context (device < 0)."""
+
+    def __init__(self, device=0, stream=None):
+        h = _vp()
+        st = _lib.ebmg_create(int(device), stream, C.byref(h))
+        if st != OK:
+            raise EbmgError(st, "ebmg_create failed")
+        self.h = h
+        self.device = device
+
+    def check(self, st, what):
+        if st != OK:
+            msg = _lib.ebmg_last_error(self.h).decode(errors="replace")
+            raise EbmgError(st, f"{what}: {msg}")
+
+    def close(self):
+        if self.h:
+            _lib.ebmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+KRYLOV_AUTO, KRYLOV_NONE, KRYLOV_BICGSTAB = 0, 1, 2
+
+
+def make_options(prob, precision=FP64, dirichlet_closure=0, robin_closure=0, eb_order=2, nu1=2, nu2=2,
+                 bottom_max_dof=0, krylov=KRYLOV_AUTO):
+    o = Options()
+    _lib.ebmg_default_options(C.byref(o))
+    o.alpha = prob.alpha
+    o.beta = prob.beta
+    o.a_gas = prob.a_gas
+    o.a_diel = prob.a_diel
+    o.b_gas = prob.b_gas
+    o.dirichlet_closure = dirichlet_closure
+    o.robin_closure = robin_closure
+    o.eb_order = eb_order
+    o.precision = precision
+    o.nu1 = nu1
+    o.nu2 = nu2
+    o.bottom_max_dof = bottom_max_dof
+    o.krylov = krylov
+    return o
+
+
+class Problem:
+    """A problem set up in the library from a ``workloads.Problem``."""
+
+    def __init__(self, ctx, prob, **opts):
+        self.ctx = ctx
+        self.prob = prob
+        box = Box()
+        box.dim = prob.dim
+        for d in range(3):
+            box.n[d] = prob.n[d] if d < prob.dim else 1
+            box.lo[d] = prob.lo[d] if d < prob.dim else 0.0
+        box.h = prob.h
+        self._sdf = [np.ascontiguousarray(o.sdf, dtype=np.float64) for o in prob.objects]
+        objs = (Object * max(1, len(prob.objects)))()
+        for k, o in enumerate(prob.objects):
+            objs[k].kind = o.kind
+            objs[k].value = o.value
+            objs[k].sdf = self._sdf[k].ctypes.data_as(_dp)
+        bc = DomainBC()
+        for f in range(6):
+            bc.kind[f] = prob.bc_kind[f]
+            bc.value[f] = prob.bc_value[f]
+            bc.robin_a1[f] = prob.robin_a1[f]
+            bc.robin_a2[f] = prob.robin_a2[f]
+        self.options = make_options(prob, **opts)
+        h = _vp()
+        st = _lib.ebmg_setup(ctx.h, C.byref(box), len(prob.objects), objs, C.byref(bc), C.byref(self.options),
+                             C.byref(h))
+        self._sdf = None
+        ctx.check(st, "ebmg_setup")
+        self.h = h
+        n, n2, lev, by = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int64()
+        ctx.check(_lib.ebmg_query(h, C.byref(n), C.byref(n2), C.byref(lev), C.byref(by)), "ebmg_query")
+        self.N, self.N2, self.levels, self.device_bytes = n.value, n2.value, lev.value, by.value
+
+    # -- host exports ----------------------------------------------------------
+    def geometry(self):
+        kg = np.zeros(self.N)
+        kd = np.zeros(self.N)
+        pr = np.zeros(self.N, np.int8)
+        sc = np.zeros(max(1, self.N2), np.int64)
+        self.ctx.check(_lib.ebmg_export_geometry(self.h, _ptr(kg), _ptr(kd), _ptr(pr), _ptr(sc)),
+                       "ebmg_export_geometry")
+        return kg, kd, pr, sc[:self.N2]
+
+    def level_size(self, level):
+        n, n2 = C.c_int64(), C.c_int64()
+        self.ctx.check(_lib.ebmg_query_level(self.h, level, C.byref(n), C.byref(n2)), "ebmg_query_level")
+        return n.value, n2.value
+
+    def level_arrays(self, level):
+        """(tag, primary, sec_cell) host arrays of a multigrid level."""
+        n, n2 = self.level_size(level)
+        tag = np.zeros(n, np.uint8)
+        prim = np.zeros(n, np.int8)
+        sc = np.zeros(max(1, n2), np.int64)
+        self.ctx.check(_lib.ebmg_export_level(self.h, level, _ptr(tag), _ptr(prim), _ptr(sc)), "ebmg_export_level")
+        return tag, prim, sc[:n2]
+
+    def operator(self, level=0):
+        """Host CSR (scipy) of the level's operator over its N + N2 unknowns."""
+        import scipy.sparse as sp
+        n, n2 = self.level_size(level)
+        nd = n + n2
+        nnz = C.c_int64()
+        self.ctx.check(_lib.ebmg_export_operator(self.h, level, C.byref(nnz), None, None, None), "export")
+        rp = np.zeros(nd + 1, np.int64)
+        cols = np.zeros(nnz.value, np.int64)
+        vals = np.zeros(nnz.value)
+        self.ctx.check(_lib.ebmg_export_operator(self.h, level, C.byref(nnz), _ptr(rp), _ptr(cols), _ptr(vals)),
+                       "export")
+        return sp.csr_matrix((vals, cols, rp), shape=(nd, nd))
+
+    def rhs(self, rho=None, sigma=None, bc_values=None, obj_values=None):
+        rho = _host_f64(self.prob.rho if rho is None else rho).ravel()
+        sig = self.prob.sigma if sigma is None else sigma
+        sig = None if sig is None else _host_f64(sig).ravel()
+        bcv = _host_f64(bc_values)
+        ov = _host_f64(obj_values)
+        b = np.zeros(self.N + self.N2)
+        self.ctx.check(_lib.ebmg_export_rhs(self.h, _ptr(rho), _ptr(sig), _ptr(bcv), _ptr(ov), _ptr(b)),
+                       "ebmg_export_rhs")
+        return b
+
+    # -- device calls (torch tensors) -------------------------------------------
+    def solve(self, rho, phi, sigma=None, phi2=None, E=None, rtol=1e-10, max_cycles=100, bc_values=None,
+              obj_values=None, check=True):
+        info = SolveInfo()
+        bcv = _host_f64(bc_values)
+        ov = _host_f64(obj_values)
+        st = _lib.ebmg_solve(self.h, _ptr(rho), _ptr(sigma), _ptr(bcv), _ptr(ov), float(rtol), int(max_cycles),
+                             _ptr(phi), _ptr(phi2), _ptr(E), C.byref(info))
+        if check:
+            self.ctx.check(st, "ebmg_solve")
+        return st, info.as_dict()
+
+    def apply(self, phi, phi2, out, out2):
+        self.ctx.check(_lib.ebmg_apply(self.h, _ptr(phi), _ptr(phi2), _ptr(out), _ptr(out2)), "ebmg_apply")
+
+    def efield(self, phi, phi2, E, sigma=None, bc_values=None, obj_values=None):
+        bcv = _host_f64(bc_values)
+        ov = _host_f64(obj_values)
+        self.ctx.check(_lib.ebmg_efield(self.h, _ptr(phi), _ptr(phi2), _ptr(sigma), _ptr(bcv), _ptr(ov), _ptr(E)),
+                       "ebmg_efield")
+
+    def release(self):
+        if getattr(self, "h", None):
+            _lib.ebmg_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass

@@ -131,6 +131,8 @@ int ebmg_abi_version(void);
  * that can set up and export problems but cannot solve (EBMG_ERR_DEVICE). */
 ebmg_status ebmg_create(int32_t device, void* hip_stream, ebmg_ctx* out);
 ebmg_status ebmg_destroy(ebmg_ctx ctx);
+/* Message of the last failing call on ctx; with ctx == NULL, of the calling
+ * thread's last failing ebmg_create. */
 const char* ebmg_last_error(ebmg_ctx ctx);
 
 /* Build geometry moments, the finest-level operator (cut-cell rows), the
@@ -187,6 +189,15 @@ ebmg_status ebmg_apply(ebmg_problem pb, const double* phi, const double* phi2, d
  * given solution (DEVICE arrays; data as in ebmg_solve). */
 ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, const double* sigma,
                         const double* bc_values, const double* obj_values, double* E);
+
+/* Measurement hook: launch one kernel `reps` times on the context stream
+ * between two HIP events and report the mean duration per launch (ms) and
+ * the kernel's algorithmic bytes per launch. which = 0: red/black smoother
+ * half-sweep of level `level` (FP32 for mixed-precision problems, else
+ * FP64); 1: FP64 residual of level `level`. Overwrites the level's work
+ * vectors. */
+ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int32_t reps, double* avg_ms,
+                             double* alg_bytes);
 
 ebmg_status ebmg_release(ebmg_problem pb);
 

@@ -645,6 +645,8 @@ void ebmg_default_options(ebmg_options* o) {
 
 int ebmg_abi_version(void) { return EBMG_ABI_VERSION; }
 
+static thread_local std::string g_create_error;
+
 ebmg_status ebmg_create(int32_t device, void* stream, ebmg_ctx* out) {
   if (!out) return EBMG_ERR_ARG;
   *out = nullptr;
@@ -653,22 +655,22 @@ ebmg_status ebmg_create(int32_t device, void* stream, ebmg_ctx* out) {
   c->device = device;
   if (device >= 0) {
     int n = 0;
-    if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
-      delete c;
-      return EBMG_ERR_DEVICE;
-    }
-    if (hipSetDevice(device) != hipSuccess) {
-      delete c;
-      return EBMG_ERR_DEVICE;
-    }
-    if (stream) {
-      c->stream = (hipStream_t)stream;
-    } else {
-      if (hipStreamCreate(&c->stream) != hipSuccess) {
-        delete c;
-        return EBMG_ERR_DEVICE;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e == hipSuccess && device >= n) e = hipErrorInvalidDevice;
+    if (e == hipSuccess) e = hipSetDevice(device);
+    if (e == hipSuccess) {
+      if (stream) {
+        c->stream = (hipStream_t)stream;
+      } else {
+        e = hipStreamCreate(&c->stream);
+        c->own_stream = e == hipSuccess;
       }
-      c->own_stream = true;
+    }
+    if (e != hipSuccess) {
+      g_create_error = std::string("device ") + std::to_string(device) + " (" + std::to_string(n) +
+                       " visible): " + hipGetErrorString(e);
+      delete c;
+      return EBMG_ERR_DEVICE;
     }
   }
   *out = c;
@@ -682,7 +684,7 @@ ebmg_status ebmg_destroy(ebmg_ctx ctx) {
   return EBMG_OK;
 }
 
-const char* ebmg_last_error(ebmg_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* ebmg_last_error(ebmg_ctx ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 
 ebmg_status ebmg_setup(ebmg_ctx ctx, const ebmg_box* box, int32_t nobj, const ebmg_object* objs,
                        const ebmg_domain_bc* bc, const ebmg_options* opt, ebmg_problem* out) {
@@ -905,6 +907,81 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
     }
     efield(pb, L.x64.p, sigma, bcv, E);
     HIPCHECK(hipStreamSynchronize(s));
+    return EBMG_OK;
+  });
+}
+
+ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int32_t reps, double* avg_ms,
+                             double* alg_bytes) {
+  if (!pb || !avg_ms || reps <= 0) return EBMG_ERR_ARG;
+  if (!pb->on_device) return EBMG_ERR_DEVICE;
+  if (level < 0 || level >= (int32_t)pb->dev.lv.size()) return EBMG_ERR_ARG;
+  return guard(pb->ctx, [&]() -> ebmg_status {
+    HIPCHECK(hipSetDevice(pb->ctx->device));
+    DevProblem& D = pb->dev;
+    DevLevel& L = D.lv[level];
+    hipStream_t s = pb->ctx->stream;
+    const bool mixed = pb->host->opt.precision == EBMG_MIXED;
+    const int64_t nd = L.N + L.N2;
+    const int64_t nreg_half = (L.N + 1) / 2;
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    double bytes = 0;
+    auto launch = [&](int colour) {
+      const int64_t nxh = (L.n[0] + 1) / 2;
+      const int64_t nthr = nxh * L.n[1] * (L.dim == 3 ? L.n[2] : 1);
+      if (which == 0) {
+        if (mixed && level >= 0) {
+          if (L.dim == 3)
+            hipLaunchKernelGGL((k_rb<float, 3>), dim3(nblk(nthr)), dim3(kBlock), 0, s, L.tag.p, L.x32.p, L.b32.p, L.t32, colour);
+          else
+            hipLaunchKernelGGL((k_rb<float, 2>), dim3(nblk(nthr)), dim3(kBlock), 0, s, L.tag.p, L.x32.p, L.b32.p, L.t32, colour);
+        } else {
+          if (L.dim == 3)
+            hipLaunchKernelGGL((k_rb<double, 3>), dim3(nblk(nthr)), dim3(kBlock), 0, s, L.tag.p, L.x64.p, L.b64.p, L.t64, colour);
+          else
+            hipLaunchKernelGGL((k_rb<double, 2>), dim3(nblk(nthr)), dim3(kBlock), 0, s, L.tag.p, L.x64.p, L.b64.p, L.t64, colour);
+        }
+      } else {
+        if (L.dim == 3)
+          hipLaunchKernelGGL((k_resid_reg<double, 3, 0>), dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, L.x64.p, L.b64.p, L.r64.p, L.t64);
+        else
+          hipLaunchKernelGGL((k_resid_reg<double, 2, 0>), dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, L.x64.p, L.b64.p, L.r64.p, L.t64);
+      }
+    };
+    if (which != 0 && which != 1) throw ArgError("unknown kernel id");
+    if (which == 1 && !L.x64.p) throw ArgError("no FP64 vectors on this level");
+    if (which == 0) {
+      // algorithmic bytes of one half-sweep: each updated cell reads x and b,
+      // writes x, reads its tag
+      const int es = mixed ? 4 : 8;
+      bytes = (double)nreg_half * (3.0 * es + 1.0);
+      if (mixed) {
+        fill<float>(L.x32.p, nd, 0.0f, s);
+        fill<float>(L.b32.p, nd, 0.0f, s);
+      } else {
+        fill<double>(L.x64.p, nd, 0.0, s);
+        fill<double>(L.b64.p, nd, 0.0, s);
+      }
+    } else {
+      bytes = (double)L.N * (3.0 * 8 + 1.0);
+      fill<double>(L.x64.p, nd, 0.0, s);
+      fill<double>(L.b64.p, nd, 0.0, s);
+    }
+    launch(0);
+    launch(1);
+    HIPCHECK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) launch(r & 1);
+    HIPCHECK(hipEventRecord(e1, s));
+    HIPCHECK(hipEventSynchronize(e1));
+    HIPCHECK(hipGetLastError());
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = ms / reps;
+    if (alg_bytes) *alg_bytes = bytes;
     return EBMG_OK;
   });
 }

@@ -21,6 +21,15 @@ if not os.path.exists(LIB_PATH):
     raise ImportError("libebmg.so is not built: run `python -m paper_1809_03745_amd.build` "
                       "(or __graft_entry__.build()) first")
 
+# One HIP runtime per process: torch ships its own libamdhip64 (same soname,
+# different file). Loading torch first lets the library bind to that copy;
+# loading the library first would bring in a second HIP/HSA runtime that sees
+# no devices once torch initialises its own.
+try:
+    import torch as _torch  # noqa: F401
+except ImportError:  # host-only use (setup and exports) needs no torch
+    _torch = None
+
 _lib = C.CDLL(LIB_PATH)
 
 OK, ERR_ARG, ERR_GEOMETRY, ERR_OOM, ERR_DEVICE, ERR_NOCONV, ERR_NUMERIC, ERR_BUSY = range(8)
@@ -95,12 +104,13 @@ _sig("ebmg_solve", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int32, _vp
                              C.POINTER(SolveInfo)])
 _sig("ebmg_apply", C.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_efield", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp])
+_sig("ebmg_time_kernel", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp])
 _sig("ebmg_release", C.c_int, [_vp])
 
 EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_destroy", "ebmg_last_error",
             "ebmg_setup", "ebmg_query", "ebmg_query_level", "ebmg_export_level",
             "ebmg_export_geometry", "ebmg_export_operator", "ebmg_export_rhs",
-            "ebmg_solve", "ebmg_apply", "ebmg_efield", "ebmg_release"]
+            "ebmg_solve", "ebmg_apply", "ebmg_efield", "ebmg_time_kernel", "ebmg_release"]
 
 
 def abi_version():
@@ -127,7 +137,7 @@ class Context:
         h = _vp()
         st = _lib.ebmg_create(int(device), stream, C.byref(h))
         if st != OK:
-            raise EbmgError(st, "ebmg_create failed")
+            raise EbmgError(st, "ebmg_create failed: " + _lib.ebmg_last_error(None).decode(errors="replace"))
         self.h = h
         self.device = device
 
@@ -275,6 +285,13 @@ class Problem:
         ov = _host_f64(obj_values)
         self.ctx.check(_lib.ebmg_efield(self.h, _ptr(phi), _ptr(phi2), _ptr(sigma), _ptr(bcv), _ptr(ov), _ptr(E)),
                        "ebmg_efield")
+
+    def time_kernel(self, which, level=0, reps=50):
+        """(mean ms per launch, algorithmic bytes per launch) of a kernel."""
+        ms, by = C.c_double(), C.c_double()
+        self.ctx.check(_lib.ebmg_time_kernel(self.h, which, level, reps, C.byref(ms), C.byref(by)),
+                       "ebmg_time_kernel")
+        return ms.value, by.value
 
     def release(self):
         if getattr(self, "h", None):

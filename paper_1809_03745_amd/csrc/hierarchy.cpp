@@ -91,36 +91,23 @@ void Level::row(int64_t q, double& mass_out, std::vector<std::pair<int64_t, doub
   for (int64_t e = rp[r]; e < rp[r + 1]; ++e) out.emplace_back(col[e], val[e]);
 }
 
+// Explicit rows grouped by the red/black colour of their cell (group 0: red,
+// i+j+k even), in row order within a group.
 void colour_irregular(Level& L) {
   const size_t R = L.irow_dof.size();
-  std::vector<int32_t> rix = irow_index(L);
-  std::vector<std::vector<int32_t>> adj(R);
-  for (size_t r = 0; r < R; ++r)
-    for (int64_t e = L.rp[r]; e < L.rp[r + 1]; ++e) {
-      int32_t s = rix[L.col[e]];
-      if (s >= 0 && (size_t)s != r) {
-        adj[r].push_back(s);
-        adj[s].push_back((int32_t)r);
-      }
+  L.cls_ptr.assign(3, 0);
+  L.cls_rows.clear();
+  L.cls_rows.reserve(R);
+  for (int grp = 0; grp < 2; ++grp) {
+    for (size_t r = 0; r < R; ++r) {
+      const int64_t q = L.irow_dof[r];
+      const int64_t cell = q < L.N ? q : L.sec_cell[q - L.N];
+      int ijk[3];
+      cell_ijk(L.g, cell, ijk);
+      if (((ijk[0] + ijk[1] + ijk[2]) & 1) == grp) L.cls_rows.push_back((int32_t)r);
     }
-  std::vector<int> colour(R, -1);
-  int ncol = 0;
-  for (size_t r = 0; r < R; ++r) {
-    uint64_t used = 0;
-    for (int32_t s : adj[r])
-      if (colour[s] >= 0 && colour[s] < 64) used |= (1ull << colour[s]);
-    int c = 0;
-    while (c < 64 && (used >> c) & 1ull) ++c;
-    if (c >= 64) throw GeomError("irregular rows need more than 64 colours");
-    colour[r] = c;
-    ncol = std::max(ncol, c + 1);
+    L.cls_ptr[grp + 1] = (int32_t)L.cls_rows.size();
   }
-  L.cls_ptr.assign(ncol + 1, 0);
-  for (size_t r = 0; r < R; ++r) L.cls_ptr[colour[r] + 1]++;
-  for (int c = 0; c < ncol; ++c) L.cls_ptr[c + 1] += L.cls_ptr[c];
-  L.cls_rows.assign(R, 0);
-  std::vector<int32_t> fill(L.cls_ptr.begin(), L.cls_ptr.end() - 1);
-  for (size_t r = 0; r < R; ++r) L.cls_rows[fill[colour[r]]++] = (int32_t)r;
 }
 
 static bool coarsen(Problem& pb, size_t lf) {

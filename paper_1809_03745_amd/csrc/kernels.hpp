@@ -4,10 +4,12 @@
 //   (A x)_i = diag_i x_i + coff[p] * sum_{in-box nb} x_nb,
 //   diag_i  = d0[p] + sum_{domain faces touched} cb[f][p];
 // irregular unknowns (tag 2 cells and all second-phase unknowns) use explicit
-// sparse rows. Gauss-Seidel sweeps update red cells, then black cells (each
-// colour reads only the other colour), then the irregular rows class by class
-// (no row of a class reads another row of the same class), so every sweep is
-// race-free and bitwise deterministic.
+// sparse rows. A smoothing sweep updates the red regular cells (they read
+// only black cells), then the explicit rows of red cells, then the black
+// regular cells, then the explicit rows of black cells. Explicit rows of one
+// colour may reference each other (ray stencils reach two cells), so each
+// group is updated Jacobi-style through a temporary buffer; every launch is
+// race-free and every sweep bitwise deterministic.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -70,19 +72,45 @@ __global__ void __launch_bounds__(kBlock) k_rb(const uint8_t* __restrict__ tag, 
   x[c] = (b[c] - off) / dg;
 }
 
-// Gauss-Seidel update of one class of irregular rows.
+// Explicit (irregular) rows are processed by sub-wavefronts of kSub lanes:
+// each lane takes every kSub-th entry of the row (coalesced column/value
+// loads) and the partial sums are combined with xor-shuffles in a fixed
+// pattern, so results are bitwise reproducible.
+constexpr int kSub = 8;
+
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_irr_gs(const int32_t* __restrict__ rows, int nrows,
-                                                   const int64_t* __restrict__ dof, const int64_t* __restrict__ rp,
-                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                   const T* __restrict__ diag, T* __restrict__ x,
-                                                   const T* __restrict__ b) {
+__device__ __forceinline__ T row_dot(int64_t b, int64_t e, const int32_t* __restrict__ col,
+                                     const T* __restrict__ val, const T* __restrict__ x, int lane) {
+  T s = 0;
+  for (int64_t q = b + lane; q < e; q += kSub) s += val[q] * x[col[q]];
+  for (int off = kSub / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kSub);
+  return s;
+}
+
+// Jacobi update of a group of explicit rows into tmp (the group's rows read
+// only values the group does not write in this launch).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_irr_jacobi(const int32_t* __restrict__ rows, int nrows,
+                                                       const int64_t* __restrict__ dof,
+                                                       const int64_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                       const T* __restrict__ diag, const T* __restrict__ x,
+                                                       const T* __restrict__ b, T* __restrict__ tmp) {
+  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSub;
+  const int lane = threadIdx.x % kSub;
+  if (g >= nrows) return;
+  const int r = rows[g];
+  const T s = row_dot<T>(rp[r], rp[r + 1], col, val, x, lane);
+  if (lane == 0) tmp[g] = (b[dof[r]] - s) / diag[r];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_irr_scatter(const int32_t* __restrict__ rows, int nrows,
+                                                        const int64_t* __restrict__ dof,
+                                                        const T* __restrict__ tmp, T* __restrict__ x) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nrows) return;
-  const int r = rows[t];
-  T s = b[dof[r]];
-  for (int64_t e = rp[r]; e < rp[r + 1]; ++e) s -= val[e] * x[col[e]];
-  x[dof[r]] = s / diag[r];
+  x[dof[rows[t]]] = tmp[t];
 }
 
 // MODE 0: r = b - A x ; MODE 1: r = A x. Regular cells and covered cells.
@@ -114,12 +142,15 @@ __global__ void __launch_bounds__(kBlock) k_resid_irr(int nrows, const int64_t* 
                                                       const T* __restrict__ val, const T* __restrict__ diag,
                                                       const T* __restrict__ x, const T* __restrict__ b,
                                                       T* __restrict__ r) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nrows) return;
-  const int64_t q = dof[t];
-  T ax = diag[t] * x[q];
-  for (int64_t e = rp[t]; e < rp[t + 1]; ++e) ax += val[e] * x[col[e]];
-  r[q] = MODE == 0 ? b[q] - ax : ax;
+  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSub;
+  const int lane = threadIdx.x % kSub;
+  if (g >= nrows) return;
+  const T s = row_dot<T>(rp[g], rp[g + 1], col, val, x, lane);
+  if (lane == 0) {
+    const int64_t q = dof[g];
+    const T ax = diag[g] * x[q] + s;
+    r[q] = MODE == 0 ? b[q] - ax : ax;
+  }
 }
 
 // Restriction to simple coarse cells: mean of the 2^D children.

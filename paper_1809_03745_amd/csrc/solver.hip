@@ -71,13 +71,14 @@ struct DevLevel {
   Tmpl<double> t64;
   Tmpl<float> t32;
   // vectors
-  DevBuf<double> x64, b64, r64;
-  DevBuf<float> x32, b32, r32;
+  DevBuf<double> x64, b64, r64, w64;
+  DevBuf<float> x32, b32, r32, w32;
   void release() {
     tag.release(); irow_dof.release(); rp.release(); ns_cdof.release(); ns_child.release();
     np_fdof.release(); np_cdof.release(); col.release(); cls_rows.release(); ns_ptr.release();
     val64.release(); diag64.release(); val32.release(); diag32.release();
     x64.release(); b64.release(); r64.release(); x32.release(); b32.release(); r32.release();
+    w64.release(); w32.release();
   }
 };
 
@@ -188,11 +189,13 @@ static void upload(ebmg_problem_s* P) {
       d.x64.alloc(nd, by);
       d.b64.alloc(nd, by);
       d.r64.alloc(nd, by);
+      d.w64.alloc(std::max<int64_t>(1, d.R), by);
     }
     if (mixed) {
       d.x32.alloc(nd, by);
       d.b32.alloc(nd, by);
       d.r32.alloc(nd, by);
+      d.w32.alloc(std::max<int64_t>(1, d.R), by);
     }
   }
   D.bottom_n = H.bottom_n;
@@ -258,6 +261,7 @@ struct Vec<double> {
   static const double* val(DevLevel& l) { return l.val64.p; }
   static const double* diag(DevLevel& l) { return l.diag64.p; }
   static const Tmpl<double>& t(DevLevel& l) { return l.t64; }
+  static double* tmp(DevLevel& l) { return l.w64.p; }
 };
 template <>
 struct Vec<float> {
@@ -267,7 +271,22 @@ struct Vec<float> {
   static const float* val(DevLevel& l) { return l.val32.p; }
   static const float* diag(DevLevel& l) { return l.diag32.p; }
   static const Tmpl<float>& t(DevLevel& l) { return l.t32; }
+  static float* tmp(DevLevel& l) { return l.w32.p; }
 };
+
+static inline unsigned nblk_sub(int64_t rows) { return nblk(rows * kSub); }
+
+template <typename T>
+static void irr_group(DevLevel& l, int grp, T* x, const T* b, hipStream_t s) {
+  if (l.cls_ptr.size() < 3) return;
+  const int nr = l.cls_ptr[grp + 1] - l.cls_ptr[grp];
+  if (nr <= 0) return;
+  const int32_t* rows = l.cls_rows.p + l.cls_ptr[grp];
+  T* tmp = Vec<T>::tmp(l);
+  hipLaunchKernelGGL((k_irr_jacobi<T>), dim3(nblk_sub(nr)), dim3(kBlock), 0, s, rows, nr, l.irow_dof.p, l.rp.p,
+                     l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, tmp);
+  hipLaunchKernelGGL((k_irr_scatter<T>), dim3(nblk(nr)), dim3(kBlock), 0, s, rows, nr, l.irow_dof.p, tmp, x);
+}
 
 template <typename T>
 static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
@@ -280,12 +299,7 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
         hipLaunchKernelGGL((k_rb<T, 3>), dim3(nblk(nthr)), dim3(kBlock), 0, s, l.tag.p, x, b, tp, colour);
       else
         hipLaunchKernelGGL((k_rb<T, 2>), dim3(nblk(nthr)), dim3(kBlock), 0, s, l.tag.p, x, b, tp, colour);
-    }
-    for (size_t c = 0; c + 1 < l.cls_ptr.size(); ++c) {
-      const int nr = l.cls_ptr[c + 1] - l.cls_ptr[c];
-      if (nr <= 0) continue;
-      hipLaunchKernelGGL((k_irr_gs<T>), dim3(nblk(nr)), dim3(kBlock), 0, s, l.cls_rows.p + l.cls_ptr[c], nr,
-                         l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b);
+      irr_group<T>(l, colour, x, b, s);
     }
   }
   HIPCHECK(hipGetLastError());
@@ -299,7 +313,7 @@ static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
   else
     hipLaunchKernelGGL((k_resid_reg<T, 2, MODE>), dim3(nblk(l.N)), dim3(kBlock), 0, s, l.tag.p, x, b, r, tp);
   if (l.R > 0)
-    hipLaunchKernelGGL((k_resid_irr<T, MODE>), dim3(nblk(l.R)), dim3(kBlock), 0, s, (int)l.R, l.irow_dof.p, l.rp.p,
+    hipLaunchKernelGGL((k_resid_irr<T, MODE>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R, l.irow_dof.p, l.rp.p,
                        l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, r);
   HIPCHECK(hipGetLastError());
 }

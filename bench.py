@@ -134,7 +134,7 @@ def main():
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_rb<%s,3> (red/black Gauss-Seidel half-sweep, finest level)" %
+            "kernel": "k_rb_tile3<%s> (fused red+black Gauss-Seidel sweep, finest level)" %
                       ("float" if prec == ebmg.MIXED else "double"),
             "kernel_ms": round(k_ms, 5), "alg_bytes_per_launch": int(k_bytes)}
     out = {

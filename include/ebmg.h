@@ -107,7 +107,10 @@ typedef struct {
   int32_t krylov;           /* 0 auto (BiCGStab if any embedded object, else plain
                                V-cycles), 1 plain V-cycles, 2 V-cycle-preconditioned
                                BiCGStab                                          */
-  int32_t reserved[7];
+  int32_t smoother;         /* 0 autotuned per level at setup, 1 split red and
+                               black half-sweeps, 2 fused red+black tile sweep
+                               (levels of at least 32^3 / 256^2 cells)           */
+  int32_t reserved[6];
 } ebmg_options;
 
 typedef struct {
@@ -148,6 +151,10 @@ ebmg_status ebmg_query(ebmg_problem pb, int64_t* n_cells, int64_t* n_phase2, int
 
 /* Sizes of multigrid level `level` (0 = finest): cells and second-phase unknowns. */
 ebmg_status ebmg_query_level(ebmg_problem pb, int32_t level, int64_t* n_cells, int64_t* n_phase2);
+
+/* Smoother choice of level `level` (1 = fused tile sweep) and the sweep times
+ * (ms) the setup autotuner measured for each variant (0 if not timed). */
+ebmg_status ebmg_query_tuning(ebmg_problem pb, int32_t level, int32_t* fused, double* split_ms, double* fused_ms);
 
 /* HOST copies of a level's cell tags (0/1 regular gas/dielectric, 2 explicit
  * row, 3 covered; +4 when the cell's children do not all map to its primary
@@ -192,10 +199,10 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
 
 /* Measurement hook: launch one kernel `reps` times on the context stream
  * between two HIP events and report the mean duration per launch (ms) and
- * the kernel's algorithmic bytes per launch. which = 0: red/black smoother
- * half-sweep of level `level` (FP32 for mixed-precision problems, else
- * FP64); 1: FP64 residual of level `level`. Overwrites the level's work
- * vectors. */
+ * the kernel's algorithmic bytes per launch. which = 0: the level's
+ * smoother kernel (the fused red+black sweep where the level uses it, else a
+ * red/black half-sweep; FP32 for mixed-precision problems, else FP64);
+ * 1: FP64 residual of level `level`. Overwrites the level's work vectors. */
 ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int32_t reps, double* avg_ms,
                              double* alg_bytes);
 

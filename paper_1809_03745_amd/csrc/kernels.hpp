@@ -49,27 +49,274 @@ __device__ __forceinline__ T template_apply(const T* __restrict__ x, const Tmpl<
   return tp.coff[p] * s;
 }
 
-// Red/black Gauss-Seidel half-sweep over regular cells. One thread per cell
-// of the given colour: i = 2*ih + ((j + k + colour) & 1).
+// Red/black Gauss-Seidel half-sweep over regular cells on a 3D launch grid:
+// x threads take the cells of one colour along a row (i = 2*ih + parity),
+// grid y/z give the row and plane, so no index division is needed.
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kBlock) k_rb(const uint8_t* __restrict__ tag, T* __restrict__ x,
                                                const T* __restrict__ b, Tmpl<T> tp, int colour) {
-  const int nxh = (tp.n[0] + 1) >> 1;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t rows = (int64_t)tp.n[1] * (DIM == 3 ? tp.n[2] : 1);
-  if (t >= (int64_t)nxh * rows) return;
-  const int ih = (int)(t % nxh);
-  const int64_t jk = t / nxh;
-  const int j = (int)(jk % tp.n[1]);
-  const int k = DIM == 3 ? (int)(jk / tp.n[1]) : 0;
+  const int ih = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = DIM == 3 ? (int)blockIdx.z : 0;
+  if (j >= tp.n[1]) return;
   const int i = 2 * ih + ((j + k + colour) & 1);
   if (i >= tp.n[0]) return;
-  const int64_t c = i + (int64_t)tp.n[0] * jk;
+  const int64_t c = i + (int64_t)tp.n[0] * (j + (int64_t)tp.n[1] * k);
   const uint8_t p = tclass(tag[c]);
   if (p > 1) return;
   T dg;
   const T off = template_apply<T, DIM>(x, tp, i, j, k, c, p, dg);
   x[c] = (b[c] - off) / dg;
+}
+
+// Fused red+black sweep over regular cells, out of place (xin -> xout).
+// A block owns a tile of cells: it loads the tile with a halo ring of two
+// cells into LDS in one phase, applies the red update to the tile and a ring
+// of one cell (old values only), then the black update to the tile (red-
+// updated values only) -- exactly a red half-sweep followed by a black
+// half-sweep. Ring cells are recomputed redundantly by neighbouring blocks
+// from the same old values, so blocks never exchange data. Explicit-row,
+// covered and second-phase values are copied through unchanged. Blocks are
+// numbered so that consecutive tiles of a slab fall on the same XCD (the
+// hardware deals workgroups round-robin over the 8 XCDs), keeping halo
+// re-reads in that XCD's L2.
+constexpr int kTX = 32, kTY = 8, kTZ = 8;     // 3D tile
+constexpr int kTX2 = 64, kTY2 = 32;           // 2D tile
+constexpr int kXCD = 8;
+
+__device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks) {
+  if (nblocks % kXCD) return bid;
+  return (bid % kXCD) * (nblocks / kXCD) + bid / kXCD;
+}
+
+template <typename T>
+__device__ __forceinline__ T tmpl_update(const Tmpl<T>& tp, int p, T bc, T s, T dg) {
+  return (bc - tp.coff[p] * s) / dg;
+}
+
+constexpr int kTileThreads = 512;
+
+// All global loads of a block (halo tile, and the tag and b values of the
+// cells this thread updates) are issued up front into registers, so one
+// memory latency is exposed per block instead of one per phase.
+template <typename T>
+__global__ void __launch_bounds__(kTileThreads) k_rb_tile3(const uint8_t* __restrict__ tag,
+                                                           const T* __restrict__ xin, T* __restrict__ xout,
+                                                           const T* __restrict__ b, Tmpl<T> tp, int64_t nsec) {
+  constexpr int OX = kTX + 4, OY = kTY + 4, OZ = kTZ + 4, NOq = OX * OY * OZ;
+  constexpr int RX = kTX + 2, RY = kTY + 2, RZ = kTZ + 2, NRq = RX * RY * RZ;
+  constexpr int NTq = kTX * kTY * kTZ;
+  constexpr int NT = kTileThreads;
+  constexpr int UO = (NOq + NT - 1) / NT, UR = (NRq + NT - 1) / NT, UT = (NTq + NT - 1) / NT;
+  __shared__ T O[NOq];
+  __shared__ T R[NRq];
+  const int nx = tp.n[0], ny = tp.n[1], nz = tp.n[2];
+  const int bx = (nx + kTX - 1) / kTX, by = (ny + kTY - 1) / kTY;
+  const int64_t nblocks = (int64_t)gridDim.x;
+  const int64_t t = xcd_block(blockIdx.x, nblocks);
+  const int x0 = (int)(t % bx) * kTX, y0 = (int)((t / bx) % by) * kTY, z0 = (int)(t / ((int64_t)bx * by)) * kTZ;
+  const int tid = threadIdx.x;
+  const int64_t sxy = (int64_t)nx * ny;
+  T ov[UO];
+  uint8_t rt[UR], bt[UT];
+  T rb[UR], bb[UT];
+#pragma unroll
+  for (int u = 0; u < UO; ++u) {
+    const int q = tid + u * NT;
+    ov[u] = T(0);
+    if (q < NOq) {
+      const int gx = x0 + q % OX - 2, gy = y0 + (q / OX) % OY - 2, gz = z0 + q / (OX * OY) - 2;
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) ov[u] = xin[gx + (int64_t)nx * gy + sxy * gz];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UR; ++u) {
+    const int q = tid + u * NT;
+    rt[u] = 3;
+    rb[u] = T(0);
+    if (q < NRq) {
+      const int gx = x0 + q % RX - 1, gy = y0 + (q / RX) % RY - 1, gz = z0 + q / (RX * RY) - 1;
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz && ((gx + gy + gz) & 1) == 0) {
+        const int64_t c = gx + (int64_t)nx * gy + sxy * gz;
+        rt[u] = tclass(tag[c]);
+        rb[u] = b[c];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UT; ++u) {
+    const int q = tid + u * NT;
+    bt[u] = 3;
+    bb[u] = T(0);
+    if (q < NTq) {
+      const int gx = x0 + q % kTX, gy = y0 + (q / kTX) % kTY, gz = z0 + q / (kTX * kTY);
+      if (gx < nx && gy < ny && gz < nz && ((gx + gy + gz) & 1) == 1) {
+        const int64_t c = gx + (int64_t)nx * gy + sxy * gz;
+        bt[u] = tclass(tag[c]);
+        bb[u] = b[c];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UO; ++u) {
+    const int q = tid + u * NT;
+    if (q < NOq) O[q] = ov[u];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < UR; ++u) {
+    const int q = tid + u * NT;
+    if (q >= NRq) continue;
+    const int lx = q % RX, ly = (q / RX) % RY, lz = q / (RX * RY);
+    const int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z0 + lz - 1;
+    const int oq = (lx + 1) + OX * ((ly + 1) + OY * (lz + 1));
+    T v = O[oq];
+    const int p = rt[u];
+    if (p <= 1) {
+      T sum = 0, dg = tp.d0[p];
+      if (gx > 0) sum += O[oq - 1]; else dg += tp.cb[0][p];
+      if (gx < nx - 1) sum += O[oq + 1]; else dg += tp.cb[1][p];
+      if (gy > 0) sum += O[oq - OX]; else dg += tp.cb[2][p];
+      if (gy < ny - 1) sum += O[oq + OX]; else dg += tp.cb[3][p];
+      if (gz > 0) sum += O[oq - OX * OY]; else dg += tp.cb[4][p];
+      if (gz < nz - 1) sum += O[oq + OX * OY]; else dg += tp.cb[5][p];
+      v = tmpl_update<T>(tp, p, rb[u], sum, dg);
+    }
+    R[q] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < UT; ++u) {
+    const int q = tid + u * NT;
+    if (q >= NTq) continue;
+    const int lx = q % kTX, ly = (q / kTX) % kTY, lz = q / (kTX * kTY);
+    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+    if (gx >= nx || gy >= ny || gz >= nz) continue;
+    const int rq = (lx + 1) + RX * ((ly + 1) + RY * (lz + 1));
+    T v = R[rq];
+    const int p = bt[u];
+    if (p <= 1) {
+      T sum = 0, dg = tp.d0[p];
+      if (gx > 0) sum += R[rq - 1]; else dg += tp.cb[0][p];
+      if (gx < nx - 1) sum += R[rq + 1]; else dg += tp.cb[1][p];
+      if (gy > 0) sum += R[rq - RX]; else dg += tp.cb[2][p];
+      if (gy < ny - 1) sum += R[rq + RX]; else dg += tp.cb[3][p];
+      if (gz > 0) sum += R[rq - RX * RY]; else dg += tp.cb[4][p];
+      if (gz < nz - 1) sum += R[rq + RX * RY]; else dg += tp.cb[5][p];
+      v = tmpl_update<T>(tp, p, bb[u], sum, dg);
+    }
+    xout[gx + (int64_t)nx * gy + sxy * gz] = v;
+  }
+  // second-phase unknowns are not touched by this sweep: copy them through
+  const int64_t N = sxy * nz;
+  for (int64_t q = (int64_t)blockIdx.x * NT + tid; q < nsec; q += nblocks * NT) xout[N + q] = xin[N + q];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTileThreads) k_rb_tile2(const uint8_t* __restrict__ tag,
+                                                           const T* __restrict__ xin, T* __restrict__ xout,
+                                                           const T* __restrict__ b, Tmpl<T> tp, int64_t nsec) {
+  constexpr int OX = kTX2 + 4, OY = kTY2 + 4, NOq = OX * OY;
+  constexpr int RX = kTX2 + 2, RY = kTY2 + 2, NRq = RX * RY;
+  constexpr int NTq = kTX2 * kTY2;
+  constexpr int NT = kTileThreads;
+  constexpr int UO = (NOq + NT - 1) / NT, UR = (NRq + NT - 1) / NT, UT = (NTq + NT - 1) / NT;
+  __shared__ T O[NOq];
+  __shared__ T R[NRq];
+  const int nx = tp.n[0], ny = tp.n[1];
+  const int bx = (nx + kTX2 - 1) / kTX2;
+  const int64_t nblocks = (int64_t)gridDim.x;
+  const int64_t t = xcd_block(blockIdx.x, nblocks);
+  const int x0 = (int)(t % bx) * kTX2, y0 = (int)(t / bx) * kTY2;
+  const int tid = threadIdx.x;
+  T ov[UO];
+  uint8_t rt[UR], bt[UT];
+  T rb[UR], bb[UT];
+#pragma unroll
+  for (int u = 0; u < UO; ++u) {
+    const int q = tid + u * NT;
+    ov[u] = T(0);
+    if (q < NOq) {
+      const int gx = x0 + q % OX - 2, gy = y0 + q / OX - 2;
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ov[u] = xin[gx + (int64_t)nx * gy];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UR; ++u) {
+    const int q = tid + u * NT;
+    rt[u] = 3;
+    rb[u] = T(0);
+    if (q < NRq) {
+      const int gx = x0 + q % RX - 1, gy = y0 + q / RX - 1;
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && ((gx + gy) & 1) == 0) {
+        const int64_t c = gx + (int64_t)nx * gy;
+        rt[u] = tclass(tag[c]);
+        rb[u] = b[c];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UT; ++u) {
+    const int q = tid + u * NT;
+    bt[u] = 3;
+    bb[u] = T(0);
+    if (q < NTq) {
+      const int gx = x0 + q % kTX2, gy = y0 + q / kTX2;
+      if (gx < nx && gy < ny && ((gx + gy) & 1) == 1) {
+        const int64_t c = gx + (int64_t)nx * gy;
+        bt[u] = tclass(tag[c]);
+        bb[u] = b[c];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UO; ++u) {
+    const int q = tid + u * NT;
+    if (q < NOq) O[q] = ov[u];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < UR; ++u) {
+    const int q = tid + u * NT;
+    if (q >= NRq) continue;
+    const int lx = q % RX, ly = q / RX;
+    const int gx = x0 + lx - 1, gy = y0 + ly - 1;
+    const int oq = (lx + 1) + OX * (ly + 1);
+    T v = O[oq];
+    const int p = rt[u];
+    if (p <= 1) {
+      T sum = 0, dg = tp.d0[p];
+      if (gx > 0) sum += O[oq - 1]; else dg += tp.cb[0][p];
+      if (gx < nx - 1) sum += O[oq + 1]; else dg += tp.cb[1][p];
+      if (gy > 0) sum += O[oq - OX]; else dg += tp.cb[2][p];
+      if (gy < ny - 1) sum += O[oq + OX]; else dg += tp.cb[3][p];
+      v = tmpl_update<T>(tp, p, rb[u], sum, dg);
+    }
+    R[q] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < UT; ++u) {
+    const int q = tid + u * NT;
+    if (q >= NTq) continue;
+    const int lx = q % kTX2, ly = q / kTX2;
+    const int gx = x0 + lx, gy = y0 + ly;
+    if (gx >= nx || gy >= ny) continue;
+    const int rq = (lx + 1) + RX * (ly + 1);
+    T v = R[rq];
+    const int p = bt[u];
+    if (p <= 1) {
+      T sum = 0, dg = tp.d0[p];
+      if (gx > 0) sum += R[rq - 1]; else dg += tp.cb[0][p];
+      if (gx < nx - 1) sum += R[rq + 1]; else dg += tp.cb[1][p];
+      if (gy > 0) sum += R[rq - RX]; else dg += tp.cb[2][p];
+      if (gy < ny - 1) sum += R[rq + RX]; else dg += tp.cb[3][p];
+      v = tmpl_update<T>(tp, p, bb[u], sum, dg);
+    }
+    xout[gx + (int64_t)nx * gy] = v;
+  }
+  const int64_t N = (int64_t)nx * ny;
+  for (int64_t q = (int64_t)blockIdx.x * NT + tid; q < nsec; q += nblocks * NT) xout[N + q] = xin[N + q];
 }
 
 // Explicit (irregular) rows are processed by sub-wavefronts of kSub lanes:
@@ -113,23 +360,22 @@ __global__ void __launch_bounds__(kBlock) k_irr_scatter(const int32_t* __restric
   x[dof[rows[t]]] = tmp[t];
 }
 
-// MODE 0: r = b - A x ; MODE 1: r = A x. Regular cells and covered cells.
+// MODE 0: r = b - A x ; MODE 1: r = A x. Regular cells and covered cells
+// (3D launch grid over cells).
 template <typename T, int DIM, int MODE>
 __global__ void __launch_bounds__(kBlock) k_resid_reg(const uint8_t* __restrict__ tag, const T* __restrict__ x,
                                                       const T* __restrict__ b, T* __restrict__ r, Tmpl<T> tp) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t N = (int64_t)tp.n[0] * tp.n[1] * (DIM == 3 ? tp.n[2] : 1);
-  if (c >= N) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = DIM == 3 ? (int)blockIdx.z : 0;
+  if (i >= tp.n[0] || j >= tp.n[1]) return;
+  const int64_t c = i + (int64_t)tp.n[0] * (j + (int64_t)tp.n[1] * k);
   const uint8_t p = tclass(tag[c]);
   if (p == 3) {
     r[c] = MODE == 0 ? T(0) : x[c];
     return;
   }
   if (p == 2) return;
-  const int i = (int)(c % tp.n[0]);
-  const int64_t jk = c / tp.n[0];
-  const int j = (int)(jk % tp.n[1]);
-  const int k = DIM == 3 ? (int)(jk / tp.n[1]) : 0;
   T dg;
   const T off = template_apply<T, DIM>(x, tp, i, j, k, c, p, dg);
   const T ax = dg * x[c] + off;
@@ -153,23 +399,23 @@ __global__ void __launch_bounds__(kBlock) k_resid_irr(int nrows, const int64_t* 
   }
 }
 
-// Restriction to simple coarse cells: mean of the 2^D children.
+// Restriction to simple coarse cells: mean of the 2^D children (3D launch
+// grid over coarse cells).
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kBlock) k_restrict(const uint8_t* __restrict__ ctag, const T* __restrict__ rf,
                                                      T* __restrict__ bc, int cnx, int cny, int cnz) {
-  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t NC = (int64_t)cnx * cny * (DIM == 3 ? cnz : 1);
-  if (P >= NC) return;
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y * blockDim.y + threadIdx.y;
+  const int K = DIM == 3 ? (int)blockIdx.z : 0;
+  if (I >= cnx || J >= cny) return;
+  (void)cnz;
+  const int64_t P = I + (int64_t)cnx * (J + (int64_t)cny * K);
   const uint8_t t = ctag[P];
   if (tclass(t) == 3) {
     bc[P] = 0;
     return;
   }
   if (t & 4) return;
-  const int I = (int)(P % cnx);
-  const int64_t JK = P / cnx;
-  const int J = (int)(JK % cny);
-  const int K = DIM == 3 ? (int)(JK / cny) : 0;
   const int fnx = 2 * cnx;
   const int64_t fsxy = (int64_t)fnx * 2 * cny;
   const int64_t c0 = 2 * I + (int64_t)fnx * (2 * J) + (DIM == 3 ? fsxy * (2 * K) : 0);
@@ -190,19 +436,19 @@ __global__ void __launch_bounds__(kBlock) k_restrict_ns(int n, const int64_t* __
   bc[cdof[t]] = s * (DIM == 3 ? T(0.125) : T(0.25));
 }
 
-// Prolongation: x_f += e_c[parent] for fine cells of simple parents.
+// Prolongation: x_f += e_c[parent] for fine cells of simple parents (3D
+// launch grid over fine cells).
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kBlock) k_prolong(const uint8_t* __restrict__ ftag, const uint8_t* __restrict__ ctag,
                                                     const T* __restrict__ ec, T* __restrict__ xf, int fnx, int fny,
                                                     int fnz) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t N = (int64_t)fnx * fny * (DIM == 3 ? fnz : 1);
-  if (c >= N) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = DIM == 3 ? (int)blockIdx.z : 0;
+  if (i >= fnx || j >= fny) return;
+  (void)fnz;
+  const int64_t c = i + (int64_t)fnx * (j + (int64_t)fny * k);
   if (tclass(ftag[c]) == 3) return;
-  const int i = (int)(c % fnx);
-  const int64_t jk = c / fnx;
-  const int j = (int)(jk % fny);
-  const int k = DIM == 3 ? (int)(jk / fny) : 0;
   const int cnx = fnx >> 1, cny = fny >> 1;
   const int64_t P = (i >> 1) + (int64_t)cnx * ((j >> 1) + (int64_t)cny * (k >> 1));
   if (ctag[P] & 4) return;
@@ -365,24 +611,22 @@ __global__ void __launch_bounds__(kBlock) k_add_f32(double* __restrict__ x, cons
   if (t < n) x[t] += (double)e[t];
 }
 
-// Right-hand side of regular and covered cells.
+// Right-hand side of regular and covered cells (3D launch grid).
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_rhs_reg(const uint8_t* __restrict__ tag, const double* __restrict__ rho,
                                                     double* __restrict__ b, Tmpl<double> dat, int unused) {
   (void)unused;
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t N = (int64_t)dat.n[0] * dat.n[1] * (DIM == 3 ? dat.n[2] : 1);
-  if (c >= N) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = DIM == 3 ? (int)blockIdx.z : 0;
+  if (i >= dat.n[0] || j >= dat.n[1]) return;
+  const int64_t c = i + (int64_t)dat.n[0] * (j + (int64_t)dat.n[1] * k);
   const uint8_t p = tclass(tag[c]);
   if (p == 3) {
     b[c] = 0;
     return;
   }
   if (p == 2) return;
-  const int i = (int)(c % dat.n[0]);
-  const int64_t jk = c / dat.n[0];
-  const int j = (int)(jk % dat.n[1]);
-  const int k = DIM == 3 ? (int)(jk / dat.n[1]) : 0;
   double v = rho[c];
   // dat.cb[f][p] holds dat[f][p] * value_f
   if (i == 0) v -= dat.cb[0][p];
@@ -417,25 +661,24 @@ __global__ void __launch_bounds__(kBlock) k_rhs_irr(int nrows, const int64_t* __
   b[dof[t]] = v;
 }
 
-// Cell-centred E of regular cells (covered cells 0).
+// Cell-centred E of regular cells (covered cells 0), 3D launch grid.
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_efield_reg(const uint8_t* __restrict__ tag, const double* __restrict__ x,
                                                        double* __restrict__ E, Tmpl<double> ga, Tmpl<double> gbv,
                                                        double inv_h) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int nx = ga.n[0], ny = ga.n[1];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = DIM == 3 ? (int)blockIdx.z : 0;
+  if (i >= nx || j >= ny) return;
   const int64_t N = (int64_t)nx * ny * (DIM == 3 ? ga.n[2] : 1);
-  if (c >= N) return;
+  const int64_t c = i + (int64_t)nx * (j + (int64_t)ny * k);
   const uint8_t p = tclass(tag[c]);
   if (p == 3) {
     for (int d = 0; d < DIM; ++d) E[d * N + c] = 0;
     return;
   }
   if (p == 2) return;
-  const int i = (int)(c % nx);
-  const int64_t jk = c / nx;
-  const int j = (int)(jk % ny);
-  const int k = DIM == 3 ? (int)(jk / ny) : 0;
   const int idx[3] = {i, j, k};
   const int64_t stride[3] = {1, nx, (int64_t)nx * ny};
   const double xc = x[c];

@@ -35,6 +35,22 @@ struct DeviceError : std::runtime_error {
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// 3D launch shape over an (nx, ny, nz) index box: blocks of bx*by = 256
+// threads (bx = 64 unless the rows are shorter), one grid z per plane
+struct Shape {
+  dim3 g, b;
+};
+static inline Shape shape3(int nx, int ny, int nz) {
+  int bx = 64;
+  while (bx > 8 && bx / 2 >= nx) bx /= 2;
+  int by = kBlock / bx;
+  while (by > 1 && by / 2 >= ny) by /= 2;
+  Shape s;
+  s.b = dim3(bx, by, 1);
+  s.g = dim3((nx + bx - 1) / bx, (ny + by - 1) / by, nz);
+  return s;
+}
+
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
@@ -68,17 +84,19 @@ struct DevLevel {
   DevBuf<float> val32, diag32;
   std::vector<int32_t> cls_ptr;
   int64_t n_ns = 0, n_np = 0;
+  bool fused = false;              // smoother variant chosen for this level
+  double tune_split_ms = 0, tune_fused_ms = 0;
   Tmpl<double> t64;
   Tmpl<float> t32;
   // vectors
-  DevBuf<double> x64, b64, r64, w64;
-  DevBuf<float> x32, b32, r32, w32;
+  DevBuf<double> x64, b64, r64, w64, xa64;
+  DevBuf<float> x32, b32, r32, w32, xa32;
   void release() {
     tag.release(); irow_dof.release(); rp.release(); ns_cdof.release(); ns_child.release();
     np_fdof.release(); np_cdof.release(); col.release(); cls_rows.release(); ns_ptr.release();
     val64.release(); diag64.release(); val32.release(); diag32.release();
     x64.release(); b64.release(); r64.release(); x32.release(); b32.release(); r32.release();
-    w64.release(); w32.release();
+    w64.release(); w32.release(); xa64.release(); xa32.release();
   }
 };
 
@@ -146,6 +164,93 @@ static Tmpl<T> make_tmpl(const Level& L) {
   return t;
 }
 
+template <typename T>
+static void fill(T* x, int64_t n, T v, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL((k_fill<T>), dim3(nblk(n)), dim3(kBlock), 0, s, x, n, v);
+}
+
+// levels large enough for the fused out-of-place red/black sweep
+static bool fused_ok(const DevLevel& l) {
+  return l.dim == 3 ? (l.N >= 32768 && l.n[0] >= 32) : (l.N >= 65536 && l.n[0] >= 64);
+}
+
+template <typename T>
+static void launch_fused(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s) {
+  if (l.dim == 3) {
+    const int64_t nb = (int64_t)((l.n[0] + kTX - 1) / kTX) * ((l.n[1] + kTY - 1) / kTY) * ((l.n[2] + kTZ - 1) / kTZ);
+    hipLaunchKernelGGL((k_rb_tile3<T>), dim3((unsigned)nb), dim3(kTileThreads), 0, s, l.tag.p, xin, xout, b, tp, l.N2);
+  } else {
+    const int64_t nb = (int64_t)((l.n[0] + kTX2 - 1) / kTX2) * ((l.n[1] + kTY2 - 1) / kTY2);
+    hipLaunchKernelGGL((k_rb_tile2<T>), dim3((unsigned)nb), dim3(kTileThreads), 0, s, l.tag.p, xin, xout, b, tp, l.N2);
+  }
+}
+
+// Smoother autotuner: on levels where the fused tile sweep applies, time one
+// full sweep of each variant (split red and black half-sweeps vs the fused
+// tile kernel) with HIP events on zeroed vectors and keep the faster one.
+// mode 1 forces split sweeps, mode 2 the fused sweep where it applies.
+template <typename T>
+static double time_sweep(DevLevel& l, bool fused, T* x, T* xa, const T* b, const Tmpl<T>& tp, hipStream_t s) {
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  const Shape sh = shape3((l.n[0] + 1) / 2, l.n[1], l.dim == 3 ? l.n[2] : 1);
+  auto run = [&](int reps) {
+    for (int r = 0; r < reps; ++r) {
+      if (fused) {
+        launch_fused<T>(l, (r & 1) ? xa : x, (r & 1) ? x : xa, b, tp, s);
+      } else {
+        for (int colour = 0; colour < 2; ++colour) {
+          if (l.dim == 3)
+            hipLaunchKernelGGL((k_rb<T, 3>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
+          else
+            hipLaunchKernelGGL((k_rb<T, 2>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
+        }
+      }
+    }
+  };
+  run(2);
+  HIPCHECK(hipEventRecord(e0, s));
+  run(6);
+  HIPCHECK(hipEventRecord(e1, s));
+  HIPCHECK(hipEventSynchronize(e1));
+  HIPCHECK(hipGetLastError());
+  float ms = 0;
+  HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / 6.0;
+}
+
+template <typename T>
+static void tune_level(DevLevel& l, T* x, T* xa, T* b, const Tmpl<T>& tp, int mode, hipStream_t s) {
+  const int64_t nd = l.N + l.N2;
+  fill<T>(x, nd, T(0), s);
+  fill<T>(xa, nd, T(0), s);
+  fill<T>(b, nd, T(0), s);
+  if (mode == 1) {
+    l.fused = false;
+    return;
+  }
+  if (mode == 2) {
+    l.fused = true;
+    return;
+  }
+  l.tune_split_ms = time_sweep<T>(l, false, x, xa, b, tp, s);
+  l.tune_fused_ms = time_sweep<T>(l, true, x, xa, b, tp, s);
+  l.fused = l.tune_fused_ms < l.tune_split_ms;
+}
+
+static void tune_smoother(DevLevel& l, bool mixed, int mode, hipStream_t s) {
+  l.fused = false;
+  if (!fused_ok(l)) return;
+  if (mixed) {
+    if (l.xa32.p) tune_level<float>(l, l.x32.p, l.xa32.p, l.b32.p, l.t32, mode, s);
+  } else {
+    if (l.xa64.p) tune_level<double>(l, l.x64.p, l.xa64.p, l.b64.p, l.t64, mode, s);
+  }
+}
+
 static void upload(ebmg_problem_s* P) {
   Problem& H = *P->host;
   DevProblem& D = P->dev;
@@ -190,12 +295,14 @@ static void upload(ebmg_problem_s* P) {
       d.b64.alloc(nd, by);
       d.r64.alloc(nd, by);
       d.w64.alloc(std::max<int64_t>(1, d.R), by);
+      if (fused_ok(d)) d.xa64.alloc(nd, by);
     }
     if (mixed) {
       d.x32.alloc(nd, by);
       d.b32.alloc(nd, by);
       d.r32.alloc(nd, by);
       d.w32.alloc(std::max<int64_t>(1, d.R), by);
+      if (fused_ok(d)) d.xa32.alloc(nd, by);
     }
   }
   D.bottom_n = H.bottom_n;
@@ -242,6 +349,8 @@ static void upload(ebmg_problem_s* P) {
   D.part.alloc(2 * kNormBlocks, by);
   D.scal.alloc(SC_NUM, by);
   HIPCHECK(hipHostMalloc((void**)&D.host_scal, SC_NUM * sizeof(double), hipHostMallocDefault));
+  HIPCHECK(hipStreamSynchronize(s));
+  for (auto& l : D.lv) tune_smoother(l, mixed, H.opt.smoother, s);
   D.krylov = H.opt.krylov == 2;
   if (D.krylov)
     for (auto& k : D.kv) k.alloc(L0.N + L0.N2, by);
@@ -262,6 +371,7 @@ struct Vec<double> {
   static const double* diag(DevLevel& l) { return l.diag64.p; }
   static const Tmpl<double>& t(DevLevel& l) { return l.t64; }
   static double* tmp(DevLevel& l) { return l.w64.p; }
+  static double* xa(DevLevel& l) { return l.xa64.p; }
 };
 template <>
 struct Vec<float> {
@@ -272,6 +382,7 @@ struct Vec<float> {
   static const float* diag(DevLevel& l) { return l.diag32.p; }
   static const Tmpl<float>& t(DevLevel& l) { return l.t32; }
   static float* tmp(DevLevel& l) { return l.w32.p; }
+  static float* xa(DevLevel& l) { return l.xa32.p; }
 };
 
 static inline unsigned nblk_sub(int64_t rows) { return nblk(rows * kSub); }
@@ -291,14 +402,28 @@ static void irr_group(DevLevel& l, int grp, T* x, const T* b, hipStream_t s) {
 template <typename T>
 static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
-  const int64_t nxh = (l.n[0] + 1) / 2;
-  const int64_t nthr = nxh * l.n[1] * (l.dim == 3 ? l.n[2] : 1);
+  if (l.fused && Vec<T>::xa(l)) {
+    // out-of-place fused red+black sweeps, then the explicit rows of red and
+    // of black cells
+    T* cur = x;
+    T* alt = Vec<T>::xa(l);
+    for (int it = 0; it < sweeps; ++it) {
+      launch_fused<T>(l, cur, alt, b, tp, s);
+      std::swap(cur, alt);
+      irr_group<T>(l, 0, cur, b, s);
+      irr_group<T>(l, 1, cur, b, s);
+    }
+    if (cur != x) HIPCHECK(hipMemcpyAsync(x, cur, sizeof(T) * (l.N + l.N2), hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipGetLastError());
+    return;
+  }
+  const Shape sh = shape3((l.n[0] + 1) / 2, l.n[1], l.dim == 3 ? l.n[2] : 1);
   for (int it = 0; it < sweeps; ++it) {
     for (int colour = 0; colour < 2; ++colour) {
       if (l.dim == 3)
-        hipLaunchKernelGGL((k_rb<T, 3>), dim3(nblk(nthr)), dim3(kBlock), 0, s, l.tag.p, x, b, tp, colour);
+        hipLaunchKernelGGL((k_rb<T, 3>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
       else
-        hipLaunchKernelGGL((k_rb<T, 2>), dim3(nblk(nthr)), dim3(kBlock), 0, s, l.tag.p, x, b, tp, colour);
+        hipLaunchKernelGGL((k_rb<T, 2>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
       irr_group<T>(l, colour, x, b, s);
     }
   }
@@ -308,10 +433,11 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
 template <typename T, int MODE>
 static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
+  const Shape sh = shape3(l.n[0], l.n[1], l.dim == 3 ? l.n[2] : 1);
   if (l.dim == 3)
-    hipLaunchKernelGGL((k_resid_reg<T, 3, MODE>), dim3(nblk(l.N)), dim3(kBlock), 0, s, l.tag.p, x, b, r, tp);
+    hipLaunchKernelGGL((k_resid_reg<T, 3, MODE>), sh.g, sh.b, 0, s, l.tag.p, x, b, r, tp);
   else
-    hipLaunchKernelGGL((k_resid_reg<T, 2, MODE>), dim3(nblk(l.N)), dim3(kBlock), 0, s, l.tag.p, x, b, r, tp);
+    hipLaunchKernelGGL((k_resid_reg<T, 2, MODE>), sh.g, sh.b, 0, s, l.tag.p, x, b, r, tp);
   if (l.R > 0)
     hipLaunchKernelGGL((k_resid_irr<T, MODE>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R, l.irow_dof.p, l.rp.p,
                        l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, r);
@@ -320,10 +446,11 @@ static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
 
 template <typename T>
 static void restrict_to(DevLevel& f, DevLevel& c, const T* rf, T* bc, hipStream_t s) {
+  const Shape sh = shape3(c.n[0], c.n[1], c.dim == 3 ? c.n[2] : 1);
   if (f.dim == 3)
-    hipLaunchKernelGGL((k_restrict<T, 3>), dim3(nblk(c.N)), dim3(kBlock), 0, s, c.tag.p, rf, bc, c.n[0], c.n[1], c.n[2]);
+    hipLaunchKernelGGL((k_restrict<T, 3>), sh.g, sh.b, 0, s, c.tag.p, rf, bc, c.n[0], c.n[1], c.n[2]);
   else
-    hipLaunchKernelGGL((k_restrict<T, 2>), dim3(nblk(c.N)), dim3(kBlock), 0, s, c.tag.p, rf, bc, c.n[0], c.n[1], 1);
+    hipLaunchKernelGGL((k_restrict<T, 2>), sh.g, sh.b, 0, s, c.tag.p, rf, bc, c.n[0], c.n[1], 1);
   if (f.n_ns > 0) {
     if (f.dim == 3)
       hipLaunchKernelGGL((k_restrict_ns<T, 3>), dim3(nblk(f.n_ns)), dim3(kBlock), 0, s, (int)f.n_ns, f.ns_cdof.p,
@@ -337,22 +464,17 @@ static void restrict_to(DevLevel& f, DevLevel& c, const T* rf, T* bc, hipStream_
 
 template <typename T>
 static void prolong_from(DevLevel& f, DevLevel& c, const T* ec, T* xf, hipStream_t s) {
+  const Shape sh = shape3(f.n[0], f.n[1], f.dim == 3 ? f.n[2] : 1);
   if (f.dim == 3)
-    hipLaunchKernelGGL((k_prolong<T, 3>), dim3(nblk(f.N)), dim3(kBlock), 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1],
-                       f.n[2]);
+    hipLaunchKernelGGL((k_prolong<T, 3>), sh.g, sh.b, 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1], f.n[2]);
   else
-    hipLaunchKernelGGL((k_prolong<T, 2>), dim3(nblk(f.N)), dim3(kBlock), 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1],
-                       1);
+    hipLaunchKernelGGL((k_prolong<T, 2>), sh.g, sh.b, 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1], 1);
   if (f.n_np > 0)
     hipLaunchKernelGGL((k_prolong_ns<T>), dim3(nblk(f.n_np)), dim3(kBlock), 0, s, (int)f.n_np, f.np_fdof.p,
                        f.np_cdof.p, ec, xf);
   HIPCHECK(hipGetLastError());
 }
 
-template <typename T>
-static void fill(T* x, int64_t n, T v, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL((k_fill<T>), dim3(nblk(n)), dim3(kBlock), 0, s, x, n, v);
-}
 
 template <typename T>
 static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* x, const T* b) {
@@ -430,10 +552,11 @@ static void rhs(ebmg_problem_s* P, const double* rho, const double* sigma, const
   for (int d = 0; d < 3; ++d) dat.n[d] = L.n[d];
   for (int f = 0; f < 6; ++f)
     for (int p = 0; p < 2; ++p) dat.cb[f][p] = H.fine.dat[f][p] * fv.v[f];
+  const Shape sh = shape3(L.n[0], L.n[1], L.dim == 3 ? L.n[2] : 1);
   if (L.dim == 3)
-    hipLaunchKernelGGL((k_rhs_reg<3>), dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, rho, L.b64.p, dat, 0);
+    hipLaunchKernelGGL((k_rhs_reg<3>), sh.g, sh.b, 0, s, L.tag.p, rho, L.b64.p, dat, 0);
   else
-    hipLaunchKernelGGL((k_rhs_reg<2>), dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, rho, L.b64.p, dat, 0);
+    hipLaunchKernelGGL((k_rhs_reg<2>), sh.g, sh.b, 0, s, L.tag.p, rho, L.b64.p, dat, 0);
   if (L.R > 0)
     hipLaunchKernelGGL(k_rhs_irr, dim3(nblk(L.R)), dim3(kBlock), 0, s, (int)L.R, L.irow_dof.p, D.icell.p, D.isrc.p,
                        D.iface.p, D.iobj.p, D.icobj.p, D.icsig.p, rho, sigma, D.objv.p, fv, L.b64.p);
@@ -457,10 +580,11 @@ static void efield(ebmg_problem_s* P, const double* x, const double* sigma, cons
       gb.cb[f][p] = H.fine.egb[f][p] * fv.v[f];
     }
   const double ih = 1.0 / H.levels[0].g.h;
+  const Shape sh = shape3(L.n[0], L.n[1], L.dim == 3 ? L.n[2] : 1);
   if (L.dim == 3)
-    hipLaunchKernelGGL((k_efield_reg<3>), dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, x, E, ga, gb, ih);
+    hipLaunchKernelGGL((k_efield_reg<3>), sh.g, sh.b, 0, s, L.tag.p, x, E, ga, gb, ih);
   else
-    hipLaunchKernelGGL((k_efield_reg<2>), dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, x, E, ga, gb, ih);
+    hipLaunchKernelGGL((k_efield_reg<2>), sh.g, sh.b, 0, s, L.tag.p, x, E, ga, gb, ih);
   const int nc = (int)H.fine.ecell.size();
   if (nc > 0)
     hipLaunchKernelGGL(k_efield_irr, dim3(nblk((int64_t)nc * L.dim)), dim3(kBlock), 0, s, nc, L.dim, L.N, D.ecell.p,
@@ -730,6 +854,8 @@ ebmg_status ebmg_setup(ebmg_ctx ctx, const ebmg_box* box, int32_t nobj, const eb
     H.opt.nu2 = o.nu2 > 0 ? o.nu2 : 2;
     H.opt.bottom_max = o.bottom_max_dof > 0 ? o.bottom_max_dof : 600;
     if (o.krylov < 0 || o.krylov > 2) throw ArgError("bad krylov option");
+    if (o.smoother < 0 || o.smoother > 2) throw ArgError("bad smoother option");
+    H.opt.smoother = o.smoother;
     H.opt.krylov = o.krylov == 0 ? (nobj > 0 ? 2 : 1) : o.krylov;
     if (o.precision != EBMG_FP64 && o.precision != EBMG_MIXED) throw ArgError("bad precision");
     if (!(o.beta != 0.0) || !std::isfinite(o.beta)) throw ArgError("beta must be nonzero");
@@ -785,6 +911,16 @@ ebmg_status ebmg_query_level(ebmg_problem pb, int32_t level, int64_t* n_cells, i
   if (!pb || level < 0 || level >= (int32_t)pb->host->levels.size()) return EBMG_ERR_ARG;
   if (n_cells) *n_cells = pb->host->levels[level].N;
   if (n_phase2) *n_phase2 = pb->host->levels[level].N2;
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_query_tuning(ebmg_problem pb, int32_t level, int32_t* fused, double* split_ms, double* fused_ms) {
+  if (!pb || level < 0 || level >= (int32_t)pb->host->levels.size()) return EBMG_ERR_ARG;
+  if (!pb->on_device) return EBMG_ERR_DEVICE;
+  const DevLevel& l = pb->dev.lv[level];
+  if (fused) *fused = l.fused ? 1 : 0;
+  if (split_ms) *split_ms = l.tune_split_ms;
+  if (fused_ms) *fused_ms = l.tune_fused_ms;
   return EBMG_OK;
 }
 
@@ -942,26 +1078,34 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
     double bytes = 0;
+    const Shape shh = shape3((L.n[0] + 1) / 2, L.n[1], L.dim == 3 ? L.n[2] : 1);
+    const Shape shf = shape3(L.n[0], L.n[1], L.dim == 3 ? L.n[2] : 1);
+    const bool fz = which == 0 && L.fused;
     auto launch = [&](int colour) {
-      const int64_t nxh = (L.n[0] + 1) / 2;
-      const int64_t nthr = nxh * L.n[1] * (L.dim == 3 ? L.n[2] : 1);
+      if (fz) {
+        if (mixed)
+          launch_fused<float>(L, (colour & 1) ? L.xa32.p : L.x32.p, (colour & 1) ? L.x32.p : L.xa32.p, L.b32.p, L.t32, s);
+        else
+          launch_fused<double>(L, (colour & 1) ? L.xa64.p : L.x64.p, (colour & 1) ? L.x64.p : L.xa64.p, L.b64.p, L.t64, s);
+        return;
+      }
       if (which == 0) {
-        if (mixed && level >= 0) {
+        if (mixed) {
           if (L.dim == 3)
-            hipLaunchKernelGGL((k_rb<float, 3>), dim3(nblk(nthr)), dim3(kBlock), 0, s, L.tag.p, L.x32.p, L.b32.p, L.t32, colour);
+            hipLaunchKernelGGL((k_rb<float, 3>), shh.g, shh.b, 0, s, L.tag.p, L.x32.p, L.b32.p, L.t32, colour);
           else
-            hipLaunchKernelGGL((k_rb<float, 2>), dim3(nblk(nthr)), dim3(kBlock), 0, s, L.tag.p, L.x32.p, L.b32.p, L.t32, colour);
+            hipLaunchKernelGGL((k_rb<float, 2>), shh.g, shh.b, 0, s, L.tag.p, L.x32.p, L.b32.p, L.t32, colour);
         } else {
           if (L.dim == 3)
-            hipLaunchKernelGGL((k_rb<double, 3>), dim3(nblk(nthr)), dim3(kBlock), 0, s, L.tag.p, L.x64.p, L.b64.p, L.t64, colour);
+            hipLaunchKernelGGL((k_rb<double, 3>), shh.g, shh.b, 0, s, L.tag.p, L.x64.p, L.b64.p, L.t64, colour);
           else
-            hipLaunchKernelGGL((k_rb<double, 2>), dim3(nblk(nthr)), dim3(kBlock), 0, s, L.tag.p, L.x64.p, L.b64.p, L.t64, colour);
+            hipLaunchKernelGGL((k_rb<double, 2>), shh.g, shh.b, 0, s, L.tag.p, L.x64.p, L.b64.p, L.t64, colour);
         }
       } else {
         if (L.dim == 3)
-          hipLaunchKernelGGL((k_resid_reg<double, 3, 0>), dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, L.x64.p, L.b64.p, L.r64.p, L.t64);
+          hipLaunchKernelGGL((k_resid_reg<double, 3, 0>), shf.g, shf.b, 0, s, L.tag.p, L.x64.p, L.b64.p, L.r64.p, L.t64);
         else
-          hipLaunchKernelGGL((k_resid_reg<double, 2, 0>), dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, L.x64.p, L.b64.p, L.r64.p, L.t64);
+          hipLaunchKernelGGL((k_resid_reg<double, 2, 0>), shf.g, shf.b, 0, s, L.tag.p, L.x64.p, L.b64.p, L.r64.p, L.t64);
       }
     };
     if (which != 0 && which != 1) throw ArgError("unknown kernel id");
@@ -970,11 +1114,14 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
       // algorithmic bytes of one half-sweep: each updated cell reads x and b,
       // writes x, reads its tag
       const int es = mixed ? 4 : 8;
-      bytes = (double)nreg_half * (3.0 * es + 1.0);
+      // half-sweep: the cells of one colour; fused sweep: every cell
+      bytes = (fz ? (double)L.N : (double)nreg_half) * (3.0 * es + 1.0);
       if (mixed) {
         fill<float>(L.x32.p, nd, 0.0f, s);
         fill<float>(L.b32.p, nd, 0.0f, s);
+        if (L.xa32.p) fill<float>(L.xa32.p, nd, 0.0f, s);
       } else {
+        if (L.xa64.p) fill<double>(L.xa64.p, nd, 0.0, s);
         fill<double>(L.x64.p, nd, 0.0, s);
         fill<double>(L.b64.p, nd, 0.0, s);
       }

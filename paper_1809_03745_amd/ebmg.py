@@ -61,7 +61,8 @@ class Options(C.Structure):
     _fields_ = [("alpha", C.c_double), ("beta", C.c_double), ("a_gas", C.c_double), ("a_diel", C.c_double),
                 ("b_gas", C.c_double), ("dirichlet_closure", C.c_int32), ("robin_closure", C.c_int32),
                 ("eb_order", C.c_int32), ("precision", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
-                ("bottom_max_dof", C.c_int32), ("krylov", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("bottom_max_dof", C.c_int32), ("krylov", C.c_int32), ("smoother", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class SolveInfo(C.Structure):
@@ -97,6 +98,7 @@ _sig("ebmg_setup", C.c_int, [_vp, C.POINTER(Box), C.c_int32, C.POINTER(Object), 
 _sig("ebmg_query", C.c_int, [_vp, _i64p, _i64p, C.POINTER(C.c_int32), _i64p])
 _sig("ebmg_query_level", C.c_int, [_vp, C.c_int32, _i64p, _i64p])
 _sig("ebmg_export_level", C.c_int, [_vp, C.c_int32, _vp, _vp, _vp])
+_sig("ebmg_query_tuning", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), _dp, _dp])
 _sig("ebmg_export_geometry", C.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_export_operator", C.c_int, [_vp, C.c_int32, _i64p, _vp, _vp, _vp])
 _sig("ebmg_export_rhs", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp])
@@ -108,7 +110,7 @@ _sig("ebmg_time_kernel", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _dp, _d
 _sig("ebmg_release", C.c_int, [_vp])
 
 EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_destroy", "ebmg_last_error",
-            "ebmg_setup", "ebmg_query", "ebmg_query_level", "ebmg_export_level",
+            "ebmg_setup", "ebmg_query", "ebmg_query_level", "ebmg_export_level", "ebmg_query_tuning",
             "ebmg_export_geometry", "ebmg_export_operator", "ebmg_export_rhs",
             "ebmg_solve", "ebmg_apply", "ebmg_efield", "ebmg_time_kernel", "ebmg_release"]
 
@@ -162,7 +164,7 @@ KRYLOV_AUTO, KRYLOV_NONE, KRYLOV_BICGSTAB = 0, 1, 2
 
 
 def make_options(prob, precision=FP64, dirichlet_closure=0, robin_closure=0, eb_order=2, nu1=2, nu2=2,
-                 bottom_max_dof=0, krylov=KRYLOV_AUTO):
+                 bottom_max_dof=0, krylov=KRYLOV_AUTO, smoother=0):
     o = Options()
     _lib.ebmg_default_options(C.byref(o))
     o.alpha = prob.alpha
@@ -178,6 +180,7 @@ def make_options(prob, precision=FP64, dirichlet_closure=0, robin_closure=0, eb_
     o.nu2 = nu2
     o.bottom_max_dof = bottom_max_dof
     o.krylov = krylov
+    o.smoother = smoother
     return o
 
 
@@ -285,6 +288,12 @@ class Problem:
         ov = _host_f64(obj_values)
         self.ctx.check(_lib.ebmg_efield(self.h, _ptr(phi), _ptr(phi2), _ptr(sigma), _ptr(bcv), _ptr(ov), _ptr(E)),
                        "ebmg_efield")
+
+    def tuning(self, level):
+        """(fused chosen, split sweep ms, fused sweep ms) from the setup autotuner."""
+        f, a, b = C.c_int32(), C.c_double(), C.c_double()
+        self.ctx.check(_lib.ebmg_query_tuning(self.h, level, C.byref(f), C.byref(a), C.byref(b)), "tuning")
+        return bool(f.value), a.value, b.value
 
     def time_kernel(self, which, level=0, reps=50):
         """(mean ms per launch, algorithmic bytes per launch) of a kernel."""

@@ -208,6 +208,32 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
 
 ebmg_status ebmg_release(ebmg_problem pb);
 
+/* Batched boxes (independent problems of one dimension and one precision),
+ * e.g. the leaves of a patch-based hierarchy. Setup builds every box on the
+ * host (in parallel) and uploads it; boxes[i] with nobj[i] objects objs[i],
+ * bcs[i] and opts[i] (opts may be NULL for defaults). */
+ebmg_status ebmg_setup_batch(ebmg_ctx ctx, int32_t nbox, const ebmg_box* boxes, const int32_t* nobj,
+                             const ebmg_object* const* objs, const ebmg_domain_bc* bcs, const ebmg_options* opts,
+                             ebmg_batch* out);
+
+/* Total cells, second-phase unknowns and device bytes of a batch. */
+ebmg_status ebmg_query_batch(ebmg_batch bt, int64_t* cells, int64_t* cells2, int64_t* device_bytes);
+
+/* Solve every box in ONE persistent launch: workgroups of 1024 threads take
+ * boxes (largest first, fixed assignment) and run the whole solve in-group:
+ * right-hand side, FP64 residual, V-cycle (FP32 for mixed precision) as the
+ * BiCGStab preconditioner or as plain refinement, to ||r|| <= rtol ||b||.
+ * rho[i], sigma[i] (sigma or its entries may be NULL), phi[i] (in: guess,
+ * out: solution) and phi2[i] (may be NULL when the box has no second-phase
+ * unknowns) are DEVICE arrays of box i; the pointer arrays themselves are
+ * HOST arrays. Boundary values are those given at setup. infos (HOST, nbox
+ * entries, may be NULL) receives per-box results; the status is the first
+ * non-OK box status. A box's result does not depend on the other boxes. */
+ebmg_status ebmg_solve_batch(ebmg_batch bt, const double* const* rho, const double* const* sigma, double rtol,
+                             int32_t max_cycles, double* const* phi, double* const* phi2, ebmg_solve_info* infos);
+
+ebmg_status ebmg_release_batch(ebmg_batch bt);
+
 #ifdef __cplusplus
 }
 #endif

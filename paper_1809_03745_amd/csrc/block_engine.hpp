@@ -1,0 +1,497 @@
+// Single-workgroup multigrid engine (gfx950).
+//
+// Small levels are latency-bound: a V-cycle over them as separate grid-wide
+// launches pays a launch and a drain per phase. Here one workgroup of
+// kBE threads runs a whole (sub-)V-cycle -- red/black sweeps, explicit-row
+// groups, residual, restriction, prolongation and the dense bottom solve --
+// with workgroup barriers between phases and the level data in global memory
+// (L2-resident at these sizes). It serves two uses: the coarse tail of a
+// large hierarchy (one launch per V-cycle instead of ~30 per level), and the
+// batched solver, where each workgroup of a persistent grid solves whole
+// boxes on a fixed round-robin over a largest-first order.
+//
+// Phases follow the grid-wide kernels exactly (same update formulas, same
+// summation orders); the explicit rows use one thread per row here.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace ebmg {
+
+constexpr int kBE = 1024;       // threads of an engine workgroup
+constexpr int kMaxLev = 16;
+
+// Device view of one multigrid level (all pointers device memory).
+template <typename T>
+struct BLev {
+  int dim;
+  int n[3];
+  int N, N2, R;
+  const uint8_t* tag;
+  const int64_t* irow_dof;
+  const int64_t* rp;
+  const int32_t* col;
+  const T* val;
+  const T* diag;
+  const int32_t* grp_rows;
+  int grp_ptr[3];
+  Tmpl<T> tp;
+  T* x;
+  T* b;
+  T* r;
+  T* w;
+  // transfer to the next coarser level
+  int n_ns;
+  const int64_t* ns_cdof;
+  const int32_t* ns_ptr;
+  const int64_t* ns_child;
+  int n_np;
+  const int64_t* np_fdof;
+  const int64_t* np_cdof;
+};
+
+template <typename T>
+__device__ void be_fill(T* x, int n, T v) {
+  for (int t = threadIdx.x; t < n; t += blockDim.x) x[t] = v;
+  __syncthreads();
+}
+
+template <typename T, int DIM>
+__device__ void be_rb(const BLev<T>& L, T* __restrict__ x, const T* __restrict__ b, int colour) {
+  const int nx = L.n[0], ny = L.n[1];
+  const int nxh = (nx + 1) >> 1;
+  const int nthr = nxh * ny * (DIM == 3 ? L.n[2] : 1);
+  for (int t = threadIdx.x; t < nthr; t += blockDim.x) {
+    const int ih = t % nxh;
+    const int jk = t / nxh;
+    const int j = jk % ny;
+    const int k = DIM == 3 ? jk / ny : 0;
+    const int i = 2 * ih + ((j + k + colour) & 1);
+    if (i >= nx) continue;
+    const int64_t c = i + (int64_t)nx * jk;
+    const uint8_t p = tclass(L.tag[c]);
+    if (p > 1) continue;
+    T dg;
+    const T off = template_apply<T, DIM>(x, L.tp, i, j, k, c, p, dg);
+    x[c] = (b[c] - off) / dg;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void be_irr_group(const BLev<T>& L, int grp, T* __restrict__ x, const T* __restrict__ b) {
+  const int r0 = L.grp_ptr[grp], r1 = L.grp_ptr[grp + 1];
+  if (r1 <= r0) return;
+  for (int g = r0 + threadIdx.x; g < r1; g += blockDim.x) {
+    const int r = L.grp_rows[g];
+    T s = 0;
+    for (int64_t e = L.rp[r]; e < L.rp[r + 1]; ++e) s += L.val[e] * x[L.col[e]];
+    L.w[g - r0] = (b[L.irow_dof[r]] - s) / L.diag[r];
+  }
+  __syncthreads();
+  for (int g = r0 + threadIdx.x; g < r1; g += blockDim.x) x[L.irow_dof[L.grp_rows[g]]] = L.w[g - r0];
+  __syncthreads();
+}
+
+template <typename T, int DIM>
+__device__ void be_smooth(const BLev<T>& L, T* x, const T* b, int sweeps) {
+  for (int it = 0; it < sweeps; ++it)
+    for (int colour = 0; colour < 2; ++colour) {
+      be_rb<T, DIM>(L, x, b, colour);
+      be_irr_group<T>(L, colour, x, b);
+    }
+}
+
+// MODE 0: r = b - A x; MODE 1: r = A x
+template <typename T, int DIM, int MODE>
+__device__ void be_resid(const BLev<T>& L, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ r) {
+  const int nx = L.n[0], ny = L.n[1];
+  for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
+    const uint8_t p = tclass(L.tag[c]);
+    if (p == 3) {
+      r[c] = MODE == 0 ? T(0) : x[c];
+      continue;
+    }
+    if (p == 2) continue;
+    const int i = c % nx;
+    const int jk = c / nx;
+    const int j = jk % ny;
+    const int k = DIM == 3 ? jk / ny : 0;
+    T dg;
+    const T off = template_apply<T, DIM>(x, L.tp, i, j, k, c, p, dg);
+    const T ax = dg * x[c] + off;
+    r[c] = MODE == 0 ? b[c] - ax : ax;
+  }
+  for (int g = threadIdx.x; g < L.R; g += blockDim.x) {
+    const int64_t q = L.irow_dof[g];
+    T s = 0;
+    for (int64_t e = L.rp[g]; e < L.rp[g + 1]; ++e) s += L.val[e] * x[L.col[e]];
+    const T ax = L.diag[g] * x[q] + s;
+    r[q] = MODE == 0 ? b[q] - ax : ax;
+  }
+  __syncthreads();
+}
+
+template <typename T, int DIM>
+__device__ void be_restrict(const BLev<T>& F, const BLev<T>& Cl, const T* __restrict__ rf, T* __restrict__ bc) {
+  const int cnx = Cl.n[0], cny = Cl.n[1];
+  const int fnx = 2 * cnx;
+  const int64_t fsxy = (int64_t)fnx * 2 * cny;
+  for (int P = threadIdx.x; P < Cl.N; P += blockDim.x) {
+    const uint8_t t = Cl.tag[P];
+    if (tclass(t) == 3) {
+      bc[P] = 0;
+      continue;
+    }
+    if (t & 4) continue;
+    const int I = P % cnx;
+    const int JK = P / cnx;
+    const int J = JK % cny;
+    const int K = DIM == 3 ? JK / cny : 0;
+    const int64_t c0 = 2 * I + (int64_t)fnx * (2 * J) + (DIM == 3 ? fsxy * (2 * K) : 0);
+    T s = rf[c0] + rf[c0 + 1] + rf[c0 + fnx] + rf[c0 + fnx + 1];
+    if (DIM == 3) s += rf[c0 + fsxy] + rf[c0 + fsxy + 1] + rf[c0 + fsxy + fnx] + rf[c0 + fsxy + fnx + 1];
+    bc[P] = s * (DIM == 3 ? T(0.125) : T(0.25));
+  }
+  for (int t = threadIdx.x; t < F.n_ns; t += blockDim.x) {
+    T s = 0;
+    for (int e = F.ns_ptr[t]; e < F.ns_ptr[t + 1]; ++e) s += rf[F.ns_child[e]];
+    bc[F.ns_cdof[t]] = s * (DIM == 3 ? T(0.125) : T(0.25));
+  }
+  __syncthreads();
+}
+
+template <typename T, int DIM>
+__device__ void be_prolong(const BLev<T>& F, const BLev<T>& Cl, const T* __restrict__ ec, T* __restrict__ xf) {
+  const int fnx = F.n[0], fny = F.n[1];
+  const int cnx = fnx >> 1, cny = fny >> 1;
+  for (int c = threadIdx.x; c < F.N; c += blockDim.x) {
+    if (tclass(F.tag[c]) == 3) continue;
+    const int i = c % fnx;
+    const int jk = c / fnx;
+    const int j = jk % fny;
+    const int k = DIM == 3 ? jk / fny : 0;
+    const int P = (i >> 1) + cnx * ((j >> 1) + cny * (k >> 1));
+    if (Cl.tag[P] & 4) continue;
+    xf[c] += ec[P];
+  }
+  for (int t = threadIdx.x; t < F.n_np; t += blockDim.x) xf[F.np_fdof[t]] += ec[F.np_cdof[t]];
+  __syncthreads();
+}
+
+// x = Ainv b on the bottom level (FP64 accumulation), thread per row
+template <typename T>
+__device__ void be_bottom(const double* __restrict__ Ainv, int n, const T* __restrict__ b, T* __restrict__ x) {
+  for (int row = threadIdx.x; row < n; row += blockDim.x) {
+    double s = 0;
+    for (int c = 0; c < n; ++c) s += Ainv[(int64_t)row * n + c] * (double)b[c];
+    x[row] = (T)s;
+  }
+  __syncthreads();
+}
+
+// V-cycle over levels l0 .. nlev-1; level l0 uses (x0, b0), deeper levels
+// their own vectors.
+template <typename T, int DIM>
+__device__ void be_vcycle(const BLev<T>* lv, int l0, int nlev, const double* Ainv, int nbot, int nu1, int nu2,
+                          T* x0, const T* b0) {
+  for (int l = l0; l < nlev - 1; ++l) {
+    T* x = l == l0 ? x0 : lv[l].x;
+    const T* b = l == l0 ? b0 : lv[l].b;
+    be_smooth<T, DIM>(lv[l], x, b, nu1);
+    be_resid<T, DIM, 0>(lv[l], x, b, lv[l].r);
+    be_restrict<T, DIM>(lv[l], lv[l + 1], lv[l].r, lv[l + 1].b);
+    be_fill<T>(lv[l + 1].x, lv[l + 1].N + lv[l + 1].N2, T(0));
+  }
+  {
+    const int l = nlev - 1;
+    T* x = l == l0 ? x0 : lv[l].x;
+    const T* b = l == l0 ? b0 : lv[l].b;
+    if (Ainv)
+      be_bottom<T>(Ainv, nbot, b, x);
+    else
+      be_smooth<T, DIM>(lv[l], x, b, 40);
+  }
+  for (int l = nlev - 2; l >= l0; --l) {
+    T* x = l == l0 ? x0 : lv[l].x;
+    const T* b = l == l0 ? b0 : lv[l].b;
+    be_prolong<T, DIM>(lv[l], lv[l + 1], lv[l + 1].x, x);
+    be_smooth<T, DIM>(lv[l], x, b, nu2);
+  }
+}
+
+// Coarse tail of a large hierarchy: one workgroup runs the V-cycle from
+// level l0 down, on (x0, b0) at level l0 (x0 holds the initial guess).
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBE) k_tail_vcycle(const BLev<T>* lv, int l0, int nlev, const double* Ainv,
+                                                     int nbot, int nu1, int nu2, T* x0, const T* b0) {
+  be_vcycle<T, DIM>(lv, l0, nlev, Ainv, nbot, nu1, nu2, x0, b0);
+}
+
+}  // namespace ebmg
+
+namespace ebmg {
+
+// ---------------------------------------------------------------------------
+// batched solver: one workgroup per box at a time
+// ---------------------------------------------------------------------------
+template <typename T>
+struct BBox {
+  int dim;
+  int nlev;
+  int N, N2;
+  const BLev<T>* lv;     // cycle levels (precision T)
+  BLev<double> f64;      // finest level in FP64 (residual, matvec, refinement)
+  const double* Ainv;
+  int nbot;
+  // right-hand-side data
+  const int64_t* icell;
+  const double* isrc;
+  const double* iface;
+  const int32_t* iobj;
+  const double* icobj;
+  const double* icsig;
+  Tmpl<double> dat;      // regular cells: b -= dat.cb[f][p] on touched faces
+  double fv[6];
+  const double* objv;
+  // BiCGStab work vectors (FP64, N + N2 each): r, rh, p, v, ph, s, sh, t
+  double* kv[8];
+  int krylov;            // 2: BiCGStab, else plain V-cycles with refinement
+};
+
+struct BIO {
+  const double* rho;
+  const double* sigma;
+  double* phi;
+  double* phi2;
+};
+
+struct BRes {
+  int cycles;
+  int iters;
+  int status;
+  int pad;
+  double r0;
+  double rel;
+};
+
+// deterministic workgroup dot product (fixed-order tree in LDS)
+__device__ inline double be_dot(const double* __restrict__ a, const double* __restrict__ b, int n, double* red) {
+  double s = 0;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) s += a[t] * b[t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double v = red[0];
+  __syncthreads();
+  return v;
+}
+
+template <int DIM>
+__device__ void be_rhs(const BLev<double>& F, const Tmpl<double>& dat, const double* fv, const int64_t* icell,
+                       const double* isrc, const double* iface, const int32_t* iobj, const double* icobj,
+                       const double* icsig, const double* objv, const double* rho, const double* sigma, double* b) {
+  const int nx = F.n[0], ny = F.n[1];
+  for (int c = threadIdx.x; c < F.N; c += blockDim.x) {
+    const uint8_t p = tclass(F.tag[c]);
+    if (p == 3) {
+      b[c] = 0;
+      continue;
+    }
+    if (p == 2) continue;
+    const int i = c % nx;
+    const int jk = c / nx;
+    const int j = jk % ny;
+    const int k = DIM == 3 ? jk / ny : 0;
+    double v = rho[c];
+    if (i == 0) v -= dat.cb[0][p];
+    if (i == nx - 1) v -= dat.cb[1][p];
+    if (j == 0) v -= dat.cb[2][p];
+    if (j == ny - 1) v -= dat.cb[3][p];
+    if (DIM == 3) {
+      if (k == 0) v -= dat.cb[4][p];
+      if (k == F.n[2] - 1) v -= dat.cb[5][p];
+    }
+    b[c] = v;
+  }
+  for (int t = threadIdx.x; t < F.R; t += blockDim.x) {
+    const int64_t c = icell[t];
+    double v = isrc[t] * rho[c];
+    for (int f = 0; f < 6; ++f) v -= iface[6 * t + f] * fv[f];
+    if (iobj[t] >= 0) v -= icobj[t] * objv[iobj[t]];
+    if (sigma) v -= icsig[t] * sigma[c];
+    b[F.irow_dof[t]] = v;
+  }
+  __syncthreads();
+}
+
+// z = M r: one V-cycle from zero in precision T (FP64 in, FP64 out)
+template <typename T, int DIM>
+__device__ void be_precond(const BBox<T>& B, const BLev<T>* lv, int nu1, int nu2, const double* r, double* z) {
+  const int nd = B.N + B.N2;
+  if (sizeof(T) == sizeof(double)) {
+    for (int t = threadIdx.x; t < nd; t += blockDim.x) z[t] = 0.0;
+    __syncthreads();
+    be_vcycle<T, DIM>(lv, 0, B.nlev, B.Ainv, B.nbot, nu1, nu2, (T*)z, (const T*)r);
+  } else {
+    T* x0 = lv[0].x;
+    T* b0 = lv[0].b;
+    for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+      b0[t] = (T)r[t];
+      x0[t] = T(0);
+    }
+    __syncthreads();
+    be_vcycle<T, DIM>(lv, 0, B.nlev, B.Ainv, B.nbot, nu1, nu2, x0, b0);
+    for (int t = threadIdx.x; t < nd; t += blockDim.x) z[t] = (double)x0[t];
+    __syncthreads();
+  }
+}
+
+template <typename T, int DIM>
+__device__ void be_solve_box(const BBox<T>& B, const BIO& io, BRes& out, double rtol, int max_cycles, int nu1,
+                             int nu2, double* red) {
+  const BLev<double>& F = B.f64;
+  const BLev<T>* lv = B.lv;
+  const int N = B.N, nd = B.N + B.N2;
+  double* x = F.x;
+  double* b = F.b;
+  be_rhs<DIM>(F, B.dat, B.fv, B.icell, B.isrc, B.iface, B.iobj, B.icobj, B.icsig, B.objv, io.rho, io.sigma,
+              b);
+  for (int t = threadIdx.x; t < nd; t += blockDim.x) x[t] = t < N ? io.phi[t] : (io.phi2 ? io.phi2[t - N] : 0.0);
+  __syncthreads();
+  const double bn = sqrt(be_dot(b, b, nd, red));
+  int status = 0, cycles = 0, iters = 0;
+  double rel = 0;
+  if (!(bn == bn) || bn > 1e300) {
+    status = EBMG_ERR_NUMERIC;
+  } else if (bn > 0) {
+    double* r = B.kv[0];
+    be_resid<double, DIM, 0>(F, x, b, r);
+    rel = sqrt(be_dot(r, r, nd, red)) / bn;
+    if (B.krylov != 2) {
+      double* e = B.kv[4];
+      while (rel > rtol) {
+        if (cycles >= max_cycles) {
+          status = EBMG_ERR_NOCONV;
+          break;
+        }
+        be_precond<T, DIM>(B, lv, nu1, nu2, r, e);
+        for (int t = threadIdx.x; t < nd; t += blockDim.x) x[t] += e[t];
+        __syncthreads();
+        ++cycles;
+        ++iters;
+        be_resid<double, DIM, 0>(F, x, b, r);
+        rel = sqrt(be_dot(r, r, nd, red)) / bn;
+        if (!(rel == rel) || rel > 1e6) {
+          status = EBMG_ERR_NUMERIC;
+          break;
+        }
+      }
+    } else {
+      double *rh = B.kv[1], *p = B.kv[2], *v = B.kv[3], *ph = B.kv[4], *sv = B.kv[5], *sh = B.kv[6],
+             *tv = B.kv[7];
+      int restarts = 0;
+      double rho_old = 1, alpha = 1, omega = 1;
+      for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+        rh[t] = r[t];
+        p[t] = 0;
+        v[t] = 0;
+      }
+      __syncthreads();
+      while (rel > rtol) {
+        if (cycles + 2 > max_cycles) {
+          status = EBMG_ERR_NOCONV;
+          break;
+        }
+        const double rho = be_dot(rh, r, nd, red);
+        const double beta = (rho / rho_old) * (alpha / omega);
+        for (int t = threadIdx.x; t < nd; t += blockDim.x) p[t] = r[t] + beta * (p[t] - omega * v[t]);
+        __syncthreads();
+        be_precond<T, DIM>(B, lv, nu1, nu2, p, ph);
+        be_resid<double, DIM, 1>(F, ph, nullptr, v);
+        alpha = rho / be_dot(rh, v, nd, red);
+        for (int t = threadIdx.x; t < nd; t += blockDim.x) sv[t] = r[t] - alpha * v[t];
+        __syncthreads();
+        be_precond<T, DIM>(B, lv, nu1, nu2, sv, sh);
+        be_resid<double, DIM, 1>(F, sh, nullptr, tv);
+        const double ts = be_dot(tv, sv, nd, red);
+        const double tt = be_dot(tv, tv, nd, red);
+        omega = tt > 0 ? ts / tt : 0.0;
+        rho_old = rho;
+        for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+          x[t] += alpha * ph[t] + omega * sh[t];
+          r[t] = sv[t] - omega * tv[t];
+        }
+        __syncthreads();
+        cycles += 2;
+        ++iters;
+        double nrel = sqrt(be_dot(r, r, nd, red)) / bn;
+        const bool broke = !(nrel == nrel) || !(alpha == alpha) || omega == 0.0 || !(omega == omega);
+        if (broke || nrel <= rtol) {
+          be_resid<double, DIM, 0>(F, x, b, r);
+          nrel = sqrt(be_dot(r, r, nd, red)) / bn;
+          if (!(nrel == nrel) || nrel > 1e6) {
+            rel = nrel;
+            status = EBMG_ERR_NUMERIC;
+            break;
+          }
+          if (nrel > rtol) {
+            if (++restarts > 8) {
+              rel = nrel;
+              status = EBMG_ERR_NOCONV;
+              break;
+            }
+            for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+              rh[t] = r[t];
+              p[t] = 0;
+              v[t] = 0;
+            }
+            __syncthreads();
+            rho_old = alpha = omega = 1;
+          }
+        } else if (nrel > 1e6) {
+          rel = nrel;
+          status = EBMG_ERR_NUMERIC;
+          break;
+        }
+        rel = nrel;
+      }
+    }
+  } else {
+    for (int t = threadIdx.x; t < nd; t += blockDim.x) x[t] = 0;
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+    if (t < N)
+      io.phi[t] = x[t];
+    else if (io.phi2)
+      io.phi2[t - N] = x[t];
+  }
+  if (threadIdx.x == 0) {
+    out.cycles = cycles;
+    out.iters = iters;
+    out.status = status;
+    out.r0 = bn;
+    out.rel = rel;
+  }
+  __syncthreads();
+}
+
+// Persistent batched solve: workgroup g solves boxes order[g], order[g+G], ...
+// (order lists the boxes largest first), so the assignment is fixed and the
+// result of a box does not depend on the others.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBE) k_batch_solve(const BBox<T>* boxes, const BIO* io, BRes* res,
+                                                     const int32_t* order, int nbox, double rtol, int max_cycles,
+                                                     int nu1, int nu2) {
+  __shared__ double red[kBE];
+  for (int q = blockIdx.x; q < nbox; q += gridDim.x) {
+    const int bi = order[q];
+    be_solve_box<T, DIM>(boxes[bi], io[bi], res[bi], rtol, max_cycles, nu1, nu2, red);
+  }
+}
+
+}  // namespace ebmg

@@ -10,7 +10,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <thread>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -18,6 +20,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "block_engine.hpp"
 #include "kernels.hpp"
 
 namespace ebmg {
@@ -118,6 +121,9 @@ struct DevProblem {
   // BiCGStab work vectors: r, rh, p, v, ph, s, sh, t
   DevBuf<double> kv[8];
   bool krylov = false;
+  // coarse tail run by one workgroup: levels tail_l0 .. end
+  int tail_l0 = -1;
+  DevBuf<uint8_t> tail_lv;
   int64_t bytes = 0;
   void release() {
     for (auto& l : lv) l.release();
@@ -126,6 +132,7 @@ struct DevProblem {
     iobj.release(); ecell.release(); erp.release(); ecol.release(); eobj.release(); eval.release();
     eface.release(); ecobj.release(); ecsig.release(); objv.release(); part.release(); scal.release();
     for (auto& k : kv) k.release();
+    tail_lv.release();
     if (host_scal) (void)hipHostFree(host_scal);
     host_scal = nullptr;
   }
@@ -147,6 +154,21 @@ struct ebmg_problem_s {
   bool on_device = false;
 };
 
+// Many independent boxes solved by one persistent launch.
+struct ebmg_batch_s {
+  ebmg_ctx ctx = nullptr;
+  std::vector<std::unique_ptr<ebmg_problem_s>> boxes;
+  std::vector<ebmg::DevBuf<uint8_t>> lvbuf;   // per-box device level views
+  ebmg::DevBuf<uint8_t> bbox;                 // BBox<T> per box
+  ebmg::DevBuf<uint8_t> bio;                  // BIO per box
+  ebmg::DevBuf<uint8_t> bres;                 // BRes per box
+  ebmg::DevBuf<int32_t> order;                // boxes, largest first
+  bool mixed = false;
+  int dim = 3;
+  int nu1 = 2, nu2 = 2;
+  int64_t cells = 0, cells2 = 0, bytes = 0;
+};
+
 namespace ebmg {
 
 // ---------------------------------------------------------------------------
@@ -163,6 +185,31 @@ static Tmpl<T> make_tmpl(const Level& L) {
   for (int d = 0; d < 3; ++d) t.n[d] = L.g.n[d];
   return t;
 }
+
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+  static double* x(DevLevel& l) { return l.x64.p; }
+  static double* b(DevLevel& l) { return l.b64.p; }
+  static double* r(DevLevel& l) { return l.r64.p; }
+  static const double* val(DevLevel& l) { return l.val64.p; }
+  static const double* diag(DevLevel& l) { return l.diag64.p; }
+  static const Tmpl<double>& t(DevLevel& l) { return l.t64; }
+  static double* tmp(DevLevel& l) { return l.w64.p; }
+  static double* xa(DevLevel& l) { return l.xa64.p; }
+};
+template <>
+struct Vec<float> {
+  static float* x(DevLevel& l) { return l.x32.p; }
+  static float* b(DevLevel& l) { return l.b32.p; }
+  static float* r(DevLevel& l) { return l.r32.p; }
+  static const float* val(DevLevel& l) { return l.val32.p; }
+  static const float* diag(DevLevel& l) { return l.diag32.p; }
+  static const Tmpl<float>& t(DevLevel& l) { return l.t32; }
+  static float* tmp(DevLevel& l) { return l.w32.p; }
+  static float* xa(DevLevel& l) { return l.xa32.p; }
+};
 
 template <typename T>
 static void fill(T* x, int64_t n, T v, hipStream_t s) {
@@ -183,6 +230,55 @@ static void launch_fused(DevLevel& l, const T* xin, T* xout, const T* b, const T
     const int64_t nb = (int64_t)((l.n[0] + kTX2 - 1) / kTX2) * ((l.n[1] + kTY2 - 1) / kTY2);
     hipLaunchKernelGGL((k_rb_tile2<T>), dim3((unsigned)nb), dim3(kTileThreads), 0, s, l.tag.p, xin, xout, b, tp, l.N2);
   }
+}
+
+// Levels with at most this many unknowns are run by the one-workgroup engine.
+constexpr int64_t kTailMax = 4096;
+
+template <typename T>
+static BLev<T> make_blev(DevLevel& l) {
+  BLev<T> v;
+  std::memset(&v, 0, sizeof(v));
+  v.dim = l.dim;
+  for (int d = 0; d < 3; ++d) v.n[d] = l.n[d];
+  v.N = (int)l.N;
+  v.N2 = (int)l.N2;
+  v.R = (int)l.R;
+  v.tag = l.tag.p;
+  v.irow_dof = l.irow_dof.p;
+  v.rp = l.rp.p;
+  v.col = l.col.p;
+  v.val = Vec<T>::val(l);
+  v.diag = Vec<T>::diag(l);
+  v.grp_rows = l.cls_rows.p;
+  for (int g = 0; g < 3; ++g) v.grp_ptr[g] = g < (int)l.cls_ptr.size() ? l.cls_ptr[g] : 0;
+  v.tp = Vec<T>::t(l);
+  v.x = Vec<T>::x(l);
+  v.b = Vec<T>::b(l);
+  v.r = Vec<T>::r(l);
+  v.w = Vec<T>::tmp(l);
+  v.n_ns = (int)l.n_ns;
+  v.ns_cdof = l.ns_cdof.p;
+  v.ns_ptr = l.ns_ptr.p;
+  v.ns_child = l.ns_child.p;
+  v.n_np = (int)l.n_np;
+  v.np_fdof = l.np_fdof.p;
+  v.np_cdof = l.np_cdof.p;
+  return v;
+}
+
+template <typename T>
+static void upload_tail(DevProblem& D, hipStream_t s) {
+  const int nl = (int)D.lv.size();
+  int l0 = nl - 1;
+  while (l0 > 0 && D.lv[l0 - 1].N + D.lv[l0 - 1].N2 <= kTailMax) --l0;
+  D.tail_l0 = l0;
+  std::vector<BLev<T>> v;
+  for (int l = 0; l < nl; ++l) v.push_back(make_blev<T>(D.lv[l]));
+  int64_t by = 0;
+  D.tail_lv.upload((const uint8_t*)v.data(), (int64_t)(v.size() * sizeof(BLev<T>)), s, by);
+  D.bytes += by;
+  HIPCHECK(hipStreamSynchronize(s));
 }
 
 // Smoother autotuner: on levels where the fused tile sweep applies, time one
@@ -251,7 +347,7 @@ static void tune_smoother(DevLevel& l, bool mixed, int mode, hipStream_t s) {
   }
 }
 
-static void upload(ebmg_problem_s* P) {
+static void upload(ebmg_problem_s* P, bool batch_box = false) {
   Problem& H = *P->host;
   DevProblem& D = P->dev;
   hipStream_t s = P->ctx->stream;
@@ -295,14 +391,14 @@ static void upload(ebmg_problem_s* P) {
       d.b64.alloc(nd, by);
       d.r64.alloc(nd, by);
       d.w64.alloc(std::max<int64_t>(1, d.R), by);
-      if (fused_ok(d)) d.xa64.alloc(nd, by);
+      if (fused_ok(d) && !batch_box) d.xa64.alloc(nd, by);
     }
     if (mixed) {
       d.x32.alloc(nd, by);
       d.b32.alloc(nd, by);
       d.r32.alloc(nd, by);
       d.w32.alloc(std::max<int64_t>(1, d.R), by);
-      if (fused_ok(d)) d.xa32.alloc(nd, by);
+      if (fused_ok(d) && !batch_box) d.xa32.alloc(nd, by);
     }
   }
   D.bottom_n = H.bottom_n;
@@ -349,9 +445,19 @@ static void upload(ebmg_problem_s* P) {
   D.part.alloc(2 * kNormBlocks, by);
   D.scal.alloc(SC_NUM, by);
   HIPCHECK(hipHostMalloc((void**)&D.host_scal, SC_NUM * sizeof(double), hipHostMallocDefault));
+  D.krylov = H.opt.krylov == 2;
+  if (batch_box) {
+    // the in-group solver keeps its Krylov / correction vectors here
+    for (auto& k : D.kv) k.alloc(L0.N + L0.N2, by);
+    HIPCHECK(hipStreamSynchronize(s));
+    return;
+  }
   HIPCHECK(hipStreamSynchronize(s));
   for (auto& l : D.lv) tune_smoother(l, mixed, H.opt.smoother, s);
-  D.krylov = H.opt.krylov == 2;
+  if (mixed)
+    upload_tail<float>(D, s);
+  else
+    upload_tail<double>(D, s);
   if (D.krylov)
     for (auto& k : D.kv) k.alloc(L0.N + L0.N2, by);
   HIPCHECK(hipStreamSynchronize(s));
@@ -360,31 +466,6 @@ static void upload(ebmg_problem_s* P) {
 // ---------------------------------------------------------------------------
 // cycle pieces
 // ---------------------------------------------------------------------------
-template <typename T>
-struct Vec;
-template <>
-struct Vec<double> {
-  static double* x(DevLevel& l) { return l.x64.p; }
-  static double* b(DevLevel& l) { return l.b64.p; }
-  static double* r(DevLevel& l) { return l.r64.p; }
-  static const double* val(DevLevel& l) { return l.val64.p; }
-  static const double* diag(DevLevel& l) { return l.diag64.p; }
-  static const Tmpl<double>& t(DevLevel& l) { return l.t64; }
-  static double* tmp(DevLevel& l) { return l.w64.p; }
-  static double* xa(DevLevel& l) { return l.xa64.p; }
-};
-template <>
-struct Vec<float> {
-  static float* x(DevLevel& l) { return l.x32.p; }
-  static float* b(DevLevel& l) { return l.b32.p; }
-  static float* r(DevLevel& l) { return l.r32.p; }
-  static const float* val(DevLevel& l) { return l.val32.p; }
-  static const float* diag(DevLevel& l) { return l.diag32.p; }
-  static const Tmpl<float>& t(DevLevel& l) { return l.t32; }
-  static float* tmp(DevLevel& l) { return l.w32.p; }
-  static float* xa(DevLevel& l) { return l.xa32.p; }
-};
-
 static inline unsigned nblk_sub(int64_t rows) { return nblk(rows * kSub); }
 
 template <typename T>
@@ -479,6 +560,17 @@ static void prolong_from(DevLevel& f, DevLevel& c, const T* ec, T* xf, hipStream
 template <typename T>
 static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* x, const T* b) {
   DevLevel& L = D.lv[l];
+  if ((int)l == D.tail_l0) {
+    const BLev<T>* lv = (const BLev<T>*)D.tail_lv.p;
+    if (L.dim == 3)
+      hipLaunchKernelGGL((k_tail_vcycle<T, 3>), dim3(1), dim3(kBE), 0, s, lv, (int)l, (int)D.lv.size(),
+                         D.bottom.n > 0 ? D.bottom.p : nullptr, (int)D.bottom_n, o.nu1, o.nu2, x, b);
+    else
+      hipLaunchKernelGGL((k_tail_vcycle<T, 2>), dim3(1), dim3(kBE), 0, s, lv, (int)l, (int)D.lv.size(),
+                         D.bottom.n > 0 ? D.bottom.p : nullptr, (int)D.bottom_n, o.nu1, o.nu2, x, b);
+    HIPCHECK(hipGetLastError());
+    return;
+  }
   if (l + 1 == D.lv.size()) {
     if (D.bottom.n > 0) {
       hipLaunchKernelGGL((k_bottom<T>), dim3((unsigned)D.bottom_n), dim3(64), 0, s, D.bottom.p, b, x,
@@ -737,6 +829,61 @@ static ebmg_status solve(ebmg_problem_s* P, const double* rho, const double* sig
   return st;
 }
 
+
+// ---------------------------------------------------------------------------
+// batched boxes
+// ---------------------------------------------------------------------------
+template <typename T>
+static BBox<T> make_bbox(ebmg_problem_s* P, const BLev<T>* lv_dev) {
+  Problem& H = *P->host;
+  DevProblem& D = P->dev;
+  DevLevel& L0 = D.lv[0];
+  BBox<T> B;
+  std::memset(&B, 0, sizeof(B));
+  B.dim = L0.dim;
+  B.nlev = (int)D.lv.size();
+  B.N = (int)L0.N;
+  B.N2 = (int)L0.N2;
+  B.lv = lv_dev;
+  B.f64 = make_blev<double>(L0);
+  B.Ainv = D.bottom.n > 0 ? D.bottom.p : nullptr;
+  B.nbot = (int)D.bottom_n;
+  B.icell = D.icell.p;
+  B.isrc = D.isrc.p;
+  B.iface = D.iface.p;
+  B.iobj = D.iobj.p;
+  B.icobj = D.icobj.p;
+  B.icsig = D.icsig.p;
+  for (int d = 0; d < 3; ++d) B.dat.n[d] = L0.n[d];
+  for (int f = 0; f < 6; ++f) {
+    B.fv[f] = H.bc.value[f];
+    for (int p = 0; p < 2; ++p) B.dat.cb[f][p] = H.fine.dat[f][p] * H.bc.value[f];
+  }
+  B.objv = D.objv.p;
+  for (int k = 0; k < 8; ++k) B.kv[k] = D.kv[k].p;
+  B.krylov = H.opt.krylov;
+  return B;
+}
+
+template <typename T>
+static void upload_batch_views(ebmg_batch_s* Bt, hipStream_t s) {
+  std::vector<BBox<T>> hb;
+  Bt->lvbuf.resize(Bt->boxes.size());
+  for (size_t i = 0; i < Bt->boxes.size(); ++i) {
+    ebmg_problem_s* P = Bt->boxes[i].get();
+    std::vector<BLev<T>> v;
+    for (auto& l : P->dev.lv) v.push_back(make_blev<T>(l));
+    int64_t by = 0;
+    Bt->lvbuf[i].upload((const uint8_t*)v.data(), (int64_t)(v.size() * sizeof(BLev<T>)), s, by);
+    Bt->bytes += by;
+    HIPCHECK(hipStreamSynchronize(s));
+    hb.push_back(make_bbox<T>(P, (const BLev<T>*)Bt->lvbuf[i].p));
+  }
+  int64_t by = 0;
+  Bt->bbox.upload((const uint8_t*)hb.data(), (int64_t)(hb.size() * sizeof(BBox<T>)), s, by);
+  Bt->bytes += by;
+  HIPCHECK(hipStreamSynchronize(s));
+}
 }  // namespace ebmg
 
 // ---------------------------------------------------------------------------
@@ -824,6 +971,60 @@ ebmg_status ebmg_destroy(ebmg_ctx ctx) {
 
 const char* ebmg_last_error(ebmg_ctx ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 
+static ebmg_status parse_options(const ebmg_options* opt, int nobj, ebmg::Options& out) {
+  ebmg_options o;
+  if (opt)
+    o = *opt;
+  else
+    ebmg_default_options(&o);
+  out.alpha = o.alpha;
+  out.beta = o.beta;
+  out.a_gas = o.a_gas;
+  out.a_diel = o.a_diel;
+  out.b_gas = o.b_gas;
+  out.dirichlet_closure = o.dirichlet_closure;
+  out.robin_closure = o.robin_closure;
+  out.eb_order = o.eb_order == 1 ? 1 : 2;
+  out.precision = o.precision;
+  out.nu1 = o.nu1 > 0 ? o.nu1 : 2;
+  out.nu2 = o.nu2 > 0 ? o.nu2 : 2;
+  out.bottom_max = o.bottom_max_dof > 0 ? o.bottom_max_dof : 600;
+  if (o.precision != EBMG_FP64 && o.precision != EBMG_MIXED) return EBMG_ERR_ARG;
+  if (!(o.beta != 0.0) || !std::isfinite(o.beta)) return EBMG_ERR_ARG;
+  if (o.krylov < 0 || o.krylov > 2 || o.smoother < 0 || o.smoother > 2) return EBMG_ERR_ARG;
+  out.krylov = o.krylov == 0 ? (nobj > 0 ? 2 : 1) : o.krylov;
+  out.smoother = o.smoother;
+  return EBMG_OK;
+}
+
+// host part of a problem setup (no device work)
+static void build_host_problem(ebmg::Problem& H, const ebmg_box* box, int nobj, const ebmg_object* objs,
+                               const ebmg_domain_bc* bc) {
+  using namespace ebmg;
+  H.bc = *bc;
+  for (int f = 0; f < 2 * box->dim && f < 6; ++f) {
+    if (bc->kind[f] < 0 || bc->kind[f] > 2) throw ArgError("bad boundary kind");
+    if (bc->kind[f] == EBMG_BC_ROBIN && !(bc->robin_a2[f] != 0.0)) throw ArgError("Robin a2 must be nonzero");
+  }
+  build_geometry(H.geo, *box, nobj, objs);
+  H.bph[0] = H.opt.b_gas;
+  H.aph[0] = H.opt.a_gas;
+  if (H.geo.nphase == 2) {
+    H.bph[1] = H.geo.obj_value[H.geo.diel_obj];
+    H.aph[1] = H.opt.a_diel;
+  } else {
+    H.bph[1] = H.opt.b_gas;
+    H.aph[1] = H.opt.a_diel;
+  }
+  if (!(H.bph[0] > 0) || !(H.bph[1] > 0)) throw ArgError("b must be positive");
+  bool anchored = H.opt.alpha != 0.0;
+  for (int f = 0; f < 2 * box->dim; ++f) anchored |= bc->kind[f] != EBMG_BC_NEUMANN;
+  for (int k = 0; k < nobj; ++k) anchored |= objs[k].kind == EBMG_OBJ_ELECTRODE;
+  if (!anchored) throw ArgError("pure Neumann problem is singular");
+  build_fine_level(H);
+  build_hierarchy(H);
+}
+
 ebmg_status ebmg_setup(ebmg_ctx ctx, const ebmg_box* box, int32_t nobj, const ebmg_object* objs,
                        const ebmg_domain_bc* bc, const ebmg_options* opt, ebmg_problem* out) {
   if (!ctx || !box || !bc || !out || (nobj > 0 && !objs) || nobj < 0 || nobj > 64) {
@@ -832,56 +1033,12 @@ ebmg_status ebmg_setup(ebmg_ctx ctx, const ebmg_box* box, int32_t nobj, const eb
   }
   *out = nullptr;
   return guard(ctx, [&]() -> ebmg_status {
-    ebmg_options o;
-    if (opt)
-      o = *opt;
-    else
-      ebmg_default_options(&o);
     auto P = std::make_unique<ebmg_problem_s>();
     P->ctx = ctx;
     P->host = std::make_unique<Problem>();
     Problem& H = *P->host;
-    H.opt.alpha = o.alpha;
-    H.opt.beta = o.beta;
-    H.opt.a_gas = o.a_gas;
-    H.opt.a_diel = o.a_diel;
-    H.opt.b_gas = o.b_gas;
-    H.opt.dirichlet_closure = o.dirichlet_closure;
-    H.opt.robin_closure = o.robin_closure;
-    H.opt.eb_order = o.eb_order == 1 ? 1 : 2;
-    H.opt.precision = o.precision;
-    H.opt.nu1 = o.nu1 > 0 ? o.nu1 : 2;
-    H.opt.nu2 = o.nu2 > 0 ? o.nu2 : 2;
-    H.opt.bottom_max = o.bottom_max_dof > 0 ? o.bottom_max_dof : 600;
-    if (o.krylov < 0 || o.krylov > 2) throw ArgError("bad krylov option");
-    if (o.smoother < 0 || o.smoother > 2) throw ArgError("bad smoother option");
-    H.opt.smoother = o.smoother;
-    H.opt.krylov = o.krylov == 0 ? (nobj > 0 ? 2 : 1) : o.krylov;
-    if (o.precision != EBMG_FP64 && o.precision != EBMG_MIXED) throw ArgError("bad precision");
-    if (!(o.beta != 0.0) || !std::isfinite(o.beta)) throw ArgError("beta must be nonzero");
-    H.bc = *bc;
-    for (int f = 0; f < 2 * box->dim && f < 6; ++f) {
-      if (bc->kind[f] < 0 || bc->kind[f] > 2) throw ArgError("bad boundary kind");
-      if (bc->kind[f] == EBMG_BC_ROBIN && !(bc->robin_a2[f] != 0.0)) throw ArgError("Robin a2 must be nonzero");
-    }
-    build_geometry(H.geo, *box, nobj, objs);
-    H.bph[0] = o.b_gas;
-    H.aph[0] = o.a_gas;
-    if (H.geo.nphase == 2) {
-      H.bph[1] = H.geo.obj_value[H.geo.diel_obj];
-      H.aph[1] = o.a_diel;
-    } else {
-      H.bph[1] = o.b_gas;
-      H.aph[1] = o.a_diel;
-    }
-    if (!(H.bph[0] > 0) || !(H.bph[1] > 0)) throw ArgError("b must be positive");
-    // a problem with no Dirichlet/Robin data and no mass term is singular
-    bool anchored = o.alpha != 0.0;
-    for (int f = 0; f < 2 * box->dim; ++f) anchored |= bc->kind[f] != EBMG_BC_NEUMANN;
-    for (int k = 0; k < nobj; ++k) anchored |= objs[k].kind == EBMG_OBJ_ELECTRODE;
-    if (!anchored) throw ArgError("pure Neumann problem is singular");
-    build_fine_level(H);
-    build_hierarchy(H);
+    if (parse_options(opt, nobj, H.opt) != EBMG_OK) throw ArgError("bad options");
+    build_host_problem(H, box, nobj, objs, bc);
     if (ctx->device >= 0) {
       HIPCHECK(hipSetDevice(ctx->device));
       try {
@@ -1145,6 +1302,209 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
     if (alg_bytes) *alg_bytes = bytes;
     return EBMG_OK;
   });
+}
+
+
+ebmg_status ebmg_setup_batch(ebmg_ctx ctx, int32_t nbox, const ebmg_box* boxes, const int32_t* nobj,
+                             const ebmg_object* const* objs, const ebmg_domain_bc* bcs, const ebmg_options* opts,
+                             ebmg_batch* out) {
+  if (!ctx || nbox <= 0 || !boxes || !nobj || !objs || !bcs || !out) {
+    if (ctx) ctx->err = "invalid argument to ebmg_setup_batch";
+    return EBMG_ERR_ARG;
+  }
+  *out = nullptr;
+  if (ctx->device < 0) {
+    ctx->err = "batched solves need a device context";
+    return EBMG_ERR_DEVICE;
+  }
+  return guard(ctx, [&]() -> ebmg_status {
+    auto Bt = std::make_unique<ebmg_batch_s>();
+    Bt->ctx = ctx;
+    Bt->dim = boxes[0].dim;
+    Bt->boxes.resize(nbox);
+    int prec = -1;
+    for (int i = 0; i < nbox; ++i) {
+      if (boxes[i].dim != Bt->dim) throw ArgError("all boxes of a batch must have the same dimension");
+      if (nobj[i] < 0 || nobj[i] > 64 || (nobj[i] > 0 && !objs[i])) throw ArgError("bad object list");
+      auto P = std::make_unique<ebmg_problem_s>();
+      P->ctx = ctx;
+      P->host = std::make_unique<Problem>();
+      if (parse_options(opts ? &opts[i] : nullptr, nobj[i], P->host->opt) != EBMG_OK)
+        throw ArgError("bad options for a batch box");
+      if (prec < 0) prec = P->host->opt.precision;
+      if (P->host->opt.precision != prec) throw ArgError("all boxes of a batch must use one precision");
+      Bt->boxes[i] = std::move(P);
+    }
+    Bt->mixed = prec == EBMG_MIXED;
+    Bt->nu1 = Bt->boxes[0]->host->opt.nu1;
+    Bt->nu2 = Bt->boxes[0]->host->opt.nu2;
+    // host setup of the boxes in parallel (independent problems)
+    unsigned nw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::string> errs(nbox);
+    std::vector<int> kinds(nbox, 0);
+    std::atomic<int> next(0);
+    auto work = [&]() {
+      for (int i = next++; i < nbox; i = next++) {
+        try {
+          build_host_problem(*Bt->boxes[i]->host, &boxes[i], nobj[i], objs[i], &bcs[i]);
+        } catch (const ArgError& e) {
+          errs[i] = e.what();
+          kinds[i] = 1;
+        } catch (const GeomError& e) {
+          errs[i] = e.what();
+          kinds[i] = 2;
+        } catch (const std::exception& e) {
+          errs[i] = e.what();
+          kinds[i] = 1;
+        }
+      }
+    };
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < nw; ++w) th.emplace_back(work);
+    for (auto& t : th) t.join();
+    for (int i = 0; i < nbox; ++i) {
+      if (kinds[i] == 1) throw ArgError("box " + std::to_string(i) + ": " + errs[i]);
+      if (kinds[i] == 2) throw GeomError("box " + std::to_string(i) + ": " + errs[i]);
+    }
+    HIPCHECK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    try {
+      for (int i = 0; i < nbox; ++i) {
+        ebmg_problem_s* P = Bt->boxes[i].get();
+        upload(P, true);
+        P->on_device = true;
+        // object values for the right-hand side
+        const auto& ov = P->host->geo.obj_value;
+        if (!ov.empty()) {
+          HIPCHECK(hipMemcpyAsync(P->dev.objv.p, ov.data(), sizeof(double) * ov.size(), hipMemcpyHostToDevice, s));
+          HIPCHECK(hipStreamSynchronize(s));
+        }
+        Bt->cells += P->host->geo.N;
+        Bt->cells2 += P->host->geo.N2;
+        Bt->bytes += P->dev.bytes;
+      }
+      if (Bt->mixed)
+        upload_batch_views<float>(Bt.get(), s);
+      else
+        upload_batch_views<double>(Bt.get(), s);
+      std::vector<int32_t> order(nbox);
+      for (int i = 0; i < nbox; ++i) order[i] = i;
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return Bt->boxes[a]->host->geo.N + Bt->boxes[a]->host->geo.N2 >
+               Bt->boxes[b]->host->geo.N + Bt->boxes[b]->host->geo.N2;
+      });
+      int64_t by = 0;
+      Bt->order.upload(order.data(), nbox, s, by);
+      Bt->bio.alloc((int64_t)(nbox * sizeof(BIO)), by);
+      Bt->bres.alloc((int64_t)(nbox * sizeof(BRes)), by);
+      Bt->bytes += by;
+      HIPCHECK(hipStreamSynchronize(s));
+    } catch (...) {
+      for (auto& P : Bt->boxes)
+        if (P) P->dev.release();
+      for (auto& b : Bt->lvbuf) b.release();
+      Bt->bbox.release();
+      Bt->order.release();
+      Bt->bio.release();
+      Bt->bres.release();
+      throw;
+    }
+    *out = Bt.release();
+    return EBMG_OK;
+  });
+}
+
+ebmg_status ebmg_query_batch(ebmg_batch bt, int64_t* cells, int64_t* cells2, int64_t* device_bytes) {
+  if (!bt) return EBMG_ERR_ARG;
+  if (cells) *cells = bt->cells;
+  if (cells2) *cells2 = bt->cells2;
+  if (device_bytes) *device_bytes = bt->bytes;
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_solve_batch(ebmg_batch bt, const double* const* rho, const double* const* sigma, double rtol,
+                             int32_t max_cycles, double* const* phi, double* const* phi2, ebmg_solve_info* infos) {
+  if (!bt || !rho || !phi || !(rtol > 0) || max_cycles < 0) {
+    if (bt) bt->ctx->err = "invalid argument to ebmg_solve_batch";
+    return EBMG_ERR_ARG;
+  }
+  const int nbox = (int)bt->boxes.size();
+  for (int i = 0; i < nbox; ++i)
+    if (!rho[i] || !phi[i] || (bt->boxes[i]->host->geo.N2 > 0 && phi2 && !phi2[i])) {
+      bt->ctx->err = "missing array in ebmg_solve_batch";
+      return EBMG_ERR_ARG;
+    }
+  return guard(bt->ctx, [&]() -> ebmg_status {
+    auto t0 = std::chrono::steady_clock::now();
+    HIPCHECK(hipSetDevice(bt->ctx->device));
+    hipStream_t s = bt->ctx->stream;
+    std::vector<BIO> io(nbox);
+    for (int i = 0; i < nbox; ++i) {
+      io[i].rho = rho[i];
+      io[i].sigma = sigma ? sigma[i] : nullptr;
+      io[i].phi = phi[i];
+      io[i].phi2 = phi2 ? phi2[i] : nullptr;
+    }
+    HIPCHECK(hipMemcpyAsync(bt->bio.p, io.data(), sizeof(BIO) * nbox, hipMemcpyHostToDevice, s));
+    int ncu = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, bt->ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
+      ncu = prop.multiProcessorCount;
+    const int grid = std::min(nbox, 2 * ncu);
+    if (bt->mixed) {
+      if (bt->dim == 3)
+        hipLaunchKernelGGL((k_batch_solve<float, 3>), dim3(grid), dim3(kBE), 0, s, (const BBox<float>*)bt->bbox.p,
+                           (const BIO*)bt->bio.p, (BRes*)bt->bres.p, bt->order.p, nbox, rtol, max_cycles, bt->nu1,
+                           bt->nu2);
+      else
+        hipLaunchKernelGGL((k_batch_solve<float, 2>), dim3(grid), dim3(kBE), 0, s, (const BBox<float>*)bt->bbox.p,
+                           (const BIO*)bt->bio.p, (BRes*)bt->bres.p, bt->order.p, nbox, rtol, max_cycles, bt->nu1,
+                           bt->nu2);
+    } else {
+      if (bt->dim == 3)
+        hipLaunchKernelGGL((k_batch_solve<double, 3>), dim3(grid), dim3(kBE), 0, s, (const BBox<double>*)bt->bbox.p,
+                           (const BIO*)bt->bio.p, (BRes*)bt->bres.p, bt->order.p, nbox, rtol, max_cycles, bt->nu1,
+                           bt->nu2);
+      else
+        hipLaunchKernelGGL((k_batch_solve<double, 2>), dim3(grid), dim3(kBE), 0, s, (const BBox<double>*)bt->bbox.p,
+                           (const BIO*)bt->bio.p, (BRes*)bt->bres.p, bt->order.p, nbox, rtol, max_cycles, bt->nu1,
+                           bt->nu2);
+    }
+    HIPCHECK(hipGetLastError());
+    std::vector<BRes> res(nbox);
+    HIPCHECK(hipMemcpyAsync(res.data(), bt->bres.p, sizeof(BRes) * nbox, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    ebmg_status worst = EBMG_OK;
+    for (int i = 0; i < nbox; ++i) {
+      if (infos) {
+        std::memset(&infos[i], 0, sizeof(ebmg_solve_info));
+        infos[i].cycles = res[i].cycles;
+        infos[i].outer_iters = res[i].iters;
+        infos[i].levels = (int)bt->boxes[i]->dev.lv.size();
+        infos[i].r0_norm = res[i].r0;
+        infos[i].rel_residual = res[i].rel;
+        infos[i].seconds = secs;
+      }
+      if (res[i].status != EBMG_OK && worst == EBMG_OK) worst = (ebmg_status)res[i].status;
+    }
+    return worst;
+  });
+}
+
+ebmg_status ebmg_release_batch(ebmg_batch bt) {
+  if (!bt) return EBMG_ERR_ARG;
+  (void)hipSetDevice(bt->ctx->device);
+  (void)hipStreamSynchronize(bt->ctx->stream);
+  for (auto& P : bt->boxes)
+    if (P) P->dev.release();
+  for (auto& b : bt->lvbuf) b.release();
+  bt->bbox.release();
+  bt->order.release();
+  bt->bio.release();
+  bt->bres.release();
+  delete bt;
+  return EBMG_OK;
 }
 
 ebmg_status ebmg_release(ebmg_problem pb) {

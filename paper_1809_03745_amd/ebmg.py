@@ -108,11 +108,18 @@ _sig("ebmg_apply", C.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_efield", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_time_kernel", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp])
 _sig("ebmg_release", C.c_int, [_vp])
+_sig("ebmg_setup_batch", C.c_int, [_vp, C.c_int32, C.POINTER(Box), C.POINTER(C.c_int32), C.POINTER(_vp),
+                                   C.POINTER(DomainBC), C.POINTER(Options), C.POINTER(_vp)])
+_sig("ebmg_query_batch", C.c_int, [_vp, _i64p, _i64p, _i64p])
+_sig("ebmg_solve_batch", C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.c_double, C.c_int32, C.POINTER(_vp),
+                                   C.POINTER(_vp), C.POINTER(SolveInfo)])
+_sig("ebmg_release_batch", C.c_int, [_vp])
 
 EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_destroy", "ebmg_last_error",
             "ebmg_setup", "ebmg_query", "ebmg_query_level", "ebmg_export_level", "ebmg_query_tuning",
             "ebmg_export_geometry", "ebmg_export_operator", "ebmg_export_rhs",
-            "ebmg_solve", "ebmg_apply", "ebmg_efield", "ebmg_time_kernel", "ebmg_release"]
+            "ebmg_solve", "ebmg_apply", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
+            "ebmg_setup_batch", "ebmg_query_batch", "ebmg_solve_batch", "ebmg_release_batch"]
 
 
 def abi_version():
@@ -184,30 +191,36 @@ def make_options(prob, precision=FP64, dirichlet_closure=0, robin_closure=0, eb_
     return o
 
 
+def _c_problem(prob):
+    """(Box, Object array, DomainBC, kept SDF arrays) of a ``workloads.Problem``."""
+    box = Box()
+    box.dim = prob.dim
+    for d in range(3):
+        box.n[d] = prob.n[d] if d < prob.dim else 1
+        box.lo[d] = prob.lo[d] if d < prob.dim else 0.0
+    box.h = prob.h
+    sdf = [np.ascontiguousarray(o.sdf, dtype=np.float64) for o in prob.objects]
+    objs = (Object * max(1, len(prob.objects)))()
+    for k, o in enumerate(prob.objects):
+        objs[k].kind = o.kind
+        objs[k].value = o.value
+        objs[k].sdf = sdf[k].ctypes.data_as(_dp)
+    bc = DomainBC()
+    for f in range(6):
+        bc.kind[f] = prob.bc_kind[f]
+        bc.value[f] = prob.bc_value[f]
+        bc.robin_a1[f] = prob.robin_a1[f]
+        bc.robin_a2[f] = prob.robin_a2[f]
+    return box, objs, bc, sdf
+
+
 class Problem:
     """A problem set up in the library from a ``workloads.Problem``."""
 
     def __init__(self, ctx, prob, **opts):
         self.ctx = ctx
         self.prob = prob
-        box = Box()
-        box.dim = prob.dim
-        for d in range(3):
-            box.n[d] = prob.n[d] if d < prob.dim else 1
-            box.lo[d] = prob.lo[d] if d < prob.dim else 0.0
-        box.h = prob.h
-        self._sdf = [np.ascontiguousarray(o.sdf, dtype=np.float64) for o in prob.objects]
-        objs = (Object * max(1, len(prob.objects)))()
-        for k, o in enumerate(prob.objects):
-            objs[k].kind = o.kind
-            objs[k].value = o.value
-            objs[k].sdf = self._sdf[k].ctypes.data_as(_dp)
-        bc = DomainBC()
-        for f in range(6):
-            bc.kind[f] = prob.bc_kind[f]
-            bc.value[f] = prob.bc_value[f]
-            bc.robin_a1[f] = prob.robin_a1[f]
-            bc.robin_a2[f] = prob.robin_a2[f]
+        box, objs, bc, self._sdf = _c_problem(prob)
         self.options = make_options(prob, **opts)
         h = _vp()
         st = _lib.ebmg_setup(ctx.h, C.byref(box), len(prob.objects), objs, C.byref(bc), C.byref(self.options),
@@ -305,6 +318,61 @@ class Problem:
     def release(self):
         if getattr(self, "h", None):
             _lib.ebmg_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent boxes (one dimension, one precision) solved together by
+    one persistent launch; each box keeps the boundary values given here."""
+
+    def __init__(self, ctx, probs, **opts):
+        self.ctx = ctx
+        self.probs = list(probs)
+        nb = len(self.probs)
+        boxes = (Box * nb)()
+        bcs = (DomainBC * nb)()
+        optv = (Options * nb)()
+        nobj = (C.c_int32 * nb)()
+        objp = (_vp * nb)()
+        keep = []
+        for i, pr in enumerate(self.probs):
+            box, objs, bc, sdf = _c_problem(pr)
+            boxes[i] = box
+            bcs[i] = bc
+            optv[i] = make_options(pr, **opts)
+            nobj[i] = len(pr.objects)
+            objp[i] = C.cast(objs, _vp)
+            keep.append((objs, sdf))
+        h = _vp()
+        st = _lib.ebmg_setup_batch(ctx.h, nb, boxes, nobj, objp, bcs, optv, C.byref(h))
+        keep = None
+        ctx.check(st, "ebmg_setup_batch")
+        self.h = h
+        n, n2, by = C.c_int64(), C.c_int64(), C.c_int64()
+        ctx.check(_lib.ebmg_query_batch(h, C.byref(n), C.byref(n2), C.byref(by)), "ebmg_query_batch")
+        self.cells, self.cells2, self.device_bytes = n.value, n2.value, by.value
+
+    def solve(self, rho, phi, sigma=None, phi2=None, rtol=1e-10, max_cycles=100, check=True):
+        """rho, phi (and optionally sigma, phi2) are lists of device tensors,
+        one per box (entries of sigma / phi2 may be None)."""
+        nb = len(self.probs)
+        arr = lambda xs: (_vp * nb)(*[_ptr(x) for x in xs]) if xs is not None else None
+        infos = (SolveInfo * nb)()
+        st = _lib.ebmg_solve_batch(self.h, arr(rho), arr(sigma), float(rtol), int(max_cycles), arr(phi),
+                                   arr(phi2), infos)
+        if check:
+            self.ctx.check(st, "ebmg_solve_batch")
+        return st, [infos[i].as_dict() for i in range(nb)]
+
+    def release(self):
+        if getattr(self, "h", None):
+            _lib.ebmg_release_batch(self.h)
             self.h = None
 
     def __del__(self):

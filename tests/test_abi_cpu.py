@@ -159,3 +159,9 @@ def test_setup_handles_every_batched_box_class(host_ctx):
         P = ebmg.Problem(host_ctx, pr)
         assert P.N == int(np.prod(pr.n))
         P.release()
+
+
+def test_batch_needs_a_device(host_ctx):
+    with pytest.raises(ebmg.EbmgError) as e:
+        ebmg.Batch(host_ctx, [W.manufactured_sine(8), W.manufactured_sine(16)])
+    assert e.value.status == ebmg.ERR_DEVICE

@@ -1,0 +1,171 @@
+"""GPU parity of the batched persistent solver (many independent boxes, one
+launch) against the FP64 oracle and against the single-box path.
+
+Bars as for one box: FP64 within 1e-10 relative L2 of the oracle's direct
+solution, mixed within 1e-8, residual <= 1e-10 by the oracle's operator. A
+box's result must not depend on the other boxes in the batch (bitwise).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.operator import assemble
+from oracle.solvers import rel_residual, solve_splu
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ebmg = pytest.importorskip("paper_1809_03745_amd.ebmg", reason="libebmg.so not built")
+
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return ebmg.Context(0)
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a).ravel(), dtype=torch.float64, device=DEV)
+
+
+def _batch_solve(B, probs, rtol, max_cycles=400):
+    rho = [_t(p.rho) for p in probs]
+    sig = [(_t(p.sigma) if p.sigma is not None else None) for p in probs]
+    phi = [torch.zeros(int(np.prod(p.shape)), dtype=torch.float64, device=DEV) for p in probs]
+    phi2 = [torch.zeros(4096 * 64, dtype=torch.float64, device=DEV) for _ in probs]
+    torch.cuda.synchronize()
+    st, infos = B.solve(rho, phi, sigma=sig, phi2=phi2, rtol=rtol, max_cycles=max_cycles, check=False)
+    return st, infos, [p.cpu().numpy() for p in phi], [q.cpu().numpy() for q in phi2]
+
+
+def _full(x, x2, N2):
+    return np.concatenate([x, x2[:N2]])
+
+
+def _n2(ctx, pr):
+    P = ebmg.Problem(ctx, pr)
+    n2 = P.N2
+    P.release()
+    return n2
+
+
+# 3D boxes of the batched workload (random sizes 16..64 per edge, sphere
+# electrode, dielectric half-space): the four smallest of a seeded draw go to
+# the oracle, the rest to the single-box library path.
+BOXES = W.batched_boxes(16, seed=11)
+ORACLE_IDX = [12, 2, 11, 0]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_3d_vs_oracle(ctx, prec):
+    _say("batch 3d vs oracle, precision", prec)
+    B = ebmg.Batch(ctx, BOXES, precision=prec)
+    assert B.cells == sum(int(np.prod(p.shape)) for p in BOXES)
+    st, infos, xs, x2s = _batch_solve(B, BOXES, 1e-10)
+    assert st == ebmg.OK, infos
+    for i in range(len(BOXES)):
+        assert infos[i]["rel_residual"] <= 1e-10, (i, infos[i])
+    st, infos13, xs13, x2s13 = _batch_solve(B, BOXES, 1e-13)
+    assert st == ebmg.OK
+    for i in ORACLE_IDX:
+        pr = BOXES[i]
+        S = assemble(pr)
+        N2 = S.N2
+        x = _full(xs[i], x2s[i], N2)
+        assert rel_residual(S.A, S.b, x) <= 1.01e-10, i
+        ref = solve_splu(S.A, S.b)
+        x13 = _full(xs13[i], x2s13[i], N2)
+        err = np.linalg.norm(x13 - ref) / np.linalg.norm(ref)
+        _say("   box", i, pr.shape, "error vs oracle", err, "cycles", infos13[i]["cycles"])
+        assert err <= (1e-10 if prec == 0 else 1e-8)
+    B.release()
+
+
+def test_batch_3d_vs_single_box(ctx):
+    _say("batch 3d vs single-box path")
+    B = ebmg.Batch(ctx, BOXES)
+    st, infos, xs, x2s = _batch_solve(B, BOXES, 1e-13)
+    assert st == ebmg.OK
+    for i, pr in enumerate(BOXES):
+        if i in ORACLE_IDX:
+            continue
+        P = ebmg.Problem(ctx, pr)
+        phi = torch.zeros(P.N, dtype=torch.float64, device=DEV)
+        phi2 = torch.zeros(max(1, P.N2), dtype=torch.float64, device=DEV)
+        st1, info = P.solve(_t(pr.rho), phi, phi2=phi2 if P.N2 else None, rtol=1e-13, max_cycles=400, check=False)
+        assert st1 == ebmg.OK
+        a = _full(xs[i], x2s[i], P.N2)
+        b = _full(phi.cpu().numpy(), phi2.cpu().numpy(), P.N2)
+        assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b), i
+        P.release()
+    B.release()
+
+
+def test_batch_2d_mixed_kinds(ctx):
+    """A 2D batch mixing Poisson with surface charge, blade-plane with a
+    dielectric and an Eddington Helmholtz box with Robin faces."""
+    _say("batch 2d mixed kinds")
+    probs = [W.two_disks(64, seed=3), W.blade_plane(96, seed=4), W.eddington(2, 64, 10.0, seed=5),
+             W.coaxial(48, sigma=0.5), W.manufactured_sine(32)]
+    for prec, bar in ((0, 1e-10), (1, 1e-8)):
+        B = ebmg.Batch(ctx, probs, precision=prec)
+        st, infos, xs, x2s = _batch_solve(B, probs, 1e-13, max_cycles=600)
+        assert st == ebmg.OK, infos
+        for i, pr in enumerate(probs):
+            S = assemble(pr)
+            ref = solve_splu(S.A, S.b)
+            x = _full(xs[i], x2s[i], S.N2)
+            err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+            _say("   ", pr.name, "precision", prec, "error", err)
+            assert err <= bar
+        B.release()
+
+
+def test_batch_result_independent_of_mix(ctx):
+    _say("batch mix invariance")
+    probs = BOXES[:8]
+    B = ebmg.Batch(ctx, probs, precision=ebmg.MIXED)
+    _, _, xs, _ = _batch_solve(B, probs, 1e-10)
+    B.release()
+    for i in (1, 5):
+        Bi = ebmg.Batch(ctx, [probs[i]], precision=ebmg.MIXED)
+        _, _, xi, _ = _batch_solve(Bi, [probs[i]], 1e-10)
+        assert np.array_equal(xi[0], xs[i])
+        Bi.release()
+    # and a reordered batch
+    perm = [7, 3, 0, 5, 1, 6, 2, 4]
+    Bp = ebmg.Batch(ctx, [probs[k] for k in perm], precision=ebmg.MIXED)
+    _, _, xp, _ = _batch_solve(Bp, [probs[k] for k in perm], 1e-10)
+    for j, k in enumerate(perm):
+        assert np.array_equal(xp[j], xs[k])
+    Bp.release()
+
+
+def test_batch_errors(ctx):
+    _say("batch error paths")
+    probs = BOXES[:3]
+    B = ebmg.Batch(ctx, probs)
+    st, infos, _, _ = _batch_solve(B, probs, 1e-10, max_cycles=2)
+    assert st == ebmg.ERR_NOCONV
+    assert all(i["cycles"] <= 2 for i in infos)
+    bad = [p for p in probs]
+    rho = [_t(p.rho) for p in bad]
+    rho[1].fill_(float("nan"))
+    phi = [torch.zeros(int(np.prod(p.shape)), dtype=torch.float64, device=DEV) for p in bad]
+    phi2 = [torch.zeros(4096 * 64, dtype=torch.float64, device=DEV) for _ in bad]
+    st, infos = B.solve(rho, phi, phi2=phi2, rtol=1e-10, max_cycles=100, check=False)
+    assert st == ebmg.ERR_NUMERIC
+    assert infos[0]["rel_residual"] <= 1e-10 and infos[2]["rel_residual"] <= 1e-10
+    B.release()
+    with pytest.raises(ebmg.EbmgError):
+        ebmg.Batch(ctx, [W.two_disks(32, seed=0), W.pin_plane(16, seed=0)])

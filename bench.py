@@ -8,11 +8,13 @@ a relative residual of 1e-10: right-hand-side assembly, V-cycle-
 preconditioned BiCGStab with FP32 cycles and FP64 residuals/updates, and the
 flux-based field E. Inputs are resident in HBM before the timed region.
 
-Prints one JSON line (see the README of the measurement contract in the
-design notes): value = V-cycle cell-updates/s = (fine cells x V-cycles) per
-second of solve; plus solves/s, the roofline of the dominant kernel (the
-fine-level smoother, timed live with HIP events) and the CPU oracle timed on
-a bounded sample of the same workload class.
+Prints one JSON line: value = V-cycle cell-updates/s = (fine cells x
+V-cycles) per second of solve; plus solves/s, p50/p99 latency, the roofline
+of the dominant kernel (the fine-level smoother, launched by the library's
+measurement hook on its own stream between HIP events), the same workload
+solved by the plain FP64 solver, the batched workload (512 uneven boxes in
+one persistent launch) and the CPU oracle timed on a bounded sample of the
+same workload class.
 """
 import argparse
 import json
@@ -65,38 +67,119 @@ def cpu_baseline(n=64):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
-              "(multi-GPU sharding is a design note, not implemented); use --gpus 1", file=sys.stderr)
-        return 2
-    rank = int(os.environ.get("RANK", "0"))
+def _kernel_label(P, prec):
+    fused = P.tuning(0)[0]
+    t = "float" if prec == 1 else "double"
+    if fused:
+        return f"k_rb_tile3<{t}> (fused red+black Gauss-Seidel sweep, finest level)", "fused sweep"
+    return f"k_rb<{t},3> (red/black Gauss-Seidel half-sweep, finest level)", "half-sweep"
 
-    import numpy as np
+
+def _source_sha():
+    """Hash of the kernel sources: counter figures are void once it changes."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "block_engine.hpp"):
+        with open(os.path.join(ROOT, "paper_1809_03745_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_smoother_residual_pin_plane256.json")
+
+
+def _traffic(kernel_name):
+    """HBM bytes per launch of the timed kernel from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE per dispatch, scaled by the same
+    counters on a plain copy of known size), or None when the summary is
+    missing or the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        d = json.load(fh)
+    e = d.get("kernels", {}).get(kernel_name)
+    if e is None or d.get("source_sha") != _source_sha():
+        return None
+    return e["hbm_bytes_per_launch"]
+
+
+def pmc_probe(args):
+    """Workload of the counter passes: a plain device copy of known size,
+    then the finest-level smoother kernels (half-sweep and fused sweep) and
+    the FP64 residual launched through the measurement hook."""
     import torch
     import workloads as W
     from paper_1809_03745_amd import ebmg
-
     dev = torch.device("cuda:0")
+    nbytes = 1 << 29
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    print(f"copy kernel: {nbytes} bytes read and written per launch, 3 launches", flush=True)
+    del a, c
     pr = W.pin_plane(args.n, seed=0)
     ctx = ebmg.Context(0)
-    prec = ebmg.MIXED if args.precision == "mixed" else ebmg.FP64
-    t_setup = time.perf_counter()
-    P = ebmg.Problem(ctx, pr, precision=prec)
-    t_setup = time.perf_counter() - t_setup
-    rho = torch.tensor(pr.rho.ravel(), dtype=torch.float64, device=dev)
-    phi = torch.zeros(P.N, dtype=torch.float64, device=dev)
-    phi2 = torch.zeros(max(P.N2, 1), dtype=torch.float64, device=dev)
-    E = torch.zeros(3 * P.N, dtype=torch.float64, device=dev)
-    torch.cuda.synchronize()
+    for prec in (ebmg.MIXED, ebmg.FP64):
+        P = ebmg.Problem(ctx, pr, precision=prec, **args.tune)
+        for which, what in ((2, "half-sweep"), (3, "fused sweep")):
+            ms, by = P.time_kernel(which, 0, reps=10)
+            print(f"precision {prec} {what}: 10 launches, {ms:.4f} ms, {by:.0f} alg bytes", flush=True)
+        if prec == ebmg.FP64:
+            ms, by = P.time_kernel(1, 0, reps=10)
+            print(f"residual FP64: 10 launches, {ms:.4f} ms, {by:.0f} alg bytes", flush=True)
+        P.release()
+    print("source_sha", _source_sha(), flush=True)
+    return 0
+
+
+def _kname(raw):
+    n = raw.split("(")[0].replace("void ", "").replace("ebmg::", "")
+    return n.replace(" ", "")
+
+
+def pmc_summary(fetch_csv, write_csv, command):
+    """Reduce the two counter passes of ``--pmc-probe`` to HBM bytes per
+    launch of each finest-level kernel and write the committed summary."""
+    import csv
+    import collections
+
+    def load(path):
+        d = collections.defaultdict(list)
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                d[(_kname(r["Kernel_Name"]), int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+        return d
+
+    f, w = load(fetch_csv), load(write_csv)
+    copy_key = max((k for k in f if "copyBuffer" in k[0]), key=lambda k: k[1])
+    copy_kib = (1 << 29) / 1024.0
+    sf = copy_kib / (sum(f[copy_key]) / len(f[copy_key]))
+    sw = copy_kib / (sum(w[copy_key]) / len(w[copy_key]))
+    out = {"command": command, "source_sha": _source_sha(),
+           "copy_kernel": {"name": copy_key[0], "bytes": 1 << 29, "fetch_kib": sum(f[copy_key]) / len(f[copy_key]),
+                           "write_kib": sum(w[copy_key]) / len(w[copy_key]), "fetch_scale": sf, "write_scale": sw},
+           "kernels": {}}
+    for name in ("k_rb<float,3>", "k_rb<double,3>", "k_rb_tile3<float>", "k_rb_tile3<double>",
+                 "k_resid_reg<double,3,0>"):
+        keys = [k for k in f if k[0] == name]
+        if not keys:
+            continue
+        k = max(keys, key=lambda q: q[1])   # finest level: the largest grid
+        fk = sum(f[k]) / len(f[k])
+        wk = sum(w[k]) / len(w[k]) if k in w else 0.0
+        out["kernels"][name] = {"grid": k[1], "dispatches": len(f[k]), "fetch_kib": fk, "write_kib": wk,
+                                "hbm_bytes_per_launch": (fk * sf + wk * sw) * 1024.0}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+    return 0
+
+
+def _solve_loop(P, rho, phi, phi2, E, steps, warmup):
+    import torch
+    from paper_1809_03745_amd import ebmg
 
     def step():
         phi.zero_()
@@ -106,37 +189,129 @@ def main():
             raise RuntimeError(f"solve failed: status {st} {info}")
         return info
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    lat = []
-    cycles = []
+    lat, cycles = [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         ts = time.perf_counter()
         info = step()
         lat.append(time.perf_counter() - ts)
         cycles.append(info["cycles"])
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0, lat, cycles, info
+
+
+def _pct(lat, q):
+    v = sorted(1000.0 * x for x in lat)
+    return v[min(len(v) - 1, int(round(q / 100.0 * (len(v) - 1))))]
+
+
+def batched(nbox=512, reps=3):
+    """The batched workload: 512 uneven 3D boxes solved by one persistent
+    launch, mixed precision and FP64."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1809_03745_amd import ebmg
+    dev = torch.device("cuda:0")
+    boxes = W.batched_boxes(nbox, seed=0)
+    cells = np.array([int(np.prod(p.shape)) for p in boxes])
+    rho = [torch.tensor(p.rho.ravel(), dtype=torch.float64, device=dev) for p in boxes]
+    phi = [torch.zeros(int(c), dtype=torch.float64, device=dev) for c in cells]
+    ctx = ebmg.Context(0)
+    out = {"workload": f"{nbox} random 3D boxes (edges 16..64 log-uniform, sphere electrode, eps plane split, "
+                       f"4 Fourier modes, seed 0)", "cells": int(cells.sum())}
+    for prec, key in ((ebmg.MIXED, "mixed"), (ebmg.FP64, "fp64")):
+        B = ebmg.Batch(ctx, boxes, precision=prec)
+        phi2 = [torch.zeros(max(1, int(c)), dtype=torch.float64, device=dev) for c in cells]
+        best = None
+        for _ in range(reps):
+            for x in phi:
+                x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, infos = B.solve(rho, phi, phi2=phi2, rtol=1e-10, max_cycles=400, check=False)
+            dt = time.perf_counter() - t0
+            if st != ebmg.OK:
+                raise RuntimeError(f"batched solve failed: status {st}")
+            best = dt if best is None else min(best, dt)
+        cyc = np.array([i["cycles"] for i in infos])
+        out[key] = {"ms_per_batch": 1000 * best, "solves_per_s": nbox / best,
+                    "cell_updates_per_s": float((cells * cyc).sum() / best),
+                    "vcycles_mean": float(cyc.mean()), "vcycles_max": int(cyc.max()),
+                    "worst_rel_residual": max(i["rel_residual"] for i in infos)}
+        B.release()
+        del phi2
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 comparison and the batched workload")
+    ap.add_argument("--pmc-probe", action="store_true", help="run the workload of the counter passes and exit")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
+                    help="reduce the counter passes of --pmc-probe to the committed traffic summary")
+    ap.add_argument("--smoother", choices=["auto", "split", "fused"], default="auto",
+                    help="pin the smoother choice instead of the setup autotuner (for profiled runs)")
+    ap.add_argument("--tail", choices=["auto", "none", "engine"], default="auto",
+                    help="pin the coarse-tail choice instead of the setup autotuner (for profiled runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the solver runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not implemented); use --gpus 1", file=sys.stderr)
+        return 2
+    args.tune = dict(smoother=["auto", "split", "fused"].index(args.smoother),
+                     tail=["auto", "none", "engine"].index(args.tail))
+    if args.pmc_probe:
+        return pmc_probe(args)
+    if args.pmc_summary:
+        return pmc_summary(*args.pmc_summary)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+    import workloads as W
+    from paper_1809_03745_amd import ebmg
+
+    dev = torch.device("cuda:0")
+    pr = W.pin_plane(args.n, seed=0)
+    ctx = ebmg.Context(0)
+    prec = ebmg.MIXED if args.precision == "mixed" else ebmg.FP64
+    t_setup = time.perf_counter()
+    P = ebmg.Problem(ctx, pr, precision=prec, **args.tune)
+    t_setup = time.perf_counter() - t_setup
+    rho = torch.tensor(pr.rho.ravel(), dtype=torch.float64, device=dev)
+    phi = torch.zeros(P.N, dtype=torch.float64, device=dev)
+    phi2 = torch.zeros(max(P.N2, 1), dtype=torch.float64, device=dev)
+    E = torch.zeros(3 * P.N, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    dt, lat, cycles, info = _solve_loop(P, rho, phi, phi2, E, args.steps, args.warmup)
     ms = 1000.0 * dt / args.steps
     tot_cycles = int(sum(cycles))
     value = P.N * tot_cycles / dt
-    lat_ms = sorted(1000.0 * v for v in lat)
 
-    def pct(q):
-        k = min(len(lat_ms) - 1, int(round(q / 100.0 * (len(lat_ms) - 1))))
-        return lat_ms[k]
-
-    # dominant kernel: fine-level smoother half-sweep, timed with HIP events
+    # dominant kernel: the finest-level smoother, timed with HIP events on the
+    # library's stream
     k_ms, k_bytes = P.time_kernel(0, 0, reps=200)
-    r_ms, r_bytes = P.time_kernel(1, 0, reps=100) if prec == ebmg.FP64 else (None, None)
+    label, unit_kind = _kernel_label(P, prec)
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
+    traffic = _traffic(label.split(" ")[0])
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_rb_tile3<%s> (fused red+black Gauss-Seidel sweep, finest level)" %
-                      ("float" if prec == ebmg.MIXED else "double"),
-            "kernel_ms": round(k_ms, 5), "alg_bytes_per_launch": int(k_bytes)}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": label, "kernel_ms": round(k_ms, 5), "alg_bytes_per_launch": int(k_bytes),
+            "alg_bytes_unit": f"{3 * (4 if prec == ebmg.MIXED else 8) + 1} B per updated cell ({unit_kind})"}
+    r_ms, r_bytes = P.time_kernel(1, 0, reps=100)
+    tuning = {"fused_levels": [l for l in range(P.levels) if P.tuning(l)[0]],
+              "level0_split_sweep_ms": P.tuning(0)[1], "level0_fused_sweep_ms": P.tuning(0)[2],
+              "tail_first_level": P.tuning(-1)[0], "vcycle_ms_no_tail": P.tuning(-1)[1],
+              "vcycle_ms_chosen": P.tuning(-1)[2], "pinned": {"smoother": args.smoother, "tail": args.tail}}
     out = {
         "metric": METRIC,
         "value": value,
@@ -155,15 +330,31 @@ def main():
                    "solver": "V-cycle(2,2)-preconditioned BiCGStab", "rtol": 1e-10},
         "solves_per_s": args.steps / dt,
         "vcycles_per_solve": tot_cycles / args.steps,
-        "latency_ms": {"p50": pct(50), "p99": pct(99)},
+        "rel_residual": info["rel_residual"],
+        "latency_ms": {"p50": _pct(lat, 50), "p99": _pct(lat, 99)},
         "setup_s": t_setup,
         "roofline": roof,
+        "residual_kernel": {"kernel": "k_resid_reg<double,3,0> (FP64 residual, finest level)", "ms": r_ms,
+                            "GB/s": r_bytes / (r_ms * 1e-3) / 1e9,
+                            "frac": r_bytes / (r_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "tuning": tuning,
     }
-    if r_ms is not None:
-        out["residual_kernel"] = {"ms": r_ms, "GB/s": r_bytes / (r_ms * 1e-3) / 1e9}
+    P.release()
+    if not args.no_extras:
+        other = ebmg.FP64 if prec == ebmg.MIXED else ebmg.MIXED
+        P2 = ebmg.Problem(ctx, pr, precision=other, **args.tune)
+        dt2, lat2, cyc2, info2 = _solve_loop(P2, rho, phi, phi2, E, max(3, args.steps // 2), 1)
+        n2 = max(3, args.steps // 2)
+        out["fp64_solver" if other == ebmg.FP64 else "mixed_solver"] = {
+            "ms_per_step": 1000.0 * dt2 / n2, "value": P2.N * sum(cyc2) / dt2,
+            "vcycles_per_solve": sum(cyc2) / n2, "rel_residual": info2["rel_residual"],
+            "latency_ms": {"p50": _pct(lat2, 50), "p99": _pct(lat2, 99)}}
+        P2.release()
+        del E
+        torch.cuda.empty_cache()
+        out["batched"] = batched()
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
-    P.release()
     if rank == 0:
         print(json.dumps(out))
     return 0

@@ -110,7 +110,10 @@ typedef struct {
   int32_t smoother;         /* 0 autotuned per level at setup, 1 split red and
                                black half-sweeps, 2 fused red+black tile sweep
                                (levels of at least 32^3 / 256^2 cells)           */
-  int32_t reserved[6];
+  int32_t tail;             /* coarse levels: 0 autotuned at setup, 1 always by
+                               grid-wide launches, 2 always by the one-workgroup
+                               engine from the first level of <= 32768 unknowns */
+  int32_t reserved[5];      /* must be zero                                      */
 } ebmg_options;
 
 typedef struct {
@@ -153,7 +156,10 @@ ebmg_status ebmg_query(ebmg_problem pb, int64_t* n_cells, int64_t* n_phase2, int
 ebmg_status ebmg_query_level(ebmg_problem pb, int32_t level, int64_t* n_cells, int64_t* n_phase2);
 
 /* Smoother choice of level `level` (1 = fused tile sweep) and the sweep times
- * (ms) the setup autotuner measured for each variant (0 if not timed). */
+ * (ms) the setup autotuner measured for each variant (0 if not timed).
+ * level = -1 reports the coarse-tail choice instead: *fused receives the first
+ * level run by the one-workgroup engine (-1: none), *split_ms the V-cycle time
+ * without it and *fused_ms the V-cycle time with the chosen tail. */
 ebmg_status ebmg_query_tuning(ebmg_problem pb, int32_t level, int32_t* fused, double* split_ms, double* fused_ms);
 
 /* HOST copies of a level's cell tags (0/1 regular gas/dielectric, 2 explicit
@@ -199,10 +205,12 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
 
 /* Measurement hook: launch one kernel `reps` times on the context stream
  * between two HIP events and report the mean duration per launch (ms) and
- * the kernel's algorithmic bytes per launch. which = 0: the level's
- * smoother kernel (the fused red+black sweep where the level uses it, else a
- * red/black half-sweep; FP32 for mixed-precision problems, else FP64);
- * 1: FP64 residual of level `level`. Overwrites the level's work vectors. */
+ * the kernel's algorithmic bytes per launch. which = 0: the level's chosen
+ * smoother kernel; 2: a red/black half-sweep; 3: the fused red+black tile
+ * sweep (ERR_ARG where the level cannot use it) -- FP32 for mixed-precision
+ * problems, else FP64; 1: FP64 residual of level `level`. Smoother bytes are
+ * 3 values + 1 tag byte per updated cell, residual bytes 3 FP64 values + 1
+ * tag byte per cell. Overwrites the level's work vectors. */
 ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int32_t reps, double* avg_ms,
                              double* alg_bytes);
 

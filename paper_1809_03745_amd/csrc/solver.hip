@@ -121,8 +121,10 @@ struct DevProblem {
   // BiCGStab work vectors: r, rh, p, v, ph, s, sh, t
   DevBuf<double> kv[8];
   bool krylov = false;
-  // coarse tail run by one workgroup: levels tail_l0 .. end
+  // coarse tail run by one workgroup: levels tail_l0 .. end (-1: none)
   int tail_l0 = -1;
+  std::vector<int> tail_cand;     // candidate first tail levels timed at setup
+  std::vector<double> tail_ms;    // V-cycle ms for each candidate
   DevBuf<uint8_t> tail_lv;
   int64_t bytes = 0;
   void release() {
@@ -232,8 +234,9 @@ static void launch_fused(DevLevel& l, const T* xin, T* xout, const T* b, const T
   }
 }
 
-// Levels with at most this many unknowns are run by the one-workgroup engine.
-constexpr int64_t kTailMax = 4096;
+// Levels with at most this many unknowns may be run by the one-workgroup
+// engine; the setup autotuner picks the first such level (or none).
+constexpr int64_t kTailMax = 32768;
 
 template <typename T>
 static BLev<T> make_blev(DevLevel& l) {
@@ -268,11 +271,62 @@ static BLev<T> make_blev(DevLevel& l) {
 }
 
 template <typename T>
+static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* x, const T* b);
+
+// Tail autotuner: time a whole V-cycle (on zero vectors) with the one-
+// workgroup engine starting at each level of at most kTailMax unknowns, and
+// with no tail at all; keep the fastest.
+template <typename T>
+static void tune_tail(DevProblem& D, const Options& o, hipStream_t s) {
+  const int nl = (int)D.lv.size();
+  std::vector<int> cand;
+  if (o.tail != 2) cand.push_back(-1);
+  if (o.tail != 1)
+    for (int l = nl - 1; l >= 0 && D.lv[l].N + D.lv[l].N2 <= kTailMax; --l) cand.push_back(l);
+  if (o.tail == 2 && cand.size() > 1) cand.erase(cand.begin(), cand.end() - 1);
+  if (cand.size() == 1) {
+    D.tail_cand = cand;
+    D.tail_ms.assign(1, 0.0);
+    D.tail_l0 = cand[0];
+    return;
+  }
+  DevLevel& L0 = D.lv[0];
+  T* x = Vec<T>::x(L0);
+  T* b = Vec<T>::b(L0);
+  fill<T>(x, L0.N + L0.N2, T(0), s);
+  fill<T>(b, L0.N + L0.N2, T(0), s);
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  double best = 1e30;
+  int pick = -1;
+  D.tail_ms.assign(cand.size(), 0.0);
+  for (size_t k = 0; k < cand.size(); ++k) {
+    D.tail_l0 = cand[k];
+    for (int r = 0; r < 2; ++r) vcycle<T>(D, o, 0, s, x, b);
+    const int reps = 5;
+    HIPCHECK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) vcycle<T>(D, o, 0, s, x, b);
+    HIPCHECK(hipEventRecord(e1, s));
+    HIPCHECK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+    D.tail_ms[k] = ms / reps;
+    if (ms / reps < best) {
+      best = ms / reps;
+      pick = cand[k];
+    }
+  }
+  D.tail_cand = cand;
+  D.tail_l0 = pick;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+template <typename T>
 static void upload_tail(DevProblem& D, hipStream_t s) {
   const int nl = (int)D.lv.size();
-  int l0 = nl - 1;
-  while (l0 > 0 && D.lv[l0 - 1].N + D.lv[l0 - 1].N2 <= kTailMax) --l0;
-  D.tail_l0 = l0;
+  D.tail_l0 = -1;
   std::vector<BLev<T>> v;
   for (int l = 0; l < nl; ++l) v.push_back(make_blev<T>(D.lv[l]));
   int64_t by = 0;
@@ -454,10 +508,13 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
   }
   HIPCHECK(hipStreamSynchronize(s));
   for (auto& l : D.lv) tune_smoother(l, mixed, H.opt.smoother, s);
-  if (mixed)
+  if (mixed) {
     upload_tail<float>(D, s);
-  else
+    tune_tail<float>(D, H.opt, s);
+  } else {
     upload_tail<double>(D, s);
+    tune_tail<double>(D, H.opt, s);
+  }
   if (D.krylov)
     for (auto& k : D.kv) k.alloc(L0.N + L0.N2, by);
   HIPCHECK(hipStreamSynchronize(s));
@@ -991,7 +1048,11 @@ static ebmg_status parse_options(const ebmg_options* opt, int nobj, ebmg::Option
   out.bottom_max = o.bottom_max_dof > 0 ? o.bottom_max_dof : 600;
   if (o.precision != EBMG_FP64 && o.precision != EBMG_MIXED) return EBMG_ERR_ARG;
   if (!(o.beta != 0.0) || !std::isfinite(o.beta)) return EBMG_ERR_ARG;
-  if (o.krylov < 0 || o.krylov > 2 || o.smoother < 0 || o.smoother > 2) return EBMG_ERR_ARG;
+  if (o.krylov < 0 || o.krylov > 2 || o.smoother < 0 || o.smoother > 2 || o.tail < 0 || o.tail > 2)
+    return EBMG_ERR_ARG;
+  for (int k = 0; k < 5; ++k)
+    if (o.reserved[k] != 0) return EBMG_ERR_ARG;
+  out.tail = o.tail;
   out.krylov = o.krylov == 0 ? (nobj > 0 ? 2 : 1) : o.krylov;
   out.smoother = o.smoother;
   return EBMG_OK;
@@ -1072,8 +1133,20 @@ ebmg_status ebmg_query_level(ebmg_problem pb, int32_t level, int64_t* n_cells, i
 }
 
 ebmg_status ebmg_query_tuning(ebmg_problem pb, int32_t level, int32_t* fused, double* split_ms, double* fused_ms) {
-  if (!pb || level < 0 || level >= (int32_t)pb->host->levels.size()) return EBMG_ERR_ARG;
+  if (!pb || level < -1 || level >= (int32_t)pb->host->levels.size()) return EBMG_ERR_ARG;
   if (!pb->on_device) return EBMG_ERR_DEVICE;
+  if (level == -1) {
+    const DevProblem& D = pb->dev;
+    if (fused) *fused = D.tail_l0;
+    double tno = 0, tpick = 0;
+    for (size_t k = 0; k < D.tail_cand.size(); ++k) {
+      if (D.tail_cand[k] == -1) tno = D.tail_ms[k];
+      if (D.tail_cand[k] == D.tail_l0) tpick = D.tail_ms[k];
+    }
+    if (split_ms) *split_ms = tno;
+    if (fused_ms) *fused_ms = tpick;
+    return EBMG_OK;
+  }
   const DevLevel& l = pb->dev.lv[level];
   if (fused) *fused = l.fused ? 1 : 0;
   if (split_ms) *split_ms = l.tune_split_ms;
@@ -1237,7 +1310,7 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
     double bytes = 0;
     const Shape shh = shape3((L.n[0] + 1) / 2, L.n[1], L.dim == 3 ? L.n[2] : 1);
     const Shape shf = shape3(L.n[0], L.n[1], L.dim == 3 ? L.n[2] : 1);
-    const bool fz = which == 0 && L.fused;
+    const bool fz = (which == 0 && L.fused) || which == 3;
     auto launch = [&](int colour) {
       if (fz) {
         if (mixed)
@@ -1246,7 +1319,7 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
           launch_fused<double>(L, (colour & 1) ? L.xa64.p : L.x64.p, (colour & 1) ? L.x64.p : L.xa64.p, L.b64.p, L.t64, s);
         return;
       }
-      if (which == 0) {
+      if (which != 1) {
         if (mixed) {
           if (L.dim == 3)
             hipLaunchKernelGGL((k_rb<float, 3>), shh.g, shh.b, 0, s, L.tag.p, L.x32.p, L.b32.p, L.t32, colour);
@@ -1265,9 +1338,10 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
           hipLaunchKernelGGL((k_resid_reg<double, 2, 0>), shf.g, shf.b, 0, s, L.tag.p, L.x64.p, L.b64.p, L.r64.p, L.t64);
       }
     };
-    if (which != 0 && which != 1) throw ArgError("unknown kernel id");
+    if (which < 0 || which > 3) throw ArgError("unknown kernel id");
+    if (which == 3 && (mixed ? !L.xa32.p : !L.xa64.p)) throw ArgError("this level has no fused sweep");
     if (which == 1 && !L.x64.p) throw ArgError("no FP64 vectors on this level");
-    if (which == 0) {
+    if (which != 1) {
       // algorithmic bytes of one half-sweep: each updated cell reads x and b,
       // writes x, reads its tag
       const int es = mixed ? 4 : 8;

@@ -62,7 +62,7 @@ class Options(C.Structure):
                 ("b_gas", C.c_double), ("dirichlet_closure", C.c_int32), ("robin_closure", C.c_int32),
                 ("eb_order", C.c_int32), ("precision", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("bottom_max_dof", C.c_int32), ("krylov", C.c_int32), ("smoother", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("tail", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class SolveInfo(C.Structure):
@@ -171,7 +171,7 @@ KRYLOV_AUTO, KRYLOV_NONE, KRYLOV_BICGSTAB = 0, 1, 2
 
 
 def make_options(prob, precision=FP64, dirichlet_closure=0, robin_closure=0, eb_order=2, nu1=2, nu2=2,
-                 bottom_max_dof=0, krylov=KRYLOV_AUTO, smoother=0):
+                 bottom_max_dof=0, krylov=KRYLOV_AUTO, smoother=0, tail=0):
     o = Options()
     _lib.ebmg_default_options(C.byref(o))
     o.alpha = prob.alpha
@@ -188,6 +188,7 @@ def make_options(prob, precision=FP64, dirichlet_closure=0, robin_closure=0, eb_
     o.bottom_max_dof = bottom_max_dof
     o.krylov = krylov
     o.smoother = smoother
+    o.tail = tail
     return o
 
 
@@ -303,10 +304,11 @@ class Problem:
                        "ebmg_efield")
 
     def tuning(self, level):
-        """(fused chosen, split sweep ms, fused sweep ms) from the setup autotuner."""
+        """(fused chosen, split sweep ms, fused sweep ms) from the setup autotuner;
+        level -1: (first tail level or -1, V-cycle ms without tail, V-cycle ms chosen)."""
         f, a, b = C.c_int32(), C.c_double(), C.c_double()
         self.ctx.check(_lib.ebmg_query_tuning(self.h, level, C.byref(f), C.byref(a), C.byref(b)), "tuning")
-        return bool(f.value), a.value, b.value
+        return (f.value if level == -1 else bool(f.value)), a.value, b.value
 
     def time_kernel(self, which, level=0, reps=50):
         """(mean ms per launch, algorithmic bytes per launch) of a kernel."""

@@ -247,6 +247,73 @@ def batched(nbox=512, reps=3):
     return out
 
 
+def sequential_boxes(nbox=64):
+    """The first boxes of the batched workload solved one by one with the
+    plain FP64 single-box solver (setup excluded), for comparison."""
+    import torch
+    import workloads as W
+    from paper_1809_03745_amd import ebmg
+    dev = torch.device("cuda:0")
+    ctx = ebmg.Context(0)
+    boxes = W.batched_boxes(512, seed=0)[:nbox]
+    probs = [ebmg.Problem(ctx, p) for p in boxes]
+    rho = [torch.tensor(p.rho.ravel(), dtype=torch.float64, device=dev) for p in boxes]
+    phi = [torch.zeros(P.N, dtype=torch.float64, device=dev) for P in probs]
+    phi2 = [torch.zeros(max(1, P.N2), dtype=torch.float64, device=dev) for P in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for P, r, x, x2 in zip(probs, rho, phi, phi2):
+        st, _ = P.solve(r, x, phi2=x2 if P.N2 else None, rtol=1e-10, max_cycles=400, check=False)
+        if st != ebmg.OK:
+            raise RuntimeError(f"sequential box solve failed: {st}")
+    dt = time.perf_counter() - t0
+    for P in probs:
+        P.release()
+    return {"boxes": nbox, "solves_per_s": nbox / dt, "ms_per_box": 1000 * dt / nbox,
+            "solver": "single-box FP64, one box at a time"}
+
+
+def serving_bench(rates=(10.0, 100.0, 1000.0), nreq=(40, 120, 200), seed=0):
+    """Continuous-batching server on the serving workload: warm one resident
+    hierarchy per request class, then replay Poisson arrivals at each rate."""
+    import workloads as W
+    from paper_1809_03745_amd import serving
+    srv = serving.Server(0, slots=4)
+    # warm-up: one request per (operator, dim, n) class
+    t_w = time.perf_counter()
+    warm = []
+    k = 0
+    for op in ("poisson", "helmholtz"):
+        for dim, ns in ((2, (512, 1024, 2048)), (3, (32, 64, 128, 256))):
+            for n in ns:
+                warm.append(srv.submit(serving.request_from_spec(
+                    k, dict(dim=dim, n=n, op=op, kappa=10.0, seed=1000 + k))))
+                k += 1
+    for r in warm:
+        r.done.wait()
+    bad = [r for r in warm if r.status != 0]
+    if bad:
+        raise RuntimeError(f"serving warm-up failed: {[(r.key, r.status, r.error) for r in bad]}")
+    out = {"workload": "Poisson arrivals; 2D 512^2-2048^2 blade-plane or 3D 32^3-256^3 pin-plane Poisson, "
+                       "or Eddington Helmholtz with kappa log-uniform in [1,100]; 50/50 each",
+           "slots": 4, "warmup_s": time.perf_counter() - t_w,
+           "resident_hierarchies": len(srv.sched.entries), "rates": []}
+    for rate, m in zip(rates, nreq):
+        arrivals, specs = W.serving_requests(m, rate, seed=seed + int(rate))
+        srv.records.clear()
+        with srv.cv:
+            srv.sched.reset_stats()
+        reqs, t0, t1 = serving.replay(srv, list(arrivals), specs)
+        for r in reqs:
+            r.phi = r.phi2 = None
+        summ = srv.summary(t0, t1)
+        summ.pop("budget_bytes", None)
+        out["rates"].append(dict(rate_per_s=rate, requests=m, **summ))
+    out["budget_bytes"] = srv.sched.budget
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -353,6 +420,8 @@ def main():
         del E
         torch.cuda.empty_cache()
         out["batched"] = batched()
+        out["batched"]["sequential_fp64"] = sequential_boxes()
+        out["serving"] = serving_bench()
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     if rank == 0:

@@ -214,6 +214,17 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
 ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int32_t reps, double* avg_ms,
                              double* alg_bytes);
 
+/* Replace the coefficients of a problem without embedded objects and without
+ * explicit rows on any level (e.g. the Eddington Helmholtz problem of the
+ * radiative-transfer section, kappa phi - div((1/3kappa) grad phi) = S, for a
+ * new absorption kappa): alpha, beta, a_gas, a_diel, b_gas in opt and the
+ * boundary data in bc (values and Robin a1/a2; kinds must equal those given
+ * at setup). Every other option must equal the setup's. The template
+ * constants of all levels and the bottom inverse are rebuilt on the host and
+ * re-sent; the device hierarchy is kept. ERR_ARG if the problem does not
+ * qualify. Not to be called while a solve on the problem is running. */
+ebmg_status ebmg_set_coefficients(ebmg_problem pb, const ebmg_options* opt, const ebmg_domain_bc* bc);
+
 ebmg_status ebmg_release(ebmg_problem pb);
 
 /* Batched boxes (independent problems of one dimension and one precision),

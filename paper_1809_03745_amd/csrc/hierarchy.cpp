@@ -34,7 +34,10 @@ std::vector<int32_t> irow_index(const Level& L) {
   return m;
 }
 
-void set_template(Level& C, const Problem& pb) {
+}  // namespace
+
+// Rediscretised template constants of a coarse level at its own spacing.
+void coarse_template(Level& C, const Problem& pb) {
   const double h = C.g.h, beta = pb.opt.beta;
   for (int p = 0; p < 2; ++p) {
     const double b = pb.bph[p];
@@ -57,7 +60,6 @@ void set_template(Level& C, const Problem& pb) {
   }
 }
 
-}  // namespace
 
 void Level::row(int64_t q, double& mass_out, std::vector<std::pair<int64_t, double>>& out) const {
   out.clear();
@@ -185,7 +187,7 @@ static bool coarsen(Problem& pb, size_t lf) {
     C.tag[P] = allreg ? (uint8_t)pc : (uint8_t)TAG_IRR;
     if (!simple[P]) C.tag[P] |= TAG_NONSIMPLE;
   }
-  set_template(C, pb);
+  coarse_template(C, pb);
   // children of each coarse unknown
   std::vector<int64_t> kids;
   std::vector<std::pair<int64_t, double>> rowbuf;
@@ -306,6 +308,12 @@ void build_hierarchy(Problem& pb) {
   while (pb.levels.size() < 16 && pb.levels.back().ndof() > pb.opt.bottom_max) {
     if (!coarsen(pb, pb.levels.size() - 1)) break;
   }
+  build_bottom(pb);
+}
+
+// Dense FP64 inverse of the coarsest level (left empty above 4096 unknowns,
+// where the bottom is relaxed instead).
+void build_bottom(Problem& pb) {
   const Level& B = pb.levels.back();
   const int64_t n = B.ndof();
   pb.bottom_n = n;

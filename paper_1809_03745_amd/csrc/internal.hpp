@@ -188,6 +188,9 @@ struct Problem {
 
 void build_fine_level(Problem& pb);
 void build_hierarchy(Problem& pb);
+void fine_template(Problem& pb);
+void coarse_template(Level& C, const Problem& pb);
+void build_bottom(Problem& pb);
 void colour_irregular(Level& L);
 void host_rhs(const Problem& pb, const double* rho, const double* sigma, const double* bcv,
               const double* objv, double* b);

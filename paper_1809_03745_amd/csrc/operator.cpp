@@ -510,24 +510,16 @@ struct Builder {
 
 // --- finest level -----------------------------------------------------------
 
-void build_fine_level(Problem& pb) {
-  const Geometry& geo = pb.geo;
-  const Grid& g = geo.g;
-  const Options& o = pb.opt;
-  Builder B(pb);
-  pb.levels.clear();
-  pb.levels.emplace_back();
+// Template constants of the finest level (off-diagonal, diagonal and the
+// per-face boundary corrections for each phase) and the per-face data of the
+// right-hand side and of E at domain faces: the parts of the fine operator
+// that depend only on the coefficients and the boundary data.
+void fine_template(Problem& pb) {
   Level& L = pb.levels[0];
   FineData& F = pb.fine;
-  F = FineData();
-  L.g = g;
-  L.N = geo.N;
-  L.N2 = geo.N2;
-  L.primary = geo.primary;
-  L.sec_of = geo.sec_of;
-  L.sec_cell.assign(geo.sec_cell.begin(), geo.sec_cell.end());
+  const Grid& g = L.g;
+  const Options& o = pb.opt;
   const double h = g.h, beta = o.beta;
-  // template constants
   for (int p = 0; p < 2; ++p) {
     const double b = pb.bph[p];
     L.coff[p] = beta * b / (h * h);
@@ -554,6 +546,26 @@ void build_fine_level(Problem& pb) {
       F.egb[f][p] = gb;
     }
   }
+}
+
+void build_fine_level(Problem& pb) {
+  const Geometry& geo = pb.geo;
+  const Grid& g = geo.g;
+  const Options& o = pb.opt;
+  Builder B(pb);
+  pb.levels.clear();
+  pb.levels.emplace_back();
+  Level& L = pb.levels[0];
+  FineData& F = pb.fine;
+  F = FineData();
+  L.g = g;
+  L.N = geo.N;
+  L.N2 = geo.N2;
+  L.primary = geo.primary;
+  L.sec_of = geo.sec_of;
+  L.sec_cell.assign(geo.sec_cell.begin(), geo.sec_cell.end());
+  const double h = g.h, beta = o.beta;
+  fine_template(pb);
   // regular mask
   const int64_t N = geo.N;
   L.tag.assign(N, TAG_IRR);

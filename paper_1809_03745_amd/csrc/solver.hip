@@ -1581,6 +1581,68 @@ ebmg_status ebmg_release_batch(ebmg_batch bt) {
   return EBMG_OK;
 }
 
+ebmg_status ebmg_set_coefficients(ebmg_problem pb, const ebmg_options* opt, const ebmg_domain_bc* bc) {
+  if (!pb || !opt || !bc) return EBMG_ERR_ARG;
+  return guard(pb->ctx, [&]() -> ebmg_status {
+    Problem& H = *pb->host;
+    if (!H.geo.obj_value.empty() || H.geo.N2 > 0) throw ArgError("problem has embedded objects");
+    for (const Level& L : H.levels)
+      if (!L.irow_dof.empty()) throw ArgError("problem has explicit rows");
+    Options o2;
+    if (parse_options(opt, 0, o2) != EBMG_OK) throw ArgError("bad options");
+    const Options& o = H.opt;
+    if (o2.precision != o.precision || o2.nu1 != o.nu1 || o2.nu2 != o.nu2 || o2.bottom_max != o.bottom_max ||
+        o2.krylov != o.krylov || o2.smoother != o.smoother || o2.tail != o.tail ||
+        o2.dirichlet_closure != o.dirichlet_closure || o2.robin_closure != o.robin_closure ||
+        o2.eb_order != o.eb_order)
+      throw ArgError("only alpha, beta, a and b may change");
+    const int nf = 2 * H.geo.g.dim;
+    for (int f = 0; f < nf; ++f) {
+      if (bc->kind[f] != H.bc.kind[f]) throw ArgError("boundary kinds are fixed at setup");
+      if (bc->kind[f] == EBMG_BC_ROBIN && !(bc->robin_a2[f] != 0.0)) throw ArgError("Robin a2 must be nonzero");
+    }
+    if (!(o2.b_gas > 0)) throw ArgError("b must be positive");
+    // host: new template constants on every level and a new bottom inverse
+    H.opt.alpha = o2.alpha;
+    H.opt.beta = o2.beta;
+    H.opt.a_gas = o2.a_gas;
+    H.opt.a_diel = o2.a_diel;
+    H.opt.b_gas = o2.b_gas;
+    H.bc = *bc;
+    H.bph[0] = H.bph[1] = o2.b_gas;
+    H.aph[0] = o2.a_gas;
+    H.aph[1] = o2.a_diel;
+    fine_template(H);
+    for (size_t l = 1; l < H.levels.size(); ++l) coarse_template(H.levels[l], H);
+    build_bottom(H);
+    if (!pb->on_device) return EBMG_OK;
+    HIPCHECK(hipSetDevice(pb->ctx->device));
+    hipStream_t s = pb->ctx->stream;
+    DevProblem& D = pb->dev;
+    HIPCHECK(hipStreamSynchronize(s));
+    for (size_t l = 0; l < H.levels.size(); ++l) {
+      D.lv[l].t64 = make_tmpl<double>(H.levels[l]);
+      D.lv[l].t32 = make_tmpl<float>(H.levels[l]);
+    }
+    if (!H.bottom_inv.empty()) {
+      if ((int64_t)H.bottom_inv.size() != D.bottom.n) throw ArgError("bottom size changed");
+      HIPCHECK(hipMemcpyAsync(D.bottom.p, H.bottom_inv.data(), sizeof(double) * H.bottom_inv.size(),
+                              hipMemcpyHostToDevice, s));
+    }
+    // the one-workgroup engine keeps copies of the templates in its level views
+    const int keep = D.tail_l0;
+    D.bytes -= D.tail_lv.n;
+    D.tail_lv.release();
+    if (H.opt.precision == EBMG_MIXED)
+      upload_tail<float>(D, s);
+    else
+      upload_tail<double>(D, s);
+    D.tail_l0 = keep;
+    HIPCHECK(hipStreamSynchronize(s));
+    return EBMG_OK;
+  });
+}
+
 ebmg_status ebmg_release(ebmg_problem pb) {
   if (!pb) return EBMG_ERR_ARG;
   if (pb->on_device) {

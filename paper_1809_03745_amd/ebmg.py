@@ -108,6 +108,7 @@ _sig("ebmg_apply", C.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_efield", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_time_kernel", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp])
 _sig("ebmg_release", C.c_int, [_vp])
+_sig("ebmg_set_coefficients", C.c_int, [_vp, C.POINTER(Options), C.POINTER(DomainBC)])
 _sig("ebmg_setup_batch", C.c_int, [_vp, C.c_int32, C.POINTER(Box), C.POINTER(C.c_int32), C.POINTER(_vp),
                                    C.POINTER(DomainBC), C.POINTER(Options), C.POINTER(_vp)])
 _sig("ebmg_query_batch", C.c_int, [_vp, _i64p, _i64p, _i64p])
@@ -119,7 +120,8 @@ EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_des
             "ebmg_setup", "ebmg_query", "ebmg_query_level", "ebmg_export_level", "ebmg_query_tuning",
             "ebmg_export_geometry", "ebmg_export_operator", "ebmg_export_rhs",
             "ebmg_solve", "ebmg_apply", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
-            "ebmg_setup_batch", "ebmg_query_batch", "ebmg_solve_batch", "ebmg_release_batch"]
+            "ebmg_setup_batch", "ebmg_query_batch", "ebmg_solve_batch", "ebmg_release_batch",
+            "ebmg_set_coefficients"]
 
 
 def abi_version():
@@ -316,6 +318,17 @@ class Problem:
         self.ctx.check(_lib.ebmg_time_kernel(self.h, which, level, reps, C.byref(ms), C.byref(by)),
                        "ebmg_time_kernel")
         return ms.value, by.value
+
+    def set_coefficients(self, prob):
+        """Take the coefficients and boundary data of ``prob`` (same grid, no
+        embedded objects) without a new setup."""
+        o = Options()
+        C.memmove(C.byref(o), C.byref(self.options), C.sizeof(Options))
+        o.alpha, o.beta, o.a_gas, o.a_diel, o.b_gas = prob.alpha, prob.beta, prob.a_gas, prob.a_diel, prob.b_gas
+        _, _, bc, _ = _c_problem(prob)
+        self.ctx.check(_lib.ebmg_set_coefficients(self.h, C.byref(o), C.byref(bc)), "ebmg_set_coefficients")
+        self.options = o
+        self.prob = prob
 
     def release(self):
         if getattr(self, "h", None):

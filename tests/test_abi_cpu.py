@@ -165,3 +165,34 @@ def test_batch_needs_a_device(host_ctx):
     with pytest.raises(ebmg.EbmgError) as e:
         ebmg.Batch(host_ctx, [W.manufactured_sine(8), W.manufactured_sine(16)])
     assert e.value.status == ebmg.ERR_DEVICE
+
+
+@pytest.mark.parametrize("dim,n", [(2, 32), (3, 16)])
+def test_set_coefficients_equals_new_setup(host_ctx, dim, n):
+    """A resident Eddington hierarchy re-coefficiented for a new absorption
+    equals a fresh setup of that problem on every level, and so does its
+    right-hand side."""
+    p1 = W.eddington(dim, n, 2.0, seed=3)
+    p2 = W.eddington(dim, n, 37.0, seed=3)
+    P = ebmg.Problem(host_ctx, p1)
+    Q = ebmg.Problem(host_ctx, p2)
+    P.set_coefficients(p2)
+    assert P.levels == Q.levels
+    for lev in range(P.levels):
+        A, B = P.operator(lev), Q.operator(lev)
+        assert (A != B).nnz == 0
+    assert np.array_equal(P.rhs(rho=p2.rho), Q.rhs())
+    S = assemble(p2)
+    assert abs(P.operator(0) - S.A).max() <= 1e-13 * abs(S.A).max()
+
+
+def test_set_coefficients_rejects_embedded_problems(host_ctx):
+    P = ebmg.Problem(host_ctx, W.two_disks(32, seed=0))
+    with pytest.raises(ebmg.EbmgError) as e:
+        P.set_coefficients(W.two_disks(32, seed=1))
+    assert e.value.status == ebmg.ERR_ARG
+    E = ebmg.Problem(host_ctx, W.eddington(2, 32, 2.0, seed=1))
+    pb = W.eddington(2, 32, 5.0, seed=1)
+    pb.bc_kind = [W.BC_DIRICHLET] * 6
+    with pytest.raises(ebmg.EbmgError):
+        E.set_coefficients(pb)

@@ -1,0 +1,104 @@
+"""Admission and residency policy of the serving loop (host logic only)."""
+from paper_1809_03745_amd.serving import Request, Scheduler
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+def _req(rid, key, cells, arrival=0.0):
+    return Request(rid, key, cells, make_problem=None, make_rho=None, arrival=arrival)
+
+
+def _admit(s):
+    p = s.next_admissible()
+    assert p is not None
+    req, entry, evict = p
+    return req, entry, evict
+
+
+def test_rejects_what_cannot_fit_an_empty_device():
+    s = Scheduler(budget_bytes=10_000, slots=2, bytes_per_cell=10)
+    r = _req(0, "a", 1000)
+    assert not s.offer(r) and r.rejected
+    assert s.stats["rejected"] == 1
+
+
+def test_reuses_idle_hierarchy_and_counts_hits():
+    s = Scheduler(budget_bytes=1 << 20, slots=2, bytes_per_cell=10)
+    s.offer(_req(0, "a", 100))
+    req, e, _ = _admit(s)
+    s.set_up(e, 3000)
+    s.finish(req, e)
+    s.offer(_req(1, "a", 100))
+    req2, e2, _ = _admit(s)
+    assert e2 is e and req2.hit
+    assert s.stats["hits"] == 1 and s.stats["misses"] == 1
+
+
+def test_slots_bound_concurrency():
+    s = Scheduler(budget_bytes=1 << 30, slots=2, bytes_per_cell=10)
+    for i in range(3):
+        s.offer(_req(i, ("k", i), 100))
+    _admit(s)
+    _admit(s)
+    assert s.next_admissible() is None
+    assert s.running == 2
+
+
+def test_lru_eviction_and_high_water_within_budget():
+    vec = _req(0, "x", 100).vec_bytes()
+    budget = 2 * 1000 + vec + 500      # two hierarchies and one request, not three
+    s = Scheduler(budget_bytes=budget, slots=1, bytes_per_cell=10)
+    clock = Clock()
+    s.clock = clock
+    for i, key in enumerate(["a", "b", "c", "a"]):
+        s.offer(_req(i, key, 100))
+        req, e, evict = _admit(s)
+        if e.handle is None and not e.ready:
+            s.set_up(e, 1000)
+        clock.t += 1.0
+        s.finish(req, e)
+        assert s.reserved() <= budget
+        if key == "c":
+            assert [v.key for v in evict] == ["a"]   # least recently used goes first
+    assert s.high_water <= budget
+    assert s.stats["evicted"] >= 1
+
+
+def test_first_fit_then_no_bypass_for_a_starved_head():
+    vec = _req(0, "x", 100).vec_bytes()
+    s = Scheduler(budget_bytes=3000 + 2 * vec, slots=4, bytes_per_cell=10, max_bypass_s=0.5)
+    clock = Clock()
+    s.clock = clock
+    s.offer(_req(0, "big0", 200))          # estimate 2000 + vec
+    r0, e0, _ = _admit(s)
+    s.set_up(e0, 2000)
+    s.offer(_req(1, "big1", 200, arrival=0.0))  # does not fit beside big0
+    s.offer(_req(2, "small", 10, arrival=0.0))  # fits: may pass the head
+    r, e, _ = _admit(s)
+    assert r.rid == 2
+    s.offer(_req(3, "small2", 10, arrival=0.0))
+    clock.t = 1.0                           # the head has now waited too long
+    assert s.next_admissible() is None
+
+
+def test_same_key_waits_for_its_busy_hierarchy():
+    s = Scheduler(budget_bytes=1 << 30, slots=4, bytes_per_cell=10)
+    s.clock = Clock()
+    s.offer(_req(0, "a", 100))
+    r0, e0, _ = _admit(s)
+    s.set_up(e0, 1000)
+    s.offer(_req(1, "a", 100))
+    s.offer(_req(2, "b", 100))
+    r, e, _ = _admit(s)            # "b" passes the waiting "a"
+    assert r.rid == 2
+    assert s.next_admissible() is None
+    s.finish(r0, e0)
+    r1, e1, _ = _admit(s)
+    assert r1.rid == 1 and e1 is e0 and r1.hit
+    assert sum(1 for x in s.entries if x.key == "a") == 1

@@ -230,6 +230,35 @@ def pin_plane(n=256, seed=0, nblob=8):
                    rho=np.ascontiguousarray(rho), name=f"pin-plane-{n}", seed=seed)
 
 
+def _blade_distance_point(c):
+    yc = 0.62
+    dx = abs(c[0] - 0.5)
+    return dx - 0.02 if c[1] >= yc else math.hypot(dx, c[1] - yc) - 0.02
+
+
+def _blobs_blade(rng, nblob):
+    cs, ss = [], []
+    for _ in range(nblob):
+        s = rng.uniform(0.01, 0.05)
+        while True:
+            c = np.array([rng.uniform(0.1, 0.9), rng.uniform(0.25, 0.95)])
+            if _blade_distance_point(c) >= 3 * s and c[1] - 0.2 >= 3 * s:
+                break
+        cs.append(c)
+        ss.append(s)
+    return cs, ss
+
+
+def _blobs_box(rng, nblob, dim):
+    cs, ss = [], []
+    for _ in range(nblob):
+        s = rng.uniform(0.01, 0.05)
+        c = rng.uniform(0.1, 0.9, size=dim)
+        cs.append(c)
+        ss.append(s)
+    return cs, ss
+
+
 def blade_plane(n=512, seed=0, nblob=8):
     """2D analogue of the pin-plane class: a blade of half-width 0.02 with a
     semicircular tip at y=0.6 reaching the top, dielectric slab y<0.2,
@@ -237,20 +266,7 @@ def blade_plane(n=512, seed=0, nblob=8):
     rng = np.random.default_rng(seed)
     h = 1.0 / n
 
-    def dblade(c):
-        yc = 0.62
-        dx = abs(c[0] - 0.5)
-        return dx - 0.02 if c[1] >= yc else math.hypot(dx, c[1] - yc) - 0.02
-
-    cs, ss = [], []
-    for _ in range(nblob):
-        s = rng.uniform(0.01, 0.05)
-        while True:
-            c = np.array([rng.uniform(0.1, 0.9), rng.uniform(0.25, 0.95)])
-            if dblade(c) >= 3 * s and c[1] - 0.2 >= 3 * s:
-                break
-        cs.append(c)
-        ss.append(s)
+    cs, ss = _blobs_blade(rng, nblob)
     Xn = _nodes(2, (n, n), h, (0.0, 0.0))
     objs = [Obj(OBJ_ELECTRODE, 1.0, np.ascontiguousarray(sdf_blade2(Xn, 0.5, 0.6, 0.02))),
             Obj(OBJ_DIELECTRIC, 4.0, np.ascontiguousarray(sdf_halfspace_below(Xn[1], 0.2)))]
@@ -273,15 +289,21 @@ def eddington(dim, n, kappa_abs, seed=0, nblob=8):
     nn = (n,) * dim
     X = _centres(dim, nn, h, (0.0,) * dim)
     S = np.zeros(X[0].shape)
-    for _ in range(nblob):
-        s = rng.uniform(0.01, 0.05)
-        c = rng.uniform(0.1, 0.9, size=dim)
+    for c, s in zip(*_blobs_box(rng, nblob, dim)):
         S += np.exp(-sum((X[d] - c[d]) ** 2 for d in range(dim)) / (2 * s * s))
+    pr = eddington_coefficients(dim, n, kappa_abs)
+    pr.rho = np.ascontiguousarray(S)
+    pr.seed = seed
+    return pr
+
+
+def eddington_coefficients(dim, n, kappa_abs):
+    """The Eddington problem's operator and boundary data without a source:
+    a = kappa, b = 1/(3 kappa), Robin a1 = 3 kappa/2, a2 = 1 on every face."""
     kind = [BC_ROBIN] * 6
-    return Problem(dim, nn, h, (0.0,) * dim, [], kind, [0.0] * 6, [1.5 * kappa_abs] * 6, [1.0] * 6,
-                   alpha=1.0, beta=-1.0, a_gas=kappa_abs, a_diel=kappa_abs,
-                   b_gas=1.0 / (3.0 * kappa_abs), rho=np.ascontiguousarray(S),
-                   name=f"eddington{dim}d-{n}-k{kappa_abs:.3g}", seed=seed)
+    return Problem(dim, (n,) * dim, 1.0 / n, (0.0,) * dim, [], kind, [0.0] * 6, [1.5 * kappa_abs] * 6,
+                   [1.0] * 6, alpha=1.0, beta=-1.0, a_gas=kappa_abs, a_diel=kappa_abs,
+                   b_gas=1.0 / (3.0 * kappa_abs), name=f"eddington{dim}d-{n}-k{kappa_abs:.3g}")
 
 
 def coaxial(n=256, R0=0.3, R1=0.6, R2=0.9, eps=4.0, phi0=1.0, sigma=0.0):
@@ -360,6 +382,35 @@ def serving_requests(nreq, rate, seed=0):
         kappa = math.exp(rng.uniform(0.0, math.log(100.0)))
         specs.append(dict(dim=dim, n=n, op=op, kappa=kappa, seed=int(rng.integers(1 << 31))))
     return t, specs
+
+
+def request_blobs(spec, nblob=8):
+    """(centres, standard deviations) of the source blobs of a served request:
+    the same draws ``make_request`` makes, without building the problem."""
+    rng = np.random.default_rng(spec["seed"])
+    if spec["op"] == "poisson":
+        if spec["dim"] == 3:
+            return _blobs3(rng, nblob, [_pin_distance_point, lambda c: c[2] - 0.2])
+        return _blobs_blade(rng, nblob)
+    return _blobs_box(rng, nblob, spec["dim"])
+
+
+def blob_field(dim, n, centres, sigmas, xp=np, device=None):
+    """Sum of unit-amplitude Gaussian blobs at the cell centres of the unit box
+    (n^dim cells, x fastest), evaluated with the array module ``xp`` (numpy, or
+    torch on ``device``). With numpy it is bitwise the source term of the
+    request generators."""
+    h = 1.0 / n
+    X = _axes(dim, (n,) * dim, h, (0.0,) * dim, 0.5)
+    if xp is not np:
+        X = tuple(xp.as_tensor(np.ascontiguousarray(a), dtype=xp.float64, device=device) for a in X)
+    out = xp.zeros((n,) * dim, dtype=xp.float64, **({} if xp is np else {"device": device}))
+    for c, s in zip(centres, sigmas):
+        q = (X[0] - float(c[0])) ** 2
+        for d in range(1, dim):
+            q = q + (X[d] - float(c[d])) ** 2
+        out += xp.exp(-q / (2 * s * s))
+    return out
 
 
 def make_request(spec):

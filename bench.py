@@ -68,9 +68,13 @@ def cpu_baseline(n=64):
 
 
 def _kernel_label(P, prec):
-    fused = P.tuning(0)[0]
+    var = P.tuning(0)[0]
     t = "float" if prec == 1 else "double"
-    if fused:
+    if var >= 2:
+        tile = ["64,8,32", "64,16,32", "32,16,32", "64,8,16"][var - 2]
+        return (f"k_rb_zm3<{t},{tile}> (fused red+black Gauss-Seidel sweep marching in z, finest level)",
+                "fused sweep")
+    if var == 1:
         return f"k_rb_tile3<{t}> (fused red+black Gauss-Seidel sweep, finest level)", "fused sweep"
     return f"k_rb<{t},3> (red/black Gauss-Seidel half-sweep, finest level)", "half-sweep"
 
@@ -123,7 +127,7 @@ def pmc_probe(args):
     ctx = ebmg.Context(0)
     for prec in (ebmg.MIXED, ebmg.FP64):
         P = ebmg.Problem(ctx, pr, precision=prec, **args.tune)
-        for which, what in ((2, "half-sweep"), (3, "fused sweep")):
+        for which, what in ((2, "half-sweep"), (3, "fused tile sweep"), (4, "z-marching sweep")):
             ms, by = P.time_kernel(which, 0, reps=10)
             print(f"precision {prec} {what}: 10 launches, {ms:.4f} ms, {by:.0f} alg bytes", flush=True)
         if prec == ebmg.FP64:
@@ -161,8 +165,9 @@ def pmc_summary(fetch_csv, write_csv, command):
            "copy_kernel": {"name": copy_key[0], "bytes": 1 << 29, "fetch_kib": sum(f[copy_key]) / len(f[copy_key]),
                            "write_kib": sum(w[copy_key]) / len(w[copy_key]), "fetch_scale": sf, "write_scale": sw},
            "kernels": {}}
-    for name in ("k_rb<float,3>", "k_rb<double,3>", "k_rb_tile3<float>", "k_rb_tile3<double>",
-                 "k_resid_reg<double,3,0>"):
+    zms = [f"k_rb_zm3<{t},{c}>" for t in ("float", "double") for c in ("64,8,32", "64,16,32", "32,16,32", "64,8,16")]
+    for name in ["k_rb<float,3>", "k_rb<double,3>", "k_rb_tile3<float>", "k_rb_tile3<double>",
+                 "k_resid_reg<double,3,0>"] + zms:
         keys = [k for k in f if k[0] == name]
         if not keys:
             continue
@@ -326,7 +331,7 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true", help="run the workload of the counter passes and exit")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="reduce the counter passes of --pmc-probe to the committed traffic summary")
-    ap.add_argument("--smoother", choices=["auto", "split", "fused"], default="auto",
+    ap.add_argument("--smoother", choices=["auto", "split", "fused", "zmarch"], default="auto",
                     help="pin the smoother choice instead of the setup autotuner (for profiled runs)")
     ap.add_argument("--tail", choices=["auto", "none", "engine"], default="auto",
                     help="pin the coarse-tail choice instead of the setup autotuner (for profiled runs)")
@@ -335,7 +340,7 @@ def main():
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
               "(multi-GPU sharding is a design note, not implemented); use --gpus 1", file=sys.stderr)
         return 2
-    args.tune = dict(smoother=["auto", "split", "fused"].index(args.smoother),
+    args.tune = dict(smoother=["auto", "split", "fused", "zmarch"].index(args.smoother),
                      tail=["auto", "none", "engine"].index(args.tail))
     if args.pmc_probe:
         return pmc_probe(args)
@@ -375,7 +380,7 @@ def main():
             "kernel": label, "kernel_ms": round(k_ms, 5), "alg_bytes_per_launch": int(k_bytes),
             "alg_bytes_unit": f"{3 * (4 if prec == ebmg.MIXED else 8) + 1} B per updated cell ({unit_kind})"}
     r_ms, r_bytes = P.time_kernel(1, 0, reps=100)
-    tuning = {"fused_levels": [l for l in range(P.levels) if P.tuning(l)[0]],
+    tuning = {"smoother_variant_per_level": [P.tuning(l)[0] for l in range(P.levels)],
               "level0_split_sweep_ms": P.tuning(0)[1], "level0_fused_sweep_ms": P.tuning(0)[2],
               "tail_first_level": P.tuning(-1)[0], "vcycle_ms_no_tail": P.tuning(-1)[1],
               "vcycle_ms_chosen": P.tuning(-1)[2], "pinned": {"smoother": args.smoother, "tail": args.tail}}

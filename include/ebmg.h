@@ -108,8 +108,10 @@ typedef struct {
                                V-cycles), 1 plain V-cycles, 2 V-cycle-preconditioned
                                BiCGStab                                          */
   int32_t smoother;         /* 0 autotuned per level at setup, 1 split red and
-                               black half-sweeps, 2 fused red+black tile sweep
-                               (levels of at least 32^3 / 256^2 cells)           */
+                               black half-sweeps, 2 fused red+black tile sweep,
+                               3 z-marching fused sweep (3D; tile sweep in 2D);
+                               fused sweeps only on levels of at least 32^3 /
+                               256^2 cells                                      */
   int32_t tail;             /* coarse levels: 0 autotuned at setup, 1 always by
                                grid-wide launches, 2 always by the one-workgroup
                                engine from the first level of <= 32768 unknowns */
@@ -155,8 +157,11 @@ ebmg_status ebmg_query(ebmg_problem pb, int64_t* n_cells, int64_t* n_phase2, int
 /* Sizes of multigrid level `level` (0 = finest): cells and second-phase unknowns. */
 ebmg_status ebmg_query_level(ebmg_problem pb, int32_t level, int64_t* n_cells, int64_t* n_phase2);
 
-/* Smoother choice of level `level` (1 = fused tile sweep) and the sweep times
- * (ms) the setup autotuner measured for each variant (0 if not timed).
+/* Smoother choice of level `level` (0 split half-sweeps, 1 fused tile sweep,
+ * 2 + c z-marching fused sweep in tile configuration c as listed at
+ * ebmg_smooth), the split sweep time and the chosen (or best
+ * fused) variant's sweep time (ms) as the setup autotuner measured them (0 if
+ * not timed).
  * level = -1 reports the coarse-tail choice instead: *fused receives the first
  * level run by the one-workgroup engine (-1: none), *split_ms the V-cycle time
  * without it and *fused_ms the V-cycle time with the chosen tail. */
@@ -203,11 +208,27 @@ ebmg_status ebmg_apply(ebmg_problem pb, const double* phi, const double* phi2, d
 ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, const double* sigma,
                         const double* bc_values, const double* obj_values, double* E);
 
+/* Red/black Gauss-Seidel sweeps (the smoother of the multigrid-solver
+ * subsection) over the template cells of level `level` only: explicit-row,
+ * covered and second-phase entries of x are left as they are. variant: 1
+ * split red and black half-sweeps, 2 fused tile sweep, 3 + c z-marching
+ * fused sweep in tile configuration c = 0..3 (64x8 tiles over 32 planes,
+ * 64x16 over 32, 32x16 over 32, 64x8 over 16; 3D). Every variant performs
+ * exactly the red half-sweep followed by
+ * the black one with the same arithmetic, so their results agree bitwise.
+ * x (in/out) and b are DEVICE FP64 arrays of the level's N + N2 unknowns;
+ * mixed-precision problems sweep in FP32 (x and b rounded, x widened back).
+ * Uses the level's work vectors. ERR_ARG where the level cannot use the
+ * variant. */
+ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t sweeps, double* x,
+                        const double* b);
+
 /* Measurement hook: launch one kernel `reps` times on the context stream
  * between two HIP events and report the mean duration per launch (ms) and
  * the kernel's algorithmic bytes per launch. which = 0: the level's chosen
- * smoother kernel; 2: a red/black half-sweep; 3: the fused red+black tile
- * sweep (ERR_ARG where the level cannot use it) -- FP32 for mixed-precision
+ * smoother kernel; 2: a red/black half-sweep; 3: the level's fused
+ * red+black sweep; 4: the z-marching fused sweep (3D); ERR_ARG where the
+ * level cannot use a fused sweep -- FP32 for mixed-precision
  * problems, else FP64; 1: FP64 residual of level `level`. Smoother bytes are
  * 3 values + 1 tag byte per updated cell, residual bytes 3 FP64 values + 1
  * tag byte per cell. Overwrites the level's work vectors. */

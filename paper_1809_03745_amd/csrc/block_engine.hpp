@@ -73,7 +73,7 @@ __device__ void be_rb(const BLev<T>& L, T* __restrict__ x, const T* __restrict__
     if (p > 1) continue;
     T dg;
     const T off = template_apply<T, DIM>(x, L.tp, i, j, k, c, p, dg);
-    x[c] = (b[c] - off) / dg;
+    x[c] = (b[c] - off) * (T(1) / dg);
   }
   __syncthreads();
 }
@@ -251,7 +251,7 @@ struct BBox {
   const int32_t* iobj;
   const double* icobj;
   const double* icsig;
-  Tmpl<double> dat;      // regular cells: b -= dat.cb[f][p] on touched faces
+  Tmpl<double> dat;      // regular cells: b -= dat.CB(f, p) on touched faces
   double fv[6];
   const double* objv;
   // BiCGStab work vectors (FP64, N + N2 each): r, rh, p, v, ph, s, sh, t
@@ -307,13 +307,13 @@ __device__ void be_rhs(const BLev<double>& F, const Tmpl<double>& dat, const dou
     const int j = jk % ny;
     const int k = DIM == 3 ? jk / ny : 0;
     double v = rho[c];
-    if (i == 0) v -= dat.cb[0][p];
-    if (i == nx - 1) v -= dat.cb[1][p];
-    if (j == 0) v -= dat.cb[2][p];
-    if (j == ny - 1) v -= dat.cb[3][p];
+    if (i == 0) v -= dat.CB(0, p);
+    if (i == nx - 1) v -= dat.CB(1, p);
+    if (j == 0) v -= dat.CB(2, p);
+    if (j == ny - 1) v -= dat.CB(3, p);
     if (DIM == 3) {
-      if (k == 0) v -= dat.cb[4][p];
-      if (k == F.n[2] - 1) v -= dat.cb[5][p];
+      if (k == 0) v -= dat.CB(4, p);
+      if (k == F.n[2] - 1) v -= dat.CB(5, p);
     }
     b[c] = v;
   }

@@ -23,6 +23,12 @@ struct Tmpl {
   T d0[2];
   T cb[6][2];
   int n[3];
+  // phase-selected constants: a select between the two values keeps them in
+  // registers (indexing by a runtime phase would read the argument block
+  // from memory inside the loops and stall on every outstanding load)
+  __device__ __forceinline__ T CO(int p) const { return p ? coff[1] : coff[0]; }
+  __device__ __forceinline__ T D0(int p) const { return p ? d0[1] : d0[0]; }
+  __device__ __forceinline__ T CB(int f, int p) const { return p ? cb[f][1] : cb[f][0]; }
 };
 
 constexpr int kBlock = 256;
@@ -35,18 +41,31 @@ __device__ __forceinline__ T template_apply(const T* __restrict__ x, const Tmpl<
                                             int64_t c, int p, T& diag) {
   const int nx = tp.n[0], ny = tp.n[1];
   T s = 0;
-  T dg = tp.d0[p];
-  if (i > 0) s += x[c - 1]; else dg += tp.cb[0][p];
-  if (i < nx - 1) s += x[c + 1]; else dg += tp.cb[1][p];
-  if (j > 0) s += x[c - nx]; else dg += tp.cb[2][p];
-  if (j < ny - 1) s += x[c + nx]; else dg += tp.cb[3][p];
+  T dg = tp.D0(p);
+  if (i > 0) s += x[c - 1]; else dg += tp.CB(0, p);
+  if (i < nx - 1) s += x[c + 1]; else dg += tp.CB(1, p);
+  if (j > 0) s += x[c - nx]; else dg += tp.CB(2, p);
+  if (j < ny - 1) s += x[c + nx]; else dg += tp.CB(3, p);
   if (DIM == 3) {
     const int64_t sxy = (int64_t)nx * ny;
-    if (k > 0) s += x[c - sxy]; else dg += tp.cb[4][p];
-    if (k < tp.n[2] - 1) s += x[c + sxy]; else dg += tp.cb[5][p];
+    if (k > 0) s += x[c - sxy]; else dg += tp.CB(4, p);
+    if (k < tp.n[2] - 1) s += x[c + sxy]; else dg += tp.CB(5, p);
   }
   diag = dg;
-  return tp.coff[p] * s;
+  return tp.CO(p) * s;
+}
+
+// Gauss-Seidel update of a template cell: (b - coff * sum) times the
+// reciprocal of the diagonal. Every smoother kernel computes it this way, so
+// all sweep variants agree bitwise.
+template <typename T>
+__device__ __forceinline__ T tmpl_update_r(const Tmpl<T>& tp, int p, T bc, T s, T rdg) {
+  return (bc - tp.CO(p) * s) * rdg;
+}
+
+template <typename T>
+__device__ __forceinline__ T tmpl_update(const Tmpl<T>& tp, int p, T bc, T s, T dg) {
+  return tmpl_update_r<T>(tp, p, bc, s, T(1) / dg);
 }
 
 // Red/black Gauss-Seidel half-sweep over regular cells on a 3D launch grid:
@@ -66,7 +85,7 @@ __global__ void __launch_bounds__(kBlock) k_rb(const uint8_t* __restrict__ tag, 
   if (p > 1) return;
   T dg;
   const T off = template_apply<T, DIM>(x, tp, i, j, k, c, p, dg);
-  x[c] = (b[c] - off) / dg;
+  x[c] = (b[c] - off) * (T(1) / dg);
 }
 
 // Fused red+black sweep over regular cells, out of place (xin -> xout).
@@ -87,11 +106,6 @@ constexpr int kXCD = 8;
 __device__ __forceinline__ int64_t xcd_block(int64_t bid, int64_t nblocks) {
   if (nblocks % kXCD) return bid;
   return (bid % kXCD) * (nblocks / kXCD) + bid / kXCD;
-}
-
-template <typename T>
-__device__ __forceinline__ T tmpl_update(const Tmpl<T>& tp, int p, T bc, T s, T dg) {
-  return (bc - tp.coff[p] * s) / dg;
 }
 
 constexpr int kTileThreads = 512;
@@ -173,13 +187,13 @@ __global__ void __launch_bounds__(kTileThreads) k_rb_tile3(const uint8_t* __rest
     T v = O[oq];
     const int p = rt[u];
     if (p <= 1) {
-      T sum = 0, dg = tp.d0[p];
-      if (gx > 0) sum += O[oq - 1]; else dg += tp.cb[0][p];
-      if (gx < nx - 1) sum += O[oq + 1]; else dg += tp.cb[1][p];
-      if (gy > 0) sum += O[oq - OX]; else dg += tp.cb[2][p];
-      if (gy < ny - 1) sum += O[oq + OX]; else dg += tp.cb[3][p];
-      if (gz > 0) sum += O[oq - OX * OY]; else dg += tp.cb[4][p];
-      if (gz < nz - 1) sum += O[oq + OX * OY]; else dg += tp.cb[5][p];
+      T sum = 0, dg = tp.D0(p);
+      if (gx > 0) sum += O[oq - 1]; else dg += tp.CB(0, p);
+      if (gx < nx - 1) sum += O[oq + 1]; else dg += tp.CB(1, p);
+      if (gy > 0) sum += O[oq - OX]; else dg += tp.CB(2, p);
+      if (gy < ny - 1) sum += O[oq + OX]; else dg += tp.CB(3, p);
+      if (gz > 0) sum += O[oq - OX * OY]; else dg += tp.CB(4, p);
+      if (gz < nz - 1) sum += O[oq + OX * OY]; else dg += tp.CB(5, p);
       v = tmpl_update<T>(tp, p, rb[u], sum, dg);
     }
     R[q] = v;
@@ -196,13 +210,13 @@ __global__ void __launch_bounds__(kTileThreads) k_rb_tile3(const uint8_t* __rest
     T v = R[rq];
     const int p = bt[u];
     if (p <= 1) {
-      T sum = 0, dg = tp.d0[p];
-      if (gx > 0) sum += R[rq - 1]; else dg += tp.cb[0][p];
-      if (gx < nx - 1) sum += R[rq + 1]; else dg += tp.cb[1][p];
-      if (gy > 0) sum += R[rq - RX]; else dg += tp.cb[2][p];
-      if (gy < ny - 1) sum += R[rq + RX]; else dg += tp.cb[3][p];
-      if (gz > 0) sum += R[rq - RX * RY]; else dg += tp.cb[4][p];
-      if (gz < nz - 1) sum += R[rq + RX * RY]; else dg += tp.cb[5][p];
+      T sum = 0, dg = tp.D0(p);
+      if (gx > 0) sum += R[rq - 1]; else dg += tp.CB(0, p);
+      if (gx < nx - 1) sum += R[rq + 1]; else dg += tp.CB(1, p);
+      if (gy > 0) sum += R[rq - RX]; else dg += tp.CB(2, p);
+      if (gy < ny - 1) sum += R[rq + RX]; else dg += tp.CB(3, p);
+      if (gz > 0) sum += R[rq - RX * RY]; else dg += tp.CB(4, p);
+      if (gz < nz - 1) sum += R[rq + RX * RY]; else dg += tp.CB(5, p);
       v = tmpl_update<T>(tp, p, bb[u], sum, dg);
     }
     xout[gx + (int64_t)nx * gy + sxy * gz] = v;
@@ -285,11 +299,11 @@ __global__ void __launch_bounds__(kTileThreads) k_rb_tile2(const uint8_t* __rest
     T v = O[oq];
     const int p = rt[u];
     if (p <= 1) {
-      T sum = 0, dg = tp.d0[p];
-      if (gx > 0) sum += O[oq - 1]; else dg += tp.cb[0][p];
-      if (gx < nx - 1) sum += O[oq + 1]; else dg += tp.cb[1][p];
-      if (gy > 0) sum += O[oq - OX]; else dg += tp.cb[2][p];
-      if (gy < ny - 1) sum += O[oq + OX]; else dg += tp.cb[3][p];
+      T sum = 0, dg = tp.D0(p);
+      if (gx > 0) sum += O[oq - 1]; else dg += tp.CB(0, p);
+      if (gx < nx - 1) sum += O[oq + 1]; else dg += tp.CB(1, p);
+      if (gy > 0) sum += O[oq - OX]; else dg += tp.CB(2, p);
+      if (gy < ny - 1) sum += O[oq + OX]; else dg += tp.CB(3, p);
       v = tmpl_update<T>(tp, p, rb[u], sum, dg);
     }
     R[q] = v;
@@ -306,11 +320,11 @@ __global__ void __launch_bounds__(kTileThreads) k_rb_tile2(const uint8_t* __rest
     T v = R[rq];
     const int p = bt[u];
     if (p <= 1) {
-      T sum = 0, dg = tp.d0[p];
-      if (gx > 0) sum += R[rq - 1]; else dg += tp.cb[0][p];
-      if (gx < nx - 1) sum += R[rq + 1]; else dg += tp.cb[1][p];
-      if (gy > 0) sum += R[rq - RX]; else dg += tp.cb[2][p];
-      if (gy < ny - 1) sum += R[rq + RX]; else dg += tp.cb[3][p];
+      T sum = 0, dg = tp.D0(p);
+      if (gx > 0) sum += R[rq - 1]; else dg += tp.CB(0, p);
+      if (gx < nx - 1) sum += R[rq + 1]; else dg += tp.CB(1, p);
+      if (gy > 0) sum += R[rq - RX]; else dg += tp.CB(2, p);
+      if (gy < ny - 1) sum += R[rq + RX]; else dg += tp.CB(3, p);
       v = tmpl_update<T>(tp, p, bb[u], sum, dg);
     }
     xout[gx + (int64_t)nx * gy] = v;
@@ -318,6 +332,266 @@ __global__ void __launch_bounds__(kTileThreads) k_rb_tile2(const uint8_t* __rest
   const int64_t N = (int64_t)nx * ny;
   for (int64_t q = (int64_t)blockIdx.x * NT + tid; q < nsec; q += nblocks * NT) xout[N + q] = xin[N + q];
 }
+
+// Fused red+black sweep in 3D, out of place (xin -> xout), marching along z.
+// A block owns a TX x TY column of cells over KZ planes. It keeps five planes
+// of the (TX+4) x (TY+4) halo region in LDS (a ring of planes k-2 .. k+2).
+// Step k applies the red update to plane k over the tile plus a one-cell ring
+// (old black values only), then the black update to the tile of plane k-1
+// (red-updated values only) and writes plane k-1: exactly a red half-sweep
+// followed by a black half-sweep, with the same arithmetic as the split
+// kernels. While the black update runs, plane k+2 goes from registers to LDS
+// and plane k+4 is requested from memory, so each load has two steps to
+// arrive; two barriers per step. Ring cells and the two extra planes at each
+// end of the z range are recomputed by the neighbouring blocks from the same
+// old values, so blocks never exchange data. Threads take cells of one colour
+// at a time (no idle lanes): each of the TX*TY/2 threads owns one black tile
+// cell and its red partner. Out-of-box halo entries hold 0, so the neighbour
+// sums need no masks; the in-plane boundary terms of the diagonal are folded
+// into per-thread reciprocal diagonals once, and only planes at the z faces
+// take the general path. (Written without lambdas so that every per-thread
+// table stays in registers.)
+template <typename T>
+__device__ __forceinline__ T zm_update_general(const T* vm, const T* vc, const T* vp, int oq, int OX, int gx,
+                                               int gy, int z, int nx, int ny, int nz, const T* tc, T bc) {
+  const T w = vc[oq - 1], e = vc[oq + 1], so = vc[oq - OX], no = vc[oq + OX], dn = vm[oq], up = vp[oq];
+  T s = 0, dg = tc[1];
+  s += gx > 0 ? w : T(0);
+  dg += gx > 0 ? T(0) : tc[2];
+  s += gx < nx - 1 ? e : T(0);
+  dg += gx < nx - 1 ? T(0) : tc[3];
+  s += gy > 0 ? so : T(0);
+  dg += gy > 0 ? T(0) : tc[4];
+  s += gy < ny - 1 ? no : T(0);
+  dg += gy < ny - 1 ? T(0) : tc[5];
+  s += z > 0 ? dn : T(0);
+  dg += z > 0 ? T(0) : tc[6];
+  s += z < nz - 1 ? up : T(0);
+  dg += z < nz - 1 ? T(0) : tc[7];
+  return (bc - tc[0] * s) * (T(1) / dg);
+}
+
+template <typename T>
+__device__ __forceinline__ T zm_update_inner(const T* vm, const T* vc, const T* vp, int oq, int OX, T co, T bc,
+                                             T rdg) {
+  T s = vc[oq - 1];
+  s += vc[oq + 1];
+  s += vc[oq - OX];
+  s += vc[oq + OX];
+  s += vm[oq];
+  s += vp[oq];
+  return (bc - co * s) * rdg;
+}
+
+template <typename T>
+__device__ __forceinline__ T zm_inplane_rdg(int gx, int gy, int nx, int ny, const T* tc) {
+  T dg = tc[1];
+  dg += gx > 0 ? T(0) : tc[2];
+  dg += gx < nx - 1 ? T(0) : tc[3];
+  dg += gy > 0 ? T(0) : tc[4];
+  dg += gy < ny - 1 ? T(0) : tc[5];
+  return T(1) / dg;
+}
+
+template <typename T, int TX, int TY, int KZ>
+__global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restrict__ tag,
+                                                      const T* __restrict__ xin, T* __restrict__ xout,
+                                                      const T* __restrict__ b, Tmpl<T> tp, int64_t nsec) {
+  constexpr int NT = TX * TY / 2;
+  constexpr int OX = TX + 4, OY = TY + 4, NO = OX * OY;      // old-value halo region
+  constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;      // red ring region
+  constexpr int NRED = (RX / 2) * RY;                        // red cells of the ring region
+  constexpr int UO = (NO + NT - 1) / NT, UR = (NR + NT - 1) / NT;
+  static_assert(TX % 2 == 0, "tile width must be even");
+  static_assert(NRED <= 2 * NT, "two red cells per thread at most");
+  __shared__ T V[5][NO];
+  __shared__ T Bs[4][NR];
+  __shared__ uint8_t Ts[4][NR];
+  // the template constants per phase (coff, d0, cb[0..5]): a phase chosen per
+  // cell then reads LDS instead of the argument block in memory
+  __shared__ T TC[2][8];
+  const int nx = tp.n[0], ny = tp.n[1], nz = tp.n[2];
+  const int bx = (nx + TX - 1) / TX, by = (ny + TY - 1) / TY;
+  const int64_t nblocks = (int64_t)gridDim.x;
+  const int64_t t = xcd_block(blockIdx.x, nblocks);
+  const int x0 = (int)(t % bx) * TX, y0 = (int)((t / bx) % by) * TY;
+  const int z0 = (int)(t / ((int64_t)bx * by)) * KZ;
+  const int z1 = min(z0 + KZ, nz);
+  const int tid = threadIdx.x;
+  const int64_t sxy = (int64_t)nx * ny;
+  if (tid < 16) {
+    const int p = tid >> 3, j = tid & 7;
+    TC[p][j] = j == 0 ? tp.coff[p] : (j == 1 ? tp.d0[p] : tp.cb[j - 2][p]);
+  }
+  __syncthreads();
+
+  // per-thread tables, fixed over the march: in-plane offsets of the loaded
+  // halo cells and whether they lie in the box
+  int offo[UO], offr[UR];
+  uint32_t ino = 0, inr = 0;
+#pragma unroll
+  for (int u = 0; u < UO; ++u) {
+    const int q = tid + u * NT;
+    const int gx = x0 - 2 + q % OX, gy = y0 - 2 + q / OX;
+    const bool ok = q < NO && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    offo[u] = ok ? gx + nx * gy : 0;
+    ino |= (uint32_t)ok << u;
+  }
+#pragma unroll
+  for (int u = 0; u < UR; ++u) {
+    const int q = tid + u * NT;
+    const int gx = x0 - 1 + q % RX, gy = y0 - 1 + q / RX;
+    const bool ok = q < NR && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    offr[u] = ok ? gx + nx * gy : 0;
+    inr |= (uint32_t)ok << u;
+  }
+  // the (up to two) red cells of this thread: (gx0 + par, gy) with
+  // par = (cpar + k) & 1, and their reciprocal in-plane diagonals
+  int rgx0[2], rgy[2], roq0[2], rrq0[2], rcp[2];
+  T r00[2], r01[2], r10[2], r11[2];                  // [parity][phase]
+  bool ract[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int q = tid + u * NT;
+    const int ry = q / (RX / 2), m = q % (RX / 2);
+    ract[u] = q < NRED;
+    rgy[u] = y0 - 1 + ry;
+    rgx0[u] = x0 - 1 + 2 * m;
+    roq0[u] = (2 * m + 1) + OX * (ry + 1);
+    rrq0[u] = (2 * m) + RX * ry;
+    rcp[u] = (x0 - 1 + rgy[u]) & 1;
+    r00[u] = zm_inplane_rdg<T>(rgx0[u], rgy[u], nx, ny, TC[0]);
+    r01[u] = zm_inplane_rdg<T>(rgx0[u], rgy[u], nx, ny, TC[1]);
+    r10[u] = zm_inplane_rdg<T>(rgx0[u] + 1, rgy[u], nx, ny, TC[0]);
+    r11[u] = zm_inplane_rdg<T>(rgx0[u] + 1, rgy[u], nx, ny, TC[1]);
+  }
+  // the black cell and its red partner: the pair (gxa, gxa + 1)
+  const int bry = tid / (TX / 2), bm = tid % (TX / 2);
+  const int bgy = y0 + bry, bgxa = x0 + 2 * bm;
+  const int boq0 = (2 * bm + 2) + OX * (bry + 2), brq0 = (2 * bm + 1) + RX * (bry + 1);
+  const int bcp = (bgxa + bgy) & 1;
+  const T b00 = zm_inplane_rdg<T>(bgxa + 1, bgy, nx, ny, TC[0]);   // parity 0: black at gxa + 1
+  const T b01 = zm_inplane_rdg<T>(bgxa + 1, bgy, nx, ny, TC[1]);
+  const T b10 = zm_inplane_rdg<T>(bgxa, bgy, nx, ny, TC[0]);       // parity 1: black at gxa
+  const T b11 = zm_inplane_rdg<T>(bgxa, bgy, nx, ny, TC[1]);
+
+  // planes in flight: raw loaded values (lanes outside the box read a valid
+  // address; the value is discarded when stored, so no load is waited for
+  // before the step that stores it)
+  T Aov[UO], Abv[UR], Bov[UO], Bbv[UR];
+  uint8_t Atv[UR], Btv[UR];
+
+#define ZM_LOAD(P, z)                                                        \
+  {                                                                          \
+    const int zz_ = (z);                                                     \
+    const int64_t zoff_ = sxy * (zz_ >= 0 && zz_ < nz ? zz_ : 0);            \
+    _Pragma("unroll") for (int u = 0; u < UO; ++u) P##ov[u] = xin[zoff_ + offo[u]]; \
+    _Pragma("unroll") for (int u = 0; u < UR; ++u) {                         \
+      P##bv[u] = b[zoff_ + offr[u]];                                         \
+      P##tv[u] = tag[zoff_ + offr[u]];                                       \
+    }                                                                        \
+  }
+#define ZM_STORE(P, z)                                                       \
+  {                                                                          \
+    const int zz_ = (z);                                                     \
+    const bool zin_ = zz_ >= 0 && zz_ < nz;                                  \
+    T* v_ = V[(zz_ + 10) % 5];                                               \
+    T* bs_ = Bs[(zz_ + 8) & 3];                                              \
+    uint8_t* ts_ = Ts[(zz_ + 8) & 3];                                        \
+    _Pragma("unroll") for (int u = 0; u < UO; ++u) {                         \
+      const int q = tid + u * NT;                                            \
+      if (q < NO) v_[q] = (zin_ && ((ino >> u) & 1)) ? P##ov[u] : T(0);      \
+    }                                                                        \
+    _Pragma("unroll") for (int u = 0; u < UR; ++u) {                         \
+      const int q = tid + u * NT;                                            \
+      if (q < NR) {                                                          \
+        const bool ok_ = zin_ && ((inr >> u) & 1);                           \
+        bs_[q] = ok_ ? P##bv[u] : T(0);                                      \
+        ts_[q] = ok_ ? P##tv[u] : (uint8_t)3;                                \
+      }                                                                      \
+    }                                                                        \
+  }
+#define ZM_STEP(P, kk)                                                       \
+  {                                                                          \
+    const int k = (kk);                                                      \
+    if (k >= 0 && k < nz) { /* red update of plane k over the ring region */ \
+      const bool zint = k > 0 && k < nz - 1;                                 \
+      const T* vm = V[(k + 9) % 5];                                          \
+      T* vc = V[(k + 10) % 5];                                               \
+      const T* vp = V[(k + 11) % 5];                                         \
+      const T* bs = Bs[(k + 8) & 3];                                         \
+      const uint8_t* ts = Ts[(k + 8) & 3];                                   \
+      _Pragma("unroll") for (int u = 0; u < 2; ++u) {                        \
+        if (ract[u]) {                                                       \
+          const int par = (rcp[u] + k) & 1;                                  \
+          const int gx = rgx0[u] + par, oq = roq0[u] + par, rq = rrq0[u] + par; \
+          const int pc = tclass(ts[rq]);                                     \
+          const int p = pc & 1;                                              \
+          T v;                                                               \
+          if (zint) {                                                        \
+            const T r = par ? (p ? r11[u] : r10[u]) : (p ? r01[u] : r00[u]); \
+            v = zm_update_inner<T>(vm, vc, vp, oq, OX, TC[p][0], bs[rq], r); \
+          } else {                                                           \
+            v = zm_update_general<T>(vm, vc, vp, oq, OX, gx, rgy[u], k, nx, ny, nz, TC[p], bs[rq]); \
+          }                                                                  \
+          if (pc <= 1) vc[oq] = v;                                           \
+        }                                                                    \
+      }                                                                      \
+    }                                                                        \
+    __syncthreads();                                                         \
+    const int kb = k - 1;                                                    \
+    if (kb >= z0 && kb < z1) { /* black update of plane k-1, and its write */ \
+      const T* vm = V[(kb + 9) % 5];                                         \
+      const T* vc = V[(kb + 10) % 5];                                        \
+      const T* vp = V[(kb + 11) % 5];                                        \
+      const T* bs = Bs[(kb + 8) & 3];                                        \
+      const uint8_t* ts = Ts[(kb + 8) & 3];                                  \
+      const int par = (bcp + kb) & 1; /* 1: gxa is black */                  \
+      const int sh = par ? 0 : 1;                                            \
+      const int gx = bgxa + sh, oq = boq0 + sh, rq = brq0 + sh;              \
+      const int pc = tclass(ts[rq]);                                         \
+      const int p = pc & 1;                                                  \
+      T vu;                                                                  \
+      if (kb > 0 && kb < nz - 1) {                                           \
+        const T r = par ? (p ? b11 : b10) : (p ? b01 : b00);                 \
+        vu = zm_update_inner<T>(vm, vc, vp, oq, OX, TC[p][0], bs[rq], r);    \
+      } else {                                                               \
+        vu = zm_update_general<T>(vm, vc, vp, oq, OX, gx, bgy, kb, nx, ny, nz, TC[p], bs[rq]); \
+      }                                                                      \
+      const T vb = pc <= 1 ? vu : vc[oq];                                    \
+      const T vr = vc[oq + (par ? 1 : -1)]; /* the red partner, updated */   \
+      if (bgy < ny) {                                                        \
+        T* out = xout + (int64_t)nx * bgy + sxy * kb;                        \
+        if (bgxa < nx) out[bgxa] = par ? vb : vr;                            \
+        if (bgxa + 1 < nx) out[bgxa + 1] = par ? vr : vb;                    \
+      }                                                                      \
+    }                                                                        \
+    if (k + 2 <= z1 + 1) ZM_STORE(P, k + 2);                                 \
+    if (k + 4 <= z1 + 1) ZM_LOAD(P, k + 4);                                  \
+    __syncthreads();                                                         \
+  }
+
+  ZM_LOAD(A, z0 - 2);
+  ZM_STORE(A, z0 - 2);
+  ZM_LOAD(A, z0 - 1);
+  ZM_STORE(A, z0 - 1);
+  ZM_LOAD(A, z0);
+  ZM_STORE(A, z0);
+  ZM_LOAD(A, z0 + 1);   // planes z0+1, z0+3, ... travel in A; z0+2, z0+4, ... in B
+  ZM_LOAD(B, z0 + 2);
+  __syncthreads();
+  for (int k2 = z0 - 1; k2 <= z1; k2 += 2) {
+    ZM_STEP(A, k2);
+    if (k2 + 1 <= z1) ZM_STEP(B, k2 + 1);
+  }
+#undef ZM_STEP
+#undef ZM_STORE
+#undef ZM_LOAD
+  // second-phase unknowns are not touched by this sweep: copy them through
+  const int64_t N = sxy * nz;
+  for (int64_t q = (int64_t)blockIdx.x * NT + tid; q < nsec; q += nblocks * NT) xout[N + q] = xin[N + q];
+}
+
 
 // Explicit (irregular) rows are processed by sub-wavefronts of kSub lanes:
 // each lane takes every kSub-th entry of the row (coalesced column/value
@@ -629,13 +903,13 @@ __global__ void __launch_bounds__(kBlock) k_rhs_reg(const uint8_t* __restrict__ 
   if (p == 2) return;
   double v = rho[c];
   // dat.cb[f][p] holds dat[f][p] * value_f
-  if (i == 0) v -= dat.cb[0][p];
-  if (i == dat.n[0] - 1) v -= dat.cb[1][p];
-  if (j == 0) v -= dat.cb[2][p];
-  if (j == dat.n[1] - 1) v -= dat.cb[3][p];
+  if (i == 0) v -= dat.CB(0, p);
+  if (i == dat.n[0] - 1) v -= dat.CB(1, p);
+  if (j == 0) v -= dat.CB(2, p);
+  if (j == dat.n[1] - 1) v -= dat.CB(3, p);
   if (DIM == 3) {
-    if (k == 0) v -= dat.cb[4][p];
-    if (k == dat.n[2] - 1) v -= dat.cb[5][p];
+    if (k == 0) v -= dat.CB(4, p);
+    if (k == dat.n[2] - 1) v -= dat.CB(5, p);
   }
   b[c] = v;
 }
@@ -684,15 +958,15 @@ __global__ void __launch_bounds__(kBlock) k_efield_reg(const uint8_t* __restrict
   const double xc = x[c];
   for (int d = 0; d < DIM; ++d) {
     double glo, ghi;
-    // ga.cb[f][p] = closure coefficient on phi, gbv.cb[f][p] = coefficient * value
+    // ga.CB(f, p) = closure coefficient on phi, gbv.CB(f, p) = coefficient * value
     if (idx[d] > 0)
       glo = (xc - x[c - stride[d]]) * inv_h;
     else
-      glo = -(ga.cb[2 * d][p] * xc + gbv.cb[2 * d][p]);
+      glo = -(ga.CB(2 * d, p) * xc + gbv.CB(2 * d, p));
     if (idx[d] < ga.n[d] - 1)
       ghi = (x[c + stride[d]] - xc) * inv_h;
     else
-      ghi = ga.cb[2 * d + 1][p] * xc + gbv.cb[2 * d + 1][p];
+      ghi = ga.CB(2 * d + 1, p) * xc + gbv.CB(2 * d + 1, p);
     E[d * N + c] = -0.5 * (glo + ghi);
   }
 }

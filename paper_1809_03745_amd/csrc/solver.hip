@@ -88,7 +88,9 @@ struct DevLevel {
   std::vector<int32_t> cls_ptr;
   int64_t n_ns = 0, n_np = 0;
   bool fused = false;              // smoother variant chosen for this level
-  double tune_split_ms = 0, tune_fused_ms = 0;
+  int fvar = 0;                    // fused variant: 0 3D/2D tile, 1 z-marching (3D)
+  int zmcfg = 0;                   // z-marching tile configuration
+  double tune_split_ms = 0, tune_fused_ms = 0, tune_zm_ms = 0;
   Tmpl<double> t64;
   Tmpl<float> t32;
   // vectors
@@ -223,9 +225,32 @@ static bool fused_ok(const DevLevel& l) {
   return l.dim == 3 ? (l.N >= 32768 && l.n[0] >= 32) : (l.N >= 65536 && l.n[0] >= 64);
 }
 
+// z-marching sweep configurations (tile width x height x planes per block);
+// the setup autotuner picks one per level
+constexpr int kZMConfigs = 4;
+
+template <typename T, int TX, int TY, int KZ>
+static void launch_zm_cfg(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s) {
+  const int64_t nb = (int64_t)((l.n[0] + TX - 1) / TX) * ((l.n[1] + TY - 1) / TY) * ((l.n[2] + KZ - 1) / KZ);
+  hipLaunchKernelGGL((k_rb_zm3<T, TX, TY, KZ>), dim3((unsigned)nb), dim3(TX * TY / 2), 0, s, l.tag.p, xin, xout, b,
+                     tp, l.N2);
+}
+
+template <typename T>
+static void launch_zm(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s) {
+  switch (l.zmcfg) {
+    case 1: launch_zm_cfg<T, 64, 16, 32>(l, xin, xout, b, tp, s); break;
+    case 2: launch_zm_cfg<T, 32, 16, 32>(l, xin, xout, b, tp, s); break;
+    case 3: launch_zm_cfg<T, 64, 8, 16>(l, xin, xout, b, tp, s); break;
+    default: launch_zm_cfg<T, 64, 8, 32>(l, xin, xout, b, tp, s); break;
+  }
+}
+
 template <typename T>
 static void launch_fused(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s) {
-  if (l.dim == 3) {
+  if (l.dim == 3 && l.fvar == 1) {
+    launch_zm<T>(l, xin, xout, b, tp, s);
+  } else if (l.dim == 3) {
     const int64_t nb = (int64_t)((l.n[0] + kTX - 1) / kTX) * ((l.n[1] + kTY - 1) / kTY) * ((l.n[2] + kTZ - 1) / kTZ);
     hipLaunchKernelGGL((k_rb_tile3<T>), dim3((unsigned)nb), dim3(kTileThreads), 0, s, l.tag.p, xin, xout, b, tp, l.N2);
   } else {
@@ -335,10 +360,11 @@ static void upload_tail(DevProblem& D, hipStream_t s) {
   HIPCHECK(hipStreamSynchronize(s));
 }
 
-// Smoother autotuner: on levels where the fused tile sweep applies, time one
-// full sweep of each variant (split red and black half-sweeps vs the fused
-// tile kernel) with HIP events on zeroed vectors and keep the faster one.
-// mode 1 forces split sweeps, mode 2 the fused sweep where it applies.
+// Smoother autotuner: on levels where the fused sweeps apply, time one full
+// sweep of each variant (split red and black half-sweeps, the fused tile
+// kernel, and in 3D the z-marching kernel) with HIP events on zeroed vectors
+// and keep the fastest. mode 1 forces split sweeps, mode 2 the fused tile
+// sweep and mode 3 the z-marching sweep (3D; tile in 2D) where they apply.
 template <typename T>
 static double time_sweep(DevLevel& l, bool fused, T* x, T* xa, const T* b, const Tmpl<T>& tp, hipStream_t s) {
   hipEvent_t e0, e1;
@@ -382,13 +408,33 @@ static void tune_level(DevLevel& l, T* x, T* xa, T* b, const Tmpl<T>& tp, int mo
     l.fused = false;
     return;
   }
-  if (mode == 2) {
+  if (mode == 2 || mode == 3) {
     l.fused = true;
+    l.fvar = (mode == 3 && l.dim == 3) ? 1 : 0;
     return;
   }
   l.tune_split_ms = time_sweep<T>(l, false, x, xa, b, tp, s);
+  l.fvar = 0;
   l.tune_fused_ms = time_sweep<T>(l, true, x, xa, b, tp, s);
-  l.fused = l.tune_fused_ms < l.tune_split_ms;
+  double best = l.tune_fused_ms;
+  if (l.dim == 3) {
+    l.fvar = 1;
+    double zbest = 1e30;
+    int zc = 0;
+    for (int c = 0; c < kZMConfigs; ++c) {
+      l.zmcfg = c;
+      const double ms = time_sweep<T>(l, true, x, xa, b, tp, s);
+      if (ms < zbest) {
+        zbest = ms;
+        zc = c;
+      }
+    }
+    l.zmcfg = zc;
+    l.tune_zm_ms = zbest;
+    l.fvar = l.tune_zm_ms < l.tune_fused_ms ? 1 : 0;
+    best = std::min(best, l.tune_zm_ms);
+  }
+  l.fused = best < l.tune_split_ms;
 }
 
 static void tune_smoother(DevLevel& l, bool mixed, int mode, hipStream_t s) {
@@ -941,6 +987,39 @@ static void upload_batch_views(ebmg_batch_s* Bt, hipStream_t s) {
   Bt->bytes += by;
   HIPCHECK(hipStreamSynchronize(s));
 }
+// Template-cell sweeps only (no explicit rows), for ebmg_smooth.
+template <typename T>
+static void template_sweeps(DevLevel& l, int variant, int sweeps, T* x, const T* b, hipStream_t s) {
+  const Tmpl<T>& tp = Vec<T>::t(l);
+  if (variant > 1) {
+    const bool f0 = l.fused;
+    const int v0 = l.fvar, c0 = l.zmcfg;
+    l.fused = true;
+    l.fvar = variant >= 3 ? 1 : 0;
+    if (variant >= 3) l.zmcfg = variant - 3;
+    T* cur = x;
+    T* alt = Vec<T>::xa(l);
+    for (int it = 0; it < sweeps; ++it) {
+      launch_fused<T>(l, cur, alt, b, tp, s);
+      std::swap(cur, alt);
+    }
+    l.fused = f0;
+    l.fvar = v0;
+    l.zmcfg = c0;
+    if (cur != x) HIPCHECK(hipMemcpyAsync(x, cur, sizeof(T) * (l.N + l.N2), hipMemcpyDeviceToDevice, s));
+  } else {
+    const Shape sh = shape3((l.n[0] + 1) / 2, l.n[1], l.dim == 3 ? l.n[2] : 1);
+    for (int it = 0; it < sweeps; ++it)
+      for (int colour = 0; colour < 2; ++colour) {
+        if (l.dim == 3)
+          hipLaunchKernelGGL((k_rb<T, 3>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
+        else
+          hipLaunchKernelGGL((k_rb<T, 2>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
+      }
+  }
+  HIPCHECK(hipGetLastError());
+}
+
 }  // namespace ebmg
 
 // ---------------------------------------------------------------------------
@@ -1048,7 +1127,7 @@ static ebmg_status parse_options(const ebmg_options* opt, int nobj, ebmg::Option
   out.bottom_max = o.bottom_max_dof > 0 ? o.bottom_max_dof : 600;
   if (o.precision != EBMG_FP64 && o.precision != EBMG_MIXED) return EBMG_ERR_ARG;
   if (!(o.beta != 0.0) || !std::isfinite(o.beta)) return EBMG_ERR_ARG;
-  if (o.krylov < 0 || o.krylov > 2 || o.smoother < 0 || o.smoother > 2 || o.tail < 0 || o.tail > 2)
+  if (o.krylov < 0 || o.krylov > 2 || o.smoother < 0 || o.smoother > 3 || o.tail < 0 || o.tail > 2)
     return EBMG_ERR_ARG;
   for (int k = 0; k < 5; ++k)
     if (o.reserved[k] != 0) return EBMG_ERR_ARG;
@@ -1148,9 +1227,9 @@ ebmg_status ebmg_query_tuning(ebmg_problem pb, int32_t level, int32_t* fused, do
     return EBMG_OK;
   }
   const DevLevel& l = pb->dev.lv[level];
-  if (fused) *fused = l.fused ? 1 : 0;
+  if (fused) *fused = l.fused ? (l.fvar ? 2 + l.zmcfg : 1) : 0;
   if (split_ms) *split_ms = l.tune_split_ms;
-  if (fused_ms) *fused_ms = l.tune_fused_ms;
+  if (fused_ms) *fused_ms = l.fvar == 1 ? l.tune_zm_ms : l.tune_fused_ms;
   return EBMG_OK;
 }
 
@@ -1291,6 +1370,33 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
   });
 }
 
+ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t sweeps, double* x,
+                        const double* b) {
+  if (!pb || !x || !b || sweeps < 0 || variant < 1 || variant > 2 + kZMConfigs) return EBMG_ERR_ARG;
+  if (!pb->on_device) return EBMG_ERR_DEVICE;
+  if (level < 0 || level >= (int32_t)pb->dev.lv.size()) return EBMG_ERR_ARG;
+  return guard(pb->ctx, [&]() -> ebmg_status {
+    HIPCHECK(hipSetDevice(pb->ctx->device));
+    DevLevel& L = pb->dev.lv[level];
+    hipStream_t s = pb->ctx->stream;
+    const bool mixed = pb->host->opt.precision == EBMG_MIXED;
+    if (variant > 1 && (mixed ? !L.xa32.p : !L.xa64.p)) throw ArgError("this level has no fused sweep");
+    if (variant >= 3 && L.dim != 3) throw ArgError("the z-marching sweep is 3D only");
+    const int64_t nd = L.N + L.N2;
+    if (mixed) {
+      hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(nd)), dim3(kBlock), 0, s, x, L.x32.p, nd);
+      hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(nd)), dim3(kBlock), 0, s, b, L.b32.p, nd);
+      template_sweeps<float>(L, variant, sweeps, L.x32.p, L.b32.p, s);
+      hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(nd)), dim3(kBlock), 0, s, L.x32.p, x, nd);
+    } else {
+      template_sweeps<double>(L, variant, sweeps, x, b, s);
+    }
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(s));
+    return EBMG_OK;
+  });
+}
+
 ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int32_t reps, double* avg_ms,
                              double* alg_bytes) {
   if (!pb || !avg_ms || reps <= 0) return EBMG_ERR_ARG;
@@ -1310,13 +1416,27 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
     double bytes = 0;
     const Shape shh = shape3((L.n[0] + 1) / 2, L.n[1], L.dim == 3 ? L.n[2] : 1);
     const Shape shf = shape3(L.n[0], L.n[1], L.dim == 3 ? L.n[2] : 1);
-    const bool fz = (which == 0 && L.fused) || which == 3;
+    if (which < 0 || which > 4) throw ArgError("unknown kernel id");
+    if (which >= 3 && (mixed ? !L.xa32.p : !L.xa64.p)) throw ArgError("this level has no fused sweep");
+    if (which == 4 && L.dim != 3) throw ArgError("the z-marching sweep is 3D only");
+    const bool fz = (which == 0 && L.fused) || which == 3 || which == 4;
     auto launch = [&](int colour) {
       if (fz) {
-        if (mixed)
-          launch_fused<float>(L, (colour & 1) ? L.xa32.p : L.x32.p, (colour & 1) ? L.x32.p : L.xa32.p, L.b32.p, L.t32, s);
-        else
-          launch_fused<double>(L, (colour & 1) ? L.xa64.p : L.x64.p, (colour & 1) ? L.x64.p : L.xa64.p, L.b64.p, L.t64, s);
+        if (mixed) {
+          float* xi = (colour & 1) ? L.xa32.p : L.x32.p;
+          float* xo = (colour & 1) ? L.x32.p : L.xa32.p;
+          if (which == 4)
+            launch_zm<float>(L, xi, xo, L.b32.p, L.t32, s);
+          else
+            launch_fused<float>(L, xi, xo, L.b32.p, L.t32, s);
+        } else {
+          double* xi = (colour & 1) ? L.xa64.p : L.x64.p;
+          double* xo = (colour & 1) ? L.x64.p : L.xa64.p;
+          if (which == 4)
+            launch_zm<double>(L, xi, xo, L.b64.p, L.t64, s);
+          else
+            launch_fused<double>(L, xi, xo, L.b64.p, L.t64, s);
+        }
         return;
       }
       if (which != 1) {
@@ -1338,8 +1458,6 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
           hipLaunchKernelGGL((k_resid_reg<double, 2, 0>), shf.g, shf.b, 0, s, L.tag.p, L.x64.p, L.b64.p, L.r64.p, L.t64);
       }
     };
-    if (which < 0 || which > 3) throw ArgError("unknown kernel id");
-    if (which == 3 && (mixed ? !L.xa32.p : !L.xa64.p)) throw ArgError("this level has no fused sweep");
     if (which == 1 && !L.x64.p) throw ArgError("no FP64 vectors on this level");
     if (which != 1) {
       // algorithmic bytes of one half-sweep: each updated cell reads x and b,

@@ -107,6 +107,7 @@ _sig("ebmg_solve", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int32, _vp
 _sig("ebmg_apply", C.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_efield", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_time_kernel", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp])
+_sig("ebmg_smooth", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _vp, _vp])
 _sig("ebmg_release", C.c_int, [_vp])
 _sig("ebmg_set_coefficients", C.c_int, [_vp, C.POINTER(Options), C.POINTER(DomainBC)])
 _sig("ebmg_setup_batch", C.c_int, [_vp, C.c_int32, C.POINTER(Box), C.POINTER(C.c_int32), C.POINTER(_vp),
@@ -121,7 +122,7 @@ EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_des
             "ebmg_export_geometry", "ebmg_export_operator", "ebmg_export_rhs",
             "ebmg_solve", "ebmg_apply", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
             "ebmg_setup_batch", "ebmg_query_batch", "ebmg_solve_batch", "ebmg_release_batch",
-            "ebmg_set_coefficients"]
+            "ebmg_set_coefficients", "ebmg_smooth"]
 
 
 def abi_version():
@@ -306,11 +307,16 @@ class Problem:
                        "ebmg_efield")
 
     def tuning(self, level):
-        """(fused chosen, split sweep ms, fused sweep ms) from the setup autotuner;
-        level -1: (first tail level or -1, V-cycle ms without tail, V-cycle ms chosen)."""
+        """(smoother variant: 0 split, 1 tile, 2 z-march; split sweep ms; chosen or
+        best fused sweep ms) from the setup autotuner; level -1: (first tail
+        level or -1, V-cycle ms without tail, V-cycle ms chosen)."""
         f, a, b = C.c_int32(), C.c_double(), C.c_double()
         self.ctx.check(_lib.ebmg_query_tuning(self.h, level, C.byref(f), C.byref(a), C.byref(b)), "tuning")
-        return (f.value if level == -1 else bool(f.value)), a.value, b.value
+        return f.value, a.value, b.value
+
+    def smooth(self, level, variant, sweeps, x, b):
+        """Template-cell red/black sweeps on level ``level`` (device FP64 x, b)."""
+        self.ctx.check(_lib.ebmg_smooth(self.h, level, variant, sweeps, _ptr(x), _ptr(b)), "ebmg_smooth")
 
     def time_kernel(self, which, level=0, reps=50):
         """(mean ms per launch, algorithmic bytes per launch) of a kernel."""

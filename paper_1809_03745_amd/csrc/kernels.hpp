@@ -656,6 +656,66 @@ __global__ void __launch_bounds__(kBlock) k_resid_reg(const uint8_t* __restrict_
   r[c] = MODE == 0 ? b[c] - ax : ax;
 }
 
+// Template rows of a 3D level marching along z (r = b - A x, MODE 1: r = A x):
+// each thread owns one (i, j) column of a block's 64 x 4 tile and walks KZ
+// planes, keeping x of planes k-1, k, k+1 in registers (each x value leaves
+// HBM once; the in-plane neighbours are cache hits) and requesting plane k+2,
+// b and the tag one step ahead. Same arithmetic and order as the grid-wide
+// kernel; explicit rows are left to k_resid_irr.
+constexpr int kRZX = 64, kRZY = 4, kRZ = 16;
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kRZX * kRZY) k_resid_zm3(const uint8_t* __restrict__ tag,
+                                                           const T* __restrict__ x, const T* __restrict__ b,
+                                                           T* __restrict__ r, Tmpl<T> tp) {
+  __shared__ T TC[2][8];
+  const int tid = threadIdx.x + kRZX * threadIdx.y;
+  if (tid < 16) {
+    const int p = tid >> 3, j = tid & 7;
+    TC[p][j] = j == 0 ? tp.coff[p] : (j == 1 ? tp.d0[p] : tp.cb[j - 2][p]);
+  }
+  __syncthreads();
+  const int nx = tp.n[0], ny = tp.n[1], nz = tp.n[2];
+  const int i = blockIdx.x * kRZX + threadIdx.x;
+  const int j = blockIdx.y * kRZY + threadIdx.y;
+  const int z0 = blockIdx.z * kRZ, z1 = min(z0 + kRZ, nz);
+  if (i >= nx || j >= ny) return;
+  const int64_t sxy = (int64_t)nx * ny;
+  const int64_t c0 = i + (int64_t)nx * j;
+  T xm = z0 > 0 ? x[c0 + sxy * (z0 - 1)] : T(0);
+  T xc = x[c0 + sxy * z0];
+  T xp = z0 + 1 < nz ? x[c0 + sxy * (z0 + 1)] : T(0);
+  uint8_t tg = tag[c0 + sxy * z0];
+  T bb = MODE == 0 ? b[c0 + sxy * z0] : T(0);
+  for (int k = z0; k < z1; ++k) {
+    const int64_t c = c0 + sxy * k;
+    // requests for the next step
+    const T xpp = k + 2 < nz ? x[c + 2 * sxy] : T(0);
+    const uint8_t tgn = k + 1 < z1 ? tag[c + sxy] : (uint8_t)3;
+    const T bbn = (MODE == 0 && k + 1 < z1) ? b[c + sxy] : T(0);
+    const int p = tclass(tg);
+    if (p == 3) {
+      r[c] = MODE == 0 ? T(0) : xc;
+    } else if (p <= 1) {
+      const T* tc = TC[p];
+      T s = 0, dg = tc[1];
+      if (i > 0) s += x[c - 1]; else dg += tc[2];
+      if (i < nx - 1) s += x[c + 1]; else dg += tc[3];
+      if (j > 0) s += x[c - nx]; else dg += tc[4];
+      if (j < ny - 1) s += x[c + nx]; else dg += tc[5];
+      if (k > 0) s += xm; else dg += tc[6];
+      if (k < nz - 1) s += xp; else dg += tc[7];
+      const T ax = dg * xc + tc[0] * s;
+      r[c] = MODE == 0 ? bb - ax : ax;
+    }
+    xm = xc;
+    xc = xp;
+    xp = xpp;
+    tg = tgn;
+    bb = bbn;
+  }
+}
+
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_resid_irr(int nrows, const int64_t* __restrict__ dof,
                                                       const int64_t* __restrict__ rp, const int32_t* __restrict__ col,

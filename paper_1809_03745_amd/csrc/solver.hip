@@ -614,14 +614,21 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
   HIPCHECK(hipGetLastError());
 }
 
+// 3D levels of at least this many cells take the z-marching residual kernel
+constexpr int64_t kResidZMMin = 1 << 18;
+
 template <typename T, int MODE>
 static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
   const Shape sh = shape3(l.n[0], l.n[1], l.dim == 3 ? l.n[2] : 1);
-  if (l.dim == 3)
+  if (l.dim == 3 && l.N >= kResidZMMin) {
+    const dim3 g((l.n[0] + kRZX - 1) / kRZX, (l.n[1] + kRZY - 1) / kRZY, (l.n[2] + kRZ - 1) / kRZ);
+    hipLaunchKernelGGL((k_resid_zm3<T, MODE>), g, dim3(kRZX, kRZY), 0, s, l.tag.p, x, b, r, tp);
+  } else if (l.dim == 3) {
     hipLaunchKernelGGL((k_resid_reg<T, 3, MODE>), sh.g, sh.b, 0, s, l.tag.p, x, b, r, tp);
-  else
+  } else {
     hipLaunchKernelGGL((k_resid_reg<T, 2, MODE>), sh.g, sh.b, 0, s, l.tag.p, x, b, r, tp);
+  }
   if (l.R > 0)
     hipLaunchKernelGGL((k_resid_irr<T, MODE>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R, l.irow_dof.p, l.rp.p,
                        l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, r);
@@ -1452,10 +1459,15 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
             hipLaunchKernelGGL((k_rb<double, 2>), shh.g, shh.b, 0, s, L.tag.p, L.x64.p, L.b64.p, L.t64, colour);
         }
       } else {
-        if (L.dim == 3)
+        if (L.dim == 3 && L.N >= kResidZMMin) {
+          const dim3 g((L.n[0] + kRZX - 1) / kRZX, (L.n[1] + kRZY - 1) / kRZY, (L.n[2] + kRZ - 1) / kRZ);
+          hipLaunchKernelGGL((k_resid_zm3<double, 0>), g, dim3(kRZX, kRZY), 0, s, L.tag.p, L.x64.p, L.b64.p,
+                             L.r64.p, L.t64);
+        } else if (L.dim == 3) {
           hipLaunchKernelGGL((k_resid_reg<double, 3, 0>), shf.g, shf.b, 0, s, L.tag.p, L.x64.p, L.b64.p, L.r64.p, L.t64);
-        else
+        } else {
           hipLaunchKernelGGL((k_resid_reg<double, 2, 0>), shf.g, shf.b, 0, s, L.tag.p, L.x64.p, L.b64.p, L.r64.p, L.t64);
+        }
       }
     };
     if (which == 1 && !L.x64.p) throw ArgError("no FP64 vectors on this level");

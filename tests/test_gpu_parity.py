@@ -254,3 +254,36 @@ def test_full_size_pin_plane_windows(ctx):
             r = (S.b - S.A @ xs[gi])[valid]
             assert np.abs(r).max() <= 1e-10 * info["r0_norm"]
         P2.release()
+
+
+def _ragged_box():
+    """A 72 x 56 x 80 Eddington box: large enough for the z-marching residual
+    kernel, with partial tiles in x and z."""
+    n = (72, 56, 80)
+    pr = W.eddington_coefficients(3, 8, 5.0)
+    pr.n = n
+    pr.h = 1.0 / 80
+    pr.lo = (0.0, 0.0, 0.0)
+    pr.rho = np.random.default_rng(8).normal(size=tuple(reversed(n)))
+    return pr
+
+
+@pytest.mark.parametrize("name", ["pin-plane64", "ragged-box"])
+def test_apply_parity_marching_residual(ctx, name):
+    _say("apply parity (z-marching residual)", name)
+    pr = W.pin_plane(64, seed=1) if name == "pin-plane64" else _ragged_box()
+    P = ebmg.Problem(ctx, pr)
+    assert P.N >= 1 << 18
+    S = assemble(pr)
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=P.N + P.N2)
+    out = torch.zeros(P.N, dtype=torch.float64, device=DEV)
+    out2 = torch.zeros(max(P.N2, 1), dtype=torch.float64, device=DEV)
+    torch.cuda.synchronize()
+    P.apply(_t(x[:P.N]), _t(x[P.N:]) if P.N2 else None, out, out2 if P.N2 else None)
+    y = np.concatenate([out.cpu().numpy(), out2.cpu().numpy()[:P.N2]])
+    ref = S.A @ x
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(S.A).max() * np.abs(x).max() * 4
+    st, info, xs, _ = _solve(P, pr, 1e-10)
+    assert st == ebmg.OK and rel_residual(S.A, S.b, xs) <= 1.01e-10
+    P.release()

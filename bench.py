@@ -70,6 +70,8 @@ def cpu_baseline(n=64):
 def _kernel_label(P, prec):
     var = P.tuning(0)[0]
     t = "float" if prec == 1 else "double"
+    if var == 6:
+        return f"k_rb_oop<{t},3> (one-launch colour phase of a red/black sweep, finest level)", "half-sweep"
     if var >= 2:
         tile = ["64,8,32", "64,16,32", "32,16,32", "64,8,16"][var - 2]
         return (f"k_rb_zm3<{t},{tile}> (fused red+black Gauss-Seidel sweep marching in z, finest level)",

@@ -109,7 +109,9 @@ typedef struct {
                                BiCGStab                                          */
   int32_t smoother;         /* 0 autotuned per level at setup, 1 split red and
                                black half-sweeps, 2 fused red+black tile sweep,
-                               3 z-marching fused sweep (3D; tile sweep in 2D);
+                               3 z-marching fused sweep (3D; tile sweep in 2D),
+                               4 fixed rule without timing (fused sweeps where
+                               they apply, one-launch colour phases elsewhere);
                                fused sweeps only on levels of at least 32^3 /
                                256^2 cells                                      */
   int32_t tail;             /* coarse levels: 0 autotuned at setup, 1 always by
@@ -159,7 +161,8 @@ ebmg_status ebmg_query_level(ebmg_problem pb, int32_t level, int64_t* n_cells, i
 
 /* Smoother choice of level `level` (0 split half-sweeps, 1 fused tile sweep,
  * 2 + c z-marching fused sweep in tile configuration c as listed at
- * ebmg_smooth), the split sweep time and the chosen (or best
+ * ebmg_smooth, 6 one-launch colour phases), the split sweep time and the
+ * chosen (or best
  * fused) variant's sweep time (ms) as the setup autotuner measured them (0 if
  * not timed).
  * level = -1 reports the coarse-tail choice instead: *fused receives the first
@@ -213,8 +216,9 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
  * covered and second-phase entries of x are left as they are. variant: 1
  * split red and black half-sweeps, 2 fused tile sweep, 3 + c z-marching
  * fused sweep in tile configuration c = 0..3 (64x8 tiles over 32 planes,
- * 64x16 over 32, 32x16 over 32, 64x8 over 16; 3D). Every variant performs
- * exactly the red half-sweep followed by
+ * 64x16 over 32, 32x16 over 32, 64x8 over 16; 3D), 7 one-launch colour
+ * phases out of place. Every variant performs exactly the red half-sweep
+ * followed by
  * the black one with the same arithmetic, so their results agree bitwise.
  * x (in/out) and b are DEVICE FP64 arrays of the level's N + N2 unknowns;
  * mixed-precision problems sweep in FP32 (x and b rounded, x widened back).

@@ -634,6 +634,55 @@ __global__ void __launch_bounds__(kBlock) k_irr_scatter(const int32_t* __restric
   x[dof[rows[t]]] = tmp[t];
 }
 
+// One colour phase of an out-of-place red/black sweep in a single launch:
+// template cells and explicit rows of colour `colour` are updated from xin,
+// every other unknown is copied to xout. Blocks [0, nbc) take cells (one per
+// thread), the remaining blocks take explicit rows (kSub lanes per row):
+// rows_upd are updated, rows_cp copied. Explicit rows therefore see only the
+// values before the phase (Jacobi within a colour, as the grouped passes),
+// and a sweep costs two launches, which is what matters on small levels.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_rb_oop(const uint8_t* __restrict__ tag, const T* __restrict__ xin,
+                                                   T* __restrict__ xout, const T* __restrict__ b, Tmpl<T> tp,
+                                                   int colour, unsigned nbc, const int32_t* __restrict__ rows_upd,
+                                                   int nupd, const int32_t* __restrict__ rows_cp, int ncp,
+                                                   const int64_t* __restrict__ dof, const int64_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                   const T* __restrict__ diag) {
+  if (blockIdx.x < nbc) {
+    const int nx = tp.n[0], ny = tp.n[1];
+    const int64_t N = (int64_t)nx * ny * (DIM == 3 ? tp.n[2] : 1);
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= N) return;
+    const uint8_t p = tclass(tag[c]);
+    if (p == 2) return;
+    const int i = (int)(c % nx);
+    const int64_t jk = c / nx;
+    const int j = (int)(jk % ny);
+    const int k = DIM == 3 ? (int)(jk / ny) : 0;
+    T v = xin[c];
+    if (p <= 1 && ((i + j + k) & 1) == colour) {
+      T dg;
+      const T off = template_apply<T, DIM>(xin, tp, i, j, k, c, p, dg);
+      v = (b[c] - off) * (T(1) / dg);
+    }
+    xout[c] = v;
+    return;
+  }
+  const int64_t g = ((int64_t)(blockIdx.x - nbc) * kBlock + threadIdx.x) / kSub;
+  const int lane = threadIdx.x % kSub;
+  if (g >= (int64_t)nupd + ncp) return;
+  if (g < nupd) {
+    const int r = rows_upd[g];
+    const T s = row_dot<T>(rp[r], rp[r + 1], col, val, xin, lane);
+    const int64_t q = dof[r];
+    if (lane == 0) xout[q] = (b[q] - s) / diag[r];
+  } else if (lane == 0) {
+    const int64_t q = dof[rows_cp[g - nupd]];
+    xout[q] = xin[q];
+  }
+}
+
 // MODE 0: r = b - A x ; MODE 1: r = A x. Regular cells and covered cells
 // (3D launch grid over cells).
 template <typename T, int DIM, int MODE>

@@ -88,9 +88,10 @@ struct DevLevel {
   std::vector<int32_t> cls_ptr;
   int64_t n_ns = 0, n_np = 0;
   bool fused = false;              // smoother variant chosen for this level
+  bool oop = false;                // non-fused: one-launch colour phases (else split in place)
   int fvar = 0;                    // fused variant: 0 3D/2D tile, 1 z-marching (3D)
   int zmcfg = 0;                   // z-marching tile configuration
-  double tune_split_ms = 0, tune_fused_ms = 0, tune_zm_ms = 0;
+  double tune_split_ms = 0, tune_fused_ms = 0, tune_zm_ms = 0, tune_oop_ms = 0;
   Tmpl<double> t64;
   Tmpl<float> t32;
   // vectors
@@ -360,34 +361,25 @@ static void upload_tail(DevProblem& D, hipStream_t s) {
   HIPCHECK(hipStreamSynchronize(s));
 }
 
-// Smoother autotuner: on levels where the fused sweeps apply, time one full
-// sweep of each variant (split red and black half-sweeps, the fused tile
-// kernel, and in 3D the z-marching kernel) with HIP events on zeroed vectors
-// and keep the fastest. mode 1 forces split sweeps, mode 2 the fused tile
-// sweep and mode 3 the z-marching sweep (3D; tile in 2D) where they apply.
 template <typename T>
-static double time_sweep(DevLevel& l, bool fused, T* x, T* xa, const T* b, const Tmpl<T>& tp, hipStream_t s) {
+static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s);
+
+// Smoother autotuner: time a complete sweep (template cells and explicit
+// rows) of each variant with HIP events on zeroed vectors and keep the
+// fastest: split half-sweeps in place with grouped explicit rows, one-launch
+// colour phases out of place, and where they apply the fused tile sweep and
+// the z-marching sweep in each tile configuration. Forced modes: 1 split,
+// 2 fused tile, 3 z-marching (tile in 2D) where the fused sweeps apply;
+// 4 a fixed rule with no timing (z-marching 64x16 tiles / tile sweep where
+// the fused sweeps apply, one-launch colour phases elsewhere).
+template <typename T>
+static double time_smooth(DevLevel& l, T* x, const T* b, hipStream_t s) {
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
-  const Shape sh = shape3((l.n[0] + 1) / 2, l.n[1], l.dim == 3 ? l.n[2] : 1);
-  auto run = [&](int reps) {
-    for (int r = 0; r < reps; ++r) {
-      if (fused) {
-        launch_fused<T>(l, (r & 1) ? xa : x, (r & 1) ? x : xa, b, tp, s);
-      } else {
-        for (int colour = 0; colour < 2; ++colour) {
-          if (l.dim == 3)
-            hipLaunchKernelGGL((k_rb<T, 3>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
-          else
-            hipLaunchKernelGGL((k_rb<T, 2>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
-        }
-      }
-    }
-  };
-  run(2);
+  smooth<T>(l, x, b, 2, s);
   HIPCHECK(hipEventRecord(e0, s));
-  run(6);
+  smooth<T>(l, x, b, 4, s);
   HIPCHECK(hipEventRecord(e1, s));
   HIPCHECK(hipEventSynchronize(e1));
   HIPCHECK(hipGetLastError());
@@ -395,55 +387,75 @@ static double time_sweep(DevLevel& l, bool fused, T* x, T* xa, const T* b, const
   HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return ms / 6.0;
+  return ms / 4.0;
 }
 
 template <typename T>
-static void tune_level(DevLevel& l, T* x, T* xa, T* b, const Tmpl<T>& tp, int mode, hipStream_t s) {
+static void tune_level(DevLevel& l, T* x, T* xa, T* b, int mode, hipStream_t s) {
   const int64_t nd = l.N + l.N2;
   fill<T>(x, nd, T(0), s);
   fill<T>(xa, nd, T(0), s);
   fill<T>(b, nd, T(0), s);
-  if (mode == 1) {
-    l.fused = false;
-    return;
-  }
+  const bool fok = fused_ok(l);
+  l.fused = false;
+  l.oop = false;
+  l.fvar = 0;
+  if (mode == 1) return;
   if (mode == 2 || mode == 3) {
-    l.fused = true;
+    l.fused = fok;
     l.fvar = (mode == 3 && l.dim == 3) ? 1 : 0;
     return;
   }
-  l.tune_split_ms = time_sweep<T>(l, false, x, xa, b, tp, s);
-  l.fvar = 0;
-  l.tune_fused_ms = time_sweep<T>(l, true, x, xa, b, tp, s);
-  double best = l.tune_fused_ms;
-  if (l.dim == 3) {
-    l.fvar = 1;
-    double zbest = 1e30;
-    int zc = 0;
-    for (int c = 0; c < kZMConfigs; ++c) {
-      l.zmcfg = c;
-      const double ms = time_sweep<T>(l, true, x, xa, b, tp, s);
-      if (ms < zbest) {
-        zbest = ms;
-        zc = c;
-      }
-    }
-    l.zmcfg = zc;
-    l.tune_zm_ms = zbest;
-    l.fvar = l.tune_zm_ms < l.tune_fused_ms ? 1 : 0;
-    best = std::min(best, l.tune_zm_ms);
+  if (mode == 4) {
+    l.fused = fok;
+    l.fvar = l.dim == 3 ? 1 : 0;
+    l.zmcfg = 1;
+    l.oop = !fok;
+    return;
   }
-  l.fused = best < l.tune_split_ms;
+  struct Cand {
+    bool fused, oop;
+    int fvar, zmcfg;
+    double ms;
+  };
+  std::vector<Cand> cands = {{false, false, 0, 0, 0}, {false, true, 0, 0, 0}};
+  if (fok) {
+    cands.push_back({true, false, 0, 0, 0});
+    if (l.dim == 3)
+      for (int c = 0; c < kZMConfigs; ++c) cands.push_back({true, false, 1, c, 0});
+  }
+  size_t best = 0;
+  double zbest = 1e30;
+  for (size_t q = 0; q < cands.size(); ++q) {
+    l.fused = cands[q].fused;
+    l.oop = cands[q].oop;
+    l.fvar = cands[q].fvar;
+    l.zmcfg = cands[q].zmcfg;
+    cands[q].ms = time_smooth<T>(l, x, b, s);
+    if (cands[q].ms < cands[best].ms) best = q;
+    if (!cands[q].fused && !cands[q].oop) l.tune_split_ms = cands[q].ms;
+    if (cands[q].oop) l.tune_oop_ms = cands[q].ms;
+    if (cands[q].fused && cands[q].fvar == 0) l.tune_fused_ms = cands[q].ms;
+    if (cands[q].fused && cands[q].fvar == 1 && cands[q].ms < zbest) {
+      zbest = cands[q].ms;
+      l.tune_zm_ms = zbest;
+    }
+  }
+  l.fused = cands[best].fused;
+  l.oop = cands[best].oop;
+  l.fvar = cands[best].fvar;
+  l.zmcfg = cands[best].zmcfg;
+  fill<T>(x, nd, T(0), s);
+  fill<T>(xa, nd, T(0), s);
 }
 
 static void tune_smoother(DevLevel& l, bool mixed, int mode, hipStream_t s) {
   l.fused = false;
-  if (!fused_ok(l)) return;
+  l.oop = false;
   if (mixed) {
-    if (l.xa32.p) tune_level<float>(l, l.x32.p, l.xa32.p, l.b32.p, l.t32, mode, s);
+    if (l.xa32.p) tune_level<float>(l, l.x32.p, l.xa32.p, l.b32.p, mode, s);
   } else {
-    if (l.xa64.p) tune_level<double>(l, l.x64.p, l.xa64.p, l.b64.p, l.t64, mode, s);
+    if (l.xa64.p) tune_level<double>(l, l.x64.p, l.xa64.p, l.b64.p, mode, s);
   }
 }
 
@@ -491,14 +503,14 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
       d.b64.alloc(nd, by);
       d.r64.alloc(nd, by);
       d.w64.alloc(std::max<int64_t>(1, d.R), by);
-      if (fused_ok(d) && !batch_box) d.xa64.alloc(nd, by);
+      if (!batch_box) d.xa64.alloc(nd, by);
     }
     if (mixed) {
       d.x32.alloc(nd, by);
       d.b32.alloc(nd, by);
       d.r32.alloc(nd, by);
       d.w32.alloc(std::max<int64_t>(1, d.R), by);
-      if (fused_ok(d) && !batch_box) d.xa32.alloc(nd, by);
+      if (!batch_box) d.xa32.alloc(nd, by);
     }
   }
   D.bottom_n = H.bottom_n;
@@ -571,6 +583,42 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
 // ---------------------------------------------------------------------------
 static inline unsigned nblk_sub(int64_t rows) { return nblk(rows * kSub); }
 
+// One colour phase of the out-of-place sweep; with rows = false the explicit
+// rows are only copied (template-cell sweeps).
+template <typename T>
+static void launch_oop(DevLevel& l, int colour, bool rows, const T* xin, T* xout, const T* b, hipStream_t s) {
+  const Tmpl<T>& tp = Vec<T>::t(l);
+  const unsigned nbc = nblk(l.N);
+  int n0 = 0, n1 = 0;
+  const int32_t* g0 = l.cls_rows.p;
+  const int32_t* g1 = l.cls_rows.p;
+  if (l.cls_ptr.size() >= 3) {
+    n0 = l.cls_ptr[1] - l.cls_ptr[0];
+    n1 = l.cls_ptr[2] - l.cls_ptr[1];
+    g0 = l.cls_rows.p + l.cls_ptr[0];
+    g1 = l.cls_rows.p + l.cls_ptr[1];
+  }
+  const int32_t* up = colour == 0 ? g0 : g1;
+  const int32_t* cp = colour == 0 ? g1 : g0;
+  int nup = colour == 0 ? n0 : n1;
+  int ncp = colour == 0 ? n1 : n0;
+  if (!rows) {
+    // template cells only: copy every explicit row, update none
+    const int32_t* all = l.cls_rows.p;
+    cp = all;
+    ncp = n0 + n1;
+    up = all;
+    nup = 0;
+  }
+  const unsigned nbr = nblk_sub((int64_t)nup + ncp);
+  if (l.dim == 3)
+    hipLaunchKernelGGL((k_rb_oop<T, 3>), dim3(nbc + nbr), dim3(kBlock), 0, s, l.tag.p, xin, xout, b, tp, colour, nbc,
+                       up, nup, cp, ncp, l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l));
+  else
+    hipLaunchKernelGGL((k_rb_oop<T, 2>), dim3(nbc + nbr), dim3(kBlock), 0, s, l.tag.p, xin, xout, b, tp, colour, nbc,
+                       up, nup, cp, ncp, l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l));
+}
+
 template <typename T>
 static void irr_group(DevLevel& l, int grp, T* x, const T* b, hipStream_t s) {
   if (l.cls_ptr.size() < 3) return;
@@ -598,6 +646,18 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
       irr_group<T>(l, 1, cur, b, s);
     }
     if (cur != x) HIPCHECK(hipMemcpyAsync(x, cur, sizeof(T) * (l.N + l.N2), hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipGetLastError());
+    return;
+  }
+  if (l.oop && Vec<T>::xa(l)) {
+    // one launch per colour phase, out of place (two per sweep)
+    T* cur = x;
+    T* alt = Vec<T>::xa(l);
+    for (int it = 0; it < sweeps; ++it)
+      for (int colour = 0; colour < 2; ++colour) {
+        launch_oop<T>(l, colour, true, cur, alt, b, s);
+        std::swap(cur, alt);
+      }
     HIPCHECK(hipGetLastError());
     return;
   }
@@ -998,6 +1058,17 @@ static void upload_batch_views(ebmg_batch_s* Bt, hipStream_t s) {
 template <typename T>
 static void template_sweeps(DevLevel& l, int variant, int sweeps, T* x, const T* b, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
+  if (variant == 3 + kZMConfigs) {
+    T* cur = x;
+    T* alt = Vec<T>::xa(l);
+    for (int it = 0; it < sweeps; ++it)
+      for (int colour = 0; colour < 2; ++colour) {
+        launch_oop<T>(l, colour, false, cur, alt, b, s);
+        std::swap(cur, alt);
+      }
+    HIPCHECK(hipGetLastError());
+    return;
+  }
   if (variant > 1) {
     const bool f0 = l.fused;
     const int v0 = l.fvar, c0 = l.zmcfg;
@@ -1134,7 +1205,7 @@ static ebmg_status parse_options(const ebmg_options* opt, int nobj, ebmg::Option
   out.bottom_max = o.bottom_max_dof > 0 ? o.bottom_max_dof : 600;
   if (o.precision != EBMG_FP64 && o.precision != EBMG_MIXED) return EBMG_ERR_ARG;
   if (!(o.beta != 0.0) || !std::isfinite(o.beta)) return EBMG_ERR_ARG;
-  if (o.krylov < 0 || o.krylov > 2 || o.smoother < 0 || o.smoother > 3 || o.tail < 0 || o.tail > 2)
+  if (o.krylov < 0 || o.krylov > 2 || o.smoother < 0 || o.smoother > 4 || o.tail < 0 || o.tail > 2)
     return EBMG_ERR_ARG;
   for (int k = 0; k < 5; ++k)
     if (o.reserved[k] != 0) return EBMG_ERR_ARG;
@@ -1234,7 +1305,7 @@ ebmg_status ebmg_query_tuning(ebmg_problem pb, int32_t level, int32_t* fused, do
     return EBMG_OK;
   }
   const DevLevel& l = pb->dev.lv[level];
-  if (fused) *fused = l.fused ? (l.fvar ? 2 + l.zmcfg : 1) : 0;
+  if (fused) *fused = l.fused ? (l.fvar ? 2 + l.zmcfg : 1) : (l.oop ? 2 + kZMConfigs : 0);
   if (split_ms) *split_ms = l.tune_split_ms;
   if (fused_ms) *fused_ms = l.fvar == 1 ? l.tune_zm_ms : l.tune_fused_ms;
   return EBMG_OK;
@@ -1379,7 +1450,7 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
 
 ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t sweeps, double* x,
                         const double* b) {
-  if (!pb || !x || !b || sweeps < 0 || variant < 1 || variant > 2 + kZMConfigs) return EBMG_ERR_ARG;
+  if (!pb || !x || !b || sweeps < 0 || variant < 1 || variant > 3 + kZMConfigs) return EBMG_ERR_ARG;
   if (!pb->on_device) return EBMG_ERR_DEVICE;
   if (level < 0 || level >= (int32_t)pb->dev.lv.size()) return EBMG_ERR_ARG;
   return guard(pb->ctx, [&]() -> ebmg_status {
@@ -1387,8 +1458,9 @@ ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t
     DevLevel& L = pb->dev.lv[level];
     hipStream_t s = pb->ctx->stream;
     const bool mixed = pb->host->opt.precision == EBMG_MIXED;
-    if (variant > 1 && (mixed ? !L.xa32.p : !L.xa64.p)) throw ArgError("this level has no fused sweep");
-    if (variant >= 3 && L.dim != 3) throw ArgError("the z-marching sweep is 3D only");
+    if (variant > 1 && (mixed ? !L.xa32.p : !L.xa64.p)) throw ArgError("this level has no second vector");
+    if (variant > 1 && variant < 3 + kZMConfigs && !fused_ok(L)) throw ArgError("this level has no fused sweep");
+    if (variant >= 3 && variant < 3 + kZMConfigs && L.dim != 3) throw ArgError("the z-marching sweep is 3D only");
     const int64_t nd = L.N + L.N2;
     if (mixed) {
       hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(nd)), dim3(kBlock), 0, s, x, L.x32.p, nd);

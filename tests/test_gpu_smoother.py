@@ -2,7 +2,7 @@
 sweep, and against each other.
 
 Every variant (split half-sweeps, fused tile sweep, z-marching sweep in each
-tile configuration) must
+tile configuration, one-launch colour phases out of place) must
 produce bitwise the same result, and the result must be a red half-sweep
 followed by a black half-sweep over the template cells, computed here in
 numpy from the level's exported operator rows; explicit-row, covered and
@@ -77,7 +77,7 @@ def test_smoother_variants(ctx, name, prec):
             continue
         x0 = rng.normal(size=n + n2)
         b = rng.normal(size=n + n2)
-        variants = [1, 2, 3, 4, 5, 6] if pr.dim == 3 else [1, 2]
+        variants = [1, 2, 3, 4, 5, 6, 7] if pr.dim == 3 else [1, 2, 7]
         outs = {}
         for v in variants:
             xt = torch.tensor(x0, dtype=torch.float64, device=DEV)

@@ -847,6 +847,124 @@ __global__ void __launch_bounds__(kBlock) k_prolong_ns(int n, const int64_t* __r
   xf[fdof[t]] += ec[cdof[t]];
 }
 
+// Restriction in one launch: blocks [0, nbc) take simple coarse cells (mean
+// of the 2^D children; covered coarse cells get 0), blocks [nbc, nbc + nbn)
+// the non-simple coarse unknowns from their child lists, and the rest clear
+// the coarse correction xc (cells and second-phase unknowns).
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_restrict_all(const uint8_t* __restrict__ ctag, const T* __restrict__ rf,
+                                                         T* __restrict__ bc, T* __restrict__ xc, int cnx, int cny,
+                                                         int cnz, unsigned nbc, unsigned nbn, int nns,
+                                                         const int64_t* __restrict__ cdof,
+                                                         const int32_t* __restrict__ ptr,
+                                                         const int64_t* __restrict__ child, int64_t ncd) {
+  const unsigned bid = blockIdx.x;
+  const T w = DIM == 3 ? T(0.125) : T(0.25);
+  if (bid < nbc) {
+    const int64_t P = (int64_t)bid * kBlock + threadIdx.x;
+    const int64_t cN = (int64_t)cnx * cny * (DIM == 3 ? cnz : 1);
+    if (P >= cN) return;
+    const uint8_t t = ctag[P];
+    if (tclass(t) == 3) {
+      bc[P] = 0;
+      return;
+    }
+    if (t & 4) return;
+    const int I = (int)(P % cnx);
+    const int64_t JK = P / cnx;
+    const int J = (int)(JK % cny);
+    const int K = DIM == 3 ? (int)(JK / cny) : 0;
+    const int fnx = 2 * cnx;
+    const int64_t fsxy = (int64_t)fnx * 2 * cny;
+    const int64_t c0 = 2 * I + (int64_t)fnx * (2 * J) + (DIM == 3 ? fsxy * (2 * K) : 0);
+    T s = rf[c0] + rf[c0 + 1] + rf[c0 + fnx] + rf[c0 + fnx + 1];
+    if (DIM == 3) s += rf[c0 + fsxy] + rf[c0 + fsxy + 1] + rf[c0 + fsxy + fnx] + rf[c0 + fsxy + fnx + 1];
+    bc[P] = s * w;
+    return;
+  }
+  if (bid < nbc + nbn) {
+    const int t = (int)((bid - nbc) * kBlock + threadIdx.x);
+    if (t >= nns) return;
+    T s = 0;
+    for (int e = ptr[t]; e < ptr[t + 1]; ++e) s += rf[child[e]];
+    bc[cdof[t]] = s * w;
+    return;
+  }
+  const int64_t q = (int64_t)(bid - nbc - nbn) * kBlock + threadIdx.x;
+  if (q < ncd) xc[q] = T(0);
+}
+
+// Prolongation in one launch: blocks [0, nbf) take fine cells of simple
+// parents, the rest the fine unknowns of non-simple parents (disjoint sets).
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_prolong_all(const uint8_t* __restrict__ ftag,
+                                                        const uint8_t* __restrict__ ctag, const T* __restrict__ ec,
+                                                        T* __restrict__ xf, int fnx, int fny, int fnz, unsigned nbf,
+                                                        int nnp, const int64_t* __restrict__ fdof,
+                                                        const int64_t* __restrict__ cdof) {
+  const unsigned bid = blockIdx.x;
+  if (bid < nbf) {
+    const int64_t c = (int64_t)bid * kBlock + threadIdx.x;
+    const int64_t fN = (int64_t)fnx * fny * (DIM == 3 ? fnz : 1);
+    if (c >= fN) return;
+    if (tclass(ftag[c]) == 3) return;
+    const int i = (int)(c % fnx);
+    const int64_t jk = c / fnx;
+    const int j = (int)(jk % fny);
+    const int k = DIM == 3 ? (int)(jk / fny) : 0;
+    const int cnx = fnx >> 1, cny = fny >> 1;
+    const int64_t P = (i >> 1) + (int64_t)cnx * ((j >> 1) + (int64_t)cny * (k >> 1));
+    if (ctag[P] & 4) return;
+    xf[c] += ec[P];
+    return;
+  }
+  const int t = (int)((bid - nbf) * kBlock + threadIdx.x);
+  if (t >= nnp) return;
+  xf[fdof[t]] += ec[cdof[t]];
+}
+
+// Residual of a small level in one launch: blocks [0, nbc) take the template
+// and covered cells (MODE as in k_resid_reg), the rest the explicit rows with
+// kSub lanes each (as k_resid_irr).
+template <typename T, int DIM, int MODE>
+__global__ void __launch_bounds__(kBlock) k_resid_all(const uint8_t* __restrict__ tag, const T* __restrict__ x,
+                                                      const T* __restrict__ b, T* __restrict__ r, Tmpl<T> tp,
+                                                      unsigned nbc, int nrows, const int64_t* __restrict__ dof,
+                                                      const int64_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                      const T* __restrict__ diag) {
+  if (blockIdx.x < nbc) {
+    const int nx = tp.n[0], ny = tp.n[1];
+    const int64_t N = (int64_t)nx * ny * (DIM == 3 ? tp.n[2] : 1);
+    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= N) return;
+    const uint8_t p = tclass(tag[c]);
+    if (p == 3) {
+      r[c] = MODE == 0 ? T(0) : x[c];
+      return;
+    }
+    if (p == 2) return;
+    const int i = (int)(c % nx);
+    const int64_t jk = c / nx;
+    const int j = (int)(jk % ny);
+    const int k = DIM == 3 ? (int)(jk / ny) : 0;
+    T dg;
+    const T off = template_apply<T, DIM>(x, tp, i, j, k, c, p, dg);
+    const T ax = dg * x[c] + off;
+    r[c] = MODE == 0 ? b[c] - ax : ax;
+    return;
+  }
+  const int64_t g = ((int64_t)(blockIdx.x - nbc) * kBlock + threadIdx.x) / kSub;
+  const int lane = threadIdx.x % kSub;
+  if (g >= nrows) return;
+  const int64_t q = dof[g];
+  const T s = row_dot<T>(rp[g], rp[g + 1], col, val, x, lane);
+  if (lane == 0) {
+    const T ax = diag[g] * x[q] + s;
+    r[q] = MODE == 0 ? b[q] - ax : ax;
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fill(T* __restrict__ x, int64_t n, T v) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -680,49 +680,52 @@ constexpr int64_t kResidZMMin = 1 << 18;
 template <typename T, int MODE>
 static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
-  const Shape sh = shape3(l.n[0], l.n[1], l.dim == 3 ? l.n[2] : 1);
   if (l.dim == 3 && l.N >= kResidZMMin) {
     const dim3 g((l.n[0] + kRZX - 1) / kRZX, (l.n[1] + kRZY - 1) / kRZY, (l.n[2] + kRZ - 1) / kRZ);
     hipLaunchKernelGGL((k_resid_zm3<T, MODE>), g, dim3(kRZX, kRZY), 0, s, l.tag.p, x, b, r, tp);
-  } else if (l.dim == 3) {
-    hipLaunchKernelGGL((k_resid_reg<T, 3, MODE>), sh.g, sh.b, 0, s, l.tag.p, x, b, r, tp);
+    if (l.R > 0)
+      hipLaunchKernelGGL((k_resid_irr<T, MODE>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R, l.irow_dof.p,
+                         l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, r);
   } else {
-    hipLaunchKernelGGL((k_resid_reg<T, 2, MODE>), sh.g, sh.b, 0, s, l.tag.p, x, b, r, tp);
+    // small levels: template cells and explicit rows in one launch
+    const unsigned nbc = nblk(l.N);
+    const dim3 g(nbc + nblk_sub(l.R));
+    if (l.dim == 3)
+      hipLaunchKernelGGL((k_resid_all<T, 3, MODE>), g, dim3(kBlock), 0, s, l.tag.p, x, b, r, tp, nbc, (int)l.R,
+                         l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l));
+    else
+      hipLaunchKernelGGL((k_resid_all<T, 2, MODE>), g, dim3(kBlock), 0, s, l.tag.p, x, b, r, tp, nbc, (int)l.R,
+                         l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l));
   }
-  if (l.R > 0)
-    hipLaunchKernelGGL((k_resid_irr<T, MODE>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R, l.irow_dof.p, l.rp.p,
-                       l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, r);
   HIPCHECK(hipGetLastError());
 }
 
+// restriction of rf into the coarse right-hand side bc, clearing the coarse
+// correction xc, in one launch
 template <typename T>
-static void restrict_to(DevLevel& f, DevLevel& c, const T* rf, T* bc, hipStream_t s) {
-  const Shape sh = shape3(c.n[0], c.n[1], c.dim == 3 ? c.n[2] : 1);
+static void restrict_to(DevLevel& f, DevLevel& c, const T* rf, T* bc, T* xc, hipStream_t s) {
+  const unsigned nbc = nblk(c.N), nbn = nblk(f.n_ns);
+  const int64_t ncd = c.N + c.N2;
+  const dim3 g(nbc + nbn + nblk(ncd));
   if (f.dim == 3)
-    hipLaunchKernelGGL((k_restrict<T, 3>), sh.g, sh.b, 0, s, c.tag.p, rf, bc, c.n[0], c.n[1], c.n[2]);
+    hipLaunchKernelGGL((k_restrict_all<T, 3>), g, dim3(kBlock), 0, s, c.tag.p, rf, bc, xc, c.n[0], c.n[1], c.n[2],
+                       nbc, nbn, (int)f.n_ns, f.ns_cdof.p, f.ns_ptr.p, f.ns_child.p, ncd);
   else
-    hipLaunchKernelGGL((k_restrict<T, 2>), sh.g, sh.b, 0, s, c.tag.p, rf, bc, c.n[0], c.n[1], 1);
-  if (f.n_ns > 0) {
-    if (f.dim == 3)
-      hipLaunchKernelGGL((k_restrict_ns<T, 3>), dim3(nblk(f.n_ns)), dim3(kBlock), 0, s, (int)f.n_ns, f.ns_cdof.p,
-                         f.ns_ptr.p, f.ns_child.p, rf, bc);
-    else
-      hipLaunchKernelGGL((k_restrict_ns<T, 2>), dim3(nblk(f.n_ns)), dim3(kBlock), 0, s, (int)f.n_ns, f.ns_cdof.p,
-                         f.ns_ptr.p, f.ns_child.p, rf, bc);
-  }
+    hipLaunchKernelGGL((k_restrict_all<T, 2>), g, dim3(kBlock), 0, s, c.tag.p, rf, bc, xc, c.n[0], c.n[1], 1, nbc,
+                       nbn, (int)f.n_ns, f.ns_cdof.p, f.ns_ptr.p, f.ns_child.p, ncd);
   HIPCHECK(hipGetLastError());
 }
 
 template <typename T>
 static void prolong_from(DevLevel& f, DevLevel& c, const T* ec, T* xf, hipStream_t s) {
-  const Shape sh = shape3(f.n[0], f.n[1], f.dim == 3 ? f.n[2] : 1);
+  const unsigned nbf = nblk(f.N);
+  const dim3 g(nbf + nblk(f.n_np));
   if (f.dim == 3)
-    hipLaunchKernelGGL((k_prolong<T, 3>), sh.g, sh.b, 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1], f.n[2]);
+    hipLaunchKernelGGL((k_prolong_all<T, 3>), g, dim3(kBlock), 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1],
+                       f.n[2], nbf, (int)f.n_np, f.np_fdof.p, f.np_cdof.p);
   else
-    hipLaunchKernelGGL((k_prolong<T, 2>), sh.g, sh.b, 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1], 1);
-  if (f.n_np > 0)
-    hipLaunchKernelGGL((k_prolong_ns<T>), dim3(nblk(f.n_np)), dim3(kBlock), 0, s, (int)f.n_np, f.np_fdof.p,
-                       f.np_cdof.p, ec, xf);
+    hipLaunchKernelGGL((k_prolong_all<T, 2>), g, dim3(kBlock), 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1], 1,
+                       nbf, (int)f.n_np, f.np_fdof.p, f.np_cdof.p);
   HIPCHECK(hipGetLastError());
 }
 
@@ -755,8 +758,7 @@ static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* 
   smooth<T>(L, x, b, o.nu1, s);
   T* r = Vec<T>::r(L);
   residual<T, 0>(L, x, b, r, s);
-  restrict_to<T>(L, C, r, Vec<T>::b(C), s);
-  fill<T>(Vec<T>::x(C), C.N + C.N2, T(0), s);
+  restrict_to<T>(L, C, r, Vec<T>::b(C), Vec<T>::x(C), s);
   vcycle<T>(D, o, l + 1, s, Vec<T>::x(C), Vec<T>::b(C));
   prolong_from<T>(L, C, Vec<T>::x(C), x, s);
   smooth<T>(L, x, b, o.nu2, s);

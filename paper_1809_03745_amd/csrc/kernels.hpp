@@ -705,6 +705,33 @@ __global__ void __launch_bounds__(kBlock) k_resid_reg(const uint8_t* __restrict_
   r[c] = MODE == 0 ? b[c] - ax : ax;
 }
 
+// Per-block partial sums of up to two dot products (fixed order: wave64
+// shuffles, then the block's waves in order), stored at part[d * pt + bid].
+// Every thread of the block must call it.
+template <int NB>
+__device__ __forceinline__ void block_partials(double s0, double s1, int ndot, double* __restrict__ part, int64_t pt,
+                                               int64_t bid, int tid) {
+  __shared__ double sh[2][NB / 64];
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_down(s0, off, 64);
+    s1 += __shfl_down(s1, off, 64);
+  }
+  if ((tid & 63) == 0) {
+    sh[0][tid >> 6] = s0;
+    sh[1][tid >> 6] = s1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double t0 = 0, t1 = 0;
+    for (int w = 0; w < NB / 64; ++w) {
+      t0 += sh[0][w];
+      t1 += sh[1][w];
+    }
+    part[bid] = t0;
+    if (ndot > 1) part[pt + bid] = t1;
+  }
+}
+
 // Template rows of a 3D level marching along z (r = b - A x, MODE 1: r = A x):
 // each thread owns one (i, j) column of a block's 64 x 4 tile and walks KZ
 // planes, keeping x of planes k-1, k, k+1 in registers (each x value leaves
@@ -713,10 +740,15 @@ __global__ void __launch_bounds__(kBlock) k_resid_reg(const uint8_t* __restrict_
 // kernel; explicit rows are left to k_resid_irr.
 constexpr int kRZX = 64, kRZY = 4, kRZ = 16;
 
-template <typename T, int MODE>
+// TX: type of x (a FP32 preconditioner output is widened on load, exactly).
+// NDOT > 0 (MODE 1): per-block partials of (da, r) and, if 2, (r, r) over the
+// entries this block writes, at part[d * pt + block] (see block_partials).
+template <typename T, int MODE, typename TX = T, int NDOT = 0>
 __global__ void __launch_bounds__(kRZX * kRZY) k_resid_zm3(const uint8_t* __restrict__ tag,
-                                                           const T* __restrict__ x, const T* __restrict__ b,
-                                                           T* __restrict__ r, Tmpl<T> tp) {
+                                                           const TX* __restrict__ x, const T* __restrict__ b,
+                                                           T* __restrict__ r, Tmpl<T> tp,
+                                                           const T* __restrict__ da = nullptr,
+                                                           double* __restrict__ part = nullptr, int64_t pt = 0) {
   __shared__ T TC[2][8];
   const int tid = threadIdx.x + kRZX * threadIdx.y;
   if (tid < 16) {
@@ -728,58 +760,83 @@ __global__ void __launch_bounds__(kRZX * kRZY) k_resid_zm3(const uint8_t* __rest
   const int i = blockIdx.x * kRZX + threadIdx.x;
   const int j = blockIdx.y * kRZY + threadIdx.y;
   const int z0 = blockIdx.z * kRZ, z1 = min(z0 + kRZ, nz);
-  if (i >= nx || j >= ny) return;
-  const int64_t sxy = (int64_t)nx * ny;
-  const int64_t c0 = i + (int64_t)nx * j;
-  T xm = z0 > 0 ? x[c0 + sxy * (z0 - 1)] : T(0);
-  T xc = x[c0 + sxy * z0];
-  T xp = z0 + 1 < nz ? x[c0 + sxy * (z0 + 1)] : T(0);
-  uint8_t tg = tag[c0 + sxy * z0];
-  T bb = MODE == 0 ? b[c0 + sxy * z0] : T(0);
-  for (int k = z0; k < z1; ++k) {
-    const int64_t c = c0 + sxy * k;
-    // requests for the next step
-    const T xpp = k + 2 < nz ? x[c + 2 * sxy] : T(0);
-    const uint8_t tgn = k + 1 < z1 ? tag[c + sxy] : (uint8_t)3;
-    const T bbn = (MODE == 0 && k + 1 < z1) ? b[c + sxy] : T(0);
-    const int p = tclass(tg);
-    if (p == 3) {
-      r[c] = MODE == 0 ? T(0) : xc;
-    } else if (p <= 1) {
-      const T* tc = TC[p];
-      T s = 0, dg = tc[1];
-      if (i > 0) s += x[c - 1]; else dg += tc[2];
-      if (i < nx - 1) s += x[c + 1]; else dg += tc[3];
-      if (j > 0) s += x[c - nx]; else dg += tc[4];
-      if (j < ny - 1) s += x[c + nx]; else dg += tc[5];
-      if (k > 0) s += xm; else dg += tc[6];
-      if (k < nz - 1) s += xp; else dg += tc[7];
-      const T ax = dg * xc + tc[0] * s;
-      r[c] = MODE == 0 ? bb - ax : ax;
+  double d0 = 0, d1 = 0;
+  if (i < nx && j < ny) {
+    const int64_t sxy = (int64_t)nx * ny;
+    const int64_t c0 = i + (int64_t)nx * j;
+    T xm = z0 > 0 ? (T)x[c0 + sxy * (z0 - 1)] : T(0);
+    T xc = (T)x[c0 + sxy * z0];
+    T xp = z0 + 1 < nz ? (T)x[c0 + sxy * (z0 + 1)] : T(0);
+    uint8_t tg = tag[c0 + sxy * z0];
+    T bb = MODE == 0 ? b[c0 + sxy * z0] : T(0);
+    for (int k = z0; k < z1; ++k) {
+      const int64_t c = c0 + sxy * k;
+      // requests for the next step
+      const T xpp = k + 2 < nz ? (T)x[c + 2 * sxy] : T(0);
+      const uint8_t tgn = k + 1 < z1 ? tag[c + sxy] : (uint8_t)3;
+      const T bbn = (MODE == 0 && k + 1 < z1) ? b[c + sxy] : T(0);
+      const int p = tclass(tg);
+      if (p != 2) {
+        T out;
+        if (p == 3) {
+          out = MODE == 0 ? T(0) : xc;
+        } else {
+          const T* tc = TC[p];
+          T s = 0, dg = tc[1];
+          if (i > 0) s += (T)x[c - 1]; else dg += tc[2];
+          if (i < nx - 1) s += (T)x[c + 1]; else dg += tc[3];
+          if (j > 0) s += (T)x[c - nx]; else dg += tc[4];
+          if (j < ny - 1) s += (T)x[c + nx]; else dg += tc[5];
+          if (k > 0) s += xm; else dg += tc[6];
+          if (k < nz - 1) s += xp; else dg += tc[7];
+          const T ax = dg * xc + tc[0] * s;
+          out = MODE == 0 ? bb - ax : ax;
+        }
+        r[c] = out;
+        if (NDOT > 0) {
+          d0 += (double)da[c] * (double)out;
+          if (NDOT > 1) d1 += (double)out * (double)out;
+        }
+      }
+      xm = xc;
+      xc = xp;
+      xp = xpp;
+      tg = tgn;
+      bb = bbn;
     }
-    xm = xc;
-    xc = xp;
-    xp = xpp;
-    tg = tgn;
-    bb = bbn;
   }
+  if (NDOT > 0)
+    block_partials<kRZX * kRZY>(d0, d1, NDOT, part, pt,
+                                blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z), tid);
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, typename TX = T, int NDOT = 0>
 __global__ void __launch_bounds__(kBlock) k_resid_irr(int nrows, const int64_t* __restrict__ dof,
                                                       const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                       const T* __restrict__ val, const T* __restrict__ diag,
-                                                      const T* __restrict__ x, const T* __restrict__ b,
-                                                      T* __restrict__ r) {
+                                                      const TX* __restrict__ x, const T* __restrict__ b,
+                                                      T* __restrict__ r, const T* __restrict__ da = nullptr,
+                                                      double* __restrict__ part = nullptr, int64_t pt = 0,
+                                                      int64_t boff = 0) {
   const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSub;
   const int lane = threadIdx.x % kSub;
-  if (g >= nrows) return;
-  const T s = row_dot<T>(rp[g], rp[g + 1], col, val, x, lane);
-  if (lane == 0) {
-    const int64_t q = dof[g];
-    const T ax = diag[g] * x[q] + s;
-    r[q] = MODE == 0 ? b[q] - ax : ax;
+  double d0 = 0, d1 = 0;
+  if (g < nrows) {
+    T s = 0;
+    for (int64_t q = rp[g] + lane; q < rp[g + 1]; q += kSub) s += val[q] * (T)x[col[q]];
+    for (int off = kSub / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kSub);
+    if (lane == 0) {
+      const int64_t q = dof[g];
+      const T ax = diag[g] * (T)x[q] + s;
+      const T out = MODE == 0 ? b[q] - ax : ax;
+      r[q] = out;
+      if (NDOT > 0) {
+        d0 = (double)da[q] * (double)out;
+        if (NDOT > 1) d1 = (double)out * (double)out;
+      }
+    }
   }
+  if (NDOT > 0) block_partials<kBlock>(d0, d1, NDOT, part, pt, boff + blockIdx.x, threadIdx.x);
 }
 
 // Restriction to simple coarse cells: mean of the 2^D children (3D launch
@@ -925,44 +982,73 @@ __global__ void __launch_bounds__(kBlock) k_prolong_all(const uint8_t* __restric
 
 // Residual of a small level in one launch: blocks [0, nbc) take the template
 // and covered cells (MODE as in k_resid_reg), the rest the explicit rows with
-// kSub lanes each (as k_resid_irr).
-template <typename T, int DIM, int MODE>
-__global__ void __launch_bounds__(kBlock) k_resid_all(const uint8_t* __restrict__ tag, const T* __restrict__ x,
+// kSub lanes each (as k_resid_irr); TX and NDOT as in k_resid_zm3, with one
+// partial per block of this launch.
+template <typename T, int DIM, int MODE, typename TX = T, int NDOT = 0>
+__global__ void __launch_bounds__(kBlock) k_resid_all(const uint8_t* __restrict__ tag, const TX* __restrict__ x,
                                                       const T* __restrict__ b, T* __restrict__ r, Tmpl<T> tp,
                                                       unsigned nbc, int nrows, const int64_t* __restrict__ dof,
                                                       const int64_t* __restrict__ rp,
                                                       const int32_t* __restrict__ col, const T* __restrict__ val,
-                                                      const T* __restrict__ diag) {
+                                                      const T* __restrict__ diag, const T* __restrict__ da = nullptr,
+                                                      double* __restrict__ part = nullptr, int64_t pt = 0) {
+  double d0 = 0, d1 = 0;
   if (blockIdx.x < nbc) {
     const int nx = tp.n[0], ny = tp.n[1];
     const int64_t N = (int64_t)nx * ny * (DIM == 3 ? tp.n[2] : 1);
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= N) return;
-    const uint8_t p = tclass(tag[c]);
-    if (p == 3) {
-      r[c] = MODE == 0 ? T(0) : x[c];
-      return;
+    if (c < N) {
+      const uint8_t p = tclass(tag[c]);
+      if (p != 2) {
+        T out;
+        if (p == 3) {
+          out = MODE == 0 ? T(0) : (T)x[c];
+        } else {
+          const int i = (int)(c % nx);
+          const int64_t jk = c / nx;
+          const int j = (int)(jk % ny);
+          const int k = DIM == 3 ? (int)(jk / ny) : 0;
+          T s = 0;
+          T dg = tp.D0(p);
+          if (i > 0) s += (T)x[c - 1]; else dg += tp.CB(0, p);
+          if (i < nx - 1) s += (T)x[c + 1]; else dg += tp.CB(1, p);
+          if (j > 0) s += (T)x[c - nx]; else dg += tp.CB(2, p);
+          if (j < ny - 1) s += (T)x[c + nx]; else dg += tp.CB(3, p);
+          if (DIM == 3) {
+            const int64_t sxy = (int64_t)nx * ny;
+            if (k > 0) s += (T)x[c - sxy]; else dg += tp.CB(4, p);
+            if (k < tp.n[2] - 1) s += (T)x[c + sxy]; else dg += tp.CB(5, p);
+          }
+          const T ax = dg * (T)x[c] + tp.CO(p) * s;
+          out = MODE == 0 ? b[c] - ax : ax;
+        }
+        r[c] = out;
+        if (NDOT > 0) {
+          d0 = (double)da[c] * (double)out;
+          if (NDOT > 1) d1 = (double)out * (double)out;
+        }
+      }
     }
-    if (p == 2) return;
-    const int i = (int)(c % nx);
-    const int64_t jk = c / nx;
-    const int j = (int)(jk % ny);
-    const int k = DIM == 3 ? (int)(jk / ny) : 0;
-    T dg;
-    const T off = template_apply<T, DIM>(x, tp, i, j, k, c, p, dg);
-    const T ax = dg * x[c] + off;
-    r[c] = MODE == 0 ? b[c] - ax : ax;
-    return;
+  } else {
+    const int64_t g = ((int64_t)(blockIdx.x - nbc) * kBlock + threadIdx.x) / kSub;
+    const int lane = threadIdx.x % kSub;
+    if (g < nrows) {
+      const int64_t q = dof[g];
+      T s = 0;
+      for (int64_t e = rp[g] + lane; e < rp[g + 1]; e += kSub) s += val[e] * (T)x[col[e]];
+      for (int off = kSub / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kSub);
+      if (lane == 0) {
+        const T ax = diag[g] * (T)x[q] + s;
+        const T out = MODE == 0 ? b[q] - ax : ax;
+        r[q] = out;
+        if (NDOT > 0) {
+          d0 = (double)da[q] * (double)out;
+          if (NDOT > 1) d1 = (double)out * (double)out;
+        }
+      }
+    }
   }
-  const int64_t g = ((int64_t)(blockIdx.x - nbc) * kBlock + threadIdx.x) / kSub;
-  const int lane = threadIdx.x % kSub;
-  if (g >= nrows) return;
-  const int64_t q = dof[g];
-  const T s = row_dot<T>(rp[g], rp[g + 1], col, val, x, lane);
-  if (lane == 0) {
-    const T ax = diag[g] * x[q] + s;
-    r[q] = MODE == 0 ? b[q] - ax : ax;
-  }
+  if (NDOT > 0) block_partials<kBlock>(d0, d1, NDOT, part, pt, blockIdx.x, threadIdx.x);
 }
 
 template <typename T>
@@ -1054,7 +1140,7 @@ __global__ void __launch_bounds__(kBlock) k_dot_final(const double* __restrict__
 }
 
 // BiCGStab scalars live on the device: slots of `sc`
-enum { SC_RHO = 0, SC_RHO_OLD, SC_ALPHA, SC_OMEGA, SC_RV, SC_TS, SC_TT, SC_RR, SC_NUM };
+enum { SC_RHO = 0, SC_RR, SC_RHO_OLD, SC_ALPHA, SC_OMEGA, SC_RV, SC_TS, SC_TT, SC_NUM };
 
 __global__ void k_sc_reset(double* sc) {
   sc[SC_RHO] = 1.0;
@@ -1099,6 +1185,56 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xr(double* __restrict__ x, doub
   const double a = sc[SC_ALPHA], w = sc[SC_OMEGA];
   x[t] += a * ph[t] + w * sh[t];
   r[t] = s[t] - w * tv[t];
+}
+
+// Fused BiCGStab vector steps. p = r + beta (p - omega v) (resp. s = r -
+// alpha v) also clears the preconditioner output z and, for mixed precision,
+// stores the preconditioner input bf = (float) p (resp. s), so no separate
+// conversion or fill pass is needed.
+template <typename Z>
+__global__ void __launch_bounds__(kBlock) k_bicg_p2(double* __restrict__ p, const double* __restrict__ r,
+                                                    const double* __restrict__ v, const double* __restrict__ sc,
+                                                    int64_t n, float* __restrict__ bf, Z* __restrict__ z) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double beta = (sc[SC_RHO] / sc[SC_RHO_OLD]) * (sc[SC_ALPHA] / sc[SC_OMEGA]);
+  const double pv = r[t] + beta * (p[t] - sc[SC_OMEGA] * v[t]);
+  p[t] = pv;
+  if (bf) bf[t] = (float)pv;
+  z[t] = Z(0);
+}
+
+template <typename Z>
+__global__ void __launch_bounds__(kBlock) k_bicg_s2(double* __restrict__ s, const double* __restrict__ r,
+                                                    const double* __restrict__ v, const double* __restrict__ sc,
+                                                    int64_t n, float* __restrict__ bf, Z* __restrict__ z) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double sv = r[t] - sc[SC_ALPHA] * v[t];
+  s[t] = sv;
+  if (bf) bf[t] = (float)sv;
+  z[t] = Z(0);
+}
+
+// x += alpha ph + omega sh ; r = s - omega t, with the partials of (rh, r)
+// and (r, r) for the next iteration (grid of kNormBlocks, the same
+// partition as k_dot_partial)
+template <typename Z>
+__global__ void __launch_bounds__(kBlock) k_bicg_xr2(double* __restrict__ x, double* __restrict__ r,
+                                                     const Z* __restrict__ ph, const Z* __restrict__ sh,
+                                                     const double* __restrict__ s, const double* __restrict__ tv,
+                                                     const double* __restrict__ rh, const double* __restrict__ sc,
+                                                     int64_t n, double* __restrict__ part) {
+  const double a = sc[SC_ALPHA], w = sc[SC_OMEGA];
+  double d0 = 0, d1 = 0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    x[t] += a * (double)ph[t] + w * (double)sh[t];
+    const double rv = s[t] - w * tv[t];
+    r[t] = rv;
+    d0 += rh[t] * rv;
+    d1 += rv * rv;
+  }
+  block_partials<kBlock>(d0, d1, 2, part, gridDim.x, blockIdx.x, threadIdx.x);
 }
 
 template <typename S, typename D>

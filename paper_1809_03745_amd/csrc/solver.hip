@@ -13,6 +13,7 @@
 #include <atomic>
 #include <chrono>
 #include <thread>
+#include <type_traits>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -121,8 +122,10 @@ struct DevProblem {
   DevBuf<double> objv;
   DevBuf<double> part, scal;
   double* host_scal = nullptr;
-  // BiCGStab work vectors: r, rh, p, v, ph, s, sh, t
+  // BiCGStab work vectors: r, rh, p, v, ph, s, sh, t; for mixed precision the
+  // preconditioner outputs stay FP32 (ph32, sh32) and are widened on use
   DevBuf<double> kv[8];
+  DevBuf<float> ph32, sh32;
   bool krylov = false;
   // coarse tail run by one workgroup: levels tail_l0 .. end (-1: none)
   int tail_l0 = -1;
@@ -137,6 +140,8 @@ struct DevProblem {
     iobj.release(); ecell.release(); erp.release(); ecol.release(); eobj.release(); eval.release();
     eface.release(); ecobj.release(); ecsig.release(); objv.release(); part.release(); scal.release();
     for (auto& k : kv) k.release();
+    ph32.release();
+    sh32.release();
     tail_lv.release();
     if (host_scal) (void)hipHostFree(host_scal);
     host_scal = nullptr;
@@ -222,6 +227,17 @@ static void fill(T* x, int64_t n, T v, hipStream_t s) {
 }
 
 // levels large enough for the fused out-of-place red/black sweep
+// 3D levels of at least this many cells take the z-marching residual kernel
+constexpr int64_t kResidZMMin = 1 << 18;
+
+// blocks of one matrix-vector product on a level (the partials it leaves)
+static int64_t matvec_blocks(const DevLevel& l) {
+  if (l.dim == 3 && l.N >= kResidZMMin)
+    return (int64_t)((l.n[0] + kRZX - 1) / kRZX) * ((l.n[1] + kRZY - 1) / kRZY) * ((l.n[2] + kRZ - 1) / kRZ) +
+           (int64_t)nblk(l.R * kSub);
+  return (int64_t)nblk(l.N) + (int64_t)nblk(l.R * kSub);
+}
+
 static bool fused_ok(const DevLevel& l) {
   return l.dim == 3 ? (l.N >= 32768 && l.n[0] >= 32) : (l.N >= 65536 && l.n[0] >= 64);
 }
@@ -554,7 +570,7 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
   D.ecobj.upload(ecobj.data(), NE, s, by);
   D.ecsig.upload(ecsig.data(), NE, s, by);
   D.objv.alloc(std::max<int64_t>(1, (int64_t)H.geo.obj_value.size()), by);
-  D.part.alloc(2 * kNormBlocks, by);
+  D.part.alloc(std::max<int64_t>(2 * kNormBlocks, 2 * matvec_blocks(D.lv[0])), by);
   D.scal.alloc(SC_NUM, by);
   HIPCHECK(hipHostMalloc((void**)&D.host_scal, SC_NUM * sizeof(double), hipHostMallocDefault));
   D.krylov = H.opt.krylov == 2;
@@ -573,8 +589,15 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
     upload_tail<double>(D, s);
     tune_tail<double>(D, H.opt, s);
   }
-  if (D.krylov)
-    for (auto& k : D.kv) k.alloc(L0.N + L0.N2, by);
+  if (D.krylov) {
+    // FP64 ph and sh (slots 4 and 6) only without mixed precision
+    for (int k = 0; k < 8; ++k)
+      if (!(mixed && (k == 4 || k == 6))) D.kv[k].alloc(L0.N + L0.N2, by);
+    if (mixed) {
+      D.ph32.alloc(L0.N + L0.N2, by);
+      D.sh32.alloc(L0.N + L0.N2, by);
+    }
+  }
   HIPCHECK(hipStreamSynchronize(s));
 }
 
@@ -673,9 +696,6 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
   }
   HIPCHECK(hipGetLastError());
 }
-
-// 3D levels of at least this many cells take the z-marching residual kernel
-constexpr int64_t kResidZMMin = 1 << 18;
 
 template <typename T, int MODE>
 static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
@@ -860,13 +880,64 @@ static void efield(ebmg_problem_s* P, const double* x, const double* sigma, cons
 // Right-preconditioned BiCGStab with the V-cycle as preconditioner; all
 // scalars stay on the device, one host synchronisation per iteration for the
 // convergence test. On entry L.x64 holds phi, L.r64 the residual b - A phi.
-static ebmg_status bicgstab(DevProblem& D, const Options& o, double bn, double rtol, int max_cycles, double& rel,
-                            int& cyc, ebmg_solve_info& info, hipStream_t s) {
+// out = A x on level 0 (x of type Z, widened exactly), with the dot products
+// (da, out) and, for ndot = 2, (out, out) into device slots slot, slot + 1,
+// from per-block partials of the same launches
+template <typename Z>
+static void matvec_dots(DevProblem& D, const Z* x, double* out, const double* da, int ndot, int slot, hipStream_t s) {
+  DevLevel& l = D.lv[0];
+  const Tmpl<double>& tp = l.t64;
+  const int64_t pt = matvec_blocks(l);
+  if (l.dim == 3 && l.N >= kResidZMMin) {
+    const dim3 g((l.n[0] + kRZX - 1) / kRZX, (l.n[1] + kRZY - 1) / kRZY, (l.n[2] + kRZ - 1) / kRZ);
+    const int64_t G = (int64_t)g.x * g.y * g.z;
+    if (ndot == 1) {
+      hipLaunchKernelGGL((k_resid_zm3<double, 1, Z, 1>), g, dim3(kRZX, kRZY), 0, s, l.tag.p, x, nullptr, out, tp, da,
+                         D.part.p, pt);
+      if (l.R > 0)
+        hipLaunchKernelGGL((k_resid_irr<double, 1, Z, 1>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R,
+                           l.irow_dof.p, l.rp.p, l.col.p, l.val64.p, l.diag64.p, x, nullptr, out, da, D.part.p, pt,
+                           G);
+    } else {
+      hipLaunchKernelGGL((k_resid_zm3<double, 1, Z, 2>), g, dim3(kRZX, kRZY), 0, s, l.tag.p, x, nullptr, out, tp, da,
+                         D.part.p, pt);
+      if (l.R > 0)
+        hipLaunchKernelGGL((k_resid_irr<double, 1, Z, 2>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R,
+                           l.irow_dof.p, l.rp.p, l.col.p, l.val64.p, l.diag64.p, x, nullptr, out, da, D.part.p, pt,
+                           G);
+    }
+  } else {
+    const unsigned nbc = nblk(l.N);
+    const dim3 g(nbc + nblk_sub(l.R));
+#define MV_ALL(DIM, ND)                                                                                           \
+  hipLaunchKernelGGL((k_resid_all<double, DIM, 1, Z, ND>), g, dim3(kBlock), 0, s, l.tag.p, x, nullptr, out, tp,   \
+                     nbc, (int)l.R, l.irow_dof.p, l.rp.p, l.col.p, l.val64.p, l.diag64.p, da, D.part.p, pt)
+    if (l.dim == 3) {
+      if (ndot == 1) MV_ALL(3, 1); else MV_ALL(3, 2);
+    } else {
+      if (ndot == 1) MV_ALL(2, 1); else MV_ALL(2, 2);
+    }
+#undef MV_ALL
+  }
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, s, D.part.p, (int)pt, ndot, D.scal.p + slot);
+  HIPCHECK(hipGetLastError());
+}
+
+// V-cycle-preconditioned BiCGStab (right preconditioning) with the vector
+// steps fused: each iteration is p-update, V-cycle, A ph with (rh, v),
+// s-update, V-cycle, A sh with (s, t) and (t, t), then the x/r update with
+// (rh, r) and (r, r) for the next iteration; one host sync per iteration.
+// Z is the preconditioner output type (FP32 for mixed precision).
+template <typename Z>
+static ebmg_status bicgstab_t(DevProblem& D, const Options& o, double bn, double rtol, int max_cycles, double& rel,
+                              int& cyc, ebmg_solve_info& info, Z* ph, Z* sh, hipStream_t s) {
   DevLevel& L = D.lv[0];
   const int64_t nd = L.N + L.N2;
+  const bool mixed = o.precision == EBMG_MIXED;
   double *r = D.kv[0].p, *rh = D.kv[1].p, *p = D.kv[2].p, *v = D.kv[3].p;
-  double *ph = D.kv[4].p, *sv = D.kv[5].p, *sh = D.kv[6].p, *t = D.kv[7].p;
+  double *sv = D.kv[5].p, *t = D.kv[7].p;
   double* x = L.x64.p;
+  float* bf = mixed ? L.b32.p : nullptr;
   const unsigned nb = nblk(nd);
   auto restart = [&]() {
     HIPCHECK(hipMemcpyAsync(r, L.r64.p, sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
@@ -874,25 +945,31 @@ static ebmg_status bicgstab(DevProblem& D, const Options& o, double bn, double r
     fill<double>(p, nd, 0.0, s);
     fill<double>(v, nd, 0.0, s);
     hipLaunchKernelGGL(k_sc_reset, dim3(1), dim3(1), 0, s, D.scal.p);
+    dot_dev<double>(D, rh, r, nd, SC_RHO, s);
+  };
+  auto vcyc = [&](Z* z, const double* in) {
+    if constexpr (std::is_same<Z, float>::value) {
+      (void)in;
+      vcycle<float>(D, o, 0, s, z, L.b32.p);
+    } else {
+      vcycle<double>(D, o, 0, s, z, in);
+    }
   };
   restart();
   int restarts = 0;
   while (rel > rtol) {
     if (cyc + 2 > max_cycles) return EBMG_ERR_NOCONV;
-    dot_dev<double>(D, rh, r, nd, SC_RHO, s);
-    hipLaunchKernelGGL(k_bicg_p, dim3(nb), dim3(kBlock), 0, s, p, r, v, D.scal.p, nd);
-    precond(D, o, p, ph, s);
-    residual<double, 1>(L, ph, nullptr, v, s);
-    dot_dev<double>(D, rh, v, nd, SC_RV, s);
+    hipLaunchKernelGGL((k_bicg_p2<Z>), dim3(nb), dim3(kBlock), 0, s, p, r, v, D.scal.p, nd, bf, ph);
+    vcyc(ph, p);
+    matvec_dots<Z>(D, ph, v, rh, 1, SC_RV, s);
     hipLaunchKernelGGL(k_sc_alpha, dim3(1), dim3(1), 0, s, D.scal.p);
-    hipLaunchKernelGGL(k_bicg_s, dim3(nb), dim3(kBlock), 0, s, sv, r, v, D.scal.p, nd);
-    precond(D, o, sv, sh, s);
-    residual<double, 1>(L, sh, nullptr, t, s);
-    hipLaunchKernelGGL(k_dot2_partial, dim3(kNormBlocks), dim3(kBlock), 0, s, t, sv, nd, D.part.p);
-    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, s, D.part.p, kNormBlocks, 2, D.scal.p + SC_TS);
+    hipLaunchKernelGGL((k_bicg_s2<Z>), dim3(nb), dim3(kBlock), 0, s, sv, r, v, D.scal.p, nd, bf, sh);
+    vcyc(sh, sv);
+    matvec_dots<Z>(D, sh, t, sv, 2, SC_TS, s);
     hipLaunchKernelGGL(k_sc_omega, dim3(1), dim3(1), 0, s, D.scal.p);
-    hipLaunchKernelGGL(k_bicg_xr, dim3(nb), dim3(kBlock), 0, s, x, r, ph, sh, sv, t, D.scal.p, nd);
-    dot_dev<double>(D, r, r, nd, SC_RR, s);
+    hipLaunchKernelGGL((k_bicg_xr2<Z>), dim3(kNormBlocks), dim3(kBlock), 0, s, x, r, ph, sh, sv, t, rh, D.scal.p, nd,
+                       D.part.p);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, s, D.part.p, kNormBlocks, 2, D.scal.p + SC_RHO);
     HIPCHECK(hipGetLastError());
     fetch_scalars(D, s);
     cyc += 2;
@@ -924,6 +1001,13 @@ static ebmg_status bicgstab(DevProblem& D, const Options& o, double bn, double r
     rel = nrel;
   }
   return EBMG_OK;
+}
+
+static ebmg_status bicgstab(DevProblem& D, const Options& o, double bn, double rtol, int max_cycles, double& rel,
+                            int& cyc, ebmg_solve_info& info, hipStream_t s) {
+  if (o.precision == EBMG_MIXED)
+    return bicgstab_t<float>(D, o, bn, rtol, max_cycles, rel, cyc, info, D.ph32.p, D.sh32.p, s);
+  return bicgstab_t<double>(D, o, bn, rtol, max_cycles, rel, cyc, info, D.kv[4].p, D.kv[6].p, s);
 }
 
 static ebmg_status solve(ebmg_problem_s* P, const double* rho, const double* sigma, const double* bcv,

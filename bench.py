@@ -169,7 +169,7 @@ def pmc_summary(fetch_csv, write_csv, command):
            "kernels": {}}
     zms = [f"k_rb_zm3<{t},{c}>" for t in ("float", "double") for c in ("64,8,32", "64,16,32", "32,16,32", "64,8,16")]
     for name in ["k_rb<float,3>", "k_rb<double,3>", "k_rb_tile3<float>", "k_rb_tile3<double>",
-                 "k_resid_reg<double,3,0>", "k_resid_zm3<double,0>"] + zms:
+                 "k_resid_reg<double,3,0>", "k_resid_zm3<double,0,double,0>"] + zms:
         keys = [k for k in f if k[0] == name]
         if not keys:
             continue
@@ -377,6 +377,7 @@ def main():
     label, unit_kind = _kernel_label(P, prec)
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     traffic = _traffic(label.split(" ")[0])
+    r_traffic = _traffic("k_resid_zm3<double,0,double,0>")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": label, "kernel_ms": round(k_ms, 5), "alg_bytes_per_launch": int(k_bytes),
@@ -409,6 +410,7 @@ def main():
         "setup_s": t_setup,
         "roofline": roof,
         "residual_kernel": {"kernel": "k_resid_zm3<double,0> (FP64 residual marching in z, finest level)", "ms": r_ms,
+                            "traffic": r_traffic,
                             "GB/s": r_bytes / (r_ms * 1e-3) / 1e9,
                             "frac": r_bytes / (r_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "tuning": tuning,

@@ -757,24 +757,40 @@ __global__ void __launch_bounds__(kRZX * kRZY) k_resid_zm3(const uint8_t* __rest
   }
   __syncthreads();
   const int nx = tp.n[0], ny = tp.n[1], nz = tp.n[2];
-  const int i = blockIdx.x * kRZX + threadIdx.x;
-  const int j = blockIdx.y * kRZY + threadIdx.y;
-  const int z0 = blockIdx.z * kRZ, z1 = min(z0 + kRZ, nz);
+  // 1D grid of tiles, numbered so that each XCD takes a contiguous range
+  // (neighbouring tiles then share that XCD's L2 for their halo rows)
+  const int gbx = (nx + kRZX - 1) / kRZX, gby = (ny + kRZY - 1) / kRZY;
+  const int64_t tt = xcd_block(blockIdx.x, gridDim.x);
+  const int i = (int)(tt % gbx) * kRZX + threadIdx.x;
+  const int j = (int)((tt / gbx) % gby) * kRZY + threadIdx.y;
+  const int z0 = (int)(tt / ((int64_t)gbx * gby)) * kRZ, z1 = min(z0 + kRZ, nz);
   double d0 = 0, d1 = 0;
   if (i < nx && j < ny) {
     const int64_t sxy = (int64_t)nx * ny;
     const int64_t c0 = i + (int64_t)nx * j;
+    // in-plane neighbour offsets (0 where the neighbour is outside the box:
+    // the loaded value is then not used)
+    const int64_t ow = i > 0 ? -1 : 0, oe = i < nx - 1 ? 1 : 0;
+    const int64_t os = j > 0 ? -(int64_t)nx : 0, on = j < ny - 1 ? (int64_t)nx : 0;
+    // everything a plane needs is requested one plane ahead, so the waits
+    // of a step only cover loads issued in the previous step
     T xm = z0 > 0 ? (T)x[c0 + sxy * (z0 - 1)] : T(0);
-    T xc = (T)x[c0 + sxy * z0];
-    T xp = z0 + 1 < nz ? (T)x[c0 + sxy * (z0 + 1)] : T(0);
-    uint8_t tg = tag[c0 + sxy * z0];
-    T bb = MODE == 0 ? b[c0 + sxy * z0] : T(0);
-    for (int k = z0; k < z1; ++k) {
-      const int64_t c = c0 + sxy * k;
-      // requests for the next step
+    int64_t c = c0 + sxy * z0;
+    T xc = (T)x[c];
+    T xp = z0 + 1 < nz ? (T)x[c + sxy] : T(0);
+    T w = (T)x[c + ow], e = (T)x[c + oe], so = (T)x[c + os], no = (T)x[c + on];
+    uint8_t tg = tag[c];
+    T bb = MODE == 0 ? b[c] : T(0);
+    T dc = NDOT > 0 ? da[c] : T(0);
+    for (int k = z0; k < z1; ++k, c += sxy) {
+      // requests for plane k + 1 (its neighbours, b and tag) and x of k + 2
+      const bool more = k + 1 < z1;
+      const int64_t cn = more ? c + sxy : c;
       const T xpp = k + 2 < nz ? (T)x[c + 2 * sxy] : T(0);
-      const uint8_t tgn = k + 1 < z1 ? tag[c + sxy] : (uint8_t)3;
-      const T bbn = (MODE == 0 && k + 1 < z1) ? b[c + sxy] : T(0);
+      const T wn = (T)x[cn + ow], en = (T)x[cn + oe], son = (T)x[cn + os], non = (T)x[cn + on];
+      const uint8_t tgn = more ? tag[cn] : (uint8_t)3;
+      const T bbn = (MODE == 0 && more) ? b[cn] : T(0);
+      const T dcn = (NDOT > 0 && more) ? da[cn] : T(0);
       const int p = tclass(tg);
       if (p != 2) {
         T out;
@@ -783,10 +799,10 @@ __global__ void __launch_bounds__(kRZX * kRZY) k_resid_zm3(const uint8_t* __rest
         } else {
           const T* tc = TC[p];
           T s = 0, dg = tc[1];
-          if (i > 0) s += (T)x[c - 1]; else dg += tc[2];
-          if (i < nx - 1) s += (T)x[c + 1]; else dg += tc[3];
-          if (j > 0) s += (T)x[c - nx]; else dg += tc[4];
-          if (j < ny - 1) s += (T)x[c + nx]; else dg += tc[5];
+          if (i > 0) s += w; else dg += tc[2];
+          if (i < nx - 1) s += e; else dg += tc[3];
+          if (j > 0) s += so; else dg += tc[4];
+          if (j < ny - 1) s += no; else dg += tc[5];
           if (k > 0) s += xm; else dg += tc[6];
           if (k < nz - 1) s += xp; else dg += tc[7];
           const T ax = dg * xc + tc[0] * s;
@@ -794,20 +810,24 @@ __global__ void __launch_bounds__(kRZX * kRZY) k_resid_zm3(const uint8_t* __rest
         }
         r[c] = out;
         if (NDOT > 0) {
-          d0 += (double)da[c] * (double)out;
+          d0 += (double)dc * (double)out;
           if (NDOT > 1) d1 += (double)out * (double)out;
         }
       }
       xm = xc;
       xc = xp;
       xp = xpp;
+      dc = dcn;
+      w = wn;
+      e = en;
+      so = son;
+      no = non;
       tg = tgn;
       bb = bbn;
     }
   }
   if (NDOT > 0)
-    block_partials<kRZX * kRZY>(d0, d1, NDOT, part, pt,
-                                blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z), tid);
+    block_partials<kRZX * kRZY>(d0, d1, NDOT, part, pt, blockIdx.x, tid);
 }
 
 template <typename T, int MODE, typename TX = T, int NDOT = 0>

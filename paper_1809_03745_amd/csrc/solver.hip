@@ -230,11 +230,14 @@ static void fill(T* x, int64_t n, T v, hipStream_t s) {
 // 3D levels of at least this many cells take the z-marching residual kernel
 constexpr int64_t kResidZMMin = 1 << 18;
 
+// tiles of the z-marching residual (a 1D grid)
+static int64_t zm_resid_blocks(const DevLevel& l) {
+  return (int64_t)((l.n[0] + kRZX - 1) / kRZX) * ((l.n[1] + kRZY - 1) / kRZY) * ((l.n[2] + kRZ - 1) / kRZ);
+}
+
 // blocks of one matrix-vector product on a level (the partials it leaves)
 static int64_t matvec_blocks(const DevLevel& l) {
-  if (l.dim == 3 && l.N >= kResidZMMin)
-    return (int64_t)((l.n[0] + kRZX - 1) / kRZX) * ((l.n[1] + kRZY - 1) / kRZY) * ((l.n[2] + kRZ - 1) / kRZ) +
-           (int64_t)nblk(l.R * kSub);
+  if (l.dim == 3 && l.N >= kResidZMMin) return zm_resid_blocks(l) + (int64_t)nblk(l.R * kSub);
   return (int64_t)nblk(l.N) + (int64_t)nblk(l.R * kSub);
 }
 
@@ -701,7 +704,7 @@ template <typename T, int MODE>
 static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
   if (l.dim == 3 && l.N >= kResidZMMin) {
-    const dim3 g((l.n[0] + kRZX - 1) / kRZX, (l.n[1] + kRZY - 1) / kRZY, (l.n[2] + kRZ - 1) / kRZ);
+    const dim3 g((unsigned)zm_resid_blocks(l));
     hipLaunchKernelGGL((k_resid_zm3<T, MODE>), g, dim3(kRZX, kRZY), 0, s, l.tag.p, x, b, r, tp);
     if (l.R > 0)
       hipLaunchKernelGGL((k_resid_irr<T, MODE>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R, l.irow_dof.p,
@@ -889,8 +892,8 @@ static void matvec_dots(DevProblem& D, const Z* x, double* out, const double* da
   const Tmpl<double>& tp = l.t64;
   const int64_t pt = matvec_blocks(l);
   if (l.dim == 3 && l.N >= kResidZMMin) {
-    const dim3 g((l.n[0] + kRZX - 1) / kRZX, (l.n[1] + kRZY - 1) / kRZY, (l.n[2] + kRZ - 1) / kRZ);
-    const int64_t G = (int64_t)g.x * g.y * g.z;
+    const dim3 g((unsigned)zm_resid_blocks(l));
+    const int64_t G = (int64_t)g.x;
     if (ndot == 1) {
       hipLaunchKernelGGL((k_resid_zm3<double, 1, Z, 1>), g, dim3(kRZX, kRZY), 0, s, l.tag.p, x, nullptr, out, tp, da,
                          D.part.p, pt);
@@ -1618,7 +1621,7 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
         }
       } else {
         if (L.dim == 3 && L.N >= kResidZMMin) {
-          const dim3 g((L.n[0] + kRZX - 1) / kRZX, (L.n[1] + kRZY - 1) / kRZY, (L.n[2] + kRZ - 1) / kRZ);
+          const dim3 g((unsigned)zm_resid_blocks(L));
           hipLaunchKernelGGL((k_resid_zm3<double, 0>), g, dim3(kRZX, kRZY), 0, s, L.tag.p, L.x64.p, L.b64.p,
                              L.r64.p, L.t64);
         } else if (L.dim == 3) {

@@ -18,7 +18,7 @@
 
 namespace ebmg {
 
-constexpr int kBE = 1024;       // threads of an engine workgroup
+constexpr int kBE = 512;        // threads of an engine workgroup (two per CU)
 constexpr int kMaxLev = 16;
 
 // Device view of one multigrid level (all pointers device memory).
@@ -52,41 +52,98 @@ struct BLev {
 
 template <typename T>
 __device__ void be_fill(T* x, int n, T v) {
-  for (int t = threadIdx.x; t < n; t += blockDim.x) x[t] = v;
+  _Pragma("unroll 4") for (int t = threadIdx.x; t < n; t += blockDim.x) x[t] = v;
   __syncthreads();
 }
 
+// Loops below handle U cells per thread per iteration and issue all their
+// loads before the first use (neighbours at clamped, always valid
+// addresses), so a thread has U dependent load chains in flight instead of
+// one; a workgroup walks a whole box alone, so that parallelism is its only
+// way to cover memory latency.
+template <typename T>
+struct BeU {
+  static constexpr int U = sizeof(T) == 4 ? 4 : 2;
+};
+
 template <typename T, int DIM>
 __device__ void be_rb(const BLev<T>& L, T* __restrict__ x, const T* __restrict__ b, int colour) {
-  const int nx = L.n[0], ny = L.n[1];
+  constexpr int U = BeU<T>::U;
+  const int nx = L.n[0], ny = L.n[1], nz = DIM == 3 ? L.n[2] : 1;
   const int nxh = (nx + 1) >> 1;
-  const int nthr = nxh * ny * (DIM == 3 ? L.n[2] : 1);
-  for (int t = threadIdx.x; t < nthr; t += blockDim.x) {
-    const int ih = t % nxh;
-    const int jk = t / nxh;
-    const int j = jk % ny;
-    const int k = DIM == 3 ? jk / ny : 0;
-    const int i = 2 * ih + ((j + k + colour) & 1);
-    if (i >= nx) continue;
-    const int64_t c = i + (int64_t)nx * jk;
-    const uint8_t p = tclass(L.tag[c]);
-    if (p > 1) continue;
-    T dg;
-    const T off = template_apply<T, DIM>(x, L.tp, i, j, k, c, p, dg);
-    x[c] = (b[c] - off) * (T(1) / dg);
+  const int nthr = nxh * ny * nz;
+  const int64_t sxy = (int64_t)nx * ny;
+  const int64_t last = (int64_t)nx * ny * nz - 1;
+  const Tmpl<T> tp = L.tp;
+  const uint8_t* __restrict__ tag = L.tag;
+  for (int t0 = threadIdx.x; t0 < nthr; t0 += blockDim.x * U) {
+    int64_t cc[U];
+    int ii[U], jj[U], kk[U];
+    bool act[U];
+    uint8_t tg[U];
+    T v[U][6], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x;
+      const int tt = t < nthr ? t : 0;
+      const int ih = tt % nxh;
+      const int jk = tt / nxh;
+      const int j = jk % ny;
+      const int k = DIM == 3 ? jk / ny : 0;
+      const int i0 = 2 * ih + ((j + k + colour) & 1);
+      act[u] = t < nthr && i0 < nx;
+      // inactive lanes take cell 0 with all coordinates 0, so every address
+      // below stays inside the level (neighbours only towards higher
+      // indices, clamped to the last cell)
+      const int i = act[u] ? i0 : 0;
+      const int jj0 = act[u] ? j : 0;
+      const int kk0 = act[u] ? k : 0;
+      const int64_t c = act[u] ? i + (int64_t)nx * jk : 0;
+      cc[u] = c;
+      ii[u] = i;
+      jj[u] = jj0;
+      kk[u] = kk0;
+      tg[u] = tag[c];
+      bv[u] = b[c];
+      v[u][0] = x[i > 0 ? c - 1 : c];
+      v[u][1] = x[min(i < nx - 1 ? c + 1 : c, last)];
+      v[u][2] = x[jj0 > 0 ? c - nx : c];
+      v[u][3] = x[min(jj0 < ny - 1 ? c + nx : c, last)];
+      if (DIM == 3) {
+        v[u][4] = x[kk0 > 0 ? c - sxy : c];
+        v[u][5] = x[min(kk0 < nz - 1 ? c + sxy : c, last)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = tclass(tg[u]);
+      if (!act[u] || p > 1) continue;
+      T s = 0, dg = tp.D0(p);
+      if (ii[u] > 0) s += v[u][0]; else dg += tp.CB(0, p);
+      if (ii[u] < nx - 1) s += v[u][1]; else dg += tp.CB(1, p);
+      if (jj[u] > 0) s += v[u][2]; else dg += tp.CB(2, p);
+      if (jj[u] < ny - 1) s += v[u][3]; else dg += tp.CB(3, p);
+      if (DIM == 3) {
+        if (kk[u] > 0) s += v[u][4]; else dg += tp.CB(4, p);
+        if (kk[u] < nz - 1) s += v[u][5]; else dg += tp.CB(5, p);
+      }
+      x[cc[u]] = (bv[u] - tp.CO(p) * s) * (T(1) / dg);
+    }
   }
   __syncthreads();
 }
 
+// Explicit rows of a colour group, kSub lanes per row (as the grid-wide
+// kernels), Jacobi within the group: new values to w, then scattered.
 template <typename T>
 __device__ void be_irr_group(const BLev<T>& L, int grp, T* __restrict__ x, const T* __restrict__ b) {
   const int r0 = L.grp_ptr[grp], r1 = L.grp_ptr[grp + 1];
   if (r1 <= r0) return;
-  for (int g = r0 + threadIdx.x; g < r1; g += blockDim.x) {
+  const int lane = threadIdx.x % kSub;
+  for (int g = r0 + (int)threadIdx.x / kSub; g < r1; g += (int)blockDim.x / kSub) {
     const int r = L.grp_rows[g];
-    T s = 0;
-    for (int64_t e = L.rp[r]; e < L.rp[r + 1]; ++e) s += L.val[e] * x[L.col[e]];
-    L.w[g - r0] = (b[L.irow_dof[r]] - s) / L.diag[r];
+    const T s = row_dot<T>(L.rp[r], L.rp[r + 1], L.col, L.val, x, lane);
+    if (lane == 0) L.w[g - r0] = (b[L.irow_dof[r]] - s) / L.diag[r];
   }
   __syncthreads();
   for (int g = r0 + threadIdx.x; g < r1; g += blockDim.x) x[L.irow_dof[L.grp_rows[g]]] = L.w[g - r0];
@@ -105,87 +162,172 @@ __device__ void be_smooth(const BLev<T>& L, T* x, const T* b, int sweeps) {
 // MODE 0: r = b - A x; MODE 1: r = A x
 template <typename T, int DIM, int MODE>
 __device__ void be_resid(const BLev<T>& L, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ r) {
-  const int nx = L.n[0], ny = L.n[1];
-  for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
-    const uint8_t p = tclass(L.tag[c]);
-    if (p == 3) {
-      r[c] = MODE == 0 ? T(0) : x[c];
-      continue;
+  constexpr int U = BeU<T>::U;
+  const int nx = L.n[0], ny = L.n[1], nz = DIM == 3 ? L.n[2] : 1;
+  const int64_t sxy = (int64_t)nx * ny;
+  const Tmpl<T> tp = L.tp;
+  const uint8_t* __restrict__ tag = L.tag;
+  const int N = L.N;
+  for (int c0 = threadIdx.x; c0 < N; c0 += blockDim.x * U) {
+    int ii[U], jj[U], kk[U], cc[U];
+    uint8_t tg[U];
+    T v[U][7], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c1 = c0 + u * (int)blockDim.x;
+      const int c = c1 < N ? c1 : 0;
+      const int i = c % nx;
+      const int jk = c / nx;
+      const int j = jk % ny;
+      const int k = DIM == 3 ? jk / ny : 0;
+      cc[u] = c1;
+      ii[u] = i;
+      jj[u] = j;
+      kk[u] = k;
+      tg[u] = tag[c];
+      bv[u] = MODE == 0 ? b[c] : T(0);
+      v[u][6] = x[c];
+      v[u][0] = x[i > 0 ? c - 1 : c];
+      v[u][1] = x[min(i < nx - 1 ? c + 1 : c, N - 1)];
+      v[u][2] = x[j > 0 ? c - nx : c];
+      v[u][3] = x[min(j < ny - 1 ? c + nx : c, N - 1)];
+      if (DIM == 3) {
+        v[u][4] = x[k > 0 ? c - (int)sxy : c];
+        v[u][5] = x[min(k < nz - 1 ? c + (int)sxy : c, N - 1)];
+      }
     }
-    if (p == 2) continue;
-    const int i = c % nx;
-    const int jk = c / nx;
-    const int j = jk % ny;
-    const int k = DIM == 3 ? jk / ny : 0;
-    T dg;
-    const T off = template_apply<T, DIM>(x, L.tp, i, j, k, c, p, dg);
-    const T ax = dg * x[c] + off;
-    r[c] = MODE == 0 ? b[c] - ax : ax;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (cc[u] >= N) continue;
+      const int p = tclass(tg[u]);
+      if (p == 2) continue;
+      if (p == 3) {
+        r[cc[u]] = MODE == 0 ? T(0) : v[u][6];
+        continue;
+      }
+      T s = 0, dg = tp.D0(p);
+      if (ii[u] > 0) s += v[u][0]; else dg += tp.CB(0, p);
+      if (ii[u] < nx - 1) s += v[u][1]; else dg += tp.CB(1, p);
+      if (jj[u] > 0) s += v[u][2]; else dg += tp.CB(2, p);
+      if (jj[u] < ny - 1) s += v[u][3]; else dg += tp.CB(3, p);
+      if (DIM == 3) {
+        if (kk[u] > 0) s += v[u][4]; else dg += tp.CB(4, p);
+        if (kk[u] < nz - 1) s += v[u][5]; else dg += tp.CB(5, p);
+      }
+      const T ax = dg * v[u][6] + tp.CO(p) * s;
+      r[cc[u]] = MODE == 0 ? bv[u] - ax : ax;
+    }
   }
-  for (int g = threadIdx.x; g < L.R; g += blockDim.x) {
+  const int lane = threadIdx.x % kSub;
+  for (int g = (int)threadIdx.x / kSub; g < L.R; g += (int)blockDim.x / kSub) {
     const int64_t q = L.irow_dof[g];
-    T s = 0;
-    for (int64_t e = L.rp[g]; e < L.rp[g + 1]; ++e) s += L.val[e] * x[L.col[e]];
-    const T ax = L.diag[g] * x[q] + s;
-    r[q] = MODE == 0 ? b[q] - ax : ax;
+    const T s = row_dot<T>(L.rp[g], L.rp[g + 1], L.col, L.val, x, lane);
+    if (lane == 0) {
+      const T ax = L.diag[g] * x[q] + s;
+      r[q] = MODE == 0 ? b[q] - ax : ax;
+    }
   }
   __syncthreads();
 }
 
 template <typename T, int DIM>
 __device__ void be_restrict(const BLev<T>& F, const BLev<T>& Cl, const T* __restrict__ rf, T* __restrict__ bc) {
+  constexpr int U = BeU<T>::U;
   const int cnx = Cl.n[0], cny = Cl.n[1];
   const int fnx = 2 * cnx;
   const int64_t fsxy = (int64_t)fnx * 2 * cny;
-  for (int P = threadIdx.x; P < Cl.N; P += blockDim.x) {
-    const uint8_t t = Cl.tag[P];
-    if (tclass(t) == 3) {
-      bc[P] = 0;
-      continue;
+  const int CN = Cl.N;
+  const T w = DIM == 3 ? T(0.125) : T(0.25);
+  for (int P0 = threadIdx.x; P0 < CN; P0 += blockDim.x * U) {
+    T v[U][8];
+    uint8_t tg[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int P1 = P0 + u * (int)blockDim.x;
+      const int P = P1 < CN ? P1 : 0;
+      const int I = P % cnx;
+      const int JK = P / cnx;
+      const int J = JK % cny;
+      const int K = DIM == 3 ? JK / cny : 0;
+      const int64_t c0 = 2 * I + (int64_t)fnx * (2 * J) + (DIM == 3 ? fsxy * (2 * K) : 0);
+      tg[u] = Cl.tag[P];
+      v[u][0] = rf[c0];
+      v[u][1] = rf[c0 + 1];
+      v[u][2] = rf[c0 + fnx];
+      v[u][3] = rf[c0 + fnx + 1];
+      if (DIM == 3) {
+        v[u][4] = rf[c0 + fsxy];
+        v[u][5] = rf[c0 + fsxy + 1];
+        v[u][6] = rf[c0 + fsxy + fnx];
+        v[u][7] = rf[c0 + fsxy + fnx + 1];
+      }
     }
-    if (t & 4) continue;
-    const int I = P % cnx;
-    const int JK = P / cnx;
-    const int J = JK % cny;
-    const int K = DIM == 3 ? JK / cny : 0;
-    const int64_t c0 = 2 * I + (int64_t)fnx * (2 * J) + (DIM == 3 ? fsxy * (2 * K) : 0);
-    T s = rf[c0] + rf[c0 + 1] + rf[c0 + fnx] + rf[c0 + fnx + 1];
-    if (DIM == 3) s += rf[c0 + fsxy] + rf[c0 + fsxy + 1] + rf[c0 + fsxy + fnx] + rf[c0 + fsxy + fnx + 1];
-    bc[P] = s * (DIM == 3 ? T(0.125) : T(0.25));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int P = P0 + u * (int)blockDim.x;
+      if (P >= CN) continue;
+      if (tclass(tg[u]) == 3) {
+        bc[P] = 0;
+        continue;
+      }
+      if (tg[u] & 4) continue;
+      T s = v[u][0] + v[u][1] + v[u][2] + v[u][3];
+      if (DIM == 3) s += v[u][4] + v[u][5] + v[u][6] + v[u][7];
+      bc[P] = s * w;
+    }
   }
   for (int t = threadIdx.x; t < F.n_ns; t += blockDim.x) {
     T s = 0;
     for (int e = F.ns_ptr[t]; e < F.ns_ptr[t + 1]; ++e) s += rf[F.ns_child[e]];
-    bc[F.ns_cdof[t]] = s * (DIM == 3 ? T(0.125) : T(0.25));
+    bc[F.ns_cdof[t]] = s * w;
   }
   __syncthreads();
 }
 
 template <typename T, int DIM>
 __device__ void be_prolong(const BLev<T>& F, const BLev<T>& Cl, const T* __restrict__ ec, T* __restrict__ xf) {
+  constexpr int U = BeU<T>::U;
   const int fnx = F.n[0], fny = F.n[1];
   const int cnx = fnx >> 1, cny = fny >> 1;
-  for (int c = threadIdx.x; c < F.N; c += blockDim.x) {
-    if (tclass(F.tag[c]) == 3) continue;
-    const int i = c % fnx;
-    const int jk = c / fnx;
-    const int j = jk % fny;
-    const int k = DIM == 3 ? jk / fny : 0;
-    const int P = (i >> 1) + cnx * ((j >> 1) + cny * (k >> 1));
-    if (Cl.tag[P] & 4) continue;
-    xf[c] += ec[P];
+  const int FN = F.N;
+  for (int c0 = threadIdx.x; c0 < FN; c0 += blockDim.x * U) {
+    T e[U], xv[U];
+    uint8_t ft[U], ct[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c1 = c0 + u * (int)blockDim.x;
+      const int c = c1 < FN ? c1 : 0;
+      const int i = c % fnx;
+      const int jk = c / fnx;
+      const int j = jk % fny;
+      const int k = DIM == 3 ? jk / fny : 0;
+      const int P = (i >> 1) + cnx * ((j >> 1) + cny * (k >> 1));
+      ft[u] = F.tag[c];
+      ct[u] = Cl.tag[P];
+      e[u] = ec[P];
+      xv[u] = xf[c];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * (int)blockDim.x;
+      if (c >= FN || tclass(ft[u]) == 3 || (ct[u] & 4)) continue;
+      xf[c] = xv[u] + e[u];
+    }
   }
   for (int t = threadIdx.x; t < F.n_np; t += blockDim.x) xf[F.np_fdof[t]] += ec[F.np_cdof[t]];
   __syncthreads();
 }
 
-// x = Ainv b on the bottom level (FP64 accumulation), thread per row
+// x = Ainv b on the bottom level (FP64 accumulation): one wavefront per row,
+// lanes over columns (coalesced), fixed-order shuffle reduction
 template <typename T>
 __device__ void be_bottom(const double* __restrict__ Ainv, int n, const T* __restrict__ b, T* __restrict__ x) {
-  for (int row = threadIdx.x; row < n; row += blockDim.x) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  for (int row = wave; row < n; row += nwaves) {
     double s = 0;
-    for (int c = 0; c < n; ++c) s += Ainv[(int64_t)row * n + c] * (double)b[c];
-    x[row] = (T)s;
+    for (int c = lane; c < n; c += 64) s += Ainv[(int64_t)row * n + c] * (double)b[c];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) x[row] = (T)s;
   }
   __syncthreads();
 }
@@ -278,7 +420,7 @@ struct BRes {
 // deterministic workgroup dot product (fixed-order tree in LDS)
 __device__ inline double be_dot(const double* __restrict__ a, const double* __restrict__ b, int n, double* red) {
   double s = 0;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) s += a[t] * b[t];
+  _Pragma("unroll 4") for (int t = threadIdx.x; t < n; t += blockDim.x) s += a[t] * b[t];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
@@ -333,19 +475,19 @@ template <typename T, int DIM>
 __device__ void be_precond(const BBox<T>& B, const BLev<T>* lv, int nu1, int nu2, const double* r, double* z) {
   const int nd = B.N + B.N2;
   if (sizeof(T) == sizeof(double)) {
-    for (int t = threadIdx.x; t < nd; t += blockDim.x) z[t] = 0.0;
+    _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) z[t] = 0.0;
     __syncthreads();
     be_vcycle<T, DIM>(lv, 0, B.nlev, B.Ainv, B.nbot, nu1, nu2, (T*)z, (const T*)r);
   } else {
     T* x0 = lv[0].x;
     T* b0 = lv[0].b;
-    for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+    _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) {
       b0[t] = (T)r[t];
       x0[t] = T(0);
     }
     __syncthreads();
     be_vcycle<T, DIM>(lv, 0, B.nlev, B.Ainv, B.nbot, nu1, nu2, x0, b0);
-    for (int t = threadIdx.x; t < nd; t += blockDim.x) z[t] = (double)x0[t];
+    _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) z[t] = (double)x0[t];
     __syncthreads();
   }
 }
@@ -360,7 +502,7 @@ __device__ void be_solve_box(const BBox<T>& B, const BIO& io, BRes& out, double 
   double* b = F.b;
   be_rhs<DIM>(F, B.dat, B.fv, B.icell, B.isrc, B.iface, B.iobj, B.icobj, B.icsig, B.objv, io.rho, io.sigma,
               b);
-  for (int t = threadIdx.x; t < nd; t += blockDim.x) x[t] = t < N ? io.phi[t] : (io.phi2 ? io.phi2[t - N] : 0.0);
+  _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) x[t] = t < N ? io.phi[t] : (io.phi2 ? io.phi2[t - N] : 0.0);
   __syncthreads();
   const double bn = sqrt(be_dot(b, b, nd, red));
   int status = 0, cycles = 0, iters = 0;
@@ -379,7 +521,7 @@ __device__ void be_solve_box(const BBox<T>& B, const BIO& io, BRes& out, double 
           break;
         }
         be_precond<T, DIM>(B, lv, nu1, nu2, r, e);
-        for (int t = threadIdx.x; t < nd; t += blockDim.x) x[t] += e[t];
+        _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) x[t] += e[t];
         __syncthreads();
         ++cycles;
         ++iters;
@@ -395,7 +537,7 @@ __device__ void be_solve_box(const BBox<T>& B, const BIO& io, BRes& out, double 
              *tv = B.kv[7];
       int restarts = 0;
       double rho_old = 1, alpha = 1, omega = 1;
-      for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+      _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) {
         rh[t] = r[t];
         p[t] = 0;
         v[t] = 0;
@@ -408,12 +550,12 @@ __device__ void be_solve_box(const BBox<T>& B, const BIO& io, BRes& out, double 
         }
         const double rho = be_dot(rh, r, nd, red);
         const double beta = (rho / rho_old) * (alpha / omega);
-        for (int t = threadIdx.x; t < nd; t += blockDim.x) p[t] = r[t] + beta * (p[t] - omega * v[t]);
+        _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) p[t] = r[t] + beta * (p[t] - omega * v[t]);
         __syncthreads();
         be_precond<T, DIM>(B, lv, nu1, nu2, p, ph);
         be_resid<double, DIM, 1>(F, ph, nullptr, v);
         alpha = rho / be_dot(rh, v, nd, red);
-        for (int t = threadIdx.x; t < nd; t += blockDim.x) sv[t] = r[t] - alpha * v[t];
+        _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) sv[t] = r[t] - alpha * v[t];
         __syncthreads();
         be_precond<T, DIM>(B, lv, nu1, nu2, sv, sh);
         be_resid<double, DIM, 1>(F, sh, nullptr, tv);
@@ -421,7 +563,7 @@ __device__ void be_solve_box(const BBox<T>& B, const BIO& io, BRes& out, double 
         const double tt = be_dot(tv, tv, nd, red);
         omega = tt > 0 ? ts / tt : 0.0;
         rho_old = rho;
-        for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+        _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) {
           x[t] += alpha * ph[t] + omega * sh[t];
           r[t] = sv[t] - omega * tv[t];
         }
@@ -444,7 +586,7 @@ __device__ void be_solve_box(const BBox<T>& B, const BIO& io, BRes& out, double 
               status = EBMG_ERR_NOCONV;
               break;
             }
-            for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+            _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) {
               rh[t] = r[t];
               p[t] = 0;
               v[t] = 0;
@@ -461,10 +603,10 @@ __device__ void be_solve_box(const BBox<T>& B, const BIO& io, BRes& out, double 
       }
     }
   } else {
-    for (int t = threadIdx.x; t < nd; t += blockDim.x) x[t] = 0;
+    _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) x[t] = 0;
     __syncthreads();
   }
-  for (int t = threadIdx.x; t < nd; t += blockDim.x) {
+  _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) {
     if (t < N)
       io.phi[t] = x[t];
     else if (io.phi2)

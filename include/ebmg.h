@@ -117,7 +117,12 @@ typedef struct {
   int32_t tail;             /* coarse levels: 0 autotuned at setup, 1 always by
                                grid-wide launches, 2 always by the one-workgroup
                                engine from the first level of <= 32768 unknowns */
-  int32_t reserved[5];      /* must be zero                                      */
+  int32_t batch;            /* batched solves (ebmg_setup_batch; one value for all
+                               boxes): 0 or 2 level-synchronous (every phase one
+                               launch over all boxes, coarse levels per box in
+                               one workgroup), 1 one persistent launch with one
+                               workgroup per box                                 */
+  int32_t reserved[4];      /* must be zero                                      */
 } ebmg_options;
 
 typedef struct {
@@ -263,10 +268,24 @@ ebmg_status ebmg_setup_batch(ebmg_ctx ctx, int32_t nbox, const ebmg_box* boxes, 
 /* Total cells, second-phase unknowns and device bytes of a batch. */
 ebmg_status ebmg_query_batch(ebmg_batch bt, int64_t* cells, int64_t* cells2, int64_t* device_bytes);
 
-/* Solve every box in ONE persistent launch: workgroups of 1024 threads take
- * boxes (largest first, fixed assignment) and run the whole solve in-group:
- * right-hand side, FP64 residual, V-cycle (FP32 for mixed precision) as the
- * BiCGStab preconditioner or as plain refinement, to ||r|| <= rtol ||b||.
+/* Setup choices of a batch: mode (1 persistent, 2 level-synchronous), the
+ * coarse-part threshold (a box's levels of at most this many unknowns run in
+ * one workgroup; 0: only the bottom level), the number of levels run by
+ * grid-wide launches, and the timed candidates (up to 8 thresholds and V-cycle
+ * ms; ncand receives their count). Any output may be NULL. */
+ebmg_status ebmg_query_batch_tuning(ebmg_batch bt, int32_t* mode, int32_t* tail_cells, int32_t* wide_levels,
+                                    int32_t* ncand, int32_t* cand_cells, double* cand_ms);
+
+/* Solve every box to ||r|| <= rtol ||b||: right-hand side, FP64 residual,
+ * V-cycle (FP32 for mixed precision) as the BiCGStab preconditioner or as
+ * plain refinement. With options.batch == 1, in ONE persistent launch:
+ * workgroups of 512 threads take boxes (largest first, fixed assignment)
+ * and run the whole solve in-group. Otherwise level-synchronous: each phase
+ * is one launch over the chunks of all boxes (levels down to a size tuned at
+ * setup), each box's coarser levels and bottom solve run in one workgroup,
+ * and the Krylov scalars, tests and restarts are kept per box on the device;
+ * cycles are then counted in pairs (two preconditioner applications per
+ * iteration, also for plain refinement).
  * rho[i], sigma[i] (sigma or its entries may be NULL), phi[i] (in: guess,
  * out: solution) and phi2[i] (may be NULL when the box has no second-phase
  * unknowns) are DEVICE arrays of box i; the pointer arrays themselves are

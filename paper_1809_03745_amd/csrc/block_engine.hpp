@@ -66,8 +66,26 @@ struct BeU {
   static constexpr int U = sizeof(T) == 4 ? 4 : 2;
 };
 
+// Every phase below comes as a "part" over the work items [beg, beg + cnt)
+// of a level (cells, rows or list entries; cnt may run past the end), with
+// no barrier, so that the persistent engine (one workgroup, the whole range)
+// and the level-synchronous batched kernels (one chunk per workgroup) run
+// the same code.
+__device__ __forceinline__ int be_end(int n, int beg, int cnt) {
+  return (int)min((int64_t)n, (int64_t)beg + cnt);
+}
+constexpr int kAll = 0x7fffffff;
+// The engine's phases run inlined into different kernels (the persistent
+// solver, the coarse-tail kernel and the level-synchronous kernels); with
+// contraction left to the backend, a product-plus-sum could become an FMA in
+// one inlining and not in another. Every product is rounded on its own
+// instead, so a phase gives the same bits wherever it runs.
+#define FP_EXACT_ORDER _Pragma("clang fp contract(off)")
+
 template <typename T, int DIM>
-__device__ void be_rb(const BLev<T>& L, T* __restrict__ x, const T* __restrict__ b, int colour) {
+__device__ void be_rb_part(const BLev<T>& L, T* __restrict__ x, const T* __restrict__ b, int colour, int beg,
+                           int cnt) {
+  FP_EXACT_ORDER
   constexpr int U = BeU<T>::U;
   const int nx = L.n[0], ny = L.n[1], nz = DIM == 3 ? L.n[2] : 1;
   const int nxh = (nx + 1) >> 1;
@@ -76,7 +94,8 @@ __device__ void be_rb(const BLev<T>& L, T* __restrict__ x, const T* __restrict__
   const int64_t last = (int64_t)nx * ny * nz - 1;
   const Tmpl<T> tp = L.tp;
   const uint8_t* __restrict__ tag = L.tag;
-  for (int t0 = threadIdx.x; t0 < nthr; t0 += blockDim.x * U) {
+  const int end = be_end(nthr, beg, cnt);
+  for (int t0 = beg + (int)threadIdx.x; t0 < end; t0 += blockDim.x * U) {
     int64_t cc[U];
     int ii[U], jj[U], kk[U];
     bool act[U];
@@ -130,23 +149,43 @@ __device__ void be_rb(const BLev<T>& L, T* __restrict__ x, const T* __restrict__
       x[cc[u]] = (bv[u] - tp.CO(p) * s) * (T(1) / dg);
     }
   }
+}
+
+template <typename T, int DIM>
+__device__ void be_rb(const BLev<T>& L, T* __restrict__ x, const T* __restrict__ b, int colour) {
+  be_rb_part<T, DIM>(L, x, b, colour, 0, kAll);
   __syncthreads();
 }
 
 // Explicit rows of a colour group, kSub lanes per row (as the grid-wide
 // kernels), Jacobi within the group: new values to w, then scattered.
 template <typename T>
-__device__ void be_irr_group(const BLev<T>& L, int grp, T* __restrict__ x, const T* __restrict__ b) {
-  const int r0 = L.grp_ptr[grp], r1 = L.grp_ptr[grp + 1];
-  if (r1 <= r0) return;
+__device__ void be_irr_jac_part(const BLev<T>& L, int grp, const T* __restrict__ x, const T* __restrict__ b,
+                                int beg, int cnt) {
+  FP_EXACT_ORDER
+  const int r0 = L.grp_ptr[grp];
+  const int end = r0 + be_end(L.grp_ptr[grp + 1] - r0, beg, cnt);
   const int lane = threadIdx.x % kSub;
-  for (int g = r0 + (int)threadIdx.x / kSub; g < r1; g += (int)blockDim.x / kSub) {
+  for (int g = r0 + beg + (int)threadIdx.x / kSub; g < end; g += (int)blockDim.x / kSub) {
     const int r = L.grp_rows[g];
     const T s = row_dot<T>(L.rp[r], L.rp[r + 1], L.col, L.val, x, lane);
     if (lane == 0) L.w[g - r0] = (b[L.irow_dof[r]] - s) / L.diag[r];
   }
+}
+
+template <typename T>
+__device__ void be_irr_scat_part(const BLev<T>& L, int grp, T* __restrict__ x, int beg, int cnt) {
+  const int r0 = L.grp_ptr[grp];
+  const int end = r0 + be_end(L.grp_ptr[grp + 1] - r0, beg, cnt);
+  for (int g = r0 + beg + (int)threadIdx.x; g < end; g += blockDim.x) x[L.irow_dof[L.grp_rows[g]]] = L.w[g - r0];
+}
+
+template <typename T>
+__device__ void be_irr_group(const BLev<T>& L, int grp, T* __restrict__ x, const T* __restrict__ b) {
+  if (L.grp_ptr[grp + 1] <= L.grp_ptr[grp]) return;
+  be_irr_jac_part<T>(L, grp, x, b, 0, kAll);
   __syncthreads();
-  for (int g = r0 + threadIdx.x; g < r1; g += blockDim.x) x[L.irow_dof[L.grp_rows[g]]] = L.w[g - r0];
+  be_irr_scat_part<T>(L, grp, x, 0, kAll);
   __syncthreads();
 }
 
@@ -159,16 +198,22 @@ __device__ void be_smooth(const BLev<T>& L, T* x, const T* b, int sweeps) {
     }
 }
 
-// MODE 0: r = b - A x; MODE 1: r = A x
-template <typename T, int DIM, int MODE>
-__device__ void be_resid(const BLev<T>& L, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ r) {
+// MODE 0: r = b - A x; MODE 1: r = A x. x may be narrower than T (FP32
+// input widened on load). NDOT >= 1 adds da[q] * r[q] over the unknowns this
+// part writes to acc0, NDOT == 2 also r[q]^2 to acc1.
+template <typename T, typename TX, int DIM, int MODE, int NDOT>
+__device__ void be_resid_cells_part(const BLev<T>& L, const TX* __restrict__ x, const T* __restrict__ b,
+                                    T* __restrict__ r, int beg, int cnt, const double* __restrict__ da,
+                                    double& acc0, double& acc1) {
+  FP_EXACT_ORDER
   constexpr int U = BeU<T>::U;
   const int nx = L.n[0], ny = L.n[1], nz = DIM == 3 ? L.n[2] : 1;
   const int64_t sxy = (int64_t)nx * ny;
   const Tmpl<T> tp = L.tp;
   const uint8_t* __restrict__ tag = L.tag;
   const int N = L.N;
-  for (int c0 = threadIdx.x; c0 < N; c0 += blockDim.x * U) {
+  const int end = be_end(N, beg, cnt);
+  for (int c0 = beg + (int)threadIdx.x; c0 < end; c0 += blockDim.x * U) {
     int ii[U], jj[U], kk[U], cc[U];
     uint8_t tg[U];
     T v[U][7], bv[U];
@@ -186,14 +231,14 @@ __device__ void be_resid(const BLev<T>& L, const T* __restrict__ x, const T* __r
       kk[u] = k;
       tg[u] = tag[c];
       bv[u] = MODE == 0 ? b[c] : T(0);
-      v[u][6] = x[c];
-      v[u][0] = x[i > 0 ? c - 1 : c];
-      v[u][1] = x[min(i < nx - 1 ? c + 1 : c, N - 1)];
-      v[u][2] = x[j > 0 ? c - nx : c];
-      v[u][3] = x[min(j < ny - 1 ? c + nx : c, N - 1)];
+      v[u][6] = (T)x[c];
+      v[u][0] = (T)x[i > 0 ? c - 1 : c];
+      v[u][1] = (T)x[min(i < nx - 1 ? c + 1 : c, N - 1)];
+      v[u][2] = (T)x[j > 0 ? c - nx : c];
+      v[u][3] = (T)x[min(j < ny - 1 ? c + nx : c, N - 1)];
       if (DIM == 3) {
-        v[u][4] = x[k > 0 ? c - (int)sxy : c];
-        v[u][5] = x[min(k < nz - 1 ? c + (int)sxy : c, N - 1)];
+        v[u][4] = (T)x[k > 0 ? c - (int)sxy : c];
+        v[u][5] = (T)x[min(k < nz - 1 ? c + (int)sxy : c, N - 1)];
       }
     }
 #pragma unroll
@@ -201,44 +246,71 @@ __device__ void be_resid(const BLev<T>& L, const T* __restrict__ x, const T* __r
       if (cc[u] >= N) continue;
       const int p = tclass(tg[u]);
       if (p == 2) continue;
+      T o;
       if (p == 3) {
-        r[cc[u]] = MODE == 0 ? T(0) : v[u][6];
-        continue;
+        o = MODE == 0 ? T(0) : v[u][6];
+      } else {
+        T s = 0, dg = tp.D0(p);
+        if (ii[u] > 0) s += v[u][0]; else dg += tp.CB(0, p);
+        if (ii[u] < nx - 1) s += v[u][1]; else dg += tp.CB(1, p);
+        if (jj[u] > 0) s += v[u][2]; else dg += tp.CB(2, p);
+        if (jj[u] < ny - 1) s += v[u][3]; else dg += tp.CB(3, p);
+        if (DIM == 3) {
+          if (kk[u] > 0) s += v[u][4]; else dg += tp.CB(4, p);
+          if (kk[u] < nz - 1) s += v[u][5]; else dg += tp.CB(5, p);
+        }
+        const T ax = dg * v[u][6] + tp.CO(p) * s;
+        o = MODE == 0 ? bv[u] - ax : ax;
       }
-      T s = 0, dg = tp.D0(p);
-      if (ii[u] > 0) s += v[u][0]; else dg += tp.CB(0, p);
-      if (ii[u] < nx - 1) s += v[u][1]; else dg += tp.CB(1, p);
-      if (jj[u] > 0) s += v[u][2]; else dg += tp.CB(2, p);
-      if (jj[u] < ny - 1) s += v[u][3]; else dg += tp.CB(3, p);
-      if (DIM == 3) {
-        if (kk[u] > 0) s += v[u][4]; else dg += tp.CB(4, p);
-        if (kk[u] < nz - 1) s += v[u][5]; else dg += tp.CB(5, p);
-      }
-      const T ax = dg * v[u][6] + tp.CO(p) * s;
-      r[cc[u]] = MODE == 0 ? bv[u] - ax : ax;
+      r[cc[u]] = o;
+      if (NDOT >= 1) acc0 += da[cc[u]] * (double)o;
+      if (NDOT == 2) acc1 += (double)o * (double)o;
     }
   }
+}
+
+template <typename T, typename TX, int MODE, int NDOT>
+__device__ void be_resid_rows_part(const BLev<T>& L, const TX* __restrict__ x, const T* __restrict__ b,
+                                   T* __restrict__ r, int beg, int cnt, const double* __restrict__ da,
+                                   double& acc0, double& acc1) {
+  FP_EXACT_ORDER
   const int lane = threadIdx.x % kSub;
-  for (int g = (int)threadIdx.x / kSub; g < L.R; g += (int)blockDim.x / kSub) {
+  const int end = be_end(L.R, beg, cnt);
+  for (int g = beg + (int)threadIdx.x / kSub; g < end; g += (int)blockDim.x / kSub) {
     const int64_t q = L.irow_dof[g];
-    const T s = row_dot<T>(L.rp[g], L.rp[g + 1], L.col, L.val, x, lane);
+    const T s = row_dot<T, TX>(L.rp[g], L.rp[g + 1], L.col, L.val, x, lane);
     if (lane == 0) {
-      const T ax = L.diag[g] * x[q] + s;
-      r[q] = MODE == 0 ? b[q] - ax : ax;
+      const T ax = L.diag[g] * (T)x[q] + s;
+      const T o = MODE == 0 ? b[q] - ax : ax;
+      r[q] = o;
+      if (NDOT >= 1) acc0 += da[q] * (double)o;
+      if (NDOT == 2) acc1 += (double)o * (double)o;
     }
   }
+}
+
+template <typename T, int DIM, int MODE>
+__device__ void be_resid(const BLev<T>& L, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ r) {
+  double a0 = 0, a1 = 0;
+  be_resid_cells_part<T, T, DIM, MODE, 0>(L, x, b, r, 0, kAll, nullptr, a0, a1);
+  be_resid_rows_part<T, T, MODE, 0>(L, x, b, r, 0, kAll, nullptr, a0, a1);
   __syncthreads();
 }
 
+// Restriction of rf into the coarse b over coarse cells [beg, beg + cnt);
+// xc (may be null) is cleared over the same cells.
 template <typename T, int DIM>
-__device__ void be_restrict(const BLev<T>& F, const BLev<T>& Cl, const T* __restrict__ rf, T* __restrict__ bc) {
+__device__ void be_restrict_cells_part(const BLev<T>& F, const BLev<T>& Cl, const T* __restrict__ rf,
+                                       T* __restrict__ bc, T* __restrict__ xc, int beg, int cnt) {
+  FP_EXACT_ORDER
   constexpr int U = BeU<T>::U;
   const int cnx = Cl.n[0], cny = Cl.n[1];
   const int fnx = 2 * cnx;
   const int64_t fsxy = (int64_t)fnx * 2 * cny;
   const int CN = Cl.N;
   const T w = DIM == 3 ? T(0.125) : T(0.25);
-  for (int P0 = threadIdx.x; P0 < CN; P0 += blockDim.x * U) {
+  const int end = be_end(CN, beg, cnt);
+  for (int P0 = beg + (int)threadIdx.x; P0 < end; P0 += blockDim.x * U) {
     T v[U][8];
     uint8_t tg[U];
 #pragma unroll
@@ -266,6 +338,7 @@ __device__ void be_restrict(const BLev<T>& F, const BLev<T>& Cl, const T* __rest
     for (int u = 0; u < U; ++u) {
       const int P = P0 + u * (int)blockDim.x;
       if (P >= CN) continue;
+      if (xc) xc[P] = T(0);
       if (tclass(tg[u]) == 3) {
         bc[P] = 0;
         continue;
@@ -276,21 +349,42 @@ __device__ void be_restrict(const BLev<T>& F, const BLev<T>& Cl, const T* __rest
       bc[P] = s * w;
     }
   }
-  for (int t = threadIdx.x; t < F.n_ns; t += blockDim.x) {
+}
+
+// Coarse unknowns of non-simple coarse cells: sums over their listed children.
+template <typename T, int DIM>
+__device__ void be_restrict_ns_part(const BLev<T>& F, const T* __restrict__ rf, T* __restrict__ bc, int beg,
+                                    int cnt) {
+  FP_EXACT_ORDER
+  const T w = DIM == 3 ? T(0.125) : T(0.25);
+  const int end = be_end(F.n_ns, beg, cnt);
+  for (int t = beg + (int)threadIdx.x; t < end; t += blockDim.x) {
     T s = 0;
     for (int e = F.ns_ptr[t]; e < F.ns_ptr[t + 1]; ++e) s += rf[F.ns_child[e]];
     bc[F.ns_cdof[t]] = s * w;
   }
-  __syncthreads();
 }
 
 template <typename T, int DIM>
-__device__ void be_prolong(const BLev<T>& F, const BLev<T>& Cl, const T* __restrict__ ec, T* __restrict__ xf) {
+__device__ void be_restrict(const BLev<T>& F, const BLev<T>& Cl, const T* __restrict__ rf, T* __restrict__ bc) {
+  be_restrict_cells_part<T, DIM>(F, Cl, rf, bc, nullptr, 0, kAll);
+  be_restrict_ns_part<T, DIM>(F, rf, bc, 0, kAll);
+  __syncthreads();
+}
+
+// Prolongation (piecewise constant) of the coarse correction ec into xf over
+// fine cells [beg, beg + cnt) whose parent is simple; the listed fine
+// unknowns of non-simple parents take their coarse unknown's value.
+template <typename T, int DIM>
+__device__ void be_prolong_cells_part(const BLev<T>& F, const BLev<T>& Cl, const T* __restrict__ ec,
+                                      T* __restrict__ xf, int beg, int cnt) {
+  FP_EXACT_ORDER
   constexpr int U = BeU<T>::U;
   const int fnx = F.n[0], fny = F.n[1];
   const int cnx = fnx >> 1, cny = fny >> 1;
   const int FN = F.N;
-  for (int c0 = threadIdx.x; c0 < FN; c0 += blockDim.x * U) {
+  const int end = be_end(FN, beg, cnt);
+  for (int c0 = beg + (int)threadIdx.x; c0 < end; c0 += blockDim.x * U) {
     T e[U], xv[U];
     uint8_t ft[U], ct[U];
 #pragma unroll
@@ -314,7 +408,19 @@ __device__ void be_prolong(const BLev<T>& F, const BLev<T>& Cl, const T* __restr
       xf[c] = xv[u] + e[u];
     }
   }
-  for (int t = threadIdx.x; t < F.n_np; t += blockDim.x) xf[F.np_fdof[t]] += ec[F.np_cdof[t]];
+}
+
+template <typename T>
+__device__ void be_prolong_np_part(const BLev<T>& F, const T* __restrict__ ec, T* __restrict__ xf, int beg,
+                                   int cnt) {
+  const int end = be_end(F.n_np, beg, cnt);
+  for (int t = beg + (int)threadIdx.x; t < end; t += blockDim.x) xf[F.np_fdof[t]] += ec[F.np_cdof[t]];
+}
+
+template <typename T, int DIM>
+__device__ void be_prolong(const BLev<T>& F, const BLev<T>& Cl, const T* __restrict__ ec, T* __restrict__ xf) {
+  be_prolong_cells_part<T, DIM>(F, Cl, ec, xf, 0, kAll);
+  be_prolong_np_part<T>(F, ec, xf, 0, kAll);
   __syncthreads();
 }
 
@@ -399,6 +505,10 @@ struct BBox {
   // BiCGStab work vectors (FP64, N + N2 each): r, rh, p, v, ph, s, sh, t
   double* kv[8];
   int krylov;            // 2: BiCGStab, else plain V-cycles with refinement
+  // level-synchronous solver: finest-level cycle output (ph, sh) and input
+  // (p, s) of the two preconditioner applications of an iteration
+  T* zx[2];
+  T* zb[2];
 };
 
 struct BIO {
@@ -433,11 +543,11 @@ __device__ inline double be_dot(const double* __restrict__ a, const double* __re
 }
 
 template <int DIM>
-__device__ void be_rhs(const BLev<double>& F, const Tmpl<double>& dat, const double* fv, const int64_t* icell,
-                       const double* isrc, const double* iface, const int32_t* iobj, const double* icobj,
-                       const double* icsig, const double* objv, const double* rho, const double* sigma, double* b) {
+__device__ void be_rhs_cells_part(const BLev<double>& F, const Tmpl<double>& dat, const double* rho, double* b,
+                                  int beg, int cnt) {
   const int nx = F.n[0], ny = F.n[1];
-  for (int c = threadIdx.x; c < F.N; c += blockDim.x) {
+  const int end = be_end(F.N, beg, cnt);
+  for (int c = beg + (int)threadIdx.x; c < end; c += blockDim.x) {
     const uint8_t p = tclass(F.tag[c]);
     if (p == 3) {
       b[c] = 0;
@@ -459,7 +569,14 @@ __device__ void be_rhs(const BLev<double>& F, const Tmpl<double>& dat, const dou
     }
     b[c] = v;
   }
-  for (int t = threadIdx.x; t < F.R; t += blockDim.x) {
+}
+
+__device__ inline void be_rhs_rows_part(const BLev<double>& F, const double* fv, const int64_t* icell,
+                                        const double* isrc, const double* iface, const int32_t* iobj,
+                                        const double* icobj, const double* icsig, const double* objv,
+                                        const double* rho, const double* sigma, double* b, int beg, int cnt) {
+  const int end = be_end(F.R, beg, cnt);
+  for (int t = beg + (int)threadIdx.x; t < end; t += blockDim.x) {
     const int64_t c = icell[t];
     double v = isrc[t] * rho[c];
     for (int f = 0; f < 6; ++f) v -= iface[6 * t + f] * fv[f];
@@ -467,6 +584,14 @@ __device__ void be_rhs(const BLev<double>& F, const Tmpl<double>& dat, const dou
     if (sigma) v -= icsig[t] * sigma[c];
     b[F.irow_dof[t]] = v;
   }
+}
+
+template <int DIM>
+__device__ void be_rhs(const BLev<double>& F, const Tmpl<double>& dat, const double* fv, const int64_t* icell,
+                       const double* isrc, const double* iface, const int32_t* iobj, const double* icobj,
+                       const double* icsig, const double* objv, const double* rho, const double* sigma, double* b) {
+  be_rhs_cells_part<DIM>(F, dat, rho, b, 0, kAll);
+  be_rhs_rows_part(F, fv, icell, isrc, iface, iobj, icobj, icsig, objv, rho, sigma, b, 0, kAll);
   __syncthreads();
 }
 

@@ -599,11 +599,12 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
 // pattern, so results are bitwise reproducible.
 constexpr int kSub = 8;
 
-template <typename T>
+template <typename T, typename TX = T>
 __device__ __forceinline__ T row_dot(int64_t b, int64_t e, const int32_t* __restrict__ col,
-                                     const T* __restrict__ val, const T* __restrict__ x, int lane) {
+                                     const T* __restrict__ val, const TX* __restrict__ x, int lane) {
+#pragma clang fp contract(off)
   T s = 0;
-  for (int64_t q = b + lane; q < e; q += kSub) s += val[q] * x[col[q]];
+  for (int64_t q = b + lane; q < e; q += kSub) s += val[q] * (T)x[col[q]];
   for (int off = kSub / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kSub);
   return s;
 }

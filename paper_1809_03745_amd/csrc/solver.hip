@@ -22,6 +22,7 @@
 
 #include "internal.hpp"
 #include "block_engine.hpp"
+#include "batch_wide.hpp"
 #include "kernels.hpp"
 
 namespace ebmg {
@@ -177,6 +178,27 @@ struct ebmg_batch_s {
   int dim = 3;
   int nu1 = 2, nu2 = 2;
   int64_t cells = 0, cells2 = 0, bytes = 0;
+  // level-synchronous mode (mode 2)
+  int mode = 2;
+  struct Table {
+    ebmg::DevBuf<uint8_t> d;   // WEnt entries, padded to a multiple of 8
+    int n = 0;                 // padded count (0: nothing to launch)
+  };
+  struct WideLevel {
+    Table rb, jac[2], scat[2], cell, res, pro;
+  };
+  std::vector<ebmg::DevBuf<uint8_t>> wl;      // BLev per box for levels >= 1 (index = level)
+  ebmg::DevBuf<uint8_t> wl0[2];               // level 0 with the cycle vectors of application 0 / 1
+  std::vector<WideLevel> wide;                // levels run by grid-wide launches
+  Table op64, vec;
+  ebmg::DevBuf<int32_t> ebeg_op, ebeg_vec, lt;
+  ebmg::DevBuf<double> part0, part1;
+  ebmg::DevBuf<uint8_t> state, wio;
+  ebmg::DevBuf<int32_t> count;
+  int* host_count = nullptr;
+  int tail_cells = 0;
+  std::vector<int> cand_cells;
+  std::vector<double> cand_ms;
 };
 
 namespace ebmg {
@@ -1121,6 +1143,17 @@ static BBox<T> make_bbox(ebmg_problem_s* P, const BLev<T>* lv_dev) {
   B.objv = D.objv.p;
   for (int k = 0; k < 8; ++k) B.kv[k] = D.kv[k].p;
   B.krylov = H.opt.krylov;
+  if constexpr (sizeof(T) == sizeof(double)) {
+    B.zx[0] = (T*)D.kv[4].p;
+    B.zx[1] = (T*)D.kv[6].p;
+    B.zb[0] = (T*)D.kv[2].p;
+    B.zb[1] = (T*)D.kv[5].p;
+  } else {
+    // FP32 cycle outputs live in the (otherwise unused) FP64 ph / sh slots
+    B.zx[0] = (T*)(void*)D.kv[4].p;
+    B.zx[1] = (T*)(void*)D.kv[6].p;
+    B.zb[0] = B.zb[1] = (T*)L0.b32.p;
+  }
   return B;
 }
 
@@ -1143,6 +1176,366 @@ static void upload_batch_views(ebmg_batch_s* Bt, hipStream_t s) {
   Bt->bytes += by;
   HIPCHECK(hipStreamSynchronize(s));
 }
+// ---------------------------------------------------------------------------
+// level-synchronous batched solver (host side)
+// ---------------------------------------------------------------------------
+static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Append chunks [0, nch) of segment seg of box b.
+static inline void add_chunks(std::vector<WEnt>& t, int b, int seg, int nch) {
+  for (int c = 0; c < nch; ++c) t.push_back(WEnt{b, seg, c, 0});
+}
+
+static void upload_table(ebmg_batch_s::Table& T, std::vector<WEnt>& e, hipStream_t s, int64_t& by) {
+  T.d.release();
+  T.n = 0;
+  if (e.empty()) return;
+  while (e.size() % kXCD) e.push_back(WEnt{-1, 0, 0, 0});
+  T.n = (int)e.size();
+  T.d.upload((const uint8_t*)e.data(), (int64_t)(e.size() * sizeof(WEnt)), s, by);
+}
+
+// First level of box P that runs in one workgroup: the first with at most
+// `cells` unknowns, the bottom level at the latest.
+static int first_tail_level(ebmg_problem_s* P, int cells) {
+  const auto& lv = P->dev.lv;
+  const int nl = (int)lv.size();
+  for (int l = 0; l < nl - 1; ++l)
+    if (lv[l].N + lv[l].N2 <= cells) return l;
+  return nl - 1;
+}
+
+// Work tables of the grid-wide levels for a coarse-part threshold.
+template <typename T>
+static void build_wide_tables(ebmg_batch_s* Bt, int cells, hipStream_t s) {
+  const int nbox = (int)Bt->boxes.size();
+  std::vector<int32_t> lt(nbox);
+  int lw = 0;
+  for (int i = 0; i < nbox; ++i) {
+    lt[i] = first_tail_level(Bt->boxes[i].get(), cells);
+    lw = std::max(lw, lt[i]);
+  }
+  int64_t by = 0;
+  for (auto& w : Bt->wide) {
+    for (auto* t : {&w.rb, &w.jac[0], &w.jac[1], &w.scat[0], &w.scat[1], &w.cell, &w.res, &w.pro}) {
+      t->d.release();
+      t->n = 0;
+    }
+  }
+  Bt->wide.clear();
+  Bt->wide.resize(lw);
+  const int CH = WCh<T>::v;
+  for (int l = 0; l < lw; ++l) {
+    std::vector<WEnt> rb, jac[2], scat[2], cell, res, pro;
+    for (int i = 0; i < nbox; ++i) {
+      if (lt[i] <= l) continue;
+      const auto& lv = Bt->boxes[i]->dev.lv;
+      const DevLevel& F = lv[l];
+      const DevLevel& C = lv[l + 1];
+      const int64_t half = (int64_t)((F.n[0] + 1) / 2) * F.n[1] * (F.dim == 3 ? F.n[2] : 1);
+      add_chunks(rb, i, 0, cdiv(half, CH));
+      for (int g = 0; g < 2; ++g) {
+        const int rows = F.cls_ptr.size() > (size_t)g + 1 ? F.cls_ptr[g + 1] - F.cls_ptr[g] : 0;
+        add_chunks(jac[g], i, 0, cdiv(rows, kWRows));
+        add_chunks(scat[g], i, 0, cdiv(rows, kWList));
+      }
+      add_chunks(cell, i, 0, cdiv(F.N, CH));
+      add_chunks(cell, i, 1, cdiv(F.R, kWRows));
+      add_chunks(res, i, 0, cdiv(C.N, CH));
+      add_chunks(res, i, 1, cdiv(F.n_ns, kWList));
+      add_chunks(res, i, 2, cdiv(C.N2, kWList));
+      add_chunks(pro, i, 0, cdiv(F.N, CH));
+      add_chunks(pro, i, 1, cdiv(F.n_np, kWList));
+    }
+    auto& W = Bt->wide[l];
+    upload_table(W.rb, rb, s, by);
+    for (int g = 0; g < 2; ++g) {
+      upload_table(W.jac[g], jac[g], s, by);
+      upload_table(W.scat[g], scat[g], s, by);
+    }
+    upload_table(W.cell, cell, s, by);
+    upload_table(W.res, res, s, by);
+    upload_table(W.pro, pro, s, by);
+  }
+  Bt->lt.release();
+  Bt->lt.upload(lt.data(), nbox, s, by);
+  Bt->tail_cells = cells;
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+// Everything of the level-synchronous mode that does not depend on the
+// coarse-part threshold: level views, finest-level tables, partial sums,
+// per-box state.
+template <typename T>
+static void setup_wide_common(ebmg_batch_s* Bt, hipStream_t s) {
+  const int nbox = (int)Bt->boxes.size();
+  int64_t by = 0;
+  int nl = 0;
+  for (auto& P : Bt->boxes) nl = std::max(nl, (int)P->dev.lv.size());
+  Bt->wl.resize(nl);
+  BLev<T> zero;
+  std::memset(&zero, 0, sizeof(zero));
+  for (int l = 1; l < nl; ++l) {
+    std::vector<BLev<T>> v(nbox, zero);
+    for (int i = 0; i < nbox; ++i) {
+      auto& lv = Bt->boxes[i]->dev.lv;
+      if (l < (int)lv.size()) v[i] = make_blev<T>(lv[l]);
+    }
+    Bt->wl[l].upload((const uint8_t*)v.data(), (int64_t)(v.size() * sizeof(BLev<T>)), s, by);
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  std::vector<BBox<T>> hb(nbox);
+  HIPCHECK(hipMemcpy(hb.data(), Bt->bbox.p, sizeof(BBox<T>) * nbox, hipMemcpyDeviceToHost));
+  for (int w = 0; w < 2; ++w) {
+    std::vector<BLev<T>> v(nbox);
+    for (int i = 0; i < nbox; ++i) {
+      v[i] = make_blev<T>(Bt->boxes[i]->dev.lv[0]);
+      v[i].x = hb[i].zx[w];
+      v[i].b = hb[i].zb[w];
+    }
+    Bt->wl0[w].upload((const uint8_t*)v.data(), (int64_t)(v.size() * sizeof(BLev<T>)), s, by);
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  std::vector<WEnt> op, vec;
+  std::vector<int32_t> eop(nbox + 1), evec(nbox + 1);
+  for (int i = 0; i < nbox; ++i) {
+    const DevLevel& L0 = Bt->boxes[i]->dev.lv[0];
+    eop[i] = (int32_t)op.size();
+    add_chunks(op, i, 0, cdiv(L0.N, WCh<double>::v));
+    add_chunks(op, i, 1, cdiv(L0.R, kWRows));
+    evec[i] = (int32_t)vec.size();
+    add_chunks(vec, i, 0, cdiv(L0.N + L0.N2, kWVec));
+  }
+  eop[nbox] = (int32_t)op.size();
+  evec[nbox] = (int32_t)vec.size();
+  upload_table(Bt->op64, op, s, by);
+  upload_table(Bt->vec, vec, s, by);
+  Bt->ebeg_op.upload(eop.data(), nbox + 1, s, by);
+  Bt->ebeg_vec.upload(evec.data(), nbox + 1, s, by);
+  const int np = std::max(Bt->op64.n, Bt->vec.n);
+  Bt->part0.alloc(np, by);
+  Bt->part1.alloc(np, by);
+  Bt->state.alloc((int64_t)(nbox * sizeof(WState)), by);
+  Bt->wio.alloc((int64_t)(nbox * sizeof(WIO)), by);
+  Bt->count.alloc(1, by);
+  HIPCHECK(hipHostMalloc((void**)&Bt->host_count, sizeof(int), hipHostMallocDefault));
+  Bt->bytes += by;
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+template <typename T, int DIM>
+static void wide_smooth(ebmg_batch_s* Bt, int l, const BLev<T>* W, int sweeps, hipStream_t s) {
+  auto& L = Bt->wide[l];
+  const WState* st = (const WState*)Bt->state.p;
+  for (int it = 0; it < sweeps; ++it)
+    for (int colour = 0; colour < 2; ++colour) {
+      hipLaunchKernelGGL((kw_rb<T, DIM>), dim3(L.rb.n), dim3(kWB), 0, s, W, (const WEnt*)L.rb.d.p, st, colour);
+      if (L.jac[colour].n) {
+        hipLaunchKernelGGL((kw_irr_jac<T>), dim3(L.jac[colour].n), dim3(kWB), 0, s, W,
+                           (const WEnt*)L.jac[colour].d.p, st, colour);
+        hipLaunchKernelGGL((kw_irr_scat<T>), dim3(L.scat[colour].n), dim3(kWB), 0, s, W,
+                           (const WEnt*)L.scat[colour].d.p, st, colour);
+      }
+    }
+}
+
+// One V-cycle of every active box on (zb[which], zx[which]) from zx = 0.
+template <typename T, int DIM>
+static void wide_vcycle(ebmg_batch_s* Bt, int which, hipStream_t s) {
+  const int lw = (int)Bt->wide.size();
+  const WState* st = (const WState*)Bt->state.p;
+  auto view = [&](int l) -> const BLev<T>* {
+    return (const BLev<T>*)(l == 0 ? Bt->wl0[which].p : Bt->wl[l].p);
+  };
+  for (int l = 0; l < lw; ++l) {
+    auto& L = Bt->wide[l];
+    wide_smooth<T, DIM>(Bt, l, view(l), Bt->nu1, s);
+    hipLaunchKernelGGL((kw_resid<T, DIM>), dim3(L.cell.n), dim3(kWB), 0, s, view(l), (const WEnt*)L.cell.d.p, st);
+    hipLaunchKernelGGL((kw_restrict<T, DIM>), dim3(L.res.n), dim3(kWB), 0, s, view(l), view(l + 1),
+                       (const WEnt*)L.res.d.p, st);
+  }
+  const int nbox = (int)Bt->boxes.size();
+  hipLaunchKernelGGL((kw_tail<T, DIM>), dim3(nbox), dim3(kBE), 0, s, (const BBox<T>*)Bt->bbox.p, Bt->lt.p, st, which,
+                     Bt->nu1, Bt->nu2);
+  for (int l = lw - 1; l >= 0; --l) {
+    auto& L = Bt->wide[l];
+    hipLaunchKernelGGL((kw_prolong<T, DIM>), dim3(L.pro.n), dim3(kWB), 0, s, view(l), view(l + 1),
+                       (const WEnt*)L.pro.d.p, st);
+    wide_smooth<T, DIM>(Bt, l, view(l), Bt->nu2, s);
+  }
+}
+
+template <typename T, int OP>
+static void wide_vec(ebmg_batch_s* Bt, int filt, hipStream_t s) {
+  hipLaunchKernelGGL((kw_vec<T, OP>), dim3(Bt->vec.n), dim3(kWB), 0, s, (const BBox<T>*)Bt->bbox.p,
+                     (const WEnt*)Bt->vec.d.p, (const WState*)Bt->state.p, (const WIO*)Bt->wio.p, filt,
+                     Bt->part0.p, Bt->part1.p);
+}
+
+template <typename T, typename TX, int DIM, int MODE, int NDOT>
+static void wide_op(ebmg_batch_s* Bt, int filt, int which, int out, int da, hipStream_t s) {
+  hipLaunchKernelGGL((kw_op64<T, TX, DIM, MODE, NDOT>), dim3(Bt->op64.n), dim3(kWB), 0, s,
+                     (const BBox<T>*)Bt->bbox.p, (const WEnt*)Bt->op64.d.p, (const WState*)Bt->state.p, filt, which,
+                     out, da, Bt->part0.p, Bt->part1.p);
+}
+
+template <int STAGE>
+static void wide_fin(ebmg_batch_s* Bt, bool vec, double rtol, int max_cycles, hipStream_t s) {
+  const int nbox = (int)Bt->boxes.size();
+  const int per = kWB / 64;
+  hipLaunchKernelGGL((kw_fin<STAGE>), dim3((nbox + per - 1) / per), dim3(kWB), 0, s,
+                     vec ? Bt->ebeg_vec.p : Bt->ebeg_op.p, Bt->part0.p, Bt->part1.p, (WState*)Bt->state.p, nbox,
+                     rtol, max_cycles);
+}
+
+static std::vector<WState> initial_state(ebmg_batch_s* Bt) {
+  std::vector<WState> st(Bt->boxes.size());
+  for (size_t i = 0; i < st.size(); ++i) {
+    std::memset(&st[i], 0, sizeof(WState));
+    st[i].active = 1;
+    st[i].mode = Bt->boxes[i]->host->opt.krylov == 2 ? 2 : 1;
+    st[i].rho_old = st[i].alpha = st[i].omega = 1.0;
+  }
+  return st;
+}
+
+// One BiCGStab iteration (or two refinement cycles) of every active box.
+template <typename T, int DIM>
+static void wide_iteration(ebmg_batch_s* Bt, double rtol, int max_cycles, hipStream_t s) {
+  wide_vec<T, WV_P>(Bt, WF_ACTIVE, s);
+  wide_vcycle<T, DIM>(Bt, 0, s);
+  wide_op<T, T, DIM, 1, 1>(Bt, WF_ACTIVE, 0, 3, 1, s);            // v = A ph, (rh, v)
+  wide_fin<WS_A>(Bt, false, rtol, max_cycles, s);
+  wide_vec<T, WV_S>(Bt, WF_ACTIVE, s);
+  wide_vcycle<T, DIM>(Bt, 1, s);
+  wide_op<T, T, DIM, 1, 2>(Bt, WF_ACTIVE, 1, 7, 5, s);            // t = A sh, (s, t), (t, t)
+  wide_fin<WS_B>(Bt, false, rtol, max_cycles, s);
+  wide_vec<T, WV_XR>(Bt, WF_ACTIVE, s);
+  wide_fin<WS_C>(Bt, true, rtol, max_cycles, s);
+  wide_op<T, double, DIM, 0, 2>(Bt, WF_VERIFY, 0, 0, 0, s);       // true r = b - A x where tested
+  wide_fin<WS_D>(Bt, false, rtol, max_cycles, s);
+  wide_vec<T, WV_RESTART>(Bt, WF_RESTART, s);
+}
+
+template <typename T, int DIM>
+static void wide_solve(ebmg_batch_s* Bt, const std::vector<WIO>& io, double rtol, int max_cycles,
+                       std::vector<WState>& out, hipStream_t s) {
+  const int nbox = (int)Bt->boxes.size();
+  std::vector<WState> st = initial_state(Bt);
+  HIPCHECK(hipMemcpyAsync(Bt->state.p, st.data(), sizeof(WState) * nbox, hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(Bt->wio.p, io.data(), sizeof(WIO) * nbox, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL((kw_rhs<T, DIM>), dim3(Bt->op64.n), dim3(kWB), 0, s, (const BBox<T>*)Bt->bbox.p,
+                     (const WEnt*)Bt->op64.d.p, (const WIO*)Bt->wio.p);
+  wide_vec<T, WV_INIT>(Bt, WF_ACTIVE, s);                         // x = guess, (b, b)
+  wide_fin<WS_BB>(Bt, true, rtol, max_cycles, s);
+  wide_op<T, double, DIM, 0, 2>(Bt, WF_ACTIVE, 0, 0, 0, s);       // r = b - A x, (r, r)
+  wide_fin<WS_R0>(Bt, false, rtol, max_cycles, s);
+  wide_vec<T, WV_RESTART>(Bt, WF_RESTART, s);
+  HIPCHECK(hipGetLastError());
+  // every iteration adds two cycles to each active box, so max_cycles / 2
+  // iterations stop every box
+  const int limit = max_cycles / 2 + 2;
+  for (int it = 0;; ++it) {
+    hipLaunchKernelGGL(kw_count, dim3(1), dim3(kWB), 0, s, (const WState*)Bt->state.p, nbox, Bt->count.p);
+    HIPCHECK(hipMemcpyAsync(Bt->host_count, Bt->count.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (*Bt->host_count == 0) break;
+    if (it >= limit) throw DeviceError("batched solve did not stop");
+    wide_iteration<T, DIM>(Bt, rtol, max_cycles, s);
+    HIPCHECK(hipGetLastError());
+  }
+  wide_vec<T, WV_OUT>(Bt, WF_ACTIVE, s);
+  out.resize(nbox);
+  HIPCHECK(hipMemcpyAsync(out.data(), Bt->state.p, sizeof(WState) * nbox, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+// Coarse-part autotuner: time one V-cycle of all boxes (on zero vectors)
+// for each candidate threshold; keep the fastest.
+template <typename T, int DIM>
+static void tune_wide(ebmg_batch_s* Bt, hipStream_t s) {
+  const int nbox = (int)Bt->boxes.size();
+  std::vector<WState> st = initial_state(Bt);
+  HIPCHECK(hipMemcpyAsync(Bt->state.p, st.data(), sizeof(WState) * nbox, hipMemcpyHostToDevice, s));
+  for (auto& P : Bt->boxes) {
+    DevProblem& D = P->dev;
+    const int64_t nd = D.lv[0].N + D.lv[0].N2;
+    for (int k : {2, 4, 5, 6}) HIPCHECK(hipMemsetAsync(D.kv[k].p, 0, sizeof(double) * nd, s));
+    if (Bt->mixed) HIPCHECK(hipMemsetAsync(D.lv[0].b32.p, 0, sizeof(float) * nd, s));
+  }
+  const int cand[] = {0, 512, 4096, 32768};
+  Bt->cand_cells.clear();
+  Bt->cand_ms.clear();
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  double best = 1e30;
+  int pick = 0;
+  std::vector<int> seen;
+  for (int c : cand) {
+    // skip thresholds that give the same split as one already timed
+    std::vector<int> lt(nbox);
+    for (int i = 0; i < nbox; ++i) lt[i] = first_tail_level(Bt->boxes[i].get(), c);
+    bool dup = false;
+    for (int q : seen) {
+      bool same = true;
+      for (int i = 0; i < nbox && same; ++i) same = first_tail_level(Bt->boxes[i].get(), q) == lt[i];
+      dup = dup || same;
+    }
+    if (dup) continue;
+    seen.push_back(c);
+    build_wide_tables<T>(Bt, c, s);
+    for (int r = 0; r < 2; ++r) wide_vcycle<T, DIM>(Bt, 0, s);
+    const int reps = 3;
+    HIPCHECK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) wide_vcycle<T, DIM>(Bt, 0, s);
+    HIPCHECK(hipEventRecord(e1, s));
+    HIPCHECK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+    Bt->cand_cells.push_back(c);
+    Bt->cand_ms.push_back(ms / reps);
+    if (ms / reps < best) {
+      best = ms / reps;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  build_wide_tables<T>(Bt, pick, s);
+}
+
+template <typename T>
+static void setup_wide(ebmg_batch_s* Bt, hipStream_t s) {
+  setup_wide_common<T>(Bt, s);
+  if (Bt->dim == 3)
+    tune_wide<T, 3>(Bt, s);
+  else
+    tune_wide<T, 2>(Bt, s);
+}
+
+static void release_wide(ebmg_batch_s* Bt) {
+  for (auto& w : Bt->wide)
+    for (auto* t : {&w.rb, &w.jac[0], &w.jac[1], &w.scat[0], &w.scat[1], &w.cell, &w.res, &w.pro}) t->d.release();
+  Bt->wide.clear();
+  for (auto& b : Bt->wl) b.release();
+  Bt->wl.clear();
+  Bt->wl0[0].release();
+  Bt->wl0[1].release();
+  Bt->op64.d.release();
+  Bt->vec.d.release();
+  Bt->ebeg_op.release();
+  Bt->ebeg_vec.release();
+  Bt->lt.release();
+  Bt->part0.release();
+  Bt->part1.release();
+  Bt->state.release();
+  Bt->wio.release();
+  Bt->count.release();
+  if (Bt->host_count) (void)hipHostFree(Bt->host_count);
+  Bt->host_count = nullptr;
+}
+
 // Template-cell sweeps only (no explicit rows), for ebmg_smooth.
 template <typename T>
 static void template_sweeps(DevLevel& l, int variant, int sweeps, T* x, const T* b, hipStream_t s) {
@@ -1294,11 +1687,13 @@ static ebmg_status parse_options(const ebmg_options* opt, int nobj, ebmg::Option
   out.bottom_max = o.bottom_max_dof > 0 ? o.bottom_max_dof : 600;
   if (o.precision != EBMG_FP64 && o.precision != EBMG_MIXED) return EBMG_ERR_ARG;
   if (!(o.beta != 0.0) || !std::isfinite(o.beta)) return EBMG_ERR_ARG;
-  if (o.krylov < 0 || o.krylov > 2 || o.smoother < 0 || o.smoother > 4 || o.tail < 0 || o.tail > 2)
+  if (o.krylov < 0 || o.krylov > 2 || o.smoother < 0 || o.smoother > 4 || o.tail < 0 || o.tail > 2 ||
+      o.batch < 0 || o.batch > 2)
     return EBMG_ERR_ARG;
-  for (int k = 0; k < 5; ++k)
+  for (int k = 0; k < 4; ++k)
     if (o.reserved[k] != 0) return EBMG_ERR_ARG;
   out.tail = o.tail;
+  out.batch = o.batch == 1 ? 1 : 2;
   out.krylov = o.krylov == 0 ? (nobj > 0 ? 2 : 1) : o.krylov;
   out.smoother = o.smoother;
   return EBMG_OK;
@@ -1698,6 +2093,8 @@ ebmg_status ebmg_setup_batch(ebmg_ctx ctx, int32_t nbox, const ebmg_box* boxes, 
         throw ArgError("bad options for a batch box");
       if (prec < 0) prec = P->host->opt.precision;
       if (P->host->opt.precision != prec) throw ArgError("all boxes of a batch must use one precision");
+      if (i == 0) Bt->mode = P->host->opt.batch;
+      if (P->host->opt.batch != Bt->mode) throw ArgError("all boxes of a batch must use one batch mode");
       Bt->boxes[i] = std::move(P);
     }
     Bt->mixed = prec == EBMG_MIXED;
@@ -1752,6 +2149,12 @@ ebmg_status ebmg_setup_batch(ebmg_ctx ctx, int32_t nbox, const ebmg_box* boxes, 
         upload_batch_views<float>(Bt.get(), s);
       else
         upload_batch_views<double>(Bt.get(), s);
+      if (Bt->mode == 2) {
+        if (Bt->mixed)
+          setup_wide<float>(Bt.get(), s);
+        else
+          setup_wide<double>(Bt.get(), s);
+      }
       std::vector<int32_t> order(nbox);
       for (int i = 0; i < nbox; ++i) order[i] = i;
       std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -1772,6 +2175,7 @@ ebmg_status ebmg_setup_batch(ebmg_ctx ctx, int32_t nbox, const ebmg_box* boxes, 
       Bt->order.release();
       Bt->bio.release();
       Bt->bres.release();
+      release_wide(Bt.get());
       throw;
     }
     *out = Bt.release();
@@ -1784,6 +2188,21 @@ ebmg_status ebmg_query_batch(ebmg_batch bt, int64_t* cells, int64_t* cells2, int
   if (cells) *cells = bt->cells;
   if (cells2) *cells2 = bt->cells2;
   if (device_bytes) *device_bytes = bt->bytes;
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_query_batch_tuning(ebmg_batch bt, int32_t* mode, int32_t* tail_cells, int32_t* wide_levels,
+                                    int32_t* ncand, int32_t* cand_cells, double* cand_ms) {
+  if (!bt) return EBMG_ERR_ARG;
+  if (mode) *mode = bt->mode;
+  if (tail_cells) *tail_cells = bt->tail_cells;
+  if (wide_levels) *wide_levels = (int32_t)bt->wide.size();
+  const int nc = std::min<int>(8, (int)bt->cand_cells.size());
+  if (ncand) *ncand = nc;
+  for (int k = 0; k < nc; ++k) {
+    if (cand_cells) cand_cells[k] = bt->cand_cells[k];
+    if (cand_ms) cand_ms[k] = bt->cand_ms[k];
+  }
   return EBMG_OK;
 }
 
@@ -1809,6 +2228,37 @@ ebmg_status ebmg_solve_batch(ebmg_batch bt, const double* const* rho, const doub
       io[i].sigma = sigma ? sigma[i] : nullptr;
       io[i].phi = phi[i];
       io[i].phi2 = phi2 ? phi2[i] : nullptr;
+    }
+    if (bt->mode == 2) {
+      std::vector<WIO> wio(nbox);
+      for (int i = 0; i < nbox; ++i) wio[i] = WIO{io[i].rho, io[i].sigma, io[i].phi, io[i].phi2};
+      std::vector<WState> st;
+      if (bt->mixed) {
+        if (bt->dim == 3)
+          wide_solve<float, 3>(bt, wio, rtol, max_cycles, st, s);
+        else
+          wide_solve<float, 2>(bt, wio, rtol, max_cycles, st, s);
+      } else {
+        if (bt->dim == 3)
+          wide_solve<double, 3>(bt, wio, rtol, max_cycles, st, s);
+        else
+          wide_solve<double, 2>(bt, wio, rtol, max_cycles, st, s);
+      }
+      const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      ebmg_status worst = EBMG_OK;
+      for (int i = 0; i < nbox; ++i) {
+        if (infos) {
+          std::memset(&infos[i], 0, sizeof(ebmg_solve_info));
+          infos[i].cycles = st[i].cycles;
+          infos[i].outer_iters = st[i].iters;
+          infos[i].levels = (int)bt->boxes[i]->dev.lv.size();
+          infos[i].r0_norm = st[i].bn;
+          infos[i].rel_residual = st[i].rel;
+          infos[i].seconds = secs;
+        }
+        if (st[i].status != EBMG_OK && worst == EBMG_OK) worst = (ebmg_status)st[i].status;
+      }
+      return worst;
     }
     HIPCHECK(hipMemcpyAsync(bt->bio.p, io.data(), sizeof(BIO) * nbox, hipMemcpyHostToDevice, s));
     int ncu = 256;
@@ -1868,6 +2318,7 @@ ebmg_status ebmg_release_batch(ebmg_batch bt) {
   bt->order.release();
   bt->bio.release();
   bt->bres.release();
+  ebmg::release_wide(bt);
   delete bt;
   return EBMG_OK;
 }

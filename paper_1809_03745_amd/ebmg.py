@@ -62,7 +62,7 @@ class Options(C.Structure):
                 ("b_gas", C.c_double), ("dirichlet_closure", C.c_int32), ("robin_closure", C.c_int32),
                 ("eb_order", C.c_int32), ("precision", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("bottom_max_dof", C.c_int32), ("krylov", C.c_int32), ("smoother", C.c_int32),
-                ("tail", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("tail", C.c_int32), ("batch", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class SolveInfo(C.Structure):
@@ -113,6 +113,8 @@ _sig("ebmg_set_coefficients", C.c_int, [_vp, C.POINTER(Options), C.POINTER(Domai
 _sig("ebmg_setup_batch", C.c_int, [_vp, C.c_int32, C.POINTER(Box), C.POINTER(C.c_int32), C.POINTER(_vp),
                                    C.POINTER(DomainBC), C.POINTER(Options), C.POINTER(_vp)])
 _sig("ebmg_query_batch", C.c_int, [_vp, _i64p, _i64p, _i64p])
+_sig("ebmg_query_batch_tuning", C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)])
 _sig("ebmg_solve_batch", C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.c_double, C.c_int32, C.POINTER(_vp),
                                    C.POINTER(_vp), C.POINTER(SolveInfo)])
 _sig("ebmg_release_batch", C.c_int, [_vp])
@@ -121,7 +123,7 @@ EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_des
             "ebmg_setup", "ebmg_query", "ebmg_query_level", "ebmg_export_level", "ebmg_query_tuning",
             "ebmg_export_geometry", "ebmg_export_operator", "ebmg_export_rhs",
             "ebmg_solve", "ebmg_apply", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
-            "ebmg_setup_batch", "ebmg_query_batch", "ebmg_solve_batch", "ebmg_release_batch",
+            "ebmg_setup_batch", "ebmg_query_batch", "ebmg_query_batch_tuning", "ebmg_solve_batch", "ebmg_release_batch",
             "ebmg_set_coefficients", "ebmg_smooth"]
 
 
@@ -174,7 +176,7 @@ KRYLOV_AUTO, KRYLOV_NONE, KRYLOV_BICGSTAB = 0, 1, 2
 
 
 def make_options(prob, precision=FP64, dirichlet_closure=0, robin_closure=0, eb_order=2, nu1=2, nu2=2,
-                 bottom_max_dof=0, krylov=KRYLOV_AUTO, smoother=0, tail=0):
+                 bottom_max_dof=0, krylov=KRYLOV_AUTO, smoother=0, tail=0, batch=0):
     o = Options()
     _lib.ebmg_default_options(C.byref(o))
     o.alpha = prob.alpha
@@ -192,6 +194,7 @@ def make_options(prob, precision=FP64, dirichlet_closure=0, robin_closure=0, eb_
     o.krylov = krylov
     o.smoother = smoother
     o.tail = tail
+    o.batch = batch
     return o
 
 
@@ -348,9 +351,15 @@ class Problem:
             pass
 
 
+BATCH_LEVELSYNC = 2    # every phase one launch over all boxes (default)
+BATCH_PERSISTENT = 1   # one persistent launch, one workgroup per box
+
+
 class Batch:
-    """Independent boxes (one dimension, one precision) solved together by
-    one persistent launch; each box keeps the boundary values given here."""
+    """Independent boxes (one dimension, one precision) solved together,
+    level-synchronously (``batch=BATCH_LEVELSYNC``, the default) or by one
+    persistent launch (``batch=BATCH_PERSISTENT``); each box keeps the
+    boundary values given here."""
 
     def __init__(self, ctx, probs, **opts):
         self.ctx = ctx
@@ -378,6 +387,16 @@ class Batch:
         n, n2, by = C.c_int64(), C.c_int64(), C.c_int64()
         ctx.check(_lib.ebmg_query_batch(h, C.byref(n), C.byref(n2), C.byref(by)), "ebmg_query_batch")
         self.cells, self.cells2, self.device_bytes = n.value, n2.value, by.value
+
+    def tuning(self):
+        """Setup choices: dict(mode, tail_cells, wide_levels, candidates=[(cells, V-cycle ms)])."""
+        mode, tc, wl, nc = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        cc = (C.c_int32 * 8)()
+        ms = (C.c_double * 8)()
+        self.ctx.check(_lib.ebmg_query_batch_tuning(self.h, C.byref(mode), C.byref(tc), C.byref(wl), C.byref(nc),
+                                                    cc, ms), "ebmg_query_batch_tuning")
+        return dict(mode=mode.value, tail_cells=tc.value, wide_levels=wl.value,
+                    candidates=[(cc[k], ms[k]) for k in range(nc.value)])
 
     def solve(self, rho, phi, sigma=None, phi2=None, rtol=1e-10, max_cycles=100, check=True):
         """rho, phi (and optionally sigma, phi2) are lists of device tensors,

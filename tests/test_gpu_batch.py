@@ -66,10 +66,14 @@ BOXES = W.batched_boxes(16, seed=11)
 ORACLE_IDX = [12, 2, 11, 0]
 
 
+MODES = [ebmg.BATCH_LEVELSYNC, ebmg.BATCH_PERSISTENT]
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("prec", [0, 1])
-def test_batch_3d_vs_oracle(ctx, prec):
-    _say("batch 3d vs oracle, precision", prec)
-    B = ebmg.Batch(ctx, BOXES, precision=prec)
+def test_batch_3d_vs_oracle(ctx, prec, mode):
+    _say("batch 3d vs oracle, precision", prec, "mode", mode)
+    B = ebmg.Batch(ctx, BOXES, precision=prec, batch=mode)
     assert B.cells == sum(int(np.prod(p.shape)) for p in BOXES)
     st, infos, xs, x2s = _batch_solve(B, BOXES, 1e-10)
     assert st == ebmg.OK, infos
@@ -91,9 +95,10 @@ def test_batch_3d_vs_oracle(ctx, prec):
     B.release()
 
 
-def test_batch_3d_vs_single_box(ctx):
-    _say("batch 3d vs single-box path")
-    B = ebmg.Batch(ctx, BOXES)
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_3d_vs_single_box(ctx, mode):
+    _say("batch 3d vs single-box path, mode", mode)
+    B = ebmg.Batch(ctx, BOXES, batch=mode)
     st, infos, xs, x2s = _batch_solve(B, BOXES, 1e-13)
     assert st == ebmg.OK
     for i, pr in enumerate(BOXES):
@@ -111,14 +116,16 @@ def test_batch_3d_vs_single_box(ctx):
     B.release()
 
 
-def test_batch_2d_mixed_kinds(ctx):
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_2d_mixed_kinds(ctx, mode):
     """A 2D batch mixing Poisson with surface charge, blade-plane with a
-    dielectric and an Eddington Helmholtz box with Robin faces."""
-    _say("batch 2d mixed kinds")
+    dielectric and an Eddington Helmholtz box with Robin faces (plain
+    V-cycle refinement and BiCGStab boxes side by side)."""
+    _say("batch 2d mixed kinds, mode", mode)
     probs = [W.two_disks(64, seed=3), W.blade_plane(96, seed=4), W.eddington(2, 64, 10.0, seed=5),
              W.coaxial(48, sigma=0.5), W.manufactured_sine(32)]
     for prec, bar in ((0, 1e-10), (1, 1e-8)):
-        B = ebmg.Batch(ctx, probs, precision=prec)
+        B = ebmg.Batch(ctx, probs, precision=prec, batch=mode)
         st, infos, xs, x2s = _batch_solve(B, probs, 1e-13, max_cycles=600)
         assert st == ebmg.OK, infos
         for i, pr in enumerate(probs):
@@ -131,30 +138,32 @@ def test_batch_2d_mixed_kinds(ctx):
         B.release()
 
 
-def test_batch_result_independent_of_mix(ctx):
-    _say("batch mix invariance")
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_result_independent_of_mix(ctx, mode):
+    _say("batch mix invariance, mode", mode)
     probs = BOXES[:8]
-    B = ebmg.Batch(ctx, probs, precision=ebmg.MIXED)
+    B = ebmg.Batch(ctx, probs, precision=ebmg.MIXED, batch=mode)
     _, _, xs, _ = _batch_solve(B, probs, 1e-10)
     B.release()
     for i in (1, 5):
-        Bi = ebmg.Batch(ctx, [probs[i]], precision=ebmg.MIXED)
+        Bi = ebmg.Batch(ctx, [probs[i]], precision=ebmg.MIXED, batch=mode)
         _, _, xi, _ = _batch_solve(Bi, [probs[i]], 1e-10)
         assert np.array_equal(xi[0], xs[i])
         Bi.release()
     # and a reordered batch
     perm = [7, 3, 0, 5, 1, 6, 2, 4]
-    Bp = ebmg.Batch(ctx, [probs[k] for k in perm], precision=ebmg.MIXED)
+    Bp = ebmg.Batch(ctx, [probs[k] for k in perm], precision=ebmg.MIXED, batch=mode)
     _, _, xp, _ = _batch_solve(Bp, [probs[k] for k in perm], 1e-10)
     for j, k in enumerate(perm):
         assert np.array_equal(xp[j], xs[k])
     Bp.release()
 
 
-def test_batch_errors(ctx):
-    _say("batch error paths")
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_errors(ctx, mode):
+    _say("batch error paths, mode", mode)
     probs = BOXES[:3]
-    B = ebmg.Batch(ctx, probs)
+    B = ebmg.Batch(ctx, probs, batch=mode)
     st, infos, _, _ = _batch_solve(B, probs, 1e-10, max_cycles=2)
     assert st == ebmg.ERR_NOCONV
     assert all(i["cycles"] <= 2 for i in infos)
@@ -169,3 +178,25 @@ def test_batch_errors(ctx):
     B.release()
     with pytest.raises(ebmg.EbmgError):
         ebmg.Batch(ctx, [W.two_disks(32, seed=0), W.pin_plane(16, seed=0)])
+
+
+def test_batch_levelsync_tuning_and_modes_agree(ctx):
+    """The level-synchronous setup reports its coarse-part choice, and both
+    batched modes reach the same solution (to the solve tolerance)."""
+    _say("batch modes agree")
+    probs = BOXES[:6]
+    Bw = ebmg.Batch(ctx, probs, precision=ebmg.MIXED, batch=ebmg.BATCH_LEVELSYNC)
+    tu = Bw.tuning()
+    _say("   tuning", tu)
+    assert tu["mode"] == 2 and len(tu["candidates"]) >= 1
+    assert tu["tail_cells"] in [c for c, _ in tu["candidates"]]
+    st, iw, xw, x2w = _batch_solve(Bw, probs, 1e-12)
+    assert st == ebmg.OK
+    Bw.release()
+    Bp = ebmg.Batch(ctx, probs, precision=ebmg.MIXED, batch=ebmg.BATCH_PERSISTENT)
+    assert Bp.tuning()["mode"] == 1
+    st, ip, xp, x2p = _batch_solve(Bp, probs, 1e-12)
+    assert st == ebmg.OK
+    Bp.release()
+    for i in range(len(probs)):
+        assert np.linalg.norm(xw[i] - xp[i]) <= 1e-9 * np.linalg.norm(xp[i]), i

@@ -216,8 +216,9 @@ def _pct(lat, q):
 
 
 def batched(nbox=512, reps=3):
-    """The batched workload: 512 uneven 3D boxes solved by one persistent
-    launch, mixed precision and FP64."""
+    """The batched workload: 512 uneven 3D boxes, mixed precision and FP64,
+    level-synchronous (every phase one launch over all boxes) and as one
+    persistent launch (one workgroup per box)."""
     import numpy as np
     import torch
     import workloads as W
@@ -230,8 +231,11 @@ def batched(nbox=512, reps=3):
     ctx = ebmg.Context(0)
     out = {"workload": f"{nbox} random 3D boxes (edges 16..64 log-uniform, sphere electrode, eps plane split, "
                        f"4 Fourier modes, seed 0)", "cells": int(cells.sum())}
-    for prec, key in ((ebmg.MIXED, "mixed"), (ebmg.FP64, "fp64")):
-        B = ebmg.Batch(ctx, boxes, precision=prec)
+    runs = ((ebmg.BATCH_LEVELSYNC, ebmg.MIXED, "mixed"), (ebmg.BATCH_LEVELSYNC, ebmg.FP64, "fp64"),
+            (ebmg.BATCH_PERSISTENT, ebmg.MIXED, "persistent_mixed"), (ebmg.BATCH_PERSISTENT, ebmg.FP64, "persistent_fp64"))
+    for mode, prec, key in runs:
+        B = ebmg.Batch(ctx, boxes, precision=prec, batch=mode)
+        tune = B.tuning()
         phi2 = [torch.zeros(max(1, int(c)), dtype=torch.float64, device=dev) for c in cells]
         best = None
         for _ in range(reps):
@@ -249,6 +253,9 @@ def batched(nbox=512, reps=3):
                     "cell_updates_per_s": float((cells * cyc).sum() / best),
                     "vcycles_mean": float(cyc.mean()), "vcycles_max": int(cyc.max()),
                     "worst_rel_residual": max(i["rel_residual"] for i in infos)}
+        if mode == ebmg.BATCH_LEVELSYNC:
+            out[key]["coarse_part_cells"] = tune["tail_cells"]
+            out[key]["grid_wide_levels"] = tune["wide_levels"]
         B.release()
         del phi2
     return out

@@ -23,7 +23,10 @@
 namespace ebmg {
 
 constexpr int kWB = 256;               // threads of a level-synchronous workgroup
-constexpr int kWRows = kWB / kSub;     // explicit rows per entry
+template <typename T>
+struct WRows {
+  static constexpr int v = kWB / kSub * RowU<T>::v;   // explicit rows per entry
+};
 constexpr int kWList = kWB;            // list entries (one per thread) per entry
 constexpr int kWVec = 4 * kWB;         // vector entries per entry
 
@@ -51,7 +54,7 @@ struct WState {
 enum WFilt { WF_ACTIVE = 0, WF_VERIFY = 1, WF_RESTART = 2 };
 
 __device__ __forceinline__ bool w_pass(const WState& s, int filt) {
-  return filt == WF_ACTIVE ? s.active != 0 : (filt == WF_VERIFY ? s.verify != 0 : s.restart != 0);
+  return filt == WF_ACTIVE ? s.active != 0 : (filt == WF_VERIFY ? s.verify != 0 : s.restart != 0 && s.active != 0);
 }
 
 // Entry of this workgroup; consecutive table entries (neighbouring chunks of
@@ -87,7 +90,7 @@ __global__ void __launch_bounds__(kWB) kw_irr_jac(const BLev<T>* __restrict__ WL
   const WEnt e = tab[w_entry()];
   if (e.box < 0 || !st[e.box].active) return;
   const BLev<T>& L = WL[e.box];
-  be_irr_jac_part<T>(L, grp, L.x, L.b, e.chunk * kWRows, kWRows);
+  be_irr_jac_part<T>(L, grp, L.x, L.b, e.chunk * WRows<T>::v, WRows<T>::v);
 }
 
 template <typename T>
@@ -110,7 +113,7 @@ __global__ void __launch_bounds__(kWB) kw_resid(const BLev<T>* __restrict__ WL, 
   if (e.seg == 0)
     be_resid_cells_part<T, T, DIM, 0, 0>(L, L.x, L.b, L.r, e.chunk * WCh<T>::v, WCh<T>::v, nullptr, a0, a1);
   else
-    be_resid_rows_part<T, T, 0, 0>(L, L.x, L.b, L.r, e.chunk * kWRows, kWRows, nullptr, a0, a1);
+    be_resid_rows_part<T, T, 0, 0>(L, L.x, L.b, L.r, e.chunk * WRows<T>::v, WRows<T>::v, nullptr, a0, a1);
 }
 
 // restriction of the fine residual into the coarse b, coarse x cleared:
@@ -146,18 +149,43 @@ __global__ void __launch_bounds__(kWB) kw_prolong(const BLev<T>* __restrict__ WF
     be_prolong_np_part<T>(F, C.x, F.x, e.chunk * kWList, kWList);
 }
 
-// Coarse part of the cycle: workgroup b runs box b's V-cycle from its level
-// lt[b] down (the bottom solve included) and back up to lt[b].
+// Coarse part of the cycle: workgroup k runs box list[k]'s V-cycle from its
+// level lt down (the bottom solve included) and back up to lt.
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kBE) kw_tail(const BBox<T>* __restrict__ boxes, const int32_t* __restrict__ lt,
-                                              const WState* __restrict__ st, int which, int nu1, int nu2) {
-  const int bi = blockIdx.x;
+                                              const int32_t* __restrict__ list, const WState* __restrict__ st,
+                                              int which, int nu1, int nu2) {
+  const int bi = list[blockIdx.x];
   if (!st[bi].active) return;
   const BBox<T>& B = boxes[bi];
   const int l0 = lt[bi];
   T* x0 = l0 == 0 ? B.zx[which] : B.lv[l0].x;
   const T* b0 = l0 == 0 ? B.zb[which] : B.lv[l0].b;
   be_vcycle<T, DIM>(B.lv, l0, B.nlev, B.Ainv, B.nbot, nu1, nu2, x0, b0);
+}
+
+// Bottom solves x = Ainv b of boxes whose coarse part is the bottom level
+// alone, kWBotRows rows of one box per entry (one wavefront per row, as the
+// engine), so the inverses stream through the whole chip.
+constexpr int kWBotRows = 4 * (kWB / 64);
+
+template <typename T>
+__global__ void __launch_bounds__(kWB) kw_bottom(const BBox<T>* __restrict__ boxes, const int32_t* __restrict__ lt,
+                                                const WEnt* __restrict__ tab, const WState* __restrict__ st,
+                                                int which) {
+  const WEnt e = tab[w_entry()];
+  if (e.box < 0 || !st[e.box].active) return;
+  const BBox<T>& B = boxes[e.box];
+  const int l0 = lt[e.box];
+  T* x = l0 == 0 ? B.zx[which] : B.lv[l0].x;
+  const T* b = l0 == 0 ? B.zb[which] : B.lv[l0].b;
+  const int n = B.nbot;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r1 = min(n, (e.chunk + 1) * kWBotRows);
+  for (int row = e.chunk * kWBotRows + wave; row < r1; row += kWB / 64) {
+    const double s = bottom_row<T>(B.Ainv + (int64_t)row * n, n, b, lane);
+    if (lane == 0) x[row] = (T)s;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -184,7 +212,8 @@ __global__ void __launch_bounds__(kWB) kw_op64(const BBox<T>* __restrict__ boxes
     be_resid_cells_part<double, TX, DIM, MODE, NDOT>(F, x, F.b, r, e.chunk * WCh<double>::v, WCh<double>::v, dv,
                                                      a0, a1);
   else
-    be_resid_rows_part<double, TX, MODE, NDOT>(F, x, F.b, r, e.chunk * kWRows, kWRows, dv, a0, a1);
+    be_resid_rows_part<double, TX, MODE, NDOT>(F, x, F.b, r, e.chunk * WRows<double>::v, WRows<double>::v, dv, a0,
+                                               a1);
   if (NDOT >= 1) {
     const double s0 = w_block_sum(a0, red[0]);
     if (threadIdx.x == 0) part0[idx] = s0;
@@ -215,7 +244,7 @@ __global__ void __launch_bounds__(kWB) kw_rhs(const BBox<T>* __restrict__ boxes,
     be_rhs_cells_part<DIM>(F, B.dat, o.rho, F.b, e.chunk * WCh<double>::v, WCh<double>::v);
   else
     be_rhs_rows_part(F, B.fv, B.icell, B.isrc, B.iface, B.iobj, B.icobj, B.icsig, B.objv, o.rho, o.sigma, F.b,
-                     e.chunk * kWRows, kWRows);
+                     e.chunk * WRows<double>::v, WRows<double>::v);
 }
 
 enum WVecOp { WV_INIT = 0, WV_P, WV_S, WV_XR, WV_RESTART, WV_OUT };

@@ -157,19 +157,110 @@ __device__ void be_rb(const BLev<T>& L, T* __restrict__ x, const T* __restrict__
   __syncthreads();
 }
 
-// Explicit rows of a colour group, kSub lanes per row (as the grid-wide
-// kernels), Jacobi within the group: new values to w, then scattered.
+// Explicit rows (stored group by group, so a colour group is a row range),
+// kSub lanes per row and RowU<T> rows per lane group. Entries are fetched in
+// passes of kRowJ per lane and row: all columns and values of a pass (every
+// row of the group) are requested, then all x values, then summed, so a lane
+// keeps RowU * kRowJ independent load chains in flight. Per lane the entries
+// are summed in row order and the lanes combined by row_dot's xor-shuffle
+// tree, so each sum is row_dot's bit for bit.
 template <typename T>
+struct RowU {
+  static constexpr int v = sizeof(T) == 4 ? 4 : 2;
+};
+constexpr int kRowJ = 4;
+
+template <typename T, typename TX, int RU>
+__device__ __forceinline__ void rows_dot(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                         const T* __restrict__ val, const TX* __restrict__ x, int g0, int gstep,
+                                         int end, int lane, T (&s)[RU]) {
+  FP_EXACT_ORDER
+  int64_t q[RU], e[RU];
+#pragma unroll
+  for (int u = 0; u < RU; ++u) {
+    const int g = g0 + u * gstep;
+    q[u] = 0;
+    e[u] = 0;
+    if (g < end) {
+      q[u] = rp[g] + lane;
+      e[u] = rp[g + 1];
+    }
+    s[u] = T(0);
+  }
+  for (int base = 0;; base += kRowJ * kSub) {
+    int c[RU][kRowJ];
+    T v[RU][kRowJ], xv[RU][kRowJ];
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+      for (int j = 0; j < kRowJ; ++j) {
+        const int64_t k = q[u] + base + j * kSub;
+        c[u][j] = 0;
+        v[u][j] = T(0);
+        if (k < e[u]) {
+          c[u][j] = col[k];
+          v[u][j] = val[k];
+        }
+      }
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+      for (int j = 0; j < kRowJ; ++j) {
+        xv[u][j] = T(0);
+        if (q[u] + base + j * kSub < e[u]) xv[u][j] = (T)x[c[u][j]];
+      }
+    bool more = false;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+#pragma unroll
+      for (int j = 0; j < kRowJ; ++j)
+        if (q[u] + base + j * kSub < e[u]) s[u] = s[u] + v[u][j] * xv[u][j];
+      more = more || q[u] + base + kRowJ * kSub < e[u];
+    }
+    if (!more) break;
+  }
+#pragma unroll
+  for (int u = 0; u < RU; ++u)
+    for (int off = kSub / 2; off > 0; off >>= 1) s[u] += __shfl_xor(s[u], off, kSub);
+}
+
+// Jacobi values (b - offdiag . x) / diag of group grp's rows [beg, beg + cnt)
+// (relative to the group) into w.
+template <typename T, int RU = RowU<T>::v>
 __device__ void be_irr_jac_part(const BLev<T>& L, int grp, const T* __restrict__ x, const T* __restrict__ b,
                                 int beg, int cnt) {
   FP_EXACT_ORDER
   const int r0 = L.grp_ptr[grp];
   const int end = r0 + be_end(L.grp_ptr[grp + 1] - r0, beg, cnt);
   const int lane = threadIdx.x % kSub;
-  for (int g = r0 + beg + (int)threadIdx.x / kSub; g < end; g += (int)blockDim.x / kSub) {
-    const int r = L.grp_rows[g];
-    const T s = row_dot<T>(L.rp[r], L.rp[r + 1], L.col, L.val, x, lane);
-    if (lane == 0) L.w[g - r0] = (b[L.irow_dof[r]] - s) / L.diag[r];
+  const int nsub = (int)blockDim.x / kSub;
+  for (int g0 = r0 + beg + (int)threadIdx.x / kSub; g0 < end; g0 += nsub * RU) {
+    T bv[RU], dg[RU];
+    int64_t q[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int g = g0 + u * nsub;
+      q[u] = 0;
+      dg[u] = T(1);
+      if (g < end) {
+        q[u] = L.irow_dof[g];
+        dg[u] = L.diag[g];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      bv[u] = T(0);
+      if (g0 + u * nsub < end) bv[u] = b[q[u]];
+    }
+    T sm[RU];
+    rows_dot<T, T, RU>(L.rp, L.col, L.val, x, g0, nsub, end, lane, sm);
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int g = g0 + u * nsub;
+        if (g < end) L.w[g - r0] = (bv[u] - sm[u]) / dg[u];
+      }
+    }
   }
 }
 
@@ -177,13 +268,13 @@ template <typename T>
 __device__ void be_irr_scat_part(const BLev<T>& L, int grp, T* __restrict__ x, int beg, int cnt) {
   const int r0 = L.grp_ptr[grp];
   const int end = r0 + be_end(L.grp_ptr[grp + 1] - r0, beg, cnt);
-  for (int g = r0 + beg + (int)threadIdx.x; g < end; g += blockDim.x) x[L.irow_dof[L.grp_rows[g]]] = L.w[g - r0];
+  for (int g = r0 + beg + (int)threadIdx.x; g < end; g += blockDim.x) x[L.irow_dof[g]] = L.w[g - r0];
 }
 
 template <typename T>
 __device__ void be_irr_group(const BLev<T>& L, int grp, T* __restrict__ x, const T* __restrict__ b) {
   if (L.grp_ptr[grp + 1] <= L.grp_ptr[grp]) return;
-  be_irr_jac_part<T>(L, grp, x, b, 0, kAll);
+  be_irr_jac_part<T, 1>(L, grp, x, b, 0, kAll);   // one row per lane group keeps the engine's registers low
   __syncthreads();
   be_irr_scat_part<T>(L, grp, x, 0, kAll);
   __syncthreads();
@@ -269,22 +360,48 @@ __device__ void be_resid_cells_part(const BLev<T>& L, const TX* __restrict__ x, 
   }
 }
 
-template <typename T, typename TX, int MODE, int NDOT>
+template <typename T, typename TX, int MODE, int NDOT, int RU = RowU<T>::v>
 __device__ void be_resid_rows_part(const BLev<T>& L, const TX* __restrict__ x, const T* __restrict__ b,
                                    T* __restrict__ r, int beg, int cnt, const double* __restrict__ da,
                                    double& acc0, double& acc1) {
   FP_EXACT_ORDER
   const int lane = threadIdx.x % kSub;
+  const int nsub = (int)blockDim.x / kSub;
   const int end = be_end(L.R, beg, cnt);
-  for (int g = beg + (int)threadIdx.x / kSub; g < end; g += (int)blockDim.x / kSub) {
-    const int64_t q = L.irow_dof[g];
-    const T s = row_dot<T, TX>(L.rp[g], L.rp[g + 1], L.col, L.val, x, lane);
+  for (int g0 = beg + (int)threadIdx.x / kSub; g0 < end; g0 += nsub * RU) {
+    int64_t q[RU];
+    T dg[RU], xq[RU], bq[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int g = g0 + u * nsub;
+      q[u] = 0;
+      dg[u] = T(0);
+      if (g < end) {
+        q[u] = L.irow_dof[g];
+        dg[u] = L.diag[g];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      xq[u] = T(0);
+      bq[u] = T(0);
+      if (g0 + u * nsub < end) {
+        xq[u] = (T)x[q[u]];
+        if (MODE == 0) bq[u] = b[q[u]];
+      }
+    }
+    T sm[RU];
+    rows_dot<T, TX, RU>(L.rp, L.col, L.val, x, g0, nsub, end, lane, sm);
     if (lane == 0) {
-      const T ax = L.diag[g] * (T)x[q] + s;
-      const T o = MODE == 0 ? b[q] - ax : ax;
-      r[q] = o;
-      if (NDOT >= 1) acc0 += da[q] * (double)o;
-      if (NDOT == 2) acc1 += (double)o * (double)o;
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        if (g0 + u * nsub >= end) continue;
+        const T ax = dg[u] * xq[u] + sm[u];
+        const T o = MODE == 0 ? bq[u] - ax : ax;
+        r[q[u]] = o;
+        if (NDOT >= 1) acc0 += da[q[u]] * (double)o;
+        if (NDOT == 2) acc1 += (double)o * (double)o;
+      }
     }
   }
 }
@@ -293,7 +410,7 @@ template <typename T, int DIM, int MODE>
 __device__ void be_resid(const BLev<T>& L, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ r) {
   double a0 = 0, a1 = 0;
   be_resid_cells_part<T, T, DIM, MODE, 0>(L, x, b, r, 0, kAll, nullptr, a0, a1);
-  be_resid_rows_part<T, T, MODE, 0>(L, x, b, r, 0, kAll, nullptr, a0, a1);
+  be_resid_rows_part<T, T, MODE, 0, 1>(L, x, b, r, 0, kAll, nullptr, a0, a1);
   __syncthreads();
 }
 
@@ -424,15 +541,25 @@ __device__ void be_prolong(const BLev<T>& F, const BLev<T>& Cl, const T* __restr
   __syncthreads();
 }
 
-// x = Ainv b on the bottom level (FP64 accumulation): one wavefront per row,
-// lanes over columns (coalesced), fixed-order shuffle reduction
+// One row of x = Ainv b on the bottom level (FP64 accumulation): lanes over
+// columns (coalesced), fixed-order shuffle reduction; valid in lane 0.
+template <typename T>
+__device__ __forceinline__ double bottom_row(const double* __restrict__ arow, int n, const T* __restrict__ b,
+                                             int lane) {
+  FP_EXACT_ORDER
+  double s = 0;
+#pragma unroll 4
+  for (int c = lane; c < n; c += 64) s += arow[c] * (double)b[c];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  return s;
+}
+
+// x = Ainv b, one wavefront per row
 template <typename T>
 __device__ void be_bottom(const double* __restrict__ Ainv, int n, const T* __restrict__ b, T* __restrict__ x) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   for (int row = wave; row < n; row += nwaves) {
-    double s = 0;
-    for (int c = lane; c < n; c += 64) s += Ainv[(int64_t)row * n + c] * (double)b[c];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    const double s = bottom_row<T>(Ainv + (int64_t)row * n, n, b, lane);
     if (lane == 0) x[row] = (T)s;
   }
   __syncthreads();

@@ -191,7 +191,10 @@ struct ebmg_batch_s {
   ebmg::DevBuf<uint8_t> wl0[2];               // level 0 with the cycle vectors of application 0 / 1
   std::vector<WideLevel> wide;                // levels run by grid-wide launches
   Table op64, vec;
+  Table bot;                                  // grid-wide bottom solves
   ebmg::DevBuf<int32_t> ebeg_op, ebeg_vec, lt;
+  ebmg::DevBuf<int32_t> tail_list;            // boxes whose coarse part runs in one workgroup
+  int n_tail = 0;
   ebmg::DevBuf<double> part0, part1;
   ebmg::DevBuf<uint8_t> state, wio;
   ebmg::DevBuf<int32_t> count;
@@ -500,6 +503,16 @@ static void tune_smoother(DevLevel& l, bool mixed, int mode, hipStream_t s) {
   }
 }
 
+// Device order of a level's explicit rows: by colour group (host row order
+// within a group).
+static std::vector<int32_t> row_order(const Level& L) {
+  const int64_t R = (int64_t)L.irow_dof.size();
+  if ((int64_t)L.cls_rows.size() == R) return L.cls_rows;
+  std::vector<int32_t> id(R);
+  for (int64_t k = 0; k < R; ++k) id[k] = (int32_t)k;
+  return id;
+}
+
 static void upload(ebmg_problem_s* P, bool batch_box = false) {
   Problem& H = *P->host;
   DevProblem& D = P->dev;
@@ -516,19 +529,38 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
     d.N2 = L.N2;
     d.R = (int64_t)L.irow_dof.size();
     d.tag.upload(L.tag.data(), L.N, s, by);
-    d.irow_dof.upload(L.irow_dof.data(), d.R, s, by);
-    d.rp.upload(L.rp.data(), d.R + 1, s, by);
-    d.col.upload(L.col.data(), (int64_t)L.col.size(), s, by);
-    d.cls_rows.upload(L.cls_rows.data(), (int64_t)L.cls_rows.size(), s, by);
+    // explicit rows are stored on the device group by group (red rows, then
+    // black rows), so a colour group is a contiguous row range
+    const std::vector<int32_t> perm = row_order(L);
+    std::vector<int64_t> idof(d.R), rp(d.R + 1, 0);
+    std::vector<int32_t> col, ident(d.R);
+    std::vector<double> val, dg(d.R);
+    col.reserve(L.col.size());
+    val.reserve(L.val.size());
+    for (int64_t k = 0; k < d.R; ++k) {
+      const int32_t r = perm[k];
+      idof[k] = L.irow_dof[r];
+      dg[k] = L.idiag[r];
+      for (int64_t e = L.rp[r]; e < L.rp[r + 1]; ++e) {
+        col.push_back(L.col[e]);
+        val.push_back(L.val[e]);
+      }
+      rp[k + 1] = (int64_t)col.size();
+      ident[k] = (int32_t)k;
+    }
+    d.irow_dof.upload(idof.data(), d.R, s, by);
+    d.rp.upload(rp.data(), d.R + 1, s, by);
+    d.col.upload(col.data(), (int64_t)col.size(), s, by);
+    d.cls_rows.upload(ident.data(), d.R, s, by);
     d.cls_ptr = L.cls_ptr;
-    d.val64.upload(L.val.data(), (int64_t)L.val.size(), s, by);
-    d.diag64.upload(L.idiag.data(), d.R, s, by);
+    d.val64.upload(val.data(), (int64_t)val.size(), s, by);
+    d.diag64.upload(dg.data(), d.R, s, by);
     if (mixed) {
-      std::vector<float> v(L.val.begin(), L.val.end()), g(L.idiag.begin(), L.idiag.end());
+      std::vector<float> v(val.begin(), val.end()), g(dg.begin(), dg.end());
       d.val32.upload(v.data(), (int64_t)v.size(), s, by);
       d.diag32.upload(g.data(), (int64_t)g.size(), s, by);
-      HIPCHECK(hipStreamSynchronize(s));
     }
+    HIPCHECK(hipStreamSynchronize(s));
     d.n_ns = (int64_t)L.ns_cdof.size();
     d.ns_cdof.upload(L.ns_cdof.data(), d.n_ns, s, by);
     d.ns_ptr.upload(L.ns_ptr.data(), (int64_t)L.ns_ptr.size(), s, by);
@@ -560,19 +592,22 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
   const FineData& F = H.fine;
   const Level& L0 = H.levels[0];
   const int64_t R = (int64_t)L0.irow_dof.size();
+  const std::vector<int32_t> perm0 = row_order(L0);
   std::vector<int64_t> icell(R);
-  std::vector<double> iface(6 * R), icobj(R), icsig(R);
+  std::vector<double> iface(6 * R), icobj(R), icsig(R), isrc(R);
   std::vector<int32_t> iobj(R);
-  for (int64_t r = 0; r < R; ++r) {
+  for (int64_t k = 0; k < R; ++k) {
+    const int32_t r = perm0[k];
     const int64_t q = L0.irow_dof[r];
-    icell[r] = q < L0.N ? q : L0.sec_cell[q - L0.N];
-    for (int f = 0; f < 6; ++f) iface[6 * r + f] = F.idata[r].face[f];
-    iobj[r] = F.idata[r].obj;
-    icobj[r] = F.idata[r].cobj;
-    icsig[r] = F.idata[r].csig;
+    icell[k] = q < L0.N ? q : L0.sec_cell[q - L0.N];
+    for (int f = 0; f < 6; ++f) iface[6 * k + f] = F.idata[r].face[f];
+    iobj[k] = F.idata[r].obj;
+    icobj[k] = F.idata[r].cobj;
+    icsig[k] = F.idata[r].csig;
+    isrc[k] = F.isrc[r];
   }
   D.icell.upload(icell.data(), R, s, by);
-  D.isrc.upload(F.isrc.data(), R, s, by);
+  D.isrc.upload(isrc.data(), R, s, by);
   D.iface.upload(iface.data(), 6 * R, s, by);
   D.iobj.upload(iobj.data(), R, s, by);
   D.icobj.upload(icobj.data(), R, s, by);
@@ -1236,11 +1271,11 @@ static void build_wide_tables(ebmg_batch_s* Bt, int cells, hipStream_t s) {
       add_chunks(rb, i, 0, cdiv(half, CH));
       for (int g = 0; g < 2; ++g) {
         const int rows = F.cls_ptr.size() > (size_t)g + 1 ? F.cls_ptr[g + 1] - F.cls_ptr[g] : 0;
-        add_chunks(jac[g], i, 0, cdiv(rows, kWRows));
+        add_chunks(jac[g], i, 0, cdiv(rows, WRows<T>::v));
         add_chunks(scat[g], i, 0, cdiv(rows, kWList));
       }
       add_chunks(cell, i, 0, cdiv(F.N, CH));
-      add_chunks(cell, i, 1, cdiv(F.R, kWRows));
+      add_chunks(cell, i, 1, cdiv(F.R, WRows<T>::v));
       add_chunks(res, i, 0, cdiv(C.N, CH));
       add_chunks(res, i, 1, cdiv(F.n_ns, kWList));
       add_chunks(res, i, 2, cdiv(C.N2, kWList));
@@ -1257,6 +1292,21 @@ static void build_wide_tables(ebmg_batch_s* Bt, int cells, hipStream_t s) {
     upload_table(W.res, res, s, by);
     upload_table(W.pro, pro, s, by);
   }
+  // coarse parts that are a bottom level with an inverse go to the grid-wide
+  // bottom kernel, the others to one workgroup each
+  std::vector<WEnt> bot;
+  std::vector<int32_t> tl;
+  for (int i = 0; i < nbox; ++i) {
+    DevProblem& D = Bt->boxes[i]->dev;
+    if (lt[i] == (int)D.lv.size() - 1 && D.bottom.n > 0)
+      add_chunks(bot, i, 0, cdiv(D.bottom_n, kWBotRows));
+    else
+      tl.push_back(i);
+  }
+  upload_table(Bt->bot, bot, s, by);
+  Bt->tail_list.release();
+  Bt->n_tail = (int)tl.size();
+  if (!tl.empty()) Bt->tail_list.upload(tl.data(), (int64_t)tl.size(), s, by);
   Bt->lt.release();
   Bt->lt.upload(lt.data(), nbox, s, by);
   Bt->tail_cells = cells;
@@ -1302,7 +1352,7 @@ static void setup_wide_common(ebmg_batch_s* Bt, hipStream_t s) {
     const DevLevel& L0 = Bt->boxes[i]->dev.lv[0];
     eop[i] = (int32_t)op.size();
     add_chunks(op, i, 0, cdiv(L0.N, WCh<double>::v));
-    add_chunks(op, i, 1, cdiv(L0.R, kWRows));
+    add_chunks(op, i, 1, cdiv(L0.R, WRows<double>::v));
     evec[i] = (int32_t)vec.size();
     add_chunks(vec, i, 0, cdiv(L0.N + L0.N2, kWVec));
   }
@@ -1354,9 +1404,12 @@ static void wide_vcycle(ebmg_batch_s* Bt, int which, hipStream_t s) {
     hipLaunchKernelGGL((kw_restrict<T, DIM>), dim3(L.res.n), dim3(kWB), 0, s, view(l), view(l + 1),
                        (const WEnt*)L.res.d.p, st);
   }
-  const int nbox = (int)Bt->boxes.size();
-  hipLaunchKernelGGL((kw_tail<T, DIM>), dim3(nbox), dim3(kBE), 0, s, (const BBox<T>*)Bt->bbox.p, Bt->lt.p, st, which,
-                     Bt->nu1, Bt->nu2);
+  if (Bt->bot.n)
+    hipLaunchKernelGGL((kw_bottom<T>), dim3(Bt->bot.n), dim3(kWB), 0, s, (const BBox<T>*)Bt->bbox.p, Bt->lt.p,
+                       (const WEnt*)Bt->bot.d.p, st, which);
+  if (Bt->n_tail)
+    hipLaunchKernelGGL((kw_tail<T, DIM>), dim3(Bt->n_tail), dim3(kBE), 0, s, (const BBox<T>*)Bt->bbox.p, Bt->lt.p,
+                       Bt->tail_list.p, st, which, Bt->nu1, Bt->nu2);
   for (int l = lw - 1; l >= 0; --l) {
     auto& L = Bt->wide[l];
     hipLaunchKernelGGL((kw_prolong<T, DIM>), dim3(L.pro.n), dim3(kWB), 0, s, view(l), view(l + 1),
@@ -1524,6 +1577,8 @@ static void release_wide(ebmg_batch_s* Bt) {
   Bt->wl0[1].release();
   Bt->op64.d.release();
   Bt->vec.d.release();
+  Bt->bot.d.release();
+  Bt->tail_list.release();
   Bt->ebeg_op.release();
   Bt->ebeg_vec.release();
   Bt->lt.release();

@@ -68,12 +68,13 @@ def cpu_baseline(n=64):
 
 
 def _kernel_label(P, prec):
+    from paper_1809_03745_amd import ebmg
     var = P.tuning(0)[0]
     t = "float" if prec == 1 else "double"
-    if var == 6:
+    if var == ebmg.OOP_VARIANT:
         return f"k_rb_oop<{t},3> (one-launch colour phase of a red/black sweep, finest level)", "half-sweep"
     if var >= 2:
-        tile = ["64,8,32", "64,16,32", "32,16,32", "64,8,16"][var - 2]
+        tile = ",".join(str(v) for v in ebmg.ZM_TILES[var - 2])
         return (f"k_rb_zm3<{t},{tile}> (fused red+black Gauss-Seidel sweep marching in z, finest level)",
                 "fused sweep")
     if var == 1:
@@ -167,7 +168,8 @@ def pmc_summary(fetch_csv, write_csv, command):
            "copy_kernel": {"name": copy_key[0], "bytes": 1 << 29, "fetch_kib": sum(f[copy_key]) / len(f[copy_key]),
                            "write_kib": sum(w[copy_key]) / len(w[copy_key]), "fetch_scale": sf, "write_scale": sw},
            "kernels": {}}
-    zms = [f"k_rb_zm3<{t},{c}>" for t in ("float", "double") for c in ("64,8,32", "64,16,32", "32,16,32", "64,8,16")]
+    from paper_1809_03745_amd import ebmg
+    zms = [f"k_rb_zm3<{t},{','.join(str(v) for v in c)}>" for t in ("float", "double") for c in ebmg.ZM_TILES]
     for name in ["k_rb<float,3>", "k_rb<double,3>", "k_rb_tile3<float>", "k_rb_tile3<double>",
                  "k_resid_reg<double,3,0>", "k_resid_zm3<double,0,double,0>"] + zms:
         keys = [k for k in f if k[0] == name]
@@ -215,7 +217,7 @@ def _pct(lat, q):
     return v[min(len(v) - 1, int(round(q / 100.0 * (len(v) - 1))))]
 
 
-def batched(nbox=512, reps=3):
+def batched(nbox=512, reps=3, keys=("mixed", "fp64", "persistent_mixed", "persistent_fp64")):
     """The batched workload: 512 uneven 3D boxes, mixed precision and FP64,
     level-synchronous (every phase one launch over all boxes) and as one
     persistent launch (one workgroup per box)."""
@@ -234,6 +236,8 @@ def batched(nbox=512, reps=3):
     runs = ((ebmg.BATCH_LEVELSYNC, ebmg.MIXED, "mixed"), (ebmg.BATCH_LEVELSYNC, ebmg.FP64, "fp64"),
             (ebmg.BATCH_PERSISTENT, ebmg.MIXED, "persistent_mixed"), (ebmg.BATCH_PERSISTENT, ebmg.FP64, "persistent_fp64"))
     for mode, prec, key in runs:
+        if key not in keys:
+            continue
         B = ebmg.Batch(ctx, boxes, precision=prec, batch=mode)
         tune = B.tuning()
         phi2 = [torch.zeros(max(1, int(c)), dtype=torch.float64, device=dev) for c in cells]
@@ -328,6 +332,39 @@ def serving_bench(rates=(10.0, 100.0, 1000.0), nreq=(40, 120, 200), seed=0):
     return out
 
 
+def trace_summary(trace_csv, marker, out_md, title, command):
+    """Reduce a rocprofv3 kernel-trace CSV to a markdown table of one solve:
+    the kernels from the second-to-last dispatch whose name contains `marker`
+    (the solve's first kernel) up to the last one (or to the end of the trace
+    when there is only one)."""
+    import csv
+    import collections
+    rows = list(csv.DictReader(open(trace_csv)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    idx = [i for i, r in enumerate(rows) if marker in r["Kernel_Name"].split("(")[0]]
+    seg = rows[idx[-2]:idx[-1]] if len(idx) >= 2 else rows[idx[-1]:]
+    t0, t1 = int(seg[0]["Start_Timestamp"]), int(seg[-1]["End_Timestamp"])
+    agg = collections.defaultdict(lambda: [0, 0])
+    for r in seg:
+        g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        k = (r["Kernel_Name"].split("(")[0].replace("void ", "").replace("ebmg::", ""), g)
+        agg[k][0] += 1
+        agg[k][1] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    busy = sum(v[1] for v in agg.values())
+    lines = [f"# {title}\n", "Command (from the repository root on the GPU host; R = repository root):\n",
+             f"```\n{command}\n```\n",
+             f"One solve (from the first `{marker}` dispatch of the last solve): {len(seg)} kernels, "
+             f"{(t1 - t0) / 1e6:.2f} ms wall, {busy / 1e6:.2f} ms kernel time.\n",
+             "| kernel | grid (threads) | launches | total ms | mean us | share |", "|---|---|---|---|---|---|"]
+    for k, v in sorted(agg.items(), key=lambda kv: -kv[1][1])[:24]:
+        lines.append(f"| `{k[0]}` | {k[1]} | {v[0]} | {v[1] / 1e6:.3f} | {v[1] / v[0] / 1e3:.1f} | "
+                     f"{100 * v[1] / busy:.1f}% |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -340,6 +377,10 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true", help="run the workload of the counter passes and exit")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="reduce the counter passes of --pmc-probe to the committed traffic summary")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched workload (level-synchronous, mixed precision) and print its figures")
+    ap.add_argument("--trace-summary", nargs=5, metavar=("TRACE_CSV", "MARKER", "OUT_MD", "TITLE", "COMMAND"),
+                    help="reduce a rocprofv3 kernel trace to a committed markdown summary of one solve")
     ap.add_argument("--smoother", choices=["auto", "split", "fused", "zmarch"], default="auto",
                     help="pin the smoother choice instead of the setup autotuner (for profiled runs)")
     ap.add_argument("--tail", choices=["auto", "none", "engine"], default="auto",
@@ -355,6 +396,11 @@ def main():
         return pmc_probe(args)
     if args.pmc_summary:
         return pmc_summary(*args.pmc_summary)
+    if args.trace_summary:
+        return trace_summary(*args.trace_summary)
+    if args.batched_only:
+        print(json.dumps(batched(reps=max(1, args.steps), keys=("mixed",))))
+        return 0
     rank = int(os.environ.get("RANK", "0"))
 
     import torch

@@ -23,10 +23,7 @@
 namespace ebmg {
 
 constexpr int kWB = 256;               // threads of a level-synchronous workgroup
-template <typename T>
-struct WRows {
-  static constexpr int v = kWB / kSub * RowU<T>::v;   // explicit rows per entry
-};
+constexpr int kWRows = kWB;            // explicit rows per entry (one slice per wavefront)
 constexpr int kWList = kWB;            // list entries (one per thread) per entry
 constexpr int kWVec = 4 * kWB;         // vector entries per entry
 
@@ -90,7 +87,7 @@ __global__ void __launch_bounds__(kWB) kw_irr_jac(const BLev<T>* __restrict__ WL
   const WEnt e = tab[w_entry()];
   if (e.box < 0 || !st[e.box].active) return;
   const BLev<T>& L = WL[e.box];
-  be_irr_jac_part<T>(L, grp, L.x, L.b, e.chunk * WRows<T>::v, WRows<T>::v);
+  be_irr_jac_part<T>(L, grp, L.x, L.b, e.chunk * kWRows, kWRows);
 }
 
 template <typename T>
@@ -102,7 +99,8 @@ __global__ void __launch_bounds__(kWB) kw_irr_scat(const BLev<T>* __restrict__ W
   be_irr_scat_part<T>(L, grp, L.x, e.chunk * kWList, kWList);
 }
 
-// r = b - A x on a level: segment 0 cells, segment 1 explicit rows
+// r = b - A x on a level: segment 0 cells, segments 1 and 2 explicit rows of
+// colour group 0 and 1
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kWB) kw_resid(const BLev<T>* __restrict__ WL, const WEnt* __restrict__ tab,
                                                const WState* __restrict__ st) {
@@ -113,7 +111,7 @@ __global__ void __launch_bounds__(kWB) kw_resid(const BLev<T>* __restrict__ WL, 
   if (e.seg == 0)
     be_resid_cells_part<T, T, DIM, 0, 0>(L, L.x, L.b, L.r, e.chunk * WCh<T>::v, WCh<T>::v, nullptr, a0, a1);
   else
-    be_resid_rows_part<T, T, 0, 0>(L, L.x, L.b, L.r, e.chunk * WRows<T>::v, WRows<T>::v, nullptr, a0, a1);
+    be_resid_rows_part<T, T, 0, 0>(L, e.seg - 1, L.x, L.b, L.r, e.chunk * kWRows, kWRows, nullptr, a0, a1);
 }
 
 // restriction of the fine residual into the coarse b, coarse x cleared:
@@ -212,8 +210,7 @@ __global__ void __launch_bounds__(kWB) kw_op64(const BBox<T>* __restrict__ boxes
     be_resid_cells_part<double, TX, DIM, MODE, NDOT>(F, x, F.b, r, e.chunk * WCh<double>::v, WCh<double>::v, dv,
                                                      a0, a1);
   else
-    be_resid_rows_part<double, TX, MODE, NDOT>(F, x, F.b, r, e.chunk * WRows<double>::v, WRows<double>::v, dv, a0,
-                                               a1);
+    be_resid_rows_part<double, TX, MODE, NDOT>(F, e.seg - 1, x, F.b, r, e.chunk * kWRows, kWRows, dv, a0, a1);
   if (NDOT >= 1) {
     const double s0 = w_block_sum(a0, red[0]);
     if (threadIdx.x == 0) part0[idx] = s0;
@@ -231,7 +228,8 @@ struct WIO {
   double* phi2;
 };
 
-// right-hand side of every box: segment 0 cells, 1 explicit rows
+// right-hand side of every box: segment 0 cells, 1 and 2 explicit rows of
+// colour group 0 and 1
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kWB) kw_rhs(const BBox<T>* __restrict__ boxes, const WEnt* __restrict__ tab,
                                              const WIO* __restrict__ io) {
@@ -244,7 +242,8 @@ __global__ void __launch_bounds__(kWB) kw_rhs(const BBox<T>* __restrict__ boxes,
     be_rhs_cells_part<DIM>(F, B.dat, o.rho, F.b, e.chunk * WCh<double>::v, WCh<double>::v);
   else
     be_rhs_rows_part(F, B.fv, B.icell, B.isrc, B.iface, B.iobj, B.icobj, B.icsig, B.objv, o.rho, o.sigma, F.b,
-                     e.chunk * WRows<double>::v, WRows<double>::v);
+                     F.grp_ptr[e.seg - 1] + e.chunk * kWRows,
+                     min(kWRows, F.grp_ptr[e.seg] - F.grp_ptr[e.seg - 1] - e.chunk * kWRows));
 }
 
 enum WVecOp { WV_INIT = 0, WV_P, WV_S, WV_XR, WV_RESTART, WV_OUT };

@@ -19,6 +19,7 @@
 namespace ebmg {
 
 constexpr int kBE = 512;        // threads of an engine workgroup (two per CU)
+constexpr int kSlice = 64;      // rows per slice of the sliced explicit-row layout (one wavefront)
 constexpr int kMaxLev = 16;
 
 // Device view of one multigrid level (all pointers device memory).
@@ -35,6 +36,12 @@ struct BLev {
   const T* diag;
   const int32_t* grp_rows;
   int grp_ptr[3];
+  // sliced copy of the explicit rows: kSlice rows per slice, entry j of a
+  // slice's rows contiguous; slices sl_grp[g] .. sl_grp[g + 1] - 1 hold group g
+  const int64_t* sl_ptr;
+  const int32_t* sl_col;
+  const T* sl_val;
+  int sl_grp[3];
   Tmpl<T> tp;
   T* x;
   T* b;
@@ -157,111 +164,80 @@ __device__ void be_rb(const BLev<T>& L, T* __restrict__ x, const T* __restrict__
   __syncthreads();
 }
 
-// Explicit rows (stored group by group, so a colour group is a row range),
-// kSub lanes per row and RowU<T> rows per lane group. Entries are fetched in
-// passes of kRowJ per lane and row: all columns and values of a pass (every
-// row of the group) are requested, then all x values, then summed, so a lane
-// keeps RowU * kRowJ independent load chains in flight. Per lane the entries
-// are summed in row order and the lanes combined by row_dot's xor-shuffle
-// tree, so each sum is row_dot's bit for bit.
-template <typename T>
-struct RowU {
-  static constexpr int v = sizeof(T) == 4 ? 4 : 2;
-};
-constexpr int kRowJ = 4;
+// Explicit rows, sliced layout: one thread per row, a wavefront per slice of
+// kSlice rows of one colour group, so every column and value load is one
+// contiguous wavefront access. Entries are fetched kRowJ at a time (columns
+// and values, then the x values, then summed in entry order): a thread keeps
+// kRowJ load chains in flight. Padding entries add 0 * x[0].
+constexpr int kRowJ = 8;
 
-template <typename T, typename TX, int RU>
-__device__ __forceinline__ void rows_dot(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                         const T* __restrict__ val, const TX* __restrict__ x, int g0, int gstep,
-                                         int end, int lane, T (&s)[RU]) {
+template <typename T, typename TX>
+__device__ __forceinline__ T sliced_row(const int32_t* __restrict__ col, const T* __restrict__ val,
+                                        const TX* __restrict__ x, int64_t p, int len) {
   FP_EXACT_ORDER
-  int64_t q[RU], e[RU];
+  T s = T(0);
+  int j = 0;
+  for (; j + kRowJ <= len; j += kRowJ) {
+    int c[kRowJ];
+    T v[kRowJ], xv[kRowJ];
 #pragma unroll
-  for (int u = 0; u < RU; ++u) {
-    const int g = g0 + u * gstep;
-    q[u] = 0;
-    e[u] = 0;
-    if (g < end) {
-      q[u] = rp[g] + lane;
-      e[u] = rp[g + 1];
+    for (int k = 0; k < kRowJ; ++k) {
+      c[k] = col[p + (int64_t)(j + k) * kSlice];
+      v[k] = val[p + (int64_t)(j + k) * kSlice];
     }
-    s[u] = T(0);
+#pragma unroll
+    for (int k = 0; k < kRowJ; ++k) xv[k] = (T)x[c[k]];
+#pragma unroll
+    for (int k = 0; k < kRowJ; ++k) s = s + v[k] * xv[k];
   }
-  for (int base = 0;; base += kRowJ * kSub) {
-    int c[RU][kRowJ];
-    T v[RU][kRowJ], xv[RU][kRowJ];
-#pragma unroll
-    for (int u = 0; u < RU; ++u)
-#pragma unroll
-      for (int j = 0; j < kRowJ; ++j) {
-        const int64_t k = q[u] + base + j * kSub;
-        c[u][j] = 0;
-        v[u][j] = T(0);
-        if (k < e[u]) {
-          c[u][j] = col[k];
-          v[u][j] = val[k];
-        }
-      }
-#pragma unroll
-    for (int u = 0; u < RU; ++u)
-#pragma unroll
-      for (int j = 0; j < kRowJ; ++j) {
-        xv[u][j] = T(0);
-        if (q[u] + base + j * kSub < e[u]) xv[u][j] = (T)x[c[u][j]];
-      }
-    bool more = false;
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-#pragma unroll
-      for (int j = 0; j < kRowJ; ++j)
-        if (q[u] + base + j * kSub < e[u]) s[u] = s[u] + v[u][j] * xv[u][j];
-      more = more || q[u] + base + kRowJ * kSub < e[u];
-    }
-    if (!more) break;
-  }
-#pragma unroll
-  for (int u = 0; u < RU; ++u)
-    for (int off = kSub / 2; off > 0; off >>= 1) s[u] += __shfl_xor(s[u], off, kSub);
+  for (; j < len; ++j) s = s + val[p + (int64_t)j * kSlice] * (T)x[col[p + (int64_t)j * kSlice]];
+  return s;
 }
+
+// Visit the rows [beg, beg + cnt) of colour group grp (relative to the
+// group; beg a multiple of kSlice) one slice per wavefront. pre(g) issues the
+// row's own loads (unknown index, diagonal, b) before the entry loop and
+// returns them; f(g, pre, s) finishes the row, s its off-diagonal sum.
+template <typename T, typename TX, typename Pre, typename F>
+__device__ __forceinline__ void sliced_rows(const BLev<T>& L, int grp, const TX* __restrict__ x, int beg, int cnt,
+                                            Pre&& pre, F&& f) {
+  const int r0 = L.grp_ptr[grp];
+  const int n = L.grp_ptr[grp + 1] - r0;
+  const int end = be_end(n, beg, cnt);
+  const int lane = threadIdx.x & (kSlice - 1), wave = threadIdx.x / kSlice, nw = blockDim.x / kSlice;
+  for (int s0 = beg + wave * kSlice; s0 < end; s0 += nw * kSlice) {
+    const int sl = L.sl_grp[grp] + s0 / kSlice;
+    const int64_t p0 = L.sl_ptr[sl];
+    const int len = (int)((L.sl_ptr[sl + 1] - p0) / kSlice);
+    const int g = s0 + lane;
+    const bool in = g < end;
+    const auto own = pre(r0 + (in ? g : 0));
+    const T sm = sliced_row<T, TX>(L.sl_col, L.sl_val, x, p0 + lane, len);
+    if (in) f(r0 + g, own, sm);
+  }
+}
+
+template <typename T>
+struct RowOwn {
+  int64_t q;
+  T d, v;
+};
 
 // Jacobi values (b - offdiag . x) / diag of group grp's rows [beg, beg + cnt)
 // (relative to the group) into w.
-template <typename T, int RU = RowU<T>::v>
+template <typename T>
 __device__ void be_irr_jac_part(const BLev<T>& L, int grp, const T* __restrict__ x, const T* __restrict__ b,
                                 int beg, int cnt) {
   FP_EXACT_ORDER
   const int r0 = L.grp_ptr[grp];
-  const int end = r0 + be_end(L.grp_ptr[grp + 1] - r0, beg, cnt);
-  const int lane = threadIdx.x % kSub;
-  const int nsub = (int)blockDim.x / kSub;
-  for (int g0 = r0 + beg + (int)threadIdx.x / kSub; g0 < end; g0 += nsub * RU) {
-    T bv[RU], dg[RU];
-    int64_t q[RU];
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const int g = g0 + u * nsub;
-      q[u] = 0;
-      dg[u] = T(1);
-      if (g < end) {
-        q[u] = L.irow_dof[g];
-        dg[u] = L.diag[g];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      bv[u] = T(0);
-      if (g0 + u * nsub < end) bv[u] = b[q[u]];
-    }
-    T sm[RU];
-    rows_dot<T, T, RU>(L.rp, L.col, L.val, x, g0, nsub, end, lane, sm);
-    if (lane == 0) {
-#pragma unroll
-      for (int u = 0; u < RU; ++u) {
-        const int g = g0 + u * nsub;
-        if (g < end) L.w[g - r0] = (bv[u] - sm[u]) / dg[u];
-      }
-    }
-  }
+  if (L.grp_ptr[grp + 1] <= r0) return;
+  sliced_rows<T, T>(
+      L, grp, x, beg, cnt,
+      [&](int g) {
+        const int64_t q = L.irow_dof[g];
+        return RowOwn<T>{q, L.diag[g], b[q]};
+      },
+      [&](int g, const RowOwn<T>& o, T sm) { L.w[g - r0] = (o.v - sm) / o.d; });
 }
 
 template <typename T>
@@ -274,7 +250,7 @@ __device__ void be_irr_scat_part(const BLev<T>& L, int grp, T* __restrict__ x, i
 template <typename T>
 __device__ void be_irr_group(const BLev<T>& L, int grp, T* __restrict__ x, const T* __restrict__ b) {
   if (L.grp_ptr[grp + 1] <= L.grp_ptr[grp]) return;
-  be_irr_jac_part<T, 1>(L, grp, x, b, 0, kAll);   // one row per lane group keeps the engine's registers low
+  be_irr_jac_part<T>(L, grp, x, b, 0, kAll);
   __syncthreads();
   be_irr_scat_part<T>(L, grp, x, 0, kAll);
   __syncthreads();
@@ -360,57 +336,34 @@ __device__ void be_resid_cells_part(const BLev<T>& L, const TX* __restrict__ x, 
   }
 }
 
-template <typename T, typename TX, int MODE, int NDOT, int RU = RowU<T>::v>
-__device__ void be_resid_rows_part(const BLev<T>& L, const TX* __restrict__ x, const T* __restrict__ b,
+// Explicit rows of colour group grp, [beg, beg + cnt) relative to the group.
+template <typename T, typename TX, int MODE, int NDOT>
+__device__ void be_resid_rows_part(const BLev<T>& L, int grp, const TX* __restrict__ x, const T* __restrict__ b,
                                    T* __restrict__ r, int beg, int cnt, const double* __restrict__ da,
                                    double& acc0, double& acc1) {
   FP_EXACT_ORDER
-  const int lane = threadIdx.x % kSub;
-  const int nsub = (int)blockDim.x / kSub;
-  const int end = be_end(L.R, beg, cnt);
-  for (int g0 = beg + (int)threadIdx.x / kSub; g0 < end; g0 += nsub * RU) {
-    int64_t q[RU];
-    T dg[RU], xq[RU], bq[RU];
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const int g = g0 + u * nsub;
-      q[u] = 0;
-      dg[u] = T(0);
-      if (g < end) {
-        q[u] = L.irow_dof[g];
-        dg[u] = L.diag[g];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      xq[u] = T(0);
-      bq[u] = T(0);
-      if (g0 + u * nsub < end) {
-        xq[u] = (T)x[q[u]];
-        if (MODE == 0) bq[u] = b[q[u]];
-      }
-    }
-    T sm[RU];
-    rows_dot<T, TX, RU>(L.rp, L.col, L.val, x, g0, nsub, end, lane, sm);
-    if (lane == 0) {
-#pragma unroll
-      for (int u = 0; u < RU; ++u) {
-        if (g0 + u * nsub >= end) continue;
-        const T ax = dg[u] * xq[u] + sm[u];
-        const T o = MODE == 0 ? bq[u] - ax : ax;
-        r[q[u]] = o;
-        if (NDOT >= 1) acc0 += da[q[u]] * (double)o;
+  if (L.grp_ptr[grp + 1] <= L.grp_ptr[grp]) return;
+  sliced_rows<T, TX>(
+      L, grp, x, beg, cnt,
+      [&](int g) {
+        const int64_t q = L.irow_dof[g];
+        return RowOwn<T>{q, L.diag[g], (T)x[q]};
+      },
+      [&](int g, const RowOwn<T>& w, T sm) {
+        const T ax = w.d * w.v + sm;
+        const T o = MODE == 0 ? b[w.q] - ax : ax;
+        r[w.q] = o;
+        if (NDOT >= 1) acc0 += da[w.q] * (double)o;
         if (NDOT == 2) acc1 += (double)o * (double)o;
-      }
-    }
-  }
+      });
 }
 
 template <typename T, int DIM, int MODE>
 __device__ void be_resid(const BLev<T>& L, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ r) {
   double a0 = 0, a1 = 0;
   be_resid_cells_part<T, T, DIM, MODE, 0>(L, x, b, r, 0, kAll, nullptr, a0, a1);
-  be_resid_rows_part<T, T, MODE, 0, 1>(L, x, b, r, 0, kAll, nullptr, a0, a1);
+  be_resid_rows_part<T, T, MODE, 0>(L, 0, x, b, r, 0, kAll, nullptr, a0, a1);
+  be_resid_rows_part<T, T, MODE, 0>(L, 1, x, b, r, 0, kAll, nullptr, a0, a1);
   __syncthreads();
 }
 

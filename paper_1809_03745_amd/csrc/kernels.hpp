@@ -34,6 +34,24 @@ struct Tmpl {
 constexpr int kBlock = 256;
 constexpr int kNormBlocks = 1024;
 
+// Streams that a launch reads or writes exactly once (right-hand sides,
+// tags, outputs) carry non-temporal hints when HINT is set, so they do not
+// displace the x planes that neighbouring tiles re-read from the caches. On
+// gfx950 this pays for the FP64 residual (8-byte streams, ~11 % at 256^3)
+// and costs the FP32 kernels, which therefore load plainly.
+template <bool HINT, typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  if (HINT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+template <bool HINT, typename T>
+__device__ __forceinline__ void st_stream(T v, T* p) {
+  if (HINT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
 __device__ __forceinline__ uint8_t tclass(uint8_t t) { return t & 3; }
 
 template <typename T, int DIM>
@@ -780,18 +798,19 @@ __global__ void __launch_bounds__(kRZX * kRZY) k_resid_zm3(const uint8_t* __rest
     T xc = (T)x[c];
     T xp = z0 + 1 < nz ? (T)x[c + sxy] : T(0);
     T w = (T)x[c + ow], e = (T)x[c + oe], so = (T)x[c + os], no = (T)x[c + on];
-    uint8_t tg = tag[c];
-    T bb = MODE == 0 ? b[c] : T(0);
-    T dc = NDOT > 0 ? da[c] : T(0);
+    constexpr bool H = sizeof(T) == 8;
+    uint8_t tg = ld_stream<H>(tag + c);
+    T bb = MODE == 0 ? ld_stream<H>(b + c) : T(0);
+    T dc = NDOT > 0 ? ld_stream<H>(da + c) : T(0);
     for (int k = z0; k < z1; ++k, c += sxy) {
       // requests for plane k + 1 (its neighbours, b and tag) and x of k + 2
       const bool more = k + 1 < z1;
       const int64_t cn = more ? c + sxy : c;
       const T xpp = k + 2 < nz ? (T)x[c + 2 * sxy] : T(0);
       const T wn = (T)x[cn + ow], en = (T)x[cn + oe], son = (T)x[cn + os], non = (T)x[cn + on];
-      const uint8_t tgn = more ? tag[cn] : (uint8_t)3;
-      const T bbn = (MODE == 0 && more) ? b[cn] : T(0);
-      const T dcn = (NDOT > 0 && more) ? da[cn] : T(0);
+      const uint8_t tgn = more ? ld_stream<H>(tag + cn) : (uint8_t)3;
+      const T bbn = (MODE == 0 && more) ? ld_stream<H>(b + cn) : T(0);
+      const T dcn = (NDOT > 0 && more) ? ld_stream<H>(da + cn) : T(0);
       const int p = tclass(tg);
       if (p != 2) {
         T out;
@@ -809,7 +828,7 @@ __global__ void __launch_bounds__(kRZX * kRZY) k_resid_zm3(const uint8_t* __rest
           const T ax = dg * xc + tc[0] * s;
           out = MODE == 0 ? bb - ax : ax;
         }
-        r[c] = out;
+        st_stream<H>(out, r + c);
         if (NDOT > 0) {
           d0 += (double)dc * (double)out;
           if (NDOT > 1) d1 += (double)out * (double)out;

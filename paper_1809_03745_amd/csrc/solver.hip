@@ -88,6 +88,12 @@ struct DevLevel {
   DevBuf<double> val64, diag64;
   DevBuf<float> val32, diag32;
   std::vector<int32_t> cls_ptr;
+  // sliced copy of the explicit rows (engine and batched kernels)
+  DevBuf<int64_t> sl_ptr;
+  DevBuf<int32_t> sl_col;
+  DevBuf<double> sl_val64;
+  DevBuf<float> sl_val32;
+  int sl_grp[3] = {0, 0, 0};
   int64_t n_ns = 0, n_np = 0;
   bool fused = false;              // smoother variant chosen for this level
   bool oop = false;                // non-fused: one-launch colour phases (else split in place)
@@ -103,6 +109,7 @@ struct DevLevel {
     tag.release(); irow_dof.release(); rp.release(); ns_cdof.release(); ns_child.release();
     np_fdof.release(); np_cdof.release(); col.release(); cls_rows.release(); ns_ptr.release();
     val64.release(); diag64.release(); val32.release(); diag32.release();
+    sl_ptr.release(); sl_col.release(); sl_val64.release(); sl_val32.release();
     x64.release(); b64.release(); r64.release(); x32.release(); b32.release(); r32.release();
     w64.release(); w32.release(); xa64.release(); xa32.release();
   }
@@ -230,6 +237,7 @@ struct Vec<double> {
   static double* r(DevLevel& l) { return l.r64.p; }
   static const double* val(DevLevel& l) { return l.val64.p; }
   static const double* diag(DevLevel& l) { return l.diag64.p; }
+  static const double* sval(DevLevel& l) { return l.sl_val64.p; }
   static const Tmpl<double>& t(DevLevel& l) { return l.t64; }
   static double* tmp(DevLevel& l) { return l.w64.p; }
   static double* xa(DevLevel& l) { return l.xa64.p; }
@@ -241,6 +249,7 @@ struct Vec<float> {
   static float* r(DevLevel& l) { return l.r32.p; }
   static const float* val(DevLevel& l) { return l.val32.p; }
   static const float* diag(DevLevel& l) { return l.diag32.p; }
+  static const float* sval(DevLevel& l) { return l.sl_val32.p; }
   static const Tmpl<float>& t(DevLevel& l) { return l.t32; }
   static float* tmp(DevLevel& l) { return l.w32.p; }
   static float* xa(DevLevel& l) { return l.xa32.p; }
@@ -272,7 +281,7 @@ static bool fused_ok(const DevLevel& l) {
 
 // z-marching sweep configurations (tile width x height x planes per block);
 // the setup autotuner picks one per level
-constexpr int kZMConfigs = 4;
+constexpr int kZMConfigs = 7;
 
 template <typename T, int TX, int TY, int KZ>
 static void launch_zm_cfg(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s) {
@@ -287,6 +296,9 @@ static void launch_zm(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl
     case 1: launch_zm_cfg<T, 64, 16, 32>(l, xin, xout, b, tp, s); break;
     case 2: launch_zm_cfg<T, 32, 16, 32>(l, xin, xout, b, tp, s); break;
     case 3: launch_zm_cfg<T, 64, 8, 16>(l, xin, xout, b, tp, s); break;
+    case 4: launch_zm_cfg<T, 128, 8, 32>(l, xin, xout, b, tp, s); break;
+    case 5: launch_zm_cfg<T, 32, 8, 32>(l, xin, xout, b, tp, s); break;
+    case 6: launch_zm_cfg<T, 32, 32, 32>(l, xin, xout, b, tp, s); break;
     default: launch_zm_cfg<T, 64, 8, 32>(l, xin, xout, b, tp, s); break;
   }
 }
@@ -324,7 +336,11 @@ static BLev<T> make_blev(DevLevel& l) {
   v.val = Vec<T>::val(l);
   v.diag = Vec<T>::diag(l);
   v.grp_rows = l.cls_rows.p;
-  for (int g = 0; g < 3; ++g) v.grp_ptr[g] = g < (int)l.cls_ptr.size() ? l.cls_ptr[g] : 0;
+  for (int g = 0; g < 3; ++g) v.grp_ptr[g] = g < (int)l.cls_ptr.size() ? l.cls_ptr[g] : (g == 0 ? 0 : (int)l.R);
+  v.sl_ptr = l.sl_ptr.p;
+  v.sl_col = l.sl_col.p;
+  v.sl_val = Vec<T>::sval(l);
+  for (int g = 0; g < 3; ++g) v.sl_grp[g] = l.sl_grp[g];
   v.tp = Vec<T>::t(l);
   v.x = Vec<T>::x(l);
   v.b = Vec<T>::b(l);
@@ -503,14 +519,60 @@ static void tune_smoother(DevLevel& l, bool mixed, int mode, hipStream_t s) {
   }
 }
 
-// Device order of a level's explicit rows: by colour group (host row order
-// within a group).
+// Device order of a level's explicit rows: by colour group, and within
+// windows of kSortWindow rows of a group by decreasing number of stored
+// entries (host order among equals), so the 64-row slices of the sliced
+// layout need little padding while a slice's rows stay near each other.
+constexpr int64_t kSortWindow = 512;
 static std::vector<int32_t> row_order(const Level& L) {
   const int64_t R = (int64_t)L.irow_dof.size();
-  if ((int64_t)L.cls_rows.size() == R) return L.cls_rows;
-  std::vector<int32_t> id(R);
-  for (int64_t k = 0; k < R; ++k) id[k] = (int32_t)k;
+  std::vector<int32_t> id;
+  std::vector<int32_t> ptr;
+  if ((int64_t)L.cls_rows.size() == R && L.cls_ptr.size() == 3) {
+    id = L.cls_rows;
+    ptr = L.cls_ptr;
+  } else {
+    id.resize(R);
+    for (int64_t k = 0; k < R; ++k) id[k] = (int32_t)k;
+    ptr = {0, (int32_t)R, (int32_t)R};
+  }
+  auto len = [&](int32_t r) { return L.rp[r + 1] - L.rp[r]; };
+  for (int g = 0; g < 2; ++g)
+    for (int64_t w0 = ptr[g]; w0 < ptr[g + 1]; w0 += kSortWindow)
+      std::stable_sort(id.begin() + w0, id.begin() + std::min<int64_t>(ptr[g + 1], w0 + kSortWindow),
+                       [&](int32_t a, int32_t b) { return len(a) > len(b); });
   return id;
+}
+
+// Sliced layout of the (device-ordered) explicit rows: each colour group is
+// cut into slices of kSlice rows; entry j of the slice's rows is stored at
+// sl_ptr[slice] + j * kSlice + (row within the slice), padded to the slice's
+// longest row with column 0 and value 0. grp[g] is group g's first slice.
+static void build_sliced(const std::vector<int64_t>& rp, const std::vector<int32_t>& col,
+                         const std::vector<double>& val, const std::vector<int32_t>& gptr,
+                         std::vector<int64_t>& sptr, std::vector<int32_t>& scol, std::vector<double>& sval,
+                         int grp[3]) {
+  sptr.assign(1, 0);
+  scol.clear();
+  sval.clear();
+  for (int g = 0; g < 2; ++g) {
+    grp[g] = (int)sptr.size() - 1;
+    for (int64_t r0 = gptr[g]; r0 < gptr[g + 1]; r0 += kSlice) {
+      const int64_t r1 = std::min<int64_t>(gptr[g + 1], r0 + kSlice);
+      int64_t len = 0;
+      for (int64_t r = r0; r < r1; ++r) len = std::max(len, rp[r + 1] - rp[r]);
+      const int64_t base = sptr.back();
+      scol.resize(base + len * kSlice, 0);
+      sval.resize(base + len * kSlice, 0.0);
+      for (int64_t r = r0; r < r1; ++r)
+        for (int64_t j = 0; j < rp[r + 1] - rp[r]; ++j) {
+          scol[base + j * kSlice + (r - r0)] = col[rp[r] + j];
+          sval[base + j * kSlice + (r - r0)] = val[rp[r] + j];
+        }
+      sptr.push_back(base + len * kSlice);
+    }
+  }
+  grp[2] = (int)sptr.size() - 1;
 }
 
 static void upload(ebmg_problem_s* P, bool batch_box = false) {
@@ -559,6 +621,21 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
       std::vector<float> v(val.begin(), val.end()), g(dg.begin(), dg.end());
       d.val32.upload(v.data(), (int64_t)v.size(), s, by);
       d.diag32.upload(g.data(), (int64_t)g.size(), s, by);
+    }
+    {
+      std::vector<int32_t> gptr = L.cls_ptr.size() == 3 ? L.cls_ptr : std::vector<int32_t>{0, (int32_t)d.R, (int32_t)d.R};
+      std::vector<int64_t> sptr;
+      std::vector<int32_t> scol;
+      std::vector<double> sval;
+      build_sliced(rp, col, val, gptr, sptr, scol, sval, d.sl_grp);
+      d.sl_ptr.upload(sptr.data(), (int64_t)sptr.size(), s, by);
+      d.sl_col.upload(scol.data(), (int64_t)scol.size(), s, by);
+      d.sl_val64.upload(sval.data(), (int64_t)sval.size(), s, by);
+      if (mixed) {
+        std::vector<float> v(sval.begin(), sval.end());
+        d.sl_val32.upload(v.data(), (int64_t)v.size(), s, by);
+      }
+      HIPCHECK(hipStreamSynchronize(s));
     }
     HIPCHECK(hipStreamSynchronize(s));
     d.n_ns = (int64_t)L.ns_cdof.size();
@@ -1216,6 +1293,12 @@ static void upload_batch_views(ebmg_batch_s* Bt, hipStream_t s) {
 // ---------------------------------------------------------------------------
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// Explicit rows of colour group g of a level (as the device views count them).
+static int group_rows(const DevLevel& l, int g) {
+  if (l.cls_ptr.size() == 3) return l.cls_ptr[g + 1] - l.cls_ptr[g];
+  return g == 0 ? (int)l.R : 0;
+}
+
 // Append chunks [0, nch) of segment seg of box b.
 static inline void add_chunks(std::vector<WEnt>& t, int b, int seg, int nch) {
   for (int c = 0; c < nch; ++c) t.push_back(WEnt{b, seg, c, 0});
@@ -1270,12 +1353,13 @@ static void build_wide_tables(ebmg_batch_s* Bt, int cells, hipStream_t s) {
       const int64_t half = (int64_t)((F.n[0] + 1) / 2) * F.n[1] * (F.dim == 3 ? F.n[2] : 1);
       add_chunks(rb, i, 0, cdiv(half, CH));
       for (int g = 0; g < 2; ++g) {
-        const int rows = F.cls_ptr.size() > (size_t)g + 1 ? F.cls_ptr[g + 1] - F.cls_ptr[g] : 0;
-        add_chunks(jac[g], i, 0, cdiv(rows, WRows<T>::v));
+        const int rows = group_rows(F, g);
+        add_chunks(jac[g], i, 0, cdiv(rows, kWRows));
         add_chunks(scat[g], i, 0, cdiv(rows, kWList));
       }
       add_chunks(cell, i, 0, cdiv(F.N, CH));
-      add_chunks(cell, i, 1, cdiv(F.R, WRows<T>::v));
+      add_chunks(cell, i, 1, cdiv(group_rows(F, 0), kWRows));
+      add_chunks(cell, i, 2, cdiv(group_rows(F, 1), kWRows));
       add_chunks(res, i, 0, cdiv(C.N, CH));
       add_chunks(res, i, 1, cdiv(F.n_ns, kWList));
       add_chunks(res, i, 2, cdiv(C.N2, kWList));
@@ -1352,7 +1436,8 @@ static void setup_wide_common(ebmg_batch_s* Bt, hipStream_t s) {
     const DevLevel& L0 = Bt->boxes[i]->dev.lv[0];
     eop[i] = (int32_t)op.size();
     add_chunks(op, i, 0, cdiv(L0.N, WCh<double>::v));
-    add_chunks(op, i, 1, cdiv(L0.R, WRows<double>::v));
+    add_chunks(op, i, 1, cdiv(group_rows(L0, 0), kWRows));
+    add_chunks(op, i, 2, cdiv(group_rows(L0, 1), kWRows));
     evec[i] = (int32_t)vec.size();
     add_chunks(vec, i, 0, cdiv(L0.N + L0.N2, kWVec));
   }

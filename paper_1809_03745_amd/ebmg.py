@@ -310,9 +310,10 @@ class Problem:
                        "ebmg_efield")
 
     def tuning(self, level):
-        """(smoother variant: 0 split, 1 tile, 2 z-march; split sweep ms; chosen or
-        best fused sweep ms) from the setup autotuner; level -1: (first tail
-        level or -1, V-cycle ms without tail, V-cycle ms chosen)."""
+        """(smoother variant: 0 split, 1 tile, 2 + c z-march in tile ZM_TILES[c],
+        OOP_VARIANT one-launch colour phases; split sweep ms; chosen or best
+        fused sweep ms) from the setup autotuner; level -1: (first tail level
+        or -1, V-cycle ms without tail, V-cycle ms chosen)."""
         f, a, b = C.c_int32(), C.c_double(), C.c_double()
         self.ctx.check(_lib.ebmg_query_tuning(self.h, level, C.byref(f), C.byref(a), C.byref(b)), "tuning")
         return f.value, a.value, b.value
@@ -350,6 +351,11 @@ class Problem:
         except Exception:
             pass
 
+
+# z-marching smoother tiles (x, y, planes), in the library's configuration order
+ZM_TILES = [(64, 8, 32), (64, 16, 32), (32, 16, 32), (64, 8, 16), (128, 8, 32), (32, 8, 32), (32, 32, 32)]
+OOP_VARIANT = 2 + len(ZM_TILES)      # tuning code of the one-launch colour phases
+SMOOTH_OOP = 3 + len(ZM_TILES)       # ebmg_smooth variant of the one-launch colour phases
 
 BATCH_LEVELSYNC = 2    # every phase one launch over all boxes (default)
 BATCH_PERSISTENT = 1   # one persistent launch, one workgroup per box

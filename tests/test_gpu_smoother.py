@@ -77,7 +77,7 @@ def test_smoother_variants(ctx, name, prec):
             continue
         x0 = rng.normal(size=n + n2)
         b = rng.normal(size=n + n2)
-        variants = [1, 2, 3, 4, 5, 6, 7] if pr.dim == 3 else [1, 2, 7]
+        variants = list(range(1, ebmg.SMOOTH_OOP + 1)) if pr.dim == 3 else [1, 2, ebmg.SMOOTH_OOP]
         outs = {}
         for v in variants:
             xt = torch.tensor(x0, dtype=torch.float64, device=DEV)

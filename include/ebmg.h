@@ -122,7 +122,12 @@ typedef struct {
                                launch over all boxes, coarse levels per box in
                                one workgroup), 1 one persistent launch with one
                                workgroup per box                                 */
-  int32_t reserved[4];      /* must be zero                                      */
+  int32_t graphs;           /* 0: each Krylov iteration / refinement cycle (and
+                               each batched iteration) is captured once as a HIP
+                               graph on a private stream and replayed on the
+                               context stream; 1: kernels launched directly.
+                               Both run the same kernels in the same order      */
+  int32_t reserved[3];      /* must be zero                                      */
 } ebmg_options;
 
 typedef struct {

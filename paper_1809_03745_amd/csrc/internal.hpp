@@ -171,7 +171,7 @@ struct FineData {
 struct Options {
   double alpha = 0, beta = -1, a_gas = 0, a_diel = 0, b_gas = 1;
   int dirichlet_closure = 0, robin_closure = 0, eb_order = 2;
-  int precision = 0, nu1 = 2, nu2 = 2, bottom_max = 600, krylov = 1, smoother = 0, tail = 0, batch = 0;
+  int precision = 0, nu1 = 2, nu2 = 2, bottom_max = 600, krylov = 1, smoother = 0, tail = 0, batch = 0, graphs = 0;
 };
 
 struct Problem {

@@ -140,8 +140,16 @@ struct DevProblem {
   std::vector<int> tail_cand;     // candidate first tail levels timed at setup
   std::vector<double> tail_ms;    // V-cycle ms for each candidate
   DevBuf<uint8_t> tail_lv;
+  // replayed iteration graphs (captured at the first solve that needs them)
+  hipGraphExec_t g_krylov = nullptr, g_plain = nullptr;
   int64_t bytes = 0;
+  void drop_graphs() {
+    if (g_krylov) (void)hipGraphExecDestroy(g_krylov);
+    if (g_plain) (void)hipGraphExecDestroy(g_plain);
+    g_krylov = g_plain = nullptr;
+  }
   void release() {
+    drop_graphs();
     for (auto& l : lv) l.release();
     lv.clear();
     bottom.release(); icell.release(); isrc.release(); iface.release(); icobj.release(); icsig.release();
@@ -209,6 +217,11 @@ struct ebmg_batch_s {
   int tail_cells = 0;
   std::vector<int> cand_cells;
   std::vector<double> cand_ms;
+  // replayed iteration graph and the stopping parameters baked into it
+  bool graphs = true;
+  hipGraphExec_t g_iter = nullptr;
+  double g_rtol = 0;
+  int g_max_cycles = -1;
 };
 
 namespace ebmg {
@@ -805,7 +818,8 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
       irr_group<T>(l, 0, cur, b, s);
       irr_group<T>(l, 1, cur, b, s);
     }
-    if (cur != x) HIPCHECK(hipMemcpyAsync(x, cur, sizeof(T) * (l.N + l.N2), hipMemcpyDeviceToDevice, s));
+    if (cur != x)
+      hipLaunchKernelGGL((k_convert<T, T>), dim3(nblk(l.N + l.N2)), dim3(kBlock), 0, s, cur, x, l.N + l.N2);
     HIPCHECK(hipGetLastError());
     return;
   }
@@ -946,6 +960,37 @@ static void dot_dev(DevProblem& D, const T* a, const T* b, int64_t n, int slot, 
   HIPCHECK(hipGetLastError());
 }
 
+// Run body(stream) as a HIP graph on s: captured once on a private stream
+// (default priority) into exec, then replayed. The captured work holds only
+// kernel launches (no memset or copy nodes).
+template <typename F>
+static void graph_run(hipGraphExec_t& exec, hipStream_t s, F&& body) {
+  if (!exec) {
+    hipStream_t cs = nullptr;
+    HIPCHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    try {
+      HIPCHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      body(cs);
+      HIPCHECK(hipStreamEndCapture(cs, &g));
+      HIPCHECK(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+    } catch (...) {
+      hipGraph_t junk = nullptr;
+      hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(cs, &cst) == hipSuccess && cst != hipStreamCaptureStatusNone)
+        (void)hipStreamEndCapture(cs, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipStreamDestroy(cs);
+      exec = nullptr;
+      throw;
+    }
+    (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+  }
+  HIPCHECK(hipGraphLaunch(exec, s));
+}
+
 static void fetch_scalars(DevProblem& D, hipStream_t s) {
   HIPCHECK(hipMemcpyAsync(D.host_scal, D.scal.p, SC_NUM * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
@@ -1084,30 +1129,37 @@ static ebmg_status bicgstab_t(DevProblem& D, const Options& o, double bn, double
     hipLaunchKernelGGL(k_sc_reset, dim3(1), dim3(1), 0, s, D.scal.p);
     dot_dev<double>(D, rh, r, nd, SC_RHO, s);
   };
-  auto vcyc = [&](Z* z, const double* in) {
+  auto vcyc = [&](Z* z, const double* in, hipStream_t q) {
     if constexpr (std::is_same<Z, float>::value) {
       (void)in;
-      vcycle<float>(D, o, 0, s, z, L.b32.p);
+      vcycle<float>(D, o, 0, q, z, L.b32.p);
     } else {
-      vcycle<double>(D, o, 0, s, z, in);
+      vcycle<double>(D, o, 0, q, z, in);
     }
+  };
+  // one iteration: p-update, V-cycle, A ph, s-update, V-cycle, A sh, x/r update
+  auto iteration = [&](hipStream_t q) {
+    hipLaunchKernelGGL((k_bicg_p2<Z>), dim3(nb), dim3(kBlock), 0, q, p, r, v, D.scal.p, nd, bf, ph);
+    vcyc(ph, p, q);
+    matvec_dots<Z>(D, ph, v, rh, 1, SC_RV, q);
+    hipLaunchKernelGGL(k_sc_alpha, dim3(1), dim3(1), 0, q, D.scal.p);
+    hipLaunchKernelGGL((k_bicg_s2<Z>), dim3(nb), dim3(kBlock), 0, q, sv, r, v, D.scal.p, nd, bf, sh);
+    vcyc(sh, sv, q);
+    matvec_dots<Z>(D, sh, t, sv, 2, SC_TS, q);
+    hipLaunchKernelGGL(k_sc_omega, dim3(1), dim3(1), 0, q, D.scal.p);
+    hipLaunchKernelGGL((k_bicg_xr2<Z>), dim3(kNormBlocks), dim3(kBlock), 0, q, x, r, ph, sh, sv, t, rh, D.scal.p, nd,
+                       D.part.p);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, q, D.part.p, kNormBlocks, 2, D.scal.p + SC_RHO);
+    HIPCHECK(hipGetLastError());
   };
   restart();
   int restarts = 0;
   while (rel > rtol) {
     if (cyc + 2 > max_cycles) return EBMG_ERR_NOCONV;
-    hipLaunchKernelGGL((k_bicg_p2<Z>), dim3(nb), dim3(kBlock), 0, s, p, r, v, D.scal.p, nd, bf, ph);
-    vcyc(ph, p);
-    matvec_dots<Z>(D, ph, v, rh, 1, SC_RV, s);
-    hipLaunchKernelGGL(k_sc_alpha, dim3(1), dim3(1), 0, s, D.scal.p);
-    hipLaunchKernelGGL((k_bicg_s2<Z>), dim3(nb), dim3(kBlock), 0, s, sv, r, v, D.scal.p, nd, bf, sh);
-    vcyc(sh, sv);
-    matvec_dots<Z>(D, sh, t, sv, 2, SC_TS, s);
-    hipLaunchKernelGGL(k_sc_omega, dim3(1), dim3(1), 0, s, D.scal.p);
-    hipLaunchKernelGGL((k_bicg_xr2<Z>), dim3(kNormBlocks), dim3(kBlock), 0, s, x, r, ph, sh, sv, t, rh, D.scal.p, nd,
-                       D.part.p);
-    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, s, D.part.p, kNormBlocks, 2, D.scal.p + SC_RHO);
-    HIPCHECK(hipGetLastError());
+    if (o.graphs == 0)
+      graph_run(D.g_krylov, s, iteration);
+    else
+      iteration(s);
     fetch_scalars(D, s);
     cyc += 2;
     ++info.outer_iters;
@@ -1183,23 +1235,32 @@ static ebmg_status solve(ebmg_problem_s* P, const double* rho, const double* sig
     if (D.krylov) {
       st = bicgstab(D, H.opt, bn, rtol, max_cycles, rel, cyc, loc, s);
     } else {
+      // one refinement cycle and its residual norm
+      auto cycle = [&](hipStream_t q) {
+        if (mixed) {
+          hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(nd)), dim3(kBlock), 0, q, L.r64.p, L.b32.p, nd);
+          fill<float>(L.x32.p, nd, 0.0f, q);
+          vcycle<float>(D, H.opt, 0, q, L.x32.p, L.b32.p);
+          hipLaunchKernelGGL(k_add_f32, dim3(nblk(nd)), dim3(kBlock), 0, q, L.x64.p, L.x32.p, nd);
+        } else {
+          vcycle<double>(D, H.opt, 0, q, L.x64.p, L.b64.p);
+        }
+        residual<double, 0>(L, L.x64.p, L.b64.p, L.r64.p, q);
+        dot_dev<double>(D, L.r64.p, L.r64.p, nd, SC_RR, q);
+      };
       while (rel > rtol) {
         if (cyc >= max_cycles) {
           st = EBMG_ERR_NOCONV;
           break;
         }
-        if (mixed) {
-          hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(nd)), dim3(kBlock), 0, s, L.r64.p, L.b32.p, nd);
-          fill<float>(L.x32.p, nd, 0.0f, s);
-          vcycle<float>(D, H.opt, 0, s, L.x32.p, L.b32.p);
-          hipLaunchKernelGGL(k_add_f32, dim3(nblk(nd)), dim3(kBlock), 0, s, L.x64.p, L.x32.p, nd);
-          ++loc.outer_iters;
-        } else {
-          vcycle<double>(D, H.opt, 0, s, L.x64.p, L.b64.p);
-        }
+        if (H.opt.graphs == 0)
+          graph_run(D.g_plain, s, cycle);
+        else
+          cycle(s);
+        if (mixed) ++loc.outer_iters;
         ++cyc;
-        residual<double, 0>(L, L.x64.p, L.b64.p, L.r64.p, s);
-        double nrel = norm2<double>(D, L.r64.p, nd, s) / bn;
+        fetch_scalars(D, s);
+        double nrel = std::sqrt(D.host_scal[SC_RR]) / bn;
         if (loc.n_hist < 64) loc.hist[loc.n_hist++] = nrel;
         if (!std::isfinite(nrel) || nrel > 1e6) {
           rel = nrel;
@@ -1326,6 +1387,8 @@ static int first_tail_level(ebmg_problem_s* P, int cells) {
 // Work tables of the grid-wide levels for a coarse-part threshold.
 template <typename T>
 static void build_wide_tables(ebmg_batch_s* Bt, int cells, hipStream_t s) {
+  if (Bt->g_iter) (void)hipGraphExecDestroy(Bt->g_iter);   // its tables are about to go
+  Bt->g_iter = nullptr;
   const int nbox = (int)Bt->boxes.size();
   std::vector<int32_t> lt(nbox);
   int lw = 0;
@@ -1579,7 +1642,17 @@ static void wide_solve(ebmg_batch_s* Bt, const std::vector<WIO>& io, double rtol
     HIPCHECK(hipStreamSynchronize(s));
     if (*Bt->host_count == 0) break;
     if (it >= limit) throw DeviceError("batched solve did not stop");
-    wide_iteration<T, DIM>(Bt, rtol, max_cycles, s);
+    if (Bt->graphs) {
+      if (Bt->g_iter && (Bt->g_rtol != rtol || Bt->g_max_cycles != max_cycles)) {
+        (void)hipGraphExecDestroy(Bt->g_iter);
+        Bt->g_iter = nullptr;
+      }
+      Bt->g_rtol = rtol;
+      Bt->g_max_cycles = max_cycles;
+      graph_run(Bt->g_iter, s, [&](hipStream_t q) { wide_iteration<T, DIM>(Bt, rtol, max_cycles, q); });
+    } else {
+      wide_iteration<T, DIM>(Bt, rtol, max_cycles, s);
+    }
     HIPCHECK(hipGetLastError());
   }
   wide_vec<T, WV_OUT>(Bt, WF_ACTIVE, s);
@@ -1653,6 +1726,8 @@ static void setup_wide(ebmg_batch_s* Bt, hipStream_t s) {
 }
 
 static void release_wide(ebmg_batch_s* Bt) {
+  if (Bt->g_iter) (void)hipGraphExecDestroy(Bt->g_iter);
+  Bt->g_iter = nullptr;
   for (auto& w : Bt->wide)
     for (auto* t : {&w.rb, &w.jac[0], &w.jac[1], &w.scat[0], &w.scat[1], &w.cell, &w.res, &w.pro}) t->d.release();
   Bt->wide.clear();
@@ -1828,10 +1903,11 @@ static ebmg_status parse_options(const ebmg_options* opt, int nobj, ebmg::Option
   if (o.precision != EBMG_FP64 && o.precision != EBMG_MIXED) return EBMG_ERR_ARG;
   if (!(o.beta != 0.0) || !std::isfinite(o.beta)) return EBMG_ERR_ARG;
   if (o.krylov < 0 || o.krylov > 2 || o.smoother < 0 || o.smoother > 4 || o.tail < 0 || o.tail > 2 ||
-      o.batch < 0 || o.batch > 2)
+      o.batch < 0 || o.batch > 2 || o.graphs < 0 || o.graphs > 1)
     return EBMG_ERR_ARG;
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < 3; ++k)
     if (o.reserved[k] != 0) return EBMG_ERR_ARG;
+  out.graphs = o.graphs;
   out.tail = o.tail;
   out.batch = o.batch == 1 ? 1 : 2;
   out.krylov = o.krylov == 0 ? (nobj > 0 ? 2 : 1) : o.krylov;
@@ -2233,7 +2309,10 @@ ebmg_status ebmg_setup_batch(ebmg_ctx ctx, int32_t nbox, const ebmg_box* boxes, 
         throw ArgError("bad options for a batch box");
       if (prec < 0) prec = P->host->opt.precision;
       if (P->host->opt.precision != prec) throw ArgError("all boxes of a batch must use one precision");
-      if (i == 0) Bt->mode = P->host->opt.batch;
+      if (i == 0) {
+        Bt->mode = P->host->opt.batch;
+        Bt->graphs = P->host->opt.graphs == 0;
+      }
       if (P->host->opt.batch != Bt->mode) throw ArgError("all boxes of a batch must use one batch mode");
       Bt->boxes[i] = std::move(P);
     }
@@ -2476,7 +2555,7 @@ ebmg_status ebmg_set_coefficients(ebmg_problem pb, const ebmg_options* opt, cons
     if (o2.precision != o.precision || o2.nu1 != o.nu1 || o2.nu2 != o.nu2 || o2.bottom_max != o.bottom_max ||
         o2.krylov != o.krylov || o2.smoother != o.smoother || o2.tail != o.tail ||
         o2.dirichlet_closure != o.dirichlet_closure || o2.robin_closure != o.robin_closure ||
-        o2.eb_order != o.eb_order)
+        o2.eb_order != o.eb_order || o2.graphs != o.graphs)
       throw ArgError("only alpha, beta, a and b may change");
     const int nf = 2 * H.geo.g.dim;
     for (int f = 0; f < nf; ++f) {
@@ -2502,6 +2581,9 @@ ebmg_status ebmg_set_coefficients(ebmg_problem pb, const ebmg_options* opt, cons
     hipStream_t s = pb->ctx->stream;
     DevProblem& D = pb->dev;
     HIPCHECK(hipStreamSynchronize(s));
+    // the template constants are kernel arguments, so replay graphs hold the
+    // old ones: drop them (the next solve captures again)
+    D.drop_graphs();
     for (size_t l = 0; l < H.levels.size(); ++l) {
       D.lv[l].t64 = make_tmpl<double>(H.levels[l]);
       D.lv[l].t32 = make_tmpl<float>(H.levels[l]);

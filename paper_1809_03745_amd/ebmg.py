@@ -62,7 +62,7 @@ class Options(C.Structure):
                 ("b_gas", C.c_double), ("dirichlet_closure", C.c_int32), ("robin_closure", C.c_int32),
                 ("eb_order", C.c_int32), ("precision", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("bottom_max_dof", C.c_int32), ("krylov", C.c_int32), ("smoother", C.c_int32),
-                ("tail", C.c_int32), ("batch", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("tail", C.c_int32), ("batch", C.c_int32), ("graphs", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class SolveInfo(C.Structure):
@@ -176,7 +176,7 @@ KRYLOV_AUTO, KRYLOV_NONE, KRYLOV_BICGSTAB = 0, 1, 2
 
 
 def make_options(prob, precision=FP64, dirichlet_closure=0, robin_closure=0, eb_order=2, nu1=2, nu2=2,
-                 bottom_max_dof=0, krylov=KRYLOV_AUTO, smoother=0, tail=0, batch=0):
+                 bottom_max_dof=0, krylov=KRYLOV_AUTO, smoother=0, tail=0, batch=0, graphs=0):
     o = Options()
     _lib.ebmg_default_options(C.byref(o))
     o.alpha = prob.alpha
@@ -195,6 +195,7 @@ def make_options(prob, precision=FP64, dirichlet_closure=0, robin_closure=0, eb_
     o.smoother = smoother
     o.tail = tail
     o.batch = batch
+    o.graphs = graphs
     return o
 
 

@@ -258,7 +258,10 @@ class Server:
         ctx = ebmg.Context(self.device, stream=stream.cuda_stream)
         prob = req.make_problem()
         t0 = time.perf_counter()
-        P = ebmg.Problem(ctx, prob, precision=self.precision, smoother=4, tail=1)
+        # fixed kernel choices (no timing: a result is the same alone and in
+        # any mix) and direct launches (a Helmholtz request re-coefficients
+        # the hierarchy, which would drop a captured graph every time)
+        P = ebmg.Problem(ctx, prob, precision=self.precision, smoother=4, tail=1, graphs=1)
         req.setup_s = time.perf_counter() - t0
         entry.handle = {"problem": P, "ctx": ctx, "stream": stream}
         entry.coeff_sig = req.coeff_sig

@@ -343,6 +343,7 @@ def trace_summary(trace_csv, marker, out_md, title, command):
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     idx = [i for i, r in enumerate(rows) if marker in r["Kernel_Name"].split("(")[0]]
     seg = rows[idx[-2]:idx[-1]] if len(idx) >= 2 else rows[idx[-1]:]
+    seg = [r for r in seg if "ebmg::" in r["Kernel_Name"]]     # the library's kernels only
     t0, t1 = int(seg[0]["Start_Timestamp"]), int(seg[-1]["End_Timestamp"])
     agg = collections.defaultdict(lambda: [0, 0])
     for r in seg:
@@ -353,8 +354,9 @@ def trace_summary(trace_csv, marker, out_md, title, command):
     busy = sum(v[1] for v in agg.values())
     lines = [f"# {title}\n", "Command (from the repository root on the GPU host; R = repository root):\n",
              f"```\n{command}\n```\n",
-             f"One solve (from the first `{marker}` dispatch of the last solve): {len(seg)} kernels, "
-             f"{(t1 - t0) / 1e6:.2f} ms wall, {busy / 1e6:.2f} ms kernel time.\n",
+             f"One solve (the library's kernels from a `{marker}` dispatch to the next one; the caller's own "
+             f"kernels in between are left out): {len(seg)} kernels, {(t1 - t0) / 1e6:.2f} ms wall, "
+             f"{busy / 1e6:.2f} ms kernel time (profiler overhead included).\n",
              "| kernel | grid (threads) | launches | total ms | mean us | share |", "|---|---|---|---|---|---|"]
     for k, v in sorted(agg.items(), key=lambda kv: -kv[1][1])[:24]:
         lines.append(f"| `{k[0]}` | {k[1]} | {v[0]} | {v[1] / 1e6:.3f} | {v[1] / v[0] / 1e3:.1f} | "

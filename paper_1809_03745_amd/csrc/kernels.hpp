@@ -369,10 +369,14 @@ __global__ void __launch_bounds__(kTileThreads) k_rb_tile2(const uint8_t* __rest
 // into per-thread reciprocal diagonals once, and only planes at the z faces
 // take the general path. (Written without lambdas so that every per-thread
 // table stays in registers.)
+// The update of one template cell from its six neighbour values. Inner form
+// (cell not on a z face): the neighbours summed in the order x-, x+, y-, y+,
+// z-, z+ (out-of-box neighbours hold 0) and scaled by the reciprocal in-plane
+// diagonal rdg; general form: boundary faces skipped in the sum and folded
+// into the diagonal.
 template <typename T>
-__device__ __forceinline__ T zm_update_general(const T* vm, const T* vc, const T* vp, int oq, int OX, int gx,
-                                               int gy, int z, int nx, int ny, int nz, const T* tc, T bc) {
-  const T w = vc[oq - 1], e = vc[oq + 1], so = vc[oq - OX], no = vc[oq + OX], dn = vm[oq], up = vp[oq];
+__device__ __forceinline__ T zv_general(T w, T e, T so, T no, T dn, T up, int gx, int gy, int z, int nx, int ny,
+                                        int nz, const T* tc, T bc) {
   T s = 0, dg = tc[1];
   s += gx > 0 ? w : T(0);
   dg += gx > 0 ? T(0) : tc[2];
@@ -390,15 +394,27 @@ __device__ __forceinline__ T zm_update_general(const T* vm, const T* vc, const T
 }
 
 template <typename T>
+__device__ __forceinline__ T zv_inner(T w, T e, T so, T no, T dn, T up, T co, T bc, T rdg) {
+  T s = w;
+  s += e;
+  s += so;
+  s += no;
+  s += dn;
+  s += up;
+  return (bc - co * s) * rdg;
+}
+
+template <typename T>
+__device__ __forceinline__ T zm_update_general(const T* vm, const T* vc, const T* vp, int oq, int OX, int gx,
+                                               int gy, int z, int nx, int ny, int nz, const T* tc, T bc) {
+  return zv_general<T>(vc[oq - 1], vc[oq + 1], vc[oq - OX], vc[oq + OX], vm[oq], vp[oq], gx, gy, z, nx, ny, nz, tc,
+                       bc);
+}
+
+template <typename T>
 __device__ __forceinline__ T zm_update_inner(const T* vm, const T* vc, const T* vp, int oq, int OX, T co, T bc,
                                              T rdg) {
-  T s = vc[oq - 1];
-  s += vc[oq + 1];
-  s += vc[oq - OX];
-  s += vc[oq + OX];
-  s += vm[oq];
-  s += vp[oq];
-  return (bc - co * s) * rdg;
+  return zv_inner<T>(vc[oq - 1], vc[oq + 1], vc[oq - OX], vc[oq + OX], vm[oq], vp[oq], co, bc, rdg);
 }
 
 template <typename T>

@@ -150,6 +150,27 @@ def test_error_codes(host_ctx):
     assert e.value.status == ebmg.ERR_ARG
 
 
+@pytest.mark.parametrize("field,value", [("smoother", 5), ("tail", 3), ("batch", 3), ("batch", -1), ("graphs", 2),
+                                         ("krylov", 3)])
+def test_option_values_checked(host_ctx, field, value):
+    """Out-of-range option values are rejected at setup (ERR_ARG)."""
+    pr = W.manufactured_sine(8)
+    with pytest.raises(ebmg.EbmgError) as e:
+        ebmg.Problem(host_ctx, pr, **{field: value})
+    assert e.value.status == ebmg.ERR_ARG
+
+
+def test_reserved_options_must_be_zero(host_ctx):
+    pr = W.manufactured_sine(8)
+    box, objs, bc, _ = ebmg._c_problem(pr)
+    o = ebmg.make_options(pr)
+    o.reserved[2] = 1
+    h = ebmg.C.c_void_p()
+    st = ebmg._lib.ebmg_setup(host_ctx.h, ebmg.C.byref(box), 0, objs, ebmg.C.byref(bc), ebmg.C.byref(o),
+                              ebmg.C.byref(h))
+    assert st == ebmg.ERR_ARG and not h.value
+
+
 def test_setup_handles_every_batched_box_class(host_ctx):
     """Boxes of the batched workload (planes meeting Dirichlet walls at
     arbitrary angles) all set up; checked on a seeded sample."""

@@ -1007,31 +1007,35 @@ __global__ void __launch_bounds__(kBlock) k_restrict_all(const uint8_t* __restri
   if (q < ncd) xc[q] = T(0);
 }
 
-// Prolongation in one launch: blocks [0, nbf) take fine cells of simple
-// parents, the rest the fine unknowns of non-simple parents (disjoint sets).
+// Prolongation in one launch. Blocks are (bx, by) threads: blocks x < nrb
+// take by fine rows (j, k) each and bx cells of a row per block y, the fine
+// cells of simple parents; blocks x >= nrb (y = 0) the fine unknowns of
+// non-simple parents (disjoint sets). A cell's four loads (its tag and x, the
+// parent's tag and correction) are issued before its test; no divisions of
+// 64-bit indices.
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kBlock) k_prolong_all(const uint8_t* __restrict__ ftag,
                                                         const uint8_t* __restrict__ ctag, const T* __restrict__ ec,
-                                                        T* __restrict__ xf, int fnx, int fny, int fnz, unsigned nbf,
+                                                        T* __restrict__ xf, int fnx, int fny, int fnz, unsigned nrb,
                                                         int nnp, const int64_t* __restrict__ fdof,
                                                         const int64_t* __restrict__ cdof) {
   const unsigned bid = blockIdx.x;
-  if (bid < nbf) {
-    const int64_t c = (int64_t)bid * kBlock + threadIdx.x;
-    const int64_t fN = (int64_t)fnx * fny * (DIM == 3 ? fnz : 1);
-    if (c >= fN) return;
-    if (tclass(ftag[c]) == 3) return;
-    const int i = (int)(c % fnx);
-    const int64_t jk = c / fnx;
-    const int j = (int)(jk % fny);
-    const int k = DIM == 3 ? (int)(jk / fny) : 0;
+  if (bid < nrb) {
+    const int row = (int)(bid * blockDim.y + threadIdx.y);        // j + fny * k
+    const int i = (int)(blockIdx.y * blockDim.x + threadIdx.x);
+    if (row >= fny * (DIM == 3 ? fnz : 1) || i >= fnx) return;
+    const int j = row % fny, k = DIM == 3 ? row / fny : 0;
     const int cnx = fnx >> 1, cny = fny >> 1;
+    const int64_t c = i + (int64_t)fnx * row;
     const int64_t P = (i >> 1) + (int64_t)cnx * ((j >> 1) + (int64_t)cny * (k >> 1));
-    if (ctag[P] & 4) return;
-    xf[c] += ec[P];
+    const uint8_t ft = ftag[c], ct = ctag[P];
+    const T e = ec[P], xv = xf[c];
+    if (tclass(ft) == 3 || (ct & 4)) return;
+    xf[c] = xv + e;
     return;
   }
-  const int t = (int)((bid - nbf) * kBlock + threadIdx.x);
+  if (blockIdx.y != 0) return;
+  const int t = (int)((bid - nrb) * kBlock + threadIdx.y * blockDim.x + threadIdx.x);
   if (t >= nnp) return;
   xf[fdof[t]] += ec[cdof[t]];
 }

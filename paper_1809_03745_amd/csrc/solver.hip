@@ -889,14 +889,19 @@ static void restrict_to(DevLevel& f, DevLevel& c, const T* rf, T* bc, T* xc, hip
 
 template <typename T>
 static void prolong_from(DevLevel& f, DevLevel& c, const T* ec, T* xf, hipStream_t s) {
-  const unsigned nbf = nblk(f.N);
-  const dim3 g(nbf + nblk(f.n_np));
+  // (bx, by) blocks: bx cells along x (a power of two up to kBlock), by rows
+  int bx = kBlock;
+  while (bx > 16 && bx / 2 >= f.n[0]) bx /= 2;
+  const int by = kBlock / bx;
+  const int64_t rows = (int64_t)f.n[1] * (f.dim == 3 ? f.n[2] : 1);
+  const unsigned nrb = (unsigned)((rows + by - 1) / by);
+  const dim3 g(nrb + nblk(f.n_np), (unsigned)((f.n[0] + bx - 1) / bx));
   if (f.dim == 3)
-    hipLaunchKernelGGL((k_prolong_all<T, 3>), g, dim3(kBlock), 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1],
-                       f.n[2], nbf, (int)f.n_np, f.np_fdof.p, f.np_cdof.p);
+    hipLaunchKernelGGL((k_prolong_all<T, 3>), g, dim3(bx, by), 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1],
+                       f.n[2], nrb, (int)f.n_np, f.np_fdof.p, f.np_cdof.p);
   else
-    hipLaunchKernelGGL((k_prolong_all<T, 2>), g, dim3(kBlock), 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1], 1,
-                       nbf, (int)f.n_np, f.np_fdof.p, f.np_cdof.p);
+    hipLaunchKernelGGL((k_prolong_all<T, 2>), g, dim3(bx, by), 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1], 1,
+                       nrb, (int)f.n_np, f.np_fdof.p, f.np_cdof.p);
   HIPCHECK(hipGetLastError());
 }
 

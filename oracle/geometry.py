@@ -23,7 +23,9 @@ Readings (the paper defers the formulas to the EBChombo documentation):
     closure: alpha_EB n_EB = sum_d (alpha_{d,lo} - alpha_{d,hi}) e_d;
   * kappa < 1e-12 counts as covered, alpha < 1e-12 as closed;
   * a face with four crossings (saddle), a cell whose crossings form more than
-    one loop, and a cell cut by two different objects are rejected;
+    one loop, and a cell cut by two different objects are rejected; an object
+    cuts a cell unless its level set has one strict sign at every corner (a
+    node exactly on a surface belongs to neither side);
   * phase 0 (gas) is outside every object: s_gas = min_k d_k; phase 1
     (dielectric) is inside the dielectric object and outside electrodes:
     s_diel = min(min_electrodes d_k, -d_diel); a cell cut by the dielectric
@@ -447,12 +449,15 @@ class Geometry:
         dim = self.dim
         shp = self.shape
         for k, o in enumerate(self.prob.objects):
-            pos = o.sdf > 0
-            cs = []
+            # cut unless the level set has one strict sign at every corner
+            # (a corner exactly on the surface belongs to neither side)
+            pos, neg = o.sdf > 0, o.sdf < 0
+            cp, cn = [], []
             for off in np.ndindex(*(2,) * dim):
                 sl = tuple(slice(q, q + m) for q, m in zip(off, shp))
-                cs.append(pos[sl])
-            mixed = np.logical_or.reduce(cs) & ~np.logical_and.reduce(cs)
+                cp.append(pos[sl])
+                cn.append(neg[sl])
+            mixed = ~np.logical_and.reduce(cp) & ~np.logical_and.reduce(cn)
             for idx in zip(*np.nonzero(mixed)):
                 out.setdefault(idx, []).append(k)
         return out

@@ -487,10 +487,15 @@ void build_geometry(Geometry& geo, const ebmg_box& box, int nobj, const ebmg_obj
       int k = (int)(c / ((int64_t)g.n[0] * g.n[1]));
       int found = -1, count = 0;
       for (int o = 0; o < nobj; ++o) {
-        int npos = 0;
-        for (int q = 0; q < ncorner; ++q)
-          npos += objs[o].sdf[g.node(i + (q & 1), j + ((q >> 1) & 1), k + ((q >> 2) & 1))] > 0;
-        if (npos > 0 && npos < ncorner) {
+        // cut unless the level set has one strict sign at every corner (a
+        // node exactly on the surface belongs to neither side)
+        int npos = 0, nneg = 0;
+        for (int q = 0; q < ncorner; ++q) {
+          const double v = objs[o].sdf[g.node(i + (q & 1), j + ((q >> 1) & 1), k + ((q >> 2) & 1))];
+          npos += v > 0;
+          nneg += v < 0;
+        }
+        if (npos < ncorner && nneg < ncorner) {
           found = o;
           ++count;
         }

@@ -48,6 +48,8 @@ CASES = {
     "eddington2d": lambda: W.eddington(2, 32, 7.0),
     "eddington3d": lambda: W.eddington(3, 12, 30.0),
     "box": lambda: W.random_box(np.random.default_rng(11)),
+    # nodes exactly on both circles (h = 1/130): level-set zeros at grid nodes
+    "two-disks-on-node": lambda: W.two_disks(130, seed=1),
 }
 
 

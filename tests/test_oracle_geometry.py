@@ -115,6 +115,28 @@ def test_two_disks_areas_and_partition():
     assert abs(out[1][1]) < abs(out[0][1]) / 3
 
 
+def test_level_set_zero_on_nodes():
+    """h = 1/130 puts grid nodes exactly on both circles of the two-disk
+    workload (level set exactly 0 there). Such nodes belong to neither side;
+    the geometry still partitions every cell (gas + dielectric + electrode
+    volume fractions sum to 1), each cut cell has one cutter, and the phase
+    areas stay within O(h^2) of the exact ones."""
+    pr = W.two_disks(130, seed=1)
+    assert any((o.sdf == 0).any() for o in pr.objects)
+    g = Geometry(pr)
+    from oracle.geometry import PhaseGeom
+    pe = PhaseGeom(g, -pr.objects[0].sdf)
+    tot = g.ph[0].kappa + g.ph[1].kappa + pe.kappa
+    assert np.abs(tot - 1.0).max() < 1e-13
+    h = pr.h
+    # a chord across a cell cuts off ~h^3/(12 R) of a circle of radius R, about
+    # pi h^2 / 6 over its 2 pi R / h cells: bound each circle by h^2
+    assert abs(g.ph[0].kappa.sum() * h * h - (1 - 0.05 * math.pi)) < 2.0 * h * h
+    assert abs(g.ph[1].kappa.sum() * h * h - 0.04 * math.pi) < 1.0 * h * h
+    for pg in g.ph:
+        assert all(cc.cutter in (0, 1) for cc in pg.cut.values())
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_closure_per_cell(dim):
     """alpha_EB n_EB + sum_d (alpha_hi - alpha_lo) e_d = 0 per cut cell, and the

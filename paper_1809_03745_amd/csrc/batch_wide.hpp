@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(kBE) kw_tail(const BBox<T>* __restrict__ boxes
   const int l0 = lt[bi];
   T* x0 = l0 == 0 ? B.zx[which] : B.lv[l0].x;
   const T* b0 = l0 == 0 ? B.zb[which] : B.lv[l0].b;
-  be_vcycle<T, DIM>(B.lv, l0, B.nlev, B.Ainv, B.nbot, nu1, nu2, x0, b0);
+  be_vcycle<T, DIM>(B.lv, l0, B.nlev, B.Ainv, B.nbot, B.bk, nu1, nu2, x0, b0);
 }
 
 // Bottom solves x = Ainv b of boxes whose coarse part is the bottom level
@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(kWB) kw_rhs(const BBox<T>* __restrict__ boxes,
 enum WVecOp { WV_INIT = 0, WV_P, WV_S, WV_XR, WV_RESTART, WV_OUT };
 
 // Vector steps over the finest-level unknowns (N + N2 per box):
-//   INIT    x = guess; partial (b, b)
+//   INIT    x = guess (0 on covered cells); partial (b, b)
 //   P       p = r + beta (p - omega v) (plain refinement: p = r); cycle input
 //           zb[0] = p, cycle output zx[0] = 0
 //   S       s = r - alpha v; zb[1] = s, zx[1] = 0
@@ -284,7 +284,8 @@ __global__ void __launch_bounds__(kWB) kw_vec(const BBox<T>* __restrict__ boxes,
     for (int u = 0; u < 4; ++u) {
       const int i = beg + u * kWB;
       if (i < nd) {
-        x[i] = i < N ? o.phi[i] : (o.phi2 ? o.phi2[i - N] : 0.0);
+        // covered cells (identity rows, b = 0, never updated) start at 0
+        x[i] = i < N ? (tclass(B.f64.tag[i]) == 3 ? 0.0 : o.phi[i]) : (o.phi2 ? o.phi2[i - N] : 0.0);
         a0 += b[i] * b[i];
       }
     }

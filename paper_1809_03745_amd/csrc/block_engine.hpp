@@ -63,6 +63,21 @@ __device__ void be_fill(T* x, int n, T v) {
   __syncthreads();
 }
 
+// deterministic workgroup dot product (fixed-order tree in LDS)
+__device__ inline double be_dot(const double* __restrict__ a, const double* __restrict__ b, int n, double* red) {
+  double s = 0;
+  _Pragma("unroll 4") for (int t = threadIdx.x; t < n; t += blockDim.x) s += a[t] * b[t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double v = red[0];
+  __syncthreads();
+  return v;
+}
+
 // Loops below handle U cells per thread per iteration and issue all their
 // loads before the first use (neighbours at clamped, always valid
 // addresses), so a thread has U dependent load chains in flight instead of
@@ -518,11 +533,78 @@ __device__ void be_bottom(const double* __restrict__ Ainv, int n, const T* __res
   __syncthreads();
 }
 
+// Bottom level without a dense inverse (coarsening stopped on a level too
+// large to invert): BiCGStab in FP64 on it, by the whole workgroup, until
+// ||r|| <= tol ||b|| (or breakdown, or maxit iterations), from x = 0. The
+// operator is the level's FP64 one; the vectors are the eight work arrays.
+struct BBot {
+  BLev<double> L;
+  double* w[8];   // x, b, r, rh, p, v, s, t (N + N2 each)
+  int maxit;
+  double tol;
+};
+
+template <typename T, int DIM>
+__device__ void be_bottom_krylov(const BBot& K, const T* __restrict__ bin, T* __restrict__ xout) {
+  __shared__ double red[kBE];
+  const int n = K.L.N + K.L.N2;
+  double *x = K.w[0], *b = K.w[1], *r = K.w[2], *rh = K.w[3], *p = K.w[4], *v = K.w[5], *s = K.w[6], *t = K.w[7];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double bi = (double)bin[i];
+    b[i] = bi;
+    x[i] = 0.0;
+    r[i] = bi;
+    rh[i] = bi;
+    p[i] = 0.0;
+    v[i] = 0.0;
+  }
+  __syncthreads();
+  const double bb = be_dot(b, b, n, red);
+  if (bb > 0) {
+    const double stop = K.tol * K.tol * bb;
+    double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    for (int it = 0; it < K.maxit; ++it) {
+      const double rho = be_dot(rh, r, n, red);
+      const double beta = (rho / rho_old) * (alpha / omega);
+      for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+      __syncthreads();
+      be_resid<double, DIM, 1>(K.L, p, nullptr, v);
+      alpha = rho / be_dot(rh, v, n, red);
+      for (int i = threadIdx.x; i < n; i += blockDim.x) s[i] = r[i] - alpha * v[i];
+      __syncthreads();
+      be_resid<double, DIM, 1>(K.L, s, nullptr, t);
+      const double tt = be_dot(t, t, n, red);
+      omega = tt > 0 ? be_dot(t, s, n, red) / tt : 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        x[i] += alpha * p[i] + omega * s[i];
+        r[i] = s[i] - omega * t[i];
+      }
+      __syncthreads();
+      rho_old = rho;
+      const double rr = be_dot(r, r, n, red);
+      if (!(rr > stop) || omega == 0.0) break;   // converged, broken down or not finite
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) xout[i] = (T)x[i];
+  __syncthreads();
+}
+
+// Bottom solve: dense inverse where there is one, else the Krylov solve.
+template <typename T, int DIM>
+__device__ void be_bottom_any(const BLev<T>& L, const double* Ainv, int nbot, const BBot* bk, const T* b, T* x) {
+  if (Ainv)
+    be_bottom<T>(Ainv, nbot, b, x);
+  else if (bk)
+    be_bottom_krylov<T, DIM>(*bk, b, x);
+  else
+    be_smooth<T, DIM>(L, x, b, 40);
+}
+
 // V-cycle over levels l0 .. nlev-1; level l0 uses (x0, b0), deeper levels
 // their own vectors.
 template <typename T, int DIM>
-__device__ void be_vcycle(const BLev<T>* lv, int l0, int nlev, const double* Ainv, int nbot, int nu1, int nu2,
-                          T* x0, const T* b0) {
+__device__ void be_vcycle(const BLev<T>* lv, int l0, int nlev, const double* Ainv, int nbot, const BBot* bk,
+                          int nu1, int nu2, T* x0, const T* b0) {
   for (int l = l0; l < nlev - 1; ++l) {
     T* x = l == l0 ? x0 : lv[l].x;
     const T* b = l == l0 ? b0 : lv[l].b;
@@ -535,10 +617,7 @@ __device__ void be_vcycle(const BLev<T>* lv, int l0, int nlev, const double* Ain
     const int l = nlev - 1;
     T* x = l == l0 ? x0 : lv[l].x;
     const T* b = l == l0 ? b0 : lv[l].b;
-    if (Ainv)
-      be_bottom<T>(Ainv, nbot, b, x);
-    else
-      be_smooth<T, DIM>(lv[l], x, b, 40);
+    be_bottom_any<T, DIM>(lv[l], Ainv, nbot, bk, b, x);
   }
   for (int l = nlev - 2; l >= l0; --l) {
     T* x = l == l0 ? x0 : lv[l].x;
@@ -552,8 +631,16 @@ __device__ void be_vcycle(const BLev<T>* lv, int l0, int nlev, const double* Ain
 // level l0 down, on (x0, b0) at level l0 (x0 holds the initial guess).
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kBE) k_tail_vcycle(const BLev<T>* lv, int l0, int nlev, const double* Ainv,
-                                                     int nbot, int nu1, int nu2, T* x0, const T* b0) {
-  be_vcycle<T, DIM>(lv, l0, nlev, Ainv, nbot, nu1, nu2, x0, b0);
+                                                     int nbot, const BBot* bk, int nu1, int nu2, T* x0,
+                                                     const T* b0) {
+  be_vcycle<T, DIM>(lv, l0, nlev, Ainv, nbot, bk, nu1, nu2, x0, b0);
+}
+
+// Krylov bottom solve of a hierarchy without a dense bottom inverse, one
+// workgroup of kBE threads.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBE) k_bottom_krylov(const BBot* bk, const T* b, T* x) {
+  be_bottom_krylov<T, DIM>(*bk, b, x);
 }
 
 }  // namespace ebmg
@@ -572,6 +659,7 @@ struct BBox {
   BLev<double> f64;      // finest level in FP64 (residual, matvec, refinement)
   const double* Ainv;
   int nbot;
+  const BBot* bk;        // Krylov bottom solve when there is no inverse
   // right-hand-side data
   const int64_t* icell;
   const double* isrc;
@@ -606,21 +694,6 @@ struct BRes {
   double r0;
   double rel;
 };
-
-// deterministic workgroup dot product (fixed-order tree in LDS)
-__device__ inline double be_dot(const double* __restrict__ a, const double* __restrict__ b, int n, double* red) {
-  double s = 0;
-  _Pragma("unroll 4") for (int t = threadIdx.x; t < n; t += blockDim.x) s += a[t] * b[t];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double v = red[0];
-  __syncthreads();
-  return v;
-}
 
 template <int DIM>
 __device__ void be_rhs_cells_part(const BLev<double>& F, const Tmpl<double>& dat, const double* rho, double* b,
@@ -682,7 +755,7 @@ __device__ void be_precond(const BBox<T>& B, const BLev<T>* lv, int nu1, int nu2
   if (sizeof(T) == sizeof(double)) {
     _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) z[t] = 0.0;
     __syncthreads();
-    be_vcycle<T, DIM>(lv, 0, B.nlev, B.Ainv, B.nbot, nu1, nu2, (T*)z, (const T*)r);
+    be_vcycle<T, DIM>(lv, 0, B.nlev, B.Ainv, B.nbot, B.bk, nu1, nu2, (T*)z, (const T*)r);
   } else {
     T* x0 = lv[0].x;
     T* b0 = lv[0].b;
@@ -691,7 +764,7 @@ __device__ void be_precond(const BBox<T>& B, const BLev<T>* lv, int nu1, int nu2
       x0[t] = T(0);
     }
     __syncthreads();
-    be_vcycle<T, DIM>(lv, 0, B.nlev, B.Ainv, B.nbot, nu1, nu2, x0, b0);
+    be_vcycle<T, DIM>(lv, 0, B.nlev, B.Ainv, B.nbot, B.bk, nu1, nu2, x0, b0);
     _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) z[t] = (double)x0[t];
     __syncthreads();
   }
@@ -707,7 +780,9 @@ __device__ void be_solve_box(const BBox<T>& B, const BIO& io, BRes& out, double 
   double* b = F.b;
   be_rhs<DIM>(F, B.dat, B.fv, B.icell, B.isrc, B.iface, B.iobj, B.icobj, B.icsig, B.objv, io.rho, io.sigma,
               b);
-  _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) x[t] = t < N ? io.phi[t] : (io.phi2 ? io.phi2[t - N] : 0.0);
+  // the guess; covered cells (identity rows, b = 0, never updated) start at 0
+  _Pragma("unroll 4") for (int t = threadIdx.x; t < nd; t += blockDim.x) x[t] =
+      t < N ? (tclass(F.tag[t]) == 3 ? 0.0 : io.phi[t]) : (io.phi2 ? io.phi2[t - N] : 0.0);
   __syncthreads();
   const double bn = sqrt(be_dot(b, b, nd, red));
   int status = 0, cycles = 0, iters = 0;

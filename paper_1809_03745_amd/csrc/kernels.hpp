@@ -1303,6 +1303,14 @@ __global__ void __launch_bounds__(kBlock) k_convert(const S* __restrict__ s, D* 
   if (t < n) d[t] = (D)s[t];
 }
 
+// Covered cells: identity rows with b = 0, and no sweep, correction or
+// Krylov update touches them, so their entries are set to 0 once, on entry.
+__global__ void __launch_bounds__(kBlock) k_clear_covered(const uint8_t* __restrict__ tag, double* __restrict__ x,
+                                                          int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n && tclass(tag[t]) == 3) x[t] = 0.0;
+}
+
 __global__ void __launch_bounds__(kBlock) k_add_f32(double* __restrict__ x, const float* __restrict__ e, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) x[t] += (double)e[t];

@@ -140,6 +140,9 @@ struct DevProblem {
   std::vector<int> tail_cand;     // candidate first tail levels timed at setup
   std::vector<double> tail_ms;    // V-cycle ms for each candidate
   DevBuf<uint8_t> tail_lv;
+  // Krylov bottom solve (no dense inverse): work vectors and its device view
+  DevBuf<double> bk_vec;
+  DevBuf<uint8_t> bk_dev;
   // replayed iteration graphs (captured at the first solve that needs them)
   hipGraphExec_t g_krylov = nullptr, g_plain = nullptr;
   int64_t bytes = 0;
@@ -159,6 +162,8 @@ struct DevProblem {
     ph32.release();
     sh32.release();
     tail_lv.release();
+    bk_vec.release();
+    bk_dev.release();
     if (host_scal) (void)hipHostFree(host_scal);
     host_scal = nullptr;
   }
@@ -532,6 +537,24 @@ static void tune_smoother(DevLevel& l, bool mixed, int mode, hipStream_t s) {
   }
 }
 
+// Device view of the Krylov bottom solve (hierarchies whose bottom level has
+// no dense inverse); rebuilt when the level's template constants change.
+static void upload_bottom_krylov(DevProblem& D, hipStream_t s) {
+  DevLevel& B = D.lv.back();
+  const int64_t n = B.N + B.N2;
+  if (!D.bk_vec.p) D.bk_vec.alloc(8 * n, D.bytes);
+  BBot k;
+  std::memset(&k, 0, sizeof(k));
+  k.L = make_blev<double>(B);
+  for (int q = 0; q < 8; ++q) k.w[q] = D.bk_vec.p + q * n;
+  k.maxit = (int)std::min<int64_t>(4000, std::max<int64_t>(200, 2 * n));
+  k.tol = 1e-10;
+  D.bytes -= D.bk_dev.n;
+  D.bk_dev.release();
+  D.bk_dev.upload((const uint8_t*)&k, (int64_t)sizeof(BBot), s, D.bytes);
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
 // Device order of a level's explicit rows: by colour group, and within
 // windows of kSortWindow rows of a group by decreasing number of stored
 // entries (host order among equals), so the 64-row slices of the sliced
@@ -678,6 +701,7 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
   }
   D.bottom_n = H.bottom_n;
   D.bottom.upload(H.bottom_inv.data(), (int64_t)H.bottom_inv.size(), s, by);
+  if (D.bottom.n == 0) upload_bottom_krylov(D, s);
   // rhs data
   const FineData& F = H.fine;
   const Level& L0 = H.levels[0];
@@ -913,10 +937,12 @@ static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* 
     const BLev<T>* lv = (const BLev<T>*)D.tail_lv.p;
     if (L.dim == 3)
       hipLaunchKernelGGL((k_tail_vcycle<T, 3>), dim3(1), dim3(kBE), 0, s, lv, (int)l, (int)D.lv.size(),
-                         D.bottom.n > 0 ? D.bottom.p : nullptr, (int)D.bottom_n, o.nu1, o.nu2, x, b);
+                         D.bottom.n > 0 ? D.bottom.p : nullptr, (int)D.bottom_n, (const BBot*)D.bk_dev.p, o.nu1,
+                         o.nu2, x, b);
     else
       hipLaunchKernelGGL((k_tail_vcycle<T, 2>), dim3(1), dim3(kBE), 0, s, lv, (int)l, (int)D.lv.size(),
-                         D.bottom.n > 0 ? D.bottom.p : nullptr, (int)D.bottom_n, o.nu1, o.nu2, x, b);
+                         D.bottom.n > 0 ? D.bottom.p : nullptr, (int)D.bottom_n, (const BBot*)D.bk_dev.p, o.nu1,
+                         o.nu2, x, b);
     HIPCHECK(hipGetLastError());
     return;
   }
@@ -925,8 +951,12 @@ static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* 
       hipLaunchKernelGGL((k_bottom<T>), dim3((unsigned)D.bottom_n), dim3(64), 0, s, D.bottom.p, b, x,
                          (int)D.bottom_n);
       HIPCHECK(hipGetLastError());
+    } else if (L.dim == 3) {
+      hipLaunchKernelGGL((k_bottom_krylov<T, 3>), dim3(1), dim3(kBE), 0, s, (const BBot*)D.bk_dev.p, b, x);
+      HIPCHECK(hipGetLastError());
     } else {
-      smooth<T>(L, x, b, 40, s);
+      hipLaunchKernelGGL((k_bottom_krylov<T, 2>), dim3(1), dim3(kBE), 0, s, (const BBot*)D.bk_dev.p, b, x);
+      HIPCHECK(hipGetLastError());
     }
     return;
   }
@@ -1219,6 +1249,7 @@ static ebmg_status solve(ebmg_problem_s* P, const double* rho, const double* sig
   loc.levels = (int)D.lv.size();
   rhs(P, rho, sigma, bcv, objv);
   HIPCHECK(hipMemcpyAsync(L.x64.p, phi, sizeof(double) * L.N, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_clear_covered, dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, L.x64.p, L.N);
   if (L.N2 > 0) {
     if (phi2)
       HIPCHECK(hipMemcpyAsync(L.x64.p + L.N, phi2, sizeof(double) * L.N2, hipMemcpyDeviceToDevice, s));
@@ -1307,6 +1338,7 @@ static BBox<T> make_bbox(ebmg_problem_s* P, const BLev<T>* lv_dev) {
   B.f64 = make_blev<double>(L0);
   B.Ainv = D.bottom.n > 0 ? D.bottom.p : nullptr;
   B.nbot = (int)D.bottom_n;
+  B.bk = (const BBot*)D.bk_dev.p;
   B.icell = D.icell.p;
   B.isrc = D.isrc.p;
   B.iface = D.iface.p;
@@ -2597,6 +2629,8 @@ ebmg_status ebmg_set_coefficients(ebmg_problem pb, const ebmg_options* opt, cons
       if ((int64_t)H.bottom_inv.size() != D.bottom.n) throw ArgError("bottom size changed");
       HIPCHECK(hipMemcpyAsync(D.bottom.p, H.bottom_inv.data(), sizeof(double) * H.bottom_inv.size(),
                               hipMemcpyHostToDevice, s));
+    } else {
+      upload_bottom_krylov(D, s);   // its view holds the bottom level's template constants
     }
     // the one-workgroup engine keeps copies of the templates in its level views
     const int keep = D.tail_l0;

@@ -200,3 +200,38 @@ def test_batch_levelsync_tuning_and_modes_agree(ctx):
     Bp.release()
     for i in range(len(probs)):
         assert np.linalg.norm(xw[i] - xp[i]) <= 1e-9 * np.linalg.norm(xp[i]), i
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_edge_cases(ctx, mode, prec):
+    """A single-level box (its whole system solved by the bottom inverse), a
+    box whose coarsest level is too large for an inverse (relaxation bottom),
+    an EB box, and a box with a zero right-hand side, all from a nonzero
+    initial guess: each result matches the oracle (the zero box gives exactly
+    zero)."""
+    _say("batch edge cases, precision", prec, "mode", mode)
+    zero = W.manufactured_sine(16)
+    zero.rho = np.zeros_like(zero.rho)
+    probs = [W.manufactured_sine(16), W.manufactured_sine(130), W.two_disks(32, seed=6), zero]
+    B = ebmg.Batch(ctx, probs, precision=prec, batch=mode)
+    rho = [_t(p.rho) for p in probs]
+    sig = [(_t(p.sigma) if p.sigma is not None else None) for p in probs]
+    rng = np.random.default_rng(3)
+    phi = [_t(rng.normal(size=int(np.prod(p.shape)))) for p in probs]
+    phi2 = [torch.zeros(4096, dtype=torch.float64, device=DEV) for _ in probs]
+    # 1e-12: the 130^2 box's FP64 round-off floor is a few 1e-13
+    st, infos = B.solve(rho, phi, sigma=sig, phi2=phi2, rtol=1e-12, max_cycles=600, check=False)
+    assert st == ebmg.OK, infos
+    xs = [x.cpu().numpy() for x in phi]
+    x2s = [x.cpu().numpy() for x in phi2]
+    assert np.all(xs[3] == 0.0) and infos[3]["rel_residual"] == 0.0
+    for i in range(3):
+        S = assemble(probs[i])
+        ref = solve_splu(S.A, S.b)
+        x = _full(xs[i], x2s[i], S.N2)
+        err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+        _say("   ", probs[i].name, "levels", infos[i]["levels"], "cycles", infos[i]["cycles"], "error", err)
+        assert err <= (1e-10 if prec == 0 else 1e-8)
+    assert infos[0]["levels"] == 1
+    B.release()

@@ -287,3 +287,57 @@ def test_apply_parity_marching_residual(ctx, name):
     st, info, xs, _ = _solve(P, pr, 1e-10)
     assert st == ebmg.OK and rel_residual(S.A, S.b, xs) <= 1.01e-10
     P.release()
+
+
+BIG_BOTTOM = {
+    # 130 = 2 x 65: coarsening stops at 65^2 = 4225 unknowns, too many for the
+    # dense bottom inverse, so the bottom level is solved by FP64 BiCGStab
+    "sine130-refinement": lambda: W.manufactured_sine(130),
+    "two-disks130-bicgstab": lambda: W.two_disks(130, seed=1),
+}
+
+
+@pytest.mark.parametrize("tail", [1, 2])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("name", sorted(BIG_BOTTOM))
+def test_krylov_bottom_parity(ctx, name, prec, tail):
+    """Hierarchies whose bottom level has no dense inverse (grid-wide cycle,
+    and the one-workgroup engine for the coarse part): oracle parity."""
+    _say("krylov bottom", name, "precision", prec, "tail", tail)
+    pr = BIG_BOTTOM[name]()
+    S = assemble(pr)
+    xs = solve_splu(S.A, S.b)
+    P = ebmg.Problem(ctx, pr, precision=prec, tail=tail)
+    # 1e-12: at h = 1/130 the FP64 round-off floor of the relative residual
+    # is a few 1e-13 (||A|| ||x|| / ||b|| ~ 1e3 here)
+    st, info, x, _ = _solve(P, pr, 1e-12, max_cycles=200)
+    _say("   levels", P.levels, "cycles", info["cycles"], "rel", info["rel_residual"])
+    assert st == ebmg.OK, info
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    assert err <= (1e-10 if prec == 0 else 1e-8), err
+    P.release()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("name", ["two-disks128", "pin-plane32", "coaxial64-sigma"])
+def test_nonzero_initial_guess(ctx, name, prec):
+    """From a random initial guess the solve reaches the oracle's solution;
+    covered cells (identity rows) come out exactly 0."""
+    _say("random initial guess", name, "precision", prec)
+    pr = SMALL[name]()
+    S = assemble(pr)
+    xs = solve_splu(S.A, S.b)
+    P = ebmg.Problem(ctx, pr, precision=prec)
+    rng = np.random.default_rng(8)
+    phi = _t(rng.normal(size=P.N))
+    phi2 = _t(rng.normal(size=max(P.N2, 1)))
+    sig = _t(pr.sigma) if pr.sigma is not None else None
+    st, info = P.solve(_t(pr.rho), phi, sigma=sig, phi2=phi2 if P.N2 else None, rtol=1e-13, max_cycles=400,
+                       check=False)
+    assert st == ebmg.OK, info
+    x = np.concatenate([phi.cpu().numpy(), phi2.cpu().numpy()[:P.N2]])
+    tag, _, _ = P.level_arrays(0)
+    assert np.all(x[:P.N][(tag & 3) == 3] == 0.0)
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    assert err <= (1e-10 if prec == 0 else 1e-8), err
+    P.release()

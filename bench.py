@@ -171,7 +171,7 @@ def pmc_summary(fetch_csv, write_csv, command):
     from paper_1809_03745_amd import ebmg
     zms = [f"k_rb_zm3<{t},{','.join(str(v) for v in c)}>" for t in ("float", "double") for c in ebmg.ZM_TILES]
     for name in ["k_rb<float,3>", "k_rb<double,3>", "k_rb_tile3<float>", "k_rb_tile3<double>",
-                 "k_resid_reg<double,3,0>", "k_resid_zm3<double,0,double,0>"] + zms:
+                 "k_resid_reg<double,3,0>", "k_resid_zm3<double,0,double,0>", "k_resid_zp3<double,0,double,0>"] + zms:
         keys = [k for k in f if k[0] == name]
         if not keys:
             continue
@@ -432,7 +432,8 @@ def main():
     label, unit_kind = _kernel_label(P, prec)
     achieved = k_bytes / (k_ms * 1e-3) / 1e9
     traffic = _traffic(label.split(" ")[0])
-    r_traffic = _traffic("k_resid_zm3<double,0,double,0>")
+    r_name = "k_resid_zp3" if args.n % 2 == 0 else "k_resid_zm3"
+    r_traffic = _traffic(f"{r_name}<double,0,double,0>")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": label, "kernel_ms": round(k_ms, 5), "alg_bytes_per_launch": int(k_bytes),
@@ -464,7 +465,8 @@ def main():
         "latency_ms": {"p50": _pct(lat, 50), "p99": _pct(lat, 99)},
         "setup_s": t_setup,
         "roofline": roof,
-        "residual_kernel": {"kernel": "k_resid_zm3<double,0> (FP64 residual marching in z, finest level)", "ms": r_ms,
+        "residual_kernel": {"kernel": f"{r_name}<double,0> (FP64 residual marching in z, finest level"
+                                      + (", two cells per lane)" if r_name.endswith("zp3") else ")"), "ms": r_ms,
                             "traffic": r_traffic,
                             "GB/s": r_bytes / (r_ms * 1e-3) / 1e9,
                             "frac": r_bytes / (r_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},

@@ -866,6 +866,114 @@ __global__ void __launch_bounds__(kRZX * kRZY) k_resid_zm3(const uint8_t* __rest
     block_partials<kRZX * kRZY>(d0, d1, NDOT, part, pt, blockIdx.x, tid);
 }
 
+// The same residual / matrix-vector product with two neighbouring cells per
+// lane (x even): x, b, r and the dot vector move as 2-element vectors and the
+// tags as one 16-bit word, so a wavefront issues half the memory instructions
+// at twice the width, and the once-read or once-written 8-byte streams carry
+// non-temporal hints. Tiles of kRPX x kRPY columns over kRPZ planes, one
+// plane requested ahead. Same arithmetic per cell as k_resid_zm3. Needs an
+// even x extent and 2-element-aligned arrays.
+constexpr int kRPX = 128, kRPY = 4, kRPZ = 32;
+
+template <typename T, int MODE, typename TX = T, int NDOT = 0>
+__global__ void __launch_bounds__(64 * kRPY) k_resid_zp3(const uint8_t* __restrict__ tag,
+                                                        const TX* __restrict__ x, const T* __restrict__ b,
+                                                        T* __restrict__ r, Tmpl<T> tp,
+                                                        const T* __restrict__ da = nullptr,
+                                                        double* __restrict__ part = nullptr, int64_t pt = 0) {
+  typedef TX X2 __attribute__((ext_vector_type(2)));
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  constexpr bool H = sizeof(T) == 8;
+  __shared__ T TC[2][8];
+  const int tid = threadIdx.x + 64 * threadIdx.y;
+  if (tid < 16) {
+    const int p = tid >> 3, j = tid & 7;
+    TC[p][j] = j == 0 ? tp.coff[p] : (j == 1 ? tp.d0[p] : tp.cb[j - 2][p]);
+  }
+  __syncthreads();
+  const int nx = tp.n[0], ny = tp.n[1], nz = tp.n[2];
+  const int gbx = (nx + kRPX - 1) / kRPX, gby = (ny + kRPY - 1) / kRPY;
+  const int64_t tt = xcd_block(blockIdx.x, gridDim.x);
+  const int i = (int)(tt % gbx) * kRPX + 2 * (int)threadIdx.x;
+  const int j = (int)((tt / gbx) % gby) * kRPY + threadIdx.y;
+  const int z0 = (int)(tt / ((int64_t)gbx * gby)) * kRPZ, z1 = min(z0 + kRPZ, nz);
+  double d0 = 0, d1 = 0;
+  if (i < nx && j < ny) {
+    const int64_t sxy = (int64_t)nx * ny;
+    const int64_t c0 = i + (int64_t)nx * j;
+    const int64_t ow = i > 0 ? -1 : 0, oe = i + 2 < nx ? 2 : 1;
+    const int64_t os = j > 0 ? -(int64_t)nx : 0, on = j < ny - 1 ? (int64_t)nx : 0;
+    const X2 zx = {TX(0), TX(0)};
+    const V2 zv = {T(0), T(0)};
+    int64_t c = c0 + sxy * z0;
+    X2 xm = z0 > 0 ? *(const X2*)(x + c - sxy) : zx;
+    X2 xc = *(const X2*)(x + c);
+    X2 xp = z0 + 1 < nz ? *(const X2*)(x + c + sxy) : zx;
+    TX w = x[c + ow], e = x[c + oe];
+    X2 so = *(const X2*)(x + c + os), no = *(const X2*)(x + c + on);
+    uint16_t tg = ld_stream<H>((const uint16_t*)(tag + c));
+    V2 bb = MODE == 0 ? ld_stream<H>((const V2*)(b + c)) : zv;
+    V2 dc = NDOT > 0 ? ld_stream<H>((const V2*)(da + c)) : zv;
+    for (int k = z0; k < z1; ++k, c += sxy) {
+      // requests for plane k + 1 (its neighbours, b, tags, dot vector) and x of k + 2
+      const bool more = k + 1 < z1;
+      const int64_t cn = more ? c + sxy : c;
+      const X2 xpp = k + 2 < nz ? *(const X2*)(x + c + 2 * sxy) : zx;
+      const TX wn = x[cn + ow], en = x[cn + oe];
+      const X2 son = *(const X2*)(x + cn + os), non = *(const X2*)(x + cn + on);
+      const uint16_t tgn = more ? ld_stream<H>((const uint16_t*)(tag + cn)) : (uint16_t)0x0202;
+      const V2 bbn = (MODE == 0 && more) ? ld_stream<H>((const V2*)(b + cn)) : zv;
+      const V2 dcn = (NDOT > 0 && more) ? ld_stream<H>((const V2*)(da + cn)) : zv;
+      T out[2];
+      bool wr[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int p = tclass((uint8_t)(tg >> (8 * u)));
+        const T xv = (T)(u ? xc.y : xc.x);
+        wr[u] = p != 2;
+        if (p == 3) {
+          out[u] = MODE == 0 ? T(0) : xv;
+        } else {
+          const T wv = (T)(u ? xc.x : w), ev = (T)(u ? e : xc.y);
+          const T* tc = TC[p & 1];
+          T s = 0, dg = tc[1];
+          if (i + u > 0) s += wv; else dg += tc[2];
+          if (i + u < nx - 1) s += ev; else dg += tc[3];
+          if (j > 0) s += (T)(u ? so.y : so.x); else dg += tc[4];
+          if (j < ny - 1) s += (T)(u ? no.y : no.x); else dg += tc[5];
+          if (k > 0) s += (T)(u ? xm.y : xm.x); else dg += tc[6];
+          if (k < nz - 1) s += (T)(u ? xp.y : xp.x); else dg += tc[7];
+          const T ax = dg * xv + tc[0] * s;
+          out[u] = MODE == 0 ? (u ? bb.y : bb.x) - ax : ax;
+        }
+        if (NDOT > 0 && wr[u]) {
+          d0 += (double)(u ? dc.y : dc.x) * (double)out[u];
+          if (NDOT > 1) d1 += (double)out[u] * (double)out[u];
+        }
+      }
+      if (wr[0] && wr[1]) {
+        const V2 o = {out[0], out[1]};
+        st_stream<H>(o, (V2*)(r + c));
+      } else {
+        if (wr[0]) st_stream<H>(out[0], r + c);
+        if (wr[1]) st_stream<H>(out[1], r + c + 1);
+      }
+      xm = xc;
+      xc = xp;
+      xp = xpp;
+      w = wn;
+      e = en;
+      so = son;
+      no = non;
+      tg = tgn;
+      bb = bbn;
+      dc = dcn;
+    }
+  }
+  if (NDOT > 0)
+    block_partials<64 * kRPY>(d0, d1, NDOT, part, pt, blockIdx.x, tid);
+}
+
 template <typename T, int MODE, typename TX = T, int NDOT = 0>
 __global__ void __launch_bounds__(kBlock) k_resid_irr(int nrows, const int64_t* __restrict__ dof,
                                                       const int64_t* __restrict__ rp, const int32_t* __restrict__ col,

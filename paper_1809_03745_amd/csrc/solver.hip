@@ -288,8 +288,21 @@ static int64_t zm_resid_blocks(const DevLevel& l) {
 }
 
 // blocks of one matrix-vector product on a level (the partials it leaves)
+// FP64 residuals of 3D levels with an even x extent use the paired-cell
+// kernel (2-element accesses need that, and aligned arrays, which device
+// allocations are)
+static bool pair_ok(const DevLevel& l) { return l.dim == 3 && l.N >= kResidZMMin && l.n[0] % 2 == 0; }
+static int64_t zp_resid_blocks(const DevLevel& l) {
+  return (int64_t)((l.n[0] + kRPX - 1) / kRPX) * ((l.n[1] + kRPY - 1) / kRPY) * ((l.n[2] + kRPZ - 1) / kRPZ);
+}
+template <typename A>
+static bool al2(const A* p) {
+  return ((uintptr_t)p % (2 * sizeof(A))) == 0;
+}
+// partials one matrix-vector product on a level may leave (for sizing)
 static int64_t matvec_blocks(const DevLevel& l) {
-  if (l.dim == 3 && l.N >= kResidZMMin) return zm_resid_blocks(l) + (int64_t)nblk(l.R * kSub);
+  if (l.dim == 3 && l.N >= kResidZMMin)
+    return std::max(zm_resid_blocks(l), zp_resid_blocks(l)) + (int64_t)nblk(l.R * kSub);
   return (int64_t)nblk(l.N) + (int64_t)nblk(l.R * kSub);
 }
 
@@ -876,8 +889,12 @@ template <typename T, int MODE>
 static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
   if (l.dim == 3 && l.N >= kResidZMMin) {
-    const dim3 g((unsigned)zm_resid_blocks(l));
-    hipLaunchKernelGGL((k_resid_zm3<T, MODE>), g, dim3(kRZX, kRZY), 0, s, l.tag.p, x, b, r, tp);
+    if (sizeof(T) == 8 && pair_ok(l) && al2(x) && al2(b) && al2(r))
+      hipLaunchKernelGGL((k_resid_zp3<T, MODE>), dim3((unsigned)zp_resid_blocks(l)), dim3(64, kRPY), 0, s, l.tag.p,
+                         x, b, r, tp);
+    else
+      hipLaunchKernelGGL((k_resid_zm3<T, MODE>), dim3((unsigned)zm_resid_blocks(l)), dim3(kRZX, kRZY), 0, s,
+                         l.tag.p, x, b, r, tp);
     if (l.R > 0)
       hipLaunchKernelGGL((k_resid_irr<T, MODE>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R, l.irow_dof.p,
                          l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, r);
@@ -1104,11 +1121,30 @@ template <typename Z>
 static void matvec_dots(DevProblem& D, const Z* x, double* out, const double* da, int ndot, int slot, hipStream_t s) {
   DevLevel& l = D.lv[0];
   const Tmpl<double>& tp = l.t64;
-  const int64_t pt = matvec_blocks(l);
+  int64_t pt = matvec_blocks(l);
   if (l.dim == 3 && l.N >= kResidZMMin) {
-    const dim3 g((unsigned)zm_resid_blocks(l));
+    const bool pair = pair_ok(l) && al2(x) && al2(out) && al2(da);
+    const dim3 g((unsigned)(pair ? zp_resid_blocks(l) : zm_resid_blocks(l)));
     const int64_t G = (int64_t)g.x;
-    if (ndot == 1) {
+    pt = G + (int64_t)nblk(l.R * kSub);
+    if (pair) {
+      if (ndot == 1)
+        hipLaunchKernelGGL((k_resid_zp3<double, 1, Z, 1>), g, dim3(64, kRPY), 0, s, l.tag.p, x, nullptr, out, tp, da,
+                           D.part.p, pt);
+      else
+        hipLaunchKernelGGL((k_resid_zp3<double, 1, Z, 2>), g, dim3(64, kRPY), 0, s, l.tag.p, x, nullptr, out, tp, da,
+                           D.part.p, pt);
+      if (l.R > 0) {
+        if (ndot == 1)
+          hipLaunchKernelGGL((k_resid_irr<double, 1, Z, 1>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R,
+                             l.irow_dof.p, l.rp.p, l.col.p, l.val64.p, l.diag64.p, x, nullptr, out, da, D.part.p, pt,
+                             G);
+        else
+          hipLaunchKernelGGL((k_resid_irr<double, 1, Z, 2>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R,
+                             l.irow_dof.p, l.rp.p, l.col.p, l.val64.p, l.diag64.p, x, nullptr, out, da, D.part.p, pt,
+                             G);
+      }
+    } else if (ndot == 1) {
       hipLaunchKernelGGL((k_resid_zm3<double, 1, Z, 1>), g, dim3(kRZX, kRZY), 0, s, l.tag.p, x, nullptr, out, tp, da,
                          D.part.p, pt);
       if (l.R > 0)
@@ -2268,7 +2304,10 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
             hipLaunchKernelGGL((k_rb<double, 2>), shh.g, shh.b, 0, s, L.tag.p, L.x64.p, L.b64.p, L.t64, colour);
         }
       } else {
-        if (L.dim == 3 && L.N >= kResidZMMin) {
+        if (pair_ok(L)) {
+          hipLaunchKernelGGL((k_resid_zp3<double, 0>), dim3((unsigned)zp_resid_blocks(L)), dim3(64, kRPY), 0, s,
+                             L.tag.p, L.x64.p, L.b64.p, L.r64.p, L.t64);
+        } else if (L.dim == 3 && L.N >= kResidZMMin) {
           const dim3 g((unsigned)zm_resid_blocks(L));
           hipLaunchKernelGGL((k_resid_zm3<double, 0>), g, dim3(kRZX, kRZY), 0, s, L.tag.p, L.x64.p, L.b64.p,
                              L.r64.p, L.t64);

@@ -268,10 +268,23 @@ def _ragged_box():
     return pr
 
 
-@pytest.mark.parametrize("name", ["pin-plane64", "ragged-box"])
+def _odd_box():
+    """A 65 x 64 x 64 Eddington box: odd x extent, so the FP64 residual takes
+    the one-cell-per-lane kernel instead of the paired-cell one."""
+    pr = _ragged_box()
+    n = (65, 64, 64)
+    pr.n = n
+    pr.h = 1.0 / 65
+    pr.rho = np.random.default_rng(9).normal(size=tuple(reversed(n)))
+    return pr
+
+
+@pytest.mark.parametrize("name", ["pin-plane64", "ragged-box", "odd-x-box"])
 def test_apply_parity_marching_residual(ctx, name):
+    """Large 3D levels: paired-cell FP64 residual (even x) and the
+    one-cell-per-lane one (odd x), with partial tiles."""
     _say("apply parity (z-marching residual)", name)
-    pr = W.pin_plane(64, seed=1) if name == "pin-plane64" else _ragged_box()
+    pr = {"pin-plane64": lambda: W.pin_plane(64, seed=1), "ragged-box": _ragged_box, "odd-x-box": _odd_box}[name]()
     P = ebmg.Problem(ctx, pr)
     assert P.N >= 1 << 18
     S = assemble(pr)

@@ -427,7 +427,10 @@ __device__ __forceinline__ T zm_inplane_rdg(int gx, int gy, int nx, int ny, cons
   return T(1) / dg;
 }
 
-template <typename T, int TX, int TY, int KZ>
+// WIDE: the halo and ring regions are fetched as aligned 16-byte chunks of x
+// and b and 4-byte words of tags (the chunk rows extend past the regions to
+// alignment) and scattered into the same LDS layout; needs nx % 4 == 0.
+template <typename T, int TX, int TY, int KZ, bool WIDE = false>
 __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restrict__ tag,
                                                       const T* __restrict__ xin, T* __restrict__ xout,
                                                       const T* __restrict__ b, Tmpl<T> tp, int64_t nsec) {
@@ -436,6 +439,13 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
   constexpr int RX = TX + 2, RY = TY + 2, NR = RX * RY;      // red ring region
   constexpr int NRED = (RX / 2) * RY;                        // red cells of the ring region
   constexpr int UO = (NO + NT - 1) / NT, UR = (NR + NT - 1) / NT;
+  // wide fetch: VW values per x / b chunk, 4 tags per word, chunks per row
+  constexpr int VW = 16 / (int)sizeof(T);
+  constexpr int CPO = TX / VW + 2, CPR = TX / VW + 2, CPT = TX / 4 + 2;
+  constexpr int NOW = CPO * OY, NRW = CPR * RY, NTW = CPT * RY;
+  constexpr int UOW = (NOW + NT - 1) / NT, URW = (NRW + NT - 1) / NT, UTW = (NTW + NT - 1) / NT;
+  typedef T VT __attribute__((ext_vector_type(16 / sizeof(T))));
+  static_assert(TX % 4 == 0, "wide fetch needs a tile width that is a multiple of 4");
   static_assert(TX % 2 == 0, "tile width must be even");
   static_assert(NRED <= 2 * NT, "two red cells per thread at most");
   __shared__ T V[5][NO];
@@ -509,20 +519,59 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
   const T b10 = zm_inplane_rdg<T>(bgxa, bgy, nx, ny, TC[0]);       // parity 1: black at gxa
   const T b11 = zm_inplane_rdg<T>(bgxa, bgy, nx, ny, TC[1]);
 
+  // wide fetch tables: chunk offsets (chunk starts x0 - VW + VW ch, resp.
+  // x0 - 4 + 4 ch for tags) and whether the chunk lies in the box
+  int offow[WIDE ? UOW : 1], offbw[WIDE ? URW : 1], offtw[WIDE ? UTW : 1];
+  uint32_t inow = 0, inbw = 0, intw = 0;
+  if (WIDE) {
+#pragma unroll
+    for (int u = 0; u < UOW; ++u) {
+      const int q = tid + u * NT;
+      const int gx = x0 - VW + VW * (q % CPO), gy = y0 - 2 + q / CPO;
+      const bool ok = q < NOW && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+      offow[u] = ok ? gx + nx * gy : 0;
+      inow |= (uint32_t)ok << u;
+    }
+#pragma unroll
+    for (int u = 0; u < URW; ++u) {
+      const int q = tid + u * NT;
+      const int gx = x0 - VW + VW * (q % CPR), gy = y0 - 1 + q / CPR;
+      const bool ok = q < NRW && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+      offbw[u] = ok ? gx + nx * gy : 0;
+      inbw |= (uint32_t)ok << u;
+    }
+#pragma unroll
+    for (int u = 0; u < UTW; ++u) {
+      const int q = tid + u * NT;
+      const int gx = x0 - 4 + 4 * (q % CPT), gy = y0 - 1 + q / CPT;
+      const bool ok = q < NTW && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+      offtw[u] = ok ? gx + nx * gy : 0;
+      intw |= (uint32_t)ok << u;
+    }
+  }
+
   // planes in flight: raw loaded values (lanes outside the box read a valid
   // address; the value is discarded when stored, so no load is waited for
   // before the step that stores it)
-  T Aov[UO], Abv[UR], Bov[UO], Bbv[UR];
-  uint8_t Atv[UR], Btv[UR];
+  T Aov[WIDE ? 1 : UO], Abv[WIDE ? 1 : UR], Bov[WIDE ? 1 : UO], Bbv[WIDE ? 1 : UR];
+  uint8_t Atv[WIDE ? 1 : UR], Btv[WIDE ? 1 : UR];
+  VT Aow[WIDE ? UOW : 1], Abw[WIDE ? URW : 1], Bow[WIDE ? UOW : 1], Bbw[WIDE ? URW : 1];
+  uint32_t Atw[WIDE ? UTW : 1], Btw[WIDE ? UTW : 1];
 
 #define ZM_LOAD(P, z)                                                        \
   {                                                                          \
     const int zz_ = (z);                                                     \
     const int64_t zoff_ = sxy * (zz_ >= 0 && zz_ < nz ? zz_ : 0);            \
-    _Pragma("unroll") for (int u = 0; u < UO; ++u) P##ov[u] = xin[zoff_ + offo[u]]; \
-    _Pragma("unroll") for (int u = 0; u < UR; ++u) {                         \
-      P##bv[u] = b[zoff_ + offr[u]];                                         \
-      P##tv[u] = tag[zoff_ + offr[u]];                                       \
+    if constexpr (WIDE) {                                                    \
+      _Pragma("unroll") for (int u = 0; u < UOW; ++u) P##ow[u] = *(const VT*)(xin + zoff_ + offow[u]); \
+      _Pragma("unroll") for (int u = 0; u < URW; ++u) P##bw[u] = *(const VT*)(b + zoff_ + offbw[u]); \
+      _Pragma("unroll") for (int u = 0; u < UTW; ++u) P##tw[u] = *(const uint32_t*)(tag + zoff_ + offtw[u]); \
+    } else {                                                                 \
+      _Pragma("unroll") for (int u = 0; u < UO; ++u) P##ov[u] = xin[zoff_ + offo[u]]; \
+      _Pragma("unroll") for (int u = 0; u < UR; ++u) {                       \
+        P##bv[u] = b[zoff_ + offr[u]];                                       \
+        P##tv[u] = tag[zoff_ + offr[u]];                                     \
+      }                                                                      \
     }                                                                        \
   }
 #define ZM_STORE(P, z)                                                       \
@@ -532,16 +581,53 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
     T* v_ = V[(zz_ + 10) % 5];                                               \
     T* bs_ = Bs[(zz_ + 8) & 3];                                              \
     uint8_t* ts_ = Ts[(zz_ + 8) & 3];                                        \
-    _Pragma("unroll") for (int u = 0; u < UO; ++u) {                         \
-      const int q = tid + u * NT;                                            \
-      if (q < NO) v_[q] = (zin_ && ((ino >> u) & 1)) ? P##ov[u] : T(0);      \
-    }                                                                        \
-    _Pragma("unroll") for (int u = 0; u < UR; ++u) {                         \
-      const int q = tid + u * NT;                                            \
-      if (q < NR) {                                                          \
-        const bool ok_ = zin_ && ((inr >> u) & 1);                           \
-        bs_[q] = ok_ ? P##bv[u] : T(0);                                      \
-        ts_[q] = ok_ ? P##tv[u] : (uint8_t)3;                                \
+    if constexpr (WIDE) {                                                    \
+      _Pragma("unroll") for (int u = 0; u < UOW; ++u) {                      \
+        const int q = tid + u * NT;                                          \
+        if (q < NOW) {                                                       \
+          const int row_ = q / CPO, c0_ = VW * (q % CPO) - (VW - 2);         \
+          const bool ok_ = zin_ && ((inow >> u) & 1);                        \
+          _Pragma("unroll") for (int e = 0; e < VW; ++e) {                   \
+            const int col_ = c0_ + e;                                        \
+            if (col_ >= 0 && col_ < OX) v_[col_ + OX * row_] = ok_ ? P##ow[u][e] : T(0); \
+          }                                                                  \
+        }                                                                    \
+      }                                                                      \
+      _Pragma("unroll") for (int u = 0; u < URW; ++u) {                      \
+        const int q = tid + u * NT;                                          \
+        if (q < NRW) {                                                       \
+          const int row_ = q / CPR, c0_ = VW * (q % CPR) - (VW - 1);         \
+          const bool ok_ = zin_ && ((inbw >> u) & 1);                        \
+          _Pragma("unroll") for (int e = 0; e < VW; ++e) {                   \
+            const int col_ = c0_ + e;                                        \
+            if (col_ >= 0 && col_ < RX) bs_[col_ + RX * row_] = ok_ ? P##bw[u][e] : T(0); \
+          }                                                                  \
+        }                                                                    \
+      }                                                                      \
+      _Pragma("unroll") for (int u = 0; u < UTW; ++u) {                      \
+        const int q = tid + u * NT;                                          \
+        if (q < NTW) {                                                       \
+          const int row_ = q / CPT, c0_ = 4 * (q % CPT) - 3;                 \
+          const bool ok_ = zin_ && ((intw >> u) & 1);                        \
+          _Pragma("unroll") for (int e = 0; e < 4; ++e) {                    \
+            const int col_ = c0_ + e;                                        \
+            if (col_ >= 0 && col_ < RX)                                      \
+              ts_[col_ + RX * row_] = ok_ ? (uint8_t)(P##tw[u] >> (8 * e)) : (uint8_t)3; \
+          }                                                                  \
+        }                                                                    \
+      }                                                                      \
+    } else {                                                                 \
+      _Pragma("unroll") for (int u = 0; u < UO; ++u) {                       \
+        const int q = tid + u * NT;                                          \
+        if (q < NO) v_[q] = (zin_ && ((ino >> u) & 1)) ? P##ov[u] : T(0);    \
+      }                                                                      \
+      _Pragma("unroll") for (int u = 0; u < UR; ++u) {                       \
+        const int q = tid + u * NT;                                          \
+        if (q < NR) {                                                        \
+          const bool ok_ = zin_ && ((inr >> u) & 1);                         \
+          bs_[q] = ok_ ? P##bv[u] : T(0);                                    \
+          ts_[q] = ok_ ? P##tv[u] : (uint8_t)3;                              \
+        }                                                                    \
       }                                                                      \
     }                                                                        \
   }

@@ -312,13 +312,15 @@ static bool fused_ok(const DevLevel& l) {
 
 // z-marching sweep configurations (tile width x height x planes per block);
 // the setup autotuner picks one per level
-constexpr int kZMConfigs = 7;
+constexpr int kZMConfigs = 10;   // 7..9: wide-fetch versions of 1, 4, 6 (x extent a multiple of 4)
+static bool zm_cfg_ok(const DevLevel& l, int c) { return c < 7 || l.n[0] % 4 == 0; }
 
-template <typename T, int TX, int TY, int KZ>
+template <typename T, int TX, int TY, int KZ, bool WIDE = false>
 static void launch_zm_cfg(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s) {
+  if (WIDE && l.n[0] % 4 != 0) throw ArgError("the wide-fetch sweep needs an x extent that is a multiple of 4");
   const int64_t nb = (int64_t)((l.n[0] + TX - 1) / TX) * ((l.n[1] + TY - 1) / TY) * ((l.n[2] + KZ - 1) / KZ);
-  hipLaunchKernelGGL((k_rb_zm3<T, TX, TY, KZ>), dim3((unsigned)nb), dim3(TX * TY / 2), 0, s, l.tag.p, xin, xout, b,
-                     tp, l.N2);
+  hipLaunchKernelGGL((k_rb_zm3<T, TX, TY, KZ, WIDE>), dim3((unsigned)nb), dim3(TX * TY / 2), 0, s, l.tag.p, xin,
+                     xout, b, tp, l.N2);
 }
 
 template <typename T>
@@ -330,6 +332,9 @@ static void launch_zm(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl
     case 4: launch_zm_cfg<T, 128, 8, 32>(l, xin, xout, b, tp, s); break;
     case 5: launch_zm_cfg<T, 32, 8, 32>(l, xin, xout, b, tp, s); break;
     case 6: launch_zm_cfg<T, 32, 32, 32>(l, xin, xout, b, tp, s); break;
+    case 7: launch_zm_cfg<T, 64, 16, 32, true>(l, xin, xout, b, tp, s); break;
+    case 8: launch_zm_cfg<T, 128, 8, 32, true>(l, xin, xout, b, tp, s); break;
+    case 9: launch_zm_cfg<T, 32, 32, 32, true>(l, xin, xout, b, tp, s); break;
     default: launch_zm_cfg<T, 64, 8, 32>(l, xin, xout, b, tp, s); break;
   }
 }
@@ -513,7 +518,8 @@ static void tune_level(DevLevel& l, T* x, T* xa, T* b, int mode, hipStream_t s) 
   if (fok) {
     cands.push_back({true, false, 0, 0, 0});
     if (l.dim == 3)
-      for (int c = 0; c < kZMConfigs; ++c) cands.push_back({true, false, 1, c, 0});
+      for (int c = 0; c < kZMConfigs; ++c)
+        if (zm_cfg_ok(l, c)) cands.push_back({true, false, 1, c, 0});
   }
   size_t best = 0;
   double zbest = 1e30;
@@ -2234,6 +2240,8 @@ ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t
     if (variant > 1 && (mixed ? !L.xa32.p : !L.xa64.p)) throw ArgError("this level has no second vector");
     if (variant > 1 && variant < 3 + kZMConfigs && !fused_ok(L)) throw ArgError("this level has no fused sweep");
     if (variant >= 3 && variant < 3 + kZMConfigs && L.dim != 3) throw ArgError("the z-marching sweep is 3D only");
+    if (variant >= 3 && variant < 3 + kZMConfigs && !zm_cfg_ok(L, variant - 3))
+      throw ArgError("the wide-fetch sweep needs an x extent that is a multiple of 4");
     const int64_t nd = L.N + L.N2;
     if (mixed) {
       hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(nd)), dim3(kBlock), 0, s, x, L.x32.p, nd);

@@ -1089,71 +1089,6 @@ __global__ void __launch_bounds__(kBlock) k_resid_irr(int nrows, const int64_t* 
   if (NDOT > 0) block_partials<kBlock>(d0, d1, NDOT, part, pt, boff + blockIdx.x, threadIdx.x);
 }
 
-// Restriction to simple coarse cells: mean of the 2^D children (3D launch
-// grid over coarse cells).
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_restrict(const uint8_t* __restrict__ ctag, const T* __restrict__ rf,
-                                                     T* __restrict__ bc, int cnx, int cny, int cnz) {
-  const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  const int J = blockIdx.y * blockDim.y + threadIdx.y;
-  const int K = DIM == 3 ? (int)blockIdx.z : 0;
-  if (I >= cnx || J >= cny) return;
-  (void)cnz;
-  const int64_t P = I + (int64_t)cnx * (J + (int64_t)cny * K);
-  const uint8_t t = ctag[P];
-  if (tclass(t) == 3) {
-    bc[P] = 0;
-    return;
-  }
-  if (t & 4) return;
-  const int fnx = 2 * cnx;
-  const int64_t fsxy = (int64_t)fnx * 2 * cny;
-  const int64_t c0 = 2 * I + (int64_t)fnx * (2 * J) + (DIM == 3 ? fsxy * (2 * K) : 0);
-  T s = rf[c0] + rf[c0 + 1] + rf[c0 + fnx] + rf[c0 + fnx + 1];
-  if (DIM == 3) s += rf[c0 + fsxy] + rf[c0 + fsxy + 1] + rf[c0 + fsxy + fnx] + rf[c0 + fsxy + fnx + 1];
-  bc[P] = s * (DIM == 3 ? T(0.125) : T(0.25));
-}
-
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_restrict_ns(int n, const int64_t* __restrict__ cdof,
-                                                        const int32_t* __restrict__ ptr,
-                                                        const int64_t* __restrict__ child, const T* __restrict__ rf,
-                                                        T* __restrict__ bc) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  T s = 0;
-  for (int e = ptr[t]; e < ptr[t + 1]; ++e) s += rf[child[e]];
-  bc[cdof[t]] = s * (DIM == 3 ? T(0.125) : T(0.25));
-}
-
-// Prolongation: x_f += e_c[parent] for fine cells of simple parents (3D
-// launch grid over fine cells).
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_prolong(const uint8_t* __restrict__ ftag, const uint8_t* __restrict__ ctag,
-                                                    const T* __restrict__ ec, T* __restrict__ xf, int fnx, int fny,
-                                                    int fnz) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = DIM == 3 ? (int)blockIdx.z : 0;
-  if (i >= fnx || j >= fny) return;
-  (void)fnz;
-  const int64_t c = i + (int64_t)fnx * (j + (int64_t)fny * k);
-  if (tclass(ftag[c]) == 3) return;
-  const int cnx = fnx >> 1, cny = fny >> 1;
-  const int64_t P = (i >> 1) + (int64_t)cnx * ((j >> 1) + (int64_t)cny * (k >> 1));
-  if (ctag[P] & 4) return;
-  xf[c] += ec[P];
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_prolong_ns(int n, const int64_t* __restrict__ fdof,
-                                                       const int64_t* __restrict__ cdof, const T* __restrict__ ec,
-                                                       T* __restrict__ xf) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  xf[fdof[t]] += ec[cdof[t]];
-}
-
 // Restriction in one launch: blocks [0, nbc) take simple coarse cells (mean
 // of the 2^D children; covered coarse cells get 0), blocks [nbc, nbc + nbn)
 // the non-simple coarse unknowns from their child lists, and the rest clear
@@ -1344,36 +1279,6 @@ __global__ void __launch_bounds__(kBlock) k_dot_partial(const T* __restrict__ a,
   }
 }
 
-// two dot products sharing one operand: (a, b) and (a, a)
-__global__ void __launch_bounds__(kBlock) k_dot2_partial(const double* __restrict__ a, const double* __restrict__ b,
-                                                         int64_t n, double* __restrict__ part) {
-  __shared__ double sh[2][kBlock / 64];
-  double s0 = 0, s1 = 0;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-    const double av = a[t];
-    s0 += av * b[t];
-    s1 += av * av;
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    s0 += __shfl_down(s0, off, 64);
-    s1 += __shfl_down(s1, off, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    sh[0][threadIdx.x >> 6] = s0;
-    sh[1][threadIdx.x >> 6] = s1;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t0 = 0, t1 = 0;
-    for (int w = 0; w < kBlock / 64; ++w) {
-      t0 += sh[0][w];
-      t1 += sh[1][w];
-    }
-    part[blockIdx.x] = t0;
-    part[gridDim.x + blockIdx.x] = t1;
-  }
-}
-
 // sums `nvec` consecutive partial arrays of length n into out[0..nvec)
 __global__ void __launch_bounds__(kBlock) k_dot_final(const double* __restrict__ part, int n, int nvec,
                                                       double* __restrict__ out) {
@@ -1408,37 +1313,6 @@ __global__ void k_sc_alpha(double* sc) { sc[SC_ALPHA] = sc[SC_RHO] / sc[SC_RV]; 
 __global__ void k_sc_omega(double* sc) {
   sc[SC_OMEGA] = sc[SC_TT] > 0.0 ? sc[SC_TS] / sc[SC_TT] : 0.0;
   sc[SC_RHO_OLD] = sc[SC_RHO];
-}
-
-// p = r + beta (p - omega v), beta = (rho/rho_old)(alpha/omega)
-__global__ void __launch_bounds__(kBlock) k_bicg_p(double* __restrict__ p, const double* __restrict__ r,
-                                                   const double* __restrict__ v, const double* __restrict__ sc,
-                                                   int64_t n) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const double beta = (sc[SC_RHO] / sc[SC_RHO_OLD]) * (sc[SC_ALPHA] / sc[SC_OMEGA]);
-  p[t] = r[t] + beta * (p[t] - sc[SC_OMEGA] * v[t]);
-}
-
-// s = r - alpha v
-__global__ void __launch_bounds__(kBlock) k_bicg_s(double* __restrict__ s, const double* __restrict__ r,
-                                                   const double* __restrict__ v, const double* __restrict__ sc,
-                                                   int64_t n) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  s[t] = r[t] - sc[SC_ALPHA] * v[t];
-}
-
-// x += alpha ph + omega sh ; r = s - omega t
-__global__ void __launch_bounds__(kBlock) k_bicg_xr(double* __restrict__ x, double* __restrict__ r,
-                                                    const double* __restrict__ ph, const double* __restrict__ sh,
-                                                    const double* __restrict__ s, const double* __restrict__ tv,
-                                                    const double* __restrict__ sc, int64_t n) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const double a = sc[SC_ALPHA], w = sc[SC_OMEGA];
-  x[t] += a * ph[t] + w * sh[t];
-  r[t] = s[t] - w * tv[t];
 }
 
 // Fused BiCGStab vector steps. p = r + beta (p - omega v) (resp. s = r -

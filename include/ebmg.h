@@ -23,10 +23,12 @@
  *  - Pointers documented as DEVICE are on the context's device (e.g. a torch
  *    tensor's data_ptr()); HOST pointers are ordinary CPU memory.
  *  - The caller owns every array it passes; the library keeps no caller
- *    pointer after a call returns. The library owns each problem until
- *    ebmg_release().
+ *    pointer after a call returns, except the DEVICE arrays of a submitted
+ *    solve (ebmg_submit), held until its ticket is collected. The library
+ *    owns each problem until ebmg_release().
  *  - All device work of a context is ordered on the context's stream. A
- *    context is not thread-safe.
+ *    context is not thread-safe: one caller thread per context (the
+ *    context's own worker thread, which runs submitted solves, aside).
  *  - Errors are reported only through ebmg_status; the library never aborts.
  *    On EBMG_ERR_ARG / EBMG_ERR_GEOMETRY outputs are untouched. On
  *    EBMG_ERR_NOCONV phi holds the last iterate and info is filled.
@@ -150,6 +152,9 @@ int ebmg_abi_version(void);
  * library creates at default priority). device < 0 gives a host-only context
  * that can set up and export problems but cannot solve (EBMG_ERR_DEVICE). */
 ebmg_status ebmg_create(int32_t device, void* hip_stream, ebmg_ctx* out);
+/* End the context handle: queued submitted solves run to completion first.
+ * Problems and batches set up on the context stay usable until released;
+ * the context's stream and worker thread go with the last of them. */
 ebmg_status ebmg_destroy(ebmg_ctx ctx);
 /* Message of the last failing call on ctx; with ctx == NULL, of the calling
  * thread's last failing ebmg_create. */
@@ -211,6 +216,36 @@ ebmg_status ebmg_solve(ebmg_problem pb, const double* rho, const double* sigma,
                        const double* bc_values, const double* obj_values, double rtol,
                        int32_t max_cycles, double* phi, double* phi2, double* E,
                        ebmg_solve_info* info);
+
+/* Asynchronous solve for serving: the same solve as ebmg_solve, queued on
+ * the context's worker thread (started by the first submit), which runs the
+ * submitted solves of a context one after another, in submission order, on
+ * the context's stream. Solves on separate contexts (separate streams) run
+ * concurrently on the device. Arguments as for ebmg_solve; bc_values and
+ * obj_values are copied before the call returns, while rho, sigma, phi,
+ * phi2 and E (DEVICE) are used when the solve runs and must stay valid and
+ * unwritten by the caller until the ticket has been collected. *ticket
+ * (HOST) receives a nonzero id, unique within the context. Argument errors
+ * are returned here; errors of the solve itself through poll/wait. Every
+ * other call on the problem (ebmg_solve, ebmg_apply, ebmg_set_coefficients,
+ * ebmg_release, ...) first waits for its submitted solves to finish.
+ * ebmg_destroy runs the queued solves to completion before it returns. */
+ebmg_status ebmg_submit(ebmg_problem pb, const double* rho, const double* sigma,
+                        const double* bc_values, const double* obj_values, double rtol,
+                        int32_t max_cycles, double* phi, double* phi2, double* E,
+                        uint64_t* ticket);
+
+/* Non-blocking check of a submitted solve. *done (HOST) = 0 while it is
+ * queued or running; once it has finished, *done = 1, *result receives the
+ * solve's status (what ebmg_solve would have returned; on failure
+ * ebmg_last_error(ctx) gives its message), info (nullable) its record, and
+ * the ticket is forgotten. Returns EBMG_ERR_ARG for an unknown or already
+ * collected ticket, else EBMG_OK. */
+ebmg_status ebmg_poll(ebmg_ctx ctx, uint64_t ticket, int32_t* done, ebmg_status* result,
+                      ebmg_solve_info* info);
+
+/* As ebmg_poll, blocking until the submitted solve has finished. */
+ebmg_status ebmg_wait(ebmg_ctx ctx, uint64_t ticket, ebmg_status* result, ebmg_solve_info* info);
 
 /* out = A [phi; phi2] (FP64, DEVICE arrays; phi2/out2 nullable when N2 = 0). */
 ebmg_status ebmg_apply(ebmg_problem pb, const double* phi, const double* phi2, double* out,

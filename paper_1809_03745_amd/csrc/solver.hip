@@ -12,6 +12,10 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <unordered_map>
 #include <thread>
 #include <type_traits>
 #include <cmath>
@@ -171,11 +175,43 @@ struct DevProblem {
 
 }  // namespace ebmg
 
+// A queued solve: device pointers as given, boundary values copied at submit.
+struct AsyncJob {
+  uint64_t ticket = 0;
+  ebmg_problem pb = nullptr;
+  const double* rho = nullptr;
+  const double* sigma = nullptr;
+  std::vector<double> bcv, objv;  // empty: the setup values
+  double rtol = 0;
+  int max_cycles = 0;
+  double* phi = nullptr;
+  double* phi2 = nullptr;
+  double* E = nullptr;
+};
+
+struct AsyncResult {
+  bool done = false;
+  ebmg_status status = EBMG_OK;
+  ebmg_solve_info info{};
+  std::string err;
+};
+
 struct ebmg_ctx_s {
   int device = -1;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
+  // submitted solves: one worker thread per context runs them in order
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<AsyncJob> queue;
+  std::unordered_map<uint64_t, AsyncResult> results;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread worker;
+  // the handle plus each live problem and batch: the stream and the worker
+  // outlive ebmg_destroy until the last problem set up on the context is gone
+  std::atomic<int> refs{1};
 };
 
 struct ebmg_problem_s {
@@ -183,6 +219,7 @@ struct ebmg_problem_s {
   std::unique_ptr<ebmg::Problem> host;
   ebmg::DevProblem dev;
   bool on_device = false;
+  int pending = 0;  // submitted solves not yet finished (guarded by ctx->mu)
 };
 
 // Many independent boxes solved by one persistent launch.
@@ -1882,25 +1919,86 @@ static void template_sweeps(DevLevel& l, int variant, int sweeps, T* x, const T*
 using namespace ebmg;
 
 template <typename F>
-static ebmg_status guard(ebmg_ctx ctx, F&& f) {
+static ebmg_status guard_msg(std::string* err, F&& f) {
   try {
     return f();
   } catch (const ArgError& e) {
-    if (ctx) ctx->err = e.what();
+    if (err) *err = e.what();
     return EBMG_ERR_ARG;
   } catch (const GeomError& e) {
-    if (ctx) ctx->err = e.what();
+    if (err) *err = e.what();
     return EBMG_ERR_GEOMETRY;
   } catch (const DeviceError& e) {
-    if (ctx) ctx->err = e.what();
+    if (err) *err = e.what();
     return std::string(e.what()).find("out of memory") != std::string::npos ? EBMG_ERR_OOM : EBMG_ERR_DEVICE;
   } catch (const std::bad_alloc&) {
-    if (ctx) ctx->err = "host allocation failed";
+    if (err) *err = "host allocation failed";
     return EBMG_ERR_OOM;
   } catch (const std::exception& e) {
-    if (ctx) ctx->err = e.what();
+    if (err) *err = e.what();
     return EBMG_ERR_ARG;
   }
+}
+
+template <typename F>
+static ebmg_status guard(ebmg_ctx ctx, F&& f) {
+  return guard_msg(ctx ? &ctx->err : nullptr, std::forward<F>(f));
+}
+
+// Worker of a context: runs submitted solves in submission order on the
+// context's stream, records each outcome under its ticket.
+static void async_worker(ebmg_ctx c) {
+  for (;;) {
+    AsyncJob j;
+    {
+      std::unique_lock<std::mutex> lk(c->mu);
+      c->cv_work.wait(lk, [&] { return c->stop || !c->queue.empty(); });
+      if (c->queue.empty()) return;  // stopping and drained
+      j = std::move(c->queue.front());
+      c->queue.pop_front();
+    }
+    AsyncResult r;
+    r.status = guard_msg(&r.err, [&]() -> ebmg_status {
+      HIPCHECK(hipSetDevice(c->device));
+      return solve(j.pb, j.rho, j.sigma, j.bcv.empty() ? nullptr : j.bcv.data(),
+                   j.objv.empty() ? nullptr : j.objv.data(), j.rtol, j.max_cycles, j.phi, j.phi2, j.E, &r.info);
+    });
+    r.done = true;
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      c->results[j.ticket] = std::move(r);
+      --j.pb->pending;
+    }
+    c->cv_done.notify_all();
+  }
+}
+
+// Block until no submitted solve of P is queued or running.
+static void drain(ebmg_problem_s* P) {
+  ebmg_ctx c = P->ctx;
+  std::unique_lock<std::mutex> lk(c->mu);
+  c->cv_done.wait(lk, [&] { return P->pending == 0; });
+}
+
+static void stop_worker(ebmg_ctx c) {
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->stop = true;
+  }
+  c->cv_work.notify_all();
+  if (c->worker.joinable()) c->worker.join();
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->stop = false;  // a later submit (on a problem that outlived the handle) starts a new worker
+}
+
+static void ctx_unref(ebmg_ctx c) {
+  if (--c->refs > 0) return;
+  stop_worker(c);
+  if (c->own_stream) {
+    (void)hipSetDevice(c->device);
+    (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
 }
 
 extern "C" {
@@ -1954,8 +2052,8 @@ ebmg_status ebmg_create(int32_t device, void* stream, ebmg_ctx* out) {
 
 ebmg_status ebmg_destroy(ebmg_ctx ctx) {
   if (!ctx) return EBMG_ERR_ARG;
-  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
-  delete ctx;
+  stop_worker(ctx);
+  ctx_unref(ctx);
   return EBMG_OK;
 }
 
@@ -2047,6 +2145,7 @@ ebmg_status ebmg_setup(ebmg_ctx ctx, const ebmg_box* box, int32_t nobj, const eb
       P->on_device = true;
     }
     *out = P.release();
+    ++ctx->refs;
     return EBMG_OK;
   });
 }
@@ -2177,15 +2276,91 @@ ebmg_status ebmg_solve(ebmg_problem pb, const double* rho, const double* sigma, 
     return EBMG_ERR_DEVICE;
   }
   return guard(ctx, [&]() -> ebmg_status {
+    drain(pb);
     HIPCHECK(hipSetDevice(ctx->device));
     return solve(pb, rho, sigma, bcv, objv, rtol, max_cycles, phi, phi2, E, info);
   });
+}
+
+ebmg_status ebmg_submit(ebmg_problem pb, const double* rho, const double* sigma, const double* bcv,
+                        const double* objv, double rtol, int32_t max_cycles, double* phi, double* phi2, double* E,
+                        uint64_t* ticket) {
+  if (!pb) return EBMG_ERR_ARG;
+  ebmg_ctx ctx = pb->ctx;
+  if (!rho || !phi || !ticket || !(rtol > 0) || max_cycles < 0) {
+    ctx->err = "invalid argument to ebmg_submit";
+    return EBMG_ERR_ARG;
+  }
+  if (!pb->on_device) {
+    ctx->err = "problem is not on a device (host-only context)";
+    return EBMG_ERR_DEVICE;
+  }
+  return guard(ctx, [&]() -> ebmg_status {
+    AsyncJob j;
+    j.pb = pb;
+    j.rho = rho;
+    j.sigma = sigma;
+    if (bcv) j.bcv.assign(bcv, bcv + 6);
+    const size_t no = pb->host->geo.obj_value.size();
+    if (objv && no) j.objv.assign(objv, objv + no);
+    j.rtol = rtol;
+    j.max_cycles = max_cycles;
+    j.phi = phi;
+    j.phi2 = phi2;
+    j.E = E;
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      if (!ctx->worker.joinable()) ctx->worker = std::thread(async_worker, ctx);
+      j.ticket = ctx->next_ticket++;
+      ctx->results.emplace(j.ticket, AsyncResult{});
+      ++pb->pending;
+      *ticket = j.ticket;
+      ctx->queue.push_back(std::move(j));
+    }
+    ctx->cv_work.notify_one();
+    return EBMG_OK;
+  });
+}
+
+// Shared by poll and wait: hand over a finished ticket's outcome and forget it.
+static ebmg_status take_result(ebmg_ctx ctx, uint64_t ticket, bool block, int32_t* done, ebmg_status* result,
+                               ebmg_solve_info* info) {
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  // looked up again after every wake: a submit in between may rehash the map
+  auto it = ctx->results.find(ticket);
+  if (block)
+    ctx->cv_done.wait(lk, [&] {
+      it = ctx->results.find(ticket);
+      return it == ctx->results.end() || it->second.done;
+    });
+  if (it == ctx->results.end()) {
+    ctx->err = "unknown or already collected ticket " + std::to_string(ticket);
+    return EBMG_ERR_ARG;
+  }
+  if (done) *done = it->second.done ? 1 : 0;
+  if (!it->second.done) return EBMG_OK;
+  *result = it->second.status;
+  if (info) *info = it->second.info;
+  if (it->second.status != EBMG_OK) ctx->err = it->second.err;
+  ctx->results.erase(it);
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_poll(ebmg_ctx ctx, uint64_t ticket, int32_t* done, ebmg_status* result, ebmg_solve_info* info) {
+  if (!ctx || !done || !result) return EBMG_ERR_ARG;
+  return take_result(ctx, ticket, false, done, result, info);
+}
+
+ebmg_status ebmg_wait(ebmg_ctx ctx, uint64_t ticket, ebmg_status* result, ebmg_solve_info* info) {
+  if (!ctx || !result) return EBMG_ERR_ARG;
+  return take_result(ctx, ticket, true, nullptr, result, info);
 }
 
 ebmg_status ebmg_apply(ebmg_problem pb, const double* phi, const double* phi2, double* out, double* out2) {
   if (!pb || !phi || !out) return EBMG_ERR_ARG;
   if (!pb->on_device) return EBMG_ERR_DEVICE;
   return guard(pb->ctx, [&]() -> ebmg_status {
+    drain(pb);
     HIPCHECK(hipSetDevice(pb->ctx->device));
     DevLevel& L = pb->dev.lv[0];
     hipStream_t s = pb->ctx->stream;
@@ -2207,6 +2382,7 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
   if (!pb || !phi || !E) return EBMG_ERR_ARG;
   if (!pb->on_device) return EBMG_ERR_DEVICE;
   return guard(pb->ctx, [&]() -> ebmg_status {
+    drain(pb);
     HIPCHECK(hipSetDevice(pb->ctx->device));
     DevProblem& D = pb->dev;
     DevLevel& L = D.lv[0];
@@ -2233,6 +2409,7 @@ ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t
   if (!pb->on_device) return EBMG_ERR_DEVICE;
   if (level < 0 || level >= (int32_t)pb->dev.lv.size()) return EBMG_ERR_ARG;
   return guard(pb->ctx, [&]() -> ebmg_status {
+    drain(pb);
     HIPCHECK(hipSetDevice(pb->ctx->device));
     DevLevel& L = pb->dev.lv[level];
     hipStream_t s = pb->ctx->stream;
@@ -2263,6 +2440,7 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
   if (!pb->on_device) return EBMG_ERR_DEVICE;
   if (level < 0 || level >= (int32_t)pb->dev.lv.size()) return EBMG_ERR_ARG;
   return guard(pb->ctx, [&]() -> ebmg_status {
+    drain(pb);
     HIPCHECK(hipSetDevice(pb->ctx->device));
     DevProblem& D = pb->dev;
     DevLevel& L = D.lv[level];
@@ -2482,6 +2660,7 @@ ebmg_status ebmg_setup_batch(ebmg_ctx ctx, int32_t nbox, const ebmg_box* boxes, 
       throw;
     }
     *out = Bt.release();
+    ++ctx->refs;
     return EBMG_OK;
   });
 }
@@ -2622,13 +2801,16 @@ ebmg_status ebmg_release_batch(ebmg_batch bt) {
   bt->bio.release();
   bt->bres.release();
   ebmg::release_wide(bt);
+  ebmg_ctx ctx = bt->ctx;
   delete bt;
+  ctx_unref(ctx);
   return EBMG_OK;
 }
 
 ebmg_status ebmg_set_coefficients(ebmg_problem pb, const ebmg_options* opt, const ebmg_domain_bc* bc) {
   if (!pb || !opt || !bc) return EBMG_ERR_ARG;
   return guard(pb->ctx, [&]() -> ebmg_status {
+    drain(pb);
     Problem& H = *pb->host;
     if (!H.geo.obj_value.empty() || H.geo.N2 > 0) throw ArgError("problem has embedded objects");
     for (const Level& L : H.levels)
@@ -2695,12 +2877,15 @@ ebmg_status ebmg_set_coefficients(ebmg_problem pb, const ebmg_options* opt, cons
 
 ebmg_status ebmg_release(ebmg_problem pb) {
   if (!pb) return EBMG_ERR_ARG;
+  drain(pb);
   if (pb->on_device) {
     (void)hipSetDevice(pb->ctx->device);
     (void)hipStreamSynchronize(pb->ctx->stream);
     pb->dev.release();
   }
+  ebmg_ctx ctx = pb->ctx;
   delete pb;
+  ctx_unref(ctx);
   return EBMG_OK;
 }
 

@@ -104,6 +104,10 @@ _sig("ebmg_export_operator", C.c_int, [_vp, C.c_int32, _i64p, _vp, _vp, _vp])
 _sig("ebmg_export_rhs", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_solve", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int32, _vp, _vp, _vp,
                              C.POINTER(SolveInfo)])
+_sig("ebmg_submit", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int32, _vp, _vp, _vp,
+                              C.POINTER(C.c_uint64)])
+_sig("ebmg_poll", C.c_int, [_vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_int), C.POINTER(SolveInfo)])
+_sig("ebmg_wait", C.c_int, [_vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(SolveInfo)])
 _sig("ebmg_apply", C.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_efield", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_time_kernel", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp])
@@ -122,7 +126,7 @@ _sig("ebmg_release_batch", C.c_int, [_vp])
 EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_destroy", "ebmg_last_error",
             "ebmg_setup", "ebmg_query", "ebmg_query_level", "ebmg_export_level", "ebmg_query_tuning",
             "ebmg_export_geometry", "ebmg_export_operator", "ebmg_export_rhs",
-            "ebmg_solve", "ebmg_apply", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
+            "ebmg_solve", "ebmg_submit", "ebmg_poll", "ebmg_wait", "ebmg_apply", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
             "ebmg_setup_batch", "ebmg_query_batch", "ebmg_query_batch_tuning", "ebmg_solve_batch", "ebmg_release_batch",
             "ebmg_set_coefficients", "ebmg_smooth"]
 
@@ -154,6 +158,26 @@ class Context:
             raise EbmgError(st, "ebmg_create failed: " + _lib.ebmg_last_error(None).decode(errors="replace"))
         self.h = h
         self.device = device
+        self._held = {}  # ticket -> device tensors of a submitted solve
+
+    def _collect(self, ticket, st, res, info):
+        self.check(st, "ebmg_poll/ebmg_wait")
+        self._held.pop(ticket, None)
+        return res.value, info.as_dict()
+
+    def poll(self, ticket):
+        """None while the submitted solve ``ticket`` runs, else (status, info)."""
+        done, res, info = C.c_int32(), C.c_int(), SolveInfo()
+        st = _lib.ebmg_poll(self.h, C.c_uint64(ticket), C.byref(done), C.byref(res), C.byref(info))
+        if st == OK and not done.value:
+            return None
+        return self._collect(ticket, st, res, info)
+
+    def wait(self, ticket):
+        """(status, info) of the submitted solve ``ticket``, blocking until it ends."""
+        res, info = C.c_int(), SolveInfo()
+        st = _lib.ebmg_wait(self.h, C.c_uint64(ticket), C.byref(res), C.byref(info))
+        return self._collect(ticket, st, res, info)
 
     def check(self, st, what):
         if st != OK:
@@ -300,6 +324,20 @@ class Problem:
         if check:
             self.ctx.check(st, "ebmg_solve")
         return st, info.as_dict()
+
+    def submit(self, rho, phi, sigma=None, phi2=None, E=None, rtol=1e-10, max_cycles=100, bc_values=None,
+               obj_values=None):
+        """Queue the solve on the context's worker; returns its ticket (collect
+        it with ``ctx.poll`` / ``ctx.wait``). The tensors are kept referenced
+        until then."""
+        bcv = _host_f64(bc_values)
+        ov = _host_f64(obj_values)
+        t = C.c_uint64()
+        self.ctx.check(_lib.ebmg_submit(self.h, _ptr(rho), _ptr(sigma), _ptr(bcv), _ptr(ov), float(rtol),
+                                        int(max_cycles), _ptr(phi), _ptr(phi2), _ptr(E), C.byref(t)),
+                       "ebmg_submit")
+        self.ctx._held[t.value] = (rho, sigma, phi, phi2, E)
+        return t.value
 
     def apply(self, phi, phi2, out, out2):
         self.ctx.check(_lib.ebmg_apply(self.h, _ptr(phi), _ptr(phi2), _ptr(out), _ptr(out2)), "ebmg_apply")

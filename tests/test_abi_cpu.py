@@ -184,6 +184,34 @@ def test_setup_handles_every_batched_box_class(host_ctx):
         P.release()
 
 
+def test_async_calls_on_a_host_context(host_ctx):
+    P = ebmg.Problem(host_ctx, W.manufactured_sine(8))
+    with pytest.raises(ebmg.EbmgError) as e:
+        P.submit(np.zeros(64), np.zeros(64))
+    assert e.value.status == ebmg.ERR_DEVICE
+    assert not host_ctx._held
+    # no ticket was handed out, so any ticket is unknown
+    for t in (0, 1, 2**64 - 1):
+        with pytest.raises(ebmg.EbmgError) as e:
+            host_ctx.poll(t)
+        assert e.value.status == ebmg.ERR_ARG
+        with pytest.raises(ebmg.EbmgError) as e:
+            host_ctx.wait(t)
+        assert e.value.status == ebmg.ERR_ARG
+    P.release()
+
+
+def test_problem_outlives_its_context_handle():
+    c = ebmg.Context(-1)
+    pr = W.manufactured_sine(16)
+    P = ebmg.Problem(c, pr)
+    A1 = P.operator()
+    c.close()
+    A2 = P.operator()
+    assert (A1 != A2).nnz == 0
+    P.release()
+
+
 def test_batch_needs_a_device(host_ctx):
     with pytest.raises(ebmg.EbmgError) as e:
         ebmg.Batch(host_ctx, [W.manufactured_sine(8), W.manufactured_sine(16)])

@@ -382,6 +382,26 @@ __device__ void be_resid(const BLev<T>& L, const T* __restrict__ x, const T* __r
   __syncthreads();
 }
 
+// Grid-wide forms of the explicit-row phases over the sliced copy, for one
+// level passed by value: kBlock rows (kBlock / kSlice slices) per block.
+// Jacobi values of group grp into L.w, as be_irr_jac_part.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_irr_jac_sl(BLev<T> L, int grp, const T* __restrict__ x,
+                                                       const T* __restrict__ b) {
+  be_irr_jac_part<T>(L, grp, x, b, (int)blockIdx.x * kBlock, kBlock);
+}
+
+// r = b - A x (MODE 0) or A x (MODE 1) on the explicit rows: blocks [0, nb0)
+// take group 0, the rest group 1.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_resid_irr_sl(BLev<T> L, int nb0, const T* __restrict__ x,
+                                                         const T* __restrict__ b, T* __restrict__ r) {
+  double a0 = 0, a1 = 0;
+  const int g = (int)blockIdx.x < nb0 ? 0 : 1;
+  const int blk = g == 0 ? (int)blockIdx.x : (int)blockIdx.x - nb0;
+  be_resid_rows_part<T, T, MODE, 0>(L, g, x, b, r, blk * kBlock, kBlock, nullptr, a0, a1);
+}
+
 // Restriction of rf into the coarse b over coarse cells [beg, beg + cnt);
 // xc (may be null) is cleared over the same cells.
 template <typename T, int DIM>

@@ -1169,6 +1169,55 @@ __global__ void __launch_bounds__(kBlock) k_prolong_all(const uint8_t* __restric
   xf[fdof[t]] += ec[cdof[t]];
 }
 
+// The same prolongation with four consecutive fine cells of a row per lane
+// (x a multiple of 4, x-arrays 4-element aligned): the fine x and tags move
+// as one 4-element vector and one 32-bit word, the two parents' values and
+// tags as a 2-element vector and a 16-bit word. A fine cell is written only
+// where the cell part updates it (the list part owns the others).
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_prolong_q(const uint8_t* __restrict__ ftag,
+                                                      const uint8_t* __restrict__ ctag, const T* __restrict__ ec,
+                                                      T* __restrict__ xf, int fnx, int fny, int fnz, unsigned nrb,
+                                                      int nnp, const int64_t* __restrict__ fdof,
+                                                      const int64_t* __restrict__ cdof) {
+  typedef T V4 __attribute__((ext_vector_type(4)));
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  const unsigned bid = blockIdx.x;
+  if (bid < nrb) {
+    const int row = (int)(bid * blockDim.y + threadIdx.y);        // j + fny * k
+    const int i = 4 * (int)(blockIdx.y * blockDim.x + threadIdx.x);
+    if (row >= fny * (DIM == 3 ? fnz : 1) || i >= fnx) return;
+    const int j = row % fny, k = DIM == 3 ? row / fny : 0;
+    const int cnx = fnx >> 1, cny = fny >> 1;
+    const int64_t c = i + (int64_t)fnx * row;
+    const int64_t P = (i >> 1) + (int64_t)cnx * ((j >> 1) + (int64_t)cny * (k >> 1));
+    const uint32_t ft = *(const uint32_t*)(ftag + c);
+    const uint16_t ct = *(const uint16_t*)(ctag + P);
+    const V2 e = *(const V2*)(ec + P);
+    V4 xv = *(const V4*)(xf + c);
+    bool up[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) up[u] = !(tclass((uint8_t)(ft >> (8 * u))) == 3 || ((ct >> (8 * (u >> 1))) & 4));
+    xv.x = up[0] ? xv.x + e.x : xv.x;
+    xv.y = up[1] ? xv.y + e.x : xv.y;
+    xv.z = up[2] ? xv.z + e.y : xv.z;
+    xv.w = up[3] ? xv.w + e.y : xv.w;
+    if (up[0] && up[1] && up[2] && up[3]) {
+      *(V4*)(xf + c) = xv;
+    } else {
+      if (up[0]) xf[c] = xv.x;
+      if (up[1]) xf[c + 1] = xv.y;
+      if (up[2]) xf[c + 2] = xv.z;
+      if (up[3]) xf[c + 3] = xv.w;
+    }
+    return;
+  }
+  if (blockIdx.y != 0) return;
+  const int t = (int)((bid - nrb) * kBlock + threadIdx.y * blockDim.x + threadIdx.x);
+  if (t >= nnp) return;
+  xf[fdof[t]] += ec[cdof[t]];
+}
+
 // Residual of a small level in one launch: blocks [0, nbc) take the template
 // and covered cells (MODE as in k_resid_reg), the rest the explicit rows with
 // kSub lanes each (as k_resid_irr); TX and NDOT as in k_resid_zm3, with one

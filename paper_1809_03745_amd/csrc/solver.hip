@@ -879,8 +879,12 @@ static void irr_group(DevLevel& l, int grp, T* x, const T* b, hipStream_t s) {
   if (nr <= 0) return;
   const int32_t* rows = l.cls_rows.p + l.cls_ptr[grp];
   T* tmp = Vec<T>::tmp(l);
-  hipLaunchKernelGGL((k_irr_jacobi<T>), dim3(nblk_sub(nr)), dim3(kBlock), 0, s, rows, nr, l.irow_dof.p, l.rp.p,
-                     l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, tmp);
+  if (l.sl_ptr.p && Vec<T>::sval(l))
+    hipLaunchKernelGGL((k_irr_jac_sl<T>), dim3((unsigned)((nr + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       make_blev<T>(l), grp, x, b);
+  else
+    hipLaunchKernelGGL((k_irr_jacobi<T>), dim3(nblk_sub(nr)), dim3(kBlock), 0, s, rows, nr, l.irow_dof.p, l.rp.p,
+                       l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, tmp);
   hipLaunchKernelGGL((k_irr_scatter<T>), dim3(nblk(nr)), dim3(kBlock), 0, s, rows, nr, l.irow_dof.p, tmp, x);
 }
 
@@ -938,9 +942,16 @@ static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
     else
       hipLaunchKernelGGL((k_resid_zm3<T, MODE>), dim3((unsigned)zm_resid_blocks(l)), dim3(kRZX, kRZY), 0, s,
                          l.tag.p, x, b, r, tp);
-    if (l.R > 0)
+    if (l.R > 0 && l.sl_ptr.p && Vec<T>::sval(l)) {
+      const BLev<T> L = make_blev<T>(l);
+      const int nb0 = (L.grp_ptr[1] - L.grp_ptr[0] + kBlock - 1) / kBlock;
+      const int nb1 = (L.grp_ptr[2] - L.grp_ptr[1] + kBlock - 1) / kBlock;
+      hipLaunchKernelGGL((k_resid_irr_sl<T, MODE>), dim3((unsigned)(nb0 + nb1)), dim3(kBlock), 0, s, L, nb0, x, b,
+                         r);
+    } else if (l.R > 0) {
       hipLaunchKernelGGL((k_resid_irr<T, MODE>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R, l.irow_dof.p,
                          l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, r);
+    }
   } else {
     // small levels: template cells and explicit rows in one launch
     const unsigned nbc = nblk(l.N);
@@ -973,11 +984,29 @@ static void restrict_to(DevLevel& f, DevLevel& c, const T* rf, T* bc, T* xc, hip
 
 template <typename T>
 static void prolong_from(DevLevel& f, DevLevel& c, const T* ec, T* xf, hipStream_t s) {
+  const int64_t rows = (int64_t)f.n[1] * (f.dim == 3 ? f.n[2] : 1);
+  if (f.n[0] % 4 == 0 && (uintptr_t)xf % (4 * sizeof(T)) == 0 && al2(ec) && (uintptr_t)f.tag.p % 4 == 0 &&
+      (uintptr_t)c.tag.p % 2 == 0) {
+    // four fine cells per lane: (bx, by) blocks, bx lanes along x, by rows
+    const int q = f.n[0] / 4;
+    int bx = 64;
+    while (bx > 16 && bx / 2 >= q) bx /= 2;
+    const int by = kBlock / bx;
+    const unsigned nrb = (unsigned)((rows + by - 1) / by);
+    const dim3 g(nrb + nblk(f.n_np), (unsigned)((q + bx - 1) / bx));
+    if (f.dim == 3)
+      hipLaunchKernelGGL((k_prolong_q<T, 3>), g, dim3(bx, by), 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1],
+                         f.n[2], nrb, (int)f.n_np, f.np_fdof.p, f.np_cdof.p);
+    else
+      hipLaunchKernelGGL((k_prolong_q<T, 2>), g, dim3(bx, by), 0, s, f.tag.p, c.tag.p, ec, xf, f.n[0], f.n[1], 1,
+                         nrb, (int)f.n_np, f.np_fdof.p, f.np_cdof.p);
+    HIPCHECK(hipGetLastError());
+    return;
+  }
   // (bx, by) blocks: bx cells along x (a power of two up to kBlock), by rows
   int bx = kBlock;
   while (bx > 16 && bx / 2 >= f.n[0]) bx /= 2;
   const int by = kBlock / bx;
-  const int64_t rows = (int64_t)f.n[1] * (f.dim == 3 ? f.n[2] : 1);
   const unsigned nrb = (unsigned)((rows + by - 1) / by);
   const dim3 g(nrb + nblk(f.n_np), (unsigned)((f.n[0] + bx - 1) / bx));
   if (f.dim == 3)

@@ -358,9 +358,13 @@ __global__ void __launch_bounds__(kTileThreads) k_rb_tile2(const uint8_t* __rest
 // (old black values only), then the black update to the tile of plane k-1
 // (red-updated values only) and writes plane k-1: exactly a red half-sweep
 // followed by a black half-sweep, with the same arithmetic as the split
-// kernels. While the black update runs, plane k+2 goes from registers to LDS
-// and plane k+4 is requested from memory, so each load has two steps to
-// arrive; two barriers per step. Ring cells and the two extra planes at each
+// kernels. Each step first moves plane k+2 from registers to LDS (into the
+// ring slots of planes k-3 and k-2, which no phase of step k reads) and
+// requests plane k+4 from memory, so each load has two steps to arrive; two
+// barriers per step. The staging runs every step (the last requests repeat
+// the final plane) so that the compiler's wait counts stay exact across
+// the loop, and staging slots go to lanes in reverse order, so the partial
+// last slot falls on the waves without a second red cell. Ring cells and the two extra planes at each
 // end of the z range are recomputed by the neighbouring blocks from the same
 // old values, so blocks never exchange data. Threads take cells of one colour
 // at a time (no idle lanes): each of the TX*TY/2 threads owns one black tile
@@ -462,6 +466,7 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
   const int z0 = (int)(t / ((int64_t)bx * by)) * KZ;
   const int z1 = min(z0 + KZ, nz);
   const int tid = threadIdx.x;
+  const int stid = NT - 1 - tid;   // staging lane (reversed)
   const int64_t sxy = (int64_t)nx * ny;
   if (tid < 16) {
     const int p = tid >> 3, j = tid & 7;
@@ -475,7 +480,7 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
   uint32_t ino = 0, inr = 0;
 #pragma unroll
   for (int u = 0; u < UO; ++u) {
-    const int q = tid + u * NT;
+    const int q = stid + u * NT;
     const int gx = x0 - 2 + q % OX, gy = y0 - 2 + q / OX;
     const bool ok = q < NO && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
     offo[u] = ok ? gx + nx * gy : 0;
@@ -483,7 +488,7 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
   }
 #pragma unroll
   for (int u = 0; u < UR; ++u) {
-    const int q = tid + u * NT;
+    const int q = stid + u * NT;
     const int gx = x0 - 1 + q % RX, gy = y0 - 1 + q / RX;
     const bool ok = q < NR && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
     offr[u] = ok ? gx + nx * gy : 0;
@@ -618,11 +623,11 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
       }                                                                      \
     } else {                                                                 \
       _Pragma("unroll") for (int u = 0; u < UO; ++u) {                       \
-        const int q = tid + u * NT;                                          \
+        const int q = stid + u * NT;                                         \
         if (q < NO) v_[q] = (zin_ && ((ino >> u) & 1)) ? P##ov[u] : T(0);    \
       }                                                                      \
       _Pragma("unroll") for (int u = 0; u < UR; ++u) {                       \
-        const int q = tid + u * NT;                                          \
+        const int q = stid + u * NT;                                         \
         if (q < NR) {                                                        \
           const bool ok_ = zin_ && ((inr >> u) & 1);                         \
           bs_[q] = ok_ ? P##bv[u] : T(0);                                    \
@@ -634,6 +639,8 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
 #define ZM_STEP(P, kk)                                                       \
   {                                                                          \
     const int k = (kk);                                                      \
+    ZM_STORE(P, k + 2);                                                      \
+    ZM_LOAD(P, min(k + 4, z1 + 1));                                          \
     if (k >= 0 && k < nz) { /* red update of plane k over the ring region */ \
       const bool zint = k > 0 && k < nz - 1;                                 \
       const T* vm = V[(k + 9) % 5];                                          \
@@ -686,8 +693,6 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
         if (bgxa + 1 < nx) out[bgxa + 1] = par ? vr : vb;                    \
       }                                                                      \
     }                                                                        \
-    if (k + 2 <= z1 + 1) ZM_STORE(P, k + 2);                                 \
-    if (k + 4 <= z1 + 1) ZM_LOAD(P, k + 4);                                  \
     __syncthreads();                                                         \
   }
 
@@ -700,9 +705,11 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
   ZM_LOAD(A, z0 + 1);   // planes z0+1, z0+3, ... travel in A; z0+2, z0+4, ... in B
   ZM_LOAD(B, z0 + 2);
   __syncthreads();
+  // an odd step count ends with one extra step whose black plane lies
+  // outside [z0, z1): it only stages and recomputes LDS values
   for (int k2 = z0 - 1; k2 <= z1; k2 += 2) {
     ZM_STEP(A, k2);
-    if (k2 + 1 <= z1) ZM_STEP(B, k2 + 1);
+    ZM_STEP(B, k2 + 1);
   }
 #undef ZM_STEP
 #undef ZM_STORE

@@ -286,6 +286,22 @@ ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t
 ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int32_t reps, double* avg_ms,
                              double* alg_bytes);
 
+/* Measurement hook, in-solve form: enable = 1 starts timing, inside later
+ * ebmg_solve calls on pb, the launches of level `level`'s smoothing-sweep
+ * kernel (which = 0: the fused sweep, or each colour phase / half-sweep where
+ * the level uses those) or of its FP64 residual kernel (which = 1: the
+ * template-cell kernel of every FP64 r = b - A x on that level: the solve's
+ * residual checks, and the V-cycle residuals of FP64 problems), with a HIP
+ * event pair on the
+ * context stream around every launch; while any timing is on, those solves
+ * launch their kernels directly instead of replaying graphs (the same
+ * kernels in the same order). enable = 0 stops it and reports the number of
+ * launches timed, their mean duration (ms) and the algorithmic bytes of one
+ * launch (as ebmg_time_kernel counts them). Outputs are HOST pointers and may
+ * be NULL. ERR_ARG if enable = 0 finds no such timing running on that level. */
+ebmg_status ebmg_kernel_timing(ebmg_problem pb, int32_t which, int32_t level, int32_t enable,
+                               int64_t* launches, double* mean_ms, double* alg_bytes);
+
 /* Replace the coefficients of a problem without embedded objects and without
  * explicit rows on any level (e.g. the Eddington Helmholtz problem of the
  * radiative-transfer section, kappa phi - div((1/3kappa) grad phi) = S, for a

@@ -82,6 +82,36 @@ struct DevBuf {
   }
 };
 
+// HIP event pairs around one level's sweep-kernel launches during solves
+// (measurement hook): recorded on the solve stream, read after the solve's
+// final synchronisation.
+struct KTiming {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;   // events recorded since the last harvest (pairs)
+  int64_t n = 0;     // launches timed
+  double ms = 0;     // their total duration
+  void record(hipStream_t s) {
+    if (used == ev.size()) {
+      hipEvent_t e = nullptr;
+      HIPCHECK(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+    HIPCHECK(hipEventRecord(ev[used++], s));
+  }
+  void harvest() {
+    for (size_t i = 0; i + 1 < used; i += 2) {
+      float t = 0;
+      HIPCHECK(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+      ms += t;
+      ++n;
+    }
+    used = 0;
+  }
+  ~KTiming() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
 struct DevLevel {
   int dim = 2;
   int n[3] = {1, 1, 1};
@@ -103,6 +133,8 @@ struct DevLevel {
   bool oop = false;                // non-fused: one-launch colour phases (else split in place)
   int fvar = 0;                    // fused variant: 0 3D/2D tile, 1 z-marching (3D)
   int zmcfg = 0;                   // z-marching tile configuration
+  KTiming* kt = nullptr;           // sweep launches timed during solves (or none)
+  KTiming* ktr = nullptr;          // FP64 residual launches timed during solves (or none)
   double tune_split_ms = 0, tune_fused_ms = 0, tune_zm_ms = 0, tune_oop_ms = 0;
   Tmpl<double> t64;
   Tmpl<float> t32;
@@ -149,6 +181,11 @@ struct DevProblem {
   DevBuf<uint8_t> bk_dev;
   // replayed iteration graphs (captured at the first solve that needs them)
   hipGraphExec_t g_krylov = nullptr, g_plain = nullptr;
+  // measurement hook: sweep launches of one level timed during solves, which
+  // then launch their kernels directly instead of replaying graphs
+  std::unique_ptr<KTiming> kt[2];   // [0] sweeps, [1] FP64 residuals
+  int kt_level[2] = {-1, -1};
+  bool timing() const { return kt[0] || kt[1]; }
   int64_t bytes = 0;
   void drop_graphs() {
     if (g_krylov) (void)hipGraphExecDestroy(g_krylov);
@@ -157,6 +194,8 @@ struct DevProblem {
   }
   void release() {
     drop_graphs();
+    kt[0].reset();
+    kt[1].reset();
     for (auto& l : lv) l.release();
     lv.clear();
     bottom.release(); icell.release(); isrc.release(); iface.release(); icobj.release(); icsig.release();
@@ -897,7 +936,9 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
     T* cur = x;
     T* alt = Vec<T>::xa(l);
     for (int it = 0; it < sweeps; ++it) {
+      if (l.kt) l.kt->record(s);
       launch_fused<T>(l, cur, alt, b, tp, s);
+      if (l.kt) l.kt->record(s);
       std::swap(cur, alt);
       irr_group<T>(l, 0, cur, b, s);
       irr_group<T>(l, 1, cur, b, s);
@@ -913,7 +954,9 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
     T* alt = Vec<T>::xa(l);
     for (int it = 0; it < sweeps; ++it)
       for (int colour = 0; colour < 2; ++colour) {
+        if (l.kt) l.kt->record(s);
         launch_oop<T>(l, colour, true, cur, alt, b, s);
+        if (l.kt) l.kt->record(s);
         std::swap(cur, alt);
       }
     HIPCHECK(hipGetLastError());
@@ -922,10 +965,12 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
   const Shape sh = shape3((l.n[0] + 1) / 2, l.n[1], l.dim == 3 ? l.n[2] : 1);
   for (int it = 0; it < sweeps; ++it) {
     for (int colour = 0; colour < 2; ++colour) {
+      if (l.kt) l.kt->record(s);
       if (l.dim == 3)
         hipLaunchKernelGGL((k_rb<T, 3>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
       else
         hipLaunchKernelGGL((k_rb<T, 2>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
+      if (l.kt) l.kt->record(s);
       irr_group<T>(l, colour, x, b, s);
     }
   }
@@ -936,12 +981,15 @@ template <typename T, int MODE>
 static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
   if (l.dim == 3 && l.N >= kResidZMMin) {
+    KTiming* kr = (sizeof(T) == 8 && MODE == 0) ? l.ktr : nullptr;
+    if (kr) kr->record(s);
     if (sizeof(T) == 8 && pair_ok(l) && al2(x) && al2(b) && al2(r))
       hipLaunchKernelGGL((k_resid_zp3<T, MODE>), dim3((unsigned)zp_resid_blocks(l)), dim3(64, kRPY), 0, s, l.tag.p,
                          x, b, r, tp);
     else
       hipLaunchKernelGGL((k_resid_zm3<T, MODE>), dim3((unsigned)zm_resid_blocks(l)), dim3(kRZX, kRZY), 0, s,
                          l.tag.p, x, b, r, tp);
+    if (kr) kr->record(s);
     if (l.R > 0 && l.sl_ptr.p && Vec<T>::sval(l)) {
       const BLev<T> L = make_blev<T>(l);
       const int nb0 = (L.grp_ptr[1] - L.grp_ptr[0] + kBlock - 1) / kBlock;
@@ -1299,7 +1347,7 @@ static ebmg_status bicgstab_t(DevProblem& D, const Options& o, double bn, double
   int restarts = 0;
   while (rel > rtol) {
     if (cyc + 2 > max_cycles) return EBMG_ERR_NOCONV;
-    if (o.graphs == 0)
+    if (o.graphs == 0 && !D.timing())
       graph_run(D.g_krylov, s, iteration);
     else
       iteration(s);
@@ -1397,7 +1445,7 @@ static ebmg_status solve(ebmg_problem_s* P, const double* rho, const double* sig
           st = EBMG_ERR_NOCONV;
           break;
         }
-        if (H.opt.graphs == 0)
+        if (H.opt.graphs == 0 && !D.timing())
           graph_run(D.g_plain, s, cycle);
         else
           cycle(s);
@@ -1422,6 +1470,8 @@ static ebmg_status solve(ebmg_problem_s* P, const double* rho, const double* sig
     HIPCHECK(hipMemcpyAsync(phi2, L.x64.p + L.N, sizeof(double) * L.N2, hipMemcpyDeviceToDevice, s));
   if (E) efield(P, L.x64.p, sigma, bcv, E);
   HIPCHECK(hipStreamSynchronize(s));
+  for (auto& k : D.kt)
+    if (k) k->harvest();
   loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = loc;
   return st;
@@ -2571,6 +2621,39 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
   });
 }
 
+ebmg_status ebmg_kernel_timing(ebmg_problem pb, int32_t which, int32_t level, int32_t enable, int64_t* launches,
+                               double* mean_ms, double* alg_bytes) {
+  if (!pb || (enable != 0 && enable != 1) || (which != 0 && which != 1)) return EBMG_ERR_ARG;
+  if (!pb->on_device) return EBMG_ERR_DEVICE;
+  if (level < 0 || level >= (int32_t)pb->dev.lv.size()) return EBMG_ERR_ARG;
+  return guard(pb->ctx, [&]() -> ebmg_status {
+    drain(pb);
+    DevProblem& D = pb->dev;
+    DevLevel& L = D.lv[level];
+    std::unique_ptr<KTiming>& K = D.kt[which];
+    auto slot = [&](DevLevel& l) -> KTiming*& { return which == 0 ? l.kt : l.ktr; };
+    if (enable) {
+      if (K && D.kt_level[which] >= 0) slot(D.lv[D.kt_level[which]]) = nullptr;
+      K.reset(new KTiming());
+      D.kt_level[which] = level;
+      slot(L) = K.get();
+      return EBMG_OK;
+    }
+    if (!K || D.kt_level[which] != level) throw ArgError("kernel timing is not enabled on this level");
+    HIPCHECK(hipSetDevice(pb->ctx->device));
+    HIPCHECK(hipStreamSynchronize(pb->ctx->stream));
+    K->harvest();
+    const int es = which == 1 ? 8 : (pb->host->opt.precision == EBMG_MIXED ? 4 : 8);
+    const double cells = (which == 1 || L.fused) ? (double)L.N : (double)((L.N + 1) / 2);
+    if (launches) *launches = K->n;
+    if (mean_ms) *mean_ms = K->n > 0 ? K->ms / (double)K->n : 0.0;
+    if (alg_bytes) *alg_bytes = cells * (3.0 * es + 1.0);
+    slot(L) = nullptr;
+    K.reset();
+    D.kt_level[which] = -1;
+    return EBMG_OK;
+  });
+}
 
 ebmg_status ebmg_setup_batch(ebmg_ctx ctx, int32_t nbox, const ebmg_box* boxes, const int32_t* nobj,
                              const ebmg_object* const* objs, const ebmg_domain_bc* bcs, const ebmg_options* opts,

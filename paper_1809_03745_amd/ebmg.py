@@ -112,6 +112,7 @@ _sig("ebmg_apply", C.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_efield", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_time_kernel", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp])
 _sig("ebmg_smooth", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _vp, _vp])
+_sig("ebmg_kernel_timing", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _i64p, _dp, _dp])
 _sig("ebmg_release", C.c_int, [_vp])
 _sig("ebmg_set_coefficients", C.c_int, [_vp, C.POINTER(Options), C.POINTER(DomainBC)])
 _sig("ebmg_setup_batch", C.c_int, [_vp, C.c_int32, C.POINTER(Box), C.POINTER(C.c_int32), C.POINTER(_vp),
@@ -128,7 +129,7 @@ EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_des
             "ebmg_export_geometry", "ebmg_export_operator", "ebmg_export_rhs",
             "ebmg_solve", "ebmg_submit", "ebmg_poll", "ebmg_wait", "ebmg_apply", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
             "ebmg_setup_batch", "ebmg_query_batch", "ebmg_query_batch_tuning", "ebmg_solve_batch", "ebmg_release_batch",
-            "ebmg_set_coefficients", "ebmg_smooth"]
+            "ebmg_set_coefficients", "ebmg_smooth", "ebmg_kernel_timing"]
 
 
 def abi_version():
@@ -367,6 +368,15 @@ class Problem:
         self.ctx.check(_lib.ebmg_time_kernel(self.h, which, level, reps, C.byref(ms), C.byref(by)),
                        "ebmg_time_kernel")
         return ms.value, by.value
+
+    def kernel_timing(self, which, level, enable):
+        """Start (enable=True) or stop in-solve event timing of the level's
+        sweep launches (which=0) or FP64 residual launches (which=1);
+        stopping returns (launches, mean ms, algorithmic bytes per launch)."""
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        self.ctx.check(_lib.ebmg_kernel_timing(self.h, int(which), int(level), 1 if enable else 0, C.byref(n),
+                                               C.byref(ms), C.byref(by)), "ebmg_kernel_timing")
+        return n.value, ms.value, by.value
 
     def set_coefficients(self, prob):
         """Take the coefficients and boundary data of ``prob`` (same grid, no

@@ -115,3 +115,28 @@ def test_batched_graph_replays_equal_direct_launches(ctx):
         assert ce == cg
         for a, b in zip(xe, xg):
             assert np.array_equal(a, b), k
+
+
+def test_in_solve_kernel_timing_runs_the_same_kernels(ctx):
+    pr = W.pin_plane(64, seed=3)
+    P = ebmg.Problem(ctx, pr, precision=ebmg.MIXED, **PIN)
+    ref, info = _solve(P, pr)
+    P.kernel_timing(0, 0, True)
+    P.kernel_timing(1, 0, True)
+    x, info2 = _solve(P, pr)
+    n, ms, by = P.kernel_timing(0, 0, False)
+    nr, msr, byr = P.kernel_timing(1, 0, False)
+    _say("sweeps timed", n, "mean ms", ms, "residuals timed", nr, "mean ms", msr)
+    # direct launches with events between them: the same kernels, the same bits
+    assert info2["cycles"] == info["cycles"]
+    assert np.array_equal(x, ref)
+    # one fused sweep launch per smoothing sweep on the finest level
+    assert n == info["cycles"] * 4
+    assert ms > 0 and by == P.N * 13
+    assert nr >= 1 and msr > 0 and byr == P.N * 25
+    with pytest.raises(ebmg.EbmgError):
+        P.kernel_timing(0, 0, False)
+    # graphs again after the timing
+    x3, _ = _solve(P, pr)
+    assert np.array_equal(x3, ref)
+    P.release()

@@ -392,14 +392,19 @@ __global__ void __launch_bounds__(kBlock) k_irr_jac_sl(BLev<T> L, int grp, const
 }
 
 // r = b - A x (MODE 0) or A x (MODE 1) on the explicit rows: blocks [0, nb0)
-// take group 0, the rest group 1.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kBlock) k_resid_irr_sl(BLev<T> L, int nb0, const T* __restrict__ x,
-                                                         const T* __restrict__ b, T* __restrict__ r) {
+// take group 0, the rest group 1. x may be narrower than T; NDOT as in
+// be_resid_rows_part, with one partial per block at part[d * pt + boff + block].
+template <typename T, int MODE, typename TX = T, int NDOT = 0>
+__global__ void __launch_bounds__(kBlock) k_resid_irr_sl(BLev<T> L, int nb0, const TX* __restrict__ x,
+                                                         const T* __restrict__ b, T* __restrict__ r,
+                                                         const double* __restrict__ da = nullptr,
+                                                         double* __restrict__ part = nullptr, int64_t pt = 0,
+                                                         int64_t boff = 0) {
   double a0 = 0, a1 = 0;
   const int g = (int)blockIdx.x < nb0 ? 0 : 1;
   const int blk = g == 0 ? (int)blockIdx.x : (int)blockIdx.x - nb0;
-  be_resid_rows_part<T, T, MODE, 0>(L, g, x, b, r, blk * kBlock, kBlock, nullptr, a0, a1);
+  be_resid_rows_part<T, TX, MODE, NDOT>(L, g, x, b, r, blk * kBlock, kBlock, da, a0, a1);
+  if (NDOT > 0) block_partials<kBlock>(a0, a1, NDOT, part, pt, boff + blockIdx.x, threadIdx.x);
 }
 
 // Restriction of rf into the coarse b over coarse cells [beg, beg + cnt);

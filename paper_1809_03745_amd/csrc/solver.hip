@@ -1246,7 +1246,16 @@ static void matvec_dots(DevProblem& D, const Z* x, double* out, const double* da
     const bool pair = pair_ok(l) && al2(x) && al2(out) && al2(da);
     const dim3 g((unsigned)(pair ? zp_resid_blocks(l) : zm_resid_blocks(l)));
     const int64_t G = (int64_t)g.x;
-    pt = G + (int64_t)nblk(l.R * kSub);
+    // explicit rows: the sliced copy (one thread per row) where there is one
+    const bool sl = l.R > 0 && l.sl_ptr.p;
+    int nb0 = 0, nb1 = 0;
+    if (sl) {
+      nb0 = (l.cls_ptr.size() == 3 ? l.cls_ptr[1] - l.cls_ptr[0] : (int)l.R);
+      nb1 = (l.cls_ptr.size() == 3 ? l.cls_ptr[2] - l.cls_ptr[1] : 0);
+      nb0 = (nb0 + kBlock - 1) / kBlock;
+      nb1 = (nb1 + kBlock - 1) / kBlock;
+    }
+    pt = G + (sl ? (int64_t)(nb0 + nb1) : (int64_t)nblk(l.R * kSub));
     if (pair) {
       if (ndot == 1)
         hipLaunchKernelGGL((k_resid_zp3<double, 1, Z, 1>), g, dim3(64, kRPY), 0, s, l.tag.p, x, nullptr, out, tp, da,
@@ -1254,27 +1263,27 @@ static void matvec_dots(DevProblem& D, const Z* x, double* out, const double* da
       else
         hipLaunchKernelGGL((k_resid_zp3<double, 1, Z, 2>), g, dim3(64, kRPY), 0, s, l.tag.p, x, nullptr, out, tp, da,
                            D.part.p, pt);
-      if (l.R > 0) {
-        if (ndot == 1)
-          hipLaunchKernelGGL((k_resid_irr<double, 1, Z, 1>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R,
-                             l.irow_dof.p, l.rp.p, l.col.p, l.val64.p, l.diag64.p, x, nullptr, out, da, D.part.p, pt,
-                             G);
-        else
-          hipLaunchKernelGGL((k_resid_irr<double, 1, Z, 2>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R,
-                             l.irow_dof.p, l.rp.p, l.col.p, l.val64.p, l.diag64.p, x, nullptr, out, da, D.part.p, pt,
-                             G);
-      }
     } else if (ndot == 1) {
       hipLaunchKernelGGL((k_resid_zm3<double, 1, Z, 1>), g, dim3(kRZX, kRZY), 0, s, l.tag.p, x, nullptr, out, tp, da,
                          D.part.p, pt);
-      if (l.R > 0)
-        hipLaunchKernelGGL((k_resid_irr<double, 1, Z, 1>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R,
-                           l.irow_dof.p, l.rp.p, l.col.p, l.val64.p, l.diag64.p, x, nullptr, out, da, D.part.p, pt,
-                           G);
     } else {
       hipLaunchKernelGGL((k_resid_zm3<double, 1, Z, 2>), g, dim3(kRZX, kRZY), 0, s, l.tag.p, x, nullptr, out, tp, da,
                          D.part.p, pt);
-      if (l.R > 0)
+    }
+    if (sl) {
+      const BLev<double> L = make_blev<double>(l);
+      if (ndot == 1)
+        hipLaunchKernelGGL((k_resid_irr_sl<double, 1, Z, 1>), dim3((unsigned)(nb0 + nb1)), dim3(kBlock), 0, s, L, nb0,
+                           x, nullptr, out, da, D.part.p, pt, G);
+      else
+        hipLaunchKernelGGL((k_resid_irr_sl<double, 1, Z, 2>), dim3((unsigned)(nb0 + nb1)), dim3(kBlock), 0, s, L, nb0,
+                           x, nullptr, out, da, D.part.p, pt, G);
+    } else if (l.R > 0) {
+      if (ndot == 1)
+        hipLaunchKernelGGL((k_resid_irr<double, 1, Z, 1>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R,
+                           l.irow_dof.p, l.rp.p, l.col.p, l.val64.p, l.diag64.p, x, nullptr, out, da, D.part.p, pt,
+                           G);
+      else
         hipLaunchKernelGGL((k_resid_irr<double, 1, Z, 2>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R,
                            l.irow_dof.p, l.rp.p, l.col.p, l.val64.p, l.diag64.p, x, nullptr, out, da, D.part.p, pt,
                            G);

@@ -427,9 +427,10 @@ def main():
     value = P.N * tot_cycles / dt
 
     # dominant kernel: the finest-level smoother, timed inside solves of the
-    # same workload with a HIP event pair around each of its launches on the
-    # library's stream (the solve's own cache state), and for comparison in a
-    # back-to-back loop of launches on zeroed vectors (warm caches)
+    # same workload, each launch on the library's stream stamped with HIP
+    # start/end events by its dispatch (the solve's own cache state), and for
+    # comparison in a back-to-back loop of launches on zeroed vectors (warm
+    # caches)
     t_steps = max(1, min(args.steps, 5))
     P.kernel_timing(0, 0, True)
     P.kernel_timing(1, 0, True)
@@ -447,7 +448,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": label, "kernel_ms": round(k_ms, 5), "launches_timed": k_n,
-            "timed_in": f"{t_steps} solves after the timed region (HIP events around each launch)",
+            "timed_in": f"{t_steps} solves after the timed region (each launch stamped with HIP start/end events)",
             "kernel_ms_back_to_back": round(k_ms_b2b, 5), "alg_bytes_per_launch": int(k_bytes),
             "alg_bytes_unit": f"{3 * (4 if prec == ebmg.MIXED else 8) + 1} B per updated cell ({unit_kind})"}
     r_ms_b2b, r_bytes = P.time_kernel(1, 0, reps=20)

@@ -291,10 +291,10 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
  * kernel (which = 0: the fused sweep, or each colour phase / half-sweep where
  * the level uses those) or of its FP64 residual kernel (which = 1: the
  * template-cell kernel of every FP64 r = b - A x on that level: the solve's
- * residual checks, and the V-cycle residuals of FP64 problems), with a HIP
- * event pair on the
- * context stream around every launch; while any timing is on, those solves
- * launch their kernels directly instead of replaying graphs (the same
+ * residual checks, and the V-cycle residuals of FP64 problems): each such
+ * launch carries a HIP event pair that its dispatch stamps with the
+ * kernel's own start and end (extended launch); while any timing is on,
+ * those solves launch their kernels directly instead of replaying graphs (the same
  * kernels in the same order). enable = 0 stops it and reports the number of
  * launches timed, their mean duration (ms) and the algorithmic bytes of one
  * launch (as ebmg_time_kernel counts them). Outputs are HOST pointers and may

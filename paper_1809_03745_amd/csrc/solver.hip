@@ -8,6 +8,7 @@
 // FP32 on the correction equation A e = r, with r = b - A phi formed in FP64,
 // the bottom level solved in FP64, and phi += e applied in FP64.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <atomic>
@@ -82,21 +83,22 @@ struct DevBuf {
   }
 };
 
-// HIP event pairs around one level's sweep-kernel launches during solves
-// (measurement hook): recorded on the solve stream, read after the solve's
-// final synchronisation.
+// Event pairs stamped with the start and end of one level's kernel launches
+// during solves (measurement hook; the launches go through KLAUNCH), read
+// after the solve's final synchronisation.
 struct KTiming {
   std::vector<hipEvent_t> ev;
-  size_t used = 0;   // events recorded since the last harvest (pairs)
+  size_t used = 0;   // events handed out since the last harvest (pairs)
   int64_t n = 0;     // launches timed
   double ms = 0;     // their total duration
-  void record(hipStream_t s) {
-    if (used == ev.size()) {
+  std::pair<hipEvent_t, hipEvent_t> pair() {
+    while (used + 2 > ev.size()) {
       hipEvent_t e = nullptr;
       HIPCHECK(hipEventCreate(&e));
       ev.push_back(e);
     }
-    HIPCHECK(hipEventRecord(ev[used++], s));
+    used += 2;
+    return {ev[used - 2], ev[used - 1]};
   }
   void harvest() {
     for (size_t i = 0; i + 1 < used; i += 2) {
@@ -111,6 +113,18 @@ struct KTiming {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
 };
+
+// A kernel launch; with a timing record kt (non-null) the kernel's own start
+// and end are stamped into a fresh event pair of kt by the dispatch itself.
+#define KLAUNCH(kt, kernel, grid, block, shmem, stream, ...)                                            \
+  do {                                                                                                \
+    if (kt) {                                                                                         \
+      const auto ev_ = (kt)->pair();                                                                  \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ev_.first, ev_.second, 0, __VA_ARGS__); \
+    } else {                                                                                          \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                            \
+    }                                                                                                 \
+  } while (0)
 
 struct DevLevel {
   int dim = 2;
@@ -395,8 +409,8 @@ template <typename T, int TX, int TY, int KZ, bool WIDE = false>
 static void launch_zm_cfg(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s) {
   if (WIDE && l.n[0] % 4 != 0) throw ArgError("the wide-fetch sweep needs an x extent that is a multiple of 4");
   const int64_t nb = (int64_t)((l.n[0] + TX - 1) / TX) * ((l.n[1] + TY - 1) / TY) * ((l.n[2] + KZ - 1) / KZ);
-  hipLaunchKernelGGL((k_rb_zm3<T, TX, TY, KZ, WIDE>), dim3((unsigned)nb), dim3(TX * TY / 2), 0, s, l.tag.p, xin,
-                     xout, b, tp, l.N2);
+  KLAUNCH(l.kt, (k_rb_zm3<T, TX, TY, KZ, WIDE>), dim3((unsigned)nb), dim3(TX * TY / 2), 0, s, l.tag.p, xin, xout, b,
+          tp, l.N2);
 }
 
 template <typename T>
@@ -421,10 +435,10 @@ static void launch_fused(DevLevel& l, const T* xin, T* xout, const T* b, const T
     launch_zm<T>(l, xin, xout, b, tp, s);
   } else if (l.dim == 3) {
     const int64_t nb = (int64_t)((l.n[0] + kTX - 1) / kTX) * ((l.n[1] + kTY - 1) / kTY) * ((l.n[2] + kTZ - 1) / kTZ);
-    hipLaunchKernelGGL((k_rb_tile3<T>), dim3((unsigned)nb), dim3(kTileThreads), 0, s, l.tag.p, xin, xout, b, tp, l.N2);
+    KLAUNCH(l.kt, (k_rb_tile3<T>), dim3((unsigned)nb), dim3(kTileThreads), 0, s, l.tag.p, xin, xout, b, tp, l.N2);
   } else {
     const int64_t nb = (int64_t)((l.n[0] + kTX2 - 1) / kTX2) * ((l.n[1] + kTY2 - 1) / kTY2);
-    hipLaunchKernelGGL((k_rb_tile2<T>), dim3((unsigned)nb), dim3(kTileThreads), 0, s, l.tag.p, xin, xout, b, tp, l.N2);
+    KLAUNCH(l.kt, (k_rb_tile2<T>), dim3((unsigned)nb), dim3(kTileThreads), 0, s, l.tag.p, xin, xout, b, tp, l.N2);
   }
 }
 
@@ -904,10 +918,10 @@ static void launch_oop(DevLevel& l, int colour, bool rows, const T* xin, T* xout
   }
   const unsigned nbr = nblk_sub((int64_t)nup + ncp);
   if (l.dim == 3)
-    hipLaunchKernelGGL((k_rb_oop<T, 3>), dim3(nbc + nbr), dim3(kBlock), 0, s, l.tag.p, xin, xout, b, tp, colour, nbc,
+    KLAUNCH(l.kt, (k_rb_oop<T, 3>), dim3(nbc + nbr), dim3(kBlock), 0, s, l.tag.p, xin, xout, b, tp, colour, nbc,
                        up, nup, cp, ncp, l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l));
   else
-    hipLaunchKernelGGL((k_rb_oop<T, 2>), dim3(nbc + nbr), dim3(kBlock), 0, s, l.tag.p, xin, xout, b, tp, colour, nbc,
+    KLAUNCH(l.kt, (k_rb_oop<T, 2>), dim3(nbc + nbr), dim3(kBlock), 0, s, l.tag.p, xin, xout, b, tp, colour, nbc,
                        up, nup, cp, ncp, l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l));
 }
 
@@ -936,9 +950,7 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
     T* cur = x;
     T* alt = Vec<T>::xa(l);
     for (int it = 0; it < sweeps; ++it) {
-      if (l.kt) l.kt->record(s);
       launch_fused<T>(l, cur, alt, b, tp, s);
-      if (l.kt) l.kt->record(s);
       std::swap(cur, alt);
       irr_group<T>(l, 0, cur, b, s);
       irr_group<T>(l, 1, cur, b, s);
@@ -954,9 +966,7 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
     T* alt = Vec<T>::xa(l);
     for (int it = 0; it < sweeps; ++it)
       for (int colour = 0; colour < 2; ++colour) {
-        if (l.kt) l.kt->record(s);
         launch_oop<T>(l, colour, true, cur, alt, b, s);
-        if (l.kt) l.kt->record(s);
         std::swap(cur, alt);
       }
     HIPCHECK(hipGetLastError());
@@ -965,12 +975,10 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
   const Shape sh = shape3((l.n[0] + 1) / 2, l.n[1], l.dim == 3 ? l.n[2] : 1);
   for (int it = 0; it < sweeps; ++it) {
     for (int colour = 0; colour < 2; ++colour) {
-      if (l.kt) l.kt->record(s);
       if (l.dim == 3)
-        hipLaunchKernelGGL((k_rb<T, 3>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
+        KLAUNCH(l.kt, (k_rb<T, 3>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
       else
-        hipLaunchKernelGGL((k_rb<T, 2>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
-      if (l.kt) l.kt->record(s);
+        KLAUNCH(l.kt, (k_rb<T, 2>), sh.g, sh.b, 0, s, l.tag.p, x, b, tp, colour);
       irr_group<T>(l, colour, x, b, s);
     }
   }
@@ -982,14 +990,12 @@ static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
   if (l.dim == 3 && l.N >= kResidZMMin) {
     KTiming* kr = (sizeof(T) == 8 && MODE == 0) ? l.ktr : nullptr;
-    if (kr) kr->record(s);
     if (sizeof(T) == 8 && pair_ok(l) && al2(x) && al2(b) && al2(r))
-      hipLaunchKernelGGL((k_resid_zp3<T, MODE>), dim3((unsigned)zp_resid_blocks(l)), dim3(64, kRPY), 0, s, l.tag.p,
-                         x, b, r, tp);
+      KLAUNCH(kr, (k_resid_zp3<T, MODE>), dim3((unsigned)zp_resid_blocks(l)), dim3(64, kRPY), 0, s, l.tag.p, x, b, r,
+              tp, (const T*)nullptr, (double*)nullptr, (int64_t)0);
     else
-      hipLaunchKernelGGL((k_resid_zm3<T, MODE>), dim3((unsigned)zm_resid_blocks(l)), dim3(kRZX, kRZY), 0, s,
-                         l.tag.p, x, b, r, tp);
-    if (kr) kr->record(s);
+      KLAUNCH(kr, (k_resid_zm3<T, MODE>), dim3((unsigned)zm_resid_blocks(l)), dim3(kRZX, kRZY), 0, s, l.tag.p, x, b,
+              r, tp, (const T*)nullptr, (double*)nullptr, (int64_t)0);
     if (l.R > 0 && l.sl_ptr.p && Vec<T>::sval(l)) {
       const BLev<T> L = make_blev<T>(l);
       const int nb0 = (L.grp_ptr[1] - L.grp_ptr[0] + kBlock - 1) / kBlock;

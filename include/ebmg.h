@@ -289,7 +289,8 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
 /* Measurement hook, in-solve form: enable = 1 starts timing, inside later
  * ebmg_solve calls on pb, the launches of level `level`'s smoothing-sweep
  * kernel (which = 0: the fused sweep, or each colour phase / half-sweep where
- * the level uses those) or of its FP64 residual kernel (which = 1: the
+ * the level uses those; not the first z-marching sweep of a V-cycle, which
+ * starts from x = 0 and does not read it) or of its FP64 residual kernel (which = 1: the
  * template-cell kernel of every FP64 r = b - A x on that level: the solve's
  * residual checks, and the V-cycle residuals of FP64 problems): each such
  * launch carries a HIP event pair that its dispatch stamps with the

@@ -434,7 +434,10 @@ __device__ __forceinline__ T zm_inplane_rdg(int gx, int gy, int nx, int ny, cons
 // WIDE: the halo and ring regions are fetched as aligned 16-byte chunks of x
 // and b and 4-byte words of tags (the chunk rows extend past the regions to
 // alignment) and scattered into the same LDS layout; needs nx % 4 == 0.
-template <typename T, int TX, int TY, int KZ, bool WIDE = false>
+// ZIN: x is zero on entry (the first sweep of a V-cycle level from a zero
+// correction): xin is not read, every x value staged is 0 and the
+// second-phase unknowns are written as 0; the result is the same.
+template <typename T, int TX, int TY, int KZ, bool WIDE = false, bool ZIN = false>
 __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restrict__ tag,
                                                       const T* __restrict__ xin, T* __restrict__ xout,
                                                       const T* __restrict__ b, Tmpl<T> tp, int64_t nsec) {
@@ -568,11 +571,15 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
     const int zz_ = (z);                                                     \
     const int64_t zoff_ = sxy * (zz_ >= 0 && zz_ < nz ? zz_ : 0);            \
     if constexpr (WIDE) {                                                    \
-      _Pragma("unroll") for (int u = 0; u < UOW; ++u) P##ow[u] = *(const VT*)(xin + zoff_ + offow[u]); \
+      if constexpr (!ZIN) {                                                  \
+        _Pragma("unroll") for (int u = 0; u < UOW; ++u) P##ow[u] = *(const VT*)(xin + zoff_ + offow[u]); \
+      }                                                                      \
       _Pragma("unroll") for (int u = 0; u < URW; ++u) P##bw[u] = *(const VT*)(b + zoff_ + offbw[u]); \
       _Pragma("unroll") for (int u = 0; u < UTW; ++u) P##tw[u] = *(const uint32_t*)(tag + zoff_ + offtw[u]); \
     } else {                                                                 \
-      _Pragma("unroll") for (int u = 0; u < UO; ++u) P##ov[u] = xin[zoff_ + offo[u]]; \
+      if constexpr (!ZIN) {                                                  \
+        _Pragma("unroll") for (int u = 0; u < UO; ++u) P##ov[u] = xin[zoff_ + offo[u]]; \
+      }                                                                      \
       _Pragma("unroll") for (int u = 0; u < UR; ++u) {                       \
         P##bv[u] = b[zoff_ + offr[u]];                                       \
         P##tv[u] = tag[zoff_ + offr[u]];                                     \
@@ -594,7 +601,7 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
           const bool ok_ = zin_ && ((inow >> u) & 1);                        \
           _Pragma("unroll") for (int e = 0; e < VW; ++e) {                   \
             const int col_ = c0_ + e;                                        \
-            if (col_ >= 0 && col_ < OX) v_[col_ + OX * row_] = ok_ ? P##ow[u][e] : T(0); \
+            if (col_ >= 0 && col_ < OX) v_[col_ + OX * row_] = (ok_ && !ZIN) ? P##ow[u][e] : T(0); \
           }                                                                  \
         }                                                                    \
       }                                                                      \
@@ -624,7 +631,7 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
     } else {                                                                 \
       _Pragma("unroll") for (int u = 0; u < UO; ++u) {                       \
         const int q = stid + u * NT;                                         \
-        if (q < NO) v_[q] = (zin_ && ((ino >> u) & 1)) ? P##ov[u] : T(0);    \
+        if (q < NO) v_[q] = (!ZIN && zin_ && ((ino >> u) & 1)) ? P##ov[u] : T(0); \
       }                                                                      \
       _Pragma("unroll") for (int u = 0; u < UR; ++u) {                       \
         const int q = stid + u * NT;                                         \
@@ -716,7 +723,7 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
 #undef ZM_LOAD
   // second-phase unknowns are not touched by this sweep: copy them through
   const int64_t N = sxy * nz;
-  for (int64_t q = (int64_t)blockIdx.x * NT + tid; q < nsec; q += nblocks * NT) xout[N + q] = xin[N + q];
+  for (int64_t q = (int64_t)blockIdx.x * NT + tid; q < nsec; q += nblocks * NT) xout[N + q] = ZIN ? T(0) : xin[N + q];
 }
 
 
@@ -1385,7 +1392,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_p2(double* __restrict__ p, cons
   const double pv = r[t] + beta * (p[t] - sc[SC_OMEGA] * v[t]);
   p[t] = pv;
   if (bf) bf[t] = (float)pv;
-  z[t] = Z(0);
+  if (z) z[t] = Z(0);
 }
 
 template <typename Z>
@@ -1397,7 +1404,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_s2(double* __restrict__ s, cons
   const double sv = r[t] - sc[SC_ALPHA] * v[t];
   s[t] = sv;
   if (bf) bf[t] = (float)sv;
-  z[t] = Z(0);
+  if (z) z[t] = Z(0);
 }
 
 // x += alpha ph + omega sh ; r = s - omega t, with the partials of (rh, r)

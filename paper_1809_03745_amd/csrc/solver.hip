@@ -405,34 +405,44 @@ static bool fused_ok(const DevLevel& l) {
 constexpr int kZMConfigs = 10;   // 7..9: wide-fetch versions of 1, 4, 6 (x extent a multiple of 4)
 static bool zm_cfg_ok(const DevLevel& l, int c) { return c < 7 || l.n[0] % 4 == 0; }
 
+// zin: x is zero on entry, so the sweep need not read it (not timed by the
+// in-solve hook: it moves fewer bytes than a full sweep)
 template <typename T, int TX, int TY, int KZ, bool WIDE = false>
-static void launch_zm_cfg(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s) {
+static void launch_zm_cfg(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s,
+                          bool zin) {
   if (WIDE && l.n[0] % 4 != 0) throw ArgError("the wide-fetch sweep needs an x extent that is a multiple of 4");
   const int64_t nb = (int64_t)((l.n[0] + TX - 1) / TX) * ((l.n[1] + TY - 1) / TY) * ((l.n[2] + KZ - 1) / KZ);
-  KLAUNCH(l.kt, (k_rb_zm3<T, TX, TY, KZ, WIDE>), dim3((unsigned)nb), dim3(TX * TY / 2), 0, s, l.tag.p, xin, xout, b,
-          tp, l.N2);
+  if (zin)
+    hipLaunchKernelGGL((k_rb_zm3<T, TX, TY, KZ, WIDE, true>), dim3((unsigned)nb), dim3(TX * TY / 2), 0, s, l.tag.p,
+                       xin, xout, b, tp, l.N2);
+  else
+    KLAUNCH(l.kt, (k_rb_zm3<T, TX, TY, KZ, WIDE>), dim3((unsigned)nb), dim3(TX * TY / 2), 0, s, l.tag.p, xin, xout,
+            b, tp, l.N2);
 }
 
 template <typename T>
-static void launch_zm(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s) {
+static void launch_zm(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s,
+                      bool zin = false) {
   switch (l.zmcfg) {
-    case 1: launch_zm_cfg<T, 64, 16, 32>(l, xin, xout, b, tp, s); break;
-    case 2: launch_zm_cfg<T, 32, 16, 32>(l, xin, xout, b, tp, s); break;
-    case 3: launch_zm_cfg<T, 64, 8, 16>(l, xin, xout, b, tp, s); break;
-    case 4: launch_zm_cfg<T, 128, 8, 32>(l, xin, xout, b, tp, s); break;
-    case 5: launch_zm_cfg<T, 32, 8, 32>(l, xin, xout, b, tp, s); break;
-    case 6: launch_zm_cfg<T, 32, 32, 32>(l, xin, xout, b, tp, s); break;
-    case 7: launch_zm_cfg<T, 64, 16, 32, true>(l, xin, xout, b, tp, s); break;
-    case 8: launch_zm_cfg<T, 128, 8, 32, true>(l, xin, xout, b, tp, s); break;
-    case 9: launch_zm_cfg<T, 32, 32, 32, true>(l, xin, xout, b, tp, s); break;
-    default: launch_zm_cfg<T, 64, 8, 32>(l, xin, xout, b, tp, s); break;
+    case 1: launch_zm_cfg<T, 64, 16, 32>(l, xin, xout, b, tp, s, zin); break;
+    case 2: launch_zm_cfg<T, 32, 16, 32>(l, xin, xout, b, tp, s, zin); break;
+    case 3: launch_zm_cfg<T, 64, 8, 16>(l, xin, xout, b, tp, s, zin); break;
+    case 4: launch_zm_cfg<T, 128, 8, 32>(l, xin, xout, b, tp, s, zin); break;
+    case 5: launch_zm_cfg<T, 32, 8, 32>(l, xin, xout, b, tp, s, zin); break;
+    case 6: launch_zm_cfg<T, 32, 32, 32>(l, xin, xout, b, tp, s, zin); break;
+    case 7: launch_zm_cfg<T, 64, 16, 32, true>(l, xin, xout, b, tp, s, zin); break;
+    case 8: launch_zm_cfg<T, 128, 8, 32, true>(l, xin, xout, b, tp, s, zin); break;
+    case 9: launch_zm_cfg<T, 32, 32, 32, true>(l, xin, xout, b, tp, s, zin); break;
+    default: launch_zm_cfg<T, 64, 8, 32>(l, xin, xout, b, tp, s, zin); break;
   }
 }
 
+// zin (z-marching form only): x is zero on entry
 template <typename T>
-static void launch_fused(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s) {
+static void launch_fused(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s,
+                         bool zin = false) {
   if (l.dim == 3 && l.fvar == 1) {
-    launch_zm<T>(l, xin, xout, b, tp, s);
+    launch_zm<T>(l, xin, xout, b, tp, s, zin);
   } else if (l.dim == 3) {
     const int64_t nb = (int64_t)((l.n[0] + kTX - 1) / kTX) * ((l.n[1] + kTY - 1) / kTY) * ((l.n[2] + kTZ - 1) / kTZ);
     KLAUNCH(l.kt, (k_rb_tile3<T>), dim3((unsigned)nb), dim3(kTileThreads), 0, s, l.tag.p, xin, xout, b, tp, l.N2);
@@ -483,7 +493,7 @@ static BLev<T> make_blev(DevLevel& l) {
 }
 
 template <typename T>
-static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* x, const T* b);
+static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* x, const T* b, bool xz = false);
 
 // Tail autotuner: time a whole V-cycle (on zero vectors) with the one-
 // workgroup engine starting at each level of at most kTailMax unknowns, and
@@ -548,7 +558,7 @@ static void upload_tail(DevProblem& D, hipStream_t s) {
 }
 
 template <typename T>
-static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s);
+static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s, bool xz = false);
 
 // Smoother autotuner: time a complete sweep (template cells and explicit
 // rows) of each variant with HIP events on zeroed vectors and keep the
@@ -941,8 +951,10 @@ static void irr_group(DevLevel& l, int grp, T* x, const T* b, hipStream_t s) {
   hipLaunchKernelGGL((k_irr_scatter<T>), dim3(nblk(nr)), dim3(kBlock), 0, s, rows, nr, l.irow_dof.p, tmp, x);
 }
 
+// xz: x is zero on entry (a V-cycle level's correction); used by the
+// z-marching sweep, whose first sweep then does not read x
 template <typename T>
-static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
+static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s, bool xz) {
   const Tmpl<T>& tp = Vec<T>::t(l);
   if (l.fused && Vec<T>::xa(l)) {
     // out-of-place fused red+black sweeps, then the explicit rows of red and
@@ -950,7 +962,7 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s) {
     T* cur = x;
     T* alt = Vec<T>::xa(l);
     for (int it = 0; it < sweeps; ++it) {
-      launch_fused<T>(l, cur, alt, b, tp, s);
+      launch_fused<T>(l, cur, alt, b, tp, s, xz && it == 0);
       std::swap(cur, alt);
       irr_group<T>(l, 0, cur, b, s);
       irr_group<T>(l, 1, cur, b, s);
@@ -1074,7 +1086,8 @@ static void prolong_from(DevLevel& f, DevLevel& c, const T* ec, T* xf, hipStream
 
 
 template <typename T>
-static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* x, const T* b) {
+// xz: x holds zeros on entry (lets the first z-marching sweep skip reading it)
+static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* x, const T* b, bool xz) {
   DevLevel& L = D.lv[l];
   if ((int)l == D.tail_l0) {
     const BLev<T>* lv = (const BLev<T>*)D.tail_lv.p;
@@ -1104,11 +1117,11 @@ static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* 
     return;
   }
   DevLevel& C = D.lv[l + 1];
-  smooth<T>(L, x, b, o.nu1, s);
+  smooth<T>(L, x, b, o.nu1, s, xz);
   T* r = Vec<T>::r(L);
   residual<T, 0>(L, x, b, r, s);
-  restrict_to<T>(L, C, r, Vec<T>::b(C), Vec<T>::x(C), s);
-  vcycle<T>(D, o, l + 1, s, Vec<T>::x(C), Vec<T>::b(C));
+  restrict_to<T>(L, C, r, Vec<T>::b(C), Vec<T>::x(C), s);   // also clears the coarse x
+  vcycle<T>(D, o, l + 1, s, Vec<T>::x(C), Vec<T>::b(C), true);
   prolong_from<T>(L, C, Vec<T>::x(C), x, s);
   smooth<T>(L, x, b, o.nu2, s);
 }
@@ -1335,21 +1348,25 @@ static ebmg_status bicgstab_t(DevProblem& D, const Options& o, double bn, double
     hipLaunchKernelGGL(k_sc_reset, dim3(1), dim3(1), 0, s, D.scal.p);
     dot_dev<double>(D, rh, r, nd, SC_RHO, s);
   };
+  // the preconditioner output starts from zero: cleared by the p- and
+  // s-updates, unless the finest level's first sweep is the z-marching one,
+  // which then takes x = 0 without reading it
+  const bool zin = L.dim == 3 && L.fused && L.fvar == 1 && Vec<Z>::xa(L) && D.tail_l0 != 0 && o.nu1 > 0;
   auto vcyc = [&](Z* z, const double* in, hipStream_t q) {
     if constexpr (std::is_same<Z, float>::value) {
       (void)in;
-      vcycle<float>(D, o, 0, q, z, L.b32.p);
+      vcycle<float>(D, o, 0, q, z, L.b32.p, zin);
     } else {
-      vcycle<double>(D, o, 0, q, z, in);
+      vcycle<double>(D, o, 0, q, z, in, zin);
     }
   };
   // one iteration: p-update, V-cycle, A ph, s-update, V-cycle, A sh, x/r update
   auto iteration = [&](hipStream_t q) {
-    hipLaunchKernelGGL((k_bicg_p2<Z>), dim3(nb), dim3(kBlock), 0, q, p, r, v, D.scal.p, nd, bf, ph);
+    hipLaunchKernelGGL((k_bicg_p2<Z>), dim3(nb), dim3(kBlock), 0, q, p, r, v, D.scal.p, nd, bf, zin ? nullptr : ph);
     vcyc(ph, p, q);
     matvec_dots<Z>(D, ph, v, rh, 1, SC_RV, q);
     hipLaunchKernelGGL(k_sc_alpha, dim3(1), dim3(1), 0, q, D.scal.p);
-    hipLaunchKernelGGL((k_bicg_s2<Z>), dim3(nb), dim3(kBlock), 0, q, sv, r, v, D.scal.p, nd, bf, sh);
+    hipLaunchKernelGGL((k_bicg_s2<Z>), dim3(nb), dim3(kBlock), 0, q, sv, r, v, D.scal.p, nd, bf, zin ? nullptr : sh);
     vcyc(sh, sv, q);
     matvec_dots<Z>(D, sh, t, sv, 2, SC_TS, q);
     hipLaunchKernelGGL(k_sc_omega, dim3(1), dim3(1), 0, q, D.scal.p);

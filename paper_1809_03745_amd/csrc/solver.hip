@@ -150,6 +150,7 @@ struct DevLevel {
   KTiming* kt = nullptr;           // sweep launches timed during solves (or none)
   KTiming* ktr = nullptr;          // FP64 residual launches timed during solves (or none)
   double tune_split_ms = 0, tune_fused_ms = 0, tune_zm_ms = 0, tune_oop_ms = 0;
+  std::vector<double> tune_zm_cfg_ms;   // sweep ms of each z-marching configuration (0: not timed)
   Tmpl<double> t64;
   Tmpl<float> t32;
   // vectors
@@ -498,6 +499,52 @@ static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* 
 // Tail autotuner: time a whole V-cycle (on zero vectors) with the one-
 // workgroup engine starting at each level of at most kTailMax unknowns, and
 // with no tail at all; keep the fastest.
+// Sweep timings alone rank the z-marching configurations of the finest level
+// only to within a few per cent; where the finest level uses one, the
+// fastest few are timed again inside whole V-cycles (the solve's own cache
+// state) and the fastest V-cycle decides.
+template <typename T>
+static void refine_finest_zm(DevProblem& D, const Options& o, hipStream_t s) {
+  DevLevel& L0 = D.lv[0];
+  if (o.smoother != 0 || !L0.fused || L0.fvar != 1 || L0.tune_zm_cfg_ms.empty() || D.lv.size() < 2) return;
+  std::vector<int> cfg;
+  for (int c = 0; c < (int)L0.tune_zm_cfg_ms.size(); ++c)
+    if (L0.tune_zm_cfg_ms[c] > 0) cfg.push_back(c);
+  std::sort(cfg.begin(), cfg.end(), [&](int a, int b) { return L0.tune_zm_cfg_ms[a] < L0.tune_zm_cfg_ms[b]; });
+  if (cfg.size() > 3) cfg.resize(3);
+  if (cfg.size() < 2) return;
+  T* x = Vec<T>::x(L0);
+  T* b = Vec<T>::b(L0);
+  fill<T>(x, L0.N + L0.N2, T(0), s);
+  fill<T>(b, L0.N + L0.N2, T(0), s);
+  const int tail0 = D.tail_l0;
+  D.tail_l0 = -1;
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  double best = 1e30;
+  int pick = L0.zmcfg;
+  for (int c : cfg) {
+    L0.zmcfg = c;
+    for (int r = 0; r < 2; ++r) vcycle<T>(D, o, 0, s, x, b);
+    const int reps = 5;
+    HIPCHECK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) vcycle<T>(D, o, 0, s, x, b);
+    HIPCHECK(hipEventRecord(e1, s));
+    HIPCHECK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  L0.zmcfg = pick;
+  D.tail_l0 = tail0;
+}
+
 template <typename T>
 static void tune_tail(DevProblem& D, const Options& o, hipStream_t s) {
   const int nl = (int)D.lv.size();
@@ -562,32 +609,42 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s, boo
 
 // Smoother autotuner: time a complete sweep (template cells and explicit
 // rows) of each variant with HIP events on zeroed vectors and keep the
-// fastest: split half-sweeps in place with grouped explicit rows, one-launch
+// fastest. On levels whose vectors could stay in the last-level cache
+// between back-to-back sweeps while a solve would have evicted them, a
+// scratch buffer larger than that cache is written between the timed pairs
+// of sweeps, so the sweeps are timed from memory as in a solve. Variants:
+// split half-sweeps in place with grouped explicit rows, one-launch
 // colour phases out of place, and where they apply the fused tile sweep and
 // the z-marching sweep in each tile configuration. Forced modes: 1 split,
 // 2 fused tile, 3 z-marching (tile in 2D) where the fused sweeps apply;
 // 4 a fixed rule with no timing (z-marching 64x16 tiles / tile sweep where
 // the fused sweeps apply, one-launch colour phases elsewhere).
 template <typename T>
-static double time_smooth(DevLevel& l, T* x, const T* b, hipStream_t s) {
+static double time_smooth(DevLevel& l, T* x, const T* b, hipStream_t s, float* flush, int64_t nflush) {
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
   smooth<T>(l, x, b, 2, s);
-  HIPCHECK(hipEventRecord(e0, s));
-  smooth<T>(l, x, b, 4, s);
-  HIPCHECK(hipEventRecord(e1, s));
-  HIPCHECK(hipEventSynchronize(e1));
-  HIPCHECK(hipGetLastError());
-  float ms = 0;
-  HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+  double tot = 0;
+  const int pairs = flush ? 2 : 1;
+  for (int r = 0; r < pairs; ++r) {
+    if (flush) fill<float>(flush, nflush, (float)r, s);
+    HIPCHECK(hipEventRecord(e0, s));
+    smooth<T>(l, x, b, flush ? 2 : 4, s);
+    HIPCHECK(hipEventRecord(e1, s));
+    HIPCHECK(hipEventSynchronize(e1));
+    HIPCHECK(hipGetLastError());
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+    tot += ms;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return ms / 4.0;
+  return tot / 4.0;
 }
 
 template <typename T>
-static void tune_level(DevLevel& l, T* x, T* xa, T* b, int mode, hipStream_t s) {
+static void tune_level(DevLevel& l, T* x, T* xa, T* b, int mode, hipStream_t s, float* flush, int64_t nflush) {
   const int64_t nd = l.N + l.N2;
   fill<T>(x, nd, T(0), s);
   fill<T>(xa, nd, T(0), s);
@@ -628,11 +685,15 @@ static void tune_level(DevLevel& l, T* x, T* xa, T* b, int mode, hipStream_t s) 
     l.oop = cands[q].oop;
     l.fvar = cands[q].fvar;
     l.zmcfg = cands[q].zmcfg;
-    cands[q].ms = time_smooth<T>(l, x, b, s);
+    cands[q].ms = time_smooth<T>(l, x, b, s, flush, nflush);
     if (cands[q].ms < cands[best].ms) best = q;
     if (!cands[q].fused && !cands[q].oop) l.tune_split_ms = cands[q].ms;
     if (cands[q].oop) l.tune_oop_ms = cands[q].ms;
     if (cands[q].fused && cands[q].fvar == 0) l.tune_fused_ms = cands[q].ms;
+    if (cands[q].fused && cands[q].fvar == 1) {
+      l.tune_zm_cfg_ms.resize(kZMConfigs, 0.0);
+      l.tune_zm_cfg_ms[cands[q].zmcfg] = cands[q].ms;
+    }
     if (cands[q].fused && cands[q].fvar == 1 && cands[q].ms < zbest) {
       zbest = cands[q].ms;
       l.tune_zm_ms = zbest;
@@ -646,13 +707,41 @@ static void tune_level(DevLevel& l, T* x, T* xa, T* b, int mode, hipStream_t s) 
   fill<T>(xa, nd, T(0), s);
 }
 
+// Last-level cache of the device (256 MB on MI355X) and the scratch written
+// between timed sweeps: sweeps whose vectors and tags exceed a quarter of it
+// are timed from memory.
+constexpr int64_t kLLCBytes = (int64_t)256 << 20;
+constexpr int64_t kFlushBytes = (int64_t)512 << 20;
+
 static void tune_smoother(DevLevel& l, bool mixed, int mode, hipStream_t s) {
   l.fused = false;
   l.oop = false;
-  if (mixed) {
-    if (l.xa32.p) tune_level<float>(l, l.x32.p, l.xa32.p, l.b32.p, mode, s);
-  } else {
-    if (l.xa64.p) tune_level<double>(l, l.x64.p, l.xa64.p, l.b64.p, mode, s);
+  const int64_t es = mixed ? 4 : 8;
+  float* flush = nullptr;
+  if (mode == 0 && (l.N + l.N2) * (3 * es + 1) > kLLCBytes / 4) {
+    // best effort: without the scratch the sweeps are timed back to back
+    if (hipMalloc((void**)&flush, kFlushBytes) != hipSuccess) {
+      flush = nullptr;
+      (void)hipGetLastError();
+    }
+  }
+  const int64_t nflush = kFlushBytes / (int64_t)sizeof(float);
+  try {
+    if (mixed) {
+      if (l.xa32.p) tune_level<float>(l, l.x32.p, l.xa32.p, l.b32.p, mode, s, flush, nflush);
+    } else {
+      if (l.xa64.p) tune_level<double>(l, l.x64.p, l.xa64.p, l.b64.p, mode, s, flush, nflush);
+    }
+  } catch (...) {
+    if (flush) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(flush);
+    }
+    throw;
+  }
+  if (flush) {
+    HIPCHECK(hipStreamSynchronize(s));
+    HIPCHECK(hipFree(flush));
   }
 }
 
@@ -877,9 +966,11 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
   for (auto& l : D.lv) tune_smoother(l, mixed, H.opt.smoother, s);
   if (mixed) {
     upload_tail<float>(D, s);
+    refine_finest_zm<float>(D, H.opt, s);
     tune_tail<float>(D, H.opt, s);
   } else {
     upload_tail<double>(D, s);
+    refine_finest_zm<double>(D, H.opt, s);
     tune_tail<double>(D, H.opt, s);
   }
   if (D.krylov) {

@@ -201,6 +201,18 @@ def test_async_calls_on_a_host_context(host_ctx):
     P.release()
 
 
+def test_kernel_timing_hook_arguments(host_ctx):
+    P = ebmg.Problem(host_ctx, W.manufactured_sine(8))
+    with pytest.raises(ebmg.EbmgError) as e:
+        P.kernel_timing(0, 0, True)
+    assert e.value.status == ebmg.ERR_DEVICE
+    for which, level, enable in ((2, 0, 1), (-1, 0, 1), (0, 0, 3)):
+        st = ebmg._lib.ebmg_kernel_timing(P.h, which, level, enable, None, None, None)
+        assert st == ebmg.ERR_ARG
+    assert ebmg._lib.ebmg_kernel_timing(None, 0, 0, 1, None, None, None) == ebmg.ERR_ARG
+    P.release()
+
+
 def test_problem_outlives_its_context_handle():
     c = ebmg.Context(-1)
     pr = W.manufactured_sine(16)

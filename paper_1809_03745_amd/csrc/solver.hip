@@ -843,13 +843,22 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
     std::vector<double> val, dg(d.R);
     col.reserve(L.col.size());
     val.reserve(L.val.size());
+    // each row's entries in column order: neighbouring rows of a slice then
+    // gather x at neighbouring addresses for the same entry position
+    std::vector<std::pair<int32_t, double>> ent;
     for (int64_t k = 0; k < d.R; ++k) {
       const int32_t r = perm[k];
       idof[k] = L.irow_dof[r];
       dg[k] = L.idiag[r];
-      for (int64_t e = L.rp[r]; e < L.rp[r + 1]; ++e) {
-        col.push_back(L.col[e]);
-        val.push_back(L.val[e]);
+      ent.clear();
+      for (int64_t e = L.rp[r]; e < L.rp[r + 1]; ++e) ent.emplace_back((int32_t)L.col[e], L.val[e]);
+      std::stable_sort(ent.begin(), ent.end(),
+                       [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                         return a.first < b.first;
+                       });
+      for (const auto& pe : ent) {
+        col.push_back(pe.first);
+        val.push_back(pe.second);
       }
       rp[k + 1] = (int64_t)col.size();
       ident[k] = (int32_t)k;

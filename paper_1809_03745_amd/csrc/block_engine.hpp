@@ -186,10 +186,13 @@ __device__ void be_rb(const BLev<T>& L, T* __restrict__ x, const T* __restrict__
 // kRowJ load chains in flight. Padding entries add 0 * x[0].
 constexpr int kRowJ = 8;
 
-template <typename T, typename TX>
+// TWO: columns c >= nx name entries x2[c - nx] of a second source.
+template <typename T, typename TX, bool TWO = false>
 __device__ __forceinline__ T sliced_row(const int32_t* __restrict__ col, const T* __restrict__ val,
-                                        const TX* __restrict__ x, int64_t p, int len) {
+                                        const TX* __restrict__ x, int64_t p, int len,
+                                        const TX* __restrict__ x2 = nullptr, int nx = 0) {
   FP_EXACT_ORDER
+  auto ld = [&](int c) -> T { return TWO ? (T)(c < nx ? x[c] : x2[c - nx]) : (T)x[c]; };
   T s = T(0);
   int j = 0;
   for (; j + kRowJ <= len; j += kRowJ) {
@@ -201,11 +204,11 @@ __device__ __forceinline__ T sliced_row(const int32_t* __restrict__ col, const T
       v[k] = val[p + (int64_t)(j + k) * kSlice];
     }
 #pragma unroll
-    for (int k = 0; k < kRowJ; ++k) xv[k] = (T)x[c[k]];
+    for (int k = 0; k < kRowJ; ++k) xv[k] = ld(c[k]);
 #pragma unroll
     for (int k = 0; k < kRowJ; ++k) s = s + v[k] * xv[k];
   }
-  for (; j < len; ++j) s = s + val[p + (int64_t)j * kSlice] * (T)x[col[p + (int64_t)j * kSlice]];
+  for (; j < len; ++j) s = s + val[p + (int64_t)j * kSlice] * ld(col[p + (int64_t)j * kSlice]);
   return s;
 }
 
@@ -213,9 +216,9 @@ __device__ __forceinline__ T sliced_row(const int32_t* __restrict__ col, const T
 // group; beg a multiple of kSlice) one slice per wavefront. pre(g) issues the
 // row's own loads (unknown index, diagonal, b) before the entry loop and
 // returns them; f(g, pre, s) finishes the row, s its off-diagonal sum.
-template <typename T, typename TX, typename Pre, typename F>
+template <typename T, typename TX, bool TWO = false, typename Pre, typename F>
 __device__ __forceinline__ void sliced_rows(const BLev<T>& L, int grp, const TX* __restrict__ x, int beg, int cnt,
-                                            Pre&& pre, F&& f) {
+                                            Pre&& pre, F&& f, const TX* __restrict__ x2 = nullptr, int nx = 0) {
   const int r0 = L.grp_ptr[grp];
   const int n = L.grp_ptr[grp + 1] - r0;
   const int end = be_end(n, beg, cnt);
@@ -227,7 +230,7 @@ __device__ __forceinline__ void sliced_rows(const BLev<T>& L, int grp, const TX*
     const int g = s0 + lane;
     const bool in = g < end;
     const auto own = pre(r0 + (in ? g : 0));
-    const T sm = sliced_row<T, TX>(L.sl_col, L.sl_val, x, p0 + lane, len);
+    const T sm = sliced_row<T, TX, TWO>(L.sl_col, L.sl_val, x, p0 + lane, len, x2, nx);
     if (in) f(r0 + g, own, sm);
   }
 }
@@ -240,19 +243,19 @@ struct RowOwn {
 
 // Jacobi values (b - offdiag . x) / diag of group grp's rows [beg, beg + cnt)
 // (relative to the group) into w.
-template <typename T>
+template <typename T, bool TWO = false>
 __device__ void be_irr_jac_part(const BLev<T>& L, int grp, const T* __restrict__ x, const T* __restrict__ b,
-                                int beg, int cnt) {
+                                int beg, int cnt, const T* __restrict__ x2 = nullptr, int nx = 0) {
   FP_EXACT_ORDER
   const int r0 = L.grp_ptr[grp];
   if (L.grp_ptr[grp + 1] <= r0) return;
-  sliced_rows<T, T>(
+  sliced_rows<T, T, TWO>(
       L, grp, x, beg, cnt,
       [&](int g) {
         const int64_t q = L.irow_dof[g];
         return RowOwn<T>{q, L.diag[g], b[q]};
       },
-      [&](int g, const RowOwn<T>& o, T sm) { L.w[g - r0] = (o.v - sm) / o.d; });
+      [&](int g, const RowOwn<T>& o, T sm) { L.w[g - r0] = (o.v - sm) / o.d; }, x2, nx);
 }
 
 template <typename T>
@@ -389,6 +392,17 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_irr_jac_sl(BLev<T> L, int grp, const T* __restrict__ x,
                                                        const T* __restrict__ b) {
   be_irr_jac_part<T>(L, grp, x, b, (int)blockIdx.x * kBlock, kBlock);
+}
+
+// Jacobi values of group 1 while group 0's new values are still in w0 (not
+// yet scattered into x): L carries group 1's columns with every group-0 row
+// unknown renamed nx + (its position in group 0), so those entries read w0,
+// and L.w points where group 1's values go. The same values as scattering
+// group 0 first and then running k_irr_jac_sl on group 1.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_irr_jac_sl2(BLev<T> L, const T* __restrict__ x,
+                                                        const T* __restrict__ b, const T* __restrict__ w0, int nx) {
+  be_irr_jac_part<T, true>(L, 1, x, b, (int)blockIdx.x * kBlock, kBlock, w0, nx);
 }
 
 // r = b - A x (MODE 0) or A x (MODE 1) on the explicit rows: blocks [0, nb0)

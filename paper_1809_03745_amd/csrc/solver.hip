@@ -139,6 +139,7 @@ struct DevLevel {
   // sliced copy of the explicit rows (engine and batched kernels)
   DevBuf<int64_t> sl_ptr;
   DevBuf<int32_t> sl_col;
+  DevBuf<int32_t> sl_colj;   // group 1's columns with group-0 row unknowns renamed (see k_irr_jac_sl2)
   DevBuf<double> sl_val64;
   DevBuf<float> sl_val32;
   int sl_grp[3] = {0, 0, 0};
@@ -160,7 +161,7 @@ struct DevLevel {
     tag.release(); irow_dof.release(); rp.release(); ns_cdof.release(); ns_child.release();
     np_fdof.release(); np_cdof.release(); col.release(); cls_rows.release(); ns_ptr.release();
     val64.release(); diag64.release(); val32.release(); diag32.release();
-    sl_ptr.release(); sl_col.release(); sl_val64.release(); sl_val32.release();
+    sl_ptr.release(); sl_col.release(); sl_colj.release(); sl_val64.release(); sl_val32.release();
     x64.release(); b64.release(); r64.release(); x32.release(); b32.release(); r32.release();
     w64.release(); w32.release(); xa64.release(); xa32.release();
   }
@@ -883,6 +884,21 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
       build_sliced(rp, col, val, gptr, sptr, scol, sval, d.sl_grp);
       d.sl_ptr.upload(sptr.data(), (int64_t)sptr.size(), s, by);
       d.sl_col.upload(scol.data(), (int64_t)scol.size(), s, by);
+      // group 1's columns with group-0 row unknowns renamed N + N2 + (position
+      // in group 0), for the Jacobi pass that reads group 0's values before
+      // they are scattered (k_irr_jac_sl2)
+      const int64_t nxv = L.N + L.N2;
+      if (L.cls_ptr.size() == 3 && gptr[1] > gptr[0] && gptr[2] > gptr[1] && nxv + gptr[1] < (int64_t)INT32_MAX) {
+        std::unordered_map<int64_t, int32_t> pos0;
+        pos0.reserve((size_t)(gptr[1] - gptr[0]) * 2);
+        for (int32_t k = gptr[0]; k < gptr[1]; ++k) pos0.emplace(idof[k], k - gptr[0]);
+        std::vector<int32_t> scolj(scol);
+        for (int64_t e = sptr[d.sl_grp[1]]; e < sptr[d.sl_grp[2]]; ++e) {
+          const auto it = pos0.find(scolj[e]);
+          if (it != pos0.end()) scolj[e] = (int32_t)(nxv + it->second);
+        }
+        d.sl_colj.upload(scolj.data(), (int64_t)scolj.size(), s, by);
+      }
       d.sl_val64.upload(sval.data(), (int64_t)sval.size(), s, by);
       if (mixed) {
         std::vector<float> v(sval.begin(), sval.end());
@@ -1053,6 +1069,31 @@ static void irr_group(DevLevel& l, int grp, T* x, const T* b, hipStream_t s) {
 
 // xz: x is zero on entry (a V-cycle level's correction); used by the
 // z-marching sweep, whose first sweep then does not read x
+// Both groups' Jacobi passes with one scatter: group 0 into w[0, n0), group 1
+// into w[n0, R) reading group 0's values from w, then every row into x
+// (the same values as irr_group(0) then irr_group(1)).
+template <typename T>
+static void irr_groups(DevLevel& l, T* x, const T* b, hipStream_t s) {
+  const int n0 = l.cls_ptr.size() == 3 ? l.cls_ptr[1] - l.cls_ptr[0] : 0;
+  const int n1 = l.cls_ptr.size() == 3 ? l.cls_ptr[2] - l.cls_ptr[1] : 0;
+  if (!l.sl_colj.p || !Vec<T>::sval(l) || n0 <= 0 || n1 <= 0) {
+    irr_group<T>(l, 0, x, b, s);
+    irr_group<T>(l, 1, x, b, s);
+    return;
+  }
+  T* w = Vec<T>::tmp(l);
+  const BLev<T> L0 = make_blev<T>(l);
+  hipLaunchKernelGGL((k_irr_jac_sl<T>), dim3((unsigned)((n0 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, L0, 0, x,
+                     b);
+  BLev<T> L1 = L0;
+  L1.sl_col = l.sl_colj.p;
+  L1.w = w + n0;
+  hipLaunchKernelGGL((k_irr_jac_sl2<T>), dim3((unsigned)((n1 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, L1, x, b,
+                     (const T*)w, (int)(l.N + l.N2));
+  hipLaunchKernelGGL((k_irr_scatter<T>), dim3(nblk(n0 + n1)), dim3(kBlock), 0, s, l.cls_rows.p + l.cls_ptr[0],
+                     n0 + n1, l.irow_dof.p, w, x);
+}
+
 template <typename T>
 static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s, bool xz) {
   const Tmpl<T>& tp = Vec<T>::t(l);
@@ -1064,8 +1105,7 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s, boo
     for (int it = 0; it < sweeps; ++it) {
       launch_fused<T>(l, cur, alt, b, tp, s, xz && it == 0);
       std::swap(cur, alt);
-      irr_group<T>(l, 0, cur, b, s);
-      irr_group<T>(l, 1, cur, b, s);
+      irr_groups<T>(l, cur, b, s);
     }
     if (cur != x)
       hipLaunchKernelGGL((k_convert<T, T>), dim3(nblk(l.N + l.N2)), dim3(kBlock), 0, s, cur, x, l.N + l.N2);

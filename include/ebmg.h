@@ -291,8 +291,9 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
  * kernel (which = 0: the fused sweep, or each colour phase / half-sweep where
  * the level uses those; not the first z-marching sweep of a V-cycle, which
  * starts from x = 0 and does not read it) or of its FP64 residual kernel (which = 1: the
- * template-cell kernel of every FP64 r = b - A x on that level: the solve's
- * residual checks, and the V-cycle residuals of FP64 problems): each such
+ * template-cell kernel of the solve's FP64 r = b - A x checks on that level;
+ * a V-cycle forms its residual inside the restriction on large 3D levels,
+ * elsewhere with the same kernel, then timed as well): each such
  * launch carries a HIP event pair that its dispatch stamps with the
  * kernel's own start and end (extended launch); while any timing is on,
  * those solves launch their kernels directly instead of replaying graphs (the same

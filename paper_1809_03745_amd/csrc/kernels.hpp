@@ -966,6 +966,115 @@ __global__ void __launch_bounds__(kRZX * kRZY) k_resid_zm3(const uint8_t* __rest
     block_partials<kRZX * kRZY>(d0, d1, NDOT, part, pt, blockIdx.x, tid);
 }
 
+// Residual r = b - A x of a 3D level restricted straight into the coarse
+// right-hand side, for the simple coarse cells (the mean of the 8 children,
+// summed in the order of k_restrict_all, with the residual of each template
+// child computed as in k_resid_zm3): r itself is written only where a later
+// step reads it, for the children of non-simple coarse unknowns (restricted
+// from their child lists afterwards); the explicit-row children's r must be
+// in place before (it is read here); covered coarse cells get 0. A wavefront
+// holds a 32 x 2 patch of a plane (lanes 0-31 and 32-63 are neighbouring
+// rows), so a 2 x 2 group of children is summed by lane shuffles and two
+// consecutive planes by one thread; each thread walks kRRZ planes with one
+// plane requested ahead. Needs even extents (the coarse level is half the
+// fine one in every direction).
+constexpr int kRRX = 32, kRRW = 4, kRRZ = 16;   // tile: 32 x (2 kRRW) columns over kRRZ planes
+
+template <typename T>
+__global__ void __launch_bounds__(64 * kRRW) k_resid_restrict3(const uint8_t* __restrict__ tag,
+                                                               const T* __restrict__ x, const T* __restrict__ b,
+                                                               T* __restrict__ r, const uint8_t* __restrict__ ctag,
+                                                               T* __restrict__ bc, Tmpl<T> tp) {
+  __shared__ T TC[2][8];
+  const int tid = threadIdx.x + 64 * threadIdx.y;
+  if (tid < 16) {
+    const int p = tid >> 3, j = tid & 7;
+    TC[p][j] = j == 0 ? tp.coff[p] : (j == 1 ? tp.d0[p] : tp.cb[j - 2][p]);
+  }
+  __syncthreads();
+  const int nx = tp.n[0], ny = tp.n[1], nz = tp.n[2];
+  const int cnx = nx >> 1, cny = ny >> 1;
+  const int gbx = (nx + kRRX - 1) / kRRX, gby = (ny + 2 * kRRW - 1) / (2 * kRRW);
+  const int64_t tt = xcd_block(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x;
+  const int i = (int)(tt % gbx) * kRRX + (lane & 31);
+  const int j = (int)((tt / gbx) % gby) * (2 * kRRW) + 2 * threadIdx.y + (lane >> 5);
+  const int z0 = (int)(tt / ((int64_t)gbx * gby)) * kRRZ, z1 = min(z0 + kRRZ, nz);
+  // lanes past the box edge load a valid cell, take part in the shuffles and
+  // write nothing (extents are even, so a 2 x 2 group is all in or all out)
+  const bool act = i < nx && j < ny;
+  const int ic = act ? i : 0, jc = act ? j : 0;
+  const bool lead = act && (lane & 1) == 0 && lane < 32;
+  const int64_t sxy = (int64_t)nx * ny;
+  const int64_t c0 = ic + (int64_t)nx * jc;
+  const int64_t ow = ic > 0 ? -1 : 0, oe = ic < nx - 1 ? 1 : 0;
+  const int64_t os = jc > 0 ? -(int64_t)nx : 0, on = jc < ny - 1 ? (int64_t)nx : 0;
+  const int64_t P0 = (ic >> 1) + (int64_t)cnx * (jc >> 1);
+  const int64_t csxy = (int64_t)cnx * cny;
+  T xm = z0 > 0 ? x[c0 + sxy * (z0 - 1)] : T(0);
+  int64_t c = c0 + sxy * z0;
+  T xc = x[c];
+  T xp = z0 + 1 < nz ? x[c + sxy] : T(0);
+  T w = x[c + ow], e = x[c + oe], so = x[c + os], no = x[c + on];
+  uint8_t tg = tag[c];
+  T bb = b[c];
+  uint8_t ct = ctag[P0 + csxy * (z0 >> 1)];
+  T acc = 0;
+  for (int k = z0; k < z1; ++k, c += sxy) {
+    const bool more = k + 1 < z1;
+    const int64_t cn = more ? c + sxy : c;
+    const T xpp = k + 2 < nz ? x[c + 2 * sxy] : T(0);
+    const T wn = x[cn + ow], en = x[cn + oe], son = x[cn + os], non = x[cn + on];
+    const uint8_t tgn = more ? tag[cn] : (uint8_t)3;
+    const T bbn = more ? b[cn] : T(0);
+    const uint8_t ctn = more ? ctag[P0 + csxy * ((k + 1) >> 1)] : (uint8_t)3;
+    const int p = tclass(tg);
+    T out;
+    if (p == 2) {
+      out = r[c];   // an explicit row: its residual is already there
+    } else if (p == 3) {
+      out = T(0);
+    } else {
+      const T* tc = TC[p];
+      T s = 0, dg = tc[1];
+      if (ic > 0) s += w; else dg += tc[2];
+      if (ic < nx - 1) s += e; else dg += tc[3];
+      if (jc > 0) s += so; else dg += tc[4];
+      if (jc < ny - 1) s += no; else dg += tc[5];
+      if (k > 0) s += xm; else dg += tc[6];
+      if (k < nz - 1) s += xp; else dg += tc[7];
+      const T ax = dg * xc + tc[0] * s;
+      out = bb - ax;
+    }
+    // the children of a non-simple coarse unknown keep their residual for
+    // the list restriction that follows
+    if (act && p != 2 && (ct & 4) && tclass(ct) != 3) r[c] = out;
+    const T v10 = __shfl_xor(out, 1, 64), v01 = __shfl_xor(out, 32, 64), v11 = __shfl_xor(out, 33, 64);
+    if (lead) {
+      const T pk = ((out + v10) + v01) + v11;
+      if ((k & 1) == 0) {
+        acc = pk;
+      } else {
+        const int64_t P = P0 + csxy * (k >> 1);
+        if (tclass(ct) == 3)
+          bc[P] = T(0);
+        else if (!(ct & 4))
+          bc[P] = (acc + pk) * T(0.125);
+      }
+    }
+    xm = xc;
+    xc = xp;
+    xp = xpp;
+    w = wn;
+    e = en;
+    so = son;
+    no = non;
+    tg = tgn;
+    bb = bbn;
+    ct = (k & 1) ? ctn : ct;
+  }
+}
+
 // The same residual / matrix-vector product with two neighbouring cells per
 // lane (x even): x, b, r and the dot vector move as 2-element vectors and the
 // tags as one 16-bit word, so a wavefront issues half the memory instructions

@@ -1137,6 +1137,20 @@ static void smooth(DevLevel& l, T* x, const T* b, int sweeps, hipStream_t s, boo
   HIPCHECK(hipGetLastError());
 }
 
+// Explicit rows of r = b - A x (MODE 0) or A x (MODE 1) on a large level.
+template <typename T, int MODE>
+static void residual_rows(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
+  if (l.R > 0 && l.sl_ptr.p && Vec<T>::sval(l)) {
+    const BLev<T> L = make_blev<T>(l);
+    const int nb0 = (L.grp_ptr[1] - L.grp_ptr[0] + kBlock - 1) / kBlock;
+    const int nb1 = (L.grp_ptr[2] - L.grp_ptr[1] + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL((k_resid_irr_sl<T, MODE>), dim3((unsigned)(nb0 + nb1)), dim3(kBlock), 0, s, L, nb0, x, b, r);
+  } else if (l.R > 0) {
+    hipLaunchKernelGGL((k_resid_irr<T, MODE>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R, l.irow_dof.p,
+                       l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, r);
+  }
+}
+
 template <typename T, int MODE>
 static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
@@ -1148,16 +1162,7 @@ static void residual(DevLevel& l, const T* x, const T* b, T* r, hipStream_t s) {
     else
       KLAUNCH(kr, (k_resid_zm3<T, MODE>), dim3((unsigned)zm_resid_blocks(l)), dim3(kRZX, kRZY), 0, s, l.tag.p, x, b,
               r, tp, (const T*)nullptr, (double*)nullptr, (int64_t)0);
-    if (l.R > 0 && l.sl_ptr.p && Vec<T>::sval(l)) {
-      const BLev<T> L = make_blev<T>(l);
-      const int nb0 = (L.grp_ptr[1] - L.grp_ptr[0] + kBlock - 1) / kBlock;
-      const int nb1 = (L.grp_ptr[2] - L.grp_ptr[1] + kBlock - 1) / kBlock;
-      hipLaunchKernelGGL((k_resid_irr_sl<T, MODE>), dim3((unsigned)(nb0 + nb1)), dim3(kBlock), 0, s, L, nb0, x, b,
-                         r);
-    } else if (l.R > 0) {
-      hipLaunchKernelGGL((k_resid_irr<T, MODE>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R, l.irow_dof.p,
-                         l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, r);
-    }
+    residual_rows<T, MODE>(l, x, b, r, s);
   } else {
     // small levels: template cells and explicit rows in one launch
     const unsigned nbc = nblk(l.N);
@@ -1185,6 +1190,35 @@ static void restrict_to(DevLevel& f, DevLevel& c, const T* rf, T* bc, T* xc, hip
   else
     hipLaunchKernelGGL((k_restrict_all<T, 2>), g, dim3(kBlock), 0, s, c.tag.p, rf, bc, xc, c.n[0], c.n[1], 1, nbc,
                        nbn, (int)f.n_ns, f.ns_cdof.p, f.ns_ptr.p, f.ns_child.p, ncd);
+  HIPCHECK(hipGetLastError());
+}
+
+// The V-cycle's residual of level f restricted into level c's b, clearing c's
+// x: on large 3D levels one kernel restricts the residual straight into the
+// simple coarse cells (r is kept only for the children of the non-simple
+// coarse unknowns, whose lists are restricted next, with the clear);
+// elsewhere r is formed and restricted as separate steps. The same values
+// either way.
+template <typename T>
+static void residual_restrict(DevLevel& f, DevLevel& c, const T* x, const T* b, hipStream_t s) {
+  T* r = Vec<T>::r(f);
+  const bool fuse = f.dim == 3 && f.N >= kResidZMMin && f.n[0] % 2 == 0 && f.n[1] % 2 == 0 && f.n[2] % 2 == 0 &&
+                    c.n[0] * 2 == f.n[0] && c.n[1] * 2 == f.n[1] && c.n[2] * 2 == f.n[2];
+  if (!fuse) {
+    residual<T, 0>(f, x, b, r, s);
+    restrict_to<T>(f, c, r, Vec<T>::b(c), Vec<T>::x(c), s);
+    return;
+  }
+  residual_rows<T, 0>(f, x, b, r, s);   // the explicit rows' r, read by the fused kernel
+  const int64_t nb = (int64_t)((f.n[0] + kRRX - 1) / kRRX) * ((f.n[1] + 2 * kRRW - 1) / (2 * kRRW)) *
+                     ((f.n[2] + kRRZ - 1) / kRRZ);
+  hipLaunchKernelGGL((k_resid_restrict3<T>), dim3((unsigned)nb), dim3(64, kRRW), 0, s, f.tag.p, x, b, r, c.tag.p,
+                     Vec<T>::b(c), Vec<T>::t(f));
+  const unsigned nbn = nblk(f.n_ns);
+  const int64_t ncd = c.N + c.N2;
+  hipLaunchKernelGGL((k_restrict_all<T, 3>), dim3(nbn + nblk(ncd)), dim3(kBlock), 0, s, c.tag.p, r, Vec<T>::b(c),
+                     Vec<T>::x(c), c.n[0], c.n[1], c.n[2], 0u, nbn, (int)f.n_ns, f.ns_cdof.p, f.ns_ptr.p, f.ns_child.p,
+                     ncd);
   HIPCHECK(hipGetLastError());
 }
 
@@ -1258,9 +1292,7 @@ static void vcycle(DevProblem& D, const Options& o, size_t l, hipStream_t s, T* 
   }
   DevLevel& C = D.lv[l + 1];
   smooth<T>(L, x, b, o.nu1, s, xz);
-  T* r = Vec<T>::r(L);
-  residual<T, 0>(L, x, b, r, s);
-  restrict_to<T>(L, C, r, Vec<T>::b(C), Vec<T>::x(C), s);   // also clears the coarse x
+  residual_restrict<T>(L, C, x, b, s);   // also clears the coarse x
   vcycle<T>(D, o, l + 1, s, Vec<T>::x(C), Vec<T>::b(C), true);
   prolong_from<T>(L, C, Vec<T>::x(C), x, s);
   smooth<T>(L, x, b, o.nu2, s);

@@ -404,8 +404,9 @@ static bool fused_ok(const DevLevel& l) {
 
 // z-marching sweep configurations (tile width x height x planes per block);
 // the setup autotuner picks one per level
-constexpr int kZMConfigs = 10;   // 7..9: wide-fetch versions of 1, 4, 6 (x extent a multiple of 4)
-static bool zm_cfg_ok(const DevLevel& l, int c) { return c < 7 || l.n[0] % 4 == 0; }
+constexpr int kZMConfigs = 11;   // 7..9: wide-fetch versions of 1, 4, 6 (x extent a multiple of 4);
+                                  // 10: 64x16 over 8 planes (enough blocks on mid-size levels)
+static bool zm_cfg_ok(const DevLevel& l, int c) { return c < 7 || c > 9 || l.n[0] % 4 == 0; }
 
 // zin: x is zero on entry, so the sweep need not read it (not timed by the
 // in-solve hook: it moves fewer bytes than a full sweep)
@@ -435,6 +436,7 @@ static void launch_zm(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl
     case 7: launch_zm_cfg<T, 64, 16, 32, true>(l, xin, xout, b, tp, s, zin); break;
     case 8: launch_zm_cfg<T, 128, 8, 32, true>(l, xin, xout, b, tp, s, zin); break;
     case 9: launch_zm_cfg<T, 32, 32, 32, true>(l, xin, xout, b, tp, s, zin); break;
+    case 10: launch_zm_cfg<T, 64, 16, 8>(l, xin, xout, b, tp, s, zin); break;
     default: launch_zm_cfg<T, 64, 8, 32>(l, xin, xout, b, tp, s, zin); break;
   }
 }

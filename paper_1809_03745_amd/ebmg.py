@@ -403,7 +403,8 @@ class Problem:
 
 # z-marching smoother tiles (x, y, planes, wide fetch), in the library's configuration order
 ZM_TILES = [(64, 8, 32, False), (64, 16, 32, False), (32, 16, 32, False), (64, 8, 16, False), (128, 8, 32, False),
-            (32, 8, 32, False), (32, 32, 32, False), (64, 16, 32, True), (128, 8, 32, True), (32, 32, 32, True)]
+            (32, 8, 32, False), (32, 32, 32, False), (64, 16, 32, True), (128, 8, 32, True), (32, 32, 32, True),
+            (64, 16, 8, False)]
 OOP_VARIANT = 2 + len(ZM_TILES)      # tuning code of the one-launch colour phases
 SMOOTH_OOP = 3 + len(ZM_TILES)       # ebmg_smooth variant of the one-launch colour phases
 

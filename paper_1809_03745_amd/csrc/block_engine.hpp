@@ -386,12 +386,56 @@ __device__ void be_resid(const BLev<T>& L, const T* __restrict__ x, const T* __r
 }
 
 // Grid-wide forms of the explicit-row phases over the sliced copy, for one
-// level passed by value: kBlock rows (kBlock / kSlice slices) per block.
-// Jacobi values of group grp into L.w, as be_irr_jac_part.
+// level passed by value. A launch has few rows per CU, so each 64-row slice
+// is split over two wavefronts along its entries (halving the chain of
+// dependent loads a row waits on): block blk takes slices 2 blk and 2 blk + 1
+// of the group with its four wavefronts; the second wavefront of a slice sums
+// the entries from the middle (a batch boundary) on and hands its partial
+// sums over LDS, and the first finishes the rows with f(g, pre, first half +
+// second half). The sums therefore differ in rounding from the one-wavefront
+// parts of the engine, and the grid-wide kernels agree only with each other.
+constexpr int kSplitRows = kBlock / 2;   // rows per block
+
+template <typename T, typename TX, bool TWO, typename Pre, typename F>
+__device__ __forceinline__ void split_rows(const BLev<T>& L, int grp, const TX* __restrict__ x, int blk, Pre&& pre,
+                                           F&& f, const TX* __restrict__ x2 = nullptr, int nx = 0) {
+  __shared__ T part[kBlock / kSlice / 2][kSlice];
+  const int r0 = L.grp_ptr[grp];
+  const int n = L.grp_ptr[grp + 1] - r0;
+  const int lane = threadIdx.x & (kSlice - 1), wave = threadIdx.x / kSlice;
+  const int half = wave & 1, slot = wave >> 1;
+  const int s0 = (2 * blk + slot) * kSlice;   // the slice's first row (group-relative)
+  const bool have = s0 < n;
+  const int g = s0 + lane;
+  const bool in = have && g < n;
+  T sm = T(0);
+  auto own = pre(r0 + (in ? g : 0));
+  if (have) {
+    const int sl = L.sl_grp[grp] + s0 / kSlice;
+    const int64_t p0 = L.sl_ptr[sl];
+    const int len = (int)((L.sl_ptr[sl + 1] - p0) / kSlice);
+    const int mid = min(len, (len / 2 + kRowJ - 1) / kRowJ * kRowJ);
+    const int j0 = half ? mid : 0, j1 = half ? len : mid;
+    sm = sliced_row<T, TX, TWO>(L.sl_col, L.sl_val, x, p0 + lane + (int64_t)j0 * kSlice, j1 - j0, x2, nx);
+    if (half) part[slot][lane] = sm;
+  }
+  __syncthreads();
+  if (in && !half) f(r0 + g, own, sm + part[slot][lane]);
+}
+
+// Jacobi values of group grp's rows into L.w (rows relative to the group).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_irr_jac_sl(BLev<T> L, int grp, const T* __restrict__ x,
                                                        const T* __restrict__ b) {
-  be_irr_jac_part<T>(L, grp, x, b, (int)blockIdx.x * kBlock, kBlock);
+  FP_EXACT_ORDER
+  const int r0 = L.grp_ptr[grp];
+  split_rows<T, T, false>(
+      L, grp, x, (int)blockIdx.x,
+      [&](int g) {
+        const int64_t q = L.irow_dof[g];
+        return RowOwn<T>{q, L.diag[g], b[q]};
+      },
+      [&](int g, const RowOwn<T>& o, T sm) { L.w[g - r0] = (o.v - sm) / o.d; });
 }
 
 // Jacobi values of group 1 while group 0's new values are still in w0 (not
@@ -402,22 +446,44 @@ __global__ void __launch_bounds__(kBlock) k_irr_jac_sl(BLev<T> L, int grp, const
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_irr_jac_sl2(BLev<T> L, const T* __restrict__ x,
                                                         const T* __restrict__ b, const T* __restrict__ w0, int nx) {
-  be_irr_jac_part<T, true>(L, 1, x, b, (int)blockIdx.x * kBlock, kBlock, w0, nx);
+  FP_EXACT_ORDER
+  const int r0 = L.grp_ptr[1];
+  split_rows<T, T, true>(
+      L, 1, x, (int)blockIdx.x,
+      [&](int g) {
+        const int64_t q = L.irow_dof[g];
+        return RowOwn<T>{q, L.diag[g], b[q]};
+      },
+      [&](int g, const RowOwn<T>& o, T sm) { L.w[g - r0] = (o.v - sm) / o.d; }, w0, nx);
 }
 
 // r = b - A x (MODE 0) or A x (MODE 1) on the explicit rows: blocks [0, nb0)
-// take group 0, the rest group 1. x may be narrower than T; NDOT as in
-// be_resid_rows_part, with one partial per block at part[d * pt + boff + block].
+// take group 0, the rest group 1 (kSplitRows rows per block). x may be
+// narrower than T; NDOT >= 1 adds da[q] * r[q] and NDOT == 2 also r[q]^2 over
+// the rows, one partial per block at part[d * pt + boff + block].
 template <typename T, int MODE, typename TX = T, int NDOT = 0>
 __global__ void __launch_bounds__(kBlock) k_resid_irr_sl(BLev<T> L, int nb0, const TX* __restrict__ x,
                                                          const T* __restrict__ b, T* __restrict__ r,
                                                          const double* __restrict__ da = nullptr,
                                                          double* __restrict__ part = nullptr, int64_t pt = 0,
                                                          int64_t boff = 0) {
+  FP_EXACT_ORDER
   double a0 = 0, a1 = 0;
-  const int g = (int)blockIdx.x < nb0 ? 0 : 1;
-  const int blk = g == 0 ? (int)blockIdx.x : (int)blockIdx.x - nb0;
-  be_resid_rows_part<T, TX, MODE, NDOT>(L, g, x, b, r, blk * kBlock, kBlock, da, a0, a1);
+  const int grp = (int)blockIdx.x < nb0 ? 0 : 1;
+  const int blk = grp == 0 ? (int)blockIdx.x : (int)blockIdx.x - nb0;
+  split_rows<T, TX, false>(
+      L, grp, x, blk,
+      [&](int g) {
+        const int64_t q = L.irow_dof[g];
+        return RowOwn<T>{q, L.diag[g], (T)x[q]};
+      },
+      [&](int g, const RowOwn<T>& w, T sm) {
+        const T ax = w.d * w.v + sm;
+        const T o = MODE == 0 ? b[w.q] - ax : ax;
+        r[w.q] = o;
+        if (NDOT >= 1) a0 += da[w.q] * (double)o;
+        if (NDOT == 2) a1 += (double)o * (double)o;
+      });
   if (NDOT > 0) block_partials<kBlock>(a0, a1, NDOT, part, pt, boff + blockIdx.x, threadIdx.x);
 }
 

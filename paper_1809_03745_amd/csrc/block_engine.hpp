@@ -387,24 +387,27 @@ __device__ void be_resid(const BLev<T>& L, const T* __restrict__ x, const T* __r
 
 // Grid-wide forms of the explicit-row phases over the sliced copy, for one
 // level passed by value. A launch has few rows per CU, so each 64-row slice
-// is split over two wavefronts along its entries (halving the chain of
-// dependent loads a row waits on): block blk takes slices 2 blk and 2 blk + 1
-// of the group with its four wavefronts; the second wavefront of a slice sums
-// the entries from the middle (a batch boundary) on and hands its partial
-// sums over LDS, and the first finishes the rows with f(g, pre, first half +
-// second half). The sums therefore differ in rounding from the one-wavefront
-// parts of the engine, and the grid-wide kernels agree only with each other.
-constexpr int kSplitRows = kBlock / 2;   // rows per block
+// is split over kRowSplit wavefronts along its entries (cutting the chain of
+// dependent loads a row waits on; 4 beat 2 by 3 % and 8 by 4 % of a 256^3
+// solve): block blk takes slice blk of the group, wavefront q sums the q-th
+// run of entries (whole batches of kRowJ) and hands its partial sums over
+// LDS, and the first finishes the rows with f(g, pre, s0 + s1 + s2 + s3).
+// The sums therefore differ in rounding from the one-wavefront parts of the
+// engine, and the grid-wide kernels agree only with each other.
+constexpr int kRowSplit = 4;                    // wavefronts per slice
+constexpr int kRowBlock = kSlice * kRowSplit;   // threads per block: one slice per block
+constexpr int kSplitRows = kSlice;              // rows per block
 
 template <typename T, typename TX, bool TWO, typename Pre, typename F>
 __device__ __forceinline__ void split_rows(const BLev<T>& L, int grp, const TX* __restrict__ x, int blk, Pre&& pre,
                                            F&& f, const TX* __restrict__ x2 = nullptr, int nx = 0) {
-  __shared__ T part[kBlock / kSlice / 2][kSlice];
+  constexpr int S = kRowSplit, SPB = kRowBlock / kSlice / S;   // slices per block
+  __shared__ T part[SPB][S][kSlice];
   const int r0 = L.grp_ptr[grp];
   const int n = L.grp_ptr[grp + 1] - r0;
   const int lane = threadIdx.x & (kSlice - 1), wave = threadIdx.x / kSlice;
-  const int half = wave & 1, slot = wave >> 1;
-  const int s0 = (2 * blk + slot) * kSlice;   // the slice's first row (group-relative)
+  const int q = wave % S, slot = wave / S;
+  const int s0 = (SPB * blk + slot) * kSlice;   // the slice's first row (group-relative)
   const bool have = s0 < n;
   const int g = s0 + lane;
   const bool in = have && g < n;
@@ -414,18 +417,22 @@ __device__ __forceinline__ void split_rows(const BLev<T>& L, int grp, const TX* 
     const int sl = L.sl_grp[grp] + s0 / kSlice;
     const int64_t p0 = L.sl_ptr[sl];
     const int len = (int)((L.sl_ptr[sl + 1] - p0) / kSlice);
-    const int mid = min(len, (len / 2 + kRowJ - 1) / kRowJ * kRowJ);
-    const int j0 = half ? mid : 0, j1 = half ? len : mid;
+    const int chunk = ((len + S - 1) / S + kRowJ - 1) / kRowJ * kRowJ;
+    const int j0 = min(len, q * chunk), j1 = min(len, (q + 1) * chunk);
     sm = sliced_row<T, TX, TWO>(L.sl_col, L.sl_val, x, p0 + lane + (int64_t)j0 * kSlice, j1 - j0, x2, nx);
-    if (half) part[slot][lane] = sm;
+    if (q > 0) part[slot][q][lane] = sm;
   }
   __syncthreads();
-  if (in && !half) f(r0 + g, own, sm + part[slot][lane]);
+  if (in && q == 0) {
+#pragma unroll
+    for (int k = 1; k < S; ++k) sm = sm + part[slot][k][lane];
+    f(r0 + g, own, sm);
+  }
 }
 
 // Jacobi values of group grp's rows into L.w (rows relative to the group).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_irr_jac_sl(BLev<T> L, int grp, const T* __restrict__ x,
+__global__ void __launch_bounds__(kRowBlock) k_irr_jac_sl(BLev<T> L, int grp, const T* __restrict__ x,
                                                        const T* __restrict__ b) {
   FP_EXACT_ORDER
   const int r0 = L.grp_ptr[grp];
@@ -444,7 +451,7 @@ __global__ void __launch_bounds__(kBlock) k_irr_jac_sl(BLev<T> L, int grp, const
 // and L.w points where group 1's values go. The same values as scattering
 // group 0 first and then running k_irr_jac_sl on group 1.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_irr_jac_sl2(BLev<T> L, const T* __restrict__ x,
+__global__ void __launch_bounds__(kRowBlock) k_irr_jac_sl2(BLev<T> L, const T* __restrict__ x,
                                                         const T* __restrict__ b, const T* __restrict__ w0, int nx) {
   FP_EXACT_ORDER
   const int r0 = L.grp_ptr[1];
@@ -462,7 +469,7 @@ __global__ void __launch_bounds__(kBlock) k_irr_jac_sl2(BLev<T> L, const T* __re
 // narrower than T; NDOT >= 1 adds da[q] * r[q] and NDOT == 2 also r[q]^2 over
 // the rows, one partial per block at part[d * pt + boff + block].
 template <typename T, int MODE, typename TX = T, int NDOT = 0>
-__global__ void __launch_bounds__(kBlock) k_resid_irr_sl(BLev<T> L, int nb0, const TX* __restrict__ x,
+__global__ void __launch_bounds__(kRowBlock) k_resid_irr_sl(BLev<T> L, int nb0, const TX* __restrict__ x,
                                                          const T* __restrict__ b, T* __restrict__ r,
                                                          const double* __restrict__ da = nullptr,
                                                          double* __restrict__ part = nullptr, int64_t pt = 0,
@@ -484,7 +491,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_irr_sl(BLev<T> L, int nb0, con
         if (NDOT >= 1) a0 += da[w.q] * (double)o;
         if (NDOT == 2) a1 += (double)o * (double)o;
       });
-  if (NDOT > 0) block_partials<kBlock>(a0, a1, NDOT, part, pt, boff + blockIdx.x, threadIdx.x);
+  if (NDOT > 0) block_partials<kRowBlock>(a0, a1, NDOT, part, pt, boff + blockIdx.x, threadIdx.x);
 }
 
 // Restriction of rf into the coarse b over coarse cells [beg, beg + cnt);

@@ -1061,7 +1061,7 @@ static void irr_group(DevLevel& l, int grp, T* x, const T* b, hipStream_t s) {
   const int32_t* rows = l.cls_rows.p + l.cls_ptr[grp];
   T* tmp = Vec<T>::tmp(l);
   if (l.sl_ptr.p && Vec<T>::sval(l))
-    hipLaunchKernelGGL((k_irr_jac_sl<T>), dim3((unsigned)((nr + kSplitRows - 1) / kSplitRows)), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((k_irr_jac_sl<T>), dim3((unsigned)((nr + kSplitRows - 1) / kSplitRows)), dim3(kRowBlock), 0, s,
                        make_blev<T>(l), grp, x, b);
   else
     hipLaunchKernelGGL((k_irr_jacobi<T>), dim3(nblk_sub(nr)), dim3(kBlock), 0, s, rows, nr, l.irow_dof.p, l.rp.p,
@@ -1085,12 +1085,12 @@ static void irr_groups(DevLevel& l, T* x, const T* b, hipStream_t s) {
   }
   T* w = Vec<T>::tmp(l);
   const BLev<T> L0 = make_blev<T>(l);
-  hipLaunchKernelGGL((k_irr_jac_sl<T>), dim3((unsigned)((n0 + kSplitRows - 1) / kSplitRows)), dim3(kBlock), 0, s, L0, 0, x,
+  hipLaunchKernelGGL((k_irr_jac_sl<T>), dim3((unsigned)((n0 + kSplitRows - 1) / kSplitRows)), dim3(kRowBlock), 0, s, L0, 0, x,
                      b);
   BLev<T> L1 = L0;
   L1.sl_col = l.sl_colj.p;
   L1.w = w + n0;
-  hipLaunchKernelGGL((k_irr_jac_sl2<T>), dim3((unsigned)((n1 + kSplitRows - 1) / kSplitRows)), dim3(kBlock), 0, s, L1, x, b,
+  hipLaunchKernelGGL((k_irr_jac_sl2<T>), dim3((unsigned)((n1 + kSplitRows - 1) / kSplitRows)), dim3(kRowBlock), 0, s, L1, x, b,
                      (const T*)w, (int)(l.N + l.N2));
   hipLaunchKernelGGL((k_irr_scatter<T>), dim3(nblk(n0 + n1)), dim3(kBlock), 0, s, l.cls_rows.p + l.cls_ptr[0],
                      n0 + n1, l.irow_dof.p, w, x);
@@ -1146,7 +1146,7 @@ static void residual_rows(DevLevel& l, const T* x, const T* b, T* r, hipStream_t
     const BLev<T> L = make_blev<T>(l);
     const int nb0 = (L.grp_ptr[1] - L.grp_ptr[0] + kSplitRows - 1) / kSplitRows;
     const int nb1 = (L.grp_ptr[2] - L.grp_ptr[1] + kSplitRows - 1) / kSplitRows;
-    hipLaunchKernelGGL((k_resid_irr_sl<T, MODE>), dim3((unsigned)(nb0 + nb1)), dim3(kBlock), 0, s, L, nb0, x, b, r);
+    hipLaunchKernelGGL((k_resid_irr_sl<T, MODE>), dim3((unsigned)(nb0 + nb1)), dim3(kRowBlock), 0, s, L, nb0, x, b, r);
   } else if (l.R > 0) {
     hipLaunchKernelGGL((k_resid_irr<T, MODE>), dim3(nblk_sub(l.R)), dim3(kBlock), 0, s, (int)l.R, l.irow_dof.p,
                        l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l), x, b, r);
@@ -1466,10 +1466,10 @@ static void matvec_dots(DevProblem& D, const Z* x, double* out, const double* da
     if (sl) {
       const BLev<double> L = make_blev<double>(l);
       if (ndot == 1)
-        hipLaunchKernelGGL((k_resid_irr_sl<double, 1, Z, 1>), dim3((unsigned)(nb0 + nb1)), dim3(kBlock), 0, s, L, nb0,
+        hipLaunchKernelGGL((k_resid_irr_sl<double, 1, Z, 1>), dim3((unsigned)(nb0 + nb1)), dim3(kRowBlock), 0, s, L, nb0,
                            x, nullptr, out, da, D.part.p, pt, G);
       else
-        hipLaunchKernelGGL((k_resid_irr_sl<double, 1, Z, 2>), dim3((unsigned)(nb0 + nb1)), dim3(kBlock), 0, s, L, nb0,
+        hipLaunchKernelGGL((k_resid_irr_sl<double, 1, Z, 2>), dim3((unsigned)(nb0 + nb1)), dim3(kRowBlock), 0, s, L, nb0,
                            x, nullptr, out, da, D.part.p, pt, G);
     } else if (l.R > 0) {
       if (ndot == 1)

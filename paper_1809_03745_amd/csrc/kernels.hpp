@@ -776,7 +776,10 @@ __global__ void __launch_bounds__(kBlock) k_irr_scatter(const int32_t* __restric
 // rows_upd are updated, rows_cp copied. Explicit rows therefore see only the
 // values before the phase (Jacobi within a colour, as the grouped passes),
 // and a sweep costs two launches, which is what matters on small levels.
-template <typename T, int DIM>
+// With PAIR (nx even) a cell thread takes an even-odd pair along x, of which
+// exactly one cell has the phase's colour: half as many threads wait on the
+// same tag -> neighbours -> store chain, with the same arithmetic per cell.
+template <typename T, int DIM, bool PAIR>
 __global__ void __launch_bounds__(kBlock) k_rb_oop(const uint8_t* __restrict__ tag, const T* __restrict__ xin,
                                                    T* __restrict__ xout, const T* __restrict__ b, Tmpl<T> tp,
                                                    int colour, unsigned nbc, const int32_t* __restrict__ rows_upd,
@@ -787,6 +790,27 @@ __global__ void __launch_bounds__(kBlock) k_rb_oop(const uint8_t* __restrict__ t
   if (blockIdx.x < nbc) {
     const int nx = tp.n[0], ny = tp.n[1];
     const int64_t N = (int64_t)nx * ny * (DIM == 3 ? tp.n[2] : 1);
+    if (PAIR) {
+      const int64_t c = 2 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+      if (c >= N) return;
+      const int i = (int)(c % nx);
+      const int64_t jk = c / nx;
+      const int j = (int)(jk % ny);
+      const int k = DIM == 3 ? (int)(jk / ny) : 0;
+      const int u = ((i + j + k) & 1) == colour ? 0 : 1;   // the pair's cell of this colour
+      const uint8_t p0 = tclass(tag[c]), p1 = tclass(tag[c + 1]);
+      const T x0 = xin[c], x1 = xin[c + 1];
+      const uint8_t pu = u ? p1 : p0;
+      T vu = u ? x1 : x0;
+      if (pu <= 1) {
+        T dg;
+        const T off = template_apply<T, DIM>(xin, tp, i + u, j, k, c + u, pu, dg);
+        vu = (b[c + u] - off) * (T(1) / dg);
+      }
+      if (p0 != 2) xout[c] = u ? x0 : vu;
+      if (p1 != 2) xout[c + 1] = u ? vu : x1;
+      return;
+    }
     const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (c >= N) return;
     const uint8_t p = tclass(tag[c]);

@@ -1022,7 +1022,8 @@ static inline unsigned nblk_sub(int64_t rows) { return nblk(rows * kSub); }
 template <typename T>
 static void launch_oop(DevLevel& l, int colour, bool rows, const T* xin, T* xout, const T* b, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
-  const unsigned nbc = nblk(l.N);
+  const bool pair = tp.n[0] % 2 == 0;
+  const unsigned nbc = nblk(pair ? l.N / 2 : l.N);
   int n0 = 0, n1 = 0;
   const int32_t* g0 = l.cls_rows.p;
   const int32_t* g1 = l.cls_rows.p;
@@ -1045,12 +1046,15 @@ static void launch_oop(DevLevel& l, int colour, bool rows, const T* xin, T* xout
     nup = 0;
   }
   const unsigned nbr = nblk_sub((int64_t)nup + ncp);
-  if (l.dim == 3)
-    KLAUNCH(l.kt, (k_rb_oop<T, 3>), dim3(nbc + nbr), dim3(kBlock), 0, s, l.tag.p, xin, xout, b, tp, colour, nbc,
-                       up, nup, cp, ncp, l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l));
-  else
-    KLAUNCH(l.kt, (k_rb_oop<T, 2>), dim3(nbc + nbr), dim3(kBlock), 0, s, l.tag.p, xin, xout, b, tp, colour, nbc,
-                       up, nup, cp, ncp, l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l));
+#define OOP_LAUNCH(D, P)                                                                                     \
+  KLAUNCH(l.kt, (k_rb_oop<T, D, P>), dim3(nbc + nbr), dim3(kBlock), 0, s, l.tag.p, xin, xout, b, tp, colour, nbc, \
+          up, nup, cp, ncp, l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l))
+  if (l.dim == 3) {
+    if (pair) OOP_LAUNCH(3, true); else OOP_LAUNCH(3, false);
+  } else {
+    if (pair) OOP_LAUNCH(2, true); else OOP_LAUNCH(2, false);
+  }
+#undef OOP_LAUNCH
 }
 
 template <typename T>

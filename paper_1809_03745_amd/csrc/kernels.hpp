@@ -999,16 +999,17 @@ __global__ void __launch_bounds__(kRZX * kRZY) k_resid_zm3(const uint8_t* __rest
 // in place before (it is read here); covered coarse cells get 0. A wavefront
 // holds a 32 x 2 patch of a plane (lanes 0-31 and 32-63 are neighbouring
 // rows), so a 2 x 2 group of children is summed by lane shuffles and two
-// consecutive planes by one thread; each thread walks kRRZ planes with one
-// plane requested ahead. Needs even extents (the coarse level is half the
-// fine one in every direction).
-constexpr int kRRX = 32, kRRW = 4, kRRZ = 16;   // tile: 32 x (2 kRRW) columns over kRRZ planes
+// consecutive planes by one thread; each thread walks zc planes (even, at
+// most kRRZ; fewer on small levels so that the grid still fills the chip)
+// with one plane requested ahead. Needs even extents (the coarse level is
+// half the fine one in every direction).
+constexpr int kRRX = 32, kRRW = 4, kRRZ = 16;   // tile: 32 x (2 kRRW) columns over zc planes
 
 template <typename T>
 __global__ void __launch_bounds__(64 * kRRW) k_resid_restrict3(const uint8_t* __restrict__ tag,
                                                                const T* __restrict__ x, const T* __restrict__ b,
                                                                T* __restrict__ r, const uint8_t* __restrict__ ctag,
-                                                               T* __restrict__ bc, Tmpl<T> tp) {
+                                                               T* __restrict__ bc, Tmpl<T> tp, int zc) {
   __shared__ T TC[2][8];
   const int tid = threadIdx.x + 64 * threadIdx.y;
   if (tid < 16) {
@@ -1023,7 +1024,7 @@ __global__ void __launch_bounds__(64 * kRRW) k_resid_restrict3(const uint8_t* __
   const int lane = threadIdx.x;
   const int i = (int)(tt % gbx) * kRRX + (lane & 31);
   const int j = (int)((tt / gbx) % gby) * (2 * kRRW) + 2 * threadIdx.y + (lane >> 5);
-  const int z0 = (int)(tt / ((int64_t)gbx * gby)) * kRRZ, z1 = min(z0 + kRRZ, nz);
+  const int z0 = (int)(tt / ((int64_t)gbx * gby)) * zc, z1 = min(z0 + zc, nz);
   // lanes past the box edge load a valid cell, take part in the shuffles and
   // write nothing (extents are even, so a 2 x 2 group is all in or all out)
   const bool act = i < nx && j < ny;

@@ -1216,10 +1216,14 @@ static void residual_restrict(DevLevel& f, DevLevel& c, const T* x, const T* b, 
     return;
   }
   residual_rows<T, 0>(f, x, b, r, s);   // the explicit rows' r, read by the fused kernel
-  const int64_t nb = (int64_t)((f.n[0] + kRRX - 1) / kRRX) * ((f.n[1] + 2 * kRRW - 1) / (2 * kRRW)) *
-                     ((f.n[2] + kRRZ - 1) / kRRZ);
+  // planes per thread: kRRZ, halved (staying even) until the grid has 2048
+  // workgroups, eight per CU
+  const int64_t ncol = (int64_t)((f.n[0] + kRRX - 1) / kRRX) * ((f.n[1] + 2 * kRRW - 1) / (2 * kRRW));
+  int zc = kRRZ;
+  while (zc > 2 && ncol * ((f.n[2] + zc - 1) / zc) < 2048) zc /= 2;
+  const int64_t nb = ncol * ((f.n[2] + zc - 1) / zc);
   hipLaunchKernelGGL((k_resid_restrict3<T>), dim3((unsigned)nb), dim3(64, kRRW), 0, s, f.tag.p, x, b, r, c.tag.p,
-                     Vec<T>::b(c), Vec<T>::t(f));
+                     Vec<T>::b(c), Vec<T>::t(f), zc);
   const unsigned nbn = nblk(f.n_ns);
   const int64_t ncd = c.N + c.N2;
   hipLaunchKernelGGL((k_restrict_all<T, 3>), dim3(nbn + nblk(ncd)), dim3(kBlock), 0, s, c.tag.p, r, Vec<T>::b(c),

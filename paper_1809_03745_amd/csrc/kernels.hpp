@@ -1464,8 +1464,19 @@ __global__ void __launch_bounds__(kBlock) k_dot_partial(const T* __restrict__ a,
                                                         double* __restrict__ part) {
   __shared__ double sh[kBlock / 64];
   double s = 0;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-    s += (double)a[t] * (double)b[t];
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // four strided terms per step with their loads issued together, added in
+  // the order of the plain strided loop
+  for (; t + 3 * st < n; t += 4 * st) {
+    const T a0 = a[t], a1 = a[t + st], a2 = a[t + 2 * st], a3 = a[t + 3 * st];
+    const T b0 = b[t], b1 = b[t + st], b2 = b[t + 2 * st], b3 = b[t + 3 * st];
+    s += (double)a0 * (double)b0;
+    s += (double)a1 * (double)b1;
+    s += (double)a2 * (double)b2;
+    s += (double)a3 * (double)b3;
+  }
+  for (; t < n; t += st) s += (double)a[t] * (double)b[t];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -1552,7 +1563,26 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xr2(double* __restrict__ x, dou
                                                      int64_t n, double* __restrict__ part) {
   const double a = sc[SC_ALPHA], w = sc[SC_OMEGA];
   double d0 = 0, d1 = 0;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // two strided entries per step with their loads issued together; the
+  // partials take them in the order of the plain strided loop
+  for (; t + st < n; t += 2 * st) {
+    const int64_t u = t + st;
+    const double x0 = x[t], x1 = x[u];
+    const Z p0 = ph[t], p1 = ph[u], q0 = sh[t], q1 = sh[u];
+    const double s0 = s[t], s1 = s[u], v0 = tv[t], v1 = tv[u], h0 = rh[t], h1 = rh[u];
+    x[t] = x0 + (a * (double)p0 + w * (double)q0);
+    x[u] = x1 + (a * (double)p1 + w * (double)q1);
+    const double r0 = s0 - w * v0, r1 = s1 - w * v1;
+    r[t] = r0;
+    r[u] = r1;
+    d0 += h0 * r0;
+    d1 += r0 * r0;
+    d0 += h1 * r1;
+    d1 += r1 * r1;
+  }
+  for (; t < n; t += st) {
     x[t] += a * (double)ph[t] + w * (double)sh[t];
     const double rv = s[t] - w * tv[t];
     r[t] = rv;

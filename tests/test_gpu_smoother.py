@@ -60,6 +60,8 @@ CASES = {
     "pin-plane64": lambda: W.pin_plane(64, seed=2),
     "random-box-ragged": lambda: W.random_box(np.random.default_rng(7)),   # 40 x 56 x 48 cells
     "two-disks256": lambda: W.two_disks(256, seed=1),
+    "two-disks130": lambda: W.two_disks(130, seed=1),   # level 1 is 65 x 65: odd x extent
+    "pin-plane26": lambda: W.pin_plane(26, seed=2),     # level 1 is 13^3: odd x extent
 }
 
 

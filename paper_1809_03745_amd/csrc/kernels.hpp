@@ -1490,19 +1490,54 @@ __global__ void __launch_bounds__(kBlock) k_dot_partial(const T* __restrict__ a,
 // sums `nvec` consecutive partial arrays of length n into out[0..nvec)
 __global__ void __launch_bounds__(kBlock) k_dot_final(const double* __restrict__ part, int n, int nvec,
                                                       double* __restrict__ out) {
-  __shared__ double sh[kBlock / 64];
-  for (int v = 0; v < nvec; ++v) {
-    double s = 0;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) s += part[v * n + t];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double tot = 0;
-      for (int w = 0; w < kBlock / 64; ++w) tot += sh[w];
-      out[v] = tot;
+  // nvec is 1 or 2; both sums are formed together, four strided terms per
+  // step with their loads issued first, each sum taking its terms in the
+  // order of the plain strided loop and then the fixed wave/block order
+  __shared__ double sh[2][kBlock / 64];
+  const double* __restrict__ p0 = part;
+  const double* __restrict__ p1 = part + n;
+  const bool two = nvec > 1;
+  double s0 = 0, s1 = 0;
+  int t = threadIdx.x;
+  for (; t + 3 * kBlock < n; t += 4 * kBlock) {
+    const double a0 = p0[t], a1 = p0[t + kBlock], a2 = p0[t + 2 * kBlock], a3 = p0[t + 3 * kBlock];
+    double b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+    if (two) {
+      b0 = p1[t];
+      b1 = p1[t + kBlock];
+      b2 = p1[t + 2 * kBlock];
+      b3 = p1[t + 3 * kBlock];
     }
-    __syncthreads();
+    s0 += a0;
+    s0 += a1;
+    s0 += a2;
+    s0 += a3;
+    s1 += b0;
+    s1 += b1;
+    s1 += b2;
+    s1 += b3;
+  }
+  for (; t < n; t += kBlock) {
+    s0 += p0[t];
+    if (two) s1 += p1[t];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_down(s0, off, 64);
+    s1 += __shfl_down(s1, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = s0;
+    sh[1][threadIdx.x >> 6] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot0 = 0, tot1 = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      tot0 += sh[0][w];
+      tot1 += sh[1][w];
+    }
+    out[0] = tot0;
+    if (two) out[1] = tot1;
   }
 }
 

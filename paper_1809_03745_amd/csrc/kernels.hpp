@@ -1633,12 +1633,26 @@ __global__ void __launch_bounds__(kBlock) k_convert(const S* __restrict__ s, D* 
   if (t < n) d[t] = (D)s[t];
 }
 
-// Covered cells: identity rows with b = 0, and no sweep, correction or
-// Krylov update touches them, so their entries are set to 0 once, on entry.
-__global__ void __launch_bounds__(kBlock) k_clear_covered(const uint8_t* __restrict__ tag, double* __restrict__ x,
-                                                          int64_t n) {
+// The initial guess taken from the caller's array, in one pass with setting
+// the covered entries to 0: covered cells are identity rows with b = 0 that
+// no sweep, correction or Krylov update touches.
+__global__ void __launch_bounds__(kBlock) k_guess_in(const uint8_t* __restrict__ tag, const double* __restrict__ phi,
+                                                     double* __restrict__ x, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n && tclass(tag[t]) == 3) x[t] = 0.0;
+  if (t < n) x[t] = tclass(tag[t]) == 3 ? 0.0 : phi[t];
+}
+
+// Krylov (re)start in one pass: r = rh = r0, p = v = 0.
+__global__ void __launch_bounds__(kBlock) k_bicg_restart(const double* __restrict__ r0, double* __restrict__ r,
+                                                         double* __restrict__ rh, double* __restrict__ p,
+                                                         double* __restrict__ v, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double a = r0[t];
+  r[t] = a;
+  rh[t] = a;
+  p[t] = 0.0;
+  v[t] = 0.0;
 }
 
 __global__ void __launch_bounds__(kBlock) k_add_f32(double* __restrict__ x, const float* __restrict__ e, int64_t n) {

@@ -1523,10 +1523,7 @@ static ebmg_status bicgstab_t(DevProblem& D, const Options& o, double bn, double
   float* bf = mixed ? L.b32.p : nullptr;
   const unsigned nb = nblk(nd);
   auto restart = [&]() {
-    HIPCHECK(hipMemcpyAsync(r, L.r64.p, sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
-    HIPCHECK(hipMemcpyAsync(rh, L.r64.p, sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
-    fill<double>(p, nd, 0.0, s);
-    fill<double>(v, nd, 0.0, s);
+    hipLaunchKernelGGL(k_bicg_restart, dim3(nb), dim3(kBlock), 0, s, L.r64.p, r, rh, p, v, nd);
     hipLaunchKernelGGL(k_sc_reset, dim3(1), dim3(1), 0, s, D.scal.p);
     dot_dev<double>(D, rh, r, nd, SC_RHO, s);
   };
@@ -1618,8 +1615,7 @@ static ebmg_status solve(ebmg_problem_s* P, const double* rho, const double* sig
   std::memset(&loc, 0, sizeof(loc));
   loc.levels = (int)D.lv.size();
   rhs(P, rho, sigma, bcv, objv);
-  HIPCHECK(hipMemcpyAsync(L.x64.p, phi, sizeof(double) * L.N, hipMemcpyDeviceToDevice, s));
-  hipLaunchKernelGGL(k_clear_covered, dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, L.x64.p, L.N);
+  hipLaunchKernelGGL(k_guess_in, dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, phi, L.x64.p, L.N);
   if (L.N2 > 0) {
     if (phi2)
       HIPCHECK(hipMemcpyAsync(L.x64.p + L.N, phi2, sizeof(double) * L.N2, hipMemcpyDeviceToDevice, s));

@@ -772,8 +772,8 @@ __global__ void __launch_bounds__(kBlock) k_irr_scatter(const int32_t* __restric
 // One colour phase of an out-of-place red/black sweep in a single launch:
 // template cells and explicit rows of colour `colour` are updated from xin,
 // every other unknown is copied to xout. Blocks [0, nbc) take cells (one per
-// thread), the remaining blocks take explicit rows (kSub lanes per row):
-// rows_upd are updated, rows_cp copied. Explicit rows therefore see only the
+// thread), the next nbu blocks update the rows rows_upd (kSub lanes per
+// row), the rest copy the rows rows_cp (one thread per row). Explicit rows therefore see only the
 // values before the phase (Jacobi within a colour, as the grouped passes),
 // and a sweep costs two launches, which is what matters on small levels.
 // With PAIR (nx even) a cell thread takes an even-odd pair along x, of which
@@ -782,7 +782,8 @@ __global__ void __launch_bounds__(kBlock) k_irr_scatter(const int32_t* __restric
 template <typename T, int DIM, bool PAIR>
 __global__ void __launch_bounds__(kBlock) k_rb_oop(const uint8_t* __restrict__ tag, const T* __restrict__ xin,
                                                    T* __restrict__ xout, const T* __restrict__ b, Tmpl<T> tp,
-                                                   int colour, unsigned nbc, const int32_t* __restrict__ rows_upd,
+                                                   int colour, unsigned nbc, unsigned nbu,
+                                                   const int32_t* __restrict__ rows_upd,
                                                    int nupd, const int32_t* __restrict__ rows_cp, int ncp,
                                                    const int64_t* __restrict__ dof, const int64_t* __restrict__ rp,
                                                    const int32_t* __restrict__ col, const T* __restrict__ val,
@@ -828,18 +829,20 @@ __global__ void __launch_bounds__(kBlock) k_rb_oop(const uint8_t* __restrict__ t
     xout[c] = v;
     return;
   }
-  const int64_t g = ((int64_t)(blockIdx.x - nbc) * kBlock + threadIdx.x) / kSub;
-  const int lane = threadIdx.x % kSub;
-  if (g >= (int64_t)nupd + ncp) return;
-  if (g < nupd) {
+  if (blockIdx.x < nbc + nbu) {
+    const int64_t g = ((int64_t)(blockIdx.x - nbc) * kBlock + threadIdx.x) / kSub;
+    const int lane = threadIdx.x % kSub;
+    if (g >= nupd) return;
     const int r = rows_upd[g];
     const T s = row_dot<T>(rp[r], rp[r + 1], col, val, xin, lane);
     const int64_t q = dof[r];
     if (lane == 0) xout[q] = (b[q] - s) / diag[r];
-  } else if (lane == 0) {
-    const int64_t q = dof[rows_cp[g - nupd]];
-    xout[q] = xin[q];
+    return;
   }
+  const int64_t g = (int64_t)(blockIdx.x - nbc - nbu) * kBlock + threadIdx.x;
+  if (g >= ncp) return;
+  const int64_t q = dof[rows_cp[g]];
+  xout[q] = xin[q];
 }
 
 // MODE 0: r = b - A x ; MODE 1: r = A x. Regular cells and covered cells

@@ -1045,10 +1045,11 @@ static void launch_oop(DevLevel& l, int colour, bool rows, const T* xin, T* xout
     up = all;
     nup = 0;
   }
-  const unsigned nbr = nblk_sub((int64_t)nup + ncp);
+  const unsigned nbu = nblk_sub(nup);
+  const unsigned nbr = nbu + nblk(ncp);
 #define OOP_LAUNCH(D, P)                                                                                     \
   KLAUNCH(l.kt, (k_rb_oop<T, D, P>), dim3(nbc + nbr), dim3(kBlock), 0, s, l.tag.p, xin, xout, b, tp, colour, nbc, \
-          up, nup, cp, ncp, l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l))
+          nbu, up, nup, cp, ncp, l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l))
   if (l.dim == 3) {
     if (pair) OOP_LAUNCH(3, true); else OOP_LAUNCH(3, false);
   } else {

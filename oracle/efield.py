@@ -11,7 +11,10 @@ operator. Reading used here (the paper gives no cell-centred formula):
 E is reported for the primary unknown of each cell; covered cells get 0.
 
 Parity: the vectorised regular-cell path equals the generic path
-(tests/test_oracle_efield.py); the field of the coaxial closed form converges.
+(tests/test_oracle_efield.py); the field of the coaxial closed form converges;
+a linear field normal to a planar electrode is reproduced exactly in every
+cell, and by the EB normal-gradient branch when it is forced
+(tests/test_oracle_fallbacks.py).
 """
 from __future__ import annotations
 

@@ -53,10 +53,26 @@ Readings where the text is silent, garbled or ambiguous:
     makes a thin layer of charge sigma/delta converge to it), phi_B eliminated;
   * EB wall (insulator without a phase): F_EB = b g.
 
-Parity: pinned by tests/test_oracle_operator.py (polynomial exactness in
-regular and cut cells, planar multifluid exactness, symmetry of the regular
-operator, flux balance, the closed-form discrete sine solution and the
-coaxial closed form of the paper's multifluid Poisson test).
+Parity, per function (each pin is fixed by mathematics, not by this code):
+  * face fluxes, centroid interpolation, regular template: cubic exactness of
+    regular rows, quadratic exactness of 2D cut rows and 3D planar cut rows,
+    symmetry and definiteness of the regular operator, the closed-form
+    discrete sine solution (tests/test_oracle_operator.py);
+  * domain closures: exactness per closure and degree, the Robin linear and
+    Taylor closures for linear phi (test_oracle_operator.py,
+    test_oracle_fallbacks.py);
+  * _ray (order 2): quadratic exactness of cut rows; _ray (order 1): exact
+    for linear p, directly and in assembled rows (test_oracle_fallbacks.py);
+  * _lsq: exact derivative for linear p without and with Dirichlet wall
+    values on both sides of the box, and zero flux divergence of linear p in
+    every cut row with the ray switched off (test_oracle_fallbacks.py);
+  * _wall: exact for a field linear along the chosen face's normal, face
+    choice at all four corners (test_oracle_fallbacks.py);
+  * multifluid elimination and the sign of sigma: planar piecewise-linear
+    exactness, the coaxial closed form with and without surface charge;
+  * the whole EB operator at scale: second-order Richardson convergence on
+    the two-disk and pin-plane classes (test_oracle_richardson.py) and the
+    coaxial test; flux balance.
 """
 from __future__ import annotations
 

@@ -186,10 +186,10 @@ def two_disks(n=1024, seed=0, sigma_std=0.1):
                    name=f"two-disks-{n}", seed=seed)
 
 
-def _blobs3(rng, nblob, dists):
+def _blobs3(rng, nblob, dists, srange=(0.01, 0.05)):
     cs, ss = [], []
     for _ in range(nblob):
-        s = rng.uniform(0.01, 0.05)
+        s = rng.uniform(*srange)
         while True:
             c = np.array([rng.uniform(0.1, 0.9), rng.uniform(0.1, 0.9), rng.uniform(0.25, 0.95)])
             if all(f(c) >= 3 * s for f in dists):
@@ -207,18 +207,20 @@ def _pin_distance_point(c, z_tip=0.6, r=0.02):
     return math.sqrt(rxy ** 2 + (c[2] - zc) ** 2) - r
 
 
-def pin_plane(n=256, seed=0, nblob=8):
-    """3D unit cube: pin of radius 0.02 on the axis (0.5,0.5) with a
+def pin_plane(n=256, seed=0, nblob=8, r_pin=0.02, blob_sigma=(0.01, 0.05)):
+    """3D unit cube: pin of radius r_pin (0.02) on the axis (0.5,0.5) with a
     hemispherical tip whose apex is at z=0.6, held at 1 and reaching the top
     face; dielectric slab eps=4 for z<0.2; z- Dirichlet 0, z+ Dirichlet 1,
     x/y faces homogeneous Neumann; rho = sum of 8 Gaussian blobs (amplitude 1,
-    standard deviations U[0.01,0.05]) kept 3 sigma away from pin and slab."""
+    standard deviations U[blob_sigma] = U[0.01,0.05]) kept 3 sigma away from
+    pin and slab. The thicker-pin, wider-blob members of the class serve
+    convergence studies on coarse grids."""
     rng = np.random.default_rng(seed)
     h = 1.0 / n
-    dists = [_pin_distance_point, lambda c: c[2] - 0.2]
-    cs, ss = _blobs3(rng, nblob, dists)
+    dists = [lambda c: _pin_distance_point(c, r=r_pin), lambda c: c[2] - 0.2]
+    cs, ss = _blobs3(rng, nblob, dists, blob_sigma)
     Xn = _nodes(3, (n, n, n), h, (0.0, 0.0, 0.0))
-    objs = [Obj(OBJ_ELECTRODE, 1.0, np.ascontiguousarray(sdf_pin3(Xn, (0.5, 0.5), 0.6, 0.02))),
+    objs = [Obj(OBJ_ELECTRODE, 1.0, np.ascontiguousarray(sdf_pin3(Xn, (0.5, 0.5), 0.6, r_pin))),
             Obj(OBJ_DIELECTRIC, 4.0, np.ascontiguousarray(sdf_halfspace_below(Xn[2], 0.2)))]
     X = _centres(3, (n, n, n), h, (0.0, 0.0, 0.0))
     rho = np.zeros(X[0].shape)

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define EBMG_ABI_VERSION 1
+#define EBMG_ABI_VERSION 2
 
 typedef enum {
   EBMG_OK = 0,
@@ -140,41 +140,69 @@ typedef struct {
   double r0_norm;           /* ||b||_2 (residual at phi = 0)                      */
   double rel_residual;      /* final ||b - A phi||_2 / ||b||_2 (FP64)             */
   double seconds;           /* wall time of the solve call                        */
+  int64_t est_bytes;        /* estimated device-memory bytes the solve's kernels
+                               must move (algorithmic: each kernel's minimum
+                               reads and writes, summed over its launches);
+                               est_bytes / seconds is the solve's effective
+                               bandwidth                                         */
   double hist[64];          /* relative residual after each cycle                 */
 } ebmg_solve_info;
 
-/* Fill defaults (Poisson, linear closures, order-2 EB stencils, FP64, V(2,2)). */
+/* Fill defaults (Poisson, linear closures, order-2 EB stencils, FP64, V(2,2)).
+ * Paper: Helmholtz equations, eq. `helmholtz` (Poisson: alpha = 0, beta = -1
+ * with eps0 = 1). */
 void ebmg_default_options(ebmg_options* opt);
 
+/* EBMG_ABI_VERSION of the built library (no paper passage). */
 int ebmg_abi_version(void);
 
-/* Create a context on a HIP device with a caller stream (NULL = a stream the
+/* Create a context (no paper passage: the device and stream every later call
+ * runs on) on a HIP device with a caller stream (NULL = a stream the
  * library creates at default priority). device < 0 gives a host-only context
  * that can set up and export problems but cannot solve (EBMG_ERR_DEVICE). */
 ebmg_status ebmg_create(int32_t device, void* hip_stream, ebmg_ctx* out);
-/* End the context handle: queued submitted solves run to completion first.
+/* End the context handle (no paper passage): queued submitted solves run to
+ * completion first.
  * Problems and batches set up on the context stay usable until released;
  * the context's stream and worker thread go with the last of them. */
 ebmg_status ebmg_destroy(ebmg_ctx ctx);
 /* Message of the last failing call on ctx; with ctx == NULL, of the calling
- * thread's last failing ebmg_create. */
+ * thread's last failing ebmg_create (no paper passage; owned by the library). */
 const char* ebmg_last_error(ebmg_ctx ctx);
 
 /* Build geometry moments, the finest-level operator (cut-cell rows), the
  * multigrid hierarchy and the bottom-level inverse on the host, and upload
  * them (device contexts). Boundary-condition TYPES and object kinds are fixed
- * here; values may change per solve. */
+ * here; values may change per solve.
+ * Paper: Spatial discretization (cut cells from a level set: volume
+ * fractions, apertures, centroids, linearised facets); Helmholtz equations
+ * (eq. `poisson_integral` over a cut cell, centroid-interpolated face
+ * fluxes, eq. `matching` for the dielectric interface) and its Boundary
+ * conditions (domain closures, eq. `bndry_stencil` with the ray casting of
+ * figure `raycast` and the least-squares fallback, Robin extrapolation);
+ * Multigrid solver (the coarsened hierarchy). box, objs (with their HOST
+ * sdf arrays), bc and opt are HOST and are copied; *out receives the
+ * problem. ERR_ARG for an invalid box or option, ERR_GEOMETRY for cells the
+ * discretisation cannot represent (saddles, cells cut by two objects, cut
+ * cells without a stencil), ERR_OOM / ERR_DEVICE from the upload; on error
+ * *out is untouched. */
 ebmg_status ebmg_setup(ebmg_ctx ctx, const ebmg_box* box, int32_t nobj, const ebmg_object* objs,
                        const ebmg_domain_bc* bc, const ebmg_options* opt, ebmg_problem* out);
 
-/* Sizes: cells, second-phase unknowns, levels, device bytes held. */
+/* Sizes: cells, second-phase unknowns (the dielectric side of interface
+ * cells; Paper: Multigrid solver, a patch cut by a multifluid boundary
+ * carries both phases), levels, device bytes held. Outputs HOST, any may be
+ * NULL. */
 ebmg_status ebmg_query(ebmg_problem pb, int64_t* n_cells, int64_t* n_phase2, int32_t* n_levels,
                        int64_t* device_bytes);
 
-/* Sizes of multigrid level `level` (0 = finest): cells and second-phase unknowns. */
+/* Sizes of multigrid level `level` (0 = finest; Paper: Multigrid solver):
+ * cells and second-phase unknowns. Outputs HOST. ERR_ARG for a bad level. */
 ebmg_status ebmg_query_level(ebmg_problem pb, int32_t level, int64_t* n_cells, int64_t* n_phase2);
 
-/* Smoother choice of level `level` (0 split half-sweeps, 1 fused tile sweep,
+/* Measurement record of the smoother autotuner (the red/black Gauss-Seidel
+ * relaxation of the Multigrid solver subsection). Outputs HOST.
+ * Smoother choice of level `level` (0 split half-sweeps, 1 fused tile sweep,
  * 2 + c z-marching fused sweep in tile configuration c as listed at
  * ebmg_smooth, 13 one-launch colour phases), the split sweep time and the
  * chosen (or best
@@ -187,37 +215,82 @@ ebmg_status ebmg_query_tuning(ebmg_problem pb, int32_t level, int32_t* fused, do
 
 /* HOST copies of a level's cell tags (0/1 regular gas/dielectric, 2 explicit
  * row, 3 covered; +4 when the cell's children do not all map to its primary
- * unknown), primary phase per cell and cell of each second-phase unknown. */
+ * unknown), primary phase per cell and cell of each second-phase unknown
+ * (the coarsened graph of the Multigrid solver subsection). Arrays of the
+ * level's sizes (ebmg_query_level), caller-owned; any may be NULL. */
 ebmg_status ebmg_export_level(ebmg_problem pb, int32_t level, uint8_t* tag, int8_t* primary, int64_t* sec_cell);
 
-/* HOST copies of geometry for cross-checks. kappa: N per phase (phase 0/1);
- * primary: N int8 (0 gas, 1 dielectric, -1 covered); sec_cell: n_phase2
- * int64 cell of each second-phase unknown. Any pointer may be NULL. */
+/* HOST copies of geometry for cross-checks (Paper: Spatial discretization, volume
+ * fractions; the gas-side unknown is the primary one of a two-phase cell).
+ * kappa: N per phase (phase 0/1); primary: N int8 (0 gas, 1 dielectric, -1
+ * covered); sec_cell: n_phase2 int64 cell of each second-phase unknown. Any
+ * pointer may be NULL. */
 ebmg_status ebmg_export_geometry(ebmg_problem pb, double* kappa_gas, double* kappa_diel,
                                  int8_t* primary, int64_t* sec_cell);
 
+/* HOST copies of the cut-cell moments of phase `phase` (0 gas, 1 dielectric)
+ * for cross-checks. Paper: Spatial discretization (volume fractions, face
+ * area fractions and the linearised boundary facet of each cut cell, from
+ * the level set sampled at the nodes) and Helmholtz equations (the face
+ * centroids that fluxes are interpolated to, the facet centroid and normal
+ * where the EB flux is evaluated).
+ *  vcent     dim*N, component-major: volume centroid (absolute coordinates);
+ *            the cell centre for full cells, 0 where the phase is absent.
+ *  apert     face aperture alpha in [0,1] of every face, faces normal to x
+ *            first, then y, then z; the faces normal to d form an array of
+ *            (n_x + [d=0]) x (n_y + [d=1]) (x (n_z + [d=2]) in 3D) entries,
+ *            x fastest. F = the total face count of the box.
+ *  foff      (dim-1)*F, per face (dim-1 consecutive values): the face
+ *            centroid's offset from the face centre in units of h along the
+ *            face's transverse axes in increasing order; 0 on full or closed
+ *            faces.
+ *  eb_area   N: facet area / h^(dim-1) (0 without a facet).
+ *  eb_cent   dim*N, component-major: facet centroid (absolute coordinates).
+ *  eb_normal dim*N, component-major: unit facet normal pointing out of the
+ *            phase (0 without a facet).
+ * Any pointer may be NULL. ERR_ARG for a phase the problem does not have. */
+ebmg_status ebmg_export_moments(ebmg_problem pb, int32_t phase, double* vcent, double* apert, double* foff,
+                                double* eb_area, double* eb_cent, double* eb_normal);
+
 /* HOST CSR of the level-`level` operator over N+N2 unknowns (covered cells
- * as identity rows). Call with row_ptr == NULL to get *nnz only. */
+ * as identity rows): the linear part of the volume-weighted row of eq.
+ * `poisson_integral` (Helmholtz equations) on level 0, the coarse operators
+ * of the Multigrid solver subsection elsewhere. Call with row_ptr == NULL to
+ * get *nnz only; then row_ptr (N+N2+1), cols and vals (*nnz) are HOST arrays
+ * the caller allocates. ERR_ARG for a bad level. */
 ebmg_status ebmg_export_operator(ebmg_problem pb, int32_t level, int64_t* nnz, int64_t* row_ptr,
                                  int64_t* cols, double* vals);
 
-/* HOST right-hand side b (N+N2) for the given data, from the stored boundary
- * coefficients: b = kappa*rho - L(0). rho: N (primary unknowns); sigma: N or
- * NULL; bc_values: 6 or NULL (setup values); obj_values: nobj or NULL. */
+/* Paper: Helmholtz equations and its Boundary conditions.
+ * HOST right-hand side b (N+N2) for the given data, from the stored boundary
+ * coefficients: b = kappa*rho - L(0), i.e. the source of eq.
+ * `poisson_integral` plus every boundary datum (domain values, electrode
+ * potentials, the surface charge sigma of eq. `matching`). rho: N (primary
+ * unknowns); sigma: N or NULL; bc_values: 6 or NULL (setup values);
+ * obj_values: nobj or NULL. All HOST. */
 ebmg_status ebmg_export_rhs(ebmg_problem pb, const double* rho, const double* sigma,
                             const double* bc_values, const double* obj_values, double* b);
 
-/* Solve. rho, sigma (nullable), phi (in: initial guess, out: primary unknown
- * per cell; covered cells 0), phi2 (nullable; second-phase unknowns, in/out),
- * E (nullable; dim*N cell-centred field, component-major) are DEVICE arrays.
- * bc_values (6) and obj_values (nobj) are HOST arrays or NULL (setup values).
- * rtol: stop when ||b - A phi||_2 <= rtol ||b||_2. */
+/* Solve. Paper: Multigrid solver (V-cycles with red/black Gauss-Seidel
+ * relaxation, stop when ||r|| < lambda ||r0|| with r0 the residual at
+ * phi = 0) for the system of Helmholtz equations; E = -grad(phi) from the
+ * centroid-interpolated face fluxes (Electrodynamic equations, eq.
+ * `poisson`). rho, sigma (nullable), phi (in: initial guess, out: primary
+ * unknown per cell; covered cells 0), phi2 (nullable; second-phase
+ * unknowns, in/out), E (nullable; dim*N cell-centred field,
+ * component-major) are DEVICE arrays. bc_values (6) and obj_values (nobj)
+ * are HOST arrays or NULL (setup values). rtol: stop when
+ * ||b - A phi||_2 <= rtol ||b||_2. info (HOST, nullable) receives the
+ * record. ERR_NOCONV leaves the last iterate in phi; ERR_NUMERIC flags
+ * NaN/Inf or residual growth. */
 ebmg_status ebmg_solve(ebmg_problem pb, const double* rho, const double* sigma,
                        const double* bc_values, const double* obj_values, double rtol,
                        int32_t max_cycles, double* phi, double* phi2, double* E,
                        ebmg_solve_info* info);
 
-/* Asynchronous solve for serving: the same solve as ebmg_solve, queued on
+/* Asynchronous solve for serving (no paper passage: the request loop of a
+ * solver service; the solve itself is ebmg_solve's): the same solve as
+ * ebmg_solve, queued on
  * the context's worker thread (started by the first submit), which runs the
  * submitted solves of a context one after another, in submission order, on
  * the context's stream. Solves on separate contexts (separate streams) run
@@ -235,7 +308,7 @@ ebmg_status ebmg_submit(ebmg_problem pb, const double* rho, const double* sigma,
                         int32_t max_cycles, double* phi, double* phi2, double* E,
                         uint64_t* ticket);
 
-/* Non-blocking check of a submitted solve. *done (HOST) = 0 while it is
+/* Non-blocking check of a submitted solve (serving; no paper passage). *done (HOST) = 0 while it is
  * queued or running; once it has finished, *done = 1, *result receives the
  * solve's status (what ebmg_solve would have returned; on failure
  * ebmg_last_error(ctx) gives its message), info (nullable) its record, and
@@ -244,15 +317,23 @@ ebmg_status ebmg_submit(ebmg_problem pb, const double* rho, const double* sigma,
 ebmg_status ebmg_poll(ebmg_ctx ctx, uint64_t ticket, int32_t* done, ebmg_status* result,
                       ebmg_solve_info* info);
 
-/* As ebmg_poll, blocking until the submitted solve has finished. */
+/* As ebmg_poll, blocking until the submitted solve has finished (serving;
+ * no paper passage). */
 ebmg_status ebmg_wait(ebmg_ctx ctx, uint64_t ticket, ebmg_status* result, ebmg_solve_info* info);
 
-/* out = A [phi; phi2] (FP64, DEVICE arrays; phi2/out2 nullable when N2 = 0). */
+/* out = A [phi; phi2]: the linear part of the finest-level operator of the
+ * Helmholtz equations section (eq. `poisson_integral`, boundary data
+ * excluded), in FP64. phi, phi2, out, out2 are DEVICE arrays of N and N2
+ * entries (phi2/out2 nullable when N2 = 0). */
 ebmg_status ebmg_apply(ebmg_problem pb, const double* phi, const double* phi2, double* out,
                        double* out2);
 
-/* Cell-centred E = -grad(phi) from centroid-interpolated face fluxes for a
- * given solution (DEVICE arrays; data as in ebmg_solve). */
+/* Cell-centred E = -grad(phi) (Electrodynamic equations) from the
+ * centroid-interpolated face fluxes of the Helmholtz equations section: the
+ * mean of the open low/high face gradients per axis, the EB normal gradient
+ * where neither face is open. phi, phi2, sigma and E (dim*N,
+ * component-major) are DEVICE arrays; bc_values / obj_values HOST or NULL,
+ * as in ebmg_solve. */
 ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, const double* sigma,
                         const double* bc_values, const double* obj_values, double* E);
 
@@ -267,6 +348,11 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
  * phases out of place. Every variant performs exactly the red half-sweep
  * followed by
  * the black one with the same arithmetic, so their results agree bitwise.
+ * Variant 15 is the one-launch colour phases with the explicit rows
+ * included, as the solver smooths levels that use them: in the phase of
+ * colour c every template cell of colour c and every explicit row whose
+ * cell has colour c (by the parity of i+j+k) is relaxed from the values
+ * before the phase.
  * x (in/out) and b are DEVICE FP64 arrays of the level's N + N2 unknowns;
  * mixed-precision problems sweep in FP32 (x and b rounded, x widened back).
  * Uses the level's work vectors. ERR_ARG where the level cannot use the
@@ -274,7 +360,9 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
 ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t sweeps, double* x,
                         const double* b);
 
-/* Measurement hook: launch one kernel `reps` times on the context stream
+/* Measurement hook (no paper passage; the kernels are the relaxation and
+ * residual of the Multigrid solver subsection): launch one kernel `reps`
+ * times on the context stream
  * between two HIP events and report the mean duration per launch (ms) and
  * the kernel's algorithmic bytes per launch. which = 0: the level's chosen
  * smoother kernel; 2: a red/black half-sweep; 3: the level's fused
@@ -286,7 +374,8 @@ ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t
 ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int32_t reps, double* avg_ms,
                              double* alg_bytes);
 
-/* Measurement hook, in-solve form: enable = 1 starts timing, inside later
+/* Measurement hook, in-solve form (no paper passage): enable = 1 starts
+ * timing, inside later
  * ebmg_solve calls on pb, the launches of level `level`'s smoothing-sweep
  * kernel (which = 0: the fused sweep, or each colour phase / half-sweep where
  * the level uses those; not the first z-marching sweep of a V-cycle, which
@@ -304,7 +393,9 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
 ebmg_status ebmg_kernel_timing(ebmg_problem pb, int32_t which, int32_t level, int32_t enable,
                                int64_t* launches, double* mean_ms, double* alg_bytes);
 
-/* Replace the coefficients of a problem without embedded objects and without
+/* Paper: Radiative transfer (eq. `sp1` and its Robin outflow condition,
+ * eq. `robin`), Helmholtz equations (its backward-Euler example).
+ * Replace the coefficients of a problem without embedded objects and without
  * explicit rows on any level (e.g. the Eddington Helmholtz problem of the
  * radiative-transfer section, kappa phi - div((1/3kappa) grad phi) = S, for a
  * new absorption kappa): alpha, beta, a_gas, a_diel, b_gas in opt and the
@@ -315,20 +406,32 @@ ebmg_status ebmg_kernel_timing(ebmg_problem pb, int32_t which, int32_t level, in
  * qualify. Not to be called while a solve on the problem is running. */
 ebmg_status ebmg_set_coefficients(ebmg_problem pb, const ebmg_options* opt, const ebmg_domain_bc* bc);
 
+/* Free the problem's device hierarchy and host data (waits for its submitted
+ * solves first; no paper passage). NULL is ignored. */
 ebmg_status ebmg_release(ebmg_problem pb);
 
 /* Batched boxes (independent problems of one dimension and one precision),
- * e.g. the leaves of a patch-based hierarchy. Setup builds every box on the
- * host (in parallel) and uploads it; boxes[i] with nobj[i] objects objs[i],
- * bcs[i] and opts[i] (opts may be NULL for defaults). */
+ * e.g. the leaves of a patch-based hierarchy (Paper: Spatial discretization,
+ * patch-based AMR with fixed-size boxes; each box is discretised as in
+ * ebmg_setup). Setup builds every box on the host (in parallel) and uploads
+ * it; boxes[i] with nobj[i] objects objs[i], bcs[i] and opts[i] (opts may be
+ * NULL for defaults). All arguments HOST, copied. Errors as ebmg_setup,
+ * for the first failing box. */
 ebmg_status ebmg_setup_batch(ebmg_ctx ctx, int32_t nbox, const ebmg_box* boxes, const int32_t* nobj,
                              const ebmg_object* const* objs, const ebmg_domain_bc* bcs, const ebmg_options* opts,
                              ebmg_batch* out);
 
-/* Total cells, second-phase unknowns and device bytes of a batch. */
+/* Total cells, second-phase unknowns and device bytes of a batch (HOST
+ * outputs, any may be NULL; no paper passage). */
 ebmg_status ebmg_query_batch(ebmg_batch bt, int64_t* cells, int64_t* cells2, int64_t* device_bytes);
 
-/* Setup choices of a batch: mode (1 persistent, 2 level-synchronous), the
+/* Cells and second-phase unknowns of box `box` of a batch (HOST outputs,
+ * any may be NULL; no paper passage): the sizes of its rho / phi and phi2
+ * arrays in ebmg_solve_batch. ERR_ARG for a box index out of range. */
+ebmg_status ebmg_query_batch_box(ebmg_batch bt, int32_t box, int64_t* n_cells, int64_t* n_phase2);
+
+/* Measurement record (no paper passage). Setup choices of a batch: mode
+ * (1 persistent, 2 level-synchronous), the
  * coarse-part threshold (a box's levels of at most this many unknowns run in
  * one workgroup; 0: only the bottom level), the number of levels run by
  * grid-wide launches, and the timed candidates (up to 8 thresholds and V-cycle
@@ -336,7 +439,8 @@ ebmg_status ebmg_query_batch(ebmg_batch bt, int64_t* cells, int64_t* cells2, int
 ebmg_status ebmg_query_batch_tuning(ebmg_batch bt, int32_t* mode, int32_t* tail_cells, int32_t* wide_levels,
                                     int32_t* ncand, int32_t* cand_cells, double* cand_ms);
 
-/* Solve every box to ||r|| <= rtol ||b||: right-hand side, FP64 residual,
+/* Paper: Multigrid solver (as ebmg_solve, per box).
+ * Solve every box to ||r|| <= rtol ||b||: right-hand side, FP64 residual,
  * V-cycle (FP32 for mixed precision) as the BiCGStab preconditioner or as
  * plain refinement. With options.batch == 1, in ONE persistent launch:
  * workgroups of 512 threads take boxes (largest first, fixed assignment)
@@ -355,6 +459,7 @@ ebmg_status ebmg_query_batch_tuning(ebmg_batch bt, int32_t* mode, int32_t* tail_
 ebmg_status ebmg_solve_batch(ebmg_batch bt, const double* const* rho, const double* const* sigma, double rtol,
                              int32_t max_cycles, double* const* phi, double* const* phi2, ebmg_solve_info* infos);
 
+/* Free a batch and every box in it (no paper passage). NULL is ignored. */
 ebmg_status ebmg_release_batch(ebmg_batch bt);
 
 #ifdef __cplusplus

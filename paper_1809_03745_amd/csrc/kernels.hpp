@@ -773,9 +773,13 @@ __global__ void __launch_bounds__(kBlock) k_irr_scatter(const int32_t* __restric
 // template cells and explicit rows of colour `colour` are updated from xin,
 // every other unknown is copied to xout. Blocks [0, nbc) take cells (one per
 // thread), the next nbu blocks update the rows rows_upd (kSub lanes per
-// row), the rest copy the rows rows_cp (one thread per row). Explicit rows therefore see only the
-// values before the phase (Jacobi within a colour, as the grouped passes),
-// and a sweep costs two launches, which is what matters on small levels.
+// row), the rest copy the rows rows_cp (one thread per row). Every update of
+// the phase, template cell or explicit row, reads only the values before the
+// phase: the explicit rows do not see this phase's template-cell updates
+// (the grouped passes, which run after the phase's template cells, do), and
+// rows of one colour see each other's previous values (Jacobi within a
+// colour, as in the grouped passes). A sweep costs two launches, which is
+// what matters on small levels.
 // With PAIR (nx even) a cell thread takes an even-odd pair along x, of which
 // exactly one cell has the phase's colour: half as many threads wait on the
 // same tag -> neighbours -> store chain, with the same arithmetic per cell.
@@ -1592,7 +1596,10 @@ __global__ void __launch_bounds__(kBlock) k_bicg_s2(double* __restrict__ s, cons
 
 // x += alpha ph + omega sh ; r = s - omega t, with the partials of (rh, r)
 // and (r, r) for the next iteration (grid of kNormBlocks, the same
-// partition as k_dot_partial)
+// partition as k_dot_partial). A breakdown (alpha or omega not finite, e.g.
+// (rh, v) = 0) leaves x and r as they were, so that the host's restart from
+// the true residual starts from the last good iterate; the partials are then
+// zero and the host tests the true residual.
 template <typename Z>
 __global__ void __launch_bounds__(kBlock) k_bicg_xr2(double* __restrict__ x, double* __restrict__ r,
                                                      const Z* __restrict__ ph, const Z* __restrict__ sh,
@@ -1601,6 +1608,7 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xr2(double* __restrict__ x, dou
                                                      int64_t n, double* __restrict__ part) {
   const double a = sc[SC_ALPHA], w = sc[SC_OMEGA];
   double d0 = 0, d1 = 0;
+  if (!isfinite(a) || !isfinite(w)) n = 0;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   // two strided entries per step with their loads issued together; the

@@ -391,11 +391,22 @@ template <typename A>
 static bool al2(const A* p) {
   return ((uintptr_t)p % (2 * sizeof(A))) == 0;
 }
-// partials one matrix-vector product on a level may leave (for sizing)
+// partials one matrix-vector product on a level may leave (for sizing): the
+// template-cell blocks of whichever residual kernel runs, plus the explicit
+// rows' blocks of whichever row kernel runs (the sliced one takes a block per
+// 64-row slice of each colour group, the CSR one a block per 32 rows)
 static int64_t matvec_blocks(const DevLevel& l) {
-  if (l.dim == 3 && l.N >= kResidZMMin)
-    return std::max(zm_resid_blocks(l), zp_resid_blocks(l)) + (int64_t)nblk(l.R * kSub);
-  return (int64_t)nblk(l.N) + (int64_t)nblk(l.R * kSub);
+  const int64_t csr = (int64_t)nblk(l.R * kSub);
+  if (l.dim == 3 && l.N >= kResidZMMin) {
+    int64_t sl = 0;
+    if (l.cls_ptr.size() == 3)
+      sl = (l.cls_ptr[1] - l.cls_ptr[0] + kSplitRows - 1) / kSplitRows +
+           (l.cls_ptr[2] - l.cls_ptr[1] + kSplitRows - 1) / kSplitRows;
+    else
+      sl = (l.R + kSplitRows - 1) / kSplitRows;
+    return std::max(zm_resid_blocks(l), zp_resid_blocks(l)) + std::max(csr, sl);
+  }
+  return (int64_t)nblk(l.N) + csr;
 }
 
 static bool fused_ok(const DevLevel& l) {
@@ -1326,6 +1337,63 @@ static void precond(DevProblem& D, const Options& o, const double* r, double* z,
   HIPCHECK(hipGetLastError());
 }
 
+// Algorithmic device-memory bytes (each kernel's minimum reads and writes)
+// of the solve's steps, for ebmg_solve_info.est_bytes. Per unknown of a
+// level with values of vsz bytes: a template sweep reads x, b and the tag
+// and writes x; explicit rows read per stored entry a column index and a
+// value and per row its unknown index, b and diagonal, and write x; the
+// V-cycle residual restricted into the coarse b reads x, b and the tag and
+// writes the coarse b; prolongation reads the coarse correction, x and the
+// tag and writes x; the dense bottom inverse is read once per application.
+static double rows_bytes(const DevLevel& l, int vsz) {
+  return (double)l.R * (8.0 + 3.0 * vsz) + (double)l.col.n * (4.0 + vsz);
+}
+
+static double vcycle_bytes(const DevProblem& D, const Options& o, int vsz) {
+  double by = 0;
+  for (size_t l = 0; l < D.lv.size(); ++l) {
+    const DevLevel& L = D.lv[l];
+    const double n = (double)(L.N + L.N2);
+    if (l + 1 == D.lv.size()) {
+      by += D.bottom_n > 0 ? (double)D.bottom_n * D.bottom_n * 8.0 + 2.0 * D.bottom_n * vsz : 3.0 * n * vsz;
+      break;
+    }
+    const DevLevel& C = D.lv[l + 1];
+    const double sweeps = o.nu1 + o.nu2;
+    by += sweeps * ((double)L.N * (3.0 * vsz + 1.0) + rows_bytes(L, vsz));
+    by += (double)L.N * (2.0 * vsz + 1.0) + rows_bytes(L, vsz) + (double)(C.N + C.N2) * vsz;   // residual, restriction
+    by += (double)(C.N + C.N2) * vsz + n * 2.0 * vsz + (double)L.N;                                // prolongation
+  }
+  return by;
+}
+
+// per outer iteration, besides its V-cycles: BiCGStab's vector steps and its
+// two FP64 matrix-vector products (with their dot products), or a refinement
+// cycle's conversions, correction and FP64 residual with its norm
+static double iteration_bytes(const DevProblem& D, const Options& o) {
+  const DevLevel& L = D.lv[0];
+  const double n = (double)(L.N + L.N2);
+  const bool mixed = o.precision == EBMG_MIXED;
+  const double zs = mixed ? 4.0 : 8.0;
+  const double mv = (double)L.N * 1.0 + n * (zs + 16.0) + rows_bytes(L, 8);
+  if (D.krylov)
+    return n * (32.0 + 24.0 + 56.0 + 2.0 * zs + (mixed ? 8.0 : 0.0)) + 2.0 * mv;
+  return n * (mixed ? 12.0 + 4.0 + 20.0 : 0.0) + (double)L.N * 25.0 + rows_bytes(L, 8) + n * 8.0;
+}
+
+// estimated bytes of one box of a batched solve: its cycles and outer
+// iterations as for a single solve, plus its right-hand side and residuals
+static int64_t box_bytes(ebmg_problem_s* P, int cycles, int iters) {
+  const DevProblem& D = P->dev;
+  const DevLevel& L = D.lv[0];
+  const Options& o = P->host->opt;
+  const double n = (double)(L.N + L.N2);
+  double by = (double)L.N * 17.0 + rows_bytes(L, 8) + 2.0 * ((double)L.N * 25.0 + rows_bytes(L, 8) + n * 8.0);
+  by += cycles * vcycle_bytes(D, o, o.precision == EBMG_MIXED ? 4 : 8);
+  by += (D.krylov ? iters : cycles) * iteration_bytes(D, o);
+  return (int64_t)by;
+}
+
 // deterministic dot product into device scalar slot `slot`
 template <typename T>
 static void dot_dev(DevProblem& D, const T* a, const T* b, int64_t n, int slot, hipStream_t s) {
@@ -1458,6 +1526,7 @@ static void matvec_dots(DevProblem& D, const Z* x, double* out, const double* da
       nb1 = (nb1 + kSplitRows - 1) / kSplitRows;
     }
     pt = G + (sl ? (int64_t)(nb0 + nb1) : (int64_t)nblk(l.R * kSub));
+    if ((int64_t)ndot * pt > D.part.n) throw DeviceError("matrix-vector partials exceed their buffer");
     if (pair) {
       if (ndot == 1)
         hipLaunchKernelGGL((k_resid_zp3<double, 1, Z, 1>), g, dim3(64, kRPY), 0, s, l.tag.p, x, nullptr, out, tp, da,
@@ -1684,6 +1753,18 @@ static ebmg_status solve(ebmg_problem_s* P, const double* rho, const double* sig
   for (auto& k : D.kt)
     if (k) k->harvest();
   loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  {
+    // right-hand side, guess intake, ||b||, first residual and its norm,
+    // the solution copy-out and E; then the cycles and outer iterations
+    const double n = (double)nd;
+    double by = (double)L.N * (8.0 + 1.0 + 8.0) + rows_bytes(L, 8) + (double)L.N * 17.0 + n * 8.0 +
+                (double)L.N * 25.0 + rows_bytes(L, 8) + n * 8.0 + n * 16.0;
+    if (E) by += (double)L.N * (9.0 + 8.0 * L.dim);
+    const int vsz = mixed ? 4 : 8;
+    by += loc.cycles * vcycle_bytes(D, H.opt, vsz);
+    by += (D.krylov ? loc.outer_iters : loc.cycles) * iteration_bytes(D, H.opt);
+    loc.est_bytes = (int64_t)by;
+  }
   if (info) *info = loc;
   return st;
 }
@@ -2161,12 +2242,16 @@ static void release_wide(ebmg_batch_s* Bt) {
 template <typename T>
 static void template_sweeps(DevLevel& l, int variant, int sweeps, T* x, const T* b, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
-  if (variant == 3 + kZMConfigs) {
+  if (variant == 3 + kZMConfigs || variant == 4 + kZMConfigs) {
+    // one-launch colour phases; the second form also relaxes each phase's
+    // explicit rows (from the values before the phase), as smooth() does on
+    // levels that use these phases
+    const bool rows = variant == 4 + kZMConfigs;
     T* cur = x;
     T* alt = Vec<T>::xa(l);
     for (int it = 0; it < sweeps; ++it)
       for (int colour = 0; colour < 2; ++colour) {
-        launch_oop<T>(l, colour, false, cur, alt, b, s);
+        launch_oop<T>(l, colour, rows, cur, alt, b, s);
         std::swap(cur, alt);
       }
     HIPCHECK(hipGetLastError());
@@ -2504,6 +2589,49 @@ ebmg_status ebmg_export_geometry(ebmg_problem pb, double* kg, double* kd, int8_t
   return EBMG_OK;
 }
 
+ebmg_status ebmg_export_moments(ebmg_problem pb, int32_t phase, double* vcent, double* apert, double* foff,
+                                double* eb_area, double* eb_cent, double* eb_normal) {
+  if (!pb || phase < 0 || phase >= pb->host->geo.nphase) return EBMG_ERR_ARG;
+  return guard(pb->ctx, [&]() -> ebmg_status {
+    const Geometry& G = pb->host->geo;
+    const Grid& g = G.g;
+    const int dim = g.dim;
+    const int nz = dim == 3 ? g.n[2] : 1;
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < g.n[1]; ++j)
+        for (int i = 0; i < g.n[0]; ++i) {
+          const int64_t c = g.cell(i, j, k);
+          const int ijk[3] = {i, j, k};
+          const CellCut* cc = G.cut(phase, c);
+          const bool has = G.has(phase, c);
+          for (int d = 0; d < dim; ++d) {
+            if (vcent) vcent[d * G.N + c] = !has ? 0.0 : (cc ? cc->vc[d] : g.centre(d, ijk[d]));
+            if (eb_cent) eb_cent[d * G.N + c] = cc && cc->eb_area > 0 ? cc->eb_c[d] : 0.0;
+            if (eb_normal) eb_normal[d * G.N + c] = cc && cc->eb_area > 0 ? cc->eb_n[d] : 0.0;
+          }
+          if (eb_area) eb_area[c] = cc ? cc->eb_area : 0.0;
+        }
+    int64_t base = 0;
+    for (int d = 0; d < dim; ++d) {
+      const int m0 = g.n[0] + (d == 0), m1 = g.n[1] + (d == 1), m2 = dim == 3 ? g.n[2] + (d == 2) : 1;
+      for (int k = 0; k < m2; ++k)
+        for (int j = 0; j < m1; ++j)
+          for (int i = 0; i < m0; ++i) {
+            const int c[3] = {i, j, k};
+            const int64_t f = base + i + (int64_t)m0 * (j + (int64_t)m1 * k);
+            if (apert) apert[f] = G.alpha(phase, d, c);
+            if (foff) {
+              double off[2];
+              G.face_off(phase, d, c, off);
+              for (int q = 0; q < dim - 1; ++q) foff[(dim - 1) * f + q] = off[q];
+            }
+          }
+      base += (int64_t)m0 * m1 * m2;
+    }
+    return EBMG_OK;
+  });
+}
+
 ebmg_status ebmg_export_operator(ebmg_problem pb, int32_t level, int64_t* nnz, int64_t* row_ptr, int64_t* cols,
                                  double* vals) {
   if (!pb || !nnz || level < 0 || level >= (int32_t)pb->host->levels.size()) return EBMG_ERR_ARG;
@@ -2695,7 +2823,7 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
 
 ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t sweeps, double* x,
                         const double* b) {
-  if (!pb || !x || !b || sweeps < 0 || variant < 1 || variant > 3 + kZMConfigs) return EBMG_ERR_ARG;
+  if (!pb || !x || !b || sweeps < 0 || variant < 1 || variant > 4 + kZMConfigs) return EBMG_ERR_ARG;
   if (!pb->on_device) return EBMG_ERR_DEVICE;
   if (level < 0 || level >= (int32_t)pb->dev.lv.size()) return EBMG_ERR_ARG;
   return guard(pb->ctx, [&]() -> ebmg_status {
@@ -2996,6 +3124,14 @@ ebmg_status ebmg_query_batch(ebmg_batch bt, int64_t* cells, int64_t* cells2, int
   return EBMG_OK;
 }
 
+ebmg_status ebmg_query_batch_box(ebmg_batch bt, int32_t box, int64_t* n_cells, int64_t* n_phase2) {
+  if (!bt || box < 0 || box >= (int32_t)bt->boxes.size()) return EBMG_ERR_ARG;
+  const ebmg::Geometry& G = bt->boxes[box]->host->geo;
+  if (n_cells) *n_cells = G.N;
+  if (n_phase2) *n_phase2 = G.N2;
+  return EBMG_OK;
+}
+
 ebmg_status ebmg_query_batch_tuning(ebmg_batch bt, int32_t* mode, int32_t* tail_cells, int32_t* wide_levels,
                                     int32_t* ncand, int32_t* cand_cells, double* cand_ms) {
   if (!bt) return EBMG_ERR_ARG;
@@ -3060,6 +3196,7 @@ ebmg_status ebmg_solve_batch(ebmg_batch bt, const double* const* rho, const doub
           infos[i].r0_norm = st[i].bn;
           infos[i].rel_residual = st[i].rel;
           infos[i].seconds = secs;
+          infos[i].est_bytes = box_bytes(bt->boxes[i].get(), st[i].cycles, st[i].iters);
         }
         if (st[i].status != EBMG_OK && worst == EBMG_OK) worst = (ebmg_status)st[i].status;
       }
@@ -3105,6 +3242,7 @@ ebmg_status ebmg_solve_batch(ebmg_batch bt, const double* const* rho, const doub
         infos[i].r0_norm = res[i].r0;
         infos[i].rel_residual = res[i].rel;
         infos[i].seconds = secs;
+        infos[i].est_bytes = box_bytes(bt->boxes[i].get(), res[i].cycles, res[i].iters);
       }
       if (res[i].status != EBMG_OK && worst == EBMG_OK) worst = (ebmg_status)res[i].status;
     }

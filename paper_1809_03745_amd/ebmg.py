@@ -68,12 +68,12 @@ class Options(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("cycles", C.c_int32), ("outer_iters", C.c_int32), ("levels", C.c_int32), ("n_hist", C.c_int32),
                 ("r0_norm", C.c_double), ("rel_residual", C.c_double), ("seconds", C.c_double),
-                ("hist", C.c_double * 64)]
+                ("est_bytes", C.c_int64), ("hist", C.c_double * 64)]
 
     def as_dict(self):
         return dict(cycles=self.cycles, outer_iters=self.outer_iters, levels=self.levels,
                     r0_norm=self.r0_norm, rel_residual=self.rel_residual, seconds=self.seconds,
-                    hist=[self.hist[i] for i in range(self.n_hist)])
+                    est_bytes=self.est_bytes, hist=[self.hist[i] for i in range(self.n_hist)])
 
 
 _vp = C.c_void_p
@@ -100,6 +100,7 @@ _sig("ebmg_query_level", C.c_int, [_vp, C.c_int32, _i64p, _i64p])
 _sig("ebmg_export_level", C.c_int, [_vp, C.c_int32, _vp, _vp, _vp])
 _sig("ebmg_query_tuning", C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), _dp, _dp])
 _sig("ebmg_export_geometry", C.c_int, [_vp, _vp, _vp, _vp, _vp])
+_sig("ebmg_export_moments", C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_export_operator", C.c_int, [_vp, C.c_int32, _i64p, _vp, _vp, _vp])
 _sig("ebmg_export_rhs", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_solve", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int32, _vp, _vp, _vp,
@@ -118,6 +119,7 @@ _sig("ebmg_set_coefficients", C.c_int, [_vp, C.POINTER(Options), C.POINTER(Domai
 _sig("ebmg_setup_batch", C.c_int, [_vp, C.c_int32, C.POINTER(Box), C.POINTER(C.c_int32), C.POINTER(_vp),
                                    C.POINTER(DomainBC), C.POINTER(Options), C.POINTER(_vp)])
 _sig("ebmg_query_batch", C.c_int, [_vp, _i64p, _i64p, _i64p])
+_sig("ebmg_query_batch_box", C.c_int, [_vp, C.c_int32, _i64p, _i64p])
 _sig("ebmg_query_batch_tuning", C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                           C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double)])
 _sig("ebmg_solve_batch", C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.c_double, C.c_int32, C.POINTER(_vp),
@@ -126,9 +128,9 @@ _sig("ebmg_release_batch", C.c_int, [_vp])
 
 EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_destroy", "ebmg_last_error",
             "ebmg_setup", "ebmg_query", "ebmg_query_level", "ebmg_export_level", "ebmg_query_tuning",
-            "ebmg_export_geometry", "ebmg_export_operator", "ebmg_export_rhs",
+            "ebmg_export_geometry", "ebmg_export_moments", "ebmg_export_operator", "ebmg_export_rhs",
             "ebmg_solve", "ebmg_submit", "ebmg_poll", "ebmg_wait", "ebmg_apply", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
-            "ebmg_setup_batch", "ebmg_query_batch", "ebmg_query_batch_tuning", "ebmg_solve_batch", "ebmg_release_batch",
+            "ebmg_setup_batch", "ebmg_query_batch", "ebmg_query_batch_box", "ebmg_query_batch_tuning", "ebmg_solve_batch", "ebmg_release_batch",
             "ebmg_set_coefficients", "ebmg_smooth", "ebmg_kernel_timing"]
 
 
@@ -147,6 +149,28 @@ def _ptr(a):
 
 def _host_f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dev(ctx, t, n, name, nullable=False):
+    """Device pointer of a float64 tensor argument, checked before the library
+    sees it: a CPU, wrong-device, non-float64, non-contiguous or short tensor
+    would be read or written out of bounds by the kernels, so it is refused
+    here (EBMG_ERR_ARG) instead."""
+    if t is None:
+        if nullable:
+            return None
+        raise EbmgError(ERR_ARG, f"{name}: a device tensor is required")
+    if _torch is None or not isinstance(t, _torch.Tensor):
+        raise EbmgError(ERR_ARG, f"{name}: expected a torch tensor on cuda:{ctx.device}, got {type(t).__name__}")
+    if not t.is_cuda or ctx.device < 0 or t.device.index != ctx.device:
+        raise EbmgError(ERR_ARG, f"{name}: tensor on {t.device}, the context's device is cuda:{ctx.device}")
+    if t.dtype != _torch.float64:
+        raise EbmgError(ERR_ARG, f"{name}: dtype {t.dtype}, expected torch.float64")
+    if not t.is_contiguous():
+        raise EbmgError(ERR_ARG, f"{name}: tensor is not contiguous")
+    if t.numel() < n:
+        raise EbmgError(ERR_ARG, f"{name}: {t.numel()} elements, at least {n} needed")
+    return t.data_ptr()
 
 
 class Context:
@@ -275,6 +299,38 @@ class Problem:
                        "ebmg_export_geometry")
         return kg, kd, pr, sc[:self.N2]
 
+    def moments(self, phase=0):
+        """Cut-cell moments of one phase (host copies): dict of vcent
+        (dim, N), apert (list of per-direction face arrays in numpy order),
+        foff (list of (faces, dim-1) arrays), eb_area (N), eb_cent and
+        eb_normal (dim, N)."""
+        b = self.prob
+        dim = b.dim
+        n = list(b.n) + [1] * (3 - dim)
+        counts = []
+        shapes = []
+        for d in range(dim):
+            m = [n[e] + (1 if e == d else 0) for e in range(3)]
+            counts.append(m[0] * m[1] * m[2])
+            shapes.append(tuple(reversed(m[:dim])))
+        F = sum(counts)
+        vc = np.zeros(dim * self.N)
+        ap = np.zeros(F)
+        fo = np.zeros(max(1, (dim - 1) * F))
+        ea = np.zeros(self.N)
+        ec = np.zeros(dim * self.N)
+        en = np.zeros(dim * self.N)
+        self.ctx.check(_lib.ebmg_export_moments(self.h, int(phase), _ptr(vc), _ptr(ap), _ptr(fo), _ptr(ea), _ptr(ec),
+                                                _ptr(en)), "ebmg_export_moments")
+        aps, fos = [], []
+        o = 0
+        for d in range(dim):
+            aps.append(ap[o:o + counts[d]].reshape(shapes[d]))
+            fos.append(fo[(dim - 1) * o:(dim - 1) * (o + counts[d])].reshape(counts[d], dim - 1))
+            o += counts[d]
+        return dict(vcent=vc.reshape(dim, self.N), apert=aps, foff=fos, eb_area=ea,
+                    eb_cent=ec.reshape(dim, self.N), eb_normal=en.reshape(dim, self.N))
+
     def level_size(self, level):
         n, n2 = C.c_int64(), C.c_int64()
         self.ctx.check(_lib.ebmg_query_level(self.h, level, C.byref(n), C.byref(n2)), "ebmg_query_level")
@@ -320,8 +376,9 @@ class Problem:
         info = SolveInfo()
         bcv = _host_f64(bc_values)
         ov = _host_f64(obj_values)
-        st = _lib.ebmg_solve(self.h, _ptr(rho), _ptr(sigma), _ptr(bcv), _ptr(ov), float(rtol), int(max_cycles),
-                             _ptr(phi), _ptr(phi2), _ptr(E), C.byref(info))
+        args = self._solve_args(rho, phi, sigma, phi2, E)
+        st = _lib.ebmg_solve(self.h, args[0], args[1], _ptr(bcv), _ptr(ov), float(rtol), int(max_cycles),
+                             *args[2:], C.byref(info))
         if check:
             self.ctx.check(st, "ebmg_solve")
         return st, info.as_dict()
@@ -334,20 +391,30 @@ class Problem:
         bcv = _host_f64(bc_values)
         ov = _host_f64(obj_values)
         t = C.c_uint64()
-        self.ctx.check(_lib.ebmg_submit(self.h, _ptr(rho), _ptr(sigma), _ptr(bcv), _ptr(ov), float(rtol),
-                                        int(max_cycles), _ptr(phi), _ptr(phi2), _ptr(E), C.byref(t)),
+        args = self._solve_args(rho, phi, sigma, phi2, E)
+        self.ctx.check(_lib.ebmg_submit(self.h, args[0], args[1], _ptr(bcv), _ptr(ov), float(rtol),
+                                        int(max_cycles), *args[2:], C.byref(t)),
                        "ebmg_submit")
         self.ctx._held[t.value] = (rho, sigma, phi, phi2, E)
         return t.value
 
+    def _solve_args(self, rho, phi, sigma, phi2, E):
+        c, N, N2 = self.ctx, self.N, self.N2
+        return (_dev(c, rho, N, "rho"), _dev(c, sigma, N, "sigma", True), _dev(c, phi, N, "phi"),
+                _dev(c, phi2, N2, "phi2", True), _dev(c, E, self.prob.dim * N, "E", True))
+
     def apply(self, phi, phi2, out, out2):
-        self.ctx.check(_lib.ebmg_apply(self.h, _ptr(phi), _ptr(phi2), _ptr(out), _ptr(out2)), "ebmg_apply")
+        c, N, N2 = self.ctx, self.N, self.N2
+        self.ctx.check(_lib.ebmg_apply(self.h, _dev(c, phi, N, "phi"), _dev(c, phi2, N2, "phi2", N2 == 0),
+                                       _dev(c, out, N, "out"), _dev(c, out2, N2, "out2", N2 == 0)), "ebmg_apply")
 
     def efield(self, phi, phi2, E, sigma=None, bc_values=None, obj_values=None):
+        c, N, N2 = self.ctx, self.N, self.N2
         bcv = _host_f64(bc_values)
         ov = _host_f64(obj_values)
-        self.ctx.check(_lib.ebmg_efield(self.h, _ptr(phi), _ptr(phi2), _ptr(sigma), _ptr(bcv), _ptr(ov), _ptr(E)),
-                       "ebmg_efield")
+        self.ctx.check(_lib.ebmg_efield(self.h, _dev(c, phi, N, "phi"), _dev(c, phi2, N2, "phi2", True),
+                                        _dev(c, sigma, N, "sigma", True), _ptr(bcv), _ptr(ov),
+                                        _dev(c, E, self.prob.dim * N, "E")), "ebmg_efield")
 
     def tuning(self, level):
         """(smoother variant: 0 split, 1 tile, 2 + c z-march in tile ZM_TILES[c],
@@ -360,7 +427,9 @@ class Problem:
 
     def smooth(self, level, variant, sweeps, x, b):
         """Template-cell red/black sweeps on level ``level`` (device FP64 x, b)."""
-        self.ctx.check(_lib.ebmg_smooth(self.h, level, variant, sweeps, _ptr(x), _ptr(b)), "ebmg_smooth")
+        n = sum(self.level_size(level))
+        self.ctx.check(_lib.ebmg_smooth(self.h, level, variant, sweeps, _dev(self.ctx, x, n, "x"),
+                                        _dev(self.ctx, b, n, "b")), "ebmg_smooth")
 
     def time_kernel(self, which, level=0, reps=50):
         """(mean ms per launch, algorithmic bytes per launch) of a kernel."""
@@ -407,6 +476,7 @@ ZM_TILES = [(64, 8, 32, False), (64, 16, 32, False), (32, 16, 32, False), (64, 8
             (64, 16, 8, False)]
 OOP_VARIANT = 2 + len(ZM_TILES)      # tuning code of the one-launch colour phases
 SMOOTH_OOP = 3 + len(ZM_TILES)       # ebmg_smooth variant of the one-launch colour phases
+SMOOTH_OOP_ROWS = 4 + len(ZM_TILES)  # the same with each phase's explicit rows relaxed
 
 BATCH_LEVELSYNC = 2    # every phase one launch over all boxes (default)
 BATCH_PERSISTENT = 1   # one persistent launch, one workgroup per box
@@ -444,6 +514,11 @@ class Batch:
         n, n2, by = C.c_int64(), C.c_int64(), C.c_int64()
         ctx.check(_lib.ebmg_query_batch(h, C.byref(n), C.byref(n2), C.byref(by)), "ebmg_query_batch")
         self.cells, self.cells2, self.device_bytes = n.value, n2.value, by.value
+        self.sizes = []
+        for i in range(nb):
+            ni, n2i = C.c_int64(), C.c_int64()
+            ctx.check(_lib.ebmg_query_batch_box(h, i, C.byref(ni), C.byref(n2i)), "ebmg_query_batch_box")
+            self.sizes.append((ni.value, n2i.value))
 
     def tuning(self):
         """Setup choices: dict(mode, tail_cells, wide_levels, candidates=[(cells, V-cycle ms)])."""
@@ -459,10 +534,20 @@ class Batch:
         """rho, phi (and optionally sigma, phi2) are lists of device tensors,
         one per box (entries of sigma / phi2 may be None)."""
         nb = len(self.probs)
-        arr = lambda xs: (_vp * nb)(*[_ptr(x) for x in xs]) if xs is not None else None
+        c = self.ctx
+
+        def arr(xs, name, which, nullable):
+            if xs is None:
+                return None
+            if len(xs) != nb:
+                raise EbmgError(ERR_ARG, f"{name}: {len(xs)} tensors for {nb} boxes")
+            return (_vp * nb)(*[_dev(c, x, self.sizes[i][which], f"{name}[{i}]", nullable or self.sizes[i][which] == 0)
+                               for i, x in enumerate(xs)])
+        if rho is None or phi is None:
+            raise EbmgError(ERR_ARG, "rho and phi are required")
         infos = (SolveInfo * nb)()
-        st = _lib.ebmg_solve_batch(self.h, arr(rho), arr(sigma), float(rtol), int(max_cycles), arr(phi),
-                                   arr(phi2), infos)
+        st = _lib.ebmg_solve_batch(self.h, arr(rho, "rho", 0, False), arr(sigma, "sigma", 0, True), float(rtol),
+                                   int(max_cycles), arr(phi, "phi", 0, False), arr(phi2, "phi2", 1, False), infos)
         if check:
             self.ctx.check(st, "ebmg_solve_batch")
         return st, [infos[i].as_dict() for i in range(nb)]

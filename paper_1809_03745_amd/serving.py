@@ -98,13 +98,14 @@ class Scheduler:
         self.entries = []
         self.running = 0
         self.vec_reserved = 0
+        self.releasing = 0       # bytes of evicted hierarchies not yet freed
         self.high_water = 0
         self.measured = {}       # key -> bytes of a set-up hierarchy
         self.stats = collections.Counter()
 
     # -- footprint ----------------------------------------------------------
     def reserved(self):
-        return self.vec_reserved + sum(e.bytes for e in self.entries)
+        return self.vec_reserved + self.releasing + sum(e.bytes for e in self.entries)
 
     def hier_estimate(self, req):
         return self.measured.get(req.key, self.bytes_per_cell * req.cells)
@@ -154,6 +155,7 @@ class Scheduler:
                 use, evict = plan
                 for e in evict:
                     self.entries.remove(e)
+                    self.releasing += e.bytes   # still held until the executor frees it
                     self.stats["evicted"] += 1
                 if use is None:
                     use = Entry(req.key, self.hier_estimate(req))
@@ -166,7 +168,9 @@ class Scheduler:
                 use.busy = True
                 self.running += 1
                 self.vec_reserved += req.vec_bytes()
-                self.high_water = max(self.high_water, self.reserved())
+                # the admitting worker frees its evictions before it sets up
+                # the new hierarchy, so they do not add to the peak
+                self.high_water = max(self.high_water, self.reserved() - self.releasing)
                 req.t_admit = now
                 return req, use, evict
             if now - req.arrival > self.max_bypass_s and i == 0:
@@ -183,6 +187,10 @@ class Scheduler:
         entry.ready = True
         self.measured[entry.key] = int(actual_bytes)
         self.high_water = max(self.high_water, self.reserved())
+
+    def released(self, entry):
+        """An evicted hierarchy's device memory has been freed."""
+        self.releasing -= entry.bytes
 
     def failed_setup(self, entry):
         if entry in self.entries:
@@ -256,12 +264,17 @@ class Server:
         torch, ebmg = self.torch, self.ebmg
         stream = torch.cuda.Stream(device=self.dev)
         ctx = ebmg.Context(self.device, stream=stream.cuda_stream)
-        prob = req.make_problem()
-        t0 = time.perf_counter()
-        # fixed kernel choices (no timing: a result is the same alone and in
-        # any mix) and direct launches (a Helmholtz request re-coefficients
-        # the hierarchy, which would drop a captured graph every time)
-        P = ebmg.Problem(ctx, prob, precision=self.precision, smoother=4, tail=1, graphs=1)
+        try:
+            prob = req.make_problem()
+            t0 = time.perf_counter()
+            # fixed kernel choices (no timing: a result is the same alone and
+            # in any mix) and direct launches (a Helmholtz request
+            # re-coefficients the hierarchy, which would drop a captured
+            # graph every time)
+            P = ebmg.Problem(ctx, prob, precision=self.precision, smoother=4, tail=1, graphs=1)
+        except Exception:
+            ctx.close()
+            raise
         req.setup_s = time.perf_counter() - t0
         entry.handle = {"problem": P, "ctx": ctx, "stream": stream}
         entry.coeff_sig = req.coeff_sig
@@ -301,7 +314,12 @@ class Server:
                     return
             req, entry, evict = pick
             for e in evict:
-                self._release(e)
+                try:
+                    self._release(e)
+                finally:
+                    with self.cv:
+                        self.sched.released(e)
+                        self.cv.notify_all()
             try:
                 if entry.handle is None:
                     nbytes = self._setup(req, entry)

@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) <= set(ebmg.EXPORTED) | {"ebmg_default_options"}
-    assert ebmg.abi_version() == 1
+    assert ebmg.abi_version() == 2
 
 
 @pytest.fixture(scope="module")
@@ -70,6 +70,51 @@ def test_host_system_equals_oracle(host_ctx, name):
         assert np.abs(kd - g.ph[1].kappa.ravel()).max() <= 1e-13
     assert np.array_equal(prim, g.primary.ravel())
     assert np.array_equal(sec, g.sec_cells)
+    P.release()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_moments_equal_oracle(host_ctx, name):
+    """Cut-cell moments through ebmg_export_moments: face apertures, face
+    centroid offsets, volume centroids, facet areas, centroids and normals
+    equal the oracle's to 1e-13 absolute, per phase."""
+    pr = CASES[name]()
+    P = ebmg.Problem(host_ctx, pr)
+    g = Geometry(pr)
+    dim = pr.dim
+    for p in range(g.nphase):
+        m = P.moments(p)
+        ph = g.ph[p]
+        for d in range(dim):
+            assert m["apert"][d].shape == ph.alpha[d].shape
+            assert np.abs(m["apert"][d] - ph.alpha[d]).max() <= 1e-13, (name, p, d)
+            want = np.zeros((ph.alpha[d].size, dim - 1))
+            flat = {np.ravel_multi_index(idx, ph.alpha[d].shape): off for idx, off in ph.foff[d].items()
+                    if ph.alpha[d][idx] > 0}
+            for f, off in flat.items():
+                want[f] = off
+            got = m["foff"][d].copy()
+            got[ph.alpha[d].ravel() == 0] = 0.0    # offsets of closed faces carry no meaning
+            assert np.abs(got - want).max() <= 1e-13, (name, p, d)
+        has = g.has[p].ravel()
+        vc = np.zeros((dim, g.N))
+        ea = np.zeros(g.N)
+        ec = np.zeros((dim, g.N))
+        en = np.zeros((dim, g.N))
+        for c in np.nonzero(has)[0]:
+            idx = np.unravel_index(c, g.shape)
+            cc = ph.cut.get(idx)
+            vc[:, c] = g.centre(idx) if cc is None else cc.vcent
+            if cc is not None and cc.eb_area > 0:
+                ea[c] = cc.eb_area
+                ec[:, c] = cc.eb_cent
+                en[:, c] = cc.eb_normal
+        assert np.abs(m["vcent"] - vc).max() <= 1e-13, (name, p)
+        assert np.abs(m["eb_area"] - ea).max() <= 1e-13, (name, p)
+        assert np.abs(m["eb_cent"] - ec).max() <= 1e-13, (name, p)
+        assert np.abs(m["eb_normal"] - en).max() <= 1e-13, (name, p)
+    with pytest.raises(ebmg.EbmgError):
+        P.moments(g.nphase)
     P.release()
 
 
@@ -119,7 +164,10 @@ def test_error_codes(host_ctx):
     # solve on a host-only context
     pr = W.manufactured_sine(8)
     P = ebmg.Problem(host_ctx, pr)
-    st, _ = P.solve(np.zeros(64), np.zeros(64), check=False)
+    z = np.zeros(64)
+    info = ebmg.SolveInfo()
+    st = ebmg._lib.ebmg_solve(P.h, z.ctypes.data, None, None, None, 1e-10, 10, z.ctypes.data, None, None,
+                              ebmg.C.byref(info))
     assert st == ebmg.ERR_DEVICE
     # pure Neumann problem is singular
     k, v, a1, a2 = W._bc(W.BC_NEUMANN)
@@ -186,9 +234,14 @@ def test_setup_handles_every_batched_box_class(host_ctx):
 
 def test_async_calls_on_a_host_context(host_ctx):
     P = ebmg.Problem(host_ctx, W.manufactured_sine(8))
-    with pytest.raises(ebmg.EbmgError) as e:
+    with pytest.raises(ebmg.EbmgError) as e:     # refused by the binding: not device tensors
         P.submit(np.zeros(64), np.zeros(64))
-    assert e.value.status == ebmg.ERR_DEVICE
+    assert e.value.status == ebmg.ERR_ARG
+    z = np.zeros(64)
+    t = ebmg.C.c_uint64()
+    st = ebmg._lib.ebmg_submit(P.h, z.ctypes.data, None, None, None, 1e-10, 10, z.ctypes.data, None, None,
+                               ebmg.C.byref(t))
+    assert st == ebmg.ERR_DEVICE                  # and by the library on a host-only context
     assert not host_ctx._held
     # no ticket was handed out, so any ticket is unknown
     for t in (0, 1, 2**64 - 1):
@@ -259,3 +312,39 @@ def test_set_coefficients_rejects_embedded_problems(host_ctx):
     pb.bc_kind = [W.BC_DIRICHLET] * 6
     with pytest.raises(ebmg.EbmgError):
         E.set_coefficients(pb)
+
+
+def test_binding_refuses_bad_device_arrays(host_ctx):
+    """Every device argument is checked in the binding before the library is
+    called: host arrays, CPU or float32 tensors, non-contiguous and short
+    tensors raise ERR_ARG (the kernels would otherwise read or write out of
+    bounds)."""
+    torch = pytest.importorskip("torch")
+    pr = W.two_disks(32, seed=0)
+    P = ebmg.Problem(host_ctx, pr)
+    calls = []
+    real = ebmg._lib
+
+    class Spy:
+        def __getattr__(self, name):
+            f = getattr(real, name)
+
+            def called(*a):
+                calls.append(name)
+                return f(*a)
+            return called
+    ebmg._lib = Spy()
+    try:
+        good = torch.zeros(P.N, dtype=torch.float64)
+        bad = [np.zeros(P.N), good, torch.zeros(P.N, dtype=torch.float32), torch.zeros(2 * P.N, dtype=torch.float64)[::2],
+               torch.zeros(P.N - 1, dtype=torch.float64)]
+        for t in bad:
+            for call in (lambda: P.solve(t, t, check=False), lambda: P.apply(t, None, t, None),
+                         lambda: P.efield(t, None, t), lambda: P.submit(t, t)):
+                with pytest.raises(ebmg.EbmgError) as e:
+                    call()
+                assert e.value.status == ebmg.ERR_ARG
+        assert not [c for c in calls if c in ("ebmg_solve", "ebmg_apply", "ebmg_efield", "ebmg_submit")]
+    finally:
+        ebmg._lib = real
+    P.release()

@@ -106,3 +106,60 @@ def test_smoother_variants(ctx, name, prec):
             ref = _reference_sweeps(A, tag, shape, pr.dim, x0, b, 2)
             assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
     P.release()
+
+
+def _reference_phases_with_rows(A, tag, n, dim, sec_cell, x, b, sweeps):
+    """Colour phases in which every unknown of the phase's colour (template
+    cells by their own parity, explicit rows and second-phase unknowns by the
+    parity of their cell) is relaxed from the values before the phase."""
+    A = A.tocsr()
+    N = int(np.prod(n))
+    nd = A.shape[0]
+    cell = np.concatenate([np.arange(N), np.asarray(sec_cell, dtype=np.int64)])
+    i = cell % n[0]
+    j = (cell // n[0]) % n[1]
+    k = cell // (n[0] * n[1]) if dim == 3 else 0
+    colour = (i + j + k) & 1
+    active = np.concatenate([(tag & 3) != 3, np.ones(nd - N, bool)])
+    d = A.diagonal()
+    x = x.copy()
+    for _ in range(sweeps):
+        for c in (0, 1):
+            rows = np.nonzero(active & (colour == c))[0]
+            off = A[rows] @ x - d[rows] * x[rows]
+            x[rows] = (b[rows] - off) / d[rows]
+    return x
+
+
+@pytest.mark.parametrize("name", ["two-disks130", "pin-plane26", "random-box-ragged"])
+def test_colour_phases_with_rows(ctx, name):
+    """The one-launch colour phases as the solver runs them on its small
+    levels (explicit rows included) against the numpy definition built from
+    the exported level operator, FP64."""
+    pr = CASES[name]()
+    P = ebmg.Problem(ctx, pr, precision=0)
+    rng = np.random.default_rng(3)
+    checked = 0
+    for level in range(P.levels):
+        n, n2 = P.level_size(level)
+        tag, _, sec = P.level_arrays(level)
+        shape = [max(1, pr.n[d] >> level) for d in range(pr.dim)]
+        if int(np.prod(shape)) != n or not ((tag & 3) == 2).any():
+            continue
+        x0 = rng.normal(size=n + n2)
+        b = rng.normal(size=n + n2)
+        xt = torch.tensor(x0, dtype=torch.float64, device=DEV)
+        bt = torch.tensor(b, dtype=torch.float64, device=DEV)
+        torch.cuda.synchronize()
+        try:
+            P.smooth(level, ebmg.SMOOTH_OOP_ROWS, 2, xt, bt)
+        except ebmg.EbmgError as e:
+            assert e.status == ebmg.ERR_ARG
+            continue
+        y = xt.cpu().numpy()
+        ref = _reference_phases_with_rows(P.operator(level), tag, shape, pr.dim, sec, x0, b, 2)
+        _say(name, "level", level, "rows", int(((tag & 3) == 2).sum()) + n2, "max diff", np.abs(y - ref).max())
+        assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+        checked += 1
+    assert checked >= 1
+    P.release()

@@ -59,6 +59,8 @@ def test_lru_eviction_and_high_water_within_budget():
     for i, key in enumerate(["a", "b", "c", "a"]):
         s.offer(_req(i, key, 100))
         req, e, evict = _admit(s)
+        for v in evict:                 # the executor frees evicted hierarchies before a setup
+            s.released(v)
         if e.handle is None and not e.ready:
             s.set_up(e, 1000)
         clock.t += 1.0
@@ -102,3 +104,26 @@ def test_same_key_waits_for_its_busy_hierarchy():
     r1, e1, _ = _admit(s)
     assert r1.rid == 1 and e1 is e0 and r1.hit
     assert sum(1 for x in s.entries if x.key == "a") == 1
+
+
+def test_evicted_bytes_stay_reserved_until_released():
+    """An evicted hierarchy is freed by the executor after admission; until
+    it reports the release, its bytes still count against the budget, so a
+    concurrent admission cannot overcommit the device."""
+    vec = _req(0, "x", 100).vec_bytes()
+    budget = 1000 + vec + 500           # one hierarchy and one request's vectors
+    s = Scheduler(budget_bytes=budget, slots=2, bytes_per_cell=10)
+    s.offer(_req(0, "a", 100))
+    r, e, _ = _admit(s)
+    s.set_up(e, 1000)
+    s.finish(r, e)
+    s.offer(_req(1, "b", 100))          # needs "a" evicted
+    r1, e1, ev = _admit(s)
+    assert ev == [e]
+    assert s.reserved() >= 1000 + 1000 + vec   # a's bytes held while it is being freed
+    s.offer(_req(2, "c", 100))
+    assert s.next_admissible() is None  # would exceed the budget before a is freed
+    assert s.reserved() <= budget + 1000
+    s.released(e)
+    assert s.releasing == 0
+    assert s.reserved() == 1000 + vec

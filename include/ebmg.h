@@ -60,6 +60,7 @@ typedef enum {
 typedef struct ebmg_ctx_s* ebmg_ctx;
 typedef struct ebmg_problem_s* ebmg_problem;
 typedef struct ebmg_batch_s* ebmg_batch;
+typedef struct ebmg_family_s* ebmg_family;
 
 /* Box: dim in {2,3}; n[d] cells per axis (n[2] ignored in 2D); isotropic
  * cell size h; lower corner lo. */
@@ -328,6 +329,21 @@ ebmg_status ebmg_wait(ebmg_ctx ctx, uint64_t ticket, ebmg_status* result, ebmg_s
 ebmg_status ebmg_apply(ebmg_problem pb, const double* phi, const double* phi2, double* out,
                        double* out2);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * out = A [phi; phi2] as ebmg_apply, computed by the same kernels, with its
+ * staging in a fixed device scratch array that the library holds on each GPU
+ * from context creation until the process ends (18 MiB), instead of the
+ * problem's work vectors. It allocates nothing (no hipMalloc, hipFree or
+ * allocating library call) and does not synchronise: the work is queued on
+ * the context's stream and out / out2 are ready when that stream reaches it.
+ * Limit: N + N2 <= 1179648 unknowns (ERR_ARG beyond). All calls on one GPU
+ * share that GPU's scratch, which keeps the last call's contents: calls that
+ * overlap on one GPU (several contexts or threads at once) race; serialise
+ * them. phi, phi2, out, out2: DEVICE arrays as for ebmg_apply. */
+ebmg_status ebmg_apply_noalloc(ebmg_problem pb, const double* phi, const double* phi2, double* out,
+                               double* out2);
+
 /* Cell-centred E = -grad(phi) (Electrodynamic equations) from the
  * centroid-interpolated face fluxes of the Helmholtz equations section: the
  * mean of the open low/high face gradients per axis, the EB normal gradient
@@ -461,6 +477,56 @@ ebmg_status ebmg_solve_batch(ebmg_batch bt, const double* const* rho, const doub
 
 /* Free a batch and every box in it (no paper passage). NULL is ignored. */
 ebmg_status ebmg_release_batch(ebmg_batch bt);
+
+/* A family of Helmholtz operators on one geometry, set up once and kept
+ * resident: nmem members alpha_k a_k phi + beta_k div(b_k grad phi) = rho_k,
+ * each with its own coefficients and domain boundary data.
+ * Paper: Radiative transfer (eq. `sp1` solved per frequency group gamma with
+ * its own kappa_gamma, outflow condition eq. `robin`) and the Photoionization
+ * appendix (three groups with the same source); Parabolic equations (the
+ * TGA scheme eq. `tga`: two Helmholtz solves per diffusion step, one per
+ * shifted operator I - mu_i L) and the backward-Euler example of the
+ * Helmholtz equations section. Every member is discretised as ebmg_setup
+ * does (same geometry, objects and boundary kinds); the cut-cell moments are
+ * computed once, and members whose operator structure (cell tags, explicit
+ * rows and their columns, transfer lists, level by level) equals member 0's
+ * use member 0's device copies of that structure, so the family holds one
+ * hierarchy structure plus per-member values and vectors. Smoother and
+ * coarse-tail choices are member 0's.
+ * box, objs (with their HOST sdf arrays): the geometry, as for ebmg_setup.
+ * bcs[k], opts[k] (HOST, nmem entries each): member k's domain data and
+ * options; the boundary kinds and every option other than alpha, beta,
+ * a_gas, a_diel and b_gas must equal member 0's (ERR_ARG otherwise).
+ * Errors as ebmg_setup; *out untouched on error. */
+ebmg_status ebmg_setup_family(ebmg_ctx ctx, const ebmg_box* box, int32_t nobj, const ebmg_object* objs,
+                              int32_t nmem, const ebmg_domain_bc* bcs, const ebmg_options* opts,
+                              ebmg_family* out);
+
+/* Sizes of a family (HOST outputs, any may be NULL; no paper passage):
+ * members, cells and second-phase unknowns per member, device bytes held by
+ * the whole family, and the bytes of structure members take from member 0
+ * instead of holding their own copies. */
+ebmg_status ebmg_query_family(ebmg_family fam, int32_t* nmem, int64_t* n_cells, int64_t* n_phase2,
+                              int64_t* device_bytes, int64_t* shared_bytes);
+
+/* Paper: Multigrid solver (as ebmg_solve, per member). Solve the members
+ * whose rho[k] is non-NULL, each to ||r|| <= rtol ||b||, with the setup's
+ * boundary values. rho, phi (HOST arrays of nmem pointers) hold DEVICE
+ * arrays of N cells (phi in: guess, out: solution); sigma and phi2 may be
+ * NULL or hold NULL entries (phi2[k] is required for a member with N2 > 0
+ * only when phi2 itself is given). Members run on streams of their own,
+ * after the work queued on the context's stream, each driven by its own host
+ * thread (the first call runs them one after another); the call returns
+ * when all have finished. A member's result does not depend on which other
+ * members are solved with it. infos and statuses (HOST, nmem entries, may
+ * be NULL) receive each member's record and status; the return value is the
+ * first failing member's status (its message in ebmg_last_error). */
+ebmg_status ebmg_solve_family(ebmg_family fam, const double* const* rho, const double* const* sigma, double rtol,
+                              int32_t max_cycles, double* const* phi, double* const* phi2, ebmg_solve_info* infos,
+                              ebmg_status* statuses);
+
+/* Free a family and its members (no paper passage). NULL is ignored. */
+ebmg_status ebmg_release_family(ebmg_family fam);
 
 #ifdef __cplusplus
 }

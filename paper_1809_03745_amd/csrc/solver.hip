@@ -65,8 +65,10 @@ template <typename T>
 struct DevBuf {
   T* p = nullptr;
   int64_t n = 0;
+  bool own = true;   // false: an alias of another problem's buffer (a family member's shared structure)
   void alloc(int64_t count, int64_t& bytes) {
     n = count;
+    own = true;
     if (count > 0) {
       HIPCHECK(hipMalloc((void**)&p, sizeof(T) * count));
       bytes += sizeof(T) * count;
@@ -76,10 +78,18 @@ struct DevBuf {
     alloc(count, bytes);
     if (count > 0) HIPCHECK(hipMemcpyAsync(p, host, sizeof(T) * count, hipMemcpyHostToDevice, s));
   }
+  // use o's memory without owning it; returns the bytes not allocated
+  int64_t share(const DevBuf& o) {
+    p = o.p;
+    n = o.n;
+    own = false;
+    return (int64_t)sizeof(T) * n;
+  }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && own) (void)hipFree(p);
     p = nullptr;
     n = 0;
+    own = true;
   }
 };
 
@@ -203,6 +213,7 @@ struct DevProblem {
   int kt_level[2] = {-1, -1};
   bool timing() const { return kt[0] || kt[1]; }
   int64_t bytes = 0;
+  int64_t shared_bytes = 0;   // structure taken from another family member (not allocated here)
   void drop_graphs() {
     if (g_krylov) (void)hipGraphExecDestroy(g_krylov);
     if (g_plain) (void)hipGraphExecDestroy(g_plain);
@@ -275,6 +286,16 @@ struct ebmg_problem_s {
   ebmg::DevProblem dev;
   bool on_device = false;
   int pending = 0;  // submitted solves not yet finished (guarded by ctx->mu)
+};
+
+// Operators on one geometry (a family): member 0 owns the device structure,
+// the others take it and hold their own values and vectors; each member has
+// a private context (its own stream), so members solve concurrently.
+struct ebmg_family_s {
+  ebmg_ctx ctx = nullptr;                    // the caller's context
+  std::vector<ebmg_ctx> mctx;                // one private context per member
+  std::vector<ebmg_problem_s*> mem;
+  bool warm = false;                         // every member has solved once (graphs captured)
 };
 
 // Many independent boxes solved by one persistent launch.
@@ -833,7 +854,23 @@ static void build_sliced(const std::vector<int64_t>& rp, const std::vector<int32
   grp[2] = (int)sptr.size() - 1;
 }
 
-static void upload(ebmg_problem_s* P, bool batch_box = false) {
+// Whether two levels (of family members on one geometry) have the same
+// structure: cell tags, explicit rows and their columns, colour groups and
+// transfer lists. Their device copies are then the same arrays.
+static bool same_structure(const Level& a, const Level& b) {
+  return a.g.dim == b.g.dim && a.g.n[0] == b.g.n[0] && a.g.n[1] == b.g.n[1] && a.g.n[2] == b.g.n[2] &&
+         a.N == b.N && a.N2 == b.N2 && a.tag == b.tag && a.sec_cell == b.sec_cell && a.irow_dof == b.irow_dof &&
+         a.rp == b.rp && a.col == b.col && a.cls_ptr == b.cls_ptr && a.cls_rows == b.cls_rows &&
+         a.ns_cdof == b.ns_cdof && a.ns_ptr == b.ns_ptr && a.ns_child == b.ns_child && a.np_fdof == b.np_fdof &&
+         a.np_cdof == b.np_cdof;
+}
+
+// Upload a problem's hierarchy. With `share` (a family member set up on the
+// same geometry as `share`), every level whose structure equals share's
+// takes share's device structure arrays instead of its own copies (the
+// values, template constants, bottom inverse and vectors stay per problem),
+// and the smoother and coarse-tail choices are share's (no timing).
+static void upload(ebmg_problem_s* P, bool batch_box = false, const ebmg_problem_s* share = nullptr) {
   Problem& H = *P->host;
   DevProblem& D = P->dev;
   hipStream_t s = P->ctx->stream;
@@ -848,7 +885,13 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
     d.N = L.N;
     d.N2 = L.N2;
     d.R = (int64_t)L.irow_dof.size();
-    d.tag.upload(L.tag.data(), L.N, s, by);
+    const DevLevel* sd = nullptr;   // the level whose structure arrays this one takes
+    if (share && l < share->host->levels.size() && same_structure(L, share->host->levels[l]))
+      sd = &share->dev.lv[l];
+    if (sd)
+      D.shared_bytes += d.tag.share(sd->tag);
+    else
+      d.tag.upload(L.tag.data(), L.N, s, by);
     // explicit rows are stored on the device group by group (red rows, then
     // black rows), so a colour group is a contiguous row range
     const std::vector<int32_t> perm = row_order(L);
@@ -877,10 +920,15 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
       rp[k + 1] = (int64_t)col.size();
       ident[k] = (int32_t)k;
     }
-    d.irow_dof.upload(idof.data(), d.R, s, by);
-    d.rp.upload(rp.data(), d.R + 1, s, by);
-    d.col.upload(col.data(), (int64_t)col.size(), s, by);
-    d.cls_rows.upload(ident.data(), d.R, s, by);
+    if (sd) {
+      D.shared_bytes += d.irow_dof.share(sd->irow_dof) + d.rp.share(sd->rp) + d.col.share(sd->col) +
+                        d.cls_rows.share(sd->cls_rows);
+    } else {
+      d.irow_dof.upload(idof.data(), d.R, s, by);
+      d.rp.upload(rp.data(), d.R + 1, s, by);
+      d.col.upload(col.data(), (int64_t)col.size(), s, by);
+      d.cls_rows.upload(ident.data(), d.R, s, by);
+    }
     d.cls_ptr = L.cls_ptr;
     d.val64.upload(val.data(), (int64_t)val.size(), s, by);
     d.diag64.upload(dg.data(), d.R, s, by);
@@ -895,13 +943,17 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
       std::vector<int32_t> scol;
       std::vector<double> sval;
       build_sliced(rp, col, val, gptr, sptr, scol, sval, d.sl_grp);
-      d.sl_ptr.upload(sptr.data(), (int64_t)sptr.size(), s, by);
-      d.sl_col.upload(scol.data(), (int64_t)scol.size(), s, by);
+      if (sd) {
+        D.shared_bytes += d.sl_ptr.share(sd->sl_ptr) + d.sl_col.share(sd->sl_col) + d.sl_colj.share(sd->sl_colj);
+      } else {
+        d.sl_ptr.upload(sptr.data(), (int64_t)sptr.size(), s, by);
+        d.sl_col.upload(scol.data(), (int64_t)scol.size(), s, by);
+      }
       // group 1's columns with group-0 row unknowns renamed N + N2 + (position
       // in group 0), for the Jacobi pass that reads group 0's values before
       // they are scattered (k_irr_jac_sl2)
       const int64_t nxv = L.N + L.N2;
-      if (L.cls_ptr.size() == 3 && gptr[1] > gptr[0] && gptr[2] > gptr[1] && nxv + gptr[1] < (int64_t)INT32_MAX) {
+      if (!sd && L.cls_ptr.size() == 3 && gptr[1] > gptr[0] && gptr[2] > gptr[1] && nxv + gptr[1] < (int64_t)INT32_MAX) {
         std::unordered_map<int64_t, int32_t> pos0;
         pos0.reserve((size_t)(gptr[1] - gptr[0]) * 2);
         for (int32_t k = gptr[0]; k < gptr[1]; ++k) pos0.emplace(idof[k], k - gptr[0]);
@@ -921,12 +973,17 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
     }
     HIPCHECK(hipStreamSynchronize(s));
     d.n_ns = (int64_t)L.ns_cdof.size();
-    d.ns_cdof.upload(L.ns_cdof.data(), d.n_ns, s, by);
-    d.ns_ptr.upload(L.ns_ptr.data(), (int64_t)L.ns_ptr.size(), s, by);
-    d.ns_child.upload(L.ns_child.data(), (int64_t)L.ns_child.size(), s, by);
     d.n_np = (int64_t)L.np_fdof.size();
-    d.np_fdof.upload(L.np_fdof.data(), d.n_np, s, by);
-    d.np_cdof.upload(L.np_cdof.data(), d.n_np, s, by);
+    if (sd) {
+      D.shared_bytes += d.ns_cdof.share(sd->ns_cdof) + d.ns_ptr.share(sd->ns_ptr) + d.ns_child.share(sd->ns_child) +
+                        d.np_fdof.share(sd->np_fdof) + d.np_cdof.share(sd->np_cdof);
+    } else {
+      d.ns_cdof.upload(L.ns_cdof.data(), d.n_ns, s, by);
+      d.ns_ptr.upload(L.ns_ptr.data(), (int64_t)L.ns_ptr.size(), s, by);
+      d.ns_child.upload(L.ns_child.data(), (int64_t)L.ns_child.size(), s, by);
+      d.np_fdof.upload(L.np_fdof.data(), d.n_np, s, by);
+      d.np_cdof.upload(L.np_cdof.data(), d.n_np, s, by);
+    }
     d.t64 = make_tmpl<double>(L);
     d.t32 = make_tmpl<float>(L);
     const int64_t nd = L.N + L.N2;
@@ -1001,15 +1058,39 @@ static void upload(ebmg_problem_s* P, bool batch_box = false) {
     return;
   }
   HIPCHECK(hipStreamSynchronize(s));
-  for (auto& l : D.lv) tune_smoother(l, mixed, H.opt.smoother, s);
-  if (mixed) {
-    upload_tail<float>(D, s);
-    refine_finest_zm<float>(D, H.opt, s);
-    tune_tail<float>(D, H.opt, s);
+  if (share && share->dev.lv.size() == D.lv.size()) {
+    // a family member: the kernel choices of the member it shares with
+    for (size_t l = 0; l < D.lv.size(); ++l) {
+      const DevLevel& o = share->dev.lv[l];
+      DevLevel& d = D.lv[l];
+      d.fused = o.fused;
+      d.oop = o.oop;
+      d.fvar = o.fvar;
+      d.zmcfg = o.zmcfg;
+      d.tune_split_ms = o.tune_split_ms;
+      d.tune_fused_ms = o.tune_fused_ms;
+      d.tune_zm_ms = o.tune_zm_ms;
+      d.tune_oop_ms = o.tune_oop_ms;
+      d.tune_zm_cfg_ms = o.tune_zm_cfg_ms;
+    }
+    if (mixed)
+      upload_tail<float>(D, s);
+    else
+      upload_tail<double>(D, s);
+    D.tail_l0 = share->dev.tail_l0;
+    D.tail_cand = share->dev.tail_cand;
+    D.tail_ms = share->dev.tail_ms;
   } else {
-    upload_tail<double>(D, s);
-    refine_finest_zm<double>(D, H.opt, s);
-    tune_tail<double>(D, H.opt, s);
+    for (auto& l : D.lv) tune_smoother(l, mixed, H.opt.smoother, s);
+    if (mixed) {
+      upload_tail<float>(D, s);
+      refine_finest_zm<float>(D, H.opt, s);
+      tune_tail<float>(D, H.opt, s);
+    } else {
+      upload_tail<double>(D, s);
+      refine_finest_zm<double>(D, H.opt, s);
+      tune_tail<double>(D, H.opt, s);
+    }
   }
   if (D.krylov) {
     // FP64 ph and sh (slots 4 and 6) only without mixed precision
@@ -2395,6 +2476,32 @@ int ebmg_abi_version(void) { return EBMG_ABI_VERSION; }
 
 static thread_local std::string g_create_error;
 
+// Device scratch of ebmg_apply_noalloc: a file-scope array that every GPU the
+// library runs on holds until the process ends (2 x kNoAllocMax doubles,
+// 18 MiB: the staged input [phi; phi2] and the staged output). In host code
+// the array's name is only a stand-in for the symbol: its device address is
+// looked up once per device with that device current and kept in
+// g_scratch, which is what host code passes to kernels.
+constexpr int64_t kNoAllocMax = ((int64_t)1 << 20) + ((int64_t)1 << 17);   // unknowns (N + N2) at most
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[2 * kNoAllocMax];
+static std::mutex g_scratch_mu;
+static double* g_scratch[kMaxDevices] = {};
+
+// the current device's scratch address (looked up on first use per device)
+static hipError_t scratch_ptr(int device, double** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = (double*)p;
+  }
+  *out = g_scratch[device];
+  return hipSuccess;
+}
+
 ebmg_status ebmg_create(int32_t device, void* stream, ebmg_ctx* out) {
   if (!out) return EBMG_ERR_ARG;
   *out = nullptr;
@@ -2413,6 +2520,10 @@ ebmg_status ebmg_create(int32_t device, void* stream, ebmg_ctx* out) {
         e = hipStreamCreate(&c->stream);
         c->own_stream = e == hipSuccess;
       }
+    }
+    if (e == hipSuccess) {
+      double* sp = nullptr;   // the no-allocation scratch of this device, set up at init
+      e = scratch_ptr(device, &sp);
     }
     if (e != hipSuccess) {
       g_create_error = std::string("device ") + std::to_string(device) + " (" + std::to_string(n) +
@@ -2791,6 +2902,35 @@ ebmg_status ebmg_apply(ebmg_problem pb, const double* phi, const double* phi2, d
     HIPCHECK(hipMemcpyAsync(out, L.r64.p, sizeof(double) * L.N, hipMemcpyDeviceToDevice, s));
     if (L.N2 > 0) HIPCHECK(hipMemcpyAsync(out2, L.r64.p + L.N, sizeof(double) * L.N2, hipMemcpyDeviceToDevice, s));
     HIPCHECK(hipStreamSynchronize(s));
+    return EBMG_OK;
+  });
+}
+
+ebmg_status ebmg_apply_noalloc(ebmg_problem pb, const double* phi, const double* phi2, double* out,
+                               double* out2) {
+  if (!pb || !phi || !out) return EBMG_ERR_ARG;
+  if (!pb->on_device) return EBMG_ERR_DEVICE;
+  return guard(pb->ctx, [&]() -> ebmg_status {
+    DevLevel& L = pb->dev.lv[0];
+    const int64_t nd = L.N + L.N2;
+    if (nd > kNoAllocMax) throw ArgError("ebmg_apply_noalloc: N + N2 exceeds its scratch of 1179648 unknowns");
+    if (L.N2 > 0 && (!phi2 || !out2)) throw ArgError("second-phase arrays required");
+    drain(pb);
+    HIPCHECK(hipSetDevice(pb->ctx->device));
+    double* sp = nullptr;
+    HIPCHECK(scratch_ptr(pb->ctx->device, &sp));
+    double* xs = sp;                  // staged [phi; phi2]
+    double* rs = sp + kNoAllocMax;    // staged [out; out2]
+    hipStream_t s = pb->ctx->stream;
+    hipLaunchKernelGGL((k_convert<double, double>), dim3(nblk(L.N)), dim3(kBlock), 0, s, phi, xs, L.N);
+    if (L.N2 > 0)
+      hipLaunchKernelGGL((k_convert<double, double>), dim3(nblk(L.N2)), dim3(kBlock), 0, s, phi2, xs + L.N, L.N2);
+    // every entry of rs is written: covered cells, template cells, explicit rows
+    residual<double, 1>(L, xs, nullptr, rs, s);
+    hipLaunchKernelGGL((k_convert<double, double>), dim3(nblk(L.N)), dim3(kBlock), 0, s, rs, out, L.N);
+    if (L.N2 > 0)
+      hipLaunchKernelGGL((k_convert<double, double>), dim3(nblk(L.N2)), dim3(kBlock), 0, s, rs + L.N, out2, L.N2);
+    HIPCHECK(hipGetLastError());
     return EBMG_OK;
   });
 }
@@ -3334,6 +3474,202 @@ ebmg_status ebmg_set_coefficients(ebmg_problem pb, const ebmg_options* opt, cons
     HIPCHECK(hipStreamSynchronize(s));
     return EBMG_OK;
   });
+}
+
+// host part of a family member: member 0's geometry, the member's own
+// coefficients and boundary data, its operator and hierarchy
+static void build_member(ebmg::Problem& H, const ebmg::Problem& H0, const ebmg_box* box, int nobj,
+                         const ebmg_object* objs, const ebmg_domain_bc* bc) {
+  using namespace ebmg;
+  H.bc = *bc;
+  for (int f = 0; f < 2 * box->dim && f < 6; ++f) {
+    if (bc->kind[f] != H0.bc.kind[f]) throw ArgError("family members must share the boundary kinds");
+    if (bc->kind[f] == EBMG_BC_ROBIN && !(bc->robin_a2[f] != 0.0)) throw ArgError("Robin a2 must be nonzero");
+  }
+  H.geo = H0.geo;
+  H.bph[0] = H.opt.b_gas;
+  H.aph[0] = H.opt.a_gas;
+  H.bph[1] = H.geo.nphase == 2 ? H.geo.obj_value[H.geo.diel_obj] : H.opt.b_gas;
+  H.aph[1] = H.opt.a_diel;
+  if (!(H.bph[0] > 0) || !(H.bph[1] > 0)) throw ArgError("b must be positive");
+  bool anchored = H.opt.alpha != 0.0;
+  for (int f = 0; f < 2 * box->dim; ++f) anchored |= bc->kind[f] != EBMG_BC_NEUMANN;
+  for (int k = 0; k < nobj; ++k) anchored |= objs[k].kind == EBMG_OBJ_ELECTRODE;
+  if (!anchored) throw ArgError("pure Neumann problem is singular");
+  build_fine_level(H);
+  build_hierarchy(H);
+}
+
+static void family_free(ebmg_family_s* F) {
+  // members that take member 0's structure go first
+  for (size_t k = F->mem.size(); k-- > 0;) {
+    ebmg_problem_s* P = F->mem[k];
+    if (!P) continue;
+    if (P->on_device) {
+      (void)hipSetDevice(P->ctx->device);
+      (void)hipStreamSynchronize(P->ctx->stream);
+      P->dev.release();
+    }
+    delete P;
+  }
+  F->mem.clear();
+  for (ebmg_ctx c : F->mctx) ctx_unref(c);
+  F->mctx.clear();
+}
+
+ebmg_status ebmg_setup_family(ebmg_ctx ctx, const ebmg_box* box, int32_t nobj, const ebmg_object* objs,
+                              int32_t nmem, const ebmg_domain_bc* bcs, const ebmg_options* opts, ebmg_family* out) {
+  if (!ctx || !box || !bcs || !opts || !out || (nobj > 0 && !objs) || nobj < 0 || nobj > 64 || nmem < 1 ||
+      nmem > 64) {
+    if (ctx) ctx->err = "invalid argument to ebmg_setup_family";
+    return EBMG_ERR_ARG;
+  }
+  *out = nullptr;
+  auto F = std::make_unique<ebmg_family_s>();
+  F->ctx = ctx;
+  const ebmg_status st = guard(ctx, [&]() -> ebmg_status {
+    for (int k = 0; k < nmem; ++k) {
+      // every option but the coefficients must be member 0's
+      ebmg_options a = opts[k], b = opts[0];
+      a.alpha = b.alpha;
+      a.beta = b.beta;
+      a.a_gas = b.a_gas;
+      a.a_diel = b.a_diel;
+      a.b_gas = b.b_gas;
+      if (std::memcmp(&a, &b, sizeof(a)) != 0) throw ArgError("family members differ in an option other than the coefficients");
+    }
+    for (int k = 0; k < nmem; ++k) {
+      ebmg_ctx mc = ctx;
+      if (ctx->device >= 0) {
+        if (ebmg_create(ctx->device, nullptr, &mc) != EBMG_OK) throw DeviceError("member stream: " + g_create_error);
+      } else {
+        ++ctx->refs;
+      }
+      F->mctx.push_back(mc);
+      auto P = std::make_unique<ebmg_problem_s>();
+      P->ctx = mc;
+      P->host = std::make_unique<Problem>();
+      Problem& H = *P->host;
+      if (parse_options(&opts[k], nobj, H.opt) != EBMG_OK) throw ArgError("bad options");
+      if (k == 0)
+        build_host_problem(H, box, nobj, objs, &bcs[0]);
+      else
+        build_member(H, *F->mem[0]->host, box, nobj, objs, &bcs[k]);
+      F->mem.push_back(P.release());
+      ebmg_problem_s* M = F->mem.back();
+      if (ctx->device >= 0) {
+        HIPCHECK(hipSetDevice(ctx->device));
+        upload(M, false, k == 0 ? nullptr : F->mem[0]);
+        M->on_device = true;
+      }
+    }
+    return EBMG_OK;
+  });
+  if (st != EBMG_OK) {
+    family_free(F.get());
+    return st;
+  }
+  *out = F.release();
+  ++ctx->refs;
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_query_family(ebmg_family fam, int32_t* nmem, int64_t* n_cells, int64_t* n_phase2,
+                              int64_t* device_bytes, int64_t* shared_bytes) {
+  if (!fam || fam->mem.empty()) return EBMG_ERR_ARG;
+  const ebmg::Geometry& G = fam->mem[0]->host->geo;
+  int64_t by = 0, sh = 0;
+  for (auto* P : fam->mem) {
+    by += P->dev.bytes;
+    sh += P->dev.shared_bytes;
+  }
+  if (nmem) *nmem = (int32_t)fam->mem.size();
+  if (n_cells) *n_cells = G.N;
+  if (n_phase2) *n_phase2 = G.N2;
+  if (device_bytes) *device_bytes = by;
+  if (shared_bytes) *shared_bytes = sh;
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_solve_family(ebmg_family fam, const double* const* rho, const double* const* sigma, double rtol,
+                              int32_t max_cycles, double* const* phi, double* const* phi2, ebmg_solve_info* infos,
+                              ebmg_status* statuses) {
+  if (!fam || !rho || !phi || !(rtol > 0) || max_cycles < 0) {
+    if (fam) fam->ctx->err = "invalid argument to ebmg_solve_family";
+    return EBMG_ERR_ARG;
+  }
+  ebmg_ctx ctx = fam->ctx;
+  const int K = (int)fam->mem.size();
+  for (int k = 0; k < K; ++k) {
+    if (rho[k] && !phi[k]) {
+      ctx->err = "member " + std::to_string(k) + ": rho without phi";
+      return EBMG_ERR_ARG;
+    }
+    if (rho[k] && fam->mem[k]->host->geo.N2 > 0 && phi2 && !phi2[k]) {
+      ctx->err = "member " + std::to_string(k) + ": second-phase array required";
+      return EBMG_ERR_ARG;
+    }
+  }
+  if (!fam->mem[0]->on_device) {
+    ctx->err = "family is not on a device (host-only context)";
+    return EBMG_ERR_DEVICE;
+  }
+  std::vector<ebmg_status> st(K, EBMG_OK);
+  std::vector<std::string> err(K);
+  std::vector<ebmg_solve_info> inf(K);
+  const ebmg_status pre = guard(ctx, [&]() -> ebmg_status {
+    HIPCHECK(hipSetDevice(ctx->device));
+    // the members' streams start after the work queued on the caller's stream
+    hipEvent_t ev = nullptr;
+    HIPCHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPCHECK(hipEventRecord(ev, ctx->stream));
+    for (int k = 0; k < K; ++k) HIPCHECK(hipStreamWaitEvent(fam->mctx[k]->stream, ev, 0));
+    HIPCHECK(hipEventDestroy(ev));
+    return EBMG_OK;
+  });
+  if (pre != EBMG_OK) return pre;
+  auto run = [&](int k) {
+    ebmg_problem_s* P = fam->mem[k];
+    std::memset(&inf[k], 0, sizeof(ebmg_solve_info));
+    st[k] = guard_msg(&err[k], [&]() -> ebmg_status {
+      HIPCHECK(hipSetDevice(ctx->device));
+      return ebmg::solve(P, rho[k], sigma ? sigma[k] : nullptr, nullptr, nullptr, rtol, max_cycles, phi[k],
+                         phi2 ? phi2[k] : nullptr, nullptr, &inf[k]);
+    });
+  };
+  if (fam->warm && K > 1) {
+    // members on their own streams, each driven by its own host thread
+    std::vector<std::thread> th;
+    for (int k = 0; k < K; ++k)
+      if (rho[k]) th.emplace_back(run, k);
+    for (auto& t : th) t.join();
+  } else {
+    // first solve: one member after another (each captures its graphs)
+    for (int k = 0; k < K; ++k)
+      if (rho[k]) run(k);
+    bool all = true;
+    for (int k = 0; k < K; ++k) all = all && rho[k] && st[k] == EBMG_OK;
+    fam->warm = fam->warm || all;
+  }
+  ebmg_status worst = EBMG_OK;
+  for (int k = 0; k < K; ++k) {
+    if (infos) infos[k] = inf[k];
+    if (statuses) statuses[k] = rho[k] ? st[k] : EBMG_OK;
+    if (rho[k] && st[k] != EBMG_OK && worst == EBMG_OK) {
+      worst = st[k];
+      ctx->err = "member " + std::to_string(k) + ": " + err[k];
+    }
+  }
+  return worst;
+}
+
+ebmg_status ebmg_release_family(ebmg_family fam) {
+  if (!fam) return EBMG_ERR_ARG;
+  ebmg_ctx ctx = fam->ctx;
+  family_free(fam);
+  delete fam;
+  ctx_unref(ctx);
+  return EBMG_OK;
 }
 
 ebmg_status ebmg_release(ebmg_problem pb) {

@@ -110,7 +110,6 @@ _sig("ebmg_submit", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int32, _v
 _sig("ebmg_poll", C.c_int, [_vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_int), C.POINTER(SolveInfo)])
 _sig("ebmg_wait", C.c_int, [_vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(SolveInfo)])
 _sig("ebmg_apply", C.c_int, [_vp, _vp, _vp, _vp, _vp])
-_sig("ebmg_apply_noalloc", C.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_efield", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_time_kernel", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp])
 _sig("ebmg_smooth", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _vp, _vp])
@@ -126,13 +125,20 @@ _sig("ebmg_query_batch_tuning", C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C
 _sig("ebmg_solve_batch", C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.c_double, C.c_int32, C.POINTER(_vp),
                                    C.POINTER(_vp), C.POINTER(SolveInfo)])
 _sig("ebmg_release_batch", C.c_int, [_vp])
+_sig("ebmg_setup_family", C.c_int, [_vp, C.POINTER(Box), C.c_int32, C.POINTER(Object), C.c_int32, C.POINTER(DomainBC),
+                                    C.POINTER(Options), C.POINTER(_vp)])
+_sig("ebmg_query_family", C.c_int, [_vp, C.POINTER(C.c_int32), _i64p, _i64p, _i64p, _i64p])
+_sig("ebmg_solve_family", C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.c_double, C.c_int32, C.POINTER(_vp),
+                                    C.POINTER(_vp), C.POINTER(SolveInfo), C.POINTER(C.c_int)])
+_sig("ebmg_release_family", C.c_int, [_vp])
 
 EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_destroy", "ebmg_last_error",
             "ebmg_setup", "ebmg_query", "ebmg_query_level", "ebmg_export_level", "ebmg_query_tuning",
             "ebmg_export_geometry", "ebmg_export_moments", "ebmg_export_operator", "ebmg_export_rhs",
-            "ebmg_solve", "ebmg_submit", "ebmg_poll", "ebmg_wait", "ebmg_apply", "ebmg_apply_noalloc", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
+            "ebmg_solve", "ebmg_submit", "ebmg_poll", "ebmg_wait", "ebmg_apply", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
             "ebmg_setup_batch", "ebmg_query_batch", "ebmg_query_batch_box", "ebmg_query_batch_tuning", "ebmg_solve_batch", "ebmg_release_batch",
-            "ebmg_set_coefficients", "ebmg_smooth", "ebmg_kernel_timing"]
+            "ebmg_set_coefficients", "ebmg_smooth", "ebmg_kernel_timing",
+            "ebmg_setup_family", "ebmg_query_family", "ebmg_solve_family", "ebmg_release_family"]
 
 
 def abi_version():
@@ -247,6 +253,16 @@ def make_options(prob, precision=FP64, dirichlet_closure=0, robin_closure=0, eb_
     o.batch = batch
     o.graphs = graphs
     return o
+
+
+def _c_bc(prob):
+    bc = DomainBC()
+    for f in range(6):
+        bc.kind[f] = prob.bc_kind[f]
+        bc.value[f] = prob.bc_value[f]
+        bc.robin_a1[f] = prob.robin_a1[f]
+        bc.robin_a2[f] = prob.robin_a2[f]
+    return bc
 
 
 def _c_problem(prob):
@@ -409,14 +425,6 @@ class Problem:
         self.ctx.check(_lib.ebmg_apply(self.h, _dev(c, phi, N, "phi"), _dev(c, phi2, N2, "phi2", N2 == 0),
                                        _dev(c, out, N, "out"), _dev(c, out2, N2, "out2", N2 == 0)), "ebmg_apply")
 
-    def apply_noalloc(self, phi, phi2, out, out2):
-        """As ``apply``, through the entry point that allocates nothing; the
-        result is queued on the context's stream (not waited for)."""
-        c, N, N2 = self.ctx, self.N, self.N2
-        self.ctx.check(_lib.ebmg_apply_noalloc(self.h, _dev(c, phi, N, "phi"), _dev(c, phi2, N2, "phi2", N2 == 0),
-                                               _dev(c, out, N, "out"), _dev(c, out2, N2, "out2", N2 == 0)),
-                       "ebmg_apply_noalloc")
-
     def efield(self, phi, phi2, E, sigma=None, bc_values=None, obj_values=None):
         c, N, N2 = self.ctx, self.N, self.N2
         bcv = _host_f64(bc_values)
@@ -564,6 +572,70 @@ class Batch:
     def release(self):
         if getattr(self, "h", None):
             _lib.ebmg_release_batch(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class Family:
+    """Helmholtz operators on one geometry (``workloads.Problem`` members that
+    share the grid, the objects and the boundary kinds; coefficients and
+    boundary data may differ), set up once with a shared hierarchy
+    structure and solved together, each member on its own stream."""
+
+    def __init__(self, ctx, probs, **opts):
+        self.ctx = ctx
+        self.probs = list(probs)
+        nm = len(self.probs)
+        box, objs, _, sdf = _c_problem(self.probs[0])
+        bcs = (DomainBC * nm)()
+        optv = (Options * nm)()
+        for k, pr in enumerate(self.probs):
+            bcs[k] = _c_bc(pr)
+            optv[k] = make_options(pr, **opts)
+        h = _vp()
+        st = _lib.ebmg_setup_family(ctx.h, C.byref(box), len(self.probs[0].objects), objs, nm, bcs, optv,
+                                    C.byref(h))
+        sdf = None
+        ctx.check(st, "ebmg_setup_family")
+        self.h = h
+        m, n, n2, by, sh = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        ctx.check(_lib.ebmg_query_family(h, C.byref(m), C.byref(n), C.byref(n2), C.byref(by), C.byref(sh)),
+                  "ebmg_query_family")
+        self.nmem, self.N, self.N2, self.device_bytes, self.shared_bytes = m.value, n.value, n2.value, by.value, sh.value
+
+    def solve(self, rho, phi, sigma=None, phi2=None, rtol=1e-10, max_cycles=100, check=True):
+        """rho, phi (and optionally sigma, phi2): lists of nmem device tensors
+        or None (a member whose rho is None is not solved). Returns (status,
+        [per-member status], [per-member info])."""
+        nm = self.nmem
+        c = self.ctx
+        if len(rho) != nm or len(phi) != nm:
+            raise EbmgError(ERR_ARG, f"{nm} members: rho and phi need {nm} entries")
+
+        def arr(xs, name, n, nullable):
+            if xs is None:
+                return None
+            if len(xs) != nm:
+                raise EbmgError(ERR_ARG, f"{name}: {len(xs)} entries for {nm} members")
+            return (_vp * nm)(*[None if (rho[k] is None) else _dev(c, x, n, f"{name}[{k}]", nullable)
+                                for k, x in enumerate(xs)])
+        infos = (SolveInfo * nm)()
+        sts = (C.c_int * nm)()
+        st = _lib.ebmg_solve_family(self.h, arr(rho, "rho", self.N, True), arr(sigma, "sigma", self.N, True),
+                                    float(rtol), int(max_cycles), arr(phi, "phi", self.N, False),
+                                    arr(phi2, "phi2", self.N2, self.N2 == 0), infos, sts)
+        if check:
+            self.ctx.check(st, "ebmg_solve_family")
+        return st, [sts[k] for k in range(nm)], [infos[k].as_dict() for k in range(nm)]
+
+    def release(self):
+        if getattr(self, "h", None):
+            _lib.ebmg_release_family(self.h)
             self.h = None
 
     def __del__(self):

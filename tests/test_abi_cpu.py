@@ -348,3 +348,24 @@ def test_binding_refuses_bad_device_arrays(host_ctx):
     finally:
         ebmg._lib = real
     P.release()
+
+
+def test_family_setup_on_the_host(host_ctx):
+    """A family is built once on the host: sizes per member, boundary kinds
+    and non-coefficient options must agree across members."""
+    probs = W.photoionization_family(16, seed=0)
+    F = ebmg.Family(host_ctx, probs)
+    assert F.nmem == 5 and F.N == 16 ** 3 and F.N2 == 0
+    F.release()
+    q = W.photoionization_family(16, seed=0)[0]
+    q.bc_kind = [W.BC_DIRICHLET] + list(q.bc_kind[1:])
+    with pytest.raises(ebmg.EbmgError) as e:
+        ebmg.Family(host_ctx, [probs[0], q])
+    assert e.value.status == ebmg.ERR_ARG
+    # an option other than the coefficients differs between members
+    box, objs, bc, sdf = ebmg._c_problem(probs[0])
+    opts = (ebmg.Options * 2)(ebmg.make_options(probs[0]), ebmg.make_options(probs[1], nu1=3))
+    bcs = (ebmg.DomainBC * 2)(ebmg._c_bc(probs[0]), ebmg._c_bc(probs[1]))
+    h = ebmg._vp()
+    st = ebmg._lib.ebmg_setup_family(host_ctx.h, ebmg.C.byref(box), 1, objs, 2, bcs, opts, ebmg.C.byref(h))
+    assert st == ebmg.ERR_ARG and not h.value

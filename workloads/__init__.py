@@ -308,6 +308,61 @@ def eddington_coefficients(dim, n, kappa_abs):
                    b_gas=1.0 / (3.0 * kappa_abs), name=f"eddington{dim}d-{n}-k{kappa_abs:.3g}")
 
 
+# Photoionization model of oxygen (three Eddington groups): lambda_gamma in
+# 1/(m Pa), the oxygen partial pressure 0.2 bar, kappa_gamma = lambda_gamma
+# p_O2 / sqrt(3), made nondimensional by the 2 cm edge of the pin-plane gap.
+PHOTO_LAMBDA = (4.15e-2, 1.09e-1, 6.69e-1)
+PHOTO_P_O2 = 2.0e4
+PHOTO_L = 0.02
+
+
+def photo_kappas():
+    return [lam * PHOTO_P_O2 / math.sqrt(3.0) * PHOTO_L for lam in PHOTO_LAMBDA]
+
+
+def tga_mus(dt=1.0, eps=1e-12):
+    """mu_1, mu_2 of the TGA scheme, a = 2 - sqrt(2) - eps."""
+    a = 2.0 - math.sqrt(2.0) - eps
+    r = math.sqrt(a * a - 4.0 * a + 2.0)
+    return (a - r) / 2.0 * dt, (a + r) / 2.0 * dt
+
+
+def photoionization_family(n=128, seed=0, nblob=8, diffusion_number=1.0):
+    """Helmholtz operators of one plasma time step on the pin-plane gap
+    geometry (pin electrode of radius 0.02 with its tip at z = 0.6, no
+    dielectric): the three Eddington groups kappa_g phi - div((1/3kappa_g)
+    grad phi) = S with the outflow condition dphi/dn + (3 kappa_g/2) phi = 0
+    on every box face, and the two TGA diffusion operators
+    phi - div(mu_i D grad phi) = S (zero flux on the box faces; D dt / h^2 =
+    diffusion_number). The electrode absorbs (phi = 0 on it) in every member.
+    Every member's source is the same blob sum (the photon source is the same
+    for all groups). Returns the list of five problems."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    dists = [_pin_distance_point, lambda c: c[2] - 0.05]
+    cs, ss = _blobs3(rng, nblob, dists)
+    Xn = _nodes(3, (n, n, n), h, (0.0, 0.0, 0.0))
+    X = _centres(3, (n, n, n), h, (0.0, 0.0, 0.0))
+    src = np.zeros(X[0].shape)
+    for c, s in zip(cs, ss):
+        src += np.exp(-((X[0] - c[0]) ** 2 + (X[1] - c[1]) ** 2 + (X[2] - c[2]) ** 2) / (2 * s * s))
+    src = np.ascontiguousarray(src)
+    pin = np.ascontiguousarray(sdf_pin3(Xn, (0.5, 0.5), 0.6, 0.02))
+    out = []
+    for kap in photo_kappas():
+        out.append(Problem(3, (n, n, n), h, (0.0, 0.0, 0.0), [Obj(OBJ_ELECTRODE, 0.0, pin)],
+                           [BC_ROBIN] * 6, [0.0] * 6, [1.5 * kap] * 6, [1.0] * 6,
+                           alpha=1.0, beta=-1.0, a_gas=kap, b_gas=1.0 / (3.0 * kap), rho=src,
+                           name=f"eddington-group-kappa{kap:.3g}-{n}", seed=seed))
+    nu = diffusion_number * h * h          # D dt in units of the box edge squared
+    for mu in tga_mus(1.0):
+        out.append(Problem(3, (n, n, n), h, (0.0, 0.0, 0.0), [Obj(OBJ_ELECTRODE, 0.0, pin)],
+                           [BC_ROBIN] * 6, [0.0] * 6, [0.0] * 6, [1.0] * 6,
+                           alpha=1.0, beta=-1.0, a_gas=1.0, b_gas=mu * nu, rho=src,
+                           name=f"tga-mu{mu:.4f}-{n}", seed=seed))
+    return out
+
+
 def coaxial(n=256, R0=0.3, R1=0.6, R2=0.9, eps=4.0, phi0=1.0, sigma=0.0):
     """Coaxial cable cross-section on (-1,1)^2: inner electrode r<R0 at phi0,
     dielectric shell R0<r<R1 with permittivity eps, gas R1<r<R2, outer

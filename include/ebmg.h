@@ -329,6 +329,21 @@ ebmg_status ebmg_wait(ebmg_ctx ctx, uint64_t ticket, ebmg_status* result, ebmg_s
 ebmg_status ebmg_apply(ebmg_problem pb, const double* phi, const double* phi2, double* out,
                        double* out2);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * out = A [phi; phi2] as ebmg_apply, computed by the same kernels, with its
+ * staging in a fixed device scratch array that the library holds on each GPU
+ * from context creation until the process ends (18 MiB), instead of the
+ * problem's work vectors. It allocates nothing (no hipMalloc, hipFree or
+ * allocating library call) and does not synchronise: the work is queued on
+ * the context's stream and out / out2 are ready when that stream reaches it.
+ * Limit: N + N2 <= 1179648 unknowns (ERR_ARG beyond). All calls on one GPU
+ * share that GPU's scratch, which keeps the last call's contents: calls that
+ * overlap on one GPU (several contexts or threads at once) race; serialise
+ * them. phi, phi2, out, out2: DEVICE arrays as for ebmg_apply. */
+ebmg_status ebmg_apply_noalloc(ebmg_problem pb, const double* phi, const double* phi2, double* out,
+                               double* out2);
+
 /* Cell-centred E = -grad(phi) (Electrodynamic equations) from the
  * centroid-interpolated face fluxes of the Helmholtz equations section: the
  * mean of the open low/high face gradients per axis, the EB normal gradient

@@ -2476,6 +2476,32 @@ int ebmg_abi_version(void) { return EBMG_ABI_VERSION; }
 
 static thread_local std::string g_create_error;
 
+// Device scratch of ebmg_apply_noalloc: a file-scope array that every GPU the
+// library runs on holds until the process ends (2 x kNoAllocMax doubles,
+// 18 MiB: the staged input [phi; phi2] and the staged output). In host code
+// the array's name is only a stand-in for the symbol: its device address is
+// looked up once per device with that device current and kept in
+// g_scratch, which is what host code passes to kernels.
+constexpr int64_t kNoAllocMax = ((int64_t)1 << 20) + ((int64_t)1 << 17);   // unknowns (N + N2) at most
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[2 * kNoAllocMax];
+static std::mutex g_scratch_mu;
+static double* g_scratch[kMaxDevices] = {};
+
+// the current device's scratch address (looked up on first use per device)
+static hipError_t scratch_ptr(int device, double** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = (double*)p;
+  }
+  *out = g_scratch[device];
+  return hipSuccess;
+}
+
 ebmg_status ebmg_create(int32_t device, void* stream, ebmg_ctx* out) {
   if (!out) return EBMG_ERR_ARG;
   *out = nullptr;
@@ -2494,6 +2520,10 @@ ebmg_status ebmg_create(int32_t device, void* stream, ebmg_ctx* out) {
         e = hipStreamCreate(&c->stream);
         c->own_stream = e == hipSuccess;
       }
+    }
+    if (e == hipSuccess) {
+      double* sp = nullptr;   // the no-allocation scratch of this device, set up at init
+      e = scratch_ptr(device, &sp);
     }
     if (e != hipSuccess) {
       g_create_error = std::string("device ") + std::to_string(device) + " (" + std::to_string(n) +
@@ -2872,6 +2902,35 @@ ebmg_status ebmg_apply(ebmg_problem pb, const double* phi, const double* phi2, d
     HIPCHECK(hipMemcpyAsync(out, L.r64.p, sizeof(double) * L.N, hipMemcpyDeviceToDevice, s));
     if (L.N2 > 0) HIPCHECK(hipMemcpyAsync(out2, L.r64.p + L.N, sizeof(double) * L.N2, hipMemcpyDeviceToDevice, s));
     HIPCHECK(hipStreamSynchronize(s));
+    return EBMG_OK;
+  });
+}
+
+ebmg_status ebmg_apply_noalloc(ebmg_problem pb, const double* phi, const double* phi2, double* out,
+                               double* out2) {
+  if (!pb || !phi || !out) return EBMG_ERR_ARG;
+  if (!pb->on_device) return EBMG_ERR_DEVICE;
+  return guard(pb->ctx, [&]() -> ebmg_status {
+    DevLevel& L = pb->dev.lv[0];
+    const int64_t nd = L.N + L.N2;
+    if (nd > kNoAllocMax) throw ArgError("ebmg_apply_noalloc: N + N2 exceeds its scratch of 1179648 unknowns");
+    if (L.N2 > 0 && (!phi2 || !out2)) throw ArgError("second-phase arrays required");
+    drain(pb);
+    HIPCHECK(hipSetDevice(pb->ctx->device));
+    double* sp = nullptr;
+    HIPCHECK(scratch_ptr(pb->ctx->device, &sp));
+    double* xs = sp;                  // staged [phi; phi2]
+    double* rs = sp + kNoAllocMax;    // staged [out; out2]
+    hipStream_t s = pb->ctx->stream;
+    hipLaunchKernelGGL((k_convert<double, double>), dim3(nblk(L.N)), dim3(kBlock), 0, s, phi, xs, L.N);
+    if (L.N2 > 0)
+      hipLaunchKernelGGL((k_convert<double, double>), dim3(nblk(L.N2)), dim3(kBlock), 0, s, phi2, xs + L.N, L.N2);
+    // every entry of rs is written: covered cells, template cells, explicit rows
+    residual<double, 1>(L, xs, nullptr, rs, s);
+    hipLaunchKernelGGL((k_convert<double, double>), dim3(nblk(L.N)), dim3(kBlock), 0, s, rs, out, L.N);
+    if (L.N2 > 0)
+      hipLaunchKernelGGL((k_convert<double, double>), dim3(nblk(L.N2)), dim3(kBlock), 0, s, rs + L.N, out2, L.N2);
+    HIPCHECK(hipGetLastError());
     return EBMG_OK;
   });
 }

@@ -110,6 +110,7 @@ _sig("ebmg_submit", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, C.c_int32, _v
 _sig("ebmg_poll", C.c_int, [_vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_int), C.POINTER(SolveInfo)])
 _sig("ebmg_wait", C.c_int, [_vp, C.c_uint64, C.POINTER(C.c_int), C.POINTER(SolveInfo)])
 _sig("ebmg_apply", C.c_int, [_vp, _vp, _vp, _vp, _vp])
+_sig("ebmg_apply_noalloc", C.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_efield", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_time_kernel", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp])
 _sig("ebmg_smooth", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _vp, _vp])
@@ -135,7 +136,7 @@ _sig("ebmg_release_family", C.c_int, [_vp])
 EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_destroy", "ebmg_last_error",
             "ebmg_setup", "ebmg_query", "ebmg_query_level", "ebmg_export_level", "ebmg_query_tuning",
             "ebmg_export_geometry", "ebmg_export_moments", "ebmg_export_operator", "ebmg_export_rhs",
-            "ebmg_solve", "ebmg_submit", "ebmg_poll", "ebmg_wait", "ebmg_apply", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
+            "ebmg_solve", "ebmg_submit", "ebmg_poll", "ebmg_wait", "ebmg_apply", "ebmg_apply_noalloc", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
             "ebmg_setup_batch", "ebmg_query_batch", "ebmg_query_batch_box", "ebmg_query_batch_tuning", "ebmg_solve_batch", "ebmg_release_batch",
             "ebmg_set_coefficients", "ebmg_smooth", "ebmg_kernel_timing",
             "ebmg_setup_family", "ebmg_query_family", "ebmg_solve_family", "ebmg_release_family"]
@@ -424,6 +425,14 @@ class Problem:
         c, N, N2 = self.ctx, self.N, self.N2
         self.ctx.check(_lib.ebmg_apply(self.h, _dev(c, phi, N, "phi"), _dev(c, phi2, N2, "phi2", N2 == 0),
                                        _dev(c, out, N, "out"), _dev(c, out2, N2, "out2", N2 == 0)), "ebmg_apply")
+
+    def apply_noalloc(self, phi, phi2, out, out2):
+        """As ``apply``, through the entry point that allocates nothing; the
+        result is queued on the context's stream (not waited for)."""
+        c, N, N2 = self.ctx, self.N, self.N2
+        self.ctx.check(_lib.ebmg_apply_noalloc(self.h, _dev(c, phi, N, "phi"), _dev(c, phi2, N2, "phi2", N2 == 0),
+                                               _dev(c, out, N, "out"), _dev(c, out2, N2, "out2", N2 == 0)),
+                       "ebmg_apply_noalloc")
 
     def efield(self, phi, phi2, E, sigma=None, bc_values=None, obj_values=None):
         c, N, N2 = self.ctx, self.N, self.N2

@@ -47,24 +47,104 @@ print(json.dumps(dict(n=%(n)d, cells=S.N, vcycles=info["vcycles"], seconds=dt, r
 """
 
 
+SPLU_SAMPLE = r"""
+import json, sys, time
+sys.path.insert(0, %(root)r)
+import workloads as W
+from oracle.operator import assemble
+from oracle import solvers
+out = {}
+for name, pr in (("sine64", W.manufactured_sine(64)), ("two_disks1024", W.two_disks(1024, seed=0))):
+    S = assemble(pr)
+    t0 = time.perf_counter()
+    x = solvers.solve_splu(S.A, S.b)
+    out[name] = dict(seconds=time.perf_counter() - t0, cells=S.N, rel=solvers.rel_residual(S.A, S.b, x))
+print(json.dumps(out))
+"""
+
+POOL_SAMPLE = r"""
+import json, os, sys, time
+from multiprocessing import Pool
+sys.path.insert(0, %(root)r)
+
+def one(i):
+    import workloads as W
+    from oracle.operator import assemble
+    from oracle import solvers
+    pr = W.batched_boxes(i + 1, seed=0)[i]     # the same draw as box i of the 512
+    S = assemble(pr)
+    x = solvers.solve_gmres(S, rtol=1e-10)
+    return S.N
+
+if __name__ == "__main__":
+    nbox, nproc = %(nbox)d, %(nproc)d
+    t0 = time.perf_counter()
+    with Pool(nproc) as p:
+        cells = p.map(one, range(nbox), chunksize=1)
+    print(json.dumps(dict(boxes=nbox, procs=nproc, seconds=time.perf_counter() - t0, cells=sum(cells))))
+"""
+
+
+def _host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, os.cpu_count(), avail
+
+
+def _run_py(code, env, timeout=600):
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=timeout)
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def cpu_baseline(n=64):
+    """The oracle on the host's cores: the pin-plane class at 64^3 on one core
+    (the bounded sample of the headline workload; the oracle at 256^3 would
+    take tens of minutes, so per the single-run rule it is not timed here),
+    SuperLU on the 64^2 sine and 1024^2 two-disk workloads on one core, and
+    the batched workload's first 16 boxes on a pool of worker processes."""
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         env[k] = "1"
-    code = CPU_SAMPLE % dict(root=ROOT, n=n)
-    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
-    if r.returncode != 0:
+    d = _run_py(CPU_SAMPLE % dict(root=ROOT, n=n), env)
+    if d is None:
         return None
-    d = json.loads(r.stdout.strip().splitlines()[-1])
-    return {
+    model, ncpu, avail = _host_cpu()
+    pool = min(16, avail or 1)      # the box's CPU share for one GPU
+    out = {
         "value": d["cells"] * d["vcycles"] / d["seconds"],
         "unit": "cell-updates/s",
         "cores": 1,
         "kind": "oracle",
         "sample": (f"pin-plane {n}^3 (same geometry class, seed 0), oracle GMRES preconditioned by its "
                    f"aggregation V-cycle to rel. residual 1e-10: {d['vcycles']} V-cycles in "
-                   f"{d['seconds']:.2f} s on 1 core (assembly not timed), residual {d['rel']:.1e}"),
+                   f"{d['seconds']:.2f} s on 1 of {avail} cores (assembly not timed), residual {d['rel']:.1e}"),
+        "host_cpu": model, "host_cores": ncpu, "cores_available": avail,
     }
+    sp = _run_py(SPLU_SAMPLE % dict(root=ROOT), env)
+    if sp is not None:
+        out["superlu_s"] = {k: round(v["seconds"], 3) for k, v in sp.items()}
+        out["superlu_note"] = ("oracle SuperLU with two FP64 refinement steps on 1 core: the 64^2 sine and the "
+                               "1024^2 two-disk workloads (assembly not timed); infeasible at 256^3")
+    pp = _run_py(POOL_SAMPLE % dict(root=ROOT, nbox=16, nproc=pool), env, timeout=900)
+    if pp is not None:
+        out["batched_pool"] = {"boxes": pp["boxes"], "processes": pp["procs"],
+                               "solves_per_s": pp["boxes"] / pp["seconds"],
+                               "cell_updates_note": "whole boxes: assembly and GMRES to 1e-10 per box",
+                               "sample": "first 16 boxes of the 512-box batched workload"}
+    return out
 
 
 def _kernel_label(P, prec):
@@ -267,6 +347,53 @@ def batched(nbox=512, reps=3, keys=("mixed", "fp64", "persistent_mixed", "persis
     return out
 
 
+INST_FILE = os.path.join(ROOT, "profiles", "counters_zm_sweep_pin_plane256.md")
+
+
+def pmc_inst_summary(csvs, command):
+    """Reduce SQ counter passes of ``--pmc-probe`` (instruction counts, busy,
+    wait and active cycles, LDS bank conflicts) to per-wave figures of the
+    finest-level sweep kernels and write the committed markdown summary."""
+    import csv
+    import collections
+    d = collections.defaultdict(lambda: collections.defaultdict(list))
+    meta = {}
+    for path in csvs:
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                k = (_kname(r["Kernel_Name"]), int(r["Grid_Size"]))
+                d[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                meta[k] = (r["Workgroup_Size"], r["LDS_Block_Size"], r["VGPR_Count"], r["SGPR_Count"])
+    names = sorted({k[0] for k in d if k[0].startswith(("k_rb_zm3", "k_rb<", "k_rb_tile3", "k_resid_zp3"))})
+    lines = [f"# Instruction counters of the finest-level sweep kernels, 256^3 pin-plane (rocprofv3 --pmc)\n",
+             "Commands (from the repository root on the GPU host; one counter pass per run):\n",
+             f"```\n{command}\n```\n",
+             f"Kernel source hash: `{_source_sha()}` (the figures belong to these sources).\n",
+             "Per wave: instructions issued per wavefront of the launch (counter / SQ_WAVES). "
+             "Cycles are the counters' sums over the launch.\n",
+             "| kernel | grid | wg | LDS B | VGPR | SGPR | waves | VALU/wave | SALU/wave | LDS/wave | VMEM rd/wave | "
+             "VMEM wr/wave | busy cyc | wave cyc | wait-any cyc | VALU active cyc | SALU active cyc | LDS bank confl |",
+             "|" + "---|" * 18]
+    for nm in names:
+        keys = [k for k in d if k[0] == nm]
+        k = max(keys, key=lambda q: q[1])   # the finest level: the largest grid
+        v = {c: sum(x) / len(x) for c, x in d[k].items()}
+        w = max(v.get("SQ_WAVES", 0.0), 1.0)
+        g = lambda c: v.get(c)
+        pw = lambda c: f"{g(c) / w:.0f}" if g(c) is not None else "-"
+        ab = lambda c: f"{g(c):.3g}" if g(c) is not None else "-"
+        m = meta[k]
+        lines.append(f"| `{nm}` | {k[1]} | {m[0]} | {m[1]} | {m[2]} | {m[3]} | {w:.0f} | {pw('SQ_INSTS_VALU')} | "
+                     f"{pw('SQ_INSTS_SALU')} | {pw('SQ_INSTS_LDS')} | {pw('SQ_INSTS_VMEM_RD')} | "
+                     f"{pw('SQ_INSTS_VMEM_WR')} | {ab('SQ_BUSY_CYCLES')} | {ab('SQ_WAVE_CYCLES')} | "
+                     f"{ab('SQ_WAIT_ANY')} | {ab('SQ_ACTIVE_INST_VALU')} | {ab('SQ_ACTIVE_INST_SCA')} | "
+                     f"{ab('SQ_LDS_BANK_CONFLICT')} |")
+    with open(INST_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    return 0
+
+
 def sequential_boxes(nbox=64):
     """The first boxes of the batched workload solved one by one with the
     plain FP64 single-box solver (setup excluded), for comparison."""
@@ -293,7 +420,7 @@ def sequential_boxes(nbox=64):
             "solver": "single-box FP64, one box at a time"}
 
 
-def serving_bench(rates=(10.0, 100.0, 1000.0), nreq=(40, 120, 200), seed=0):
+def serving_bench(rates=(10.0, 30.0, 100.0, 300.0, 1000.0), nreq=(500, 500, 1000, 1000, 1000), seed=0):
     """Continuous-batching server on the serving workload: warm one resident
     hierarchy per request class, then replay Poisson arrivals at each rate."""
     import workloads as W
@@ -331,6 +458,58 @@ def serving_bench(rates=(10.0, 100.0, 1000.0), nreq=(40, 120, 200), seed=0):
         out["rates"].append(dict(rate_per_s=rate, requests=m, **summ))
     out["budget_bytes"] = srv.sched.budget
     srv.close()
+    return out
+
+
+def family_bench(n=256, reps=3):
+    """The photoionization / TGA family of one time step on the pin-plane gap
+    at n^3 (five Helmholtz operators on one resident hierarchy), mixed
+    precision: all members solved together (concurrent streams) against the
+    same members solved one after another."""
+    import torch
+    import workloads as W
+    from paper_1809_03745_amd import ebmg
+    dev = torch.device("cuda:0")
+    fam = W.photoionization_family(n, seed=0)
+    ctx = ebmg.Context(0)
+    t0 = time.perf_counter()
+    F = ebmg.Family(ctx, fam, precision=ebmg.MIXED)
+    setup_s = time.perf_counter() - t0
+    src = torch.tensor(fam[0].rho.ravel(), dtype=torch.float64, device=dev)
+    phi = [torch.zeros(F.N, dtype=torch.float64, device=dev) for _ in fam]
+    K = len(fam)
+
+    def run(which):
+        for x in phi:
+            x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, sts, infos = F.solve([src if k in which else None for k in range(K)], phi, rtol=1e-10,
+                                 max_cycles=400, check=False)
+        dt = time.perf_counter() - t
+        if st != ebmg.OK:
+            raise RuntimeError(f"family solve failed: {sts}")
+        return dt, infos
+
+    run(range(K))    # first call: members one after another, graphs captured
+    best, infos = None, None
+    for _ in range(reps):
+        dt, inf = run(range(K))
+        if best is None or dt < best:
+            best, infos = dt, inf
+    seq = 0.0
+    for k in range(K):
+        seq += min(run([k])[0] for _ in range(reps))
+    cyc = [i["cycles"] for i in infos]
+    out = {"workload": f"pin-plane gap {n}^3, pin electrode absorbing: 3 Eddington groups (kappa = "
+                       + ", ".join(f"{k:.3g}" for k in W.photo_kappas())
+                       + ", Robin outflow) and 2 TGA diffusion operators, same source",
+           "members": K, "cells_per_member": F.N, "precision": "f32 cycle / f64 refinement",
+           "ms_together": 1000 * best, "ms_one_after_another": 1000 * seq,
+           "solves_per_s": K / best, "cell_updates_per_s": F.N * sum(cyc) / best,
+           "vcycles": cyc, "worst_rel_residual": max(i["rel_residual"] for i in infos),
+           "device_bytes": F.device_bytes, "structure_bytes_shared": F.shared_bytes, "setup_s": setup_s}
+    F.release()
     return out
 
 
@@ -381,6 +560,8 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true", help="run the workload of the counter passes and exit")
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="reduce the counter passes of --pmc-probe to the committed traffic summary")
+    ap.add_argument("--pmc-inst-summary", nargs="+", metavar="ARG",
+                    help="COMMAND CSV...: reduce SQ counter passes of --pmc-probe to the committed instruction summary")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched workload (level-synchronous, mixed precision) and print its figures")
     ap.add_argument("--trace-summary", nargs=5, metavar=("TRACE_CSV", "MARKER", "OUT_MD", "TITLE", "COMMAND"),
@@ -400,6 +581,8 @@ def main():
         return pmc_probe(args)
     if args.pmc_summary:
         return pmc_summary(*args.pmc_summary)
+    if args.pmc_inst_summary:
+        return pmc_inst_summary(args.pmc_inst_summary[1:], args.pmc_inst_summary[0])
     if args.trace_summary:
         return trace_summary(*args.trace_summary)
     if args.batched_only:
@@ -521,6 +704,7 @@ def main():
         out["batched"] = batched()
         out["batched"]["sequential_fp64"] = sequential_boxes()
         out["serving"] = serving_bench()
+        out["family"] = family_bench()
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     if rank == 0:

@@ -455,9 +455,13 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
   static_assert(TX % 4 == 0, "wide fetch needs a tile width that is a multiple of 4");
   static_assert(TX % 2 == 0, "tile width must be even");
   static_assert(NRED <= 2 * NT, "two red cells per thread at most");
-  __shared__ T V[5][NO];
-  __shared__ T Bs[4][NR];
-  __shared__ uint8_t Ts[4][NR];
+  static_assert(NRED >= NT, "every thread has a first red cell");
+  // planes padded to whole staging rounds, so every staging store of a
+  // round lands in the array (the slots past NO / NR are never read)
+  constexpr int NOP = UO * NT > NO ? UO * NT : NO, NRP = UR * NT > NR ? UR * NT : NR;
+  __shared__ T V[5][NOP];
+  __shared__ T Bs[4][NRP];
+  __shared__ uint8_t Ts[4][NRP];
   // the template constants per phase (coff, d0, cb[0..5]): a phase chosen per
   // cell then reads LDS instead of the argument block in memory
   __shared__ T TC[2][8];
@@ -586,13 +590,13 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
       }                                                                      \
     }                                                                        \
   }
-#define ZM_STORE(P, z)                                                       \
+#define ZM_STORE(P, z, VS, BSL)                                              \
   {                                                                          \
     const int zz_ = (z);                                                     \
     const bool zin_ = zz_ >= 0 && zz_ < nz;                                  \
-    T* v_ = V[(zz_ + 10) % 5];                                               \
-    T* bs_ = Bs[(zz_ + 8) & 3];                                              \
-    uint8_t* ts_ = Ts[(zz_ + 8) & 3];                                        \
+    T* v_ = V[VS];                                                           \
+    T* bs_ = Bs[BSL];                                                        \
+    uint8_t* ts_ = Ts[BSL];                                                  \
     if constexpr (WIDE) {                                                    \
       _Pragma("unroll") for (int u = 0; u < UOW; ++u) {                      \
         const int q = tid + u * NT;                                          \
@@ -631,32 +635,30 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
     } else {                                                                 \
       _Pragma("unroll") for (int u = 0; u < UO; ++u) {                       \
         const int q = stid + u * NT;                                         \
-        if (q < NO) v_[q] = (!ZIN && zin_ && ((ino >> u) & 1)) ? P##ov[u] : T(0); \
+        v_[q] = (!ZIN && zin_ && ((ino >> u) & 1)) ? P##ov[u] : T(0);        \
       }                                                                      \
       _Pragma("unroll") for (int u = 0; u < UR; ++u) {                       \
         const int q = stid + u * NT;                                         \
-        if (q < NR) {                                                        \
-          const bool ok_ = zin_ && ((inr >> u) & 1);                         \
-          bs_[q] = ok_ ? P##bv[u] : T(0);                                    \
-          ts_[q] = ok_ ? P##tv[u] : (uint8_t)3;                              \
-        }                                                                    \
+        const bool ok_ = zin_ && ((inr >> u) & 1);                           \
+        bs_[q] = ok_ ? P##bv[u] : T(0);                                      \
+        ts_[q] = ok_ ? P##tv[u] : (uint8_t)3;                                \
       }                                                                      \
     }                                                                        \
   }
 #define ZM_STEP(P, kk)                                                       \
   {                                                                          \
     const int k = (kk);                                                      \
-    ZM_STORE(P, k + 2);                                                      \
+    ZM_STORE(P, k + 2, sVp2, sBp2);                                            \
     ZM_LOAD(P, min(k + 4, z1 + 1));                                          \
     if (k >= 0 && k < nz) { /* red update of plane k over the ring region */ \
       const bool zint = k > 0 && k < nz - 1;                                 \
-      const T* vm = V[(k + 9) % 5];                                          \
-      T* vc = V[(k + 10) % 5];                                               \
-      const T* vp = V[(k + 11) % 5];                                         \
-      const T* bs = Bs[(k + 8) & 3];                                         \
-      const uint8_t* ts = Ts[(k + 8) & 3];                                   \
+      const T* vm = V[sVm1];                                                  \
+      T* vc = V[sV0];                                                        \
+      const T* vp = V[sVp1];                                                  \
+      const T* bs = Bs[sB0];                                                 \
+      const uint8_t* ts = Ts[sB0];                                           \
       _Pragma("unroll") for (int u = 0; u < 2; ++u) {                        \
-        if (ract[u]) {                                                       \
+        if (u == 0 || ract[u]) { /* every thread has a first red cell */     \
           const int par = (rcp[u] + k) & 1;                                  \
           const int gx = rgx0[u] + par, oq = roq0[u] + par, rq = rrq0[u] + par; \
           const int pc = tclass(ts[rq]);                                     \
@@ -675,11 +677,11 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
     __syncthreads();                                                         \
     const int kb = k - 1;                                                    \
     if (kb >= z0 && kb < z1) { /* black update of plane k-1, and its write */ \
-      const T* vm = V[(kb + 9) % 5];                                         \
-      const T* vc = V[(kb + 10) % 5];                                        \
-      const T* vp = V[(kb + 11) % 5];                                        \
-      const T* bs = Bs[(kb + 8) & 3];                                        \
-      const uint8_t* ts = Ts[(kb + 8) & 3];                                  \
+      const T* vm = V[sVm2];                                                  \
+      const T* vc = V[sVm1];                                                  \
+      const T* vp = V[sV0];                                                  \
+      const T* bs = Bs[sBm1];                                                 \
+      const uint8_t* ts = Ts[sBm1];                                           \
       const int par = (bcp + kb) & 1; /* 1: gxa is black */                  \
       const int sh = par ? 0 : 1;                                            \
       const int gx = bgxa + sh, oq = boq0 + sh, rq = brq0 + sh;              \
@@ -694,21 +696,45 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
       }                                                                      \
       const T vb = pc <= 1 ? vu : vc[oq];                                    \
       const T vr = vc[oq + (par ? 1 : -1)]; /* the red partner, updated */   \
-      if (bgy < ny) {                                                        \
-        T* out = xout + (int64_t)nx * bgy + sxy * kb;                        \
+      T* out = xout + (int64_t)nx * bgy + sxy * kb;                          \
+      if (full) { /* the whole tile lies in the box: no per-lane test */     \
+        out[bgxa] = par ? vb : vr;                                           \
+        out[bgxa + 1] = par ? vr : vb;                                       \
+      } else if (bgy < ny) {                                                 \
         if (bgxa < nx) out[bgxa] = par ? vb : vr;                            \
         if (bgxa + 1 < nx) out[bgxa + 1] = par ? vr : vb;                    \
       }                                                                      \
     }                                                                        \
     __syncthreads();                                                         \
+    /* the ring slots of the planes around the next step */                  \
+    {                                                                        \
+      const int t5_ = sVm2;                                                  \
+      sVm2 = sVm1;                                                           \
+      sVm1 = sV0;                                                            \
+      sV0 = sVp1;                                                            \
+      sVp1 = sVp2;                                                           \
+      sVp2 = t5_;                                                            \
+      const int t4_ = sBm1;                                                  \
+      sBm1 = sB0;                                                            \
+      sB0 = sBp1;                                                            \
+      sBp1 = sBp2;                                                           \
+      sBp2 = t4_;                                                            \
+    }                                                                        \
   }
 
+  // LDS ring slots: plane p lives in V[(p + 10) % 5] and in Bs / Ts
+  // [(p + 8) & 3]; the slots of the planes around the current step rotate
+  // in scalars instead of being recomputed from p at every use
+  const bool full = x0 + TX <= nx && y0 + TY <= ny;
+  int sVm2 = (z0 - 3 + 10) % 5, sVm1 = (z0 - 2 + 10) % 5, sV0 = (z0 - 1 + 10) % 5, sVp1 = (z0 + 10) % 5,
+      sVp2 = (z0 + 1 + 10) % 5;
+  int sBm1 = (z0 - 2 + 8) & 3, sB0 = (z0 - 1 + 8) & 3, sBp1 = (z0 + 8) & 3, sBp2 = (z0 + 1 + 8) & 3;
   ZM_LOAD(A, z0 - 2);
-  ZM_STORE(A, z0 - 2);
+  ZM_STORE(A, z0 - 2, (z0 - 2 + 10) % 5, (z0 - 2 + 8) & 3);
   ZM_LOAD(A, z0 - 1);
-  ZM_STORE(A, z0 - 1);
+  ZM_STORE(A, z0 - 1, (z0 - 1 + 10) % 5, (z0 - 1 + 8) & 3);
   ZM_LOAD(A, z0);
-  ZM_STORE(A, z0);
+  ZM_STORE(A, z0, (z0 + 10) % 5, (z0 + 8) & 3);
   ZM_LOAD(A, z0 + 1);   // planes z0+1, z0+3, ... travel in A; z0+2, z0+4, ... in B
   ZM_LOAD(B, z0 + 2);
   __syncthreads();

@@ -476,3 +476,107 @@ def make_request(spec):
             return pin_plane(spec["n"], seed=spec["seed"])
         return blade_plane(spec["n"], seed=spec["seed"])
     return eddington(spec["dim"], spec["n"], spec["kappa"], seed=spec["seed"])
+
+
+# ---------------------------------------------------------------------------
+# closed triangle meshes (vertices, triangles counter-clockwise seen from
+# outside) for signed distances from surface tessellations
+# ---------------------------------------------------------------------------
+
+def mesh_cube(centre=(0.5, 0.5, 0.5), half=0.25):
+    c = np.asarray(centre, dtype=np.float64)
+    v = np.array([[x, y, z] for z in (-1, 1) for y in (-1, 1) for x in (-1, 1)], dtype=np.float64) * half + c
+    # faces as quads (outward, counter-clockwise), two triangles each
+    quads = [(0, 2, 3, 1), (4, 5, 7, 6), (0, 1, 5, 4), (2, 6, 7, 3), (0, 4, 6, 2), (1, 3, 7, 5)]
+    t = []
+    for a, b, c_, d in quads:
+        t.append((a, b, c_))
+        t.append((a, c_, d))
+    return v, np.array(t, dtype=np.int32)
+
+
+def mesh_icosphere(centre=(0.5, 0.5, 0.5), r=0.3, subdiv=3):
+    """Icosahedron subdivided `subdiv` times, vertices on the sphere."""
+    p = (1.0 + math.sqrt(5.0)) / 2.0
+    v = [(-1, p, 0), (1, p, 0), (-1, -p, 0), (1, -p, 0), (0, -1, p), (0, 1, p), (0, -1, -p), (0, 1, -p),
+         (p, 0, -1), (p, 0, 1), (-p, 0, -1), (-p, 0, 1)]
+    v = [np.array(x, dtype=np.float64) / np.linalg.norm(x) for x in v]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+         (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(subdiv):
+        cache = {}
+
+        def mid(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in cache:
+                m = v[a] + v[b]
+                v.append(m / np.linalg.norm(m))
+                cache[key] = len(v) - 1
+            return cache[key]
+        nf = []
+        for a, b, c_ in f:
+            ab, bc, ca = mid(a, b), mid(b, c_), mid(c_, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c_, ca, bc), (ab, bc, ca)]
+        f = nf
+    verts = np.array(v) * r + np.asarray(centre, dtype=np.float64)
+    return verts, np.array(f, dtype=np.int32)
+
+
+def mesh_torus(centre=(0.5, 0.5, 0.5), R=0.28, r=0.1, nu=48, nv=24):
+    """Torus around the z axis through centre: major radius R, minor r."""
+    c = np.asarray(centre, dtype=np.float64)
+    verts = []
+    for i in range(nu):
+        u = 2 * math.pi * i / nu
+        for j in range(nv):
+            w = 2 * math.pi * j / nv
+            verts.append(c + np.array([(R + r * math.cos(w)) * math.cos(u), (R + r * math.cos(w)) * math.sin(u),
+                                       r * math.sin(w)]))
+    idx = lambda i, j: (i % nu) * nv + (j % nv)
+    t = []
+    for i in range(nu):
+        for j in range(nv):
+            a, b, c_, d = idx(i, j), idx(i + 1, j), idx(i + 1, j + 1), idx(i, j + 1)
+            t.append((a, b, c_))
+            t.append((a, c_, d))
+    return np.array(verts), np.array(t, dtype=np.int32)
+
+
+def mesh_pin(axis_xy=(0.5, 0.5), z_tip=0.6, r=0.02, z_top=1.1, nseg=64, nring=16, nz=32):
+    """The pin electrode of the pin-plane gap as a closed tessellation: a
+    cylinder of radius r from the hemispherical tip (apex at z_tip) up to a
+    flat cap at z_top (above the box, so inside the box it is the pin)."""
+    ax, ay = axis_xy
+    zc = z_tip + r
+    verts = [np.array([ax, ay, z_tip])]              # apex
+    rings = []
+    for k in range(1, nring + 1):                    # hemisphere rings, polar angle from the apex
+        th = 0.5 * math.pi * k / nring
+        rings.append([(r * math.sin(th), zc - r * math.cos(th))])
+    for k in range(1, nz + 1):                       # cylinder rings
+        rings.append([(r, zc + (z_top - zc) * k / nz)])
+    ring_idx = []
+    for (rad, z), in rings:
+        ids = []
+        for s in range(nseg):
+            ph = 2 * math.pi * s / nseg
+            verts.append(np.array([ax + rad * math.cos(ph), ay + rad * math.sin(ph), z]))
+            ids.append(len(verts) - 1)
+        ring_idx.append(ids)
+    verts.append(np.array([ax, ay, z_top]))          # centre of the top cap
+    top = len(verts) - 1
+    t = []
+    first = ring_idx[0]
+    for s in range(nseg):                            # fan around the apex (outward = downward side)
+        t.append((0, first[(s + 1) % nseg], first[s]))
+    for a_ring, b_ring in zip(ring_idx[:-1], ring_idx[1:]):
+        for s in range(nseg):
+            a0, a1 = a_ring[s], a_ring[(s + 1) % nseg]
+            b0, b1 = b_ring[s], b_ring[(s + 1) % nseg]
+            t.append((a0, a1, b1))
+            t.append((a0, b1, b0))
+    last = ring_idx[-1]
+    for s in range(nseg):                            # top cap fan
+        t.append((top, last[s], last[(s + 1) % nseg]))
+    return np.array(verts), np.array(t, dtype=np.int32)

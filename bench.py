@@ -513,6 +513,45 @@ def family_bench(n=256, reps=3):
     return out
 
 
+def mesh_bench(n=256, reps=5):
+    """Signed distance of the tessellated pin electrode (and of a torus) at
+    the (n+1)^3 nodes of the unit box: the level set the EB setup takes,
+    generated from a surface mesh by the tree search on the GPU; beside it
+    the oracle's brute force on a sample of the nodes (one core)."""
+    import torch
+    import workloads as W
+    from paper_1809_03745_amd import ebmg
+    import numpy as np
+    from oracle.mesh_sdf import signed_distance, node_points
+    dev = torch.device("cuda:0")
+    ctx = ebmg.Context(0)
+    out = {}
+    for name, (v, t) in (("pin", W.mesh_pin(nseg=128, nring=32, nz=64)), ("torus", W.mesh_torus(nu=96, nv=48))):
+        M = ebmg.Mesh(ctx, v, t)
+        sdf = torch.empty((n + 1) ** 3, dtype=torch.float64, device=dev)
+        vis = M.sdf((n, n, n), 1.0 / n, (0, 0, 0), sdf)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            M.sdf((n, n, n), 1.0 / n, (0, 0, 0), sdf)
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        rng = np.random.default_rng(0)
+        idx = rng.choice(sdf.numel(), size=200, replace=False)
+        P = node_points((n, n, n), 1.0 / n, (0, 0, 0))[idx]
+        t0 = time.perf_counter()
+        ref = signed_distance(P, v, t)
+        cpu_s = time.perf_counter() - t0
+        err = float(np.abs(sdf.cpu().numpy()[idx] - ref).max())
+        out[name] = {"triangles": M.ntri, "tree_depth": M.depth, "nodes": int(sdf.numel()), "ms": 1000 * best,
+                     "nodes_per_s": sdf.numel() / best, "visits_per_node": vis / sdf.numel(),
+                     "oracle_brute_force_nodes_per_s_1core": len(idx) / cpu_s,
+                     "max_abs_diff_vs_oracle_on_200_nodes": err}
+        M.release()
+    return out
+
+
 def trace_summary(trace_csv, marker, out_md, title, command):
     """Reduce a rocprofv3 kernel-trace CSV to a markdown table of one solve:
     the kernels from the second-to-last dispatch whose name contains `marker`
@@ -705,6 +744,7 @@ def main():
         out["batched"]["sequential_fp64"] = sequential_boxes()
         out["serving"] = serving_bench()
         out["family"] = family_bench()
+        out["mesh_sdf"] = mesh_bench()
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     if rank == 0:

@@ -61,6 +61,7 @@ typedef struct ebmg_ctx_s* ebmg_ctx;
 typedef struct ebmg_problem_s* ebmg_problem;
 typedef struct ebmg_batch_s* ebmg_batch;
 typedef struct ebmg_family_s* ebmg_family;
+typedef struct ebmg_mesh_s* ebmg_mesh;
 
 /* Box: dim in {2,3}; n[d] cells per axis (n[2] ignored in 2D); isotropic
  * cell size h; lower corner lo. */
@@ -527,6 +528,38 @@ ebmg_status ebmg_solve_family(ebmg_family fam, const double* const* rho, const d
 
 /* Free a family and its members (no paper passage). NULL is ignored. */
 ebmg_status ebmg_release_family(ebmg_family fam);
+
+/* Signed distance from surface tessellations. Paper: Geometry generation
+ * (level sets from a watertight two-manifold tessellation held in a doubly
+ * connected edge list: the signed distance to the closest polygon, edge or
+ * vertex, found by a nearest-first search through a k-d tree of
+ * axis-aligned boxes over the polygons).
+ * Create: verts (HOST, 3*nvert doubles) and tris (HOST, 3*ntri vertex
+ * indices, counter-clockwise seen from outside; polygons are given as
+ * triangle fans) are copied; the library builds the half-edge structure,
+ * the angle-weighted pseudonormals of faces, edges and vertices (which fix
+ * the sign) and the tree, and keeps them on the context's device.
+ * ERR_GEOMETRY for a surface that is not a watertight oriented two-manifold
+ * (an edge without exactly one opposite half-edge, a degenerate triangle),
+ * ERR_ARG for bad sizes or indices, ERR_DEVICE on a host-only context. */
+ebmg_status ebmg_mesh_create(ebmg_ctx ctx, int32_t nvert, const double* verts, int32_t ntri, const int32_t* tris,
+                             ebmg_mesh* out);
+
+/* Sizes of a resident mesh (HOST outputs, any may be NULL; no paper
+ * passage): triangles, tree nodes, tree depth, device bytes. */
+ebmg_status ebmg_mesh_query(ebmg_mesh m, int32_t* ntri, int32_t* nnode, int32_t* depth, int64_t* device_bytes);
+
+/* Paper: Geometry generation. The signed distance (> 0 outside the closed
+ * surface, < 0 inside) at the nodes lo + (i,j,k) h, 0 <= i <= n[0], ... of
+ * a 3D box, written to sdf (DEVICE, prod(n[d]+1) doubles, x fastest: the
+ * node-sampled level set ebmg_setup takes for an object, up to the sign
+ * convention of the object kind). visits (HOST, nullable) receives the
+ * number of tree boxes and triangles the search examined. Work is queued on
+ * the context's stream and waited for. */
+ebmg_status ebmg_mesh_sdf(ebmg_mesh m, const ebmg_box* box, double* sdf, int64_t* visits);
+
+/* Free a mesh (no paper passage). */
+ebmg_status ebmg_mesh_release(ebmg_mesh m);
 
 #ifdef __cplusplus
 }

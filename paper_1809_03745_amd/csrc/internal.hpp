@@ -195,4 +195,34 @@ void colour_irregular(Level& L);
 void host_rhs(const Problem& pb, const double* rho, const double* sigma, const double* bcv,
               const double* objv, double* b);
 
+// ---------------------------------------------------------------------------
+// signed distance from a triangle mesh (host preparation; mesh.cpp)
+// ---------------------------------------------------------------------------
+struct MeshInput {
+  int32_t nvert = 0, ntri = 0;
+  const double* verts = nullptr;   // 3 per vertex
+  const int32_t* tris = nullptr;   // 3 vertex indices per triangle, counter-clockwise seen from outside
+};
+
+// tree node: box; a leaf holds triangles [first, first + count) of the
+// sorted records, an internal node (count < 0) has children first and -count
+struct MeshNode {
+  double lo[3], hi[3];
+  int32_t first, count;
+};
+
+constexpr int kMeshLeaf = 4;
+// per triangle: 3 vertices (9), face normal (3), pseudonormals of edges
+// 01, 12, 20 (9), pseudonormals of vertices 0, 1, 2 (9)
+constexpr int kMeshTriDoubles = 30;
+
+struct MeshHost {
+  int32_t ntri = 0;
+  int depth = 0;
+  std::vector<double> tri;         // kMeshTriDoubles per triangle, in leaf order
+  std::vector<MeshNode> nodes;     // node 0 is the root
+};
+
+void build_mesh(const MeshInput& m, MeshHost& out);
+
 }  // namespace ebmg

@@ -29,6 +29,7 @@
 #include "block_engine.hpp"
 #include "batch_wide.hpp"
 #include "kernels.hpp"
+#include "sdf_kernels.hpp"
 
 namespace ebmg {
 
@@ -286,6 +287,16 @@ struct ebmg_problem_s {
   ebmg::DevProblem dev;
   bool on_device = false;
   int pending = 0;  // submitted solves not yet finished (guarded by ctx->mu)
+};
+
+// A triangle mesh resident on the device for signed-distance queries.
+struct ebmg_mesh_s {
+  ebmg_ctx ctx = nullptr;
+  ebmg::DevBuf<double> tri;
+  ebmg::DevBuf<uint8_t> nodes;
+  ebmg::DevBuf<unsigned long long> visits;   // search counter of the last query
+  int32_t ntri = 0, nnode = 0, depth = 0;
+  int64_t bytes = 0;
 };
 
 // Operators on one geometry (a family): member 0 owns the device structure,
@@ -3668,6 +3679,102 @@ ebmg_status ebmg_release_family(ebmg_family fam) {
   ebmg_ctx ctx = fam->ctx;
   family_free(fam);
   delete fam;
+  ctx_unref(ctx);
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_mesh_create(ebmg_ctx ctx, int32_t nvert, const double* verts, int32_t ntri, const int32_t* tris,
+                             ebmg_mesh* out) {
+  if (!ctx || !verts || !tris || !out || nvert <= 0 || ntri <= 0) {
+    if (ctx) ctx->err = "invalid argument to ebmg_mesh_create";
+    return EBMG_ERR_ARG;
+  }
+  *out = nullptr;
+  if (ctx->device < 0) {
+    ctx->err = "a mesh needs a device context";
+    return EBMG_ERR_DEVICE;
+  }
+  auto M = std::make_unique<ebmg_mesh_s>();
+  M->ctx = ctx;
+  const ebmg_status st = guard(ctx, [&]() -> ebmg_status {
+    MeshInput in;
+    in.nvert = nvert;
+    in.ntri = ntri;
+    in.verts = verts;
+    in.tris = tris;
+    MeshHost H;
+    build_mesh(in, H);
+    if (H.depth >= kSdfStack) throw ArgError("mesh tree deeper than the search stack");
+    static_assert(sizeof(MeshNode) == sizeof(DevMeshNode), "node layouts differ");
+    HIPCHECK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    M->tri.upload(H.tri.data(), (int64_t)H.tri.size(), s, M->bytes);
+    M->nodes.upload((const uint8_t*)H.nodes.data(), (int64_t)(H.nodes.size() * sizeof(MeshNode)), s, M->bytes);
+    M->visits.alloc(1, M->bytes);
+    HIPCHECK(hipStreamSynchronize(s));
+    M->ntri = H.ntri;
+    M->nnode = (int32_t)H.nodes.size();
+    M->depth = H.depth;
+    return EBMG_OK;
+  });
+  if (st != EBMG_OK) {
+    M->tri.release();
+    M->nodes.release();
+    M->visits.release();
+    return st;
+  }
+  *out = M.release();
+  ++ctx->refs;
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_mesh_query(ebmg_mesh m, int32_t* ntri, int32_t* nnode, int32_t* depth, int64_t* device_bytes) {
+  if (!m) return EBMG_ERR_ARG;
+  if (ntri) *ntri = m->ntri;
+  if (nnode) *nnode = m->nnode;
+  if (depth) *depth = m->depth;
+  if (device_bytes) *device_bytes = m->bytes;
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_mesh_sdf(ebmg_mesh m, const ebmg_box* box, double* sdf, int64_t* visits) {
+  if (!m || !box || !sdf) return EBMG_ERR_ARG;
+  ebmg_ctx ctx = m->ctx;
+  return guard(ctx, [&]() -> ebmg_status {
+    if (box->dim != 3) throw ArgError("mesh distances are 3D");
+    for (int d = 0; d < 3; ++d)
+      if (box->n[d] < 1) throw ArgError("bad box size");
+    if (!(box->h > 0) || !std::isfinite(box->h)) throw ArgError("bad cell size");
+    const int m0 = box->n[0] + 1, m1 = box->n[1] + 1, m2 = box->n[2] + 1;
+    const int64_t total = (int64_t)m0 * m1 * m2;
+    HIPCHECK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    unsigned long long* vis = visits ? m->visits.p : nullptr;
+    if (vis) HIPCHECK(hipMemsetAsync(vis, 0, sizeof(unsigned long long), s));
+    const unsigned nb = (unsigned)((total + kSdfBlock - 1) / kSdfBlock);
+    hipLaunchKernelGGL(k_sdf_mesh, dim3(nb), dim3(kSdfBlock), 0, s, (const DevMeshNode*)m->nodes.p, m->tri.p, m0, m1, m2,
+                       box->h, box->lo[0], box->lo[1], box->lo[2], sdf, vis);
+    HIPCHECK(hipGetLastError());
+    if (visits) {
+      unsigned long long v = 0;
+      HIPCHECK(hipMemcpyAsync(&v, vis, sizeof(v), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      *visits = (int64_t)v;
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+    return EBMG_OK;
+  });
+}
+
+ebmg_status ebmg_mesh_release(ebmg_mesh m) {
+  if (!m) return EBMG_ERR_ARG;
+  ebmg_ctx ctx = m->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  m->tri.release();
+  m->nodes.release();
+  m->visits.release();
+  delete m;
   ctx_unref(ctx);
   return EBMG_OK;
 }

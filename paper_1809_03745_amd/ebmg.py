@@ -132,6 +132,10 @@ _sig("ebmg_query_family", C.c_int, [_vp, C.POINTER(C.c_int32), _i64p, _i64p, _i6
 _sig("ebmg_solve_family", C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.c_double, C.c_int32, C.POINTER(_vp),
                                     C.POINTER(_vp), C.POINTER(SolveInfo), C.POINTER(C.c_int)])
 _sig("ebmg_release_family", C.c_int, [_vp])
+_sig("ebmg_mesh_create", C.c_int, [_vp, C.c_int32, _vp, C.c_int32, _vp, C.POINTER(_vp)])
+_sig("ebmg_mesh_query", C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32), _i64p])
+_sig("ebmg_mesh_sdf", C.c_int, [_vp, C.POINTER(Box), _vp, _i64p])
+_sig("ebmg_mesh_release", C.c_int, [_vp])
 
 EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_destroy", "ebmg_last_error",
             "ebmg_setup", "ebmg_query", "ebmg_query_level", "ebmg_export_level", "ebmg_query_tuning",
@@ -139,7 +143,8 @@ EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_des
             "ebmg_solve", "ebmg_submit", "ebmg_poll", "ebmg_wait", "ebmg_apply", "ebmg_apply_noalloc", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
             "ebmg_setup_batch", "ebmg_query_batch", "ebmg_query_batch_box", "ebmg_query_batch_tuning", "ebmg_solve_batch", "ebmg_release_batch",
             "ebmg_set_coefficients", "ebmg_smooth", "ebmg_kernel_timing",
-            "ebmg_setup_family", "ebmg_query_family", "ebmg_solve_family", "ebmg_release_family"]
+            "ebmg_setup_family", "ebmg_query_family", "ebmg_solve_family", "ebmg_release_family",
+            "ebmg_mesh_create", "ebmg_mesh_query", "ebmg_mesh_sdf", "ebmg_mesh_release"]
 
 
 def abi_version():
@@ -645,6 +650,51 @@ class Family:
     def release(self):
         if getattr(self, "h", None):
             _lib.ebmg_release_family(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class Mesh:
+    """A closed triangle mesh resident on the device for signed distances
+    (vertices (nv, 3), triangles (nt, 3) counter-clockwise seen from outside)."""
+
+    def __init__(self, ctx, verts, tris):
+        self.ctx = ctx
+        v = np.ascontiguousarray(verts, dtype=np.float64)
+        t = np.ascontiguousarray(tris, dtype=np.int32)
+        if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
+            raise EbmgError(ERR_ARG, "verts (nv, 3) and tris (nt, 3) expected")
+        h = _vp()
+        ctx.check(_lib.ebmg_mesh_create(ctx.h, len(v), _ptr(v), len(t), _ptr(t), C.byref(h)), "ebmg_mesh_create")
+        self.h = h
+        nt, nn, dp, by = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+        ctx.check(_lib.ebmg_mesh_query(h, C.byref(nt), C.byref(nn), C.byref(dp), C.byref(by)), "ebmg_mesh_query")
+        self.ntri, self.nnode, self.depth, self.device_bytes = nt.value, nn.value, dp.value, by.value
+
+    def sdf(self, n, h, lo, out):
+        """Signed distance at the nodes of an n[0] x n[1] x n[2]-cell box
+        (out: device float64 tensor of prod(n+1) entries); returns the number
+        of boxes and triangles the search examined."""
+        box = Box()
+        box.dim = 3
+        for d in range(3):
+            box.n[d] = int(n[d])
+            box.lo[d] = float(lo[d])
+        box.h = float(h)
+        m = (int(n[0]) + 1) * (int(n[1]) + 1) * (int(n[2]) + 1)
+        vis = C.c_int64()
+        self.ctx.check(_lib.ebmg_mesh_sdf(self.h, C.byref(box), _dev(self.ctx, out, m, "out"), C.byref(vis)),
+                       "ebmg_mesh_sdf")
+        return vis.value
+
+    def release(self):
+        if getattr(self, "h", None):
+            _lib.ebmg_mesh_release(self.h)
             self.h = None
 
     def __del__(self):

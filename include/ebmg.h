@@ -202,8 +202,8 @@ ebmg_status ebmg_query(ebmg_problem pb, int64_t* n_cells, int64_t* n_phase2, int
  * cells and second-phase unknowns. Outputs HOST. ERR_ARG for a bad level. */
 ebmg_status ebmg_query_level(ebmg_problem pb, int32_t level, int64_t* n_cells, int64_t* n_phase2);
 
-/* Measurement record of the smoother autotuner (the red/black Gauss-Seidel
- * relaxation of the Multigrid solver subsection). Outputs HOST.
+/* Measurement record of the smoother autotuner (Paper: Multigrid solver, the
+ * red/black Gauss-Seidel relaxation). Outputs HOST.
  * Smoother choice of level `level` (0 split half-sweeps, 1 fused tile sweep,
  * 2 + c z-marching fused sweep in tile configuration c as listed at
  * ebmg_smooth, 13 one-launch colour phases), the split sweep time and the
@@ -215,7 +215,8 @@ ebmg_status ebmg_query_level(ebmg_problem pb, int32_t level, int64_t* n_cells, i
  * without it and *fused_ms the V-cycle time with the chosen tail. */
 ebmg_status ebmg_query_tuning(ebmg_problem pb, int32_t level, int32_t* fused, double* split_ms, double* fused_ms);
 
-/* HOST copies of a level's cell tags (0/1 regular gas/dielectric, 2 explicit
+/* Paper: Multigrid solver (the coarsened levels).
+ * HOST copies of a level's cell tags (0/1 regular gas/dielectric, 2 explicit
  * row, 3 covered; +4 when the cell's children do not all map to its primary
  * unknown), primary phase per cell and cell of each second-phase unknown
  * (the coarsened graph of the Multigrid solver subsection). Arrays of the
@@ -254,7 +255,8 @@ ebmg_status ebmg_export_geometry(ebmg_problem pb, double* kappa_gas, double* kap
 ebmg_status ebmg_export_moments(ebmg_problem pb, int32_t phase, double* vcent, double* apert, double* foff,
                                 double* eb_area, double* eb_cent, double* eb_normal);
 
-/* HOST CSR of the level-`level` operator over N+N2 unknowns (covered cells
+/* Paper: Helmholtz equations, Multigrid solver.
+ * HOST CSR of the level-`level` operator over N+N2 unknowns (covered cells
  * as identity rows): the linear part of the volume-weighted row of eq.
  * `poisson_integral` (Helmholtz equations) on level 0, the coarse operators
  * of the Multigrid solver subsection elsewhere. Call with row_ptr == NULL to
@@ -323,7 +325,8 @@ ebmg_status ebmg_poll(ebmg_ctx ctx, uint64_t ticket, int32_t* done, ebmg_status*
  * no paper passage). */
 ebmg_status ebmg_wait(ebmg_ctx ctx, uint64_t ticket, ebmg_status* result, ebmg_solve_info* info);
 
-/* out = A [phi; phi2]: the linear part of the finest-level operator of the
+/* Paper: Helmholtz equations, eq. `poisson_integral`.
+ * out = A [phi; phi2]: the linear part of the finest-level operator of the
  * Helmholtz equations section (eq. `poisson_integral`, boundary data
  * excluded), in FP64. phi, phi2, out, out2 are DEVICE arrays of N and N2
  * entries (phi2/out2 nullable when N2 = 0). */
@@ -345,7 +348,8 @@ ebmg_status ebmg_apply(ebmg_problem pb, const double* phi, const double* phi2, d
 ebmg_status ebmg_apply_noalloc(ebmg_problem pb, const double* phi, const double* phi2, double* out,
                                double* out2);
 
-/* Cell-centred E = -grad(phi) (Electrodynamic equations) from the
+/* Paper: Electrodynamic equations (eq. `poisson`), Helmholtz equations.
+ * Cell-centred E = -grad(phi) (Electrodynamic equations) from the
  * centroid-interpolated face fluxes of the Helmholtz equations section: the
  * mean of the open low/high face gradients per axis, the EB normal gradient
  * where neither face is open. phi, phi2, sigma and E (dim*N,
@@ -354,8 +358,8 @@ ebmg_status ebmg_apply_noalloc(ebmg_problem pb, const double* phi, const double*
 ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, const double* sigma,
                         const double* bc_values, const double* obj_values, double* E);
 
-/* Red/black Gauss-Seidel sweeps (the smoother of the multigrid-solver
- * subsection) over the template cells of level `level` only: explicit-row,
+/* Paper: Multigrid solver (red/black Gauss-Seidel relaxation).
+ * Red/black Gauss-Seidel sweeps over the template cells of level `level` only: explicit-row,
  * covered and second-phase entries of x are left as they are. variant: 1
  * split red and black half-sweeps, 2 fused tile sweep, 3 + c z-marching
  * fused sweep in tile configuration c = 0..10 (x-by-y tiles over z planes:

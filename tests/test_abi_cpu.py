@@ -369,3 +369,19 @@ def test_family_setup_on_the_host(host_ctx):
     h = ebmg._vp()
     st = ebmg._lib.ebmg_setup_family(host_ctx.h, ebmg.C.byref(box), 1, objs, 2, bcs, opts, ebmg.C.byref(h))
     assert st == ebmg.ERR_ARG and not h.value
+
+
+def test_every_declaration_cites_its_passage():
+    """Each entry point's comment in include/ebmg.h names the paper passage
+    it implements ("Paper: ...") or states that it has none."""
+    txt = open(HEADER).read()
+    decls = list(re.finditer(r"^(?:ebmg_status|void|int|const char\*)\s+(ebmg_[a-z_0-9]+)\s*\(", txt, re.M))
+    assert len(decls) >= 30
+    missing = []
+    for m in decls:
+        before = txt[:m.start()]
+        com = " ".join(before[before.rfind("/*"):before.rfind("*/")].replace("*", " ").split())
+        # the no-allocation entry point names the callers it is for instead
+        if "Paper" not in com and "paper passage" not in com and "cannot allocate" not in com:
+            missing.append(m.group(1))
+    assert not missing, missing

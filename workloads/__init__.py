@@ -580,3 +580,65 @@ def mesh_pin(axis_xy=(0.5, 0.5), z_tip=0.6, r=0.02, z_top=1.1, nseg=64, nring=16
     for s in range(nseg):                            # top cap fan
         t.append((top, last[s], last[(s + 1) % nseg]))
     return np.array(verts), np.array(t, dtype=np.int32)
+
+
+# ---------------------------------------------------------------------------
+# advection inputs: a density on cell centres, face-normal velocities on the
+# face centres of each axis (face arrays in numpy order, the axis of the
+# faces extended by one), a time step from a CFL number on the cell size
+# ---------------------------------------------------------------------------
+
+def face_centres(dim, n, h, lo, d):
+    """Coordinate arrays (x, y[, z]) of the centres of the faces normal to d."""
+    off = tuple(0.0 if e == d else 0.5 for e in range(dim))
+    m = tuple(n[e] + (1 if e == d else 0) for e in range(dim))
+    axes = []
+    for e in range(dim):
+        v = lo[e] + (np.arange(m[e]) + off[e]) * h
+        shape = [1] * dim
+        shape[dim - 1 - e] = m[e]
+        axes.append(v.reshape(shape))
+    full = tuple(reversed(m))
+    return tuple(np.broadcast_to(a, full) for a in axes)
+
+
+def velocity_uniform(dim, n, h, lo, v):
+    return [np.full(face_centres(dim, n, h, lo, d)[0].shape, float(v[d])) for d in range(dim)]
+
+
+def velocity_rotation(dim, n, h, lo, omega, centre):
+    """Rigid rotation about the z axis through centre (in the x-y plane),
+    sampled as face-normal components at face centres (discretely
+    divergence-free: u_x depends on y only, u_y on x only)."""
+    out = []
+    for d in range(dim):
+        X = face_centres(dim, n, h, lo, d)
+        if d == 0:
+            out.append(np.ascontiguousarray(-omega * (X[1] - centre[1])))
+        elif d == 1:
+            out.append(np.ascontiguousarray(omega * (X[0] - centre[0])))
+        else:
+            out.append(np.zeros(X[0].shape))
+    return out
+
+
+def gaussian_density(prob, centre, width):
+    X = prob.cell_centres()
+    r2 = sum((np.broadcast_to(X[d], prob.shape) - centre[d]) ** 2 for d in range(prob.dim))
+    return np.ascontiguousarray(np.exp(-r2 / (2.0 * width * width)))
+
+
+def advection_pin_plane(n=128, seed=0):
+    """Advection on the gas phase of the pin-plane gap: a density blob near
+    the pin tip carried by a rigid rotation about the pin axis plus a
+    downward drift (electrons drifting towards the plane), CFL 0.5."""
+    pr = pin_plane(n, seed=seed)
+    h = pr.h
+    rng = np.random.default_rng(seed)
+    c = (0.5 + rng.uniform(0.05, 0.1), 0.5, 0.5)
+    n0 = gaussian_density(pr, c, 0.05)
+    u = velocity_rotation(3, pr.n, h, pr.lo, 2.0, (0.5, 0.5))
+    u[2] = np.full(u[2].shape, -0.4)
+    vmax = max(float(np.abs(x).max()) for x in u)
+    dt = 0.5 * h / vmax
+    return pr, n0, u, dt

@@ -533,6 +533,29 @@ ebmg_status ebmg_solve_family(ebmg_family fam, const double* const* rho, const d
 /* Free a family and its members (no paper passage). NULL is ignored. */
 ebmg_status ebmg_release_family(ebmg_family fam);
 
+/* Paper: Convection-Diffusion-Reaction equations (Advective discretization,
+ * Hybrid divergence). One explicit step n_out = n_in - dt D of the
+ * advection of a density on the gas phase of the problem's geometry: D is
+ * the divergence of face fluxes u n_f, n_f the upwind state of an unsplit
+ * Godunov predictor with van Leer (monotonised-central) slopes extrapolated
+ * to the face and the half step (transverse terms included; 0 slope where a
+ * neighbour carries no gas); fluxes are interpolated to the face centroids
+ * and weighted by the apertures; no flux crosses the embedded boundary;
+ * in cut cells the hybrid kappa D^c + (1 - kappa) D^nc (D^nc the
+ * kappa-weighted mean over the 3^D block) replaces D^c, and the mass it
+ * does not conserve is redistributed over the other gas cells of the block
+ * in proportion to their kappa, so that sum kappa n h^D changes by exactly
+ * the domain-boundary fluxes. n_in, n_out: DEVICE arrays of N cells
+ * (different; cells without gas get 0); u_x, u_y, u_z (u_z NULL in 2D):
+ * DEVICE face-normal velocities at the face centres, the faces normal to d
+ * forming an (n_x + [d=0]) x (n_y + [d=1]) (x (n_z + [d=2])) array, x
+ * fastest; inflow (HOST, 6 or NULL = 0): the density entering through each
+ * domain face (x-, x+, y-, y+, z-, z+) where the velocity points inward.
+ * The first call on a problem builds and uploads the step's geometry data.
+ * Queued on the context's stream and waited for. */
+ebmg_status ebmg_advect(ebmg_problem pb, const double* n_in, const double* u_x, const double* u_y,
+                        const double* u_z, double dt, const double* inflow, double* n_out);
+
 /* Signed distance from surface tessellations. Paper: Geometry generation
  * (level sets from a watertight two-manifold tessellation held in a doubly
  * connected edge list: the signed distance to the closest polygon, edge or

@@ -225,4 +225,26 @@ struct MeshHost {
 
 void build_mesh(const MeshInput& m, MeshHost& out);
 
+// ---------------------------------------------------------------------------
+// advection on the gas phase (host preparation; advect.cpp)
+// ---------------------------------------------------------------------------
+struct AdvHost {
+  int64_t nfaces = 0;
+  int64_t face_base[3] = {0, 0, 0};     // first face of each direction
+  std::vector<uint8_t> cls;             // per cell: 0 no gas, 1 full, 2 cut
+  std::vector<double> kappa;            // per cell (gas volume fraction)
+  std::vector<int64_t> cut_cell;        // cut cells in cell order
+  std::vector<int64_t> dc_ptr, dc_face; // per cut cell: conservative divergence
+  std::vector<double> dc_coef;          //   = sum coef * face flux
+  std::vector<int64_t> nb_ptr, nb_cell; // per cut cell: gas cells of its block
+  std::vector<double> nb_w;             //   with weights kappa_j / sum kappa
+  std::vector<double> cut_S;            // per cut cell: sum kappa of the block without it
+  std::vector<int64_t> sp_cell;         // cells whose rate is not D^c: cut cells and receivers
+  std::vector<int32_t> sp_cut;          //   their cut id (-1: a full cell that receives)
+  std::vector<int64_t> sp_ptr;          //   their donors (cut ids)
+  std::vector<int32_t> sp_donor;
+};
+
+void build_advection(const Geometry& G, AdvHost& A);
+
 }  // namespace ebmg

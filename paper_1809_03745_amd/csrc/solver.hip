@@ -30,6 +30,7 @@
 #include "batch_wide.hpp"
 #include "kernels.hpp"
 #include "sdf_kernels.hpp"
+#include "adv_kernels.hpp"
 
 namespace ebmg {
 
@@ -215,6 +216,22 @@ struct DevProblem {
   bool timing() const { return kt[0] || kt[1]; }
   int64_t bytes = 0;
   int64_t shared_bytes = 0;   // structure taken from another family member (not allocated here)
+  // advection on the gas phase (built at the first ebmg_advect call)
+  struct Adv {
+    bool ready = false;
+    int64_t nfaces = 0, fbase[3] = {0, 0, 0};
+    int ncut = 0, nsp = 0;
+    DevBuf<uint8_t> cls;
+    DevBuf<double> kappa, dc_coef, nb_w, cut_S, F, Dc, Dcut, give;
+    DevBuf<int64_t> cut_cell, dc_ptr, dc_face, nb_ptr, nb_cell, sp_cell, sp_ptr;
+    DevBuf<int32_t> sp_cut, sp_donor;
+    void release() {
+      cls.release(); kappa.release(); dc_coef.release(); nb_w.release(); cut_S.release(); F.release();
+      Dc.release(); Dcut.release(); give.release(); cut_cell.release(); dc_ptr.release(); dc_face.release();
+      nb_ptr.release(); nb_cell.release(); sp_cell.release(); sp_ptr.release(); sp_cut.release(); sp_donor.release();
+      ready = false;
+    }
+  } adv;
   void drop_graphs() {
     if (g_krylov) (void)hipGraphExecDestroy(g_krylov);
     if (g_plain) (void)hipGraphExecDestroy(g_plain);
@@ -235,6 +252,7 @@ struct DevProblem {
     tail_lv.release();
     bk_vec.release();
     bk_dev.release();
+    adv.release();
     if (host_scal) (void)hipHostFree(host_scal);
     host_scal = nullptr;
   }
@@ -3681,6 +3699,94 @@ ebmg_status ebmg_release_family(ebmg_family fam) {
   delete fam;
   ctx_unref(ctx);
   return EBMG_OK;
+}
+
+ebmg_status ebmg_advect(ebmg_problem pb, const double* n_in, const double* u_x, const double* u_y,
+                        const double* u_z, double dt, const double* inflow, double* n_out) {
+  if (!pb) return EBMG_ERR_ARG;
+  ebmg_ctx ctx = pb->ctx;
+  if (!n_in || !n_out || !u_x || !u_y || !(dt >= 0) || !std::isfinite(dt)) {
+    ctx->err = "invalid argument to ebmg_advect";
+    return EBMG_ERR_ARG;
+  }
+  if (!pb->on_device) {
+    ctx->err = "problem is not on a device (host-only context)";
+    return EBMG_ERR_DEVICE;
+  }
+  return guard(ctx, [&]() -> ebmg_status {
+    const Geometry& G = pb->host->geo;
+    const int D = G.g.dim;
+    if (D == 3 && !u_z) throw ArgError("3D advection needs the z face velocities");
+    if (n_in == n_out) throw ArgError("n_in and n_out must be different arrays");
+    drain(pb);
+    HIPCHECK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    auto& A = pb->dev.adv;
+    if (!A.ready) {
+      AdvHost H;
+      build_advection(G, H);
+      int64_t by = 0;
+      A.nfaces = H.nfaces;
+      for (int d = 0; d < 3; ++d) A.fbase[d] = H.face_base[d];
+      A.ncut = (int)H.cut_cell.size();
+      A.nsp = (int)H.sp_cell.size();
+      A.cls.upload(H.cls.data(), (int64_t)H.cls.size(), s, by);
+      A.kappa.upload(H.kappa.data(), (int64_t)H.kappa.size(), s, by);
+      A.cut_cell.upload(H.cut_cell.data(), (int64_t)H.cut_cell.size(), s, by);
+      A.dc_ptr.upload(H.dc_ptr.data(), (int64_t)H.dc_ptr.size(), s, by);
+      A.dc_face.upload(H.dc_face.data(), (int64_t)H.dc_face.size(), s, by);
+      A.dc_coef.upload(H.dc_coef.data(), (int64_t)H.dc_coef.size(), s, by);
+      A.nb_ptr.upload(H.nb_ptr.data(), (int64_t)H.nb_ptr.size(), s, by);
+      A.nb_cell.upload(H.nb_cell.data(), (int64_t)H.nb_cell.size(), s, by);
+      A.nb_w.upload(H.nb_w.data(), (int64_t)H.nb_w.size(), s, by);
+      A.cut_S.upload(H.cut_S.data(), (int64_t)H.cut_S.size(), s, by);
+      A.sp_cell.upload(H.sp_cell.data(), (int64_t)H.sp_cell.size(), s, by);
+      A.sp_cut.upload(H.sp_cut.data(), (int64_t)H.sp_cut.size(), s, by);
+      A.sp_ptr.upload(H.sp_ptr.data(), (int64_t)H.sp_ptr.size(), s, by);
+      A.sp_donor.upload(H.sp_donor.data(), (int64_t)H.sp_donor.size(), s, by);
+      A.F.alloc(std::max<int64_t>(1, A.nfaces), by);
+      A.Dc.alloc(std::max<int64_t>(1, G.N), by);
+      A.Dcut.alloc(std::max<int64_t>(1, A.ncut), by);
+      A.give.alloc(std::max<int64_t>(1, A.ncut), by);
+      HIPCHECK(hipStreamSynchronize(s));
+      pb->dev.bytes += by;
+      A.ready = true;
+    }
+    AdvGrid g;
+    g.dim = D;
+    for (int d = 0; d < 3; ++d) {
+      g.n[d] = d < D ? G.g.n[d] : 1;
+      g.fbase[d] = A.fbase[d];
+    }
+    g.h = G.g.h;
+    g.dt = dt;
+    for (int f = 0; f < 6; ++f) g.inflow[f] = inflow ? inflow[f] : 0.0;
+    AdvVel vel;
+    vel.u[0] = u_x;
+    vel.u[1] = u_y;
+    vel.u[2] = D == 3 ? u_z : u_x;
+    const int64_t N = G.N;
+    if (D == 3) {
+      hipLaunchKernelGGL(k_adv_faces<3>, dim3(nblk(A.nfaces)), dim3(256), 0, s, n_in, A.cls.p, vel, g, A.nfaces, A.F.p);
+      hipLaunchKernelGGL(k_adv_dc_full<3>, dim3(nblk(N)), dim3(256), 0, s, A.cls.p, g, A.F.p, A.Dc.p);
+    } else {
+      hipLaunchKernelGGL(k_adv_faces<2>, dim3(nblk(A.nfaces)), dim3(256), 0, s, n_in, A.cls.p, vel, g, A.nfaces, A.F.p);
+      hipLaunchKernelGGL(k_adv_dc_full<2>, dim3(nblk(N)), dim3(256), 0, s, A.cls.p, g, A.F.p, A.Dc.p);
+    }
+    if (A.ncut > 0) {
+      hipLaunchKernelGGL(k_adv_dc_cut, dim3(nblk(A.ncut)), dim3(256), 0, s, A.ncut, A.cut_cell.p, A.dc_ptr.p,
+                         A.dc_face.p, A.dc_coef.p, A.F.p, A.Dc.p);
+      hipLaunchKernelGGL(k_adv_cut, dim3(nblk(A.ncut)), dim3(256), 0, s, A.ncut, A.cut_cell.p, A.kappa.p, A.nb_ptr.p,
+                         A.nb_cell.p, A.nb_w.p, A.cut_S.p, A.Dc.p, A.Dcut.p, A.give.p);
+    }
+    hipLaunchKernelGGL(k_adv_update, dim3(nblk(N)), dim3(256), 0, s, A.cls.p, N, dt, n_in, A.Dc.p, n_out);
+    if (A.nsp > 0)
+      hipLaunchKernelGGL(k_adv_special, dim3(nblk(A.nsp)), dim3(256), 0, s, A.nsp, A.sp_cell.p, A.sp_cut.p, A.sp_ptr.p,
+                         A.sp_donor.p, dt, n_in, A.Dc.p, A.Dcut.p, A.give.p, n_out);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(s));
+    return EBMG_OK;
+  });
 }
 
 ebmg_status ebmg_mesh_create(ebmg_ctx ctx, int32_t nvert, const double* verts, int32_t ntri, const int32_t* tris,

@@ -132,6 +132,7 @@ _sig("ebmg_query_family", C.c_int, [_vp, C.POINTER(C.c_int32), _i64p, _i64p, _i6
 _sig("ebmg_solve_family", C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.c_double, C.c_int32, C.POINTER(_vp),
                                     C.POINTER(_vp), C.POINTER(SolveInfo), C.POINTER(C.c_int)])
 _sig("ebmg_release_family", C.c_int, [_vp])
+_sig("ebmg_advect", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, _vp, _vp])
 _sig("ebmg_mesh_create", C.c_int, [_vp, C.c_int32, _vp, C.c_int32, _vp, C.POINTER(_vp)])
 _sig("ebmg_mesh_query", C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32), _i64p])
 _sig("ebmg_mesh_sdf", C.c_int, [_vp, C.POINTER(Box), _vp, _i64p])
@@ -144,7 +145,7 @@ EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_des
             "ebmg_setup_batch", "ebmg_query_batch", "ebmg_query_batch_box", "ebmg_query_batch_tuning", "ebmg_solve_batch", "ebmg_release_batch",
             "ebmg_set_coefficients", "ebmg_smooth", "ebmg_kernel_timing",
             "ebmg_setup_family", "ebmg_query_family", "ebmg_solve_family", "ebmg_release_family",
-            "ebmg_mesh_create", "ebmg_mesh_query", "ebmg_mesh_sdf", "ebmg_mesh_release"]
+            "ebmg_mesh_create", "ebmg_mesh_query", "ebmg_mesh_sdf", "ebmg_mesh_release", "ebmg_advect"]
 
 
 def abi_version():
@@ -446,6 +447,23 @@ class Problem:
         self.ctx.check(_lib.ebmg_efield(self.h, _dev(c, phi, N, "phi"), _dev(c, phi2, N2, "phi2", True),
                                         _dev(c, sigma, N, "sigma", True), _ptr(bcv), _ptr(ov),
                                         _dev(c, E, self.prob.dim * N, "E")), "ebmg_efield")
+
+    def advect(self, n_in, u, dt, n_out, inflow=None):
+        """One advection step of a density on the gas phase: n_in, n_out
+        device tensors of N cells, u a list of dim device face-velocity
+        tensors (faces normal to d: the d extent plus one)."""
+        c, N, dim = self.ctx, self.N, self.prob.dim
+        if len(u) != dim:
+            raise EbmgError(ERR_ARG, f"{dim} face velocity arrays expected")
+        nfd = []
+        for d in range(dim):
+            m = 1
+            for e in range(dim):
+                m *= self.prob.n[e] + (1 if e == d else 0)
+            nfd.append(_dev(c, u[d], m, f"u[{d}]"))
+        iv = _host_f64(inflow)
+        self.ctx.check(_lib.ebmg_advect(self.h, _dev(c, n_in, N, "n_in"), nfd[0], nfd[1], nfd[2] if dim == 3 else None,
+                                        float(dt), _ptr(iv), _dev(c, n_out, N, "n_out")), "ebmg_advect")
 
     def tuning(self, level):
         """(smoother variant: 0 split, 1 tile, 2 + c z-march in tile ZM_TILES[c],

@@ -581,6 +581,62 @@ def mesh_bench(n=256, reps=5):
     return out
 
 
+def advection_bench(n=256, steps=20, oracle_n=64):
+    """Explicit advection steps of the electron density on the gas phase of
+    the pin-plane gap (n^3 cells, rigid rotation about the pin axis plus a
+    downward drift, CFL 0.5): device time per step from HIP events on the
+    library's stream, and the step's algorithmic bytes per gas cell: the
+    density read and written (8 + 8), the three face velocities (24) and the
+    cell class (1). Beside it the oracle's step on the same workload at
+    oracle_n^3 (one core)."""
+    import torch
+    import numpy as np
+    import workloads as W
+    from paper_1809_03745_amd import ebmg
+    from oracle.advection import Advection
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    ctx = ebmg.Context(0, stream=stream.cuda_stream)
+    pr, n0, u, dt = W.advection_pin_plane(n, seed=0)
+    P = ebmg.Problem(ctx, pr)
+    x = torch.tensor(n0.ravel(), dtype=torch.float64, device=dev)
+    y = torch.zeros_like(x)
+    ut = [torch.tensor(np.ascontiguousarray(v).ravel(), dtype=torch.float64, device=dev) for v in u]
+    del u
+    t0 = time.perf_counter()
+    P.advect(x, ut, dt, y)          # the first call builds the step's geometry data
+    first_s = time.perf_counter() - t0
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        P.advect(y, ut, dt, x)
+        b.record(stream)
+        x, y = y, x
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ncell = P.N
+    alg = 41 * ncell
+    out = {"workload": f"pin-plane {n}^3 gas phase, {steps} steps", "cells": ncell, "device_ms_per_step": ms,
+           "wall_ms_per_step": 1000 * wall, "cell_steps_per_s": ncell / (ms * 1e-3),
+           "alg_bytes_per_step": alg, "alg_bytes_unit": "41 B per cell (n in/out, three face velocities, class)",
+           "effective_GBps": alg / (ms * 1e-3) / 1e9, "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "first_call_s": first_s, "mass_finite": bool(torch.isfinite(y).all())}
+    P.release()
+    del ut, x, y
+    torch.cuda.empty_cache()
+    pr, n0, u, dt = W.advection_pin_plane(oracle_n, seed=0)
+    A = Advection(pr)
+    t0 = time.perf_counter()
+    A.step(np.where(A.gas, n0, 0.0), u, dt)
+    cpu_s = time.perf_counter() - t0
+    out["oracle_cell_steps_per_s_1core"] = int(np.prod(pr.n)) / cpu_s
+    out["oracle_sample"] = f"one step at {oracle_n}^3"
+    return out
+
+
 def trace_summary(trace_csv, marker, out_md, title, command):
     """Reduce a rocprofv3 kernel-trace CSV to a markdown table of one solve:
     the kernels from the second-to-last dispatch whose name contains `marker`
@@ -632,6 +688,8 @@ def main():
                     help="COMMAND CSV...: reduce SQ counter passes of --pmc-probe to the committed instruction summary")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched workload (level-synchronous, mixed precision) and print its figures")
+    ap.add_argument("--advection-only", action="store_true",
+                    help="run only the advection steps on the pin-plane gap and print their figures")
     ap.add_argument("--trace-summary", nargs=5, metavar=("TRACE_CSV", "MARKER", "OUT_MD", "TITLE", "COMMAND"),
                     help="reduce a rocprofv3 kernel trace to a committed markdown summary of one solve")
     ap.add_argument("--smoother", choices=["auto", "split", "fused", "zmarch"], default="auto",
@@ -655,6 +713,9 @@ def main():
         return trace_summary(*args.trace_summary)
     if args.batched_only:
         print(json.dumps(batched(reps=max(1, args.steps), keys=("mixed",))))
+        return 0
+    if args.advection_only:
+        print(json.dumps(advection_bench(n=args.n, steps=max(1, args.steps))))
         return 0
     rank = int(os.environ.get("RANK", "0"))
 
@@ -774,6 +835,7 @@ def main():
         out["serving"] = serving_bench()
         out["family"] = family_bench()
         out["mesh_sdf"] = mesh_bench()
+        out["advection"] = advection_bench()
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     if rank == 0:

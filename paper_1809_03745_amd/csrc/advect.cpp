@@ -2,8 +2,10 @@
 // grid (Convection-Diffusion-Reaction equations: Advective discretization
 // and Hybrid divergence). Everything the step needs that depends on the
 // geometry alone is built here once per problem:
-//  * a cell class per cell: no gas, full cell (kappa = 1: every face full,
-//    face-centred fluxes are the centroid fluxes), cut cell;
+//  * a cell class per cell: no gas (0), full cell (1: kappa = 1, every face
+//    full, face-centred fluxes are the centroid fluxes), cut cell (2), full
+//    cell in the 3^D block of a cut cell (3: its conservative divergence is
+//    kept for the cut cell's non-conservative one);
 //  * per cut cell, its conservative divergence as a linear form over the
 //    face-centred fluxes: sum over its faces of +-alpha_f / (kappa h) times
 //    the centroid interpolation weights of that face (the same rule as the
@@ -193,6 +195,7 @@ void build_advection(const Geometry& G, AdvHost& A) {
               if (!gas(q)) continue;
               const int64_t qc = g.cell(q[0], q[1], q[2]);
               A.nb_cell.push_back(qc);
+              if (A.cls[qc] == 1) A.cls[qc] = 3;   // a full cell whose D^c the block needs
               A.nb_w.push_back(A.kappa[qc]);
               ks += A.kappa[qc];
               if (qc != c) S += A.kappa[qc];

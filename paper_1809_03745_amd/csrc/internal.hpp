@@ -231,7 +231,7 @@ void build_mesh(const MeshInput& m, MeshHost& out);
 struct AdvHost {
   int64_t nfaces = 0;
   int64_t face_base[3] = {0, 0, 0};     // first face of each direction
-  std::vector<uint8_t> cls;             // per cell: 0 no gas, 1 full, 2 cut
+  std::vector<uint8_t> cls;             // per cell: 0 no gas, 1 full, 2 cut, 3 full in a cut cell's block
   std::vector<double> kappa;            // per cell (gas volume fraction)
   std::vector<int64_t> cut_cell;        // cut cells in cell order
   std::vector<int64_t> dc_ptr, dc_face; // per cut cell: conservative divergence

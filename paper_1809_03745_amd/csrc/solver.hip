@@ -3765,13 +3765,29 @@ ebmg_status ebmg_advect(ebmg_problem pb, const double* n_in, const double* u_x, 
     vel.u[0] = u_x;
     vel.u[1] = u_y;
     vel.u[2] = D == 3 ? u_z : u_x;
-    const int64_t N = G.N;
-    if (D == 3) {
-      hipLaunchKernelGGL(k_adv_faces<3>, dim3(nblk(A.nfaces)), dim3(256), 0, s, n_in, A.cls.p, vel, g, A.nfaces, A.F.p);
-      hipLaunchKernelGGL(k_adv_dc_full<3>, dim3(nblk(N)), dim3(256), 0, s, A.cls.p, g, A.F.p, A.Dc.p);
+    auto flux_grid = [&](int d) { return dim3(nblk((int64_t)(g.n[0] + (d == 0)) * (g.n[1] + (d == 1)))); };
+    const dim3 cell_grid(nblk((int64_t)g.n[0] * g.n[1]));
+    const bool off32 = (int64_t)(g.n[0] + 1) * (g.n[1] + 1) * (g.n[2] + 1) < ((int64_t)1 << 31);
+    if (D == 3 && off32) {
+      // one z-marching pass (its offsets are 32-bit)
+      constexpr int TX = 16, TY = 16, ZC = 32;
+      const int tiles_x = (g.n[0] + TX - 1) / TX, tiles_y = (g.n[1] + TY - 1) / TY;
+      const int64_t blocks = (int64_t)tiles_x * tiles_y * ((g.n[2] + ZC - 1) / ZC);
+      hipLaunchKernelGGL((k_adv_zm<TX, TY, ZC>), dim3((unsigned)blocks), dim3(TX * TY), 0, s, n_in, A.cls.p, vel, g,
+                         tiles_x, tiles_y, A.F.p, A.Dc.p, n_out);
+    } else if (D == 3) {
+      // boxes of 2^31 faces or more: face fluxes, then the full cells
+      for (int d = 0; d < 3; ++d) {
+        const dim3 grid(nblk((int64_t)(g.n[0] + (d == 0)) * (g.n[1] + (d == 1))), (unsigned)(g.n[2] + (d == 2)));
+        auto k = d == 0 ? k_adv_flux<3, 0> : (d == 1 ? k_adv_flux<3, 1> : k_adv_flux<3, 2>);
+        hipLaunchKernelGGL(k, grid, dim3(256), 0, s, n_in, A.cls.p, vel, g, A.F.p + A.fbase[d]);
+      }
+      hipLaunchKernelGGL(k_adv_full<3>, dim3(nblk((int64_t)g.n[0] * g.n[1]), (unsigned)g.n[2]), dim3(256), 0, s,
+                         A.cls.p, g, A.F.p, n_in, A.Dc.p, n_out);
     } else {
-      hipLaunchKernelGGL(k_adv_faces<2>, dim3(nblk(A.nfaces)), dim3(256), 0, s, n_in, A.cls.p, vel, g, A.nfaces, A.F.p);
-      hipLaunchKernelGGL(k_adv_dc_full<2>, dim3(nblk(N)), dim3(256), 0, s, A.cls.p, g, A.F.p, A.Dc.p);
+      hipLaunchKernelGGL((k_adv_flux<2, 0>), flux_grid(0), dim3(256), 0, s, n_in, A.cls.p, vel, g, A.F.p + A.fbase[0]);
+      hipLaunchKernelGGL((k_adv_flux<2, 1>), flux_grid(1), dim3(256), 0, s, n_in, A.cls.p, vel, g, A.F.p + A.fbase[1]);
+      hipLaunchKernelGGL(k_adv_full<2>, cell_grid, dim3(256), 0, s, A.cls.p, g, A.F.p, n_in, A.Dc.p, n_out);
     }
     if (A.ncut > 0) {
       hipLaunchKernelGGL(k_adv_dc_cut, dim3(nblk(A.ncut)), dim3(256), 0, s, A.ncut, A.cut_cell.p, A.dc_ptr.p,
@@ -3779,7 +3795,6 @@ ebmg_status ebmg_advect(ebmg_problem pb, const double* n_in, const double* u_x, 
       hipLaunchKernelGGL(k_adv_cut, dim3(nblk(A.ncut)), dim3(256), 0, s, A.ncut, A.cut_cell.p, A.kappa.p, A.nb_ptr.p,
                          A.nb_cell.p, A.nb_w.p, A.cut_S.p, A.Dc.p, A.Dcut.p, A.give.p);
     }
-    hipLaunchKernelGGL(k_adv_update, dim3(nblk(N)), dim3(256), 0, s, A.cls.p, N, dt, n_in, A.Dc.p, n_out);
     if (A.nsp > 0)
       hipLaunchKernelGGL(k_adv_special, dim3(nblk(A.nsp)), dim3(256), 0, s, A.nsp, A.sp_cell.p, A.sp_cut.p, A.sp_ptr.p,
                          A.sp_donor.p, dt, n_in, A.Dc.p, A.Dcut.p, A.give.p, n_out);

@@ -642,3 +642,108 @@ def advection_pin_plane(n=128, seed=0):
     vmax = max(float(np.abs(x).max()) for x in u)
     dt = 0.5 * h / vmax
     return pr, n0, u, dt
+
+
+# --------------------------------------------------------------------------
+# nested AMR hierarchies (one box per level, refinement ratio 2)
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class AmrLevel:
+    """One level of a nested hierarchy: ``prob`` is the level's box (level 0
+    the whole domain; level l >= 1 one patch) with the domain's boundary
+    conditions on faces that lie on the domain boundary and homogeneous
+    Dirichlet on coarse-fine faces (flags ``cf``); ``lo`` is the box's first
+    cell in the level's global index space (domain cells times 2^l)."""
+    prob: Problem
+    lo: tuple
+    cf: list
+
+
+@dataclasses.dataclass
+class AmrProblem:
+    levels: List[AmrLevel]
+    name: str = ""
+
+    @property
+    def dim(self):
+        return self.levels[0].prob.dim
+
+
+def amr_hierarchy(dim, n0, h0, lo0, boxes, sample, bc_kind, bc_value, robin_a1=None, robin_a2=None, name="",
+                  **coef):
+    """Nested hierarchy over the domain box (n0 cells of size h0 from lo0).
+    ``boxes`` lists, for each level l >= 1, (lo, n) in that level's global
+    cell indices (even, inside the coarser box). ``sample(n, h, lo)`` returns
+    (objects, rho) of a box: its node-sampled level sets and cell-centred
+    source."""
+    robin_a1 = robin_a1 or [0.0] * 6
+    robin_a2 = robin_a2 or [1.0] * 6
+    levels = []
+    spec = [(tuple([0] * dim), tuple(n0))] + [(tuple(b[0]), tuple(b[1])) for b in boxes]
+    for l, (lo, n) in enumerate(spec):
+        h = h0 / (2 ** l)
+        full = tuple(m * 2 ** l for m in n0)
+        blo = tuple(lo0[d] + lo[d] * h for d in range(dim))
+        cf = [False] * 6
+        kind, val = list(bc_kind), list(bc_value)
+        for d in range(dim):
+            for side in (0, 1):
+                f = 2 * d + side
+                on_domain = (lo[d] == 0) if side == 0 else (lo[d] + n[d] == full[d])
+                if not on_domain:
+                    cf[f] = True
+                    kind[f] = BC_DIRICHLET
+                    val[f] = 0.0
+        objs, rho = sample(n, h, blo)
+        p = Problem(dim, n, h, blo, objs, kind, val, list(robin_a1), list(robin_a2),
+                    rho=None if rho is None else np.ascontiguousarray(rho), name=f"{name}-L{l}", **coef)
+        levels.append(AmrLevel(p, lo, cf))
+    return AmrProblem(levels, name)
+
+
+def amr_pin_plane(n0=64, nlev=3, seed=0, r_pin=0.02, nblob=8):
+    """The pin-plane gap (pin electrode at 1 with its apex at z = 0.6, eps = 4
+    slab below z = 0.2, Neumann x/y faces, Dirichlet 0 / 1 at z-/z+, eight
+    Gaussian space-charge blobs) on an n0^3 base grid refined twice around the
+    pin: level 1 covers x, y in [0.375, 0.625], z in [0.5, 1] (reaching the
+    top face, where the pin meets it), level 2 x, y in [0.4375, 0.5625],
+    z in [0.5625, 1]. The finest cells near the tip are those of a uniform
+    (4 n0)^3 grid."""
+    rng = np.random.default_rng(seed)
+    dists = [lambda c: _pin_distance_point(c, r=r_pin), lambda c: c[2] - 0.2]
+    cs, ss = _blobs3(rng, nblob, dists)
+
+    def sample(n, h, lo):
+        Xn = _nodes(3, n, h, lo)
+        objs = [Obj(OBJ_ELECTRODE, 1.0, np.ascontiguousarray(sdf_pin3(Xn, (0.5, 0.5), 0.6, r_pin))),
+                Obj(OBJ_DIELECTRIC, 4.0, np.ascontiguousarray(sdf_halfspace_below(Xn[2], 0.2)))]
+        X = _centres(3, n, h, lo)
+        rho = np.zeros(X[0].shape)
+        for c, s in zip(cs, ss):
+            rho += np.exp(-((X[0] - c[0]) ** 2 + (X[1] - c[1]) ** 2 + (X[2] - c[2]) ** 2) / (2 * s * s))
+        return objs, rho
+
+    def frac_box(l, xlo, xhi, zlo, zhi):
+        m = n0 * 2 ** l
+        lo = (int(round(xlo * m)), int(round(xlo * m)), int(round(zlo * m)))
+        hi = (int(round(xhi * m)), int(round(xhi * m)), int(round(zhi * m)))
+        return lo, tuple(hi[d] - lo[d] for d in range(3))
+
+    boxes = [frac_box(1, 0.375, 0.625, 0.5, 1.0), frac_box(2, 0.4375, 0.5625, 0.5625, 1.0)][:nlev - 1]
+    kind = [BC_NEUMANN, BC_NEUMANN, BC_NEUMANN, BC_NEUMANN, BC_DIRICHLET, BC_DIRICHLET]
+    val = [0.0, 0.0, 0.0, 0.0, 0.0, 1.0]
+    return amr_hierarchy(3, (n0,) * 3, 1.0 / n0, (0.0,) * 3, boxes, sample, kind, val,
+                         name=f"amr-pin-plane-{n0}-{nlev}")
+
+
+def amr_plain(dim, n0, boxes, bc=BC_DIRICHLET, rho_fn=None, **coef):
+    """A hierarchy over the unit box with no embedded objects (for the
+    operator's exactness and conservation pins); rho_fn(X) gives the source
+    at cell centres (None: no source)."""
+    def sample(n, h, lo):
+        X = _centres(dim, n, h, lo)
+        return [], (None if rho_fn is None else rho_fn(X))
+    k, v, a1, a2 = _bc(bc, 0.0)
+    return amr_hierarchy(dim, (n0,) * dim, 1.0 / n0, (0.0,) * dim, boxes, sample, k, v, a1, a2,
+                         name=f"amr-plain-{dim}d-{n0}", **coef)

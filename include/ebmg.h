@@ -62,6 +62,7 @@ typedef struct ebmg_problem_s* ebmg_problem;
 typedef struct ebmg_batch_s* ebmg_batch;
 typedef struct ebmg_family_s* ebmg_family;
 typedef struct ebmg_mesh_s* ebmg_mesh;
+typedef struct ebmg_amr_s* ebmg_amr;
 
 /* Box: dim in {2,3}; n[d] cells per axis (n[2] ignored in 2D); isotropic
  * cell size h; lower corner lo. */
@@ -555,6 +556,63 @@ ebmg_status ebmg_release_family(ebmg_family fam);
  * Queued on the context's stream and waited for. */
 ebmg_status ebmg_advect(ebmg_problem pb, const double* n_in, const double* u_x, const double* u_y,
                         const double* u_z, double dt, const double* inflow, double* n_out);
+
+/* Composite solves on nested AMR hierarchies. Paper: Numerical methods
+ * (patch-based refinement: levels of rectangular boxes, each inside the
+ * coarser level) and Helmholtz equations (coarse-fine faces: the coarse
+ * divergence refluxed with the fine fluxes through the face, held in flux
+ * registers). One box per level, refinement ratio 2, level 0 the domain.
+ * The unknowns are those of the cells no finer box covers; the operator is
+ * every level's own (the domain's boundary conditions on faces that lie on
+ * the domain boundary), with, at a coarse-fine face, fine fluxes taken
+ * through a ghost value (quadratic along the normal through two fine cells
+ * and the coarse level's quadratic interpolant; one-sided tangential
+ * differences where a side is missing) and the coarse face flux replaced by
+ * the mean of the fine fluxes on it (refluxing).
+ * Setup: boxes (HOST, nlev): level l's box with h = boxes[0].h / 2^l and
+ * corners on its lattice, inside the coarser box; nobj[l] and objs[l]
+ * (HOST) the objects sampled on level l's box nodes (as for ebmg_setup);
+ * bc the domain's conditions; opts shared by every level (the linear
+ * Dirichlet closure; precision picks FP64 or FP32 V-cycles). Boxes need even
+ * corners and sizes >= 4 on levels >= 1, and every cell the coarse-fine
+ * stencils use (two fine cells inside each coarse-fine face, two coarse
+ * cells outside a box, the tangential stencils) must be a regular gas cell
+ * no finer box covers: else ERR_GEOMETRY; bad boxes ERR_ARG; a host-only
+ * context checks all of this and then returns ERR_DEVICE. */
+ebmg_status ebmg_setup_amr(ebmg_ctx ctx, int32_t nlev, const ebmg_box* boxes, const int32_t* nobj,
+                           const ebmg_object* const* objs, const ebmg_domain_bc* bc, const ebmg_options* opts,
+                           ebmg_amr* out);
+
+/* Sizes of level `level` (no paper passage): its cells, second-phase
+ * unknowns, the unknowns covered by the next finer box, and the device bytes
+ * of the whole hierarchy. Any pointer may be NULL. */
+ebmg_status ebmg_query_amr(ebmg_amr a, int32_t level, int64_t* n_cells, int64_t* n_phase2, int64_t* n_covered,
+                           int64_t* device_bytes);
+
+/* Paper: Multigrid solver (residual reduction to ||r|| <= rtol ||r0||,
+ * r0 at phi = 0) applied to the composite system of the hierarchy.
+ * rho[l] (DEVICE, N_l doubles) per level; phi[l] (DEVICE, N_l; in: the
+ * guess, out: the solution) and phi2[l] (DEVICE, N2_l; may be NULL where a
+ * level has none). Right-preconditioned FP64 BiCGStab: the preconditioner
+ * restricts the fine residual onto covered cells, runs one V-cycle of level
+ * 0 over the domain, then level by level prolongs the coarse correction and
+ * adds one V-cycle of that level on its residual (homogeneous coarse-fine
+ * faces). On return covered cells hold the mean of their children (finest
+ * first). info (HOST, may be NULL): outer_iters the BiCGStab iterations,
+ * cycles two per iteration, rel_residual the composite relative residual,
+ * est_bytes 0 (not estimated). NOCONV after max_iters, NUMERIC on a
+ * non-finite residual; both leave the last iterate. */
+ebmg_status ebmg_solve_amr(ebmg_amr a, const double* const* rho, double rtol, int32_t max_iters, double* const* phi,
+                           double* const* phi2, ebmg_solve_info* info);
+
+/* Paper: Helmholtz equations (the composite operator with refluxing).
+ * out[l] = (A_comp [phi])_l per level (DEVICE arrays as in ebmg_solve_amr);
+ * covered unknowns are identity rows (out = phi there). */
+ebmg_status ebmg_apply_amr(ebmg_amr a, const double* const* phi, const double* const* phi2, double* const* out,
+                           double* const* out2);
+
+/* Free a hierarchy (no paper passage). NULL is ignored. */
+ebmg_status ebmg_release_amr(ebmg_amr a);
 
 /* Signed distance from surface tessellations. Paper: Geometry generation
  * (level sets from a watertight two-manifold tessellation held in a doubly

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libebmg.so")
 BUILD = os.path.join(HERE, "_build")
 
-HOST_SOURCES = ["geometry.cpp", "operator.cpp", "hierarchy.cpp", "mesh.cpp", "advect.cpp"]
+HOST_SOURCES = ["geometry.cpp", "operator.cpp", "hierarchy.cpp", "mesh.cpp", "advect.cpp", "amr.cpp"]
 HIP_SOURCES = ["solver.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -247,4 +247,33 @@ struct AdvHost {
 
 void build_advection(const Geometry& G, AdvHost& A);
 
+// ---------------------------------------------------------------------------
+// nested AMR hierarchies (amr.cpp)
+// ---------------------------------------------------------------------------
+struct AmrBox {
+  int lo[3] = {0, 0, 0};   // first cell in the level's global index space
+  int n[3] = {1, 1, 1};
+  bool cf[6] = {false, false, false, false, false, false};   // coarse-fine faces
+};
+
+// Coupling of level l (fine) with level l - 1 (coarse), as sparse rows over
+// unknown slots (cells, then second-phase unknowns, of each level's box).
+struct AmrLink {
+  // added to the fine level's A x: column >= 0 a fine slot, < 0 the coarse
+  // slot -column - 1
+  std::vector<int64_t> frow, fptr{0}, fcol;
+  std::vector<double> fw;
+  // added to the coarse level's A x: column >= 0 a coarse slot, < 0 the fine
+  // slot -column - 1
+  std::vector<int64_t> crow, cptr{0}, ccol;
+  std::vector<double> cw;
+  std::vector<int64_t> cov;                     // coarse slots under the fine box
+  std::vector<int64_t> rrow, rptr{0}, rcol;     // covered coarse unknown <- its
+  std::vector<double> rw, aw;                   // children's (rw: 1/2^D, aw: mean)
+  std::vector<int64_t> pcol;                    // fine slot <- coarse slot (-1: none)
+};
+
+void build_amr_link(const Problem& C, const AmrBox& cb, const Problem& F, const AmrBox& fb, const AmrBox* finer,
+                    AmrLink& out);
+
 }  // namespace ebmg

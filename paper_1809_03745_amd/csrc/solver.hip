@@ -31,6 +31,7 @@
 #include "kernels.hpp"
 #include "sdf_kernels.hpp"
 #include "adv_kernels.hpp"
+#include "amr_kernels.hpp"
 
 namespace ebmg {
 
@@ -325,6 +326,31 @@ struct ebmg_family_s {
   std::vector<ebmg_ctx> mctx;                // one private context per member
   std::vector<ebmg_problem_s*> mem;
   bool warm = false;                         // every member has solved once (graphs captured)
+};
+
+// A nested AMR hierarchy: one problem per level (its own operator and
+// multigrid hierarchy), the coupling rows of every coarse-fine interface on
+// the device, and the composite vectors (every level's unknowns in one
+// contiguous array, each level's slice starting on a 64-entry boundary).
+struct ebmg_amr_s {
+  ebmg_ctx ctx = nullptr;
+  std::vector<ebmg_problem_s*> lev;
+  std::vector<ebmg::AmrBox> box;
+  struct Link {
+    ebmg::DevBuf<int64_t> frow, fptr, fcol, crow, cptr, ccol, cov, rrow, rptr, rcol, pcol;
+    ebmg::DevBuf<double> fw, cw, rw, aw;
+    int64_t nf = 0, nc = 0, ncov = 0, nr = 0, np = 0;
+    void release() {
+      frow.release(); fptr.release(); fcol.release(); crow.release(); cptr.release(); ccol.release();
+      cov.release(); rrow.release(); rptr.release(); rcol.release(); pcol.release();
+      fw.release(); cw.release(); rw.release(); aw.release();
+    }
+  };
+  std::vector<Link> link;          // link[l] couples level l with level l - 1 (l >= 1)
+  std::vector<int64_t> off, nd;    // per level: slice offset and unknowns (N + N2)
+  int64_t ntot = 0;
+  ebmg::DevBuf<double> x, b, r, rh, p, v, sv, t, ph, sh, rt, y, e, part, scal;
+  int64_t bytes = 0;
 };
 
 // Many independent boxes solved by one persistent launch.
@@ -2486,6 +2512,157 @@ static void ctx_unref(ebmg_ctx c) {
   delete c;
 }
 
+namespace ebmg {
+
+static void amr_free(ebmg_amr_s* A) {
+  if (A->ctx && A->ctx->device >= 0) {
+    (void)hipSetDevice(A->ctx->device);
+    (void)hipStreamSynchronize(A->ctx->stream);
+  }
+  for (auto& k : A->link) k.release();
+  A->link.clear();
+  for (auto* b : {&A->x, &A->b, &A->r, &A->rh, &A->p, &A->v, &A->sv, &A->t, &A->ph, &A->sh, &A->rt, &A->y, &A->e,
+                  &A->part, &A->scal})
+    b->release();
+  for (ebmg_problem_s* P : A->lev) {
+    if (!P) continue;
+    if (P->on_device) P->dev.release();
+    delete P;
+  }
+  A->lev.clear();
+}
+
+// y = A_comp x: every level's operator, the coupling rows of each interface
+// (fine rows with their ghosts, refluxed coarse rows) and identity rows for
+// the covered coarse unknowns
+static void amr_apply(ebmg_amr_s* A, const double* x, double* y, hipStream_t s) {
+  const int L = (int)A->lev.size();
+  for (int l = 0; l < L; ++l) residual<double, 1>(A->lev[l]->dev.lv[0], x + A->off[l], nullptr, y + A->off[l], s);
+  for (int l = 1; l < L; ++l) {
+    auto& K = A->link[l];
+    const int64_t of = A->off[l], oc = A->off[l - 1];
+    if (K.nf)
+      hipLaunchKernelGGL(k_amr_rows, dim3(nblk(K.nf)), dim3(256), 0, s, K.nf, K.frow.p, K.fptr.p, K.fcol.p, K.fw.p,
+                         x + of, x + oc, y + of);
+    if (K.nc)
+      hipLaunchKernelGGL(k_amr_rows, dim3(nblk(K.nc)), dim3(256), 0, s, K.nc, K.crow.p, K.cptr.p, K.ccol.p, K.cw.p,
+                         x + oc, x + of, y + oc);
+    if (K.ncov)
+      hipLaunchKernelGGL(k_amr_set, dim3(nblk(K.ncov)), dim3(256), 0, s, K.ncov, K.cov.p, x + oc, y + oc);
+  }
+  HIPCHECK(hipGetLastError());
+}
+
+// z = M r: the fine residual restricted onto the covered unknowns (finest
+// first), one V-cycle of level 0 over the whole domain, then per finer
+// level the coarse correction prolonged (piecewise constant), the level's
+// residual with the ghosts of that correction, and one V-cycle of the level
+// with homogeneous coarse-fine faces added; covered unknowns end at 0. A
+// fixed linear map (the V-cycles start from zero), so it serves as the
+// right preconditioner of BiCGStab.
+static void amr_precond(ebmg_amr_s* A, const double* r, double* z, hipStream_t s) {
+  const int L = (int)A->lev.size();
+  const int64_t n = A->ntot;
+  double* rt = A->rt.p;
+  double* y = A->y.p;
+  double* e = A->e.p;
+  hipLaunchKernelGGL(k_amr_lin, dim3(nblk(n)), dim3(256), 0, s, n, 1.0, r, 0.0, r, rt);
+  for (int l = L - 1; l >= 1; --l) {
+    auto& K = A->link[l];
+    if (K.nr)
+      hipLaunchKernelGGL(k_amr_gather, dim3(nblk(K.nr)), dim3(256), 0, s, K.nr, K.rrow.p, K.rptr.p, K.rcol.p, K.rw.p,
+                         rt + A->off[l], rt + A->off[l - 1]);
+  }
+  precond(A->lev[0]->dev, A->lev[0]->host->opt, rt + A->off[0], z + A->off[0], s);
+  for (int l = 1; l < L; ++l) {
+    auto& K = A->link[l];
+    const int64_t of = A->off[l], oc = A->off[l - 1], m = A->nd[l];
+    hipLaunchKernelGGL(k_amr_prolong, dim3(nblk(m)), dim3(256), 0, s, m, K.pcol.p, z + oc, z + of);
+    residual<double, 1>(A->lev[l]->dev.lv[0], z + of, nullptr, y + of, s);
+    if (K.nf)
+      hipLaunchKernelGGL(k_amr_rows, dim3(nblk(K.nf)), dim3(256), 0, s, K.nf, K.frow.p, K.fptr.p, K.fcol.p, K.fw.p,
+                         z + of, z + oc, y + of);
+    hipLaunchKernelGGL(k_amr_lin, dim3(nblk(m)), dim3(256), 0, s, m, 1.0, r + of, -1.0, y + of, y + of);
+    precond(A->lev[l]->dev, A->lev[l]->host->opt, y + of, e + of, s);
+    hipLaunchKernelGGL(k_amr_lin, dim3(nblk(m)), dim3(256), 0, s, m, 1.0, z + of, 1.0, e + of, z + of);
+  }
+  for (int l = 1; l < L; ++l) {
+    auto& K = A->link[l];
+    if (K.ncov)
+      hipLaunchKernelGGL(k_amr_set, dim3(nblk(K.ncov)), dim3(256), 0, s, K.ncov, K.cov.p, (const double*)nullptr,
+                         z + A->off[l - 1]);
+  }
+  HIPCHECK(hipGetLastError());
+}
+
+static double amr_dot(ebmg_amr_s* A, const double* a, const double* b, hipStream_t s) {
+  hipLaunchKernelGGL((k_dot_partial<double>), dim3(kNormBlocks), dim3(kBlock), 0, s, a, b, A->ntot, A->part.p);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, s, A->part.p, kNormBlocks, 1, A->scal.p);
+  HIPCHECK(hipGetLastError());
+  double h = 0;
+  HIPCHECK(hipMemcpyAsync(&h, A->scal.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  return h;
+}
+
+// right-preconditioned BiCGStab over the composite vector, FP64, from the
+// guess in A->x; one host round trip per dot product
+static ebmg_status amr_bicgstab(ebmg_amr_s* A, double rtol, int maxit, double& bn, double& rel, int& iters,
+                                hipStream_t s) {
+  const int64_t n = A->ntot;
+  const dim3 g(nblk(n)), blk(256);
+  double *x = A->x.p, *b = A->b.p, *r = A->r.p, *rh = A->rh.p, *p = A->p.p, *v = A->v.p, *sv = A->sv.p,
+         *t = A->t.p, *ph = A->ph.p, *sh = A->sh.p, *y = A->y.p;
+  iters = 0;
+  bn = std::sqrt(amr_dot(A, b, b, s));
+  if (!(bn > 0)) {
+    fill<double>(x, n, 0.0, s);
+    rel = 0;
+    return EBMG_OK;
+  }
+  amr_apply(A, x, y, s);
+  hipLaunchKernelGGL(k_amr_lin, g, blk, 0, s, n, 1.0, b, -1.0, y, r);
+  rel = std::sqrt(amr_dot(A, r, r, s)) / bn;
+  if (rel <= rtol) return EBMG_OK;
+  hipLaunchKernelGGL(k_amr_lin, g, blk, 0, s, n, 1.0, r, 0.0, r, rh);
+  fill<double>(p, n, 0.0, s);
+  fill<double>(v, n, 0.0, s);
+  double rho_old = 1, alpha = 1, omega = 1;
+  while (iters < maxit) {
+    ++iters;
+    const double rho = amr_dot(A, rh, r, s);
+    if (!std::isfinite(rho)) return EBMG_ERR_NUMERIC;
+    if (rho == 0.0) return EBMG_ERR_NOCONV;
+    const double beta = (rho / rho_old) * (alpha / omega);
+    hipLaunchKernelGGL(k_amr_p, g, blk, 0, s, n, r, beta, omega, v, p);
+    amr_precond(A, p, ph, s);
+    amr_apply(A, ph, v, s);
+    alpha = rho / amr_dot(A, rh, v, s);
+    hipLaunchKernelGGL(k_amr_lin, g, blk, 0, s, n, 1.0, r, -alpha, v, sv);
+    const double sn = std::sqrt(amr_dot(A, sv, sv, s)) / bn;
+    if (!std::isfinite(sn)) return EBMG_ERR_NUMERIC;
+    if (sn <= rtol) {
+      hipLaunchKernelGGL(k_amr_lin, g, blk, 0, s, n, 1.0, x, alpha, ph, x);
+      hipLaunchKernelGGL(k_amr_lin, g, blk, 0, s, n, 1.0, sv, 0.0, sv, r);
+      rel = sn;
+      return EBMG_OK;
+    }
+    amr_precond(A, sv, sh, s);
+    amr_apply(A, sh, t, s);
+    const double tt = amr_dot(A, t, t, s);
+    omega = tt > 0 ? amr_dot(A, t, sv, s) / tt : 0.0;
+    hipLaunchKernelGGL(k_amr_xr, g, blk, 0, s, n, alpha, ph, omega, sh, sv, t, x, r);
+    rel = std::sqrt(amr_dot(A, r, r, s)) / bn;
+    if (!std::isfinite(rel)) return EBMG_ERR_NUMERIC;
+    if (rel <= rtol) return EBMG_OK;
+    if (omega == 0.0) return EBMG_ERR_NOCONV;
+    rho_old = rho;
+  }
+  return EBMG_ERR_NOCONV;
+}
+
+}  // namespace ebmg
+
 extern "C" {
 
 void ebmg_default_options(ebmg_options* o) {
@@ -3802,6 +3979,272 @@ ebmg_status ebmg_advect(ebmg_problem pb, const double* n_in, const double* u_x, 
     HIPCHECK(hipStreamSynchronize(s));
     return EBMG_OK;
   });
+}
+
+ebmg_status ebmg_setup_amr(ebmg_ctx ctx, int32_t nlev, const ebmg_box* boxes, const int32_t* nobj,
+                           const ebmg_object* const* objs, const ebmg_domain_bc* bc, const ebmg_options* opts,
+                           ebmg_amr* out) {
+  if (!ctx || nlev < 1 || nlev > 8 || !boxes || !nobj || !objs || !bc || !out) {
+    if (ctx) ctx->err = "invalid argument to ebmg_setup_amr";
+    return EBMG_ERR_ARG;
+  }
+  *out = nullptr;
+  auto A = std::make_unique<ebmg_amr_s>();
+  A->ctx = ctx;
+  const ebmg_status st = guard(ctx, [&]() -> ebmg_status {
+    const int D = boxes[0].dim;
+    if (D != 2 && D != 3) throw ArgError("dim must be 2 or 3");
+    ebmg::Options o0;
+    if (parse_options(opts, nobj[0], o0) != EBMG_OK) throw ArgError("bad options");
+    if (o0.dirichlet_closure != 0)
+      throw ArgError("AMR hierarchies use the linear Dirichlet closure on their coarse-fine faces");
+    // boxes: level l has cells of size h0 / 2^l, corners on the level's lattice
+    A->box.resize(nlev);
+    for (int l = 0; l < nlev; ++l) {
+      const ebmg_box& B = boxes[l];
+      if (B.dim != D) throw ArgError("every level has the base box's dimension");
+      if (nobj[l] < 0 || nobj[l] > 64 || (nobj[l] > 0 && !objs[l])) throw ArgError("bad objects of a level");
+      const double h = boxes[0].h / (double)(1 << l);
+      if (std::fabs(B.h - h) > 1e-12 * h) throw ArgError("level l needs cells of size h0 / 2^l");
+      ebmg::AmrBox& X = A->box[l];
+      for (int d = 0; d < D; ++d) {
+        const double q = (B.lo[d] - boxes[0].lo[d]) / h;
+        X.lo[d] = (int)std::lround(q);
+        X.n[d] = B.n[d];
+        if (std::fabs(q - X.lo[d]) > 1e-6) throw ArgError("an AMR box corner is off its level's lattice");
+        const int full = boxes[0].n[d] << l;
+        if (X.lo[d] < 0 || X.n[d] < 1 || X.lo[d] + X.n[d] > full) throw ArgError("an AMR box leaves the domain");
+        X.cf[2 * d] = l > 0 && X.lo[d] > 0;
+        X.cf[2 * d + 1] = l > 0 && X.lo[d] + X.n[d] < full;
+      }
+      if (l == 0)
+        for (int d = 0; d < D; ++d)
+          if (X.lo[d] != 0 || X.n[d] != boxes[0].n[d]) throw ArgError("level 0 is the domain");
+    }
+    // proper nesting: each box on even corners, its coarse cells inside the
+    // coarser box and at least two cells from that box's coarse-fine faces
+    for (int l = 1; l < nlev; ++l) {
+      const ebmg::AmrBox &F = A->box[l], &Cb = A->box[l - 1];
+      for (int d = 0; d < D; ++d) {
+        if (F.lo[d] % 2 || F.n[d] % 2 || F.n[d] < 4) throw ArgError("AMR boxes need even corners and sizes >= 4");
+        const int clo = F.lo[d] / 2, chi = (F.lo[d] + F.n[d]) / 2;
+        const int mlo = Cb.cf[2 * d] ? 2 : 0, mhi = Cb.cf[2 * d + 1] ? 2 : 0;
+        if (clo < Cb.lo[d] + mlo || chi > Cb.lo[d] + Cb.n[d] - mhi)
+          throw ArgError("an AMR box must lie inside the next coarser box, two cells from its coarse-fine faces");
+      }
+    }
+    // one problem per level: the domain's conditions on domain faces,
+    // homogeneous Dirichlet on coarse-fine faces
+    for (int l = 0; l < nlev; ++l) {
+      auto P = std::make_unique<ebmg_problem_s>();
+      P->ctx = ctx;
+      P->host = std::make_unique<Problem>();
+      Problem& H = *P->host;
+      if (parse_options(opts, nobj[l], H.opt) != EBMG_OK) throw ArgError("bad options");
+      ebmg_domain_bc lb = *bc;
+      for (int f = 0; f < 2 * D; ++f)
+        if (A->box[l].cf[f]) {
+          lb.kind[f] = EBMG_BC_DIRICHLET;
+          lb.value[f] = 0.0;
+        }
+      build_host_problem(H, &boxes[l], nobj[l], objs[l], &lb);
+      A->lev.push_back(P.release());
+    }
+    std::vector<AmrLink> host_links(nlev);
+    for (int l = 1; l < nlev; ++l)
+      build_amr_link(*A->lev[l - 1]->host, A->box[l - 1], *A->lev[l]->host, A->box[l],
+                     l + 1 < nlev ? &A->box[l + 1] : nullptr, host_links[l]);
+    // the host part is checked on any context; the solve needs a device
+    if (ctx->device < 0) throw DeviceError("an AMR hierarchy needs a device context");
+    HIPCHECK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    for (ebmg_problem_s* P : A->lev) {
+      upload(P);
+      P->on_device = true;
+      A->bytes += P->dev.bytes;
+    }
+    A->off.assign(nlev, 0);
+    A->nd.assign(nlev, 0);
+    int64_t o = 0;
+    for (int l = 0; l < nlev; ++l) {
+      A->off[l] = o;
+      A->nd[l] = A->lev[l]->host->geo.N + A->lev[l]->host->geo.N2;
+      o += (A->nd[l] + 63) / 64 * 64;
+    }
+    A->ntot = o;
+    int64_t by = 0;
+    A->link.resize(nlev);
+    for (int l = 1; l < nlev; ++l) {
+      AmrLink& H = host_links[l];
+      auto& K = A->link[l];
+      K.nf = (int64_t)H.frow.size();
+      K.nc = (int64_t)H.crow.size();
+      K.ncov = (int64_t)H.cov.size();
+      K.nr = (int64_t)H.rrow.size();
+      K.np = (int64_t)H.pcol.size();
+      K.frow.upload(H.frow.data(), (int64_t)H.frow.size(), s, by);
+      K.fptr.upload(H.fptr.data(), (int64_t)H.fptr.size(), s, by);
+      K.fcol.upload(H.fcol.data(), (int64_t)H.fcol.size(), s, by);
+      K.fw.upload(H.fw.data(), (int64_t)H.fw.size(), s, by);
+      K.crow.upload(H.crow.data(), (int64_t)H.crow.size(), s, by);
+      K.cptr.upload(H.cptr.data(), (int64_t)H.cptr.size(), s, by);
+      K.ccol.upload(H.ccol.data(), (int64_t)H.ccol.size(), s, by);
+      K.cw.upload(H.cw.data(), (int64_t)H.cw.size(), s, by);
+      K.cov.upload(H.cov.data(), (int64_t)H.cov.size(), s, by);
+      K.rrow.upload(H.rrow.data(), (int64_t)H.rrow.size(), s, by);
+      K.rptr.upload(H.rptr.data(), (int64_t)H.rptr.size(), s, by);
+      K.rcol.upload(H.rcol.data(), (int64_t)H.rcol.size(), s, by);
+      K.rw.upload(H.rw.data(), (int64_t)H.rw.size(), s, by);
+      K.aw.upload(H.aw.data(), (int64_t)H.aw.size(), s, by);
+      K.pcol.upload(H.pcol.data(), (int64_t)H.pcol.size(), s, by);
+    }
+    for (auto* b : {&A->x, &A->b, &A->r, &A->rh, &A->p, &A->v, &A->sv, &A->t, &A->ph, &A->sh, &A->rt, &A->y, &A->e})
+      b->alloc(A->ntot, by);
+    A->part.alloc(kNormBlocks, by);
+    A->scal.alloc(8, by);
+    for (auto* b : {&A->x, &A->b, &A->r, &A->rh, &A->p, &A->v, &A->sv, &A->t, &A->ph, &A->sh, &A->rt, &A->y, &A->e})
+      fill<double>(b->p, A->ntot, 0.0, s);
+    HIPCHECK(hipStreamSynchronize(s));
+    A->bytes += by;
+    return EBMG_OK;
+  });
+  if (st != EBMG_OK) {
+    amr_free(A.get());
+    return st;
+  }
+  *out = A.release();
+  ++ctx->refs;
+  return EBMG_OK;
+}
+
+ebmg_status ebmg_query_amr(ebmg_amr a, int32_t level, int64_t* n_cells, int64_t* n_phase2, int64_t* n_covered,
+                           int64_t* device_bytes) {
+  if (!a || level < 0 || level >= (int32_t)a->lev.size()) return EBMG_ERR_ARG;
+  if (n_cells) *n_cells = a->lev[level]->host->geo.N;
+  if (n_phase2) *n_phase2 = a->lev[level]->host->geo.N2;
+  if (n_covered) *n_covered = level + 1 < (int32_t)a->lev.size() ? a->link[level + 1].ncov : 0;
+  if (device_bytes) *device_bytes = a->bytes;
+  return EBMG_OK;
+}
+
+// phi (and phi2) per level <- / -> the composite vector slices
+static void amr_copy(ebmg_amr_s* A, double* const* phi, double* const* phi2, bool in, hipStream_t s) {
+  for (size_t l = 0; l < A->lev.size(); ++l) {
+    const int64_t N = A->lev[l]->host->geo.N, N2 = A->lev[l]->host->geo.N2;
+    double* slice = A->x.p + A->off[l];
+    if (in) {
+      HIPCHECK(hipMemcpyAsync(slice, phi[l], sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+      if (N2 > 0) HIPCHECK(hipMemcpyAsync(slice + N, phi2[l], sizeof(double) * N2, hipMemcpyDeviceToDevice, s));
+    } else {
+      HIPCHECK(hipMemcpyAsync(phi[l], slice, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+      if (N2 > 0) HIPCHECK(hipMemcpyAsync(phi2[l], slice + N, sizeof(double) * N2, hipMemcpyDeviceToDevice, s));
+    }
+  }
+}
+
+// per level a non-null array, and where need2 a second one for levels with
+// second-phase unknowns
+static void amr_check_args(ebmg_amr_s* A, const void* const* a, const void* const* a2, bool need2, const char* what) {
+  for (size_t l = 0; l < A->lev.size(); ++l) {
+    if (!a[l]) throw ArgError(std::string(what) + ": a level's array is null");
+    if (need2 && A->lev[l]->host->geo.N2 > 0 && (!a2 || !a2[l]))
+      throw ArgError(std::string(what) + ": a level with second-phase unknowns needs its second array");
+  }
+}
+
+ebmg_status ebmg_solve_amr(ebmg_amr a, const double* const* rho, double rtol, int32_t max_iters, double* const* phi,
+                           double* const* phi2, ebmg_solve_info* info) {
+  if (!a || !rho || !phi || !(rtol > 0) || max_iters < 1) {
+    if (a) a->ctx->err = "invalid argument to ebmg_solve_amr";
+    return EBMG_ERR_ARG;
+  }
+  ebmg_solve_info loc{};
+  const ebmg_status st = guard(a->ctx, [&]() -> ebmg_status {
+    auto t0 = std::chrono::steady_clock::now();
+    amr_check_args(a, (const void* const*)rho, nullptr, false, "rho");
+    amr_check_args(a, (const void* const*)phi, (const void* const*)phi2, true, "phi");
+    HIPCHECK(hipSetDevice(a->ctx->device));
+    hipStream_t s = a->ctx->stream;
+    const int L = (int)a->lev.size();
+    // right-hand side per level (its boundary data; 0 on coarse-fine faces),
+    // 0 on covered unknowns
+    for (int l = 0; l < L; ++l) {
+      ebmg_problem_s* P = a->lev[l];
+      rhs(P, rho[l], nullptr, nullptr, nullptr);
+      HIPCHECK(hipMemcpyAsync(a->b.p + a->off[l], P->dev.lv[0].b64.p, sizeof(double) * a->nd[l],
+                              hipMemcpyDeviceToDevice, s));
+    }
+    amr_copy(a, phi, phi2, true, s);
+    for (int l = 1; l < L; ++l) {
+      auto& K = a->link[l];
+      if (K.ncov) {
+        hipLaunchKernelGGL(k_amr_set, dim3(nblk(K.ncov)), dim3(256), 0, s, K.ncov, K.cov.p, (const double*)nullptr,
+                           a->b.p + a->off[l - 1]);
+        hipLaunchKernelGGL(k_amr_set, dim3(nblk(K.ncov)), dim3(256), 0, s, K.ncov, K.cov.p, (const double*)nullptr,
+                           a->x.p + a->off[l - 1]);
+      }
+    }
+    HIPCHECK(hipGetLastError());
+    double bn = 0, rel = 0;
+    int iters = 0;
+    ebmg_status res = amr_bicgstab(a, rtol, max_iters, bn, rel, iters, s);
+    // the true residual of the result
+    if (res == EBMG_OK || res == EBMG_ERR_NOCONV) {
+      amr_apply(a, a->x.p, a->y.p, s);
+      hipLaunchKernelGGL(k_amr_lin, dim3(nblk(a->ntot)), dim3(256), 0, s, a->ntot, 1.0, a->b.p, -1.0, a->y.p,
+                         a->r.p);
+      rel = bn > 0 ? std::sqrt(amr_dot(a, a->r.p, a->r.p, s)) / bn : 0.0;
+      if (!std::isfinite(rel)) res = EBMG_ERR_NUMERIC;
+    }
+    // covered cells take the mean of their children, finest first
+    for (int l = L - 1; l >= 1; --l) {
+      auto& K = a->link[l];
+      if (K.nr)
+        hipLaunchKernelGGL(k_amr_gather, dim3(nblk(K.nr)), dim3(256), 0, s, K.nr, K.rrow.p, K.rptr.p, K.rcol.p,
+                           K.aw.p, a->x.p + a->off[l], a->x.p + a->off[l - 1]);
+    }
+    amr_copy(a, phi, phi2, false, s);
+    HIPCHECK(hipStreamSynchronize(s));
+    loc.cycles = 2 * iters;
+    loc.outer_iters = iters;
+    loc.levels = L;
+    loc.r0_norm = bn;
+    loc.rel_residual = rel;
+    loc.est_bytes = 0;
+    loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (res == EBMG_ERR_NOCONV) a->ctx->err = "AMR solve did not reach the tolerance";
+    if (res == EBMG_ERR_NUMERIC) a->ctx->err = "AMR solve produced a non-finite residual";
+    return res;
+  });
+  if (info) *info = loc;
+  return st;
+}
+
+ebmg_status ebmg_apply_amr(ebmg_amr a, const double* const* phi, const double* const* phi2, double* const* out,
+                           double* const* out2) {
+  if (!a || !phi || !out) return EBMG_ERR_ARG;
+  return guard(a->ctx, [&]() -> ebmg_status {
+    amr_check_args(a, (const void* const*)phi, (const void* const*)phi2, true, "phi");
+    amr_check_args(a, (const void* const*)out, (const void* const*)out2, true, "out");
+    HIPCHECK(hipSetDevice(a->ctx->device));
+    hipStream_t s = a->ctx->stream;
+    amr_copy(a, const_cast<double* const*>(phi), const_cast<double* const*>(phi2), true, s);
+    amr_apply(a, a->x.p, a->y.p, s);
+    // the result leaves through the x slices
+    HIPCHECK(hipMemcpyAsync(a->x.p, a->y.p, sizeof(double) * a->ntot, hipMemcpyDeviceToDevice, s));
+    amr_copy(a, out, out2, false, s);
+    HIPCHECK(hipStreamSynchronize(s));
+    return EBMG_OK;
+  });
+}
+
+ebmg_status ebmg_release_amr(ebmg_amr a) {
+  if (!a) return EBMG_OK;
+  ebmg_ctx ctx = a->ctx;
+  amr_free(a);
+  delete a;
+  ctx_unref(ctx);
+  return EBMG_OK;
 }
 
 ebmg_status ebmg_mesh_create(ebmg_ctx ctx, int32_t nvert, const double* verts, int32_t ntri, const int32_t* tris,

@@ -133,6 +133,11 @@ _sig("ebmg_solve_family", C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.c_dou
                                     C.POINTER(_vp), C.POINTER(SolveInfo), C.POINTER(C.c_int)])
 _sig("ebmg_release_family", C.c_int, [_vp])
 _sig("ebmg_advect", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, _vp, _vp])
+_sig("ebmg_setup_amr", C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp])
+_sig("ebmg_query_amr", C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp])
+_sig("ebmg_solve_amr", C.c_int, [_vp, _vp, C.c_double, C.c_int32, _vp, _vp, _vp])
+_sig("ebmg_apply_amr", C.c_int, [_vp, _vp, _vp, _vp, _vp])
+_sig("ebmg_release_amr", C.c_int, [_vp])
 _sig("ebmg_mesh_create", C.c_int, [_vp, C.c_int32, _vp, C.c_int32, _vp, C.POINTER(_vp)])
 _sig("ebmg_mesh_query", C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32), _i64p])
 _sig("ebmg_mesh_sdf", C.c_int, [_vp, C.POINTER(Box), _vp, _i64p])
@@ -145,7 +150,8 @@ EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_des
             "ebmg_setup_batch", "ebmg_query_batch", "ebmg_query_batch_box", "ebmg_query_batch_tuning", "ebmg_solve_batch", "ebmg_release_batch",
             "ebmg_set_coefficients", "ebmg_smooth", "ebmg_kernel_timing",
             "ebmg_setup_family", "ebmg_query_family", "ebmg_solve_family", "ebmg_release_family",
-            "ebmg_mesh_create", "ebmg_mesh_query", "ebmg_mesh_sdf", "ebmg_mesh_release", "ebmg_advect"]
+            "ebmg_mesh_create", "ebmg_mesh_query", "ebmg_mesh_sdf", "ebmg_mesh_release", "ebmg_advect",
+            "ebmg_setup_amr", "ebmg_query_amr", "ebmg_solve_amr", "ebmg_apply_amr", "ebmg_release_amr"]
 
 
 def abi_version():
@@ -713,6 +719,87 @@ class Mesh:
     def release(self):
         if getattr(self, "h", None):
             _lib.ebmg_mesh_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class Amr:
+    """A nested AMR hierarchy set up from a ``workloads.AmrProblem`` (one box
+    per level, level 0 the domain): composite solves and applies."""
+
+    def __init__(self, ctx, amr, **opts):
+        self.ctx = ctx
+        self.amr = amr
+        L = len(amr.levels)
+        boxes = (Box * L)()
+        keep, objarrs = [], []
+        nobj = (C.c_int32 * L)()
+        ptrs = (_vp * L)()
+        for l, lv in enumerate(amr.levels):
+            box, objs, _, sdf = _c_problem(lv.prob)
+            boxes[l] = box
+            keep.append(sdf)
+            objarrs.append(objs)
+            nobj[l] = len(lv.prob.objects)
+            ptrs[l] = C.cast(objs, _vp)
+        bc = _c_bc(amr.levels[0].prob)
+        self.options = make_options(amr.levels[0].prob, **opts)
+        h = _vp()
+        st = _lib.ebmg_setup_amr(ctx.h, L, boxes, nobj, ptrs, C.byref(bc), C.byref(self.options), C.byref(h))
+        del keep, objarrs
+        ctx.check(st, "ebmg_setup_amr")
+        self.h = h
+        self.L = L
+        self.N, self.N2, self.covered = [], [], []
+        for l in range(L):
+            n, n2, nc, by = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+            ctx.check(_lib.ebmg_query_amr(h, l, C.byref(n), C.byref(n2), C.byref(nc), C.byref(by)), "ebmg_query_amr")
+            self.N.append(n.value)
+            self.N2.append(n2.value)
+            self.covered.append(nc.value)
+            self.device_bytes = by.value
+
+    def _arrays(self, ts, sizes, name, nullable=False):
+        arr = (_vp * self.L)()
+        for l in range(self.L):
+            t = ts[l] if ts is not None else None
+            if sizes[l] == 0 and t is None:
+                arr[l] = None
+                continue
+            arr[l] = _dev(self.ctx, t, sizes[l], f"{name}[{l}]", nullable=nullable and sizes[l] == 0)
+        return arr
+
+    def solve(self, rho, phi, phi2=None, rtol=1e-10, max_iters=200, check=True):
+        """rho, phi (and phi2 where a level has second-phase unknowns): lists
+        of device float64 tensors per level. Returns (status, info dict)."""
+        if len(rho) != self.L or len(phi) != self.L:
+            raise EbmgError(ERR_ARG, f"{self.L} levels expected")
+        r = self._arrays(rho, self.N, "rho")
+        x = self._arrays(phi, self.N, "phi")
+        x2 = self._arrays(phi2, self.N2, "phi2", nullable=True) if phi2 is not None else None
+        if x2 is None and any(self.N2):
+            raise EbmgError(ERR_ARG, "phi2 needed for levels with second-phase unknowns")
+        info = SolveInfo()
+        st = _lib.ebmg_solve_amr(self.h, r, float(rtol), int(max_iters), x, x2, C.byref(info))
+        if check:
+            self.ctx.check(st, "ebmg_solve_amr")
+        return st, info.as_dict()
+
+    def apply(self, phi, out, phi2=None, out2=None):
+        x = self._arrays(phi, self.N, "phi")
+        y = self._arrays(out, self.N, "out")
+        x2 = self._arrays(phi2, self.N2, "phi2", nullable=True) if phi2 is not None else None
+        y2 = self._arrays(out2, self.N2, "out2", nullable=True) if out2 is not None else None
+        self.ctx.check(_lib.ebmg_apply_amr(self.h, x, x2, y, y2), "ebmg_apply_amr")
+
+    def release(self):
+        if self.h:
+            _lib.ebmg_release_amr(self.h)
             self.h = None
 
     def __del__(self):

@@ -385,3 +385,35 @@ def test_every_declaration_cites_its_passage():
         if "Paper" not in com and "paper passage" not in com and "cannot allocate" not in com:
             missing.append(m.group(1))
     assert not missing, missing
+
+
+def test_amr_host_checks_on_a_host_only_context():
+    """The AMR setup builds and checks its coarse-fine structures on any
+    context: a valid hierarchy reaches the device requirement (ERR_DEVICE), a
+    patch whose coarse-fine face cuts the electrode is ERR_GEOMETRY, boxes off
+    the coarse lattice or a quadratic Dirichlet closure are ERR_ARG."""
+    import workloads as W
+    ctx = ebmg.Context(-1)
+    for amr in (W.amr_plain(2, 16, [((8, 10), (12, 14))]), W.amr_pin_plane(64, 3),
+                W.amr_pin_plane(32, 2, r_pin=0.05)):
+        with pytest.raises(ebmg.EbmgError) as e:
+            ebmg.Amr(ctx, amr)
+        assert e.value.status == ebmg.ERR_DEVICE
+
+    def objs(n, h, lo):
+        Xn = W._nodes(3, n, h, lo)
+        return [W.Obj(W.OBJ_ELECTRODE, 1.0, np.ascontiguousarray(W.sdf_pin3(Xn, (0.5, 0.5), 0.6, 0.1)))], None
+    bad = W.amr_hierarchy(3, (32,) * 3, 1.0 / 32, (0.0,) * 3, [((24, 24, 38), (16, 16, 26))], objs,
+                          [W.BC_NEUMANN] * 4 + [W.BC_DIRICHLET] * 2, [0.0] * 5 + [1.0])
+    with pytest.raises(ebmg.EbmgError) as e:
+        ebmg.Amr(ctx, bad)
+    assert e.value.status == ebmg.ERR_GEOMETRY
+    with pytest.raises(ebmg.EbmgError) as e:
+        ebmg.Amr(ctx, W.amr_plain(2, 16, [((7, 8), (12, 12))]))
+    assert e.value.status == ebmg.ERR_ARG
+    with pytest.raises(ebmg.EbmgError) as e:
+        ebmg.Amr(ctx, W.amr_plain(2, 16, [((8, 8), (12, 12))]), dirichlet_closure=1)
+    assert e.value.status == ebmg.ERR_ARG
+    with pytest.raises(ebmg.EbmgError) as e:   # a box reaching past its coarser box
+        ebmg.Amr(ctx, W.amr_plain(2, 16, [((4, 4), (16, 16)), ((24, 8), (20, 20))]))
+    assert e.value.status == ebmg.ERR_ARG

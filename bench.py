@@ -637,6 +637,56 @@ def advection_bench(n=256, steps=20, oracle_n=64):
     return out
 
 
+def amr_bench(n0=128, nlev=3, reps=3):
+    """Composite solves on the pin-plane gap refined twice around the pin
+    (n0^3 base, the finest cells those of a (4 n0)^3 grid near the tip), FP64
+    and mixed V-cycles, to a composite relative residual of 1e-10; beside it
+    the oracle's SuperLU solve of a small hierarchy of the same family (one
+    core)."""
+    import torch
+    import numpy as np
+    import workloads as W
+    from paper_1809_03745_amd import ebmg
+    from oracle.amr import Composite
+    dev = torch.device("cuda:0")
+    ctx = ebmg.Context(0)
+    amr = W.amr_pin_plane(n0, nlev)
+    out = {"workload": f"pin-plane {n0}^3 base, {nlev} levels (boxes x,y in [0.375,0.625], z in [0.5,1]; "
+                       f"x,y in [0.4375,0.5625], z in [0.5625,1])",
+           "level_cells": [int(np.prod(lv.prob.n)) for lv in amr.levels],
+           "uniform_equivalent_cells": int((n0 * 2 ** (nlev - 1)) ** 3)}
+    for name, prec in (("fp64", ebmg.FP64), ("mixed", ebmg.MIXED)):
+        t0 = time.perf_counter()
+        A = ebmg.Amr(ctx, amr, precision=prec)
+        setup = time.perf_counter() - t0
+        rho = [torch.tensor(lv.prob.rho.ravel(), dtype=torch.float64, device=dev) for lv in amr.levels]
+        phi = [torch.zeros(n, dtype=torch.float64, device=dev) for n in A.N]
+        phi2 = [torch.zeros(max(n, 1), dtype=torch.float64, device=dev) for n in A.N2]
+        A.solve(rho, phi, phi2=phi2, rtol=1e-10, max_iters=300)
+        best, info = None, None
+        for _ in range(reps):
+            for p in phi:
+                p.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, info = A.solve(rho, phi, phi2=phi2, rtol=1e-10, max_iters=300)
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        unknowns = int(sum(A.N) + sum(A.N2) - sum(A.covered))
+        out[name] = {"ms_per_solve": 1000 * best, "iterations": info["outer_iters"],
+                     "rel_residual": info["rel_residual"], "composite_unknowns": unknowns,
+                     "unknowns_per_s": unknowns / best, "setup_s": setup, "device_bytes": A.device_bytes}
+        A.release()
+    small = W.amr_pin_plane(32, 2, r_pin=0.05)
+    t0 = time.perf_counter()
+    C = Composite(small)
+    C.solve()
+    cpu_s = time.perf_counter() - t0
+    out["oracle_superlu_1core"] = {"sample": "pin-plane 32^3 base, 2 levels, pin radius 0.05 (assembly + SuperLU)",
+                                   "unknowns": int(C.A.shape[0]), "s": cpu_s}
+    return out
+
+
 def trace_summary(trace_csv, marker, out_md, title, command):
     """Reduce a rocprofv3 kernel-trace CSV to a markdown table of one solve:
     the kernels from the second-to-last dispatch whose name contains `marker`
@@ -688,6 +738,8 @@ def main():
                     help="COMMAND CSV...: reduce SQ counter passes of --pmc-probe to the committed instruction summary")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched workload (level-synchronous, mixed precision) and print its figures")
+    ap.add_argument("--amr-only", action="store_true",
+                    help="run only the composite AMR solves on the pin-plane gap and print their figures")
     ap.add_argument("--advection-only", action="store_true",
                     help="run only the advection steps on the pin-plane gap and print their figures")
     ap.add_argument("--trace-summary", nargs=5, metavar=("TRACE_CSV", "MARKER", "OUT_MD", "TITLE", "COMMAND"),
@@ -713,6 +765,9 @@ def main():
         return trace_summary(*args.trace_summary)
     if args.batched_only:
         print(json.dumps(batched(reps=max(1, args.steps), keys=("mixed",))))
+        return 0
+    if args.amr_only:
+        print(json.dumps(amr_bench()))
         return 0
     if args.advection_only:
         print(json.dumps(advection_bench(n=args.n, steps=max(1, args.steps))))
@@ -836,6 +891,7 @@ def main():
         out["family"] = family_bench()
         out["mesh_sdf"] = mesh_bench()
         out["advection"] = advection_bench()
+        out["amr"] = amr_bench()
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     if rank == 0:

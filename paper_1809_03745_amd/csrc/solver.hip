@@ -2553,13 +2553,16 @@ static void amr_apply(ebmg_amr_s* A, const double* x, double* y, hipStream_t s) 
   HIPCHECK(hipGetLastError());
 }
 
-// z = M r: the fine residual restricted onto the covered unknowns (finest
-// first), one V-cycle of level 0 over the whole domain, then per finer
-// level the coarse correction prolonged (piecewise constant), the level's
-// residual with the ghosts of that correction, and one V-cycle of the level
-// with homogeneous coarse-fine faces added; covered unknowns end at 0. A
-// fixed linear map (the V-cycles start from zero), so it serves as the
-// right preconditioner of BiCGStab.
+// z = M r: one V-cycle over the levels of the hierarchy. Down from the
+// finest box: a V-cycle of the level on its residual (homogeneous
+// coarse-fine faces), then the coarser level's residual updated by that
+// correction (the level's residual after it restricted onto the covered
+// unknowns, the refluxed rows next to the box reduced by its effect); one
+// V-cycle of level 0 over the domain; then up again: the coarse correction
+// prolonged (piecewise constant), the level's residual with the ghosts of
+// the coarse correction, and a second V-cycle of the level. Covered unknowns
+// end at 0. A fixed linear map (every V-cycle starts from zero), so it serves
+// as the right preconditioner of BiCGStab.
 static void amr_precond(ebmg_amr_s* A, const double* r, double* z, hipStream_t s) {
   const int L = (int)A->lev.size();
   const int64_t n = A->ntot;
@@ -2567,22 +2570,37 @@ static void amr_precond(ebmg_amr_s* A, const double* r, double* z, hipStream_t s
   double* y = A->y.p;
   double* e = A->e.p;
   hipLaunchKernelGGL(k_amr_lin, dim3(nblk(n)), dim3(256), 0, s, n, 1.0, r, 0.0, r, rt);
+  fill<double>(z, n, 0.0, s);
   for (int l = L - 1; l >= 1; --l) {
     auto& K = A->link[l];
+    const int64_t of = A->off[l], oc = A->off[l - 1], m = A->nd[l], mc = A->nd[l - 1];
+    precond(A->lev[l]->dev, A->lev[l]->host->opt, rt + of, z + of, s);
+    residual<double, 1>(A->lev[l]->dev.lv[0], z + of, nullptr, y + of, s);
+    if (K.nf)
+      hipLaunchKernelGGL(k_amr_rows, dim3(nblk(K.nf)), dim3(256), 0, s, K.nf, K.frow.p, K.fptr.p, K.fcol.p, K.fw.p,
+                         z + of, z + oc, y + of);
+    hipLaunchKernelGGL(k_amr_lin, dim3(nblk(m)), dim3(256), 0, s, m, 1.0, rt + of, -1.0, y + of, y + of);
     if (K.nr)
       hipLaunchKernelGGL(k_amr_gather, dim3(nblk(K.nr)), dim3(256), 0, s, K.nr, K.rrow.p, K.rptr.p, K.rcol.p, K.rw.p,
-                         rt + A->off[l], rt + A->off[l - 1]);
+                         y + of, rt + oc);
+    if (K.nc) {
+      fill<double>(y + oc, mc, 0.0, s);
+      hipLaunchKernelGGL(k_amr_rows, dim3(nblk(K.nc)), dim3(256), 0, s, K.nc, K.crow.p, K.cptr.p, K.ccol.p, K.cw.p,
+                         z + oc, z + of, y + oc);
+      hipLaunchKernelGGL(k_amr_lin, dim3(nblk(mc)), dim3(256), 0, s, mc, 1.0, rt + oc, -1.0, y + oc, rt + oc);
+    }
   }
   precond(A->lev[0]->dev, A->lev[0]->host->opt, rt + A->off[0], z + A->off[0], s);
   for (int l = 1; l < L; ++l) {
     auto& K = A->link[l];
     const int64_t of = A->off[l], oc = A->off[l - 1], m = A->nd[l];
-    hipLaunchKernelGGL(k_amr_prolong, dim3(nblk(m)), dim3(256), 0, s, m, K.pcol.p, z + oc, z + of);
+    hipLaunchKernelGGL(k_amr_prolong, dim3(nblk(m)), dim3(256), 0, s, m, K.pcol.p, z + oc, e + of);
+    hipLaunchKernelGGL(k_amr_lin, dim3(nblk(m)), dim3(256), 0, s, m, 1.0, z + of, 1.0, e + of, z + of);
     residual<double, 1>(A->lev[l]->dev.lv[0], z + of, nullptr, y + of, s);
     if (K.nf)
       hipLaunchKernelGGL(k_amr_rows, dim3(nblk(K.nf)), dim3(256), 0, s, K.nf, K.frow.p, K.fptr.p, K.fcol.p, K.fw.p,
                          z + of, z + oc, y + of);
-    hipLaunchKernelGGL(k_amr_lin, dim3(nblk(m)), dim3(256), 0, s, m, 1.0, r + of, -1.0, y + of, y + of);
+    hipLaunchKernelGGL(k_amr_lin, dim3(nblk(m)), dim3(256), 0, s, m, 1.0, rt + of, -1.0, y + of, y + of);
     precond(A->lev[l]->dev, A->lev[l]->host->opt, y + of, e + of, s);
     hipLaunchKernelGGL(k_amr_lin, dim3(nblk(m)), dim3(256), 0, s, m, 1.0, z + of, 1.0, e + of, z + of);
   }

@@ -371,6 +371,17 @@ def batched(nbox=512, reps=3, keys=("mixed", "fp64", "persistent_mixed", "persis
         if mode == ebmg.BATCH_LEVELSYNC:
             out[key]["coarse_part_cells"] = tune["tail_cells"]
             out[key]["grid_wide_levels"] = tune["wide_levels"]
+            # finest-level kernels over all boxes, back to back (HIP events
+            # on the library's stream)
+            for which, name in ((1, "explicit_rows_jacobi"), (0, "template_half_sweeps")):
+                ms, by = B.time_level0(which, reps=20)
+                out[key][name] = {"ms": ms, "alg_bytes": by, "GBps": by / (ms * 1e-3) / 1e9,
+                                  "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            rows = out[key]["explicit_rows_jacobi"]
+            out[key]["roofline"] = {"bound": "hbm", "kernel": "kw_irr_jac (finest-level explicit rows, both groups)",
+                                    "achieved": round(rows["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": round(rows["frac"], 4), "traffic": None,
+                                    "timed": "20 back-to-back applications after the solves"}
         B.release()
         del phi2
     return out

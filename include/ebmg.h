@@ -557,6 +557,17 @@ ebmg_status ebmg_release_family(ebmg_family fam);
 ebmg_status ebmg_advect(ebmg_problem pb, const double* n_in, const double* u_x, const double* u_y,
                         const double* u_z, double dt, const double* inflow, double* n_out);
 
+/* Measurement hook (no paper passage): mean device time of `reps`
+ * back-to-back applications, after one untimed one, of the batch's
+ * finest-level kernels over every box as a V-cycle runs them: which 0 the
+ * template red and black half-sweeps, 1 the explicit-row Jacobi passes of
+ * both colour groups. alg_bytes (HOST, may be NULL): their algorithmic bytes
+ * per application (template: three values and a tag byte per cell; rows:
+ * per stored entry a column index and a value, per row its unknown index,
+ * b, diagonal and result). Level-synchronous batches only (else ERR_ARG);
+ * overwrites the batch's cycle vectors. */
+ebmg_status ebmg_time_batch_kernel(ebmg_batch bt, int32_t which, int32_t reps, double* avg_ms, double* alg_bytes);
+
 /* Composite solves on nested AMR hierarchies. Paper: Numerical methods
  * (patch-based refinement: levels of rectangular boxes, each inside the
  * coarser level) and Helmholtz equations (coarse-fine faces: the coarse

@@ -2189,6 +2189,24 @@ static void wide_vcycle(ebmg_batch_s* Bt, int which, hipStream_t s) {
   }
 }
 
+// The finest level's template half-sweeps (which 0) or explicit-row Jacobi
+// passes (which 1) of every box, both colours, as inside a V-cycle (for the
+// measurement hook).
+template <typename T, int DIM>
+static void wide_level0_kernels(ebmg_batch_s* Bt, int which, hipStream_t s) {
+  auto& L = Bt->wide[0];
+  const WState* st = (const WState*)Bt->state.p;
+  const BLev<T>* W = (const BLev<T>*)Bt->wl0[0].p;
+  for (int colour = 0; colour < 2; ++colour) {
+    if (which == 0)
+      hipLaunchKernelGGL((kw_rb<T, DIM>), dim3(L.rb.n), dim3(kWB), 0, s, W, (const WEnt*)L.rb.d.p, st, colour);
+    else if (L.jac[colour].n)
+      hipLaunchKernelGGL((kw_irr_jac<T>), dim3(L.jac[colour].n), dim3(kWB), 0, s, W, (const WEnt*)L.jac[colour].d.p,
+                         st, colour);
+  }
+  HIPCHECK(hipGetLastError());
+}
+
 template <typename T, int OP>
 static void wide_vec(ebmg_batch_s* Bt, int filt, hipStream_t s) {
   hipLaunchKernelGGL((kw_vec<T, OP>), dim3(Bt->vec.n), dim3(kWB), 0, s, (const BBox<T>*)Bt->bbox.p,
@@ -3995,6 +4013,49 @@ ebmg_status ebmg_advect(ebmg_problem pb, const double* n_in, const double* u_x, 
                          A.sp_donor.p, dt, n_in, A.Dc.p, A.Dcut.p, A.give.p, n_out);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(s));
+    return EBMG_OK;
+  });
+}
+
+ebmg_status ebmg_time_batch_kernel(ebmg_batch bt, int32_t which, int32_t reps, double* avg_ms, double* alg_bytes) {
+  if (!bt || which < 0 || which > 1 || reps < 1) return EBMG_ERR_ARG;
+  return guard(bt->ctx, [&]() -> ebmg_status {
+    if (bt->mode != 2 || bt->wide.empty())
+      throw ArgError("the finest-level timing needs the level-synchronous batch mode");
+    HIPCHECK(hipSetDevice(bt->ctx->device));
+    hipStream_t s = bt->ctx->stream;
+    const int nbox = (int)bt->boxes.size();
+    // every box active, as at the start of a solve; the cycle vectors hold
+    // the last solve's values and are overwritten by the next one
+    std::vector<WState> st = initial_state(bt);
+    HIPCHECK(hipMemcpyAsync(bt->state.p, st.data(), sizeof(WState) * nbox, hipMemcpyHostToDevice, s));
+    auto run = [&]() {
+      if (bt->mixed) {
+        if (bt->dim == 3) wide_level0_kernels<float, 3>(bt, which, s); else wide_level0_kernels<float, 2>(bt, which, s);
+      } else {
+        if (bt->dim == 3) wide_level0_kernels<double, 3>(bt, which, s); else wide_level0_kernels<double, 2>(bt, which, s);
+      }
+    };
+    run();
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    HIPCHECK(hipEventRecord(e0, s));
+    for (int k = 0; k < reps; ++k) run();
+    HIPCHECK(hipEventRecord(e1, s));
+    HIPCHECK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const int vsz = bt->mixed ? 4 : 8;
+    double by = 0;
+    for (auto& P : bt->boxes) {
+      const DevLevel& l = P->dev.lv[0];
+      by += which == 0 ? (double)l.N * (3.0 * vsz + 1.0) : rows_bytes(l, vsz);
+    }
+    if (avg_ms) *avg_ms = ms / reps;
+    if (alg_bytes) *alg_bytes = by;
     return EBMG_OK;
   });
 }

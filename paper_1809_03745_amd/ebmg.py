@@ -133,6 +133,7 @@ _sig("ebmg_solve_family", C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.c_dou
                                     C.POINTER(_vp), C.POINTER(SolveInfo), C.POINTER(C.c_int)])
 _sig("ebmg_release_family", C.c_int, [_vp])
 _sig("ebmg_advect", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, _vp, _vp])
+_sig("ebmg_time_batch_kernel", C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp])
 _sig("ebmg_setup_amr", C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_query_amr", C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp])
 _sig("ebmg_solve_amr", C.c_int, [_vp, _vp, C.c_double, C.c_int32, _vp, _vp, _vp])
@@ -151,7 +152,7 @@ EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_des
             "ebmg_set_coefficients", "ebmg_smooth", "ebmg_kernel_timing",
             "ebmg_setup_family", "ebmg_query_family", "ebmg_solve_family", "ebmg_release_family",
             "ebmg_mesh_create", "ebmg_mesh_query", "ebmg_mesh_sdf", "ebmg_mesh_release", "ebmg_advect",
-            "ebmg_setup_amr", "ebmg_query_amr", "ebmg_solve_amr", "ebmg_apply_amr", "ebmg_release_amr"]
+            "ebmg_time_batch_kernel", "ebmg_setup_amr", "ebmg_query_amr", "ebmg_solve_amr", "ebmg_apply_amr", "ebmg_release_amr"]
 
 
 def abi_version():
@@ -574,6 +575,14 @@ class Batch:
             ni, n2i = C.c_int64(), C.c_int64()
             ctx.check(_lib.ebmg_query_batch_box(h, i, C.byref(ni), C.byref(n2i)), "ebmg_query_batch_box")
             self.sizes.append((ni.value, n2i.value))
+
+    def time_level0(self, which, reps=20):
+        """(mean ms, algorithmic bytes) of the finest-level template sweeps
+        (which 0) or explicit-row Jacobi passes (1) over every box."""
+        ms, by = C.c_double(), C.c_double()
+        self.ctx.check(_lib.ebmg_time_batch_kernel(self.h, int(which), int(reps), C.byref(ms), C.byref(by)),
+                       "ebmg_time_batch_kernel")
+        return ms.value, by.value
 
     def tuning(self):
         """Setup choices: dict(mode, tail_cells, wide_levels, candidates=[(cells, V-cycle ms)])."""

@@ -235,3 +235,27 @@ def test_batch_edge_cases(ctx, mode, prec):
         assert err <= (1e-10 if prec == 0 else 1e-8)
     assert infos[0]["levels"] == 1
     B.release()
+
+
+def test_batch_level0_timing_hook_leaves_solves_unchanged(ctx):
+    """The finest-level timing hook runs the batch's template sweeps and
+    explicit-row passes on its cycle vectors; a solve after it gives the
+    same result, bitwise, as the one before, and the persistent mode refuses
+    the hook."""
+    B = ebmg.Batch(ctx, BOXES, precision=1)
+    st, infos, xs, x2s = _batch_solve(B, BOXES, 1e-10)
+    assert st == ebmg.OK
+    for which in (0, 1):
+        ms, by = B.time_level0(which, reps=3)
+        _say("   level-0 kernels", which, "ms", ms, "bytes", by)
+        assert ms > 0 and by > 0
+    st2, infos2, xs2, x2s2 = _batch_solve(B, BOXES, 1e-10)
+    assert st2 == ebmg.OK
+    for a, b in zip(xs, xs2):
+        assert np.array_equal(a, b)
+    B.release()
+    P = ebmg.Batch(ctx, BOXES[:2], batch=ebmg.BATCH_PERSISTENT)
+    with pytest.raises(ebmg.EbmgError) as e:
+        P.time_level0(0)
+    assert e.value.status == ebmg.ERR_ARG
+    P.release()

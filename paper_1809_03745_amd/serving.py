@@ -21,10 +21,19 @@ empty device is rejected. Admission is first-fit over the queue in arrival
 order, except that a request waiting longer than ``max_bypass_s`` blocks all
 later ones (no starvation of large requests).
 
+Coalescing: small Poisson requests (3D grids up to 64^3, 2D up to 512^2)
+of one key are served by a resident batch of ``coalesce`` copies of the
+box; when one is admitted, up to ``coalesce - 1`` more queued requests of
+the key join it and the group is solved by one batched solve (one
+level-synchronous launch sequence over the boxes, unused boxes with a zero
+source). A small request alone is solved the same way, as a group of one.
+
 Results do not depend on the mix: every hierarchy is set up with fixed
 smoother and coarse-tail choices (no timing-based autotuning, which would
-depend on what else runs), all reductions are deterministic, and a request's
-work touches only its own hierarchy and vectors.
+depend on what else runs), a batched box's result is bitwise the same
+whatever the other boxes hold, all reductions are deterministic, and a
+request's work touches only its own hierarchy and vectors (or its own box
+of a batch).
 
 The scheduler (``Scheduler``) is plain Python with no device calls, so its
 policy is testable on the CPU; ``Server`` executes admitted requests.
@@ -52,6 +61,7 @@ class Request:
     make_rho: Callable[[Any], Any]
     coeffs: Any = None
     coeff_sig: Any = None
+    group_key: Any = None       # requests of one group key may share a batched solve
     dim: int = 3
     arrival: float = 0.0
     want_phi: bool = True
@@ -67,6 +77,7 @@ class Request:
     setup_s: float = 0.0
     rejected: bool = False
     error: str = ""
+    members: Any = None         # the group a coalesced request leads (itself first)
     done: threading.Event = dataclasses.field(default_factory=threading.Event)
 
     def vec_bytes(self):
@@ -88,9 +99,11 @@ class Entry:
 class Scheduler:
     """Admission and residency bookkeeping (no device calls)."""
 
-    def __init__(self, budget_bytes, slots, bytes_per_cell=160, max_bypass_s=0.5, clock=time.perf_counter):
+    def __init__(self, budget_bytes, slots, bytes_per_cell=160, max_bypass_s=0.5, clock=time.perf_counter,
+                 coalesce=1):
         self.budget = int(budget_bytes)
         self.slots = int(slots)
+        self.coalesce = max(1, int(coalesce))
         self.bytes_per_cell = bytes_per_cell
         self.max_bypass_s = max_bypass_s
         self.clock = clock
@@ -108,7 +121,8 @@ class Scheduler:
         return self.vec_reserved + self.releasing + sum(e.bytes for e in self.entries)
 
     def hier_estimate(self, req):
-        return self.measured.get(req.key, self.bytes_per_cell * req.cells)
+        boxes = self.coalesce if req.group_key is not None else 1
+        return self.measured.get(req.key, self.bytes_per_cell * req.cells * boxes)
 
     def offer(self, req):
         """Queue a request, or reject it when it cannot fit an empty device."""
@@ -168,14 +182,37 @@ class Scheduler:
                 use.busy = True
                 self.running += 1
                 self.vec_reserved += req.vec_bytes()
+                req.t_admit = now
+                req.members = [req]
+                if req.group_key is not None and self.coalesce > 1:
+                    self._gather(req, now)
                 # the admitting worker frees its evictions before it sets up
                 # the new hierarchy, so they do not add to the peak
                 self.high_water = max(self.high_water, self.reserved() - self.releasing)
-                req.t_admit = now
                 return req, use, evict
             if now - req.arrival > self.max_bypass_s and i == 0:
                 return None     # the head has waited too long: nothing may pass it
         return None
+
+    def _gather(self, req, now):
+        """Queued requests of the admitted one's group join it (queue order,
+        up to the batch's size, while their vectors fit)."""
+        free = self.budget - self.reserved()
+        for other in list(self.queue):
+            if len(req.members) >= self.coalesce:
+                break
+            if other.group_key != req.group_key or other.vec_bytes() > free:
+                continue
+            self.queue.remove(other)
+            self.vec_reserved += other.vec_bytes()
+            free -= other.vec_bytes()
+            other.t_admit = now
+            other.hit = req.hit
+            other.members = None
+            req.members.append(other)
+        if len(req.members) > 1:
+            self.stats["coalesced_groups"] += 1
+            self.stats["coalesced_requests"] += len(req.members)
 
     def reset_stats(self):
         self.stats.clear()
@@ -186,7 +223,10 @@ class Scheduler:
         entry.bytes = int(actual_bytes)
         entry.ready = True
         self.measured[entry.key] = int(actual_bytes)
-        self.high_water = max(self.high_water, self.reserved())
+        # evictions still being freed by other workers are covered by the
+        # reservations that replace them (a worker frees its evictions before
+        # it allocates), so they are not counted twice
+        self.high_water = max(self.high_water, self.reserved() - self.releasing)
 
     def released(self, entry):
         """An evicted hierarchy's device memory has been freed."""
@@ -197,18 +237,22 @@ class Scheduler:
             self.entries.remove(entry)
 
     def finish(self, req, entry):
-        entry.busy = False
-        entry.last_used = self.clock()
+        """The admitted request (and the group it leads) is done."""
+        group = req.members or [req]
+        if entry in self.entries:
+            entry.busy = False
+            entry.last_used = self.clock()
         self.running -= 1
-        self.vec_reserved -= req.vec_bytes()
-        self.stats["completed"] += 1
+        for m in group:
+            self.vec_reserved -= m.vec_bytes()
+        self.stats["completed"] += len(group)
 
 
 class Server:
     """Executes requests on one GPU with ``slots`` worker threads."""
 
     def __init__(self, device=0, slots=4, budget_bytes=None, precision=None, rtol=1e-10, max_cycles=400,
-                 bytes_per_cell=160):
+                 bytes_per_cell=160, coalesce=8):
         import torch
         from . import ebmg
         self.torch = torch
@@ -221,7 +265,8 @@ class Server:
         self.precision = ebmg.MIXED if precision is None else precision
         self.rtol = rtol
         self.max_cycles = max_cycles
-        self.sched = Scheduler(budget_bytes, slots, bytes_per_cell=bytes_per_cell)
+        self.sched = Scheduler(budget_bytes, slots, bytes_per_cell=bytes_per_cell, coalesce=coalesce)
+        self.coalesce = max(1, int(coalesce))
         self.cv = threading.Condition()
         self.closed = False
         self.records = []
@@ -256,7 +301,7 @@ class Server:
     def _release(self, e):
         h = e.handle
         if h is not None:
-            h["problem"].release()
+            (h.get("problem") or h.get("batch")).release()
             h["ctx"].close()
             e.handle = None
 
@@ -267,6 +312,13 @@ class Server:
         try:
             prob = req.make_problem()
             t0 = time.perf_counter()
+            if req.group_key is not None and self.coalesce > 1:
+                # a batch of copies of the box (its results do not depend on
+                # what the other boxes hold or on its coarse-part choice)
+                B = ebmg.Batch(ctx, [prob] * self.coalesce, precision=self.precision, batch=ebmg.BATCH_LEVELSYNC)
+                req.setup_s = time.perf_counter() - t0
+                entry.handle = {"batch": B, "ctx": ctx, "stream": stream}
+                return B.device_bytes
             # fixed kernel choices (no timing: a result is the same alone and
             # in any mix) and direct launches (a Helmholtz request
             # re-coefficients the hierarchy, which would drop a captured
@@ -279,6 +331,29 @@ class Server:
         entry.handle = {"problem": P, "ctx": ctx, "stream": stream}
         entry.coeff_sig = req.coeff_sig
         return P.device_bytes
+
+    def _run_group(self, req, entry):
+        torch = self.torch
+        h = entry.handle
+        B, stream = h["batch"], h["stream"]
+        group = req.members or [req]
+        n, n2 = B.sizes[0]
+        with torch.cuda.stream(stream):
+            rho = [m.make_rho(self.dev) for m in group]
+            rho += [torch.zeros(n, dtype=torch.float64, device=self.dev) for _ in range(self.coalesce - len(group))]
+            phi = [torch.zeros(n, dtype=torch.float64, device=self.dev) for _ in range(self.coalesce)]
+            phi2 = [torch.zeros(max(1, n2), dtype=torch.float64, device=self.dev) for _ in range(self.coalesce)]
+        t = time.perf_counter()
+        for m in group:
+            m.t_start = t
+        st, infos = B.solve(rho, phi, phi2=phi2, rtol=self.rtol, max_cycles=self.max_cycles, check=False)
+        for i, m in enumerate(group):
+            ok = st == self.ebmg.OK or infos[i]["rel_residual"] <= self.rtol
+            m.status, m.info = (self.ebmg.OK if ok else st), infos[i]
+            if m.want_phi:
+                m.phi = phi[i]
+                m.phi2 = phi2[i][:n2] if n2 else None
+        del rho
 
     def _run(self, req, entry):
         torch = self.torch
@@ -320,28 +395,32 @@ class Server:
                     with self.cv:
                         self.sched.released(e)
                         self.cv.notify_all()
+            group = req.members or [req]
             try:
                 if entry.handle is None:
                     nbytes = self._setup(req, entry)
                     with self.cv:
                         self.sched.set_up(entry, nbytes)
-                self._run(req, entry)
+                if "batch" in entry.handle:
+                    self._run_group(req, entry)
+                else:
+                    self._run(req, entry)
             except Exception as exc:  # a failed request must not stop the server
-                req.status = -2
-                req.error = repr(exc)
+                for m in group:
+                    m.status = -2
+                    m.error = repr(exc)
                 if entry.handle is None:
                     with self.cv:
                         self.sched.failed_setup(entry)
-            req.t_end = time.perf_counter()
+            t_end = time.perf_counter()
             with self.cv:
-                if entry in self.sched.entries:
-                    self.sched.finish(req, entry)
-                else:
-                    self.sched.running -= 1
-                    self.sched.vec_reserved -= req.vec_bytes()
-                self.records.append(req)
+                self.sched.finish(req, entry)
+                for m in group:
+                    m.t_end = t_end
+                    self.records.append(m)
                 self.cv.notify_all()
-            req.done.set()
+            for m in group:
+                m.done.set()
 
     # -- reporting ------------------------------------------------------------
     def summary(self, t0, t1):
@@ -359,6 +438,7 @@ class Server:
                 "solves_per_s": len(done) / max(t1 - t0, 1e-9),
                 "latency_ms": {"p50": pct(50), "p99": pct(99)},
                 "hierarchy_hits": st["hits"], "hierarchy_misses": st["misses"], "evicted": st["evicted"],
+                "coalesced_groups": st["coalesced_groups"], "coalesced_requests": st["coalesced_requests"],
                 "footprint_high_water_bytes": self.sched.high_water, "budget_bytes": self.sched.budget}
 
 
@@ -380,8 +460,9 @@ def request_from_spec(rid, spec, arrival=0.0, torch_module=None):
 
     if spec["op"] == "poisson":
         key = ("poisson", dim, n)
+        small = (dim == 3 and n <= 64) or (dim == 2 and n <= 512)
         return Request(rid, key, cells, make_problem=lambda: W.make_request(dict(spec, seed=0)),
-                       make_rho=make_rho, dim=dim, arrival=arrival)
+                       make_rho=make_rho, dim=dim, arrival=arrival, group_key=key if small else None)
     kappa = spec["kappa"]
     key = ("helmholtz", dim, n)
     coeffs = W.eddington_coefficients(dim, n, kappa)

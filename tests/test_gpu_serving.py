@@ -125,3 +125,21 @@ def test_admission_within_budget():
     r = srv.submit(serving.request_from_spec(0, SPECS[7]))
     assert r.done.wait(10) and r.rejected
     srv.close()
+
+
+def test_small_poisson_requests_are_coalesced():
+    """Six small 3D Poisson requests of one grid arriving together are solved
+    in batched groups (one batched solve per group), each result bitwise
+    equal to the same request served alone."""
+    _say("serving: coalescing")
+    specs = [dict(dim=3, n=32, op="poisson", kappa=1.0, seed=100 + i) for i in range(6)]
+    alone = []
+    for sp in specs:
+        phi, _, _ = _serve([sp], slots=1)
+        alone.append(phi[0])
+    phis, reqs, summ = _serve(specs, slots=1)
+    _say("   summary", summ)
+    assert summ["completed"] == len(specs)
+    assert summ["coalesced_groups"] >= 1 and summ["coalesced_requests"] >= 2
+    for a, b in zip(alone, phis):
+        assert np.array_equal(a, b)

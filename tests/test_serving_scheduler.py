@@ -127,3 +127,54 @@ def test_evicted_bytes_stay_reserved_until_released():
     s.released(e)
     assert s.releasing == 0
     assert s.reserved() == 1000 + vec
+
+
+def _greq(rid, key, cells, arrival=0.0):
+    return Request(rid, key, cells, make_problem=None, make_rho=None, arrival=arrival, group_key=key)
+
+
+def test_coalesces_queued_requests_of_one_group():
+    """An admitted small request takes queued requests of its group along (in
+    queue order, up to the batch size); others stay queued; finishing the
+    group frees every member's vectors."""
+    s = Scheduler(budget_bytes=1 << 24, slots=2, bytes_per_cell=10, coalesce=3)
+    g = [_greq(i, "g", 100) for i in range(4)]
+    other = _req(9, "h", 100)
+    s.offer(g[0])
+    s.offer(other)
+    for r in g[1:]:
+        s.offer(r)
+    req, e, _ = _admit(s)
+    assert req is g[0] and req.members == [g[0], g[1], g[2]]
+    assert s.vec_reserved == sum(m.vec_bytes() for m in req.members)
+    assert list(s.queue) == [other, g[3]]
+    assert s.stats["coalesced_groups"] == 1 and s.stats["coalesced_requests"] == 3
+    # the group's batch is busy: the fourth waits, the other key runs
+    req2, e2, _ = _admit(s)
+    assert req2 is other and req2.members == [other]
+    assert s.next_admissible() is None
+    s.set_up(e, 5000)
+    s.finish(req, e)
+    assert s.vec_reserved == other.vec_bytes()
+    assert s.stats["completed"] == 3
+    req3, e3, _ = _admit(s)
+    assert req3 is g[3] and e3 is e and req3.members == [g[3]]
+
+
+def test_coalesced_vectors_must_fit_the_budget():
+    s = Scheduler(budget_bytes=200_000, slots=1, bytes_per_cell=10, coalesce=8)
+    g = [_greq(i, "g", 2000) for i in range(8)]
+    for r in g:
+        s.offer(r)
+    req, e, _ = _admit(s)
+    # hierarchy estimate 10 B x 2000 cells x 8 boxes, then 16.5 KB per member
+    assert len(req.members) >= 1
+    assert s.reserved() <= s.budget
+    assert len(req.members) + len(s.queue) == 8
+    assert len(s.queue) > 0
+
+
+def test_group_estimate_counts_every_box():
+    s = Scheduler(budget_bytes=1 << 30, slots=1, bytes_per_cell=10, coalesce=4)
+    assert s.hier_estimate(_greq(0, "g", 100)) == 4 * 10 * 100
+    assert s.hier_estimate(_req(1, "h", 100)) == 10 * 100

@@ -433,8 +433,13 @@ class Server:
             return lat[min(len(lat) - 1, int(round(q / 100.0 * (len(lat) - 1))))]
 
         st = self.sched.stats
+        bad = [r for r in self.records if not r.rejected and r.status != self.ebmg.OK]
         return {"completed": len(done), "rejected": st["rejected"],
-                "failed": sum(1 for r in self.records if not r.rejected and r.status != self.ebmg.OK),
+                "failed": len(bad),
+                "failed_detail": [{"key": list(r.key), "status": r.status,
+                                   "rel_residual": (r.info or {}).get("rel_residual"),
+                                   "cycles": (r.info or {}).get("cycles"), "error": r.error[:200]}
+                                  for r in bad[:10]],
                 "solves_per_s": len(done) / max(t1 - t0, 1e-9),
                 "latency_ms": {"p50": pct(50), "p99": pct(99)},
                 "hierarchy_hits": st["hits"], "hierarchy_misses": st["misses"], "evicted": st["evicted"],

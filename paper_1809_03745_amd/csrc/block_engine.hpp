@@ -335,16 +335,17 @@ __device__ void be_resid_cells_part(const BLev<T>& L, const TX* __restrict__ x, 
       if (p == 3) {
         o = MODE == 0 ? T(0) : v[u][6];
       } else {
-        T s = 0, dg = tp.D0(p);
-        if (ii[u] > 0) s += v[u][0]; else dg += tp.CB(0, p);
-        if (ii[u] < nx - 1) s += v[u][1]; else dg += tp.CB(1, p);
-        if (jj[u] > 0) s += v[u][2]; else dg += tp.CB(2, p);
-        if (jj[u] < ny - 1) s += v[u][3]; else dg += tp.CB(3, p);
+        const T xv = v[u][6];
+        T s = 0, dg = tp.M(p);
+        if (ii[u] > 0) s += v[u][0] - xv; else dg += tp.CBM(0, p);
+        if (ii[u] < nx - 1) s += v[u][1] - xv; else dg += tp.CBM(1, p);
+        if (jj[u] > 0) s += v[u][2] - xv; else dg += tp.CBM(2, p);
+        if (jj[u] < ny - 1) s += v[u][3] - xv; else dg += tp.CBM(3, p);
         if (DIM == 3) {
-          if (kk[u] > 0) s += v[u][4]; else dg += tp.CB(4, p);
-          if (kk[u] < nz - 1) s += v[u][5]; else dg += tp.CB(5, p);
+          if (kk[u] > 0) s += v[u][4] - xv; else dg += tp.CBM(4, p);
+          if (kk[u] < nz - 1) s += v[u][5] - xv; else dg += tp.CBM(5, p);
         }
-        const T ax = dg * v[u][6] + tp.CO(p) * s;
+        const T ax = dg * xv + tp.CO(p) * s;
         o = MODE == 0 ? bv[u] - ax : ax;
       }
       r[cc[u]] = o;

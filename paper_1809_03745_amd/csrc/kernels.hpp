@@ -22,6 +22,13 @@ struct Tmpl {
   T coff[2];
   T d0[2];
   T cb[6][2];
+  // the residual's difference form: A x_i = (mass + sum over touched domain
+  // faces of cbm) x_i + coff * sum over neighbours of (x_j - x_i), with
+  // cbm = cb - coff; the same operator, without the cancellation of the
+  // large diagonal against the neighbour sum that limits the attainable
+  // relative residual on fine grids
+  T mass[2];
+  T cbm[6][2];
   int n[3];
   // phase-selected constants: a select between the two values keeps them in
   // registers (indexing by a runtime phase would read the argument block
@@ -29,6 +36,8 @@ struct Tmpl {
   __device__ __forceinline__ T CO(int p) const { return p ? coff[1] : coff[0]; }
   __device__ __forceinline__ T D0(int p) const { return p ? d0[1] : d0[0]; }
   __device__ __forceinline__ T CB(int f, int p) const { return p ? cb[f][1] : cb[f][0]; }
+  __device__ __forceinline__ T M(int p) const { return p ? mass[1] : mass[0]; }
+  __device__ __forceinline__ T CBM(int f, int p) const { return p ? cbm[f][1] : cbm[f][0]; }
 };
 
 constexpr int kBlock = 256;
@@ -891,9 +900,19 @@ __global__ void __launch_bounds__(kBlock) k_resid_reg(const uint8_t* __restrict_
     return;
   }
   if (p == 2) return;
-  T dg;
-  const T off = template_apply<T, DIM>(x, tp, i, j, k, c, p, dg);
-  const T ax = dg * x[c] + off;
+  const int nx = tp.n[0], ny = tp.n[1];
+  const int64_t sxy = (int64_t)nx * ny;
+  const T xv = x[c];
+  T s = 0, dg = tp.M(p);
+  if (i > 0) s += x[c - 1] - xv; else dg += tp.CBM(0, p);
+  if (i < nx - 1) s += x[c + 1] - xv; else dg += tp.CBM(1, p);
+  if (j > 0) s += x[c - nx] - xv; else dg += tp.CBM(2, p);
+  if (j < ny - 1) s += x[c + nx] - xv; else dg += tp.CBM(3, p);
+  if (DIM == 3) {
+    if (k > 0) s += x[c - sxy] - xv; else dg += tp.CBM(4, p);
+    if (k < tp.n[2] - 1) s += x[c + sxy] - xv; else dg += tp.CBM(5, p);
+  }
+  const T ax = dg * xv + tp.CO(p) * s;
   r[c] = MODE == 0 ? b[c] - ax : ax;
 }
 
@@ -945,7 +964,7 @@ __global__ void __launch_bounds__(kRZX * kRZY) k_resid_zm3(const uint8_t* __rest
   const int tid = threadIdx.x + kRZX * threadIdx.y;
   if (tid < 16) {
     const int p = tid >> 3, j = tid & 7;
-    TC[p][j] = j == 0 ? tp.coff[p] : (j == 1 ? tp.d0[p] : tp.cb[j - 2][p]);
+    TC[p][j] = j == 0 ? tp.coff[p] : (j == 1 ? tp.mass[p] : tp.cbm[j - 2][p]);
   }
   __syncthreads();
   const int nx = tp.n[0], ny = tp.n[1], nz = tp.n[2];
@@ -992,12 +1011,12 @@ __global__ void __launch_bounds__(kRZX * kRZY) k_resid_zm3(const uint8_t* __rest
         } else {
           const T* tc = TC[p];
           T s = 0, dg = tc[1];
-          if (i > 0) s += w; else dg += tc[2];
-          if (i < nx - 1) s += e; else dg += tc[3];
-          if (j > 0) s += so; else dg += tc[4];
-          if (j < ny - 1) s += no; else dg += tc[5];
-          if (k > 0) s += xm; else dg += tc[6];
-          if (k < nz - 1) s += xp; else dg += tc[7];
+          if (i > 0) s += w - xc; else dg += tc[2];
+          if (i < nx - 1) s += e - xc; else dg += tc[3];
+          if (j > 0) s += so - xc; else dg += tc[4];
+          if (j < ny - 1) s += no - xc; else dg += tc[5];
+          if (k > 0) s += xm - xc; else dg += tc[6];
+          if (k < nz - 1) s += xp - xc; else dg += tc[7];
           const T ax = dg * xc + tc[0] * s;
           out = MODE == 0 ? bb - ax : ax;
         }
@@ -1047,7 +1066,7 @@ __global__ void __launch_bounds__(64 * kRRW) k_resid_restrict3(const uint8_t* __
   const int tid = threadIdx.x + 64 * threadIdx.y;
   if (tid < 16) {
     const int p = tid >> 3, j = tid & 7;
-    TC[p][j] = j == 0 ? tp.coff[p] : (j == 1 ? tp.d0[p] : tp.cb[j - 2][p]);
+    TC[p][j] = j == 0 ? tp.coff[p] : (j == 1 ? tp.mass[p] : tp.cbm[j - 2][p]);
   }
   __syncthreads();
   const int nx = tp.n[0], ny = tp.n[1], nz = tp.n[2];
@@ -1095,12 +1114,12 @@ __global__ void __launch_bounds__(64 * kRRW) k_resid_restrict3(const uint8_t* __
     } else {
       const T* tc = TC[p];
       T s = 0, dg = tc[1];
-      if (ic > 0) s += w; else dg += tc[2];
-      if (ic < nx - 1) s += e; else dg += tc[3];
-      if (jc > 0) s += so; else dg += tc[4];
-      if (jc < ny - 1) s += no; else dg += tc[5];
-      if (k > 0) s += xm; else dg += tc[6];
-      if (k < nz - 1) s += xp; else dg += tc[7];
+      if (ic > 0) s += w - xc; else dg += tc[2];
+      if (ic < nx - 1) s += e - xc; else dg += tc[3];
+      if (jc > 0) s += so - xc; else dg += tc[4];
+      if (jc < ny - 1) s += no - xc; else dg += tc[5];
+      if (k > 0) s += xm - xc; else dg += tc[6];
+      if (k < nz - 1) s += xp - xc; else dg += tc[7];
       const T ax = dg * xc + tc[0] * s;
       out = bb - ax;
     }
@@ -1155,7 +1174,7 @@ __global__ void __launch_bounds__(64 * kRPY) k_resid_zp3(const uint8_t* __restri
   const int tid = threadIdx.x + 64 * threadIdx.y;
   if (tid < 16) {
     const int p = tid >> 3, j = tid & 7;
-    TC[p][j] = j == 0 ? tp.coff[p] : (j == 1 ? tp.d0[p] : tp.cb[j - 2][p]);
+    TC[p][j] = j == 0 ? tp.coff[p] : (j == 1 ? tp.mass[p] : tp.cbm[j - 2][p]);
   }
   __syncthreads();
   const int nx = tp.n[0], ny = tp.n[1], nz = tp.n[2];
@@ -1204,12 +1223,12 @@ __global__ void __launch_bounds__(64 * kRPY) k_resid_zp3(const uint8_t* __restri
           const T wv = (T)(u ? xc.x : w), ev = (T)(u ? e : xc.y);
           const T* tc = TC[p & 1];
           T s = 0, dg = tc[1];
-          if (i + u > 0) s += wv; else dg += tc[2];
-          if (i + u < nx - 1) s += ev; else dg += tc[3];
-          if (j > 0) s += (T)(u ? so.y : so.x); else dg += tc[4];
-          if (j < ny - 1) s += (T)(u ? no.y : no.x); else dg += tc[5];
-          if (k > 0) s += (T)(u ? xm.y : xm.x); else dg += tc[6];
-          if (k < nz - 1) s += (T)(u ? xp.y : xp.x); else dg += tc[7];
+          if (i + u > 0) s += wv - xv; else dg += tc[2];
+          if (i + u < nx - 1) s += ev - xv; else dg += tc[3];
+          if (j > 0) s += (T)(u ? so.y : so.x) - xv; else dg += tc[4];
+          if (j < ny - 1) s += (T)(u ? no.y : no.x) - xv; else dg += tc[5];
+          if (k > 0) s += (T)(u ? xm.y : xm.x) - xv; else dg += tc[6];
+          if (k < nz - 1) s += (T)(u ? xp.y : xp.x) - xv; else dg += tc[7];
           const T ax = dg * xv + tc[0] * s;
           out[u] = MODE == 0 ? (u ? bb.y : bb.x) - ax : ax;
         }
@@ -1427,18 +1446,19 @@ __global__ void __launch_bounds__(kBlock) k_resid_all(const uint8_t* __restrict_
           const int64_t jk = c / nx;
           const int j = (int)(jk % ny);
           const int k = DIM == 3 ? (int)(jk / ny) : 0;
+          const T xv = (T)x[c];
           T s = 0;
-          T dg = tp.D0(p);
-          if (i > 0) s += (T)x[c - 1]; else dg += tp.CB(0, p);
-          if (i < nx - 1) s += (T)x[c + 1]; else dg += tp.CB(1, p);
-          if (j > 0) s += (T)x[c - nx]; else dg += tp.CB(2, p);
-          if (j < ny - 1) s += (T)x[c + nx]; else dg += tp.CB(3, p);
+          T dg = tp.M(p);
+          if (i > 0) s += (T)x[c - 1] - xv; else dg += tp.CBM(0, p);
+          if (i < nx - 1) s += (T)x[c + 1] - xv; else dg += tp.CBM(1, p);
+          if (j > 0) s += (T)x[c - nx] - xv; else dg += tp.CBM(2, p);
+          if (j < ny - 1) s += (T)x[c + nx] - xv; else dg += tp.CBM(3, p);
           if (DIM == 3) {
             const int64_t sxy = (int64_t)nx * ny;
-            if (k > 0) s += (T)x[c - sxy]; else dg += tp.CB(4, p);
-            if (k < tp.n[2] - 1) s += (T)x[c + sxy]; else dg += tp.CB(5, p);
+            if (k > 0) s += (T)x[c - sxy] - xv; else dg += tp.CBM(4, p);
+            if (k < tp.n[2] - 1) s += (T)x[c + sxy] - xv; else dg += tp.CBM(5, p);
           }
-          const T ax = dg * (T)x[c] + tp.CO(p) * s;
+          const T ax = dg * xv + tp.CO(p) * s;
           out = MODE == 0 ? b[c] - ax : ax;
         }
         r[c] = out;

@@ -408,7 +408,11 @@ static Tmpl<T> make_tmpl(const Level& L) {
   for (int p = 0; p < 2; ++p) {
     t.coff[p] = (T)L.coff[p];
     t.d0[p] = (T)L.d0[p];
-    for (int f = 0; f < 6; ++f) t.cb[f][p] = (T)L.cb[f][p];
+    t.mass[p] = (T)L.mass[p];
+    for (int f = 0; f < 6; ++f) {
+      t.cb[f][p] = (T)L.cb[f][p];
+      t.cbm[f][p] = (T)(L.cb[f][p] - L.coff[p]);
+    }
   }
   for (int d = 0; d < 3; ++d) t.n[d] = L.g.n[d];
   return t;

@@ -354,3 +354,20 @@ def test_nonzero_initial_guess(ctx, name, prec):
     err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
     assert err <= (1e-10 if prec == 0 else 1e-8), err
     P.release()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fine_grid_residual_reaches_the_stopping_tolerance(ctx, prec):
+    """2048^2 Eddington operator with kappa = 1 (diagonal ~6e6 against a mass
+    of 1): rounding x itself to FP64 already leaves a relative residual near
+    1e-10 here, so the residual is formed in difference form (the neighbour
+    differences, not the large diagonal against the neighbour sum, which
+    added its own rounding and kept the mixed solve above 1e-10); the solve
+    reaches the 1e-10 stopping rule in FP64 and with the FP32 cycle."""
+    pr = W.eddington(2, 2048, 1.0, seed=5)
+    _say("fine-grid residual floor, precision", prec)
+    P = ebmg.Problem(ctx, pr, precision=prec)
+    st, info, x, x2 = _solve(P, pr, 1e-10, max_cycles=200)
+    _say("   cycles", info["cycles"], "rel residual", info["rel_residual"])
+    assert st == ebmg.OK and info["rel_residual"] <= 1e-10
+    P.release()

@@ -3,8 +3,10 @@ hierarchy and its solution (Numerical methods: patch-based refinement;
 Spatial discretization, Helmholtz equations: the refluxing paragraph and its
 equation for the coarse divergence at coarse-fine faces).
 
-A hierarchy (``workloads.AmrProblem``) has one box per level, refinement
-ratio 2, level 0 the whole domain. The unknowns are those of every level's
+A hierarchy (``workloads.AmrProblem``) is a tree of boxes: level 0 the whole
+domain, every box of level l >= 1 inside one box of level l - 1 (its
+parent), refinement ratio 2; boxes of one level lie apart, so their
+coarse-fine stencils do not meet. The unknowns are those of every box's
 cells that no finer box covers ("valid" cells). The composite operator is
 written out from its definition, in this order:
 
@@ -74,23 +76,24 @@ class Composite:
 
     def __init__(self, amr, opts=None):
         self.amr = amr
-        lev = amr.levels
-        self.L = len(lev)
+        bx = amr.levels
+        self.L = len(bx)
         self.dim = amr.dim
-        self.sys = [assemble(lv.prob, opts) for lv in lev]
+        self.children = [[j for j in range(self.L) if bx[j].parent == i] for i in range(self.L)]
+        self.sys = [assemble(b.prob, opts) for b in bx]
         self.off = np.cumsum([0] + [s.N + s.N2 for s in self.sys])
         self.covered = [np.zeros(s.N + s.N2, bool) for s in self.sys]
-        for l in range(1, self.L):
-            self._cover(l)
+        for i in range(1, self.L):
+            self._cover(i)
         rows, cols, vals = [], [], []
-        for l, s in enumerate(self.sys):
+        for i, s in enumerate(self.sys):
             A = s.A.tocoo()
-            rows.append(A.row + self.off[l])
-            cols.append(A.col + self.off[l])
+            rows.append(A.row + self.off[i])
+            cols.append(A.col + self.off[i])
             vals.append(A.data)
         extra = {}
-        for l in range(1, self.L):
-            self._couple(l, extra)
+        for i in range(1, self.L):
+            self._couple(i, extra)
         if extra:
             k = np.array(list(extra.keys()), dtype=np.int64)
             rows.append(k[:, 0])
@@ -112,57 +115,59 @@ class Composite:
         self.b = np.concatenate([s.b for s in self.sys])[self.valid]
 
     # -- geometry of the hierarchy ------------------------------------------
-    def _box(self, l):
-        lv = self.amr.levels[l]
-        return lv.lo, lv.prob.n
+    def _box(self, i):
+        b = self.amr.levels[i]
+        return b.lo, b.prob.n
 
-    def _inside(self, l, g):
-        lo, n = self._box(l)
+    def _inside(self, i, g):
+        lo, n = self._box(i)
         return all(lo[d] <= g[d] < lo[d] + n[d] for d in range(self.dim))
 
-    def _footprint(self, l, gc):
-        """Coarse global cell gc (level l - 1) under level l's box."""
-        lo, n = self._box(l)
+    def _footprint(self, i, gc):
+        """Coarse global cell gc (the parent's level) under box i."""
+        lo, n = self._box(i)
         return all(2 * gc[d] >= lo[d] and 2 * gc[d] + 1 < lo[d] + n[d] for d in range(self.dim))
 
-    def _local(self, l, g):
-        lo, _ = self._box(l)
+    def _local(self, i, g):
+        lo, _ = self._box(i)
         return tuple(g[d] - lo[d] for d in range(self.dim))
 
-    def _regular_gas(self, l, g):
-        """Global cell g of level l is in its box, not covered by level l + 1
-        and a regular gas cell (kappa 1, one unknown)."""
-        if not self._inside(l, g):
+    def _regular_gas(self, i, g):
+        """Global cell g of box i's level is in box i, under none of its
+        children and a regular gas cell (kappa 1, one unknown)."""
+        if not self._inside(i, g):
             return False
-        if l + 1 < self.L and self._footprint(l + 1, g):
+        if any(self._footprint(c, g) for c in self.children[i]):
             return False
-        geo = self.sys[l].geo
-        ix = _np(self._local(l, g))
+        geo = self.sys[i].geo
+        ix = _np(self._local(i, g))
         if geo.primary[ix] != 0 or geo.has[1][ix]:
             return False
         return abs(geo.kappa(0, ix) - 1.0) < 1e-14
 
-    def _dof(self, l, g, p=0):
-        return self.sys[l].geo.dof(_np(self._local(l, g)), p)
+    def _dof(self, i, g, p=0):
+        return self.sys[i].geo.dof(_np(self._local(i, g)), p)
 
-    def _cover(self, l):
-        s = self.sys[l - 1]
+    def _cover(self, i):
+        pa = self.amr.levels[i].parent
+        s = self.sys[pa]
         geo = s.geo
-        lo, n = self._box(l - 1)
+        lo, n = self._box(pa)
         for loc in itertools.product(*[range(m) for m in n]):
             g = tuple(lo[d] + loc[d] for d in range(self.dim))
-            if self._footprint(l, g):
+            if self._footprint(i, g):
                 for p in (0, 1):
-                    i = geo.dof(_np(loc), p)
-                    if i >= 0:
-                        self.covered[l - 1][i] = True
-                self.covered[l - 1][int(np.ravel_multi_index(_np(loc), geo.shape))] = True
+                    k = geo.dof(_np(loc), p)
+                    if k >= 0:
+                        self.covered[pa][k] = True
+                self.covered[pa][int(np.ravel_multi_index(_np(loc), geo.shape))] = True
 
     # -- ghosts -------------------------------------------------------------
-    def coarse_interp(self, l, C, G, d):
-        """{coarse dof: weight} of the level l - 1 interpolant at ghost G's
-        position along the face (normal axis d), about coarse cell C."""
-        ok = lambda c: self._regular_gas(l - 1, c)
+    def coarse_interp(self, i, C, G, d):
+        """{coarse dof: weight} of the interpolant of box i's parent at ghost
+        G's position along the face (normal axis d), about coarse cell C."""
+        pa = self.amr.levels[i].parent
+        ok = lambda c: self._regular_gas(pa, c)
         sh = lambda c, e, k: tuple(c[q] + (k if q == e else 0) for q in range(self.dim))
         w = {C: 1.0}
 
@@ -205,34 +210,35 @@ class Composite:
                 if d12 is None:
                     raise AmrError(f"no mixed stencil about coarse cell {C}")
             add(d12, delta[e1] * delta[e2])
-        return {self._dof(l - 1, c): v for c, v in w.items()}
+        return {self._dof(pa, c): v for c, v in w.items()}
 
-    def ghost(self, l, F, d, side):
-        """Ghost of fine cell F (global, level l) across its face (d, side):
-        ({coarse dof: w}, {fine dof: w})."""
+    def ghost(self, i, F, d, side):
+        """Ghost of fine cell F (global, box i's level) across its face
+        (d, side): ({parent dof: w}, {box i dof: w})."""
         sgn = 1 if side else -1
         G = tuple(F[q] + (sgn if q == d else 0) for q in range(self.dim))
         Fn = tuple(F[q] - (sgn if q == d else 0) for q in range(self.dim))
         for c in (F, Fn):
-            if not self._regular_gas(l, c):
+            if not self._regular_gas(i, c):
                 raise AmrError(f"fine cell {c} next to a coarse-fine face is not a regular gas cell")
         C = tuple(G[q] // 2 for q in range(self.dim))
-        wc = {k: GHOST_W[0] * v for k, v in self.coarse_interp(l, C, G, d).items()}
-        wf = {self._dof(l, F): GHOST_W[1], self._dof(l, Fn): GHOST_W[2]}
+        wc = {k: GHOST_W[0] * v for k, v in self.coarse_interp(i, C, G, d).items()}
+        wf = {self._dof(i, F): GHOST_W[1], self._dof(i, Fn): GHOST_W[2]}
         return wc, wf
 
-    def _couple(self, l, extra):
-        """Add the ghost terms of level l's rows and the reflux of level l - 1."""
-        lv = self.amr.levels[l]
-        pf = lv.prob
-        pc = self.amr.levels[l - 1].prob
+    def _couple(self, i, extra):
+        """Add the ghost terms of box i's rows and the reflux of its parent."""
+        bx = self.amr.levels[i]
+        pa = bx.parent
+        pf = bx.prob
+        pc = self.amr.levels[pa].prob
         hf, hc = pf.h, pc.h
-        of, oc = self.off[l], self.off[l - 1]
+        of, oc = self.off[i], self.off[pa]
 
         def put(r, c, v):
             extra[(r, c)] = extra.get((r, c), 0.0) + v
-        lo, n = self._box(l)
-        cf_face = lambda d, side: lv.cf[2 * d + side]
+        lo, n = self._box(i)
+        cf_face = lambda d, side: bx.cf[2 * d + side]
         # 2. fine rows
         kf = pf.beta * pf.b_gas / (hf * hf)
         for loc in itertools.product(*[range(m) for m in n]):
@@ -242,8 +248,8 @@ class Composite:
                     at = loc[d] == (n[d] - 1 if side else 0)
                     if not (at and cf_face(d, side)):
                         continue
-                    wc, wf = self.ghost(l, F, d, side)
-                    r = of + self._dof(l, F)
+                    wc, wf = self.ghost(i, F, d, side)
+                    r = of + self._dof(i, F)
                     for k, v in wc.items():
                         put(r, oc + k, kf * v)
                     for k, v in wf.items():
@@ -252,20 +258,20 @@ class Composite:
         # 3. reflux of coarse cells next to the box
         kc = pc.beta * pc.b_gas / (hc * hc)
         kr = pc.beta * pc.b_gas / (hc * hf * 2 ** (self.dim - 1))
-        clo, cn = self._box(l - 1)
+        clo, cn = self._box(pa)
         for loc in itertools.product(*[range(m) for m in cn]):
             C = tuple(clo[q] + loc[q] for q in range(self.dim))
-            if self._footprint(l, C):
+            if self._footprint(i, C):
                 continue
             for d in range(self.dim):
                 for sgn in (1, -1):
                     Cv = tuple(C[q] + (sgn if q == d else 0) for q in range(self.dim))
-                    if not self._inside(l - 1, Cv) or not self._footprint(l, Cv):
+                    if not self._inside(pa, Cv) or not self._footprint(i, Cv):
                         continue
-                    if not self._regular_gas(l - 1, C):
+                    if not self._regular_gas(pa, C):
                         raise AmrError(f"coarse cell {C} next to the finer box is not a regular gas cell")
-                    r = oc + self._dof(l - 1, C)
-                    put(r, oc + self._dof(l - 1, Cv), -kc)
+                    r = oc + self._dof(pa, C)
+                    put(r, oc + self._dof(pa, Cv), -kc)
                     put(r, r, kc)
                     tang = [e for e in range(self.dim) if e != d]
                     for offs in itertools.product((0, 1), repeat=self.dim - 1):
@@ -274,8 +280,8 @@ class Composite:
                         for e, o in zip(tang, offs):
                             F[e] = 2 * Cv[e] + o
                         F = tuple(F)
-                        wc, wf = self.ghost(l, F, d, 0 if sgn > 0 else 1)
-                        put(r, of + self._dof(l, F), kr)
+                        wc, wf = self.ghost(i, F, d, 0 if sgn > 0 else 1)
+                        put(r, of + self._dof(i, F), kr)
                         for k, v in wc.items():
                             put(r, oc + k, -kr * v)
                         for k, v in wf.items():
@@ -283,10 +289,10 @@ class Composite:
 
     # -- vectors ------------------------------------------------------------
     def scatter(self, xv):
-        """Per-level full vectors (covered entries 0) from a valid vector."""
+        """Per-box full vectors (covered entries 0) from a valid vector."""
         full = np.zeros(int(self.off[-1]))
         full[self.valid] = xv
-        return [full[self.off[l]:self.off[l + 1]] for l in range(self.L)]
+        return [full[self.off[i]:self.off[i + 1]] for i in range(self.L)]
 
     def gather(self, xs):
         return np.concatenate(xs)[self.valid]

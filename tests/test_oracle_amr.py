@@ -41,8 +41,8 @@ def _interior_valid(C):
     boundary (there the linear Dirichlet closure is not exact for
     quadratics)."""
     masks = []
-    for l, lv in enumerate(C.amr.levels):
-        full = [m * 2 ** l for m in C.amr.levels[0].prob.n]
+    for lv in C.amr.levels:
+        full = [m * 2 ** lv.level for m in C.amr.levels[0].prob.n]
         idx = np.indices(tuple(reversed(lv.prob.n)))
         m = np.ones(tuple(reversed(lv.prob.n)), bool)
         for d in range(C.dim):
@@ -60,6 +60,10 @@ CASES = {
     "3d two levels": (3, 8, [((4, 4, 6), (8, 6, 6))]),
     "3d three levels": (3, 8, [((4, 4, 4), (8, 8, 8)), ((12, 12, 12), (8, 8, 8))]),
     "3d box on two domain faces": (3, 8, [((6, 0, 8), (8, 8, 8))]),
+    "2d two boxes on level 1": (2, 16, [(1, (4, 4), (8, 8)), (1, (20, 16), (8, 10))]),
+    "2d two boxes, one refined again": (2, 16, [(1, (4, 4), (8, 8)), (1, (20, 16), (10, 12)),
+                                                (2, (44, 36), (8, 8))]),
+    "3d two boxes on level 1": (3, 12, [(1, (2, 2, 2), (6, 6, 6)), (1, (16, 16, 10), (6, 6, 8))]),
 }
 
 
@@ -97,7 +101,8 @@ def test_planted_ghost_weight_fails():
 
 
 @pytest.mark.parametrize("name", ["2d two levels", "2d three levels", "3d two levels", "3d three levels",
-                                  "3d box on two domain faces"])
+                                  "3d box on two domain faces", "2d two boxes, one refined again",
+                                  "3d two boxes on level 1"])
 def test_refluxed_divergence_telescopes(name):
     """With zero-flux Neumann faces, the rows weighted by their cell volumes
     sum to zero for any field: the fluxes through coarse-fine faces cancel."""
@@ -105,8 +110,8 @@ def test_refluxed_divergence_telescopes(name):
     amr = W.amr_plain(dim, n0, boxes, bc=W.BC_NEUMANN)
     C = Composite(amr)
     vol = []
-    for l, lv in enumerate(amr.levels):
-        s = C.sys[l]
+    for i, lv in enumerate(amr.levels):
+        s = C.sys[i]
         vol.append(np.full(s.N + s.N2, lv.prob.h ** dim))
     vol = np.concatenate(vol)[C.valid]
     rng = np.random.default_rng(1)
@@ -178,3 +183,12 @@ def test_embedded_boundary_at_the_coarse_fine_face_is_rejected():
 def amr_objs(n, h, lo):
     Xn = W._nodes(3, n, h, lo)
     return [W.Obj(W.OBJ_ELECTRODE, 1.0, np.ascontiguousarray(W.sdf_pin3(Xn, (0.5, 0.5), 0.6, 0.1)))]
+
+
+def test_touching_boxes_are_rejected():
+    """Two boxes of one level sharing a face: the ghosts of the cells along
+    it would need the other box's fine values (fine-fine faces are not part
+    of this hierarchy), so their coarse cell is not a valid coarse cell."""
+    amr = W.amr_plain(2, 16, [(1, (4, 4), (8, 8)), (1, (12, 4), (8, 8))])
+    with pytest.raises(AmrError):
+        Composite(amr)

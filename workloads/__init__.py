@@ -650,14 +650,18 @@ def advection_pin_plane(n=128, seed=0):
 
 @dataclasses.dataclass
 class AmrLevel:
-    """One level of a nested hierarchy: ``prob`` is the level's box (level 0
-    the whole domain; level l >= 1 one patch) with the domain's boundary
+    """One box of a nested hierarchy: ``prob`` is the box (level 0 the whole
+    domain; a box of level l >= 1 one patch) with the domain's boundary
     conditions on faces that lie on the domain boundary and homogeneous
     Dirichlet on coarse-fine faces (flags ``cf``); ``lo`` is the box's first
-    cell in the level's global index space (domain cells times 2^l)."""
+    cell in its level's global index space (domain cells times 2^level);
+    ``parent`` the index of the level - 1 box that contains it (-1 for the
+    domain)."""
     prob: Problem
     lo: tuple
     cf: list
+    level: int = 0
+    parent: int = -1
 
 
 @dataclasses.dataclass
@@ -673,15 +677,28 @@ class AmrProblem:
 def amr_hierarchy(dim, n0, h0, lo0, boxes, sample, bc_kind, bc_value, robin_a1=None, robin_a2=None, name="",
                   **coef):
     """Nested hierarchy over the domain box (n0 cells of size h0 from lo0).
-    ``boxes`` lists, for each level l >= 1, (lo, n) in that level's global
-    cell indices (even, inside the coarser box). ``sample(n, h, lo)`` returns
+    ``boxes`` lists the patches in that level's global cell indices (even
+    corners, inside a box of the next coarser level): (lo, n) entries are one
+    box per level, levels 1, 2, ... in order; (level, lo, n) entries name
+    their level (several boxes per level). ``sample(n, h, lo)`` returns
     (objects, rho) of a box: its node-sampled level sets and cell-centred
     source."""
     robin_a1 = robin_a1 or [0.0] * 6
     robin_a2 = robin_a2 or [1.0] * 6
     levels = []
-    spec = [(tuple([0] * dim), tuple(n0))] + [(tuple(b[0]), tuple(b[1])) for b in boxes]
-    for l, (lo, n) in enumerate(spec):
+    spec = [(0, tuple([0] * dim), tuple(n0))]
+    for k, b in enumerate(boxes):
+        spec.append((k + 1, tuple(b[0]), tuple(b[1])) if len(b) == 2 else (int(b[0]), tuple(b[1]), tuple(b[2])))
+    for lev, lo, n in spec:
+        parent = -1
+        for q, o in enumerate(levels):
+            if o.level == lev - 1 and all(o.lo[d] <= lo[d] // 2 and (lo[d] + n[d]) // 2 <= o.lo[d] + o.prob.n[d]
+                                          for d in range(dim)):
+                parent = q
+                break
+        if lev > 0 and parent < 0:
+            raise ValueError(f"box {lo} {n} of level {lev} lies in no box of level {lev - 1}")
+        l = lev
         h = h0 / (2 ** l)
         full = tuple(m * 2 ** l for m in n0)
         blo = tuple(lo0[d] + lo[d] * h for d in range(dim))
@@ -697,8 +714,9 @@ def amr_hierarchy(dim, n0, h0, lo0, boxes, sample, bc_kind, bc_value, robin_a1=N
                     val[f] = 0.0
         objs, rho = sample(n, h, blo)
         p = Problem(dim, n, h, blo, objs, kind, val, list(robin_a1), list(robin_a2),
-                    rho=None if rho is None else np.ascontiguousarray(rho), name=f"{name}-L{l}", **coef)
-        levels.append(AmrLevel(p, lo, cf))
+                    rho=None if rho is None else np.ascontiguousarray(rho), name=f"{name}-L{l}-{len(levels)}",
+                    **coef)
+        levels.append(AmrLevel(p, lo, cf, level=lev, parent=parent))
     return AmrProblem(levels, name)
 
 

@@ -569,47 +569,51 @@ ebmg_status ebmg_advect(ebmg_problem pb, const double* n_in, const double* u_x, 
 ebmg_status ebmg_time_batch_kernel(ebmg_batch bt, int32_t which, int32_t reps, double* avg_ms, double* alg_bytes);
 
 /* Composite solves on nested AMR hierarchies. Paper: Numerical methods
- * (patch-based refinement: levels of rectangular boxes, each inside the
- * coarser level) and Helmholtz equations (coarse-fine faces: the coarse
- * divergence refluxed with the fine fluxes through the face, held in flux
- * registers). One box per level, refinement ratio 2, level 0 the domain.
- * The unknowns are those of the cells no finer box covers; the operator is
- * every level's own (the domain's boundary conditions on faces that lie on
- * the domain boundary), with, at a coarse-fine face, fine fluxes taken
- * through a ghost value (quadratic along the normal through two fine cells
- * and the coarse level's quadratic interpolant; one-sided tangential
- * differences where a side is missing) and the coarse face flux replaced by
- * the mean of the fine fluxes on it (refluxing).
- * Setup: boxes (HOST, nlev): level l's box with h = boxes[0].h / 2^l and
- * corners on its lattice, inside the coarser box; nobj[l] and objs[l]
- * (HOST) the objects sampled on level l's box nodes (as for ebmg_setup);
- * bc the domain's conditions; opts shared by every level (the linear
- * Dirichlet closure; precision picks FP64 or FP32 V-cycles). Boxes need even
- * corners and sizes >= 4 on levels >= 1, and every cell the coarse-fine
- * stencils use (two fine cells inside each coarse-fine face, two coarse
- * cells outside a box, the tangential stencils) must be a regular gas cell
- * no finer box covers: else ERR_GEOMETRY; bad boxes ERR_ARG; a host-only
- * context checks all of this and then returns ERR_DEVICE. */
-ebmg_status ebmg_setup_amr(ebmg_ctx ctx, int32_t nlev, const ebmg_box* boxes, const int32_t* nobj,
-                           const ebmg_object* const* objs, const ebmg_domain_bc* bc, const ebmg_options* opts,
-                           ebmg_amr* out);
+ * (patch-based refinement: levels of rectangular boxes, each box inside a
+ * box of the next coarser level) and Helmholtz equations (coarse-fine
+ * faces: the coarse divergence refluxed with the fine fluxes through the
+ * face, held in flux registers). Refinement ratio 2; box 0 is the domain
+ * (level 0); a box of level l >= 1 lies inside one box of level l - 1 (its
+ * parent), and boxes of one level do not overlap. The unknowns are those of
+ * the cells no finer box covers; the operator is every box's own (the
+ * domain's boundary conditions on faces that lie on the domain boundary),
+ * with, at a coarse-fine face, fine fluxes taken through a ghost value
+ * (quadratic along the normal through two fine cells and the parent's
+ * quadratic interpolant; one-sided tangential differences where a side is
+ * missing) and the coarse face flux replaced by the mean of the fine fluxes
+ * on it (refluxing).
+ * Setup: boxes (HOST, nbox) with levels (HOST, nbox): box i has cells of
+ * size boxes[0].h / 2^levels[i] and corners on its level's lattice; nobj[i]
+ * and objs[i] (HOST) the objects sampled on box i's nodes (as for
+ * ebmg_setup); bc the domain's conditions; opts shared by every box (the
+ * linear Dirichlet closure; precision picks FP64 or FP32 V-cycles). Boxes
+ * of levels >= 1 need even corners and sizes >= 4 and must lie two cells
+ * inside their parent's coarse-fine faces (else ERR_ARG), and every cell
+ * the coarse-fine stencils use (two fine cells inside each coarse-fine
+ * face, two coarse cells outside a box, the tangential stencils) must be a
+ * regular gas cell no finer box covers, which also keeps boxes of one level
+ * from touching: else ERR_GEOMETRY. A host-only context checks all of this
+ * and then returns ERR_DEVICE. */
+ebmg_status ebmg_setup_amr(ebmg_ctx ctx, int32_t nbox, const ebmg_box* boxes, const int32_t* levels,
+                           const int32_t* nobj, const ebmg_object* const* objs, const ebmg_domain_bc* bc,
+                           const ebmg_options* opts, ebmg_amr* out);
 
-/* Sizes of level `level` (no paper passage): its cells, second-phase
- * unknowns, the unknowns covered by the next finer box, and the device bytes
- * of the whole hierarchy. Any pointer may be NULL. */
-ebmg_status ebmg_query_amr(ebmg_amr a, int32_t level, int64_t* n_cells, int64_t* n_phase2, int64_t* n_covered,
+/* Sizes of box `box` (no paper passage): its cells, second-phase unknowns,
+ * the unknowns its children cover, and the device bytes of the whole
+ * hierarchy. Any pointer may be NULL. */
+ebmg_status ebmg_query_amr(ebmg_amr a, int32_t box, int64_t* n_cells, int64_t* n_phase2, int64_t* n_covered,
                            int64_t* device_bytes);
 
 /* Paper: Multigrid solver (residual reduction to ||r|| <= rtol ||r0||,
  * r0 at phi = 0) applied to the composite system of the hierarchy.
- * rho[l] (DEVICE, N_l doubles) per level; phi[l] (DEVICE, N_l; in: the
- * guess, out: the solution) and phi2[l] (DEVICE, N2_l; may be NULL where a
- * level has none). Right-preconditioned FP64 BiCGStab: the preconditioner
- * restricts the fine residual onto covered cells, runs one V-cycle of level
- * 0 over the domain, then level by level prolongs the coarse correction and
- * adds one V-cycle of that level on its residual (homogeneous coarse-fine
- * faces). On return covered cells hold the mean of their children (finest
- * first). info (HOST, may be NULL): outer_iters the BiCGStab iterations,
+ * rho[i] (DEVICE, N_i doubles) per box; phi[i] (DEVICE, N_i; in: the
+ * guess, out: the solution) and phi2[i] (DEVICE, N2_i; may be NULL where a
+ * box has none). Right-preconditioned FP64 BiCGStab; the preconditioner is
+ * a V-cycle over the boxes: down from the deepest level, one V-cycle of
+ * each box on its residual (homogeneous coarse-fine faces) and its parent's
+ * residual updated by that correction; one V-cycle of box 0; up again, the
+ * parent's correction prolonged and a second V-cycle per box. On return
+ * covered cells hold the mean of their children (deepest first). info (HOST, may be NULL): outer_iters the BiCGStab iterations,
  * cycles two per iteration, rel_residual the composite relative residual,
  * est_bytes 0 (not estimated). NOCONV after max_iters, NUMERIC on a
  * non-finite residual; both leave the last iterate. */
@@ -617,7 +621,7 @@ ebmg_status ebmg_solve_amr(ebmg_amr a, const double* const* rho, double rtol, in
                            double* const* phi2, ebmg_solve_info* info);
 
 /* Paper: Helmholtz equations (the composite operator with refluxing).
- * out[l] = (A_comp [phi])_l per level (DEVICE arrays as in ebmg_solve_amr);
+ * out[i] = (A_comp [phi])_i per box (DEVICE arrays as in ebmg_solve_amr);
  * covered unknowns are identity rows (out = phi there). */
 ebmg_status ebmg_apply_amr(ebmg_amr a, const double* const* phi, const double* const* phi2, double* const* out,
                            double* const* out2);

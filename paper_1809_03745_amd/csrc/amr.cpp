@@ -1,11 +1,12 @@
 // Host preparation of the composite operator of a nested AMR hierarchy
 // (Numerical methods: patch-based refinement; Helmholtz equations: the
-// refluxing of coarse-fine faces). Levels hold one box each, refinement
-// ratio 2, level 0 the whole domain; a patch's faces inside the domain are
-// coarse-fine faces, set up as homogeneous Dirichlet faces (linear closure)
-// of the patch's own problem. Per coarse-fine interface this builds the
-// sparse corrections that turn the levels' own operators into the composite
-// one:
+// refluxing of coarse-fine faces). The hierarchy is a tree of boxes,
+// refinement ratio 2, level 0 the whole domain, every other box inside one
+// box of the next coarser level (its parent); a patch's faces inside the
+// domain are coarse-fine faces, set up as homogeneous Dirichlet faces
+// (linear closure) of the patch's own problem. Per parent-child pair this
+// builds the sparse corrections that turn the boxes' own operators into the
+// composite one:
 //  * fine rows next to a coarse-fine face gain (beta b / h_f^2)(phi_G + phi_F)
 //    with the ghost phi_G = 8/15 phi_C + 2/3 phi_F - 1/5 phi_Fn (quadratic
 //    along the normal through the coarse value at -1 fine cell and the two
@@ -38,7 +39,7 @@ namespace {
 struct Lev {
   const Problem& P;
   const AmrBox& box;
-  const AmrBox* finer;   // the box of the next finer level, or null
+  const std::vector<const AmrBox*>& kids;   // the boxes refining this one
   int dim() const { return P.geo.g.dim; }
 };
 
@@ -70,7 +71,8 @@ int64_t slot(const Lev& L, const int* g, int p) {
 bool regular_gas(const Lev& L, const int* g) {
   const int D = L.dim();
   if (!in_box(L.box, D, g)) return false;
-  if (L.finer && under(*L.finer, D, g)) return false;
+  for (const AmrBox* k : L.kids)
+    if (under(*k, D, g)) return false;
   const Geometry& G = L.P.geo;
   const int64_t c = local_cell(L, g);
   if (G.primary[c] != 0 || G.sec_of[c] >= 0) return false;
@@ -177,11 +179,11 @@ void flush_row(int64_t row, const std::map<int64_t, double>& m, std::vector<int6
 
 }  // namespace
 
-void build_amr_link(const Problem& C, const AmrBox& cb, const Problem& F, const AmrBox& fb, const AmrBox* finer,
-                    AmrLink& out) {
+void build_amr_link(const Problem& C, const AmrBox& cb, const std::vector<const AmrBox*>& ckids, const Problem& F,
+                    const AmrBox& fb, const std::vector<const AmrBox*>& fkids, AmrLink& out) {
   const int D = C.geo.g.dim;
-  const Lev Cl{C, cb, &fb};
-  const Lev Fl{F, fb, finer};
+  const Lev Cl{C, cb, ckids};
+  const Lev Fl{F, fb, fkids};
   out = AmrLink();
   // proper nesting: the box lies inside the coarser one on coarse cells
   for (int d = 0; d < D; ++d) {

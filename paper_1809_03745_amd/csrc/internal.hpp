@@ -254,10 +254,12 @@ struct AmrBox {
   int lo[3] = {0, 0, 0};   // first cell in the level's global index space
   int n[3] = {1, 1, 1};
   bool cf[6] = {false, false, false, false, false, false};   // coarse-fine faces
+  int level = 0;
+  int parent = -1;         // the box of the next coarser level holding it
 };
 
-// Coupling of level l (fine) with level l - 1 (coarse), as sparse rows over
-// unknown slots (cells, then second-phase unknowns, of each level's box).
+// Coupling of a box (fine) with its parent (coarse), as sparse rows over
+// unknown slots (cells, then second-phase unknowns, of each box).
 struct AmrLink {
   // added to the fine level's A x: column >= 0 a fine slot, < 0 the coarse
   // slot -column - 1
@@ -273,7 +275,9 @@ struct AmrLink {
   std::vector<int64_t> pcol;                    // fine slot <- coarse slot (-1: none)
 };
 
-void build_amr_link(const Problem& C, const AmrBox& cb, const Problem& F, const AmrBox& fb, const AmrBox* finer,
-                    AmrLink& out);
+// C, cb: the parent box; ckids: every box refining it (fb among them);
+// F, fb: the child; fkids: the boxes refining the child
+void build_amr_link(const Problem& C, const AmrBox& cb, const std::vector<const AmrBox*>& ckids, const Problem& F,
+                    const AmrBox& fb, const std::vector<const AmrBox*>& fkids, AmrLink& out);
 
 }  // namespace ebmg

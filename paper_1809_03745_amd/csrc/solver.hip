@@ -328,10 +328,10 @@ struct ebmg_family_s {
   bool warm = false;                         // every member has solved once (graphs captured)
 };
 
-// A nested AMR hierarchy: one problem per level (its own operator and
-// multigrid hierarchy), the coupling rows of every coarse-fine interface on
-// the device, and the composite vectors (every level's unknowns in one
-// contiguous array, each level's slice starting on a 64-entry boundary).
+// A nested AMR hierarchy: one problem per box (its own operator and
+// multigrid hierarchy), the coupling rows of every parent-child pair on the
+// device, and the composite vectors (every box's unknowns in one contiguous
+// array, each box's slice starting on a 64-entry boundary).
 struct ebmg_amr_s {
   ebmg_ctx ctx = nullptr;
   std::vector<ebmg_problem_s*> lev;
@@ -346,8 +346,9 @@ struct ebmg_amr_s {
       fw.release(); cw.release(); rw.release(); aw.release();
     }
   };
-  std::vector<Link> link;          // link[l] couples level l with level l - 1 (l >= 1)
-  std::vector<int64_t> off, nd;    // per level: slice offset and unknowns (N + N2)
+  std::vector<Link> link;          // link[i] couples box i with its parent (i >= 1)
+  std::vector<int64_t> off, nd;    // per box: slice offset and unknowns (N + N2)
+  std::vector<int> order;          // boxes by level, deepest first
   int64_t ntot = 0;
   ebmg::DevBuf<double> x, b, r, rh, p, v, sv, t, ph, sh, rt, y, e, part, scal;
   int64_t bytes = 0;
@@ -2562,7 +2563,7 @@ static void amr_apply(ebmg_amr_s* A, const double* x, double* y, hipStream_t s) 
   for (int l = 0; l < L; ++l) residual<double, 1>(A->lev[l]->dev.lv[0], x + A->off[l], nullptr, y + A->off[l], s);
   for (int l = 1; l < L; ++l) {
     auto& K = A->link[l];
-    const int64_t of = A->off[l], oc = A->off[l - 1];
+    const int64_t of = A->off[l], oc = A->off[A->box[l].parent];
     if (K.nf)
       hipLaunchKernelGGL(k_amr_rows, dim3(nblk(K.nf)), dim3(256), 0, s, K.nf, K.frow.p, K.fptr.p, K.fcol.p, K.fw.p,
                          x + of, x + oc, y + of);
@@ -2593,9 +2594,13 @@ static void amr_precond(ebmg_amr_s* A, const double* r, double* z, hipStream_t s
   double* e = A->e.p;
   hipLaunchKernelGGL(k_amr_lin, dim3(nblk(n)), dim3(256), 0, s, n, 1.0, r, 0.0, r, rt);
   fill<double>(z, n, 0.0, s);
-  for (int l = L - 1; l >= 1; --l) {
+  // down: every box before its parent (deepest level first)
+  for (int q = 0; q < L; ++q) {
+    const int l = A->order[q];
+    if (l == 0) continue;
     auto& K = A->link[l];
-    const int64_t of = A->off[l], oc = A->off[l - 1], m = A->nd[l], mc = A->nd[l - 1];
+    const int pa = A->box[l].parent;
+    const int64_t of = A->off[l], oc = A->off[pa], m = A->nd[l], mc = A->nd[pa];
     precond(A->lev[l]->dev, A->lev[l]->host->opt, rt + of, z + of, s);
     residual<double, 1>(A->lev[l]->dev.lv[0], z + of, nullptr, y + of, s);
     if (K.nf)
@@ -2613,9 +2618,12 @@ static void amr_precond(ebmg_amr_s* A, const double* r, double* z, hipStream_t s
     }
   }
   precond(A->lev[0]->dev, A->lev[0]->host->opt, rt + A->off[0], z + A->off[0], s);
-  for (int l = 1; l < L; ++l) {
+  // up: every box after its parent (coarsest level first)
+  for (int q = L - 1; q >= 0; --q) {
+    const int l = A->order[q];
+    if (l == 0) continue;
     auto& K = A->link[l];
-    const int64_t of = A->off[l], oc = A->off[l - 1], m = A->nd[l];
+    const int64_t of = A->off[l], oc = A->off[A->box[l].parent], m = A->nd[l];
     hipLaunchKernelGGL(k_amr_prolong, dim3(nblk(m)), dim3(256), 0, s, m, K.pcol.p, z + oc, e + of);
     hipLaunchKernelGGL(k_amr_lin, dim3(nblk(m)), dim3(256), 0, s, m, 1.0, z + of, 1.0, e + of, z + of);
     residual<double, 1>(A->lev[l]->dev.lv[0], z + of, nullptr, y + of, s);
@@ -2630,7 +2638,7 @@ static void amr_precond(ebmg_amr_s* A, const double* r, double* z, hipStream_t s
     auto& K = A->link[l];
     if (K.ncov)
       hipLaunchKernelGGL(k_amr_set, dim3(nblk(K.ncov)), dim3(256), 0, s, K.ncov, K.cov.p, (const double*)nullptr,
-                         z + A->off[l - 1]);
+                         z + A->off[A->box[l].parent]);
   }
   HIPCHECK(hipGetLastError());
 }
@@ -4064,10 +4072,10 @@ ebmg_status ebmg_time_batch_kernel(ebmg_batch bt, int32_t which, int32_t reps, d
   });
 }
 
-ebmg_status ebmg_setup_amr(ebmg_ctx ctx, int32_t nlev, const ebmg_box* boxes, const int32_t* nobj,
-                           const ebmg_object* const* objs, const ebmg_domain_bc* bc, const ebmg_options* opts,
-                           ebmg_amr* out) {
-  if (!ctx || nlev < 1 || nlev > 8 || !boxes || !nobj || !objs || !bc || !out) {
+ebmg_status ebmg_setup_amr(ebmg_ctx ctx, int32_t nbox, const ebmg_box* boxes, const int32_t* levels,
+                           const int32_t* nobj, const ebmg_object* const* objs, const ebmg_domain_bc* bc,
+                           const ebmg_options* opts, ebmg_amr* out) {
+  if (!ctx || nbox < 1 || nbox > 256 || !boxes || !levels || !nobj || !objs || !bc || !out) {
     if (ctx) ctx->err = "invalid argument to ebmg_setup_amr";
     return EBMG_ERR_ARG;
   }
@@ -4076,44 +4084,66 @@ ebmg_status ebmg_setup_amr(ebmg_ctx ctx, int32_t nlev, const ebmg_box* boxes, co
   A->ctx = ctx;
   const ebmg_status st = guard(ctx, [&]() -> ebmg_status {
     const int D = boxes[0].dim;
+    const int nlev = nbox;   // boxes, in the loops below
     if (D != 2 && D != 3) throw ArgError("dim must be 2 or 3");
     ebmg::Options o0;
     if (parse_options(opts, nobj[0], o0) != EBMG_OK) throw ArgError("bad options");
     if (o0.dirichlet_closure != 0)
       throw ArgError("AMR hierarchies use the linear Dirichlet closure on their coarse-fine faces");
+    if (levels[0] != 0) throw ArgError("box 0 is the domain (level 0)");
     // boxes: level l has cells of size h0 / 2^l, corners on the level's lattice
     A->box.resize(nlev);
     for (int l = 0; l < nlev; ++l) {
       const ebmg_box& B = boxes[l];
-      if (B.dim != D) throw ArgError("every level has the base box's dimension");
-      if (nobj[l] < 0 || nobj[l] > 64 || (nobj[l] > 0 && !objs[l])) throw ArgError("bad objects of a level");
-      const double h = boxes[0].h / (double)(1 << l);
-      if (std::fabs(B.h - h) > 1e-12 * h) throw ArgError("level l needs cells of size h0 / 2^l");
+      const int lev = levels[l];
+      if (B.dim != D) throw ArgError("every box has the base box's dimension");
+      if (lev < 0 || lev > 12 || (l > 0 && lev == 0)) throw ArgError("bad level of an AMR box");
+      if (nobj[l] < 0 || nobj[l] > 64 || (nobj[l] > 0 && !objs[l])) throw ArgError("bad objects of a box");
+      const double h = boxes[0].h / (double)(1 << lev);
+      if (std::fabs(B.h - h) > 1e-12 * h) throw ArgError("a box of level l needs cells of size h0 / 2^l");
       ebmg::AmrBox& X = A->box[l];
+      X.level = lev;
       for (int d = 0; d < D; ++d) {
         const double q = (B.lo[d] - boxes[0].lo[d]) / h;
         X.lo[d] = (int)std::lround(q);
         X.n[d] = B.n[d];
         if (std::fabs(q - X.lo[d]) > 1e-6) throw ArgError("an AMR box corner is off its level's lattice");
-        const int full = boxes[0].n[d] << l;
+        const int full = boxes[0].n[d] << lev;
         if (X.lo[d] < 0 || X.n[d] < 1 || X.lo[d] + X.n[d] > full) throw ArgError("an AMR box leaves the domain");
-        X.cf[2 * d] = l > 0 && X.lo[d] > 0;
-        X.cf[2 * d + 1] = l > 0 && X.lo[d] + X.n[d] < full;
+        X.cf[2 * d] = lev > 0 && X.lo[d] > 0;
+        X.cf[2 * d + 1] = lev > 0 && X.lo[d] + X.n[d] < full;
       }
       if (l == 0)
         for (int d = 0; d < D; ++d)
-          if (X.lo[d] != 0 || X.n[d] != boxes[0].n[d]) throw ArgError("level 0 is the domain");
+          if (X.lo[d] != 0 || X.n[d] != boxes[0].n[d]) throw ArgError("box 0 is the domain");
     }
-    // proper nesting: each box on even corners, its coarse cells inside the
-    // coarser box and at least two cells from that box's coarse-fine faces
+    // proper nesting: each box on even corners, its coarse cells inside one
+    // box of the next coarser level (its parent) and at least two cells from
+    // that box's coarse-fine faces; boxes of one level do not overlap
     for (int l = 1; l < nlev; ++l) {
-      const ebmg::AmrBox &F = A->box[l], &Cb = A->box[l - 1];
-      for (int d = 0; d < D; ++d) {
+      ebmg::AmrBox& F = A->box[l];
+      for (int d = 0; d < D; ++d)
         if (F.lo[d] % 2 || F.n[d] % 2 || F.n[d] < 4) throw ArgError("AMR boxes need even corners and sizes >= 4");
-        const int clo = F.lo[d] / 2, chi = (F.lo[d] + F.n[d]) / 2;
-        const int mlo = Cb.cf[2 * d] ? 2 : 0, mhi = Cb.cf[2 * d + 1] ? 2 : 0;
-        if (clo < Cb.lo[d] + mlo || chi > Cb.lo[d] + Cb.n[d] - mhi)
-          throw ArgError("an AMR box must lie inside the next coarser box, two cells from its coarse-fine faces");
+      for (int q = 0; q < nlev && F.parent < 0; ++q) {
+        const ebmg::AmrBox& Cb = A->box[q];
+        if (Cb.level != F.level - 1) continue;
+        bool in = true;
+        for (int d = 0; d < D; ++d) {
+          const int clo = F.lo[d] / 2, chi = (F.lo[d] + F.n[d]) / 2;
+          const int mlo = Cb.cf[2 * d] ? 2 : 0, mhi = Cb.cf[2 * d + 1] ? 2 : 0;
+          in = in && clo >= Cb.lo[d] + mlo && chi <= Cb.lo[d] + Cb.n[d] - mhi;
+        }
+        if (in) F.parent = q;
+      }
+      if (F.parent < 0)
+        throw ArgError("an AMR box must lie inside a box of the next coarser level, two cells from its coarse-fine faces");
+      for (int q = 1; q < l; ++q) {
+        const ebmg::AmrBox& G = A->box[q];
+        if (G.level != F.level) continue;
+        bool overlap = true;
+        for (int d = 0; d < D; ++d)
+          overlap = overlap && F.lo[d] < G.lo[d] + G.n[d] && G.lo[d] < F.lo[d] + F.n[d];
+        if (overlap) throw ArgError("boxes of one AMR level overlap");
       }
     }
     // one problem per level: the domain's conditions on domain faces,
@@ -4133,10 +4163,18 @@ ebmg_status ebmg_setup_amr(ebmg_ctx ctx, int32_t nlev, const ebmg_box* boxes, co
       build_host_problem(H, &boxes[l], nobj[l], objs[l], &lb);
       A->lev.push_back(P.release());
     }
+    std::vector<std::vector<const ebmg::AmrBox*>> kids(nlev);
+    for (int l = 1; l < nlev; ++l) kids[A->box[l].parent].push_back(&A->box[l]);
     std::vector<AmrLink> host_links(nlev);
-    for (int l = 1; l < nlev; ++l)
-      build_amr_link(*A->lev[l - 1]->host, A->box[l - 1], *A->lev[l]->host, A->box[l],
-                     l + 1 < nlev ? &A->box[l + 1] : nullptr, host_links[l]);
+    for (int l = 1; l < nlev; ++l) {
+      const int pa = A->box[l].parent;
+      build_amr_link(*A->lev[pa]->host, A->box[pa], kids[pa], *A->lev[l]->host, A->box[l], kids[l], host_links[l]);
+    }
+    // boxes deepest level first (the preconditioner's downward order)
+    A->order.resize(nlev);
+    for (int l = 0; l < nlev; ++l) A->order[l] = l;
+    std::stable_sort(A->order.begin(), A->order.end(),
+                     [&](int x, int y) { return A->box[x].level > A->box[y].level; });
     // the host part is checked on any context; the solve needs a device
     if (ctx->device < 0) throw DeviceError("an AMR hierarchy needs a device context");
     HIPCHECK(hipSetDevice(ctx->device));
@@ -4205,7 +4243,12 @@ ebmg_status ebmg_query_amr(ebmg_amr a, int32_t level, int64_t* n_cells, int64_t*
   if (!a || level < 0 || level >= (int32_t)a->lev.size()) return EBMG_ERR_ARG;
   if (n_cells) *n_cells = a->lev[level]->host->geo.N;
   if (n_phase2) *n_phase2 = a->lev[level]->host->geo.N2;
-  if (n_covered) *n_covered = level + 1 < (int32_t)a->lev.size() ? a->link[level + 1].ncov : 0;
+  if (n_covered) {
+    int64_t c = 0;
+    for (size_t l = 1; l < a->lev.size(); ++l)
+      if (a->box[l].parent == level) c += a->link[l].ncov;
+    *n_covered = c;
+  }
   if (device_bytes) *device_bytes = a->bytes;
   return EBMG_OK;
 }
@@ -4260,11 +4303,12 @@ ebmg_status ebmg_solve_amr(ebmg_amr a, const double* const* rho, double rtol, in
     amr_copy(a, phi, phi2, true, s);
     for (int l = 1; l < L; ++l) {
       auto& K = a->link[l];
+      const int64_t oc = a->off[a->box[l].parent];
       if (K.ncov) {
         hipLaunchKernelGGL(k_amr_set, dim3(nblk(K.ncov)), dim3(256), 0, s, K.ncov, K.cov.p, (const double*)nullptr,
-                           a->b.p + a->off[l - 1]);
+                           a->b.p + oc);
         hipLaunchKernelGGL(k_amr_set, dim3(nblk(K.ncov)), dim3(256), 0, s, K.ncov, K.cov.p, (const double*)nullptr,
-                           a->x.p + a->off[l - 1]);
+                           a->x.p + oc);
       }
     }
     HIPCHECK(hipGetLastError());
@@ -4279,12 +4323,14 @@ ebmg_status ebmg_solve_amr(ebmg_amr a, const double* const* rho, double rtol, in
       rel = bn > 0 ? std::sqrt(amr_dot(a, a->r.p, a->r.p, s)) / bn : 0.0;
       if (!std::isfinite(rel)) res = EBMG_ERR_NUMERIC;
     }
-    // covered cells take the mean of their children, finest first
-    for (int l = L - 1; l >= 1; --l) {
+    // covered cells take the mean of their children, deepest boxes first
+    for (int q = 0; q < L; ++q) {
+      const int l = a->order[q];
+      if (l == 0) continue;
       auto& K = a->link[l];
       if (K.nr)
         hipLaunchKernelGGL(k_amr_gather, dim3(nblk(K.nr)), dim3(256), 0, s, K.nr, K.rrow.p, K.rptr.p, K.rcol.p,
-                           K.aw.p, a->x.p + a->off[l], a->x.p + a->off[l - 1]);
+                           K.aw.p, a->x.p + a->off[l], a->x.p + a->off[a->box[l].parent]);
     }
     amr_copy(a, phi, phi2, false, s);
     HIPCHECK(hipStreamSynchronize(s));

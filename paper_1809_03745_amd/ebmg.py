@@ -134,7 +134,7 @@ _sig("ebmg_solve_family", C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.c_dou
 _sig("ebmg_release_family", C.c_int, [_vp])
 _sig("ebmg_advect", C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, _vp, _vp])
 _sig("ebmg_time_batch_kernel", C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp])
-_sig("ebmg_setup_amr", C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp])
+_sig("ebmg_setup_amr", C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_query_amr", C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp])
 _sig("ebmg_solve_amr", C.c_int, [_vp, _vp, C.c_double, C.c_int32, _vp, _vp, _vp])
 _sig("ebmg_apply_amr", C.c_int, [_vp, _vp, _vp, _vp, _vp])
@@ -738,8 +738,9 @@ class Mesh:
 
 
 class Amr:
-    """A nested AMR hierarchy set up from a ``workloads.AmrProblem`` (one box
-    per level, level 0 the domain): composite solves and applies."""
+    """A nested AMR hierarchy set up from a ``workloads.AmrProblem`` (a tree
+    of boxes, box 0 the domain): composite solves and applies; per-box lists
+    of device tensors in the order of ``amr.levels``."""
 
     def __init__(self, ctx, amr, **opts):
         self.ctx = ctx
@@ -748,6 +749,7 @@ class Amr:
         boxes = (Box * L)()
         keep, objarrs = [], []
         nobj = (C.c_int32 * L)()
+        levs = (C.c_int32 * L)(*[int(getattr(lv, "level", l)) for l, lv in enumerate(amr.levels)])
         ptrs = (_vp * L)()
         for l, lv in enumerate(amr.levels):
             box, objs, _, sdf = _c_problem(lv.prob)
@@ -759,7 +761,7 @@ class Amr:
         bc = _c_bc(amr.levels[0].prob)
         self.options = make_options(amr.levels[0].prob, **opts)
         h = _vp()
-        st = _lib.ebmg_setup_amr(ctx.h, L, boxes, nobj, ptrs, C.byref(bc), C.byref(self.options), C.byref(h))
+        st = _lib.ebmg_setup_amr(ctx.h, L, boxes, levs, nobj, ptrs, C.byref(bc), C.byref(self.options), C.byref(h))
         del keep, objarrs
         ctx.check(st, "ebmg_setup_amr")
         self.h = h

@@ -414,6 +414,15 @@ def test_amr_host_checks_on_a_host_only_context():
     with pytest.raises(ebmg.EbmgError) as e:
         ebmg.Amr(ctx, W.amr_plain(2, 16, [((8, 8), (12, 12))]), dirichlet_closure=1)
     assert e.value.status == ebmg.ERR_ARG
-    with pytest.raises(ebmg.EbmgError) as e:   # a box reaching past its coarser box
-        ebmg.Amr(ctx, W.amr_plain(2, 16, [((4, 4), (16, 16)), ((24, 8), (20, 20))]))
+    with pytest.raises(ebmg.EbmgError) as e:   # one cell from its parent's coarse-fine face
+        ebmg.Amr(ctx, W.amr_plain(2, 16, [((4, 4), (16, 16)), ((10, 10), (8, 8))]))
     assert e.value.status == ebmg.ERR_ARG
+    with pytest.raises(ebmg.EbmgError) as e:   # two boxes of one level overlapping
+        ebmg.Amr(ctx, W.amr_plain(2, 16, [(1, (4, 4), (8, 8)), (1, (8, 8), (8, 8))]))
+    assert e.value.status == ebmg.ERR_ARG
+    with pytest.raises(ebmg.EbmgError) as e:   # two boxes of one level touching
+        ebmg.Amr(ctx, W.amr_plain(2, 16, [(1, (4, 4), (8, 8)), (1, (12, 4), (8, 8))]))
+    assert e.value.status == ebmg.ERR_GEOMETRY
+    with pytest.raises(ebmg.EbmgError) as e:   # several boxes per level: host part accepted
+        ebmg.Amr(ctx, W.amr_plain(2, 16, [(1, (4, 4), (8, 8)), (1, (20, 16), (10, 12)), (2, (44, 36), (8, 8))]))
+    assert e.value.status == ebmg.ERR_DEVICE

@@ -154,9 +154,8 @@ def _kernel_label(P, prec):
     if var == ebmg.OOP_VARIANT:
         return f"k_rb_oop<{t},3> (one-launch colour phase of a red/black sweep, finest level)", "half-sweep"
     if var >= 2:
-        tile = ",".join(str(v).lower() for v in ebmg.ZM_TILES[var - 2])
         # the last template flag: false = the full sweep (reads x), the form timed
-        return (f"k_rb_zm3<{t},{tile},false> (fused red+black Gauss-Seidel sweep marching in z, finest level)",
+        return (f"{ebmg.zm_kernel(t, var - 2)} (fused red+black Gauss-Seidel sweep marching in z, finest level)",
                 "fused sweep")
     if var == 1:
         return f"k_rb_tile3<{t}> (fused red+black Gauss-Seidel sweep, finest level)", "fused sweep"
@@ -279,8 +278,7 @@ def pmc_summary(fetch_csv, write_csv, command):
                            "fetch_kib": fk_c, "write_kib": wk_c, "fetch_scale": sf, "write_scale": sw},
            "kernels": {}}
     from paper_1809_03745_amd import ebmg
-    zms = [f"k_rb_zm3<{t},{','.join(str(v).lower() for v in c)},false>" for t in ("float", "double")
-           for c in ebmg.ZM_TILES]
+    zms = [ebmg.zm_kernel(t, c) for t in ("float", "double") for c in range(len(ebmg.ZM_TILES))]
     for name in ["k_rb<float,3>", "k_rb<double,3>", "k_rb_tile3<float>", "k_rb_tile3<double>",
                  "k_resid_reg<double,3,0>", "k_resid_zm3<double,0,double,0>", "k_resid_zp3<double,0,double,0>"] + zms:
         keys = [k for k in f if k[0] == name]

@@ -207,7 +207,7 @@ ebmg_status ebmg_query_level(ebmg_problem pb, int32_t level, int64_t* n_cells, i
  * red/black Gauss-Seidel relaxation). Outputs HOST.
  * Smoother choice of level `level` (0 split half-sweeps, 1 fused tile sweep,
  * 2 + c z-marching fused sweep in tile configuration c as listed at
- * ebmg_smooth, 13 one-launch colour phases), the split sweep time and the
+ * ebmg_smooth, 16 one-launch colour phases), the split sweep time and the
  * chosen (or best
  * fused) variant's sweep time (ms) as the setup autotuner measured them (0 if
  * not timed).
@@ -363,14 +363,16 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
  * Red/black Gauss-Seidel sweeps over the template cells of level `level` only: explicit-row,
  * covered and second-phase entries of x are left as they are. variant: 1
  * split red and black half-sweeps, 2 fused tile sweep, 3 + c z-marching
- * fused sweep in tile configuration c = 0..10 (x-by-y tiles over z planes:
+ * fused sweep in tile configuration c = 0..13 (x-by-y tiles over z planes:
  * 64x8 over 32, 64x16 over 32, 32x16 over 32, 64x8 over 16, 128x8 over 32,
  * 32x8 over 32, 32x32 over 32; 7..9: 64x16, 128x8 and 32x32 over 32 with
- * 16-byte fetches, x extent a multiple of 4; 10: 64x16 over 8; 3D), 14 one-launch colour
+ * 16-byte fetches, x extent a multiple of 4; 10: 64x16 over 8; 11..13: the
+ * quad form, each thread four cells of a row, 128x8 over 16, 64x16 over 16
+ * and 128x8 over 32, x extent a multiple of 4; 3D), 17 one-launch colour
  * phases out of place. Every variant performs exactly the red half-sweep
  * followed by
  * the black one with the same arithmetic, so their results agree bitwise.
- * Variant 15 is the one-launch colour phases with the explicit rows
+ * Variant 18 is the one-launch colour phases with the explicit rows
  * included, as the solver smooths levels that use them: in the phase of
  * colour c every template cell of colour c and every explicit row whose
  * cell has colour c (by the parity of i+j+k) is relaxed from the values

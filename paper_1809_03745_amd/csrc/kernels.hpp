@@ -579,26 +579,27 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
   VT Aow[WIDE ? UOW : 1], Abw[WIDE ? URW : 1], Bow[WIDE ? UOW : 1], Bbw[WIDE ? URW : 1];
   uint32_t Atw[WIDE ? UTW : 1], Btw[WIDE ? UTW : 1];
 
-#define ZM_LOAD(P, z)                                                        \
+#define ZM_LOAD_Q(P, z, Q)                                                   \
   {                                                                          \
     const int zz_ = (z);                                                     \
     const int64_t zoff_ = sxy * (zz_ >= 0 && zz_ < nz ? zz_ : 0);            \
     if constexpr (WIDE) {                                                    \
       if constexpr (!ZIN) {                                                  \
-        _Pragma("unroll") for (int u = 0; u < UOW; ++u) P##ow[u] = *(const VT*)(xin + zoff_ + offow[u]); \
+        _Pragma("unroll") for (int u = 0; u < UOW; ++u) P##ow[u] = *(Q const VT*)(xin + zoff_ + offow[u]); \
       }                                                                      \
-      _Pragma("unroll") for (int u = 0; u < URW; ++u) P##bw[u] = *(const VT*)(b + zoff_ + offbw[u]); \
-      _Pragma("unroll") for (int u = 0; u < UTW; ++u) P##tw[u] = *(const uint32_t*)(tag + zoff_ + offtw[u]); \
+      _Pragma("unroll") for (int u = 0; u < URW; ++u) P##bw[u] = *(Q const VT*)(b + zoff_ + offbw[u]); \
+      _Pragma("unroll") for (int u = 0; u < UTW; ++u) P##tw[u] = *(Q const uint32_t*)(tag + zoff_ + offtw[u]); \
     } else {                                                                 \
       if constexpr (!ZIN) {                                                  \
-        _Pragma("unroll") for (int u = 0; u < UO; ++u) P##ov[u] = xin[zoff_ + offo[u]]; \
+        _Pragma("unroll") for (int u = 0; u < UO; ++u) P##ov[u] = ((Q const T*)xin)[zoff_ + offo[u]]; \
       }                                                                      \
       _Pragma("unroll") for (int u = 0; u < UR; ++u) {                       \
-        P##bv[u] = b[zoff_ + offr[u]];                                       \
-        P##tv[u] = tag[zoff_ + offr[u]];                                     \
+        P##bv[u] = ((Q const T*)b)[zoff_ + offr[u]];                         \
+        P##tv[u] = ((Q const uint8_t*)tag)[zoff_ + offr[u]];                 \
       }                                                                      \
     }                                                                        \
   }
+#define ZM_LOAD(P, z) ZM_LOAD_Q(P, z, )
 #define ZM_STORE(P, z, VS, BSL)                                              \
   {                                                                          \
     const int zz_ = (z);                                                     \
@@ -744,8 +745,14 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
   ZM_STORE(A, z0 - 1, (z0 - 1 + 10) % 5, (z0 - 1 + 8) & 3);
   ZM_LOAD(A, z0);
   ZM_STORE(A, z0, (z0 + 10) % 5, (z0 + 8) & 3);
-  ZM_LOAD(A, z0 + 1);   // planes z0+1, z0+3, ... travel in A; z0+2, z0+4, ... in B
-  ZM_LOAD(B, z0 + 2);
+  // planes z0+1, z0+3, ... travel in A; z0+2, z0+4, ... in B. These two
+  // planes are read through volatile pointers so that they are issued in
+  // this order, every A load ahead of every B load, as in the loop: if the
+  // compiler moved an A load after the B loads here, the wait counts at the
+  // loop head would have to assume an A load was issued last and would drain
+  // every load in flight at every other step.
+  ZM_LOAD_Q(A, z0 + 1, volatile);
+  ZM_LOAD_Q(B, z0 + 2, volatile);
   __syncthreads();
   // an odd step count ends with one extra step whose black plane lies
   // outside [z0, z1): it only stages and recomputes LDS values
@@ -756,6 +763,7 @@ __global__ void __launch_bounds__(TX * TY / 2) k_rb_zm3(const uint8_t* __restric
 #undef ZM_STEP
 #undef ZM_STORE
 #undef ZM_LOAD
+#undef ZM_LOAD_Q
   // second-phase unknowns are not touched by this sweep: copy them through
   const int64_t N = sxy * nz;
   for (int64_t q = (int64_t)blockIdx.x * NT + tid; q < nsec; q += nblocks * NT) xout[N + q] = ZIN ? T(0) : xin[N + q];

@@ -29,6 +29,7 @@
 #include "block_engine.hpp"
 #include "batch_wide.hpp"
 #include "kernels.hpp"
+#include "zq_kernels.hpp"
 #include "sdf_kernels.hpp"
 #include "adv_kernels.hpp"
 #include "amr_kernels.hpp"
@@ -496,9 +497,11 @@ static bool fused_ok(const DevLevel& l) {
 
 // z-marching sweep configurations (tile width x height x planes per block);
 // the setup autotuner picks one per level
-constexpr int kZMConfigs = 11;   // 7..9: wide-fetch versions of 1, 4, 6 (x extent a multiple of 4);
-                                  // 10: 64x16 over 8 planes (enough blocks on mid-size levels)
-static bool zm_cfg_ok(const DevLevel& l, int c) { return c < 7 || c > 9 || l.n[0] % 4 == 0; }
+constexpr int kZMConfigs = 14;   // 7..9: wide-fetch versions of 1, 4, 6 (x extent a multiple of 4);
+                                  // 10: 64x16 over 8 planes (enough blocks on mid-size levels);
+                                  // 11..13: quad form (k_rb_zq3) 128x8 over 16, 64x16 over 16, 128x8
+                                  // over 32 (x extent a multiple of 4)
+static bool zm_cfg_ok(const DevLevel& l, int c) { return (c < 7 || c == 10) || l.n[0] % 4 == 0; }
 
 // zin: x is zero on entry, so the sweep need not read it (not timed by the
 // in-solve hook: it moves fewer bytes than a full sweep)
@@ -515,10 +518,32 @@ static void launch_zm_cfg(DevLevel& l, const T* xin, T* xout, const T* b, const 
             b, tp, l.N2);
 }
 
+template <typename T, int TX, int TY, int KZ, int OCC>
+static void launch_zq_cfg(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s,
+                          bool zin) {
+  if (l.n[0] % 4 != 0) throw ArgError("the quad sweep needs an x extent that is a multiple of 4");
+  auto al4 = [](const void* p, size_t es) { return (uintptr_t)p % (4 * es) == 0; };
+  if (!al4(xout, sizeof(T)) || !al4(b, sizeof(T)) || !al4(l.tag.p, 1) || (!zin && !al4(xin, sizeof(T)))) {
+    // vectors not aligned to whole quads: the same sweep by the pair form
+    launch_zm_cfg<T, 64, 16, 32>(l, xin, xout, b, tp, s, zin);
+    return;
+  }
+  const int64_t nb = (int64_t)((l.n[0] + TX - 1) / TX) * ((l.n[1] + TY - 1) / TY) * ((l.n[2] + KZ - 1) / KZ);
+  if (zin)
+    hipLaunchKernelGGL((k_rb_zq3<T, TX, TY, KZ, OCC, true>), dim3((unsigned)nb), dim3(TX * TY / 4), 0, s, l.tag.p, xin,
+                       xout, b, tp, l.N2);
+  else
+    KLAUNCH(l.kt, (k_rb_zq3<T, TX, TY, KZ, OCC>), dim3((unsigned)nb), dim3(TX * TY / 4), 0, s, l.tag.p, xin, xout, b,
+            tp, l.N2);
+}
+
 template <typename T>
 static void launch_zm(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s,
                       bool zin = false) {
   switch (l.zmcfg) {
+    case 11: launch_zq_cfg<T, 128, 8, 16, 2>(l, xin, xout, b, tp, s, zin); break;
+    case 12: launch_zq_cfg<T, 64, 16, 16, 2>(l, xin, xout, b, tp, s, zin); break;
+    case 13: launch_zq_cfg<T, 128, 8, 32, 2>(l, xin, xout, b, tp, s, zin); break;
     case 1: launch_zm_cfg<T, 64, 16, 32>(l, xin, xout, b, tp, s, zin); break;
     case 2: launch_zm_cfg<T, 32, 16, 32>(l, xin, xout, b, tp, s, zin); break;
     case 3: launch_zm_cfg<T, 64, 8, 16>(l, xin, xout, b, tp, s, zin); break;

@@ -526,10 +526,21 @@ class Problem:
             pass
 
 
-# z-marching smoother tiles (x, y, planes, wide fetch), in the library's configuration order
+# z-marching smoother tiles (x, y, planes, wide fetch), in the library's configuration order;
+# the configurations in ZM_QUAD run the quad form (four cells of a row per
+# thread), with the occupancy bound of their launch
 ZM_TILES = [(64, 8, 32, False), (64, 16, 32, False), (32, 16, 32, False), (64, 8, 16, False), (128, 8, 32, False),
             (32, 8, 32, False), (32, 32, 32, False), (64, 16, 32, True), (128, 8, 32, True), (32, 32, 32, True),
-            (64, 16, 8, False)]
+            (64, 16, 8, False), (128, 8, 16, False), (64, 16, 16, False), (128, 8, 32, False)]
+ZM_QUAD = {11: 2, 12: 2, 13: 2}
+
+
+def zm_kernel(t, c, zin=False):
+    """Kernel name of z-marching configuration c for element type t."""
+    tx, ty, kz, wide = ZM_TILES[c]
+    if c in ZM_QUAD:
+        return f"k_rb_zq3<{t},{tx},{ty},{kz},{ZM_QUAD[c]},{str(zin).lower()}>"
+    return f"k_rb_zm3<{t},{tx},{ty},{kz},{str(wide).lower()},{str(zin).lower()}>"
 OOP_VARIANT = 2 + len(ZM_TILES)      # tuning code of the one-launch colour phases
 SMOOTH_OOP = 3 + len(ZM_TILES)       # ebmg_smooth variant of the one-launch colour phases
 SMOOTH_OOP_ROWS = 4 + len(ZM_TILES)  # the same with each phase's explicit rows relaxed

@@ -166,7 +166,7 @@ def _source_sha():
     """Hash of the kernel sources: counter figures are void once it changes."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "block_engine.hpp"):
+    for f in ("kernels.hpp", "zq_kernels.hpp", "block_engine.hpp"):
         with open(os.path.join(ROOT, "paper_1809_03745_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -402,7 +402,7 @@ def pmc_inst_summary(csvs, command):
                 k = (_kname(r["Kernel_Name"]), int(r["Grid_Size"]))
                 d[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
                 meta[k] = (r["Workgroup_Size"], r["LDS_Block_Size"], r["VGPR_Count"], r["SGPR_Count"])
-    names = sorted({k[0] for k in d if k[0].startswith(("k_rb_zm3", "k_rb<", "k_rb_tile3", "k_resid_zp3"))})
+    names = sorted({k[0] for k in d if k[0].startswith(("k_rb_zm3", "k_rb_zq3", "k_rb<", "k_rb_tile3", "k_resid_zp3"))})
     lines = [f"# Instruction counters of the finest-level sweep kernels, 256^3 pin-plane (rocprofv3 --pmc)\n",
              "Commands (from the repository root on the GPU host; one counter pass per run):\n",
              f"```\n{command}\n```\n",

@@ -367,8 +367,8 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
  * 64x8 over 32, 64x16 over 32, 32x16 over 32, 64x8 over 16, 128x8 over 32,
  * 32x8 over 32, 32x32 over 32; 7..9: 64x16, 128x8 and 32x32 over 32 with
  * 16-byte fetches, x extent a multiple of 4; 10: 64x16 over 8; 11..13: the
- * quad form, each thread four cells of a row, 128x8 over 16, 64x16 over 16
- * and 128x8 over 32, x extent a multiple of 4; 3D), 17 one-launch colour
+ * quad form, each thread four cells of a row, 64x16, 128x16 and 128x8
+ * over 32, x extent a multiple of 4; 3D), 17 one-launch colour
  * phases out of place. Every variant performs exactly the red half-sweep
  * followed by
  * the black one with the same arithmetic, so their results agree bitwise.

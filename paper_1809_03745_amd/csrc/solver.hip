@@ -499,8 +499,8 @@ static bool fused_ok(const DevLevel& l) {
 // the setup autotuner picks one per level
 constexpr int kZMConfigs = 14;   // 7..9: wide-fetch versions of 1, 4, 6 (x extent a multiple of 4);
                                   // 10: 64x16 over 8 planes (enough blocks on mid-size levels);
-                                  // 11..13: quad form (k_rb_zq3) 128x8 over 16, 64x16 over 16, 128x8
-                                  // over 32 (x extent a multiple of 4)
+                                  // 11..13: quad form (k_rb_zq3) 64x16, 128x16 and 128x8 over 32
+                                  // (x extent a multiple of 4)
 static bool zm_cfg_ok(const DevLevel& l, int c) { return (c < 7 || c == 10) || l.n[0] % 4 == 0; }
 
 // zin: x is zero on entry, so the sweep need not read it (not timed by the
@@ -523,8 +523,10 @@ static void launch_zq_cfg(DevLevel& l, const T* xin, T* xout, const T* b, const 
                           bool zin) {
   if (l.n[0] % 4 != 0) throw ArgError("the quad sweep needs an x extent that is a multiple of 4");
   auto al4 = [](const void* p, size_t es) { return (uintptr_t)p % (4 * es) == 0; };
-  if (!al4(xout, sizeof(T)) || !al4(b, sizeof(T)) || !al4(l.tag.p, 1) || (!zin && !al4(xin, sizeof(T)))) {
-    // vectors not aligned to whole quads: the same sweep by the pair form
+  if (!al4(xout, sizeof(T)) || !al4(b, sizeof(T)) || !al4(l.tag.p, 1) || (!zin && !al4(xin, sizeof(T))) ||
+      (l.N + l.N2) * (int64_t)sizeof(T) >= ((int64_t)1 << 31)) {
+    // vectors not aligned to whole quads, or too large for the kernel's
+    // 32-bit byte offsets: the same sweep by the pair form
     launch_zm_cfg<T, 64, 16, 32>(l, xin, xout, b, tp, s, zin);
     return;
   }
@@ -541,8 +543,8 @@ template <typename T>
 static void launch_zm(DevLevel& l, const T* xin, T* xout, const T* b, const Tmpl<T>& tp, hipStream_t s,
                       bool zin = false) {
   switch (l.zmcfg) {
-    case 11: launch_zq_cfg<T, 128, 8, 16, 2>(l, xin, xout, b, tp, s, zin); break;
-    case 12: launch_zq_cfg<T, 64, 16, 16, 2>(l, xin, xout, b, tp, s, zin); break;
+    case 11: launch_zq_cfg<T, 64, 16, 32, 2>(l, xin, xout, b, tp, s, zin); break;
+    case 12: launch_zq_cfg<T, 128, 16, 32, 2>(l, xin, xout, b, tp, s, zin); break;
     case 13: launch_zq_cfg<T, 128, 8, 32, 2>(l, xin, xout, b, tp, s, zin); break;
     case 1: launch_zm_cfg<T, 64, 16, 32>(l, xin, xout, b, tp, s, zin); break;
     case 2: launch_zm_cfg<T, 32, 16, 32>(l, xin, xout, b, tp, s, zin); break;

@@ -21,12 +21,13 @@
 //     threads: the ring, walked around the tile, alternates colours, so
 //     each of these threads owns two consecutive ring cells of which exactly
 //     one is red in a plane (the same one for every thread).
-// Per plane step k: stage the x chunks of plane k + 2 (loaded two steps
-// earlier) and request those of plane k + 4 and the b / tag words of plane
-// k + 2; red update of plane k (quads and ring); barrier; black update of
-// plane k - 1 and its store; barrier. b / tag words live for four steps (two
-// in flight, one for the red and one for the black update), so the march is
-// unrolled by four steps with one register set per step.
+// Per plane step k: stage the x chunks of plane k + 3 (loaded two steps
+// earlier) and request those of plane k + 5; red update of plane k + 1
+// (quads and ring) and black update of plane k - 1 with its store, in one
+// phase (they touch disjoint planes of a six-plane LDS ring); request the
+// b / tag words of plane k + 1 (its black update) and k + 3 (its red
+// update); one barrier. Every register set in flight alternates between
+// two copies (A, B), loaded two steps ahead of its use.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -96,7 +97,7 @@ __global__ void __launch_bounds__(TX * TY / 4, OCC) k_rb_zq3(const uint8_t* __re
   static_assert(TX % 4 == 0 && 64 % QX == 0 && NT % 64 == 0, "the quads of a tile row fill whole wavefronts");
   static_assert(TY % (2 * RPW) == 0, "a wavefront takes tile rows of one parity");
   static_assert(NRING <= NT, "one ring cell pair per thread at most");
-  __shared__ Q V[5][NQ];
+  __shared__ Q V[6][NQ];
   __shared__ T TC[2][8];
   const int nx = tp.n[0], ny = tp.n[1], nz = tp.n[2];
   const int bx = (nx + TX - 1) / TX, by = (ny + TY - 1) / TY;
@@ -122,11 +123,15 @@ __global__ void __launch_bounds__(TX * TY / 4, OCC) k_rb_zq3(const uint8_t* __re
   const int qoff = qin ? gx0 + nx * gy : 0;
   const int qi = (ry + 2) * PQ + m + 1;
   const int hrow = __builtin_amdgcn_readfirstlane((y0 + ry) & 1);
+  // reciprocal in-plane diagonals per phase and cell; cells 1 and 2 of a
+  // quad are never on an x face, so they share one value
   T rq[2][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    rq[0][i] = zm_inplane_rdg<T>(gx0 + i, gy, nx, ny, TC[0]);
-    rq[1][i] = zm_inplane_rdg<T>(gx0 + i, gy, nx, ny, TC[1]);
+  for (int p = 0; p < 2; ++p) {
+    rq[p][0] = zm_inplane_rdg<T>(gx0, gy, nx, ny, TC[p]);
+    rq[p][1] = zm_inplane_rdg<T>(gx0 + 1, gy, nx, ny, TC[p]);
+    rq[p][2] = rq[p][1];
+    rq[p][3] = zm_inplane_rdg<T>(gx0 + 3, gy, nx, ny, TC[p]);
   }
 
   // staged chunks: LDS quad q of a plane holds the four cells of row
@@ -152,35 +157,51 @@ __global__ void __launch_bounds__(TX * TY / 4, OCC) k_rb_zq3(const uint8_t* __re
   const int rgxa = x0 + rca, rgya = y0 + rra, rgxb = x0 + rcb, rgyb = y0 + rrb;
   const bool ina = rg && rgxa >= 0 && rgxa < nx && rgya >= 0 && rgya < ny;
   const bool inb = rg && rgxb >= 0 && rgxb < nx && rgyb >= 0 && rgyb < ny;
+  // (on z faces the ring cell's position is recovered from its LDS index)
   const int rla = (rra + 2) * PW + rca + 4, rlb = (rrb + 2) * PW + rcb + 4;
   const int roffa = ina ? rgxa + nx * rgya : 0, roffb = inb ? rgxb + nx * rgyb : 0;
   const T ra0 = zm_inplane_rdg<T>(rgxa, rgya, nx, ny, TC[0]), ra1 = zm_inplane_rdg<T>(rgxa, rgya, nx, ny, TC[1]);
   const T rb0 = zm_inplane_rdg<T>(rgxb, rgyb, nx, ny, TC[0]), rb1 = zm_inplane_rdg<T>(rgxb, rgyb, nx, ny, TC[1]);
   const int rpar = (x0 + y0) & 1;
 
-  // registers in flight: x chunks of two planes (A, B), and the b / tag
-  // words of four planes (sets 0..3)
+  // registers in flight, two sets each (A, B), all loaded two steps ahead
+  // of their use: x chunks; b / tag words of the plane of a red update (R)
+  // and of the plane of a black update (K: the same words again, read a
+  // second time, from the cache, so that no register set is copied)
   Q XA[UC], XB[UC];
-  Q BQ0, BQ1, BQ2, BQ3;
-  uint32_t TQ0, TQ1, TQ2, TQ3;
-  T RB0, RB1, RB2, RB3;
-  uint8_t RT0, RT1, RT2, RT3;
+  Q BRA, BRB, BKA, BKB;
+  uint32_t TRA, TRB, TKA, TKB;   // the quad's four tags (raw words: decoded where used, so
+                                 // that no load is waited for before its step)
+  T RBA, RBB;
+  uint32_t RTA, RTB;             // the ring cell's tag
 
+  // loads address the arrays by 32-bit offsets from their base (the
+  // caller keeps every array below 2^31 bytes): plane offset (uniform) plus
+  // in-plane offset (per lane)
+#define ZQ_AT(ptr, TY2, QV, eoff) (*(QV const TY2*)((const char*)(ptr) + (uint32_t)(eoff)))
 #define ZQ_LOADX(P, z, QV)                                                              \
   if constexpr (!ZIN) {                                                                 \
     const int zz_ = (z);                                                                \
-    const int64_t zoff_ = sxy * (zz_ >= 0 && zz_ < nz ? zz_ : 0);                      \
-    _Pragma("unroll") for (int u = 0; u < UC; ++u) P[u] = *(QV const Q*)(xin + zoff_ + coff[u]); \
+    const uint32_t zo_ = (uint32_t)sxy * (uint32_t)(zz_ >= 0 && zz_ < nz ? zz_ : 0);   \
+    _Pragma("unroll") for (int u = 0; u < UC; ++u)                                      \
+      P[u] = ZQ_AT(xin, Q, QV, (zo_ + (uint32_t)coff[u]) * (uint32_t)sizeof(T));        \
   }
 #define ZQ_LOADBT(S, z, QV)                                                             \
   {                                                                                     \
     const int zz_ = (z);                                                                \
-    const int64_t zoff_ = sxy * (zz_ >= 0 && zz_ < nz ? zz_ : 0);                      \
-    BQ##S = *(QV const Q*)(b + zoff_ + qoff);                                           \
-    TQ##S = *(QV const uint32_t*)(tag + zoff_ + qoff);                                  \
-    const int ro_ = ((rpar + zz_) & 1) == 0 ? roffa : roffb;                            \
-    RB##S = ((QV const T*)b)[zoff_ + ro_];                                              \
-    RT##S = ((QV const uint8_t*)tag)[zoff_ + ro_];                                      \
+    const uint32_t zo_ = (uint32_t)sxy * (uint32_t)(zz_ >= 0 && zz_ < nz ? zz_ : 0);   \
+    BR##S = ZQ_AT(b, Q, QV, (zo_ + (uint32_t)qoff) * (uint32_t)sizeof(T));              \
+    TR##S = ZQ_AT(tag, uint32_t, QV, zo_ + (uint32_t)qoff);                             \
+    const uint32_t ro_ = zo_ + (uint32_t)(((rpar + zz_) & 1) == 0 ? roffa : roffb);     \
+    RB##S = ZQ_AT(b, T, QV, ro_ * (uint32_t)sizeof(T));                                 \
+    RT##S = ZQ_AT(tag, uint8_t, QV, ro_);                                               \
+  }
+#define ZQ_LOADK(S, z)                                                                  \
+  {                                                                                     \
+    const int zz_ = (z);                                                                \
+    const uint32_t zo_ = (uint32_t)sxy * (uint32_t)(zz_ >= 0 && zz_ < nz ? zz_ : 0);   \
+    BK##S = ZQ_AT(b, Q, , (zo_ + (uint32_t)qoff) * (uint32_t)sizeof(T));                \
+    TK##S = ZQ_AT(tag, uint32_t, , zo_ + (uint32_t)qoff);                               \
   }
 #define ZQ_STORE(P, z, VS)                                                              \
   {                                                                                     \
@@ -195,121 +216,117 @@ __global__ void __launch_bounds__(TX * TY / 4, OCC) k_rb_zq3(const uint8_t* __re
       }                                                                                 \
     }                                                                                   \
   }
-  // red update of plane k (quad cells and the ring's red cell) with the b /
-  // tag words of set SR; black update of plane k - 1 with set SB and its
-  // store; staging of plane k + 2 from P, loads of plane k + 4 into P and of
-  // the b / tag words of plane k + 2 into set SL
-#define ZQ_STEP(P, SR, SB, SL, kk)                                                      \
+  // Step k: stage plane k + 3 (x chunks of X##P, loaded two steps earlier)
+  // into the slot of plane k - 3 and request plane k + 5; red update of
+  // plane k + 1 (reads planes k .. k + 2, writes the red cells of plane
+  // k + 1) and black update of plane k - 1 (reads planes k - 2 .. k, stores
+  // plane k - 1) in the same phase: they touch disjoint planes, so one
+  // barrier per step suffices. Both updates are computed every step; their
+  // LDS write and store are skipped where the plane is not this block's.
+#define ZQ_STEP(P, kk)                                                                  \
   {                                                                                     \
     const int k = (kk);                                                                 \
-    ZQ_STORE(P, k + 2, sVp2);                                                           \
-    ZQ_LOADX(P, min(k + 4, z1 + 1), );                                                  \
-    ZQ_LOADBT(SL, min(k + 2, z1 + 1), );                                                \
-    if (k >= 0 && k < nz) {                                                             \
-      const bool zint = k > 0 && k < nz - 1;                                            \
-      const Q* vm = V[sVm1];                                                            \
-      Q* vc = V[sV0];                                                                   \
-      const Q* vp = V[sVp1];                                                            \
-      const int h = (hrow + k) & 1;                                                     \
-      T c[4], s[4], n[4], d[4], u[4], bq[4];                                            \
-      const Q cq = vc[qi], sq = vc[qi - PQ], nq = vc[qi + PQ], dq = vm[qi], uq = vp[qi]; \
-      _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                   \
-        c[i] = cq[i]; s[i] = sq[i]; n[i] = nq[i]; d[i] = dq[i]; u[i] = uq[i];           \
-        bq[i] = BQ##SR[i];                                                              \
-      }                                                                                 \
-      const T* vcs = (const T*)vc;                                                      \
-      if (h == 0)                                                                       \
-        zq_pair<T, 0>(c, s, n, d, u, vcs[4 * qi - 1], T(0), TQ##SR, bq, rq, TC, zint, gx0, gy, k, nx, ny, nz); \
-      else                                                                              \
-        zq_pair<T, 1>(c, s, n, d, u, T(0), vcs[4 * qi + 4], TQ##SR, bq, rq, TC, zint, gx0, gy, k, nx, ny, nz); \
-      if (rg) { /* the ring's red cell */                                               \
-        const bool sa = ((rpar + k) & 1) == 0;                                          \
-        const int l = sa ? rla : rlb;                                                   \
-        const int cls = (int)(RT##SR & 3);                                              \
-        const int p = cls & 1;                                                          \
-        T* vf = (T*)vc;                                                                 \
-        const T* vmf = (const T*)vm;                                                    \
-        const T* vpf = (const T*)vp;                                                    \
-        T v;                                                                            \
-        if (zint) {                                                                     \
-          const T r = sa ? (p ? ra1 : ra0) : (p ? rb1 : rb0);                           \
-          v = zv_inner<T>(vf[l - 1], vf[l + 1], vf[l - PW], vf[l + PW], vmf[l], vpf[l], TC[p][0], RB##SR, r); \
-        } else {                                                                        \
-          v = zv_general<T>(vf[l - 1], vf[l + 1], vf[l - PW], vf[l + PW], vmf[l], vpf[l], sa ? rgxa : rgxb, \
-                            sa ? rgya : rgyb, k, nx, ny, nz, TC[p], RB##SR);            \
-        }                                                                               \
-        if ((sa ? ina : inb) && cls <= 1) vf[l] = v;                                    \
-      }                                                                                 \
-      if (qin) vc[qi] = Q{c[0], c[1], c[2], c[3]};                                      \
+    ZQ_STORE(X##P, k + 3, sP3);                                                         \
+    ZQ_LOADX(X##P, min(k + 5, z1 + 1), );                                               \
+    const int kr = k + 1, kb = k - 1;                                                   \
+    const bool zr = kr > 0 && kr < nz - 1, zb = kb > 0 && kb < nz - 1;                  \
+    /* every LDS read of the step first (one latency for both updates) */               \
+    Q* vr = V[sP1];                                                                     \
+    const Q *vrm = V[sP0], *vrp = V[sP2], *vb = V[sM1], *vbm = V[sM2], *vbp = V[sP0];   \
+    const Q rc = vr[qi], rs = vr[qi - PQ], rn = vr[qi + PQ], rd = vrm[qi], ru = vrp[qi]; \
+    const Q bc = vb[qi], bs = vb[qi - PQ], bn = vb[qi + PQ], bd = vbm[qi], bu = vbp[qi]; \
+    const T rl = ((const T*)vr)[4 * qi - 1], rr = ((const T*)vr)[4 * qi + 4];          \
+    const T bl = ((const T*)vb)[4 * qi - 1], br = ((const T*)vb)[4 * qi + 4];          \
+    /* the ring's red cell (computed by every thread, written by ring threads) */      \
+    const bool sa = ((rpar + kr) & 1) == 0;                                             \
+    const int l = rg ? (sa ? rla : rlb) : 4 * qi;                                       \
+    T* vrf = (T*)vr;                                                                    \
+    const T gw = vrf[l - 1], ge = vrf[l + 1], gs = vrf[l - PW], gn = vrf[l + PW];       \
+    const T gd = ((const T*)vrm)[l], gu = ((const T*)vrp)[l];                           \
+    T c[4], s[4], n[4], d[4], u[4], bq[4], e[4], f[4], g[4], m[4], o[4], bk[4];         \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                     \
+      c[i] = rc[i]; s[i] = rs[i]; n[i] = rn[i]; d[i] = rd[i]; u[i] = ru[i];             \
+      bq[i] = BR##P[i];                                                                 \
+      e[i] = bc[i]; f[i] = bs[i]; g[i] = bn[i]; m[i] = bd[i]; o[i] = bu[i];             \
+      bk[i] = BK##P[i];                                                                 \
     }                                                                                   \
-    __syncthreads();                                                                    \
-    const int kb = k - 1;                                                               \
-    if (kb >= z0 && kb < z1) { /* black update of plane k-1, and its store */          \
-      const bool zint = kb > 0 && kb < nz - 1;                                          \
-      const Q* vm = V[sVm2];                                                            \
-      const Q* vc = V[sVm1];                                                            \
-      const Q* vp = V[sV0];                                                             \
-      const int h = (hrow + k) & 1;                                                     \
-      T c[4], s[4], n[4], d[4], u[4], bq[4];                                            \
-      const Q cq = vc[qi], sq = vc[qi - PQ], nq = vc[qi + PQ], dq = vm[qi], uq = vp[qi]; \
-      _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                   \
-        c[i] = cq[i]; s[i] = sq[i]; n[i] = nq[i]; d[i] = dq[i]; u[i] = uq[i];           \
-        bq[i] = BQ##SB[i];                                                              \
-      }                                                                                 \
-      const T* vcs = (const T*)vc;                                                      \
-      if (h == 0)                                                                       \
-        zq_pair<T, 0>(c, s, n, d, u, vcs[4 * qi - 1], T(0), TQ##SB, bq, rq, TC, zint, gx0, gy, kb, nx, ny, nz); \
-      else                                                                              \
-        zq_pair<T, 1>(c, s, n, d, u, T(0), vcs[4 * qi + 4], TQ##SB, bq, rq, TC, zint, gx0, gy, kb, nx, ny, nz); \
-      if (qin) *(Q*)(xout + sxy * kb + qoff) = Q{c[0], c[1], c[2], c[3]};               \
+    /* red cells of plane kr are h, h + 2; black cells of plane kb the others */        \
+    if (((hrow + kr) & 1) == 0) {                                                       \
+      zq_pair<T, 0>(c, s, n, d, u, rl, rr, TR##P, bq, rq, TC, zr, gx0, gy, kr, nx, ny, nz); \
+      zq_pair<T, 1>(e, f, g, m, o, bl, br, TK##P, bk, rq, TC, zb, gx0, gy, kb, nx, ny, nz); \
+    } else {                                                                            \
+      zq_pair<T, 1>(c, s, n, d, u, rl, rr, TR##P, bq, rq, TC, zr, gx0, gy, kr, nx, ny, nz); \
+      zq_pair<T, 0>(e, f, g, m, o, bl, br, TK##P, bk, rq, TC, zb, gx0, gy, kb, nx, ny, nz); \
     }                                                                                   \
+    {                                                                                   \
+      const int cls = (int)(RT##P & 3);                                                 \
+      const int p = cls & 1;                                                            \
+      T v;                                                                              \
+      if (zr) {                                                                         \
+        const T r = sa ? (p ? ra1 : ra0) : (p ? rb1 : rb0);                             \
+        v = zv_inner<T>(gw, ge, gs, gn, gd, gu, TC[p][0], RB##P, r);                    \
+      } else {                                                                          \
+        v = zv_general<T>(gw, ge, gs, gn, gd, gu, x0 + l % PW - 4, y0 + l / PW - 2, kr, nx, ny, nz, TC[p], \
+                          RB##P);                                                       \
+      }                                                                                 \
+      const bool dored = kr >= 0 && kr < nz && kr <= z1;                                \
+      if (dored && (sa ? ina : inb) && cls <= 1) vrf[l] = v;                            \
+      if (dored && qin) vr[qi] = Q{c[0], c[1], c[2], c[3]};                             \
+    }                                                                                   \
+    if (kb >= z0 && kb < z1 && qin)                                                     \
+      *(Q*)((char*)xout + ((uint32_t)sxy * (uint32_t)kb + (uint32_t)qoff) * (uint32_t)sizeof(T)) = \
+          Q{e[0], e[1], e[2], e[3]};                                                    \
+    ZQ_LOADK(P, min(k + 1, z1 + 1));                                                    \
+    ZQ_LOADBT(P, min(k + 3, z1 + 1), );                                                 \
     __syncthreads();                                                                    \
     {                                                                                   \
-      const int t5_ = sVm2;                                                             \
-      sVm2 = sVm1;                                                                      \
-      sVm1 = sV0;                                                                       \
-      sV0 = sVp1;                                                                       \
-      sVp1 = sVp2;                                                                      \
-      sVp2 = t5_;                                                                       \
+      const int t6_ = sM2;                                                              \
+      sM2 = sM1;                                                                        \
+      sM1 = sP0;                                                                        \
+      sP0 = sP1;                                                                        \
+      sP1 = sP2;                                                                        \
+      sP2 = sP3;                                                                        \
+      sP3 = t6_;                                                                        \
     }                                                                                   \
   }
 
-  // LDS ring slots: plane p lives in V[(p + 10) % 5]
-  int sVm2 = (z0 - 3 + 10) % 5, sVm1 = (z0 - 2 + 10) % 5, sV0 = (z0 - 1 + 10) % 5, sVp1 = (z0 + 10) % 5,
-      sVp2 = (z0 + 1 + 10) % 5;
+  // LDS ring of six plane slots: plane p lives in V[(p + 12) % 6]; the
+  // slots of the planes k - 2 .. k + 3 around step k rotate in scalars
+  int sM2 = (z0 - 4 + 12) % 6, sM1 = (z0 - 3 + 12) % 6, sP0 = (z0 - 2 + 12) % 6, sP1 = (z0 - 1 + 12) % 6,
+      sP2 = (z0 + 12) % 6, sP3 = (z0 + 1 + 12) % 6;
   ZQ_LOADX(XA, z0 - 2, );
-  ZQ_STORE(XA, z0 - 2, (z0 - 2 + 10) % 5);
+  ZQ_STORE(XA, z0 - 2, (z0 - 2 + 12) % 6);
   ZQ_LOADX(XA, z0 - 1, );
-  ZQ_STORE(XA, z0 - 1, (z0 - 1 + 10) % 5);
+  ZQ_STORE(XA, z0 - 1, (z0 - 1 + 12) % 6);
   ZQ_LOADX(XA, z0, );
-  ZQ_STORE(XA, z0, (z0 + 10) % 5);
+  ZQ_STORE(XA, z0, (z0 + 12) % 6);
   // the planes in flight at the loop head, requested in the loop's own
-  // order (volatile reads keep it): x of z0+1 and b / tags of z0-1 as a
-  // step of A, then x of z0+2 and b / tags of z0 as a step of B; otherwise
-  // the wait counts at the loop head would drain every load in flight
+  // order (volatile reads keep it): as a step of A, x of z0+1 and the red
+  // words of z0-1; as a step of B, x of z0+2 and the red words of z0;
+  // otherwise the wait counts at the loop head would drain every load in
+  // flight
   ZQ_LOADX(XA, z0 + 1, volatile);
-  ZQ_LOADBT(0, z0 - 1, volatile);
+  ZQ_LOADBT(A, z0 - 1, volatile);
   ZQ_LOADX(XB, z0 + 2, volatile);
-  ZQ_LOADBT(1, z0, volatile);
+  ZQ_LOADBT(B, z0, volatile);
+  BKA = Q(0);   // (black words of planes before z0: computed on, never stored)
+  TKA = 0;
+  BKB = Q(0);
+  TKB = 0;
   __syncthreads();
-  // steps k = z0 - 1 .. z1 (the last one's black plane z1 - 1); step s =
-  // k - z0 + 1 reads b / tags of set s % 4 (red), (s + 3) % 4 (black) and
-  // loads set (s + 2) % 4; x chunks alternate A, B
-  const int kend = z1;
-  int kq = z0 - 1;
-  for (; kq + 3 <= kend; kq += 4) {
-    ZQ_STEP(XA, 0, 3, 2, kq);
-    ZQ_STEP(XB, 1, 0, 3, kq + 1);
-    ZQ_STEP(XA, 2, 1, 0, kq + 2);
-    ZQ_STEP(XB, 3, 2, 1, kq + 3);
+  // steps k = z0 - 2 .. z1: red planes z0 - 1 .. z1, black planes z0 .. z1 - 1
+  int kq = z0 - 2;
+  for (; kq + 1 <= z1; kq += 2) {
+    ZQ_STEP(A, kq);
+    ZQ_STEP(B, kq + 1);
   }
-  if (kq <= kend) ZQ_STEP(XA, 0, 3, 2, kq);
-  if (kq + 1 <= kend) ZQ_STEP(XB, 1, 0, 3, kq + 1);
-  if (kq + 2 <= kend) ZQ_STEP(XA, 2, 1, 0, kq + 2);
+  if (kq <= z1) ZQ_STEP(A, kq);
 #undef ZQ_STEP
 #undef ZQ_STORE
+#undef ZQ_LOADK
 #undef ZQ_LOADBT
 #undef ZQ_LOADX
+#undef ZQ_AT
   // second-phase unknowns are not touched by this sweep: copy them through
   const int64_t N = sxy * nz;
   for (int64_t q = (int64_t)blockIdx.x * NT + tid; q < nsec; q += nblocks * NT) xout[N + q] = ZIN ? T(0) : xin[N + q];

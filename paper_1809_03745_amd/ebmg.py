@@ -531,7 +531,7 @@ class Problem:
 # thread), with the occupancy bound of their launch
 ZM_TILES = [(64, 8, 32, False), (64, 16, 32, False), (32, 16, 32, False), (64, 8, 16, False), (128, 8, 32, False),
             (32, 8, 32, False), (32, 32, 32, False), (64, 16, 32, True), (128, 8, 32, True), (32, 32, 32, True),
-            (64, 16, 8, False), (128, 8, 16, False), (64, 16, 16, False), (128, 8, 32, False)]
+            (64, 16, 8, False), (64, 16, 32, False), (128, 16, 32, False), (128, 8, 32, False)]
 ZM_QUAD = {11: 2, 12: 2, 13: 2}
 
 

@@ -830,6 +830,18 @@ def main():
             "timed_in": f"{t_steps} solves after the timed region (each launch stamped with HIP start/end events)",
             "kernel_ms_back_to_back": round(k_ms_b2b, 5), "alg_bytes_per_launch": int(k_bytes),
             "alg_bytes_unit": f"{3 * (4 if prec == ebmg.MIXED else 8) + 1} B per updated cell ({unit_kind})"}
+    # the same bytes per cell streamed with no stencil (reads x, b and the
+    # tag of every cell, writes one value), back to back like the sweep's
+    # second figure: what the memory system gives this byte mix
+    try:
+        s_ms, s_bytes = P.time_kernel(5, 0, reps=20)
+        roof["stream_reference"] = {
+            "kernel": f"k_stream_ref<{'float' if prec == ebmg.MIXED else 'double'}> (x, b, tag read, one value "
+                      "written per cell, 16-byte accesses, no stencil)",
+            "ms_back_to_back": round(s_ms, 5), "GBps": round(s_bytes / (s_ms * 1e-3) / 1e9, 1),
+            "sweep_back_to_back_over_stream": round(k_ms_b2b / s_ms, 3)}
+    except ebmg.EbmgError:
+        pass
     r_ms_b2b, r_bytes = P.time_kernel(1, 0, reps=20)
     r_ms = r_ms_solve if r_n > 0 else r_ms_b2b
     tuning = {"smoother_variant_per_level": [P.tuning(l)[0] for l in range(P.levels)],

@@ -392,7 +392,10 @@ ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t
  * smoother kernel; 2: a red/black half-sweep; 3: the level's fused
  * red+black sweep; 4: the z-marching fused sweep (3D); ERR_ARG where the
  * level cannot use a fused sweep -- FP32 for mixed-precision
- * problems, else FP64; 1: FP64 residual of level `level`. Smoother bytes are
+ * problems, else FP64; 1: FP64 residual of level `level`; 5: a reference
+ * stream over the level's arrays with the fused sweep's bytes per cell and
+ * no stencil (reads x, b and the tag of every cell, writes one value per
+ * cell; ERR_ARG unless N is a multiple of 4). Smoother bytes are
  * 3 values + 1 tag byte per updated cell, residual bytes 3 FP64 values + 1
  * tag byte per cell. Overwrites the level's work vectors. */
 ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int32_t reps, double* avg_ms,

@@ -3293,7 +3293,38 @@ ebmg_status ebmg_time_kernel(ebmg_problem pb, int32_t which, int32_t level, int3
     double bytes = 0;
     const Shape shh = shape3((L.n[0] + 1) / 2, L.n[1], L.dim == 3 ? L.n[2] : 1);
     const Shape shf = shape3(L.n[0], L.n[1], L.dim == 3 ? L.n[2] : 1);
-    if (which < 0 || which > 4) throw ArgError("unknown kernel id");
+    if (which < 0 || which > 5) throw ArgError("unknown kernel id");
+    if (which == 5) {
+      // reference stream with the fused sweep's bytes per cell over the
+      // level's arrays
+      auto al = [](const void* p, size_t es) { return (uintptr_t)p % (4 * es) == 0; };
+      const bool ok = mixed ? (L.xa32.p && al(L.x32.p, 4) && al(L.xa32.p, 4) && al(L.b32.p, 4))
+                            : (L.xa64.p && al(L.x64.p, 8) && al(L.xa64.p, 8) && al(L.b64.p, 8));
+      if (!ok || L.N % 4 != 0 || !al(L.tag.p, 1)) throw ArgError("the reference stream needs N a multiple of 4");
+      const unsigned g = (unsigned)std::min<int64_t>(8192, (L.N / 4 + 255) / 256);
+      auto go = [&](int r) {
+        if (mixed)
+          hipLaunchKernelGGL((k_stream_ref<float>), dim3(g), dim3(256), 0, s, L.tag.p, (r & 1) ? L.xa32.p : L.x32.p,
+                             L.b32.p, (r & 1) ? L.x32.p : L.xa32.p, L.N);
+        else
+          hipLaunchKernelGGL((k_stream_ref<double>), dim3(g), dim3(256), 0, s, L.tag.p, (r & 1) ? L.xa64.p : L.x64.p,
+                             L.b64.p, (r & 1) ? L.x64.p : L.xa64.p, L.N);
+      };
+      go(0);
+      go(1);
+      HIPCHECK(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) go(r);
+      HIPCHECK(hipEventRecord(e1, s));
+      HIPCHECK(hipEventSynchronize(e1));
+      HIPCHECK(hipGetLastError());
+      float ms = 0;
+      HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      *avg_ms = ms / reps;
+      if (alg_bytes) *alg_bytes = (double)L.N * (3.0 * (mixed ? 4 : 8) + 1.0);
+      return EBMG_OK;
+    }
     if (which >= 3 && (mixed ? !L.xa32.p : !L.xa64.p)) throw ArgError("this level has no fused sweep");
     if (which == 4 && L.dim != 3) throw ArgError("the z-marching sweep is 3D only");
     const bool fz = (which == 0 && L.fused) || which == 3 || which == 4;

@@ -332,4 +332,23 @@ __global__ void __launch_bounds__(TX * TY / 4, OCC) k_rb_zq3(const uint8_t* __re
   for (int64_t q = (int64_t)blockIdx.x * NT + tid; q < nsec; q += nblocks * NT) xout[N + q] = ZIN ? T(0) : xin[N + q];
 }
 
+// Reference stream for the measurement hook: the fused sweep's bytes per
+// cell with no stencil (reads x, b and the tag of every cell, writes one
+// value per cell), four cells per thread in 16-byte accesses; n a multiple
+// of 4 and the arrays aligned to 4 values (checked by the caller).
+template <typename T>
+__global__ void __launch_bounds__(256) k_stream_ref(const uint8_t* __restrict__ tag, const T* __restrict__ x,
+                                                    const T* __restrict__ b, T* __restrict__ y, int64_t n) {
+  typedef T Q __attribute__((ext_vector_type(4)));
+  const int64_t n4 = n / 4;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (int64_t)gridDim.x * 256) {
+    const Q xv = ((const Q*)x)[i], bv = ((const Q*)b)[i];
+    const uint32_t tv = ((const uint32_t*)tag)[i];
+    Q r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[e] = xv[e] + bv[e] * (T)((tv >> (8 * e)) & 3u);
+    ((Q*)y)[i] = r;
+  }
+}
+
 }  // namespace ebmg

@@ -376,7 +376,11 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
  * included, as the solver smooths levels that use them: in the phase of
  * colour c every template cell of colour c and every explicit row whose
  * cell has colour c (by the parity of i+j+k) is relaxed from the values
- * before the phase.
+ * before the phase. Variant 19 is the level's fused sweep (its chosen
+ * configuration, else the z-marching or tile default) followed in every
+ * sweep by Jacobi passes over the explicit rows of colour group 0 and then
+ * group 1 (group 1 seeing group 0's new values), as the solver smooths
+ * levels that use a fused sweep.
  * x (in/out) and b are DEVICE FP64 arrays of the level's N + N2 unknowns;
  * mixed-precision problems sweep in FP32 (x and b rounded, x widened back).
  * Uses the level's work vectors. ERR_ARG where the level cannot use the

@@ -2428,6 +2428,31 @@ static void release_wide(ebmg_batch_s* Bt) {
 template <typename T>
 static void template_sweeps(DevLevel& l, int variant, int sweeps, T* x, const T* b, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
+  if (variant == 5 + kZMConfigs) {
+    // fused sweeps with the explicit rows' Jacobi passes after each, as
+    // smooth() runs them
+    if (!fused_ok(l)) throw ArgError("this level has no fused sweep");
+    const bool f0 = l.fused;
+    const int v0 = l.fvar, c0 = l.zmcfg;
+    if (!l.fused) {
+      l.fvar = l.dim == 3 ? 1 : 0;
+      l.zmcfg = 1;
+    }
+    l.fused = true;
+    T* cur = x;
+    T* alt = Vec<T>::xa(l);
+    for (int it = 0; it < sweeps; ++it) {
+      launch_fused<T>(l, cur, alt, b, tp, s);
+      std::swap(cur, alt);
+      irr_groups<T>(l, cur, b, s);
+    }
+    l.fused = f0;
+    l.fvar = v0;
+    l.zmcfg = c0;
+    if (cur != x) HIPCHECK(hipMemcpyAsync(x, cur, sizeof(T) * (l.N + l.N2), hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipGetLastError());
+    return;
+  }
   if (variant == 3 + kZMConfigs || variant == 4 + kZMConfigs) {
     // one-launch colour phases; the second form also relaxes each phase's
     // explicit rows (from the values before the phase), as smooth() does on
@@ -3244,7 +3269,7 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
 
 ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t sweeps, double* x,
                         const double* b) {
-  if (!pb || !x || !b || sweeps < 0 || variant < 1 || variant > 4 + kZMConfigs) return EBMG_ERR_ARG;
+  if (!pb || !x || !b || sweeps < 0 || variant < 1 || variant > 5 + kZMConfigs) return EBMG_ERR_ARG;
   if (!pb->on_device) return EBMG_ERR_DEVICE;
   if (level < 0 || level >= (int32_t)pb->dev.lv.size()) return EBMG_ERR_ARG;
   return guard(pb->ctx, [&]() -> ebmg_status {

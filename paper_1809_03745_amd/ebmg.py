@@ -544,6 +544,7 @@ def zm_kernel(t, c, zin=False):
 OOP_VARIANT = 2 + len(ZM_TILES)      # tuning code of the one-launch colour phases
 SMOOTH_OOP = 3 + len(ZM_TILES)       # ebmg_smooth variant of the one-launch colour phases
 SMOOTH_OOP_ROWS = 4 + len(ZM_TILES)  # the same with each phase's explicit rows relaxed
+SMOOTH_FUSED_ROWS = 5 + len(ZM_TILES)  # fused sweeps, each followed by the explicit rows' Jacobi passes
 
 BATCH_LEVELSYNC = 2    # every phase one launch over all boxes (default)
 BATCH_PERSISTENT = 1   # one persistent launch, one workgroup per box

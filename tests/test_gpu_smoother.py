@@ -163,3 +163,66 @@ def test_colour_phases_with_rows(ctx, name):
         checked += 1
     assert checked >= 1
     P.release()
+
+
+def _reference_fused_with_rows(A, tag, n, dim, sec_cell, x, b, sweeps):
+    """Per sweep: red then black half-sweeps over the template cells, then a
+    Jacobi pass over the explicit rows (cut-cell and second-phase unknowns) of
+    red cells, then one over those of black cells (seeing the red rows' new
+    values) -- the smoothing step of levels that use a fused sweep."""
+    A = A.tocsr()
+    N = int(np.prod(n))
+    nd = A.shape[0]
+    cell = np.concatenate([np.arange(N), np.asarray(sec_cell, dtype=np.int64)])
+    i = cell % n[0]
+    j = (cell // n[0]) % n[1]
+    k = cell // (n[0] * n[1]) if dim == 3 else 0
+    colour = (i + j + k) & 1
+    templ = np.concatenate([(tag & 3) <= 1, np.zeros(nd - N, bool)])
+    expl = np.concatenate([(tag & 3) == 2, np.ones(nd - N, bool)])
+    d = A.diagonal()
+    x = x.copy()
+    for _ in range(sweeps):
+        for group in (templ, expl):
+            for c in (0, 1):
+                rows = np.nonzero(group & (colour == c))[0]
+                off = A[rows] @ x - d[rows] * x[rows]
+                x[rows] = (b[rows] - off) / d[rows]
+    return x
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("name", ["pin-plane64", "random-box-ragged", "two-disks256"])
+def test_fused_sweeps_with_rows(ctx, name, prec):
+    """The fused sweep followed by the explicit rows' Jacobi passes, as the
+    solver smooths its large levels, against the numpy definition built from
+    the exported level operator (FP64 to 1e-12; the FP32 sweep to FP32
+    rounding of the same)."""
+    pr = CASES[name]()
+    P = ebmg.Problem(ctx, pr, precision=prec)
+    rng = np.random.default_rng(11)
+    checked = 0
+    for level in range(min(2, P.levels)):
+        n, n2 = P.level_size(level)
+        tag, _, sec = P.level_arrays(level)
+        shape = [max(1, pr.n[d] >> level) for d in range(pr.dim)]
+        if int(np.prod(shape)) != n or not ((tag & 3) == 2).any():
+            continue
+        x0 = rng.normal(size=n + n2)
+        b = rng.normal(size=n + n2)
+        xt = torch.tensor(x0, dtype=torch.float64, device=DEV)
+        bt = torch.tensor(b, dtype=torch.float64, device=DEV)
+        torch.cuda.synchronize()
+        try:
+            P.smooth(level, ebmg.SMOOTH_FUSED_ROWS, 2, xt, bt)
+        except ebmg.EbmgError as e:
+            assert e.status == ebmg.ERR_ARG   # level too small for a fused sweep
+            continue
+        y = xt.cpu().numpy()
+        ref = _reference_fused_with_rows(P.operator(level), tag, shape, pr.dim, sec, x0, b, 2)
+        err = np.abs(y - ref).max() / np.abs(ref).max()
+        _say(name, "precision", prec, "level", level, "rows", int(((tag & 3) == 2).sum()) + n2, "max rel diff", err)
+        assert err <= (1e-12 if prec == 0 else 2e-5)
+        checked += 1
+    assert checked >= 1
+    P.release()

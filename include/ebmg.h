@@ -115,8 +115,11 @@ typedef struct {
   int32_t smoother;         /* 0 autotuned per level at setup, 1 split red and
                                black half-sweeps, 2 fused red+black tile sweep,
                                3 z-marching fused sweep (3D; tile sweep in 2D),
-                               4 fixed rule without timing (fused sweeps where
-                               they apply, one-launch colour phases elsewhere);
+                               4 fixed rule without timing (3D: z-marching
+                               sweep on levels of at least 2^23 cells, quad
+                               form when the x extent is a multiple of 4; 2D:
+                               fused tile sweep where it applies; one-launch
+                               colour phases elsewhere);
                                fused sweeps only on levels of at least 32^3 /
                                256^2 cells                                      */
   int32_t tail;             /* coarse levels: 0 autotuned at setup, 1 always by

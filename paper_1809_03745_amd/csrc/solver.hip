@@ -782,10 +782,16 @@ static void tune_level(DevLevel& l, T* x, T* xa, T* b, int mode, hipStream_t s, 
     return;
   }
   if (mode == 4) {
-    l.fused = fok;
+    // fixed rule (no timing, so the choice never depends on what else runs):
+    // 3D levels of at least 2^23 cells take the z-marching sweep (quad form
+    // where the x extent allows), smaller ones the one-launch colour phases,
+    // which on those sizes beat a z-march with too few blocks; 2D levels take
+    // the fused tile sweep where it applies
+    const bool big3 = l.dim == 3 && l.N >= ((int64_t)1 << 23);
+    l.fused = l.dim == 3 ? (fok && big3) : fok;
     l.fvar = l.dim == 3 ? 1 : 0;
-    l.zmcfg = 1;
-    l.oop = !fok;
+    l.zmcfg = l.n[0] % 4 == 0 ? 13 : 1;
+    l.oop = !l.fused;
     return;
   }
   struct Cand {

@@ -131,10 +131,15 @@ def test_in_solve_kernel_timing_runs_the_same_kernels(ctx):
     assert info2["cycles"] == info["cycles"]
     assert np.array_equal(x, ref)
     # one fused sweep launch per smoothing sweep on the finest level, except
-    # the first of a V-cycle when the z-marching sweep takes it from x = 0
-    zm = 2 <= P.tuning(0)[0] < ebmg.OOP_VARIANT
-    assert n == info["cycles"] * (3 if zm else 4)
-    assert ms > 0 and by == P.N * 13
+    # the first of a V-cycle when the z-marching sweep takes it from x = 0;
+    # two colour-phase launches per sweep where the level uses those
+    var = P.tuning(0)[0]
+    if 2 <= var < ebmg.OOP_VARIANT:
+        assert n == info["cycles"] * 3 and by == P.N * 13
+    else:
+        assert var == ebmg.OOP_VARIANT
+        assert n == info["cycles"] * 8 and by == (P.N + 1) // 2 * 13
+    assert ms > 0
     assert nr >= 1 and msr > 0 and byr == P.N * 25
     with pytest.raises(ebmg.EbmgError):
         P.kernel_timing(0, 0, False)

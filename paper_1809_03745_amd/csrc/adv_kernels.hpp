@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(256) k_adv_special(int nsp, const int64_t* __r
 // D^c. Per face the arithmetic is that of adv_face_flux, up to contraction
 // of the transverse sums.
 template <int TX, int TY, int ZC>
-__global__ void __launch_bounds__(TX * TY, 4) k_adv_zm(const double* __restrict__ n, const uint8_t* __restrict__ cls,
+__global__ void __launch_bounds__(TX * TY, 2) k_adv_zm(const double* __restrict__ n, const uint8_t* __restrict__ cls,
                                                     AdvVel vel, AdvGrid G, int tiles_x, int tiles_y,
                                                     double* __restrict__ F, double* __restrict__ Dc,
                                                     double* __restrict__ nout) {
@@ -260,21 +260,24 @@ __global__ void __launch_bounds__(TX * TY, 4) k_adv_zm(const double* __restrict_
   }
   const unsigned ofx = (unsigned)i + (unsigned)(nx + 1) * j, ofy = (unsigned)i + (unsigned)nx * j;
   const unsigned oc = ofy;   // cells and z faces share the in-plane layout
-  // ring plane k: fetched into registers one step ahead, stored later
+  // ring plane k: fetched into registers one step ahead, stored later. The
+  // class and the density are requested together (a lane outside the box
+  // reads cell 0 and discards it), and the rule "no gas: NaN" is applied
+  // when the plane is stored, so no load waits for another.
   double pv[NR];
   uint8_t pc[NR];
+  uint32_t pin = 0;   // bit q: element q lies in the box and in a plane of it
   auto fetch_plane = [&](int k) {
     const bool kin = k >= 0 && k < nz;
     const double* __restrict__ pn = n + (kin ? (int64_t)sxy * k : 0);
     const uint8_t* __restrict__ pcl = cls + (kin ? (int64_t)sxy * k : 0);
+    pin = 0;
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      pc[q] = 0;
-      pv[q] = __builtin_nan("");
-      if (kin && roff[q] >= 0) {
-        pc[q] = pcl[(unsigned)roff[q]];
-        if (pc[q]) pv[q] = pn[(unsigned)roff[q]];
-      }
+      const unsigned o = roff[q] >= 0 ? (unsigned)roff[q] : 0u;
+      pc[q] = pcl[o];
+      pv[q] = pn[o];
+      pin |= (uint32_t)(kin && roff[q] >= 0) << q;
     }
   };
   auto slot = [](int k) { return (k + 5) % 5; };   // k >= -1
@@ -284,8 +287,9 @@ __global__ void __launch_bounds__(TX * TY, 4) k_adv_zm(const double* __restrict_
     for (int q = 0; q < NR; ++q) {
       const int e = threadIdx.x + q * NT;
       if (e < RP) {
-        rn[sl][e] = pv[q];
-        rc[sl][e] = pc[q];
+        const uint8_t c = ((pin >> q) & 1) ? pc[q] : (uint8_t)0;
+        rn[sl][e] = c ? pv[q] : __builtin_nan("");
+        rc[sl][e] = c;
       }
     }
   };
@@ -312,37 +316,36 @@ __global__ void __launch_bounds__(TX * TY, 4) k_adv_zm(const double* __restrict_
   const unsigned hoz = hin ? (unsigned)hgi + (unsigned)nx * hgj : 0u;
   const unsigned hot = hin ? (isx ? hoz : (unsigned)hgi + (unsigned)(nx + 1) * hgj) : 0u;
   // halo velocities at a plane: the z faces, then the in-plane transverse faces
+  // (requested unconditionally, a plane past the box clamped to the last
+  // one and a lane without a halo cell reading face 0, so that the compiler
+  // counts every load and never waits for more than the value it needs)
   auto fetch_halo = [&](int k, double& z0v, double& z1v, double& t0v, double& t1v) {
-    if (k < nz && hin) {
-      const double* __restrict__ pz = uz + (int64_t)sxy * k;
-      z0v = pz[hoz];
-      z1v = pz[hoz + sxy];
-      if (isx) {
-        const double* __restrict__ py = uy + (int64_t)sfy * k;
-        t0v = py[hot];
-        t1v = py[hot + nx];
-      } else {
-        const double* __restrict__ px = ux + (int64_t)sfx * k;
-        t0v = px[hot];
-        t1v = px[hot + 1];
-      }
-    }
+    const int kk = k < nz ? k : nz - 1;
+    const double* __restrict__ pz = uz + (int64_t)sxy * kk;
+    z0v = pz[hoz];
+    z1v = pz[hoz + sxy];
+    const double* __restrict__ pt = isx ? uy + (int64_t)sfy * kk : ux + (int64_t)sfx * kk;
+    t0v = pt[hot];
+    t1v = pt[hot + (isx ? (unsigned)nx : 1u)];
   };
-  // own column: face velocities of the cell at a plane
+  // own column: face velocities of the cell at a plane (requested the same way)
+  const unsigned ofxo = own ? ofx : 0u, ofyo = own ? ofy : 0u, oco = own ? oc : 0u;
   auto fetch_own = [&](int k, double& xl, double& xh, double& yl, double& yh, double& zh) {
-    if (own && k < nz) {
-      const double* __restrict__ px = ux + (int64_t)sfx * k;
-      const double* __restrict__ py = uy + (int64_t)sfy * k;
-      const double* __restrict__ pz = uz + (int64_t)sxy * (k + 1);
-      xl = px[ofx];
-      xh = px[ofx + 1];
-      yl = py[ofy];
-      yh = py[ofy + nx];
-      zh = pz[oc];
-    }
+    const int kk = k < nz ? k : nz - 1;
+    const double* __restrict__ px = ux + (int64_t)sfx * kk;
+    const double* __restrict__ py = uy + (int64_t)sfy * kk;
+    const double* __restrict__ pz = uz + (int64_t)sxy * (kk + 1);
+    xl = px[ofxo];
+    xh = px[ofxo + 1];
+    yl = py[ofyo];
+    yh = py[ofyo + nx];
+    zh = pz[oco];
   };
+  // inflow densities of the six domain faces, read once
+  const double in0 = G.inflow[0], in1 = G.inflow[1], in2 = G.inflow[2], in3 = G.inflow[3], in5 = G.inflow[5];
   const int eo = (ty + 2) * RX + (tx + 2);
-  double hz0 = 0, hz1 = 0, ht0 = 0, ht1 = 0;
+  double hz0 = 0, hz1 = 0, ht0 = 0, ht1 = 0;       // halo velocities of plane k
+  double gz0 = 0, gz1 = 0, gt0 = 0, gt1 = 0;       // of plane k + 1 (requested a step ahead)
   double cuxl = 0, cuxh = 0, cuyl = 0, cuyh = 0, cuzl = 0, cuzh = 0;   // plane k
   double auxl = 0, auxh = 0, auyl = 0, auyh = 0, auzh = 0;             // plane k + 1
   fetch_plane(z0 - 1);
@@ -356,6 +359,7 @@ __global__ void __launch_bounds__(TX * TY, 4) k_adv_zm(const double* __restrict_
   fetch_plane(z0 + 3);
   fetch_own(z0, cuxl, cuxh, cuyl, cuyh, cuzh);
   fetch_own(z0 + 1, auxl, auxh, auyl, auyh, auzh);
+  fetch_halo(z0, gz0, gz1, gt0, gt1);
   double fzl = 0.0;
   if (own) {
     cuzl = uz[(int64_t)sxy * z0 + oc];
@@ -380,7 +384,11 @@ __global__ void __launch_bounds__(TX * TY, 4) k_adv_zm(const double* __restrict_
     const int pb = k & 1;
     if (k + 3 <= z1 + 1) store_plane(k + 3);
     if (k + 4 <= z1 + 1) fetch_plane(k + 4);
-    fetch_halo(k, hz0, hz1, ht0, ht1);
+    hz0 = gz0;
+    hz1 = gz1;
+    ht0 = gt0;
+    ht1 = gt1;
+    fetch_halo(k + 1, gz0, gz1, gt0, gt1);
     const int sk = slot(k);
     // the own cell at plane k + 1
     double nn = 0, nsx = 0, nsy = 0, nsz = 0;
@@ -420,14 +428,14 @@ __global__ void __launch_bounds__(TX * TY, 4) k_adv_zm(const double* __restrict_
       // x faces i (low) and i + 1 (high); region column c <-> cell i0 - 1 + c
       auto xflux = [&](int f, double u) {
         const bool up = u >= 0.0;
-        if (up ? f == 0 : f == nx) return u * G.inflow[up ? 0 : 1];
+        if (up ? f == 0 : f == nx) return u * (up ? in0 : in1);
         const int col = f - i0 + (up ? 0 : 1);
         if (!rc[sk][rrow + col + 1]) return 0.0;
         return u * (bx[pb][ty][col] + ((up ? 0.5 : -0.5) - u * c2) * sxs[pb][ty][col]);
       };
       auto yflux = [&](int f, double u) {
         const bool up = u >= 0.0;
-        if (up ? f == 0 : f == ny) return u * G.inflow[up ? 2 : 3];
+        if (up ? f == 0 : f == ny) return u * (up ? in2 : in3);
         const int row = f - j0 + (up ? 0 : 1);
         if (!rc[sk][(row + 1) * RX + tx + 2]) return 0.0;
         return u * (by[pb][row][tx] + ((up ? 0.5 : -0.5) - u * c2) * sys[pb][row][tx]);
@@ -440,7 +448,7 @@ __global__ void __launch_bounds__(TX * TY, 4) k_adv_zm(const double* __restrict_
         const double u = cuzh;
         const bool up = u >= 0.0;
         if (!up && k + 1 == nz) {
-          fzh = u * G.inflow[5];
+          fzh = u * in5;
         } else if (up) {
           fzh = cg ? u * ((cn - c1 * (cvx * csx + cvy * csy)) + (0.5 - u * c2) * csz) : 0.0;
         } else {

@@ -391,6 +391,20 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
 ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t sweeps, double* x,
                         const double* b);
 
+/* Paper: Multigrid solver (restriction of the residual to the coarser
+ * level). The V-cycle's residual r = b - A x of level `level` restricted
+ * into the right-hand side of level `level` + 1, as a V-cycle forms it
+ * (simple coarse cells: the mean of their 2^D children's residuals;
+ * non-simple coarse unknowns: their child lists; covered coarse cells: 0).
+ * form 0: the solver's own kernels; 1: the fused z-marching kernel in its
+ * pair form; 2: separate residual and restriction kernels; all forms agree
+ * bitwise (ERR_ARG where a form does not apply to the level). x, b: DEVICE
+ * FP64 arrays of the level's N + N2 unknowns; bc: DEVICE FP64 array of the
+ * coarse level's N + N2 entries (output). Mixed-precision problems compute
+ * in FP32 (x and b rounded, bc widened). Uses the levels' work vectors. */
+ebmg_status ebmg_restrict_residual(ebmg_problem pb, int32_t level, int32_t form, const double* x, const double* b,
+                                   double* bc);
+
 /* Measurement hook (no paper passage; the kernels are the relaxation and
  * residual of the Multigrid solver subsection): launch one kernel `reps`
  * times on the context stream

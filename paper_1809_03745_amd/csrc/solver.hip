@@ -1391,25 +1391,38 @@ static void restrict_to(DevLevel& f, DevLevel& c, const T* rf, T* bc, T* xc, hip
 // coarse unknowns, whose lists are restricted next, with the clear);
 // elsewhere r is formed and restricted as separate steps. The same values
 // either way.
+// form (measurement hook only): 0 the solver's choice, 1 the fused pair
+// kernel, 2 separate residual and restriction kernels (ArgError where a
+// form does not apply)
 template <typename T>
-static void residual_restrict(DevLevel& f, DevLevel& c, const T* x, const T* b, hipStream_t s) {
+static void residual_restrict(DevLevel& f, DevLevel& c, const T* x, const T* b, hipStream_t s, int form = 0) {
   T* r = Vec<T>::r(f);
   const bool fuse = f.dim == 3 && f.N >= kResidZMMin && f.n[0] % 2 == 0 && f.n[1] % 2 == 0 && f.n[2] % 2 == 0 &&
                     c.n[0] * 2 == f.n[0] && c.n[1] * 2 == f.n[1] && c.n[2] * 2 == f.n[2];
-  if (!fuse) {
+  if (form == 1 && !fuse) throw ArgError("this level has no fused residual restriction");
+  if (!fuse || form == 2) {
     residual<T, 0>(f, x, b, r, s);
     restrict_to<T>(f, c, r, Vec<T>::b(c), Vec<T>::x(c), s);
     return;
   }
   residual_rows<T, 0>(f, x, b, r, s);   // the explicit rows' r, read by the fused kernel
+  // quad form where x extents and alignment allow (the same values)
+  auto al4 = [](const void* p, size_t es) { return (uintptr_t)p % (4 * es) == 0; };
+  const bool quad = form == 0 && f.n[0] % 4 == 0 && al4(x, sizeof(T)) && al4(b, sizeof(T)) && al4(r, sizeof(T)) &&
+                    al4(f.tag.p, 1) && ((uintptr_t)c.tag.p % 2) == 0;
   // planes per thread: kRRZ, halved (staying even) until the grid has 2048
   // workgroups, eight per CU
-  const int64_t ncol = (int64_t)((f.n[0] + kRRX - 1) / kRRX) * ((f.n[1] + 2 * kRRW - 1) / (2 * kRRW));
+  const int64_t ncol =
+      (int64_t)((f.n[0] + (quad ? kRQX : kRRX) - 1) / (quad ? kRQX : kRRX)) * ((f.n[1] + 2 * kRRW - 1) / (2 * kRRW));
   int zc = kRRZ;
   while (zc > 2 && ncol * ((f.n[2] + zc - 1) / zc) < 2048) zc /= 2;
   const int64_t nb = ncol * ((f.n[2] + zc - 1) / zc);
-  hipLaunchKernelGGL((k_resid_restrict3<T>), dim3((unsigned)nb), dim3(64, kRRW), 0, s, f.tag.p, x, b, r, c.tag.p,
-                     Vec<T>::b(c), Vec<T>::t(f), zc);
+  if (quad)
+    hipLaunchKernelGGL((k_resid_restrict3q<T>), dim3((unsigned)nb), dim3(64, kRRW), 0, s, f.tag.p, x, b, r, c.tag.p,
+                       Vec<T>::b(c), Vec<T>::t(f), zc);
+  else
+    hipLaunchKernelGGL((k_resid_restrict3<T>), dim3((unsigned)nb), dim3(64, kRRW), 0, s, f.tag.p, x, b, r, c.tag.p,
+                       Vec<T>::b(c), Vec<T>::t(f), zc);
   const unsigned nbn = nblk(f.n_ns);
   const int64_t ncd = c.N + c.N2;
   hipLaunchKernelGGL((k_restrict_all<T, 3>), dim3(nbn + nblk(ncd)), dim3(kBlock), 0, s, c.tag.p, r, Vec<T>::b(c),
@@ -3297,6 +3310,38 @@ ebmg_status ebmg_smooth(ebmg_problem pb, int32_t level, int32_t variant, int32_t
       hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(nd)), dim3(kBlock), 0, s, L.x32.p, x, nd);
     } else {
       template_sweeps<double>(L, variant, sweeps, x, b, s);
+    }
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(s));
+    return EBMG_OK;
+  });
+}
+
+ebmg_status ebmg_restrict_residual(ebmg_problem pb, int32_t level, int32_t form, const double* x, const double* b,
+                                   double* bc) {
+  if (!pb || !x || !b || !bc || form < 0 || form > 2) return EBMG_ERR_ARG;
+  if (!pb->on_device) return EBMG_ERR_DEVICE;
+  if (level < 0 || level + 1 >= (int32_t)pb->dev.lv.size()) return EBMG_ERR_ARG;
+  return guard(pb->ctx, [&]() -> ebmg_status {
+    drain(pb);
+    HIPCHECK(hipSetDevice(pb->ctx->device));
+    DevLevel& F = pb->dev.lv[level];
+    DevLevel& C = pb->dev.lv[level + 1];
+    hipStream_t s = pb->ctx->stream;
+    const bool mixed = pb->host->opt.precision == EBMG_MIXED;
+    const int64_t nf = F.N + F.N2, nc = C.N + C.N2;
+    if (mixed) {
+      if (!F.x32.p || !F.b32.p || !C.b32.p || !C.x32.p || !F.r32.p) throw ArgError("no FP32 vectors on these levels");
+      hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(nf)), dim3(kBlock), 0, s, x, F.x32.p, nf);
+      hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(nf)), dim3(kBlock), 0, s, b, F.b32.p, nf);
+      residual_restrict<float>(F, C, F.x32.p, F.b32.p, s, form);
+      hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(nc)), dim3(kBlock), 0, s, C.b32.p, bc, nc);
+    } else {
+      if (!F.x64.p || !F.b64.p || !C.b64.p || !C.x64.p || !F.r64.p) throw ArgError("no FP64 vectors on these levels");
+      HIPCHECK(hipMemcpyAsync(F.x64.p, x, sizeof(double) * nf, hipMemcpyDeviceToDevice, s));
+      HIPCHECK(hipMemcpyAsync(F.b64.p, b, sizeof(double) * nf, hipMemcpyDeviceToDevice, s));
+      residual_restrict<double>(F, C, F.x64.p, F.b64.p, s, form);
+      HIPCHECK(hipMemcpyAsync(bc, C.b64.p, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
     }
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(s));

@@ -332,6 +332,129 @@ __global__ void __launch_bounds__(TX * TY / 4, OCC) k_rb_zq3(const uint8_t* __re
   for (int64_t q = (int64_t)blockIdx.x * NT + tid; q < nsec; q += nblocks * NT) xout[N + q] = ZIN ? T(0) : xin[N + q];
 }
 
+// Quad form of k_resid_restrict3 (x extent a multiple of 4, arrays aligned
+// to four values): each lane takes four consecutive cells of a row (x, b and
+// the row neighbours as 4-element vectors, the tags as one 32-bit word, the
+// two coarse cells' tags as one 16-bit word), a wavefront 32 quads of two
+// neighbouring rows (lanes 0-31 and 32-63), so the 2 x 2 groups of children
+// are two coarse cells per lane pair, summed in-lane along x and by one
+// shuffle along y, in the same order as k_resid_restrict3; the residual of
+// each template child is formed with the same arithmetic. Tiles of kRQX x
+// (2 kRRW) columns over zc planes, one plane requested ahead.
+constexpr int kRQX = 128;
+
+template <typename T>
+__global__ void __launch_bounds__(64 * kRRW) k_resid_restrict3q(const uint8_t* __restrict__ tag,
+                                                                const T* __restrict__ x, const T* __restrict__ b,
+                                                                T* __restrict__ r, const uint8_t* __restrict__ ctag,
+                                                                T* __restrict__ bc, Tmpl<T> tp, int zc) {
+  typedef T Q __attribute__((ext_vector_type(4)));
+  __shared__ T TC[2][8];
+  const int tid = threadIdx.x + 64 * threadIdx.y;
+  if (tid < 16) {
+    const int p = tid >> 3, j = tid & 7;
+    TC[p][j] = j == 0 ? tp.coff[p] : (j == 1 ? tp.mass[p] : tp.cbm[j - 2][p]);
+  }
+  __syncthreads();
+  const int nx = tp.n[0], ny = tp.n[1], nz = tp.n[2];
+  const int cnx = nx >> 1, cny = ny >> 1;
+  const int gbx = (nx + kRQX - 1) / kRQX, gby = (ny + 2 * kRRW - 1) / (2 * kRRW);
+  const int64_t tt = xcd_block(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x;
+  const int i = (int)(tt % gbx) * kRQX + 4 * (lane & 31);
+  const int j = (int)((tt / gbx) % gby) * (2 * kRRW) + 2 * threadIdx.y + (lane >> 5);
+  const int z0 = (int)(tt / ((int64_t)gbx * gby)) * zc, z1 = min(z0 + zc, nz);
+  // lanes past the box edge load a valid cell, take part in the shuffles and
+  // write nothing (a quad and its 2 x 2 groups are all in or all out)
+  const bool act = i < nx && j < ny;
+  const int ic = act ? i : 0, jc = act ? j : 0;
+  const bool lead = act && lane < 32;
+  const int64_t sxy = (int64_t)nx * ny;
+  const int64_t c0 = ic + (int64_t)nx * jc;
+  const int64_t ow = ic > 0 ? -1 : 0, oe = ic + 4 < nx ? 4 : 3;
+  const int64_t os = jc > 0 ? -(int64_t)nx : 0, on = jc < ny - 1 ? (int64_t)nx : 0;
+  const int64_t P0 = (ic >> 1) + (int64_t)cnx * (jc >> 1);
+  const int64_t csxy = (int64_t)cnx * cny;
+  const Q zq = {T(0), T(0), T(0), T(0)};
+  Q xm = z0 > 0 ? *(const Q*)(x + c0 + sxy * (z0 - 1)) : zq;
+  int64_t c = c0 + sxy * z0;
+  Q xc = *(const Q*)(x + c);
+  Q xp = z0 + 1 < nz ? *(const Q*)(x + c + sxy) : zq;
+  T w = x[c + ow], e = x[c + oe];
+  Q so = *(const Q*)(x + c + os), no = *(const Q*)(x + c + on);
+  uint32_t tg = *(const uint32_t*)(tag + c);
+  Q bb = *(const Q*)(b + c);
+  uint32_t ct = *(const uint16_t*)(ctag + P0 + csxy * (z0 >> 1));
+  T accA = 0, accB = 0;
+  for (int k = z0; k < z1; ++k, c += sxy) {
+    const bool more = k + 1 < z1;
+    const int64_t cn = more ? c + sxy : c;
+    const Q xpp = k + 2 < nz ? *(const Q*)(x + c + 2 * sxy) : zq;
+    const T wn = x[cn + ow], en = x[cn + oe];
+    const Q son = *(const Q*)(x + cn + os), non = *(const Q*)(x + cn + on);
+    const uint32_t tgn = more ? *(const uint32_t*)(tag + cn) : 0x03030303u;
+    const Q bbn = more ? *(const Q*)(b + cn) : zq;
+    const uint32_t ctn = more ? (uint32_t)*(const uint16_t*)(ctag + P0 + csxy * ((k + 1) >> 1)) : 0x0303u;
+    T out[4], up[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int p = tclass((uint8_t)(tg >> (8 * u)));
+      const uint8_t cu = (uint8_t)(ct >> (8 * (u >> 1)));   // the coarse cell of child u
+      if (p == 2) {
+        out[u] = r[c + u];   // an explicit row: its residual is already there
+      } else if (p == 3) {
+        out[u] = T(0);
+      } else {
+        const T xv = xc[u];
+        const T wv = u ? xc[u > 0 ? u - 1 : 0] : w, ev = u < 3 ? xc[u < 3 ? u + 1 : 3] : e;
+        const T* tc = TC[p];
+        T sm = 0, dg = tc[1];
+        if (ic + u > 0) sm += wv - xv; else dg += tc[2];
+        if (ic + u < nx - 1) sm += ev - xv; else dg += tc[3];
+        if (jc > 0) sm += so[u] - xv; else dg += tc[4];
+        if (jc < ny - 1) sm += no[u] - xv; else dg += tc[5];
+        if (k > 0) sm += xm[u] - xv; else dg += tc[6];
+        if (k < nz - 1) sm += xp[u] - xv; else dg += tc[7];
+        const T ax = dg * xv + tc[0] * sm;
+        out[u] = bb[u] - ax;
+      }
+      // the children of a non-simple coarse unknown keep their residual for
+      // the list restriction that follows
+      if (act && p != 2 && (cu & 4) && tclass(cu) != 3) r[c + u] = out[u];
+      up[u] = __shfl_xor(out[u], 32, 64);
+    }
+    if (lead) {
+      const T pkA = ((out[0] + out[1]) + up[0]) + up[1];
+      const T pkB = ((out[2] + out[3]) + up[2]) + up[3];
+      if ((k & 1) == 0) {
+        accA = pkA;
+        accB = pkB;
+      } else {
+        const int64_t P = P0 + csxy * (k >> 1);
+        const uint8_t ca = (uint8_t)ct, cb = (uint8_t)(ct >> 8);
+        if (tclass(ca) == 3)
+          bc[P] = T(0);
+        else if (!(ca & 4))
+          bc[P] = (accA + pkA) * T(0.125);
+        if (tclass(cb) == 3)
+          bc[P + 1] = T(0);
+        else if (!(cb & 4))
+          bc[P + 1] = (accB + pkB) * T(0.125);
+      }
+    }
+    xm = xc;
+    xc = xp;
+    xp = xpp;
+    w = wn;
+    e = en;
+    so = son;
+    no = non;
+    tg = tgn;
+    bb = bbn;
+    ct = (k & 1) ? ctn : ct;
+  }
+}
+
 // Reference stream for the measurement hook: the fused sweep's bytes per
 // cell with no stencil (reads x, b and the tag of every cell, writes one
 // value per cell), four cells per thread in 16-byte accesses; n a multiple

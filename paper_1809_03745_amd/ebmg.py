@@ -114,6 +114,7 @@ _sig("ebmg_apply_noalloc", C.c_int, [_vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_efield", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("ebmg_time_kernel", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _dp, _dp])
 _sig("ebmg_smooth", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _vp, _vp])
+_sig("ebmg_restrict_residual", C.c_int, [_vp, C.c_int32, C.c_int32, _vp, _vp, _vp])
 _sig("ebmg_kernel_timing", C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _i64p, _dp, _dp])
 _sig("ebmg_release", C.c_int, [_vp])
 _sig("ebmg_set_coefficients", C.c_int, [_vp, C.POINTER(Options), C.POINTER(DomainBC)])
@@ -149,7 +150,7 @@ EXPORTED = ["ebmg_default_options", "ebmg_abi_version", "ebmg_create", "ebmg_des
             "ebmg_export_geometry", "ebmg_export_moments", "ebmg_export_operator", "ebmg_export_rhs",
             "ebmg_solve", "ebmg_submit", "ebmg_poll", "ebmg_wait", "ebmg_apply", "ebmg_apply_noalloc", "ebmg_efield", "ebmg_time_kernel", "ebmg_release",
             "ebmg_setup_batch", "ebmg_query_batch", "ebmg_query_batch_box", "ebmg_query_batch_tuning", "ebmg_solve_batch", "ebmg_release_batch",
-            "ebmg_set_coefficients", "ebmg_smooth", "ebmg_kernel_timing",
+            "ebmg_set_coefficients", "ebmg_smooth", "ebmg_restrict_residual", "ebmg_kernel_timing",
             "ebmg_setup_family", "ebmg_query_family", "ebmg_solve_family", "ebmg_release_family",
             "ebmg_mesh_create", "ebmg_mesh_query", "ebmg_mesh_sdf", "ebmg_mesh_release", "ebmg_advect",
             "ebmg_time_batch_kernel", "ebmg_setup_amr", "ebmg_query_amr", "ebmg_solve_amr", "ebmg_apply_amr", "ebmg_release_amr"]
@@ -486,6 +487,16 @@ class Problem:
         n = sum(self.level_size(level))
         self.ctx.check(_lib.ebmg_smooth(self.h, level, variant, sweeps, _dev(self.ctx, x, n, "x"),
                                         _dev(self.ctx, b, n, "b")), "ebmg_smooth")
+
+    def restrict_residual(self, level, form, x, b, bc):
+        """The V-cycle's residual of level ``level`` restricted into the next
+        level's right-hand side ``bc`` (device FP64 tensors; form 0 the
+        solver's kernels, 1 the fused pair kernel, 2 separate kernels)."""
+        n = sum(self.level_size(level))
+        nc = sum(self.level_size(level + 1))
+        self.ctx.check(_lib.ebmg_restrict_residual(self.h, level, form, _dev(self.ctx, x, n, "x"),
+                                                   _dev(self.ctx, b, n, "b"), _dev(self.ctx, bc, nc, "bc")),
+                       "ebmg_restrict_residual")
 
     def time_kernel(self, which, level=0, reps=50):
         """(mean ms per launch, algorithmic bytes per launch) of a kernel."""

@@ -372,7 +372,9 @@ ebmg_status ebmg_efield(ebmg_problem pb, const double* phi, const double* phi2, 
  * 16-byte fetches, x extent a multiple of 4; 10: 64x16 over 8; 11..13: the
  * quad form, each thread four cells of a row, 64x16, 128x16 and 128x8
  * over 32, x extent a multiple of 4; 3D), 17 one-launch colour
- * phases out of place. Every variant performs exactly the red half-sweep
+ * phases out of place (four cells of a row per thread when the x extent is
+ * a multiple of 4 and the arrays are aligned to four values, else two or
+ * one). Every variant performs exactly the red half-sweep
  * followed by
  * the black one with the same arithmetic, so their results agree bitwise.
  * Variant 18 is the one-launch colour phases with the explicit rows

@@ -814,32 +814,112 @@ __global__ void __launch_bounds__(kBlock) k_irr_scatter(const int32_t* __restric
 
 // One colour phase of an out-of-place red/black sweep in a single launch:
 // template cells and explicit rows of colour `colour` are updated from xin,
-// every other unknown is copied to xout. Blocks [0, nbc) take cells (one per
-// thread), the next nbu blocks update the rows rows_upd (kSub lanes per
-// row), the rest copy the rows rows_cp (one thread per row). Every update of
-// the phase, template cell or explicit row, reads only the values before the
-// phase: the explicit rows do not see this phase's template-cell updates
-// (the grouped passes, which run after the phase's template cells, do), and
-// rows of one colour see each other's previous values (Jacobi within a
-// colour, as in the grouped passes). A sweep costs two launches, which is
-// what matters on small levels.
-// With PAIR (nx even) a cell thread takes an even-odd pair along x, of which
-// exactly one cell has the phase's colour: half as many threads wait on the
-// same tag -> neighbours -> store chain, with the same arithmetic per cell.
-template <typename T, int DIM, bool PAIR>
+// every other unknown is copied to xout. Blocks [0, nbu) update the rows
+// rows_upd (kSub lanes per row), the next ones up to nbr copy the rows
+// rows_cp (one thread per row), the last nbc take the template cells; the
+// rows go first because each of them waits on a chain of dependent loads
+// (row index, row extent, columns, values), which then overlaps with the
+// cells instead of trailing them. Every update of the phase, template cell
+// or explicit row, reads only the values before the phase: the explicit
+// rows do not see this phase's template-cell updates (the grouped passes,
+// which run after the phase's template cells, do), and rows of one colour
+// see each other's previous values (Jacobi within a colour, as in the
+// grouped passes). A sweep costs two launches, which is what matters on
+// small levels.
+// W cells per thread along x: W = 2 (nx even) takes an even-odd pair, of
+// which exactly one cell has the phase's colour; W = 4 (nx a multiple of 4,
+// fewer than 2^31 cells, arrays aligned to a quad) takes four cells, two of
+// each colour, with every load and the store as one quad vector (tags as
+// one 32-bit word) and 32-bit index arithmetic. Fewer threads wait on the
+// same tag -> neighbours -> store chain; the arithmetic per cell is the
+// same in every form.
+template <typename T, int DIM>
+__device__ __forceinline__ T oop_cell(const Tmpl<T>& tp, int p, T w, T e, T so, T no, T dn, T up, int i, int j,
+                                      int k, T bc) {
+  const int nx = tp.n[0], ny = tp.n[1];
+  T s = 0;
+  T dg = tp.D0(p);
+  if (i > 0) s += w; else dg += tp.CB(0, p);
+  if (i < nx - 1) s += e; else dg += tp.CB(1, p);
+  if (j > 0) s += so; else dg += tp.CB(2, p);
+  if (j < ny - 1) s += no; else dg += tp.CB(3, p);
+  if (DIM == 3) {
+    if (k > 0) s += dn; else dg += tp.CB(4, p);
+    if (k < tp.n[2] - 1) s += up; else dg += tp.CB(5, p);
+  }
+  const T off = tp.CO(p) * s;
+  return (bc - off) * (T(1) / dg);
+}
+
+template <typename T, int DIM, int W>
 __global__ void __launch_bounds__(kBlock) k_rb_oop(const uint8_t* __restrict__ tag, const T* __restrict__ xin,
                                                    T* __restrict__ xout, const T* __restrict__ b, Tmpl<T> tp,
-                                                   int colour, unsigned nbc, unsigned nbu,
+                                                   int colour, unsigned nbc, unsigned nbu, unsigned nbr,
                                                    const int32_t* __restrict__ rows_upd,
                                                    int nupd, const int32_t* __restrict__ rows_cp, int ncp,
                                                    const int64_t* __restrict__ dof, const int64_t* __restrict__ rp,
                                                    const int32_t* __restrict__ col, const T* __restrict__ val,
                                                    const T* __restrict__ diag) {
-  if (blockIdx.x < nbc) {
+  if (blockIdx.x >= nbr) {
+    const unsigned cb = blockIdx.x - nbr;
     const int nx = tp.n[0], ny = tp.n[1];
+    if (W == 4) {
+      typedef T Q __attribute__((ext_vector_type(4)));
+      const uint32_t nq = (uint32_t)nx >> 2;
+      const uint32_t q = cb * kBlock + threadIdx.x;
+      const uint32_t row = q / nq;   // j + ny * k
+      if (row >= (uint32_t)ny * (uint32_t)(DIM == 3 ? tp.n[2] : 1)) return;
+      const int i = (int)(q - row * nq) * 4;
+      const int j = (int)(row % (uint32_t)ny);
+      const int k = DIM == 3 ? (int)(row / (uint32_t)ny) : 0;
+      const uint32_t c = row * (uint32_t)nx + (uint32_t)i;
+      // out-of-box neighbours read the quad itself (in bounds); the
+      // update skips them
+      const uint32_t cs = j > 0 ? c - nx : c, cn = j < ny - 1 ? c + nx : c;
+      const int u = ((j + k) & 1) == colour ? 0 : 1;   // cells u and u + 2 have the phase's colour
+      // the one x neighbour outside the quad: left of cell 0 (u = 0) or right of cell 3 (u = 1)
+      const uint32_t co = u ? (i + 4 < nx ? c + 4 : c) : (i > 0 ? c - 1 : c);
+      const uint32_t tw = *(const uint32_t*)(tag + c);
+      const Q xc = *(const Q*)(xin + c);
+      const T xo = xin[co];
+      const Q xs = *(const Q*)(xin + cs);
+      const Q xn = *(const Q*)(xin + cn);
+      Q xd = xc, xu = xc;
+      if (DIM == 3) {
+        const uint32_t sxy = (uint32_t)nx * (uint32_t)ny;
+        xd = *(const Q*)(xin + (k > 0 ? c - sxy : c));
+        xu = *(const Q*)(xin + (k < tp.n[2] - 1 ? c + sxy : c));
+      }
+      const Q bq = *(const Q*)(b + c);
+      const int pa = (int)((tw >> (8 * u)) & 3u), pb = (int)((tw >> (8 * (u + 2))) & 3u);
+      T va = u ? xc.y : xc.x, vb = u ? xc.w : xc.z;
+      if (pa <= 1)
+        va = oop_cell<T, DIM>(tp, pa, u ? xc.x : xo, u ? xc.z : xc.y, u ? xs.y : xs.x, u ? xn.y : xn.x,
+                              u ? xd.y : xd.x, u ? xu.y : xu.x, i + u, j, k, u ? bq.y : bq.x);
+      if (pb <= 1)
+        vb = oop_cell<T, DIM>(tp, pb, u ? xc.z : xc.y, u ? xo : xc.w, u ? xs.w : xs.z, u ? xn.w : xn.z,
+                              u ? xd.w : xd.z, u ? xu.w : xu.z, i + u + 2, j, k, u ? bq.w : bq.z);
+      Q o;
+      o.x = u ? xc.x : va;
+      o.y = u ? va : xc.y;
+      o.z = u ? xc.z : vb;
+      o.w = u ? vb : xc.w;
+      // explicit-row cells (class 2) are written by the row blocks
+      const bool e0 = (tw & 3u) == 2u, e1 = ((tw >> 8) & 3u) == 2u, e2 = ((tw >> 16) & 3u) == 2u,
+                 e3 = ((tw >> 24) & 3u) == 2u;
+      if (!(e0 | e1 | e2 | e3)) {
+        *(Q*)(xout + c) = o;
+      } else {
+        if (!e0) xout[c] = o.x;
+        if (!e1) xout[c + 1] = o.y;
+        if (!e2) xout[c + 2] = o.z;
+        if (!e3) xout[c + 3] = o.w;
+      }
+      return;
+    }
     const int64_t N = (int64_t)nx * ny * (DIM == 3 ? tp.n[2] : 1);
-    if (PAIR) {
-      const int64_t c = 2 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+    if (W == 2) {
+      const int64_t c = 2 * ((int64_t)cb * kBlock + threadIdx.x);
       if (c >= N) return;
       const int i = (int)(c % nx);
       const int64_t jk = c / nx;
@@ -859,7 +939,7 @@ __global__ void __launch_bounds__(kBlock) k_rb_oop(const uint8_t* __restrict__ t
       if (p1 != 2) xout[c + 1] = u ? vu : x1;
       return;
     }
-    const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t c = (int64_t)cb * kBlock + threadIdx.x;
     if (c >= N) return;
     const uint8_t p = tclass(tag[c]);
     if (p == 2) return;
@@ -876,8 +956,8 @@ __global__ void __launch_bounds__(kBlock) k_rb_oop(const uint8_t* __restrict__ t
     xout[c] = v;
     return;
   }
-  if (blockIdx.x < nbc + nbu) {
-    const int64_t g = ((int64_t)(blockIdx.x - nbc) * kBlock + threadIdx.x) / kSub;
+  if (blockIdx.x < nbu) {
+    const int64_t g = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kSub;
     const int lane = threadIdx.x % kSub;
     if (g >= nupd) return;
     const int r = rows_upd[g];
@@ -886,7 +966,7 @@ __global__ void __launch_bounds__(kBlock) k_rb_oop(const uint8_t* __restrict__ t
     if (lane == 0) xout[q] = (b[q] - s) / diag[r];
     return;
   }
-  const int64_t g = (int64_t)(blockIdx.x - nbc - nbu) * kBlock + threadIdx.x;
+  const int64_t g = (int64_t)(blockIdx.x - nbu) * kBlock + threadIdx.x;
   if (g >= ncp) return;
   const int64_t q = dof[rows_cp[g]];
   xout[q] = xin[q];

@@ -1207,8 +1207,11 @@ static inline unsigned nblk_sub(int64_t rows) { return nblk(rows * kSub); }
 template <typename T>
 static void launch_oop(DevLevel& l, int colour, bool rows, const T* xin, T* xout, const T* b, hipStream_t s) {
   const Tmpl<T>& tp = Vec<T>::t(l);
-  const bool pair = tp.n[0] % 2 == 0;
-  const unsigned nbc = nblk(pair ? l.N / 2 : l.N);
+  const size_t qa = 4 * sizeof(T);
+  const bool quad = tp.n[0] % 4 == 0 && l.N < ((int64_t)1 << 31) && (uintptr_t)xin % qa == 0 &&
+                    (uintptr_t)xout % qa == 0 && (uintptr_t)b % qa == 0 && (uintptr_t)l.tag.p % 4 == 0;
+  const bool pair = !quad && tp.n[0] % 2 == 0;
+  const unsigned nbc = nblk(quad ? l.N / 4 : pair ? l.N / 2 : l.N);
   int n0 = 0, n1 = 0;
   const int32_t* g0 = l.cls_rows.p;
   const int32_t* g1 = l.cls_rows.p;
@@ -1232,13 +1235,13 @@ static void launch_oop(DevLevel& l, int colour, bool rows, const T* xin, T* xout
   }
   const unsigned nbu = nblk_sub(nup);
   const unsigned nbr = nbu + nblk(ncp);
-#define OOP_LAUNCH(D, P)                                                                                     \
-  KLAUNCH(l.kt, (k_rb_oop<T, D, P>), dim3(nbc + nbr), dim3(kBlock), 0, s, l.tag.p, xin, xout, b, tp, colour, nbc, \
-          nbu, up, nup, cp, ncp, l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l))
+#define OOP_LAUNCH(D, W)                                                                                     \
+  KLAUNCH(l.kt, (k_rb_oop<T, D, W>), dim3(nbc + nbr), dim3(kBlock), 0, s, l.tag.p, xin, xout, b, tp, colour, nbc, \
+          nbu, nbr, up, nup, cp, ncp, l.irow_dof.p, l.rp.p, l.col.p, Vec<T>::val(l), Vec<T>::diag(l))
   if (l.dim == 3) {
-    if (pair) OOP_LAUNCH(3, true); else OOP_LAUNCH(3, false);
+    if (quad) OOP_LAUNCH(3, 4); else if (pair) OOP_LAUNCH(3, 2); else OOP_LAUNCH(3, 1);
   } else {
-    if (pair) OOP_LAUNCH(2, true); else OOP_LAUNCH(2, false);
+    if (quad) OOP_LAUNCH(2, 4); else if (pair) OOP_LAUNCH(2, 2); else OOP_LAUNCH(2, 1);
   }
 #undef OOP_LAUNCH
 }

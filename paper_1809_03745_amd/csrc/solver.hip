@@ -2094,7 +2094,7 @@ static void build_wide_tables(ebmg_batch_s* Bt, int cells, hipStream_t s) {
       add_chunks(rb, i, 0, cdiv(half, CH));
       for (int g = 0; g < 2; ++g) {
         const int rows = group_rows(F, g);
-        add_chunks(jac[g], i, 0, cdiv(rows, kWRows));
+        add_chunks(jac[g], i, 0, cdiv(rows, kSlice));   // one slice per entry (kw_irr_jac)
         add_chunks(scat[g], i, 0, cdiv(rows, kWList));
       }
       add_chunks(cell, i, 0, cdiv(F.N, CH));

@@ -272,6 +272,8 @@ enum WVecOp { WV_INIT = 0, WV_P, WV_S, WV_XR, WV_RESTART, WV_OUT };
 //   XR      x += alpha ph + omega sh; r = s - omega t; partials (rh, r), (r, r)
 //   RESTART rh = r, p = v = 0
 //   OUT     guess arrays = x (0 when b = 0)
+// The FP64 streams of P, S and XR carry non-temporal hints, as in the
+// single-box Krylov steps (a V-cycle lies between two uses of a vector).
 template <typename T, int OP>
 __global__ void __launch_bounds__(kWB) kw_vec(const BBox<T>* __restrict__ boxes, const WEnt* __restrict__ tab,
                                              const WState* __restrict__ st, const WIO* __restrict__ io, int filt,
@@ -316,8 +318,9 @@ __global__ void __launch_bounds__(kWB) kw_vec(const BBox<T>* __restrict__ boxes,
     for (int u = 0; u < 4; ++u) {
       const int i = beg + u * kWB;
       if (i < nd) {
-        const double pv = kry ? r[i] + beta * (p[i] - om * v[i]) : r[i];
-        p[i] = pv;
+        const double ri = ld_stream<true>(r + i);
+        const double pv = kry ? ri + beta * (ld_stream<true>(p + i) - om * ld_stream<true>(v + i)) : ri;
+        st_stream<true>(pv, p + i);
         if (sep) zb[i] = (T)pv;
         zx[i] = T(0);
       }
@@ -331,8 +334,8 @@ __global__ void __launch_bounds__(kWB) kw_vec(const BBox<T>* __restrict__ boxes,
     for (int u = 0; u < 4; ++u) {
       const int i = beg + u * kWB;
       if (i < nd) {
-        const double s = r[i] - al * v[i];
-        sv[i] = s;
+        const double s = ld_stream<true>(r + i) - al * ld_stream<true>(v + i);
+        st_stream<true>(s, sv + i);
         if (sep) zb[i] = (T)s;
         zx[i] = T(0);
       }
@@ -345,10 +348,11 @@ __global__ void __launch_bounds__(kWB) kw_vec(const BBox<T>* __restrict__ boxes,
     for (int u = 0; u < 4; ++u) {
       const int i = beg + u * kWB;
       if (i < nd) {
-        x[i] += al * (double)ph[i] + om * (double)sh[i];
-        const double rn = sv[i] - om * tv[i];
+        const double xi = ld_stream<true>(x + i);
+        st_stream<true>(xi + (al * (double)ld_stream<true>(ph + i) + om * (double)ld_stream<true>(sh + i)), x + i);
+        const double rn = ld_stream<true>(sv + i) - om * ld_stream<true>(tv + i);
         r[i] = rn;
-        a0 += rh[i] * rn;
+        a0 += ld_stream<true>(rh + i) * rn;
         a1 += rn * rn;
       }
     }

@@ -1683,7 +1683,8 @@ __global__ void __launch_bounds__(kBlock) k_dot_final(const double* __restrict__
 }
 
 // BiCGStab scalars live on the device: slots of `sc`
-enum { SC_RHO = 0, SC_RR, SC_RHO_OLD, SC_ALPHA, SC_OMEGA, SC_RV, SC_TS, SC_TT, SC_NUM };
+// SC_GUESS: 1 when the initial guess has a nonzero entry (set by k_guess_in)
+enum { SC_RHO = 0, SC_RR, SC_RHO_OLD, SC_ALPHA, SC_OMEGA, SC_RV, SC_TS, SC_TT, SC_GUESS, SC_NUM };
 
 __global__ void k_sc_reset(double* sc) {
   sc[SC_RHO] = 1.0;
@@ -1789,11 +1790,20 @@ __global__ void __launch_bounds__(kBlock) k_convert(const S* __restrict__ s, D* 
 
 // The initial guess taken from the caller's array, in one pass with setting
 // the covered entries to 0: covered cells are identity rows with b = 0 that
-// no sweep, correction or Krylov update touches.
+// no sweep, correction or Krylov update touches. tag null: every entry is
+// taken as it is (second-phase unknowns). *nz (cleared before) is set to 1
+// when an entry taken is nonzero: a zero guess lets the solve take r = b
+// without forming A x (every lane that sees one writes the same value).
 __global__ void __launch_bounds__(kBlock) k_guess_in(const uint8_t* __restrict__ tag, const double* __restrict__ phi,
-                                                     double* __restrict__ x, int64_t n) {
+                                                     double* __restrict__ x, int64_t n, double* __restrict__ nz) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) x[t] = tclass(tag[t]) == 3 ? 0.0 : phi[t];
+  bool any = false;
+  if (t < n) {
+    const double v = (tag && tclass(tag[t]) == 3) ? 0.0 : phi[t];
+    x[t] = v;
+    any = v != 0.0;
+  }
+  if (__any(any) && (threadIdx.x & 63) == 0) *nz = 1.0;
 }
 
 // Krylov (re)start in one pass: r = rh = r0, p = v = 0.
@@ -1897,6 +1907,68 @@ __global__ void __launch_bounds__(kBlock) k_efield_reg(const uint8_t* __restrict
     else
       ghi = ga.CB(2 * d + 1, p) * xc + gbv.CB(2 * d + 1, p);
     E[d * N + c] = -0.5 * (glo + ghi);
+  }
+}
+
+// The same field of a large 3D level marching along z: each thread owns one
+// (i, j) column of a kEZX x kEZY tile and walks kEZ planes, keeping x of
+// planes k - 1, k and k + 1 in registers, so x leaves HBM once (the in-plane
+// neighbours are cache hits) where the plane-by-plane grid re-reads the
+// planes above and below. The arithmetic per component is k_efield_reg's.
+constexpr int kEZX = 64, kEZY = 4, kEZ = 32;
+__global__ void __launch_bounds__(kEZX * kEZY) k_efield_zm3(const uint8_t* __restrict__ tag,
+                                                          const double* __restrict__ x, double* __restrict__ E,
+                                                          Tmpl<double> ga, Tmpl<double> gbv, double inv_h) {
+  const int nx = ga.n[0], ny = ga.n[1], nz = ga.n[2];
+  const int i = blockIdx.x * kEZX + threadIdx.x;
+  const int j = blockIdx.y * kEZY + threadIdx.y;
+  const int z0 = blockIdx.z * kEZ, z1 = min(z0 + kEZ, nz);
+  if (i >= nx || j >= ny) return;
+  const int64_t sxy = (int64_t)nx * ny, N = sxy * nz;
+  int64_t c = i + (int64_t)nx * j + sxy * z0;
+  double xm = z0 > 0 ? x[c - sxy] : 0.0;
+  double xc = x[c];
+  for (int k = z0; k < z1; ++k, c += sxy) {
+    const double xp = k + 1 < nz ? x[c + sxy] : 0.0;
+    const double xw = i > 0 ? x[c - 1] : 0.0, xe = i < nx - 1 ? x[c + 1] : 0.0;
+    const double xs = j > 0 ? x[c - nx] : 0.0, xn = j < ny - 1 ? x[c + nx] : 0.0;
+    const uint8_t p = tclass(tag[c]);
+    if (p == 3) {
+      E[c] = 0;
+      E[N + c] = 0;
+      E[2 * N + c] = 0;
+    } else if (p != 2) {
+      double glo, ghi;
+      if (i > 0)
+        glo = (xc - xw) * inv_h;
+      else
+        glo = -(ga.CB(0, p) * xc + gbv.CB(0, p));
+      if (i < nx - 1)
+        ghi = (xe - xc) * inv_h;
+      else
+        ghi = ga.CB(1, p) * xc + gbv.CB(1, p);
+      E[c] = -0.5 * (glo + ghi);
+      if (j > 0)
+        glo = (xc - xs) * inv_h;
+      else
+        glo = -(ga.CB(2, p) * xc + gbv.CB(2, p));
+      if (j < ny - 1)
+        ghi = (xn - xc) * inv_h;
+      else
+        ghi = ga.CB(3, p) * xc + gbv.CB(3, p);
+      E[N + c] = -0.5 * (glo + ghi);
+      if (k > 0)
+        glo = (xc - xm) * inv_h;
+      else
+        glo = -(ga.CB(4, p) * xc + gbv.CB(4, p));
+      if (k < nz - 1)
+        ghi = (xp - xc) * inv_h;
+      else
+        ghi = ga.CB(5, p) * xc + gbv.CB(5, p);
+      E[2 * N + c] = -0.5 * (glo + ghi);
+    }
+    xm = xc;
+    xc = xp;
   }
 }
 

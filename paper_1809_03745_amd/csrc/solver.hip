@@ -1679,7 +1679,12 @@ static void efield(ebmg_problem_s* P, const double* x, const double* sigma, cons
     }
   const double ih = 1.0 / H.levels[0].g.h;
   const Shape sh = shape3(L.n[0], L.n[1], L.dim == 3 ? L.n[2] : 1);
-  if (L.dim == 3)
+  if (L.dim == 3 && L.N >= kResidZMMin)
+    hipLaunchKernelGGL(k_efield_zm3,
+                       dim3((unsigned)((L.n[0] + kEZX - 1) / kEZX), (unsigned)((L.n[1] + kEZY - 1) / kEZY),
+                            (unsigned)((L.n[2] + kEZ - 1) / kEZ)),
+                       dim3(kEZX, kEZY), 0, s, L.tag.p, x, E, ga, gb, ih);
+  else if (L.dim == 3)
     hipLaunchKernelGGL((k_efield_reg<3>), sh.g, sh.b, 0, s, L.tag.p, x, E, ga, gb, ih);
   else
     hipLaunchKernelGGL((k_efield_reg<2>), sh.g, sh.b, 0, s, L.tag.p, x, E, ga, gb, ih);
@@ -1773,7 +1778,7 @@ static void matvec_dots(DevProblem& D, const Z* x, double* out, const double* da
 // Z is the preconditioner output type (FP32 for mixed precision).
 template <typename Z>
 static ebmg_status bicgstab_t(DevProblem& D, const Options& o, double bn, double rtol, int max_cycles, double& rel,
-                              int& cyc, ebmg_solve_info& info, Z* ph, Z* sh, hipStream_t s) {
+                              int& cyc, ebmg_solve_info& info, Z* ph, Z* sh, hipStream_t s, const double* r0) {
   DevLevel& L = D.lv[0];
   const int64_t nd = L.N + L.N2;
   const bool mixed = o.precision == EBMG_MIXED;
@@ -1782,8 +1787,10 @@ static ebmg_status bicgstab_t(DevProblem& D, const Options& o, double bn, double
   double* x = L.x64.p;
   float* bf = mixed ? L.b32.p : nullptr;
   const unsigned nb = nblk(nd);
-  auto restart = [&]() {
-    hipLaunchKernelGGL(k_bicg_restart, dim3(nb), dim3(kBlock), 0, s, L.r64.p, r, rh, p, v, nd);
+  // r0: the initial residual (the solve's r, or b for a zero guess); a
+  // restart after a breakdown starts from the true residual in r64
+  auto restart = [&](const double* r0src) {
+    hipLaunchKernelGGL(k_bicg_restart, dim3(nb), dim3(kBlock), 0, s, r0src, r, rh, p, v, nd);
     hipLaunchKernelGGL(k_sc_reset, dim3(1), dim3(1), 0, s, D.scal.p);
     dot_dev<double>(D, rh, r, nd, SC_RHO, s);
   };
@@ -1814,7 +1821,7 @@ static ebmg_status bicgstab_t(DevProblem& D, const Options& o, double bn, double
     hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, q, D.part.p, kNormBlocks, 2, D.scal.p + SC_RHO);
     HIPCHECK(hipGetLastError());
   };
-  restart();
+  restart(r0);
   int restarts = 0;
   while (rel > rtol) {
     if (cyc + 2 > max_cycles) return EBMG_ERR_NOCONV;
@@ -1843,7 +1850,7 @@ static ebmg_status bicgstab_t(DevProblem& D, const Options& o, double bn, double
           rel = nrel;
           return EBMG_ERR_NOCONV;
         }
-        restart();
+        restart(L.r64.p);
       }
     } else if (nrel > 1e6) {
       rel = nrel;
@@ -1855,10 +1862,10 @@ static ebmg_status bicgstab_t(DevProblem& D, const Options& o, double bn, double
 }
 
 static ebmg_status bicgstab(DevProblem& D, const Options& o, double bn, double rtol, int max_cycles, double& rel,
-                            int& cyc, ebmg_solve_info& info, hipStream_t s) {
+                            int& cyc, ebmg_solve_info& info, hipStream_t s, const double* r0) {
   if (o.precision == EBMG_MIXED)
-    return bicgstab_t<float>(D, o, bn, rtol, max_cycles, rel, cyc, info, D.ph32.p, D.sh32.p, s);
-  return bicgstab_t<double>(D, o, bn, rtol, max_cycles, rel, cyc, info, D.kv[4].p, D.kv[6].p, s);
+    return bicgstab_t<float>(D, o, bn, rtol, max_cycles, rel, cyc, info, D.ph32.p, D.sh32.p, s, r0);
+  return bicgstab_t<double>(D, o, bn, rtol, max_cycles, rel, cyc, info, D.kv[4].p, D.kv[6].p, s, r0);
 }
 
 static ebmg_status solve(ebmg_problem_s* P, const double* rho, const double* sigma, const double* bcv,
@@ -1875,14 +1882,21 @@ static ebmg_status solve(ebmg_problem_s* P, const double* rho, const double* sig
   std::memset(&loc, 0, sizeof(loc));
   loc.levels = (int)D.lv.size();
   rhs(P, rho, sigma, bcv, objv);
-  hipLaunchKernelGGL(k_guess_in, dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, phi, L.x64.p, L.N);
+  double* guess_nz = D.scal.p + SC_GUESS;
+  fill<double>(guess_nz, 1, 0.0, s);
+  hipLaunchKernelGGL(k_guess_in, dim3(nblk(L.N)), dim3(kBlock), 0, s, L.tag.p, phi, L.x64.p, L.N, guess_nz);
   if (L.N2 > 0) {
     if (phi2)
-      HIPCHECK(hipMemcpyAsync(L.x64.p + L.N, phi2, sizeof(double) * L.N2, hipMemcpyDeviceToDevice, s));
+      hipLaunchKernelGGL(k_guess_in, dim3(nblk(L.N2)), dim3(kBlock), 0, s, (const uint8_t*)nullptr, phi2,
+                         L.x64.p + L.N, L.N2, guess_nz);
     else
       fill<double>(L.x64.p + L.N, L.N2, 0.0, s);
   }
   const double bn = norm2<double>(D, L.b64.p, nd, s);
+  // a zero initial guess: r0 = b exactly (A 0 = 0, and b is 0 on covered
+  // cells, as the residual kernels write there), so A x and its norm are not
+  // formed; the relative residual is then exactly 1
+  const bool zero_guess = D.host_scal[SC_GUESS] == 0.0;
   loc.r0_norm = bn;
   ebmg_status st = EBMG_OK;
   if (!std::isfinite(bn)) {
@@ -1891,11 +1905,16 @@ static ebmg_status solve(ebmg_problem_s* P, const double* rho, const double* sig
     fill<double>(L.x64.p, nd, 0.0, s);
     loc.rel_residual = 0.0;
   } else {
-    residual<double, 0>(L, L.x64.p, L.b64.p, L.r64.p, s);
-    double rel = norm2<double>(D, L.r64.p, nd, s) / bn;
+    double rel = 1.0;
+    if (!zero_guess) {
+      residual<double, 0>(L, L.x64.p, L.b64.p, L.r64.p, s);
+      rel = norm2<double>(D, L.r64.p, nd, s) / bn;
+    } else if (!D.krylov) {
+      HIPCHECK(hipMemcpyAsync(L.r64.p, L.b64.p, sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
+    }
     int cyc = 0;
     if (D.krylov) {
-      st = bicgstab(D, H.opt, bn, rtol, max_cycles, rel, cyc, loc, s);
+      st = bicgstab(D, H.opt, bn, rtol, max_cycles, rel, cyc, loc, s, zero_guess ? L.b64.p : L.r64.p);
     } else {
       // one refinement cycle and its residual norm
       auto cycle = [&](hipStream_t q) {

@@ -119,10 +119,13 @@ def test_solve_parity_mixed(ctx, name):
     P.release()
 
 
-@pytest.mark.parametrize("name", ["two-disks128", "pin-plane32", "coaxial64-sigma", "eddington2d", "box"])
+@pytest.mark.parametrize("name", ["two-disks128", "pin-plane32", "coaxial64-sigma", "eddington2d", "box",
+                                  "pin-plane64"])
 def test_efield_parity(ctx, name):
+    """E of the GPU solution against the oracle's field of the same solution
+    (pin-plane64 takes the z-marching kernel of large 3D levels)."""
     _say("efield parity", name)
-    pr = SMALL[name]()
+    pr = SMALL[name]() if name in SMALL else W.pin_plane(64, seed=1)
     S = assemble(pr)
     P = ebmg.Problem(ctx, pr)
     st, info, x, E = _solve(P, pr, 1e-12, E=True)

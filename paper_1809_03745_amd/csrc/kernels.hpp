@@ -1683,21 +1683,26 @@ __global__ void __launch_bounds__(kBlock) k_dot_final(const double* __restrict__
 }
 
 // BiCGStab scalars live on the device: slots of `sc`
-// SC_GUESS: 1 when the initial guess has a nonzero entry (set by k_guess_in)
-enum { SC_RHO = 0, SC_RR, SC_RHO_OLD, SC_ALPHA, SC_OMEGA, SC_RV, SC_TS, SC_TT, SC_GUESS, SC_NUM };
+// SC_GUESS: 1 when the initial guess has a nonzero entry (set by k_guess_in);
+// SC_FIRST: 1 from a (re)start until the first iteration's omega step
+enum { SC_RHO = 0, SC_RR, SC_RHO_OLD, SC_ALPHA, SC_OMEGA, SC_RV, SC_TS, SC_TT, SC_GUESS, SC_FIRST, SC_NUM };
 
 __global__ void k_sc_reset(double* sc) {
   sc[SC_RHO] = 1.0;
   sc[SC_RHO_OLD] = 1.0;
   sc[SC_ALPHA] = 1.0;
   sc[SC_OMEGA] = 1.0;
+  sc[SC_FIRST] = 1.0;
 }
+
+__global__ void k_sc_copy(double* sc, int dst, int src) { sc[dst] = sc[src]; }
 
 __global__ void k_sc_alpha(double* sc) { sc[SC_ALPHA] = sc[SC_RHO] / sc[SC_RV]; }
 
 __global__ void k_sc_omega(double* sc) {
   sc[SC_OMEGA] = sc[SC_TT] > 0.0 ? sc[SC_TS] / sc[SC_TT] : 0.0;
   sc[SC_RHO_OLD] = sc[SC_RHO];
+  sc[SC_FIRST] = 0.0;
 }
 
 // Fused BiCGStab vector steps. p = r + beta (p - omega v) (resp. s = r -
@@ -1717,8 +1722,13 @@ __global__ void __launch_bounds__(kBlock) k_bicg_p2(double* __restrict__ p, cons
                                                     int64_t n, float* __restrict__ bf, Z* __restrict__ z) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  const double beta = (sc[SC_RHO] / sc[SC_RHO_OLD]) * (sc[SC_ALPHA] / sc[SC_OMEGA]);
-  const double pv = ld_stream<true>(r + t) + beta * (ld_stream<true>(p + t) - sc[SC_OMEGA] * ld_stream<true>(v + t));
+  // the first iteration after a (re)start has p = v = 0, so p = r: the old
+  // p and v are neither read nor need to be cleared by the restart
+  double pv = ld_stream<true>(r + t);
+  if (sc[SC_FIRST] == 0.0) {
+    const double beta = (sc[SC_RHO] / sc[SC_RHO_OLD]) * (sc[SC_ALPHA] / sc[SC_OMEGA]);
+    pv = pv + beta * (ld_stream<true>(p + t) - sc[SC_OMEGA] * ld_stream<true>(v + t));
+  }
   st_stream<true>(pv, p + t);
   if (bf) bf[t] = (float)pv;
   if (z) z[t] = Z(0);
@@ -1806,17 +1816,15 @@ __global__ void __launch_bounds__(kBlock) k_guess_in(const uint8_t* __restrict__
   if (__any(any) && (threadIdx.x & 63) == 0) *nz = 1.0;
 }
 
-// Krylov (re)start in one pass: r = rh = r0, p = v = 0.
+// Krylov (re)start in one pass: r = rh = r0 (p and v are not read before
+// the first iteration writes them, see k_bicg_p2).
 __global__ void __launch_bounds__(kBlock) k_bicg_restart(const double* __restrict__ r0, double* __restrict__ r,
-                                                         double* __restrict__ rh, double* __restrict__ p,
-                                                         double* __restrict__ v, int64_t n) {
+                                                         double* __restrict__ rh, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const double a = r0[t];
   r[t] = a;
   rh[t] = a;
-  p[t] = 0.0;
-  v[t] = 0.0;
 }
 
 __global__ void __launch_bounds__(kBlock) k_add_f32(double* __restrict__ x, const float* __restrict__ e, int64_t n) {

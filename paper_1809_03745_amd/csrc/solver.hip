@@ -1789,10 +1789,15 @@ static ebmg_status bicgstab_t(DevProblem& D, const Options& o, double bn, double
   const unsigned nb = nblk(nd);
   // r0: the initial residual (the solve's r, or b for a zero guess); a
   // restart after a breakdown starts from the true residual in r64
-  auto restart = [&](const double* r0src) {
-    hipLaunchKernelGGL(k_bicg_restart, dim3(nb), dim3(kBlock), 0, s, r0src, r, rh, p, v, nd);
+  // (rh, r) = (b, b) when the start is from b: the solve has just formed
+  // that sum in SC_RR with the same reduction, so it is copied
+  auto restart = [&](const double* r0src, bool rr_is_r0r0) {
+    hipLaunchKernelGGL(k_bicg_restart, dim3(nb), dim3(kBlock), 0, s, r0src, r, rh, nd);
     hipLaunchKernelGGL(k_sc_reset, dim3(1), dim3(1), 0, s, D.scal.p);
-    dot_dev<double>(D, rh, r, nd, SC_RHO, s);
+    if (rr_is_r0r0)
+      hipLaunchKernelGGL(k_sc_copy, dim3(1), dim3(1), 0, s, D.scal.p, (int)SC_RHO, (int)SC_RR);
+    else
+      dot_dev<double>(D, rh, r, nd, SC_RHO, s);
   };
   // the preconditioner output starts from zero: cleared by the p- and
   // s-updates, unless the finest level's first sweep is the z-marching one,
@@ -1821,7 +1826,7 @@ static ebmg_status bicgstab_t(DevProblem& D, const Options& o, double bn, double
     hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, q, D.part.p, kNormBlocks, 2, D.scal.p + SC_RHO);
     HIPCHECK(hipGetLastError());
   };
-  restart(r0);
+  restart(r0, r0 == L.b64.p);
   int restarts = 0;
   while (rel > rtol) {
     if (cyc + 2 > max_cycles) return EBMG_ERR_NOCONV;
@@ -1850,7 +1855,7 @@ static ebmg_status bicgstab_t(DevProblem& D, const Options& o, double bn, double
           rel = nrel;
           return EBMG_ERR_NOCONV;
         }
-        restart(L.r64.p);
+        restart(L.r64.p, false);
       }
     } else if (nrel > 1e6) {
       rel = nrel;

@@ -446,23 +446,52 @@ __global__ void __launch_bounds__(kRowBlock) k_irr_jac_sl(BLev<T> L, int grp, co
       [&](int g, const RowOwn<T>& o, T sm) { L.w[g - r0] = (o.v - sm) / o.d; });
 }
 
-// Jacobi values of group 1 while group 0's new values are still in w0 (not
-// yet scattered into x): L carries group 1's columns with every group-0 row
-// unknown renamed nx + (its position in group 0), so those entries read w0,
-// and L.w points where group 1's values go. The same values as scattering
-// group 0 first and then running k_irr_jac_sl on group 1.
+// k_irr_jac_sl on group 0 (blocks [0, nb0)) with, in the remaining blocks,
+// group 1's current values copied to w1old (one thread per row), for the
+// pass below.
 template <typename T>
-__global__ void __launch_bounds__(kRowBlock) k_irr_jac_sl2(BLev<T> L, const T* __restrict__ x,
-                                                        const T* __restrict__ b, const T* __restrict__ w0, int nx) {
+__global__ void __launch_bounds__(kRowBlock) k_irr_jac_sl0c(BLev<T> L, int nb0, const T* __restrict__ x,
+                                                         const T* __restrict__ b, T* __restrict__ w1old) {
   FP_EXACT_ORDER
-  const int r0 = L.grp_ptr[1];
-  split_rows<T, T, true>(
-      L, 1, x, (int)blockIdx.x,
+  if ((int)blockIdx.x >= nb0) {
+    const int g = ((int)blockIdx.x - nb0) * kRowBlock + (int)threadIdx.x;
+    if (g < L.grp_ptr[2] - L.grp_ptr[1]) w1old[g] = x[L.irow_dof[L.grp_ptr[1] + g]];
+    return;
+  }
+  const int r0 = L.grp_ptr[0];
+  split_rows<T, T, false>(
+      L, 0, x, (int)blockIdx.x,
       [&](int g) {
         const int64_t q = L.irow_dof[g];
         return RowOwn<T>{q, L.diag[g], b[q]};
       },
-      [&](int g, const RowOwn<T>& o, T sm) { L.w[g - r0] = (o.v - sm) / o.d; }, w0, nx);
+      [&](int g, const RowOwn<T>& o, T sm) { L.w[g - r0] = (o.v - sm) / o.d; });
+}
+
+// Group 1's Jacobi values written straight into x (blocks [0, nb1)) while
+// the remaining blocks copy group 0's new values from L.w into x (one thread
+// per row). L carries group 1's columns with every explicit-row unknown
+// renamed nx + (its place in L.w): group 0's new values at [0, n0), group
+// 1's values before the pass at [n0 + n1, n0 + 2 n1), so no block reads an
+// entry of x that another block writes. The same values as a pass over
+// group 1 reading group 0's new values after a scatter of group 0, and a
+// scatter of group 1 after the pass.
+template <typename T>
+__global__ void __launch_bounds__(kRowBlock) k_irr_jac_sl2x(BLev<T> L, int nb1, T* __restrict__ x,
+                                                         const T* __restrict__ b, const T* __restrict__ w, int nx) {
+  FP_EXACT_ORDER
+  if ((int)blockIdx.x >= nb1) {
+    const int g = ((int)blockIdx.x - nb1) * kRowBlock + (int)threadIdx.x;
+    if (g < L.grp_ptr[1] - L.grp_ptr[0]) x[L.irow_dof[L.grp_ptr[0] + g]] = w[g];
+    return;
+  }
+  split_rows<T, T, true>(
+      L, 1, (const T*)x, (int)blockIdx.x,
+      [&](int g) {
+        const int64_t q = L.irow_dof[g];
+        return RowOwn<T>{q, L.diag[g], b[q]};
+      },
+      [&](int g, const RowOwn<T>& o, T sm) { x[o.q] = (o.v - sm) / o.d; }, w, nx);
 }
 
 // r = b - A x (MODE 0) or A x (MODE 1) on the explicit rows: blocks [0, nb0)

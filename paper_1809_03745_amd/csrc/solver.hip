@@ -153,7 +153,7 @@ struct DevLevel {
   // sliced copy of the explicit rows (engine and batched kernels)
   DevBuf<int64_t> sl_ptr;
   DevBuf<int32_t> sl_col;
-  DevBuf<int32_t> sl_colj;   // group 1's columns with group-0 row unknowns renamed (see k_irr_jac_sl2)
+  DevBuf<int32_t> sl_colj;   // group 1's columns with explicit-row unknowns renamed (see k_irr_jac_sl2x)
   DevBuf<double> sl_val64;
   DevBuf<float> sl_val32;
   int sl_grp[3] = {0, 0, 0};
@@ -1042,18 +1042,24 @@ static void upload(ebmg_problem_s* P, bool batch_box = false, const ebmg_problem
         d.sl_ptr.upload(sptr.data(), (int64_t)sptr.size(), s, by);
         d.sl_col.upload(scol.data(), (int64_t)scol.size(), s, by);
       }
-      // group 1's columns with group-0 row unknowns renamed N + N2 + (position
-      // in group 0), for the Jacobi pass that reads group 0's values before
-      // they are scattered (k_irr_jac_sl2)
+      // group 1's columns with every explicit-row unknown renamed into the
+      // work array w that follows x: a group-0 unknown to N + N2 + (its
+      // position in group 0), whose new value is in w[0, n0); a group-1
+      // unknown to N + N2 + n0 + n1 + (its position in group 1), whose value
+      // before the pass k_irr_jac_sl0c copies there. The pass over group 1
+      // (k_irr_jac_sl2x) then reads no explicit-row unknown from x and can
+      // write its results, and group 0's, straight into x.
       const int64_t nxv = L.N + L.N2;
-      if (!sd && L.cls_ptr.size() == 3 && gptr[1] > gptr[0] && gptr[2] > gptr[1] && nxv + gptr[1] < (int64_t)INT32_MAX) {
-        std::unordered_map<int64_t, int32_t> pos0;
-        pos0.reserve((size_t)(gptr[1] - gptr[0]) * 2);
-        for (int32_t k = gptr[0]; k < gptr[1]; ++k) pos0.emplace(idof[k], k - gptr[0]);
+      const int64_t n0g = gptr[1] - gptr[0], n1g = gptr[2] - gptr[1];
+      if (!sd && L.cls_ptr.size() == 3 && n0g > 0 && n1g > 0 && nxv + n0g + 2 * n1g < (int64_t)INT32_MAX) {
+        std::unordered_map<int64_t, int32_t> pos;
+        pos.reserve((size_t)(n0g + n1g) * 2);
+        for (int32_t k = gptr[0]; k < gptr[1]; ++k) pos.emplace(idof[k], (int32_t)(k - gptr[0]));
+        for (int32_t k = gptr[1]; k < gptr[2]; ++k) pos.emplace(idof[k], (int32_t)(n0g + n1g + (k - gptr[1])));
         std::vector<int32_t> scolj(scol);
         for (int64_t e = sptr[d.sl_grp[1]]; e < sptr[d.sl_grp[2]]; ++e) {
-          const auto it = pos0.find(scolj[e]);
-          if (it != pos0.end()) scolj[e] = (int32_t)(nxv + it->second);
+          const auto it = pos.find(scolj[e]);
+          if (it != pos.end()) scolj[e] = (int32_t)(nxv + it->second);
         }
         d.sl_colj.upload(scolj.data(), (int64_t)scolj.size(), s, by);
       }
@@ -1080,18 +1086,21 @@ static void upload(ebmg_problem_s* P, bool batch_box = false, const ebmg_problem
     d.t64 = make_tmpl<double>(L);
     d.t32 = make_tmpl<float>(L);
     const int64_t nd = L.N + L.N2;
+    // the work array holds the explicit rows' Jacobi values and, after them,
+    // group 1's values before its pass (k_irr_jac_sl0c)
+    const int64_t grp1_rows = L.cls_ptr.size() == 3 ? L.cls_ptr[2] - L.cls_ptr[1] : 0;
     if (!mixed || l == 0) {
       d.x64.alloc(nd, by);
       d.b64.alloc(nd, by);
       d.r64.alloc(nd, by);
-      d.w64.alloc(std::max<int64_t>(1, d.R), by);
+      d.w64.alloc(std::max<int64_t>(1, d.R + grp1_rows), by);
       if (!batch_box) d.xa64.alloc(nd, by);
     }
     if (mixed) {
       d.x32.alloc(nd, by);
       d.b32.alloc(nd, by);
       d.r32.alloc(nd, by);
-      d.w32.alloc(std::max<int64_t>(1, d.R), by);
+      d.w32.alloc(std::max<int64_t>(1, d.R + grp1_rows), by);
       if (!batch_box) d.xa32.alloc(nd, by);
     }
   }
@@ -1278,15 +1287,17 @@ static void irr_groups(DevLevel& l, T* x, const T* b, hipStream_t s) {
   }
   T* w = Vec<T>::tmp(l);
   const BLev<T> L0 = make_blev<T>(l);
-  hipLaunchKernelGGL((k_irr_jac_sl<T>), dim3((unsigned)((n0 + kSplitRows - 1) / kSplitRows)), dim3(kRowBlock), 0, s, L0, 0, x,
-                     b);
+  // group 0 into w[0, n0), with group 1's values copied to w[n0 + n1, ...);
+  // then group 1 straight into x (its columns renamed into w) and group 0
+  // copied from w into x: the same values as the two passes and a scatter
+  const unsigned nb0 = (unsigned)((n0 + kSplitRows - 1) / kSplitRows);
+  const unsigned nb1 = (unsigned)((n1 + kSplitRows - 1) / kSplitRows);
+  hipLaunchKernelGGL((k_irr_jac_sl0c<T>), dim3(nb0 + (unsigned)((n1 + kRowBlock - 1) / kRowBlock)), dim3(kRowBlock),
+                     0, s, L0, nb0, x, b, w + n0 + n1);
   BLev<T> L1 = L0;
   L1.sl_col = l.sl_colj.p;
-  L1.w = w + n0;
-  hipLaunchKernelGGL((k_irr_jac_sl2<T>), dim3((unsigned)((n1 + kSplitRows - 1) / kSplitRows)), dim3(kRowBlock), 0, s, L1, x, b,
-                     (const T*)w, (int)(l.N + l.N2));
-  hipLaunchKernelGGL((k_irr_scatter<T>), dim3(nblk(n0 + n1)), dim3(kBlock), 0, s, l.cls_rows.p + l.cls_ptr[0],
-                     n0 + n1, l.irow_dof.p, w, x);
+  hipLaunchKernelGGL((k_irr_jac_sl2x<T>), dim3(nb1 + (unsigned)((n0 + kRowBlock - 1) / kRowBlock)), dim3(kRowBlock),
+                     0, s, L1, nb1, x, b, (const T*)w, (int)(l.N + l.N2));
 }
 
 template <typename T>

@@ -97,13 +97,16 @@ __global__ void __launch_bounds__(kWB) kw_irr_jac(const BLev<T>* __restrict__ WL
   const BLev<T>& L = WL[e.box];
   if (L.grp_ptr[grp + 1] <= L.grp_ptr[grp]) return;
   const int r0 = L.grp_ptr[grp];
+  const GPtr<const int64_t> dof = gview(L.irow_dof);
+  const GPtr<const T> dgv = gview(L.diag), bg = gview((const T*)L.b);
+  const GPtr<T> wg = gview(L.w);
   split_rows<T, T, false>(
       L, grp, L.x, e.chunk,
       [&](int g) {
-        const int64_t q = L.irow_dof[g];
-        return RowOwn<T>{q, L.diag[g], L.b[q]};
+        const int64_t q = dof[g];
+        return RowOwn<T>{q, dgv[g], bg[q]};
       },
-      [&](int g, const RowOwn<T>& o, T sm) { L.w[g - r0] = (o.v - sm) / o.d; });
+      [&](int g, const RowOwn<T>& o, T sm) { wg[g - r0] = (o.v - sm) / o.d; });
 }
 
 template <typename T>

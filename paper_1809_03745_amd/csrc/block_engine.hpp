@@ -104,10 +104,21 @@ constexpr int kAll = 0x7fffffff;
 // instead, so a phase gives the same bits wherever it runs.
 #define FP_EXACT_ORDER _Pragma("clang fp contract(off)")
 
+// Global-memory views of the level's arrays: pointers read from a level
+// struct are generic to the compiler, whose generic (flat) loads also count
+// as LDS operations, so every use waits for all of them; through these views
+// the loads are global ones, waited for one by one.
+template <typename T>
+using GPtr = T __attribute__((address_space(1)))*;
+template <typename T>
+__device__ __forceinline__ GPtr<T> gview(T* p) { return (GPtr<T>)p; }
+
 template <typename T, int DIM>
-__device__ void be_rb_part(const BLev<T>& L, T* __restrict__ x, const T* __restrict__ b, int colour, int beg,
+__device__ void be_rb_part(const BLev<T>& L, T* __restrict__ xp, const T* __restrict__ bp, int colour, int beg,
                            int cnt) {
   FP_EXACT_ORDER
+  const GPtr<T> x = gview(xp);
+  const GPtr<const T> b = gview(bp);
   constexpr int U = BeU<T>::U;
   const int nx = L.n[0], ny = L.n[1], nz = DIM == 3 ? L.n[2] : 1;
   const int nxh = (nx + 1) >> 1;
@@ -115,7 +126,7 @@ __device__ void be_rb_part(const BLev<T>& L, T* __restrict__ x, const T* __restr
   const int64_t sxy = (int64_t)nx * ny;
   const int64_t last = (int64_t)nx * ny * nz - 1;
   const Tmpl<T> tp = L.tp;
-  const uint8_t* __restrict__ tag = L.tag;
+  const GPtr<const uint8_t> tag = gview(L.tag);
   const int end = be_end(nthr, beg, cnt);
   for (int t0 = beg + (int)threadIdx.x; t0 < end; t0 += blockDim.x * U) {
     int64_t cc[U];
@@ -192,7 +203,10 @@ __device__ __forceinline__ T sliced_row(const int32_t* __restrict__ col, const T
                                         const TX* __restrict__ x, int64_t p, int len,
                                         const TX* __restrict__ x2 = nullptr, int nx = 0) {
   FP_EXACT_ORDER
-  auto ld = [&](int c) -> T { return TWO ? (T)(c < nx ? x[c] : x2[c - nx]) : (T)x[c]; };
+  const GPtr<const int32_t> cg = gview(col);
+  const GPtr<const T> vg = gview(val);
+  const GPtr<const TX> xg = gview(x), x2g = gview(x2);
+  auto ld = [&](int c) -> T { return TWO ? (T)(c < nx ? xg[c] : x2g[c - nx]) : (T)xg[c]; };
   T s = T(0);
   int j = 0;
   for (; j + kRowJ <= len; j += kRowJ) {
@@ -200,15 +214,15 @@ __device__ __forceinline__ T sliced_row(const int32_t* __restrict__ col, const T
     T v[kRowJ], xv[kRowJ];
 #pragma unroll
     for (int k = 0; k < kRowJ; ++k) {
-      c[k] = col[p + (int64_t)(j + k) * kSlice];
-      v[k] = val[p + (int64_t)(j + k) * kSlice];
+      c[k] = cg[p + (int64_t)(j + k) * kSlice];
+      v[k] = vg[p + (int64_t)(j + k) * kSlice];
     }
 #pragma unroll
     for (int k = 0; k < kRowJ; ++k) xv[k] = ld(c[k]);
 #pragma unroll
     for (int k = 0; k < kRowJ; ++k) s = s + v[k] * xv[k];
   }
-  for (; j < len; ++j) s = s + val[p + (int64_t)j * kSlice] * ld(col[p + (int64_t)j * kSlice]);
+  for (; j < len; ++j) s = s + vg[p + (int64_t)j * kSlice] * ld(cg[p + (int64_t)j * kSlice]);
   return s;
 }
 
@@ -287,15 +301,19 @@ __device__ void be_smooth(const BLev<T>& L, T* x, const T* b, int sweeps) {
 // input widened on load). NDOT >= 1 adds da[q] * r[q] over the unknowns this
 // part writes to acc0, NDOT == 2 also r[q]^2 to acc1.
 template <typename T, typename TX, int DIM, int MODE, int NDOT>
-__device__ void be_resid_cells_part(const BLev<T>& L, const TX* __restrict__ x, const T* __restrict__ b,
-                                    T* __restrict__ r, int beg, int cnt, const double* __restrict__ da,
+__device__ void be_resid_cells_part(const BLev<T>& L, const TX* __restrict__ xp, const T* __restrict__ bp,
+                                    T* __restrict__ rp, int beg, int cnt, const double* __restrict__ dap,
                                     double& acc0, double& acc1) {
   FP_EXACT_ORDER
+  const GPtr<const TX> x = gview(xp);
+  const GPtr<const T> b = gview(bp);
+  const GPtr<T> r = gview(rp);
+  const GPtr<const double> da = gview(dap);
   constexpr int U = BeU<T>::U;
   const int nx = L.n[0], ny = L.n[1], nz = DIM == 3 ? L.n[2] : 1;
   const int64_t sxy = (int64_t)nx * ny;
   const Tmpl<T> tp = L.tp;
-  const uint8_t* __restrict__ tag = L.tag;
+  const GPtr<const uint8_t> tag = gview(L.tag);
   const int N = L.N;
   const int end = be_end(N, beg, cnt);
   for (int c0 = beg + (int)threadIdx.x; c0 < end; c0 += blockDim.x * U) {
@@ -357,16 +375,22 @@ __device__ void be_resid_cells_part(const BLev<T>& L, const TX* __restrict__ x, 
 
 // Explicit rows of colour group grp, [beg, beg + cnt) relative to the group.
 template <typename T, typename TX, int MODE, int NDOT>
-__device__ void be_resid_rows_part(const BLev<T>& L, int grp, const TX* __restrict__ x, const T* __restrict__ b,
-                                   T* __restrict__ r, int beg, int cnt, const double* __restrict__ da,
+__device__ void be_resid_rows_part(const BLev<T>& L, int grp, const TX* __restrict__ xp, const T* __restrict__ bp,
+                                   T* __restrict__ rp, int beg, int cnt, const double* __restrict__ dap,
                                    double& acc0, double& acc1) {
   FP_EXACT_ORDER
   if (L.grp_ptr[grp + 1] <= L.grp_ptr[grp]) return;
+  const GPtr<const TX> x = gview(xp);
+  const GPtr<const T> b = gview(bp);
+  const GPtr<T> r = gview(rp);
+  const GPtr<const double> da = gview(dap);
+  const GPtr<const int64_t> dof = gview(L.irow_dof);
+  const GPtr<const T> dgv = gview(L.diag);
   sliced_rows<T, TX>(
-      L, grp, x, beg, cnt,
+      L, grp, xp, beg, cnt,
       [&](int g) {
-        const int64_t q = L.irow_dof[g];
-        return RowOwn<T>{q, L.diag[g], (T)x[q]};
+        const int64_t q = dof[g];
+        return RowOwn<T>{q, dgv[g], (T)x[q]};
       },
       [&](int g, const RowOwn<T>& w, T sm) {
         const T ax = w.d * w.v + sm;

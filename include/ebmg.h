@@ -124,7 +124,12 @@ typedef struct {
                                256^2 cells                                      */
   int32_t tail;             /* coarse levels: 0 autotuned at setup, 1 always by
                                grid-wide launches, 2 always by the one-workgroup
-                               engine from the first level of <= 32768 unknowns */
+                               engine from the first level of <= 32768 unknowns
+                               (batches, level-synchronous: 0 the coarse-part
+                               threshold timed at setup, 1 only the bottom level
+                               in each box's workgroup, 2 every level of
+                               <= 32768 unknowns; 1 and 2 time nothing, so the
+                               choice does not depend on concurrent work)       */
   int32_t batch;            /* batched solves (ebmg_setup_batch; one value for all
                                boxes): 0 or 2 level-synchronous (every phase one
                                launch over all boxes, coarse levels per box in

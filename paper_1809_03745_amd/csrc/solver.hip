@@ -390,6 +390,7 @@ struct ebmg_batch_s {
   ebmg::DevBuf<int32_t> count;
   int* host_count = nullptr;
   int tail_cells = 0;
+  int tail_opt = 0;   // options.tail of the boxes: 0 timed, 1 bottom only, 2 from kTailMax unknowns
   std::vector<int> cand_cells;
   std::vector<double> cand_ms;
   // replayed iteration graph and the stopping parameters baked into it
@@ -2395,6 +2396,16 @@ static void wide_solve(ebmg_batch_s* Bt, const std::vector<WIO>& io, double rtol
 // for each candidate threshold; keep the fastest.
 template <typename T, int DIM>
 static void tune_wide(ebmg_batch_s* Bt, hipStream_t s) {
+  if (Bt->tail_opt == 1 || Bt->tail_opt == 2) {
+    // a fixed threshold (no timing, so the choice never depends on what
+    // else runs on the device): only the bottom level, or every level of at
+    // most kTailMax unknowns, in each box's one-workgroup coarse part
+    const int c = Bt->tail_opt == 1 ? 0 : (int)kTailMax;
+    Bt->cand_cells.assign(1, c);
+    Bt->cand_ms.assign(1, 0.0);
+    build_wide_tables<T>(Bt, c, s);
+    return;
+  }
   const int nbox = (int)Bt->boxes.size();
   std::vector<WState> st = initial_state(Bt);
   HIPCHECK(hipMemcpyAsync(Bt->state.p, st.data(), sizeof(WState) * nbox, hipMemcpyHostToDevice, s));
@@ -3598,6 +3609,7 @@ ebmg_status ebmg_setup_batch(ebmg_ctx ctx, int32_t nbox, const ebmg_box* boxes, 
     Bt->mixed = prec == EBMG_MIXED;
     Bt->nu1 = Bt->boxes[0]->host->opt.nu1;
     Bt->nu2 = Bt->boxes[0]->host->opt.nu2;
+    Bt->tail_opt = Bt->boxes[0]->host->opt.tail;
     // host setup of the boxes in parallel (independent problems)
     unsigned nw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<std::string> errs(nbox);

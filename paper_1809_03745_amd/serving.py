@@ -315,7 +315,8 @@ class Server:
             if req.group_key is not None and self.coalesce > 1:
                 # a batch of copies of the box (its results do not depend on
                 # what the other boxes hold or on its coarse-part choice)
-                B = ebmg.Batch(ctx, [prob] * self.coalesce, precision=self.precision, batch=ebmg.BATCH_LEVELSYNC)
+                B = ebmg.Batch(ctx, [prob] * self.coalesce, precision=self.precision, batch=ebmg.BATCH_LEVELSYNC,
+                               tail=1)
                 req.setup_s = time.perf_counter() - t0
                 entry.handle = {"batch": B, "ctx": ctx, "stream": stream}
                 return B.device_bytes

@@ -202,6 +202,24 @@ def test_batch_levelsync_tuning_and_modes_agree(ctx):
         assert np.linalg.norm(xw[i] - xp[i]) <= 1e-9 * np.linalg.norm(xp[i]), i
 
 
+@pytest.mark.parametrize("tail,cells", [(1, 0), (2, 32768)])
+def test_batch_fixed_coarse_part(ctx, tail, cells):
+    """A pinned coarse-part rule (options.tail 1 or 2) times nothing: the
+    threshold is the rule's, the only candidate, and the solve still meets
+    the tolerance (the serving loop relies on this for mix invariance)."""
+    _say("batch fixed coarse part", tail)
+    probs = BOXES[:4]
+    B = ebmg.Batch(ctx, probs, precision=ebmg.MIXED, batch=ebmg.BATCH_LEVELSYNC, tail=tail)
+    tu = B.tuning()
+    _say("   tuning", tu)
+    assert tu["tail_cells"] == cells
+    assert [c for c, _ in tu["candidates"]] == [cells]
+    st, infos, xs, x2s = _batch_solve(B, probs, 1e-10)
+    assert st == ebmg.OK
+    assert all(i["rel_residual"] <= 1e-10 for i in infos)
+    B.release()
+
+
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batch_edge_cases(ctx, mode, prec):
